@@ -327,7 +327,7 @@ static int prepare(prep_t *p, uint32_t n_blocks, uint32_t tpb, uint32_t warp_siz
             /* instance = (block, warp, id, occurrence); the warp is identified by the tid of its
              * lane 0, so (warp0, id, occ) names the instance exactly */
             uint32_t warp0 = t - ((t % tpb) % warp_size);
-            uint64_t key = mix64(((uint64_t)warp0 << 32) | ev[i].addr) ^ mix64(((uint64_t)occ << 1) | 1);
+            uint64_t key = mix64(mix64(((uint64_t)warp0 << 32) | ev[i].addr) + 0x9e3779b97f4a7c15ULL * (occ + 1));
             int ins;
             uint32_t inst = hmap_get(&wmap, key, p->n_winst, &ins);
             if (ins) {
