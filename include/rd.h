@@ -1,0 +1,131 @@
+/*
+ * rd.h -- scoped happens-before race checking of recorded GPU event traces on MI355X (gfx950).
+ *
+ * The problem (paper Section 2.2): a kernel trace is a sequence of per-thread events in the order
+ * the GPU executed them.  Two events race when they access the same global word, or the same
+ * shared word of one block (Section 4.1, "shared memory"), at least one writes, they are not both
+ * atomics whose scopes overlap (Section 4, Section 5.1), and neither happens before the other
+ * (Section 1 race definition).  Happens-before is the scoped HB relation of Section 2.2: program
+ * order (rule i), block and warp barriers (rule iii; Section 5.1 for __syncwarp), and a release
+ * followed by an acquire of the same sync variable unless both are block scoped in different
+ * blocks (rule iv).  Releases and acquires are explicit lock events, or atomics next to a fence in
+ * program order (Section 2.1 lock idiom, scope taken from the fence as in Section 5.1).  A fence
+ * orders nothing by itself.  The report is every racing pair (first, second), first < second,
+ * sorted ascending.
+ *
+ * Record format (16 bytes, little endian; trace index = position in the array):
+ *   addr  4-byte word address; WBAR: warp-barrier id; FENCE and BAR: 0
+ *   tid   block * threads_per_block + thread_in_block
+ *   meta  kind (bits 0-3) | scope << 4 | space << 6; bits 7-31 must be zero
+ *   aux   WBAR: lane mask (bit l = lane l of the warp); otherwise opaque (e.g. a site id)
+ *
+ * Validity (a trace that breaks a rule is rejected with RD_ETRACE and the first offending index):
+ *   record rules, checked first: kind <= 7, scope <= 2, reserved meta bits zero;
+ *     tid < n_blocks * threads_per_block; FENCE, BAR and WBAR are in global space.
+ *   barrier rules, checked when every record is well formed:
+ *     a thread emits nothing after its k-th BAR until every active thread of its block (a thread
+ *     with at least one event) has emitted its k-th BAR;
+ *     a WBAR's mask contains the emitting lane and equals the mask of the earliest arrival of the
+ *     same instance (warp, id, occurrence of that id in the lane's program order); a lane emits
+ *     nothing after a WBAR until every lane of the mask has arrived at that instance.
+ *   The first offending index is the smallest index of an event that breaks a record rule, or,
+ *   when there is none, the smallest index of an event that breaks a barrier rule.
+ *
+ * Memory: every device buffer is owned by the caller.  rd_workspace_bytes() sizes one workspace
+ * per trace; the library never allocates device memory.
+ *
+ * Errors: every call returns an rd_status; nothing throws across this interface.  Errors found on
+ * the device during rd_check (trace errors, capacity overflows) are reported by rd_races().
+ */
+#ifndef RD_H
+#define RD_H
+
+#include <stdint.h>
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t rd_status;
+enum {
+    RD_OK = 0,
+    RD_EINVAL = -1, /* bad argument: null pointer, bad grid, size out of range */
+    RD_ENOMEM = -2, /* workspace, clock pool or internal pair buffer too small */
+    RD_ETRACE = -3, /* the trace breaks a validity rule; rd_last_error() gives the event index */
+    RD_ETRUNC = -4, /* rd_races: more pairs than the caller's capacity; *n_races has the total */
+    RD_EHIP = -5,   /* a HIP runtime call failed */
+    RD_ESTATE = -6  /* call out of order (e.g. rd_races before rd_check) */
+};
+
+/* event kinds (meta bits 0-3) */
+enum { RD_READ = 0, RD_WRITE = 1, RD_ATOMIC = 2, RD_FENCE = 3, RD_BAR = 4, RD_WBAR = 5, RD_ACQ = 6, RD_REL = 7 };
+/* scopes (meta bits 4-5); system scope behaves as device scope on one GPU */
+enum { RD_BLOCK = 0, RD_DEVICE = 1, RD_SYSTEM = 2 };
+/* spaces (meta bit 6) */
+enum { RD_GLOBAL = 0, RD_SHARED = 1 };
+
+typedef struct {
+    uint32_t addr, tid, meta, aux;
+} rd_event;
+
+typedef struct {
+    uint32_t n_blocks;          /* >= 1 */
+    uint32_t threads_per_block; /* 1 .. 1024 */
+    uint32_t warp_size;         /* 1 .. 32, 0 means 32; only warp barriers use it */
+    uint32_t reserved;          /* must be 0 */
+} rd_grid;
+
+typedef struct {
+    uint32_t first, second; /* trace indices, first < second */
+} rd_pair;
+
+/* Capacity limits of one workspace.  Zero fields take defaults:
+ *   max_pairs    internal race-pair buffer (default max(2^20, n_events / 4));
+ *   clock_bytes  pool for knowledge vectors of release/acquire and warp-barrier traces
+ *                (default 256 MiB); traces with only block barriers do not use it. */
+typedef struct {
+    uint64_t max_pairs;
+    uint64_t clock_bytes;
+} rd_limits;
+
+typedef struct rd_ctx_s *rd_ctx;
+typedef struct rd_trace_s *rd_trace;
+
+/* Context on one HIP device.  Thread safe: distinct traces may be used concurrently. */
+rd_status rd_init(int hip_device, rd_ctx *out);
+rd_status rd_shutdown(rd_ctx ctx);
+
+/* Bytes of device workspace one trace of this shape needs (limits may be NULL). */
+rd_status rd_workspace_bytes(rd_ctx ctx, const rd_grid *grid, uint64_t n_events,
+                             const rd_limits *limits, uint64_t *bytes);
+
+/* Binds a trace to a caller-owned workspace of at least rd_workspace_bytes() bytes (256-byte
+ * aligned).  events_on_device = 0: `events` is host memory; it is copied into the workspace on
+ * `stream` and may be freed when the call returns.  events_on_device = 1: `events` is device
+ * memory the library reads until rd_trace_free().  No validation of the contents happens here. */
+rd_status rd_trace_upload(rd_ctx ctx, const rd_grid *grid, const rd_event *events, uint64_t n_events,
+                          int events_on_device, void *workspace, uint64_t workspace_bytes,
+                          const rd_limits *limits, hipStream_t stream, rd_trace *out);
+
+/* Enqueues the whole check on `stream` and returns without waiting.  The workspace and the events
+ * must stay valid until rd_races() returns or the stream is synchronised. */
+rd_status rd_check(rd_ctx ctx, rd_trace trace, hipStream_t stream);
+
+/* Waits for the check and copies the report: min(capacity, total) pairs in canonical order into
+ * `out` (may be NULL to query the count), *n_races = total.  Returns RD_ETRACE for an invalid
+ * trace, RD_ENOMEM when a device-side capacity overflowed, RD_ETRUNC when capacity < total. */
+rd_status rd_races(rd_ctx ctx, rd_trace trace, rd_pair *out, uint64_t capacity, uint64_t *n_races);
+
+rd_status rd_trace_free(rd_ctx ctx, rd_trace trace);
+
+const char *rd_strerror(rd_status status);
+
+/* Details of the last error on this context: for RD_ETRACE the first offending event index
+ * (UINT64_MAX otherwise) and a message. */
+rd_status rd_last_error(rd_ctx ctx, uint64_t *event_index, char *msg, uint64_t msg_len);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* RD_H */

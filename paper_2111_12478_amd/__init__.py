@@ -1,0 +1,236 @@
+"""Scoped happens-before race checking of GPU event traces on MI355X (gfx950).
+
+A thin ctypes binding of ``librd.so`` (``include/rd.h``).  The functions named ``rd_*`` mirror the
+C interface one to one (argument marshalling only); :class:`RaceChecker` wraps them for the common
+case: a torch-owned workspace on the current HIP device, the current torch stream, and a numpy
+report.  Every step of the check runs in the library's HIP kernels; there is no other code path:
+if the library is not built, or there is no GPU, the calls raise.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "librd.so")
+
+RD_OK, RD_EINVAL, RD_ENOMEM, RD_ETRACE, RD_ETRUNC, RD_EHIP, RD_ESTATE = 0, -1, -2, -3, -4, -5, -6
+READ, WRITE, ATOMIC, FENCE, BAR, WBAR, ACQ, REL = range(8)
+BLOCK, DEVICE, SYSTEM = 0, 1, 2
+GLOBAL, SHARED = 0, 1
+
+
+class rd_grid(ctypes.Structure):
+    _fields_ = [("n_blocks", ctypes.c_uint32), ("threads_per_block", ctypes.c_uint32),
+                ("warp_size", ctypes.c_uint32), ("reserved", ctypes.c_uint32)]
+
+
+class rd_limits(ctypes.Structure):
+    _fields_ = [("max_pairs", ctypes.c_uint64), ("clock_bytes", ctypes.c_uint64)]
+
+
+class rd_pair(ctypes.Structure):
+    _fields_ = [("first", ctypes.c_uint32), ("second", ctypes.c_uint32)]
+
+
+class RdError(RuntimeError):
+    def __init__(self, status, msg, event_index=None):
+        super().__init__(f"{msg} (status {status})")
+        self.status = status
+        self.event_index = event_index
+
+
+_lib = None
+
+
+def load_library():
+    """Loads librd.so; raises if it has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: build it with paper_2111_12478_amd/build.py")
+        lib = ctypes.CDLL(LIB_PATH)
+        vp, u64, i32, u32 = ctypes.c_void_p, ctypes.c_uint64, ctypes.c_int32, ctypes.c_uint32
+        P = ctypes.POINTER
+        sig = {
+            "rd_init": ([ctypes.c_int, P(vp)], i32),
+            "rd_shutdown": ([vp], i32),
+            "rd_workspace_bytes": ([vp, P(rd_grid), u64, P(rd_limits), P(u64)], i32),
+            "rd_trace_upload": ([vp, P(rd_grid), vp, u64, ctypes.c_int, vp, u64, P(rd_limits), vp, P(vp)], i32),
+            "rd_check": ([vp, vp, vp], i32),
+            "rd_races": ([vp, vp, vp, u64, P(u64)], i32),
+            "rd_trace_free": ([vp, vp], i32),
+            "rd_strerror": ([i32], ctypes.c_char_p),
+            "rd_last_error": ([vp, P(u64), ctypes.c_char_p, u64], i32),
+        }
+        for name, (args, res) in sig.items():
+            f = getattr(lib, name)
+            f.argtypes = args
+            f.restype = res
+        _lib = lib
+    return _lib
+
+
+# ---------------------------------------------------------------- the C interface, by name
+
+def rd_init(device: int = 0) -> int:
+    ctx = ctypes.c_void_p()
+    st = load_library().rd_init(device, ctypes.byref(ctx))
+    if st != RD_OK:
+        raise RdError(st, f"rd_init({device}) failed")
+    return ctx.value
+
+
+def rd_shutdown(ctx: int) -> int:
+    return load_library().rd_shutdown(ctx)
+
+
+def _grid(grid) -> rd_grid:
+    g = list(grid) + [0] * (3 - len(grid))
+    return rd_grid(int(g[0]), int(g[1]), int(g[2]), 0)
+
+
+def _limits(limits):
+    if limits is None:
+        return None
+    if isinstance(limits, rd_limits):
+        return ctypes.byref(limits)
+    return ctypes.byref(rd_limits(int(limits.get("max_pairs", 0)), int(limits.get("clock_bytes", 0))))
+
+
+def rd_workspace_bytes(ctx: int, grid, n_events: int, limits=None) -> int:
+    out = ctypes.c_uint64()
+    g = _grid(grid)
+    st = load_library().rd_workspace_bytes(ctx, ctypes.byref(g), n_events, _limits(limits), ctypes.byref(out))
+    if st != RD_OK:
+        raise RdError(st, "rd_workspace_bytes failed")
+    return out.value
+
+
+def rd_trace_upload(ctx, grid, events_ptr, n_events, events_on_device, workspace_ptr, workspace_bytes,
+                    limits, stream) -> tuple[int, int]:
+    """Returns (status, trace handle)."""
+    tr = ctypes.c_void_p()
+    g = _grid(grid)
+    st = load_library().rd_trace_upload(ctx, ctypes.byref(g), events_ptr, n_events, int(events_on_device),
+                                        workspace_ptr, workspace_bytes, _limits(limits), stream, ctypes.byref(tr))
+    return st, tr.value
+
+
+def rd_check(ctx, trace, stream) -> int:
+    return load_library().rd_check(ctx, trace, stream)
+
+
+def rd_races(ctx, trace, out_ptr, capacity) -> tuple[int, int]:
+    n = ctypes.c_uint64()
+    st = load_library().rd_races(ctx, trace, out_ptr, capacity, ctypes.byref(n))
+    return st, n.value
+
+
+def rd_trace_free(ctx, trace) -> int:
+    return load_library().rd_trace_free(ctx, trace)
+
+
+def rd_strerror(status: int) -> str:
+    return load_library().rd_strerror(status).decode()
+
+
+def rd_last_error(ctx) -> tuple[int, str]:
+    idx = ctypes.c_uint64()
+    buf = ctypes.create_string_buffer(256)
+    load_library().rd_last_error(ctx, ctypes.byref(idx), buf, 256)
+    v = idx.value
+    return (-1 if v == (1 << 64) - 1 else v), buf.value.decode()
+
+
+# ---------------------------------------------------------------- convenience wrapper
+
+class CheckResult:
+    def __init__(self, status, pairs, bad_index=-1, message=""):
+        self.status = status
+        self.pairs = pairs
+        self.bad_index = bad_index
+        self.message = message
+
+    def __repr__(self):
+        return f"CheckResult(status={self.status}, bad_index={self.bad_index}, n_pairs={len(self.pairs)})"
+
+
+class RaceChecker:
+    """One context on a HIP device; check() runs the whole pipeline on the current torch stream."""
+
+    def __init__(self, device: int = 0):
+        import torch
+        if not torch.cuda.is_available():
+            raise RuntimeError("the race checker needs a HIP device")
+        self.torch = torch
+        self.device = device
+        self.ctx = rd_init(device)
+
+    def close(self):
+        if self.ctx:
+            rd_shutdown(self.ctx)
+            self.ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def workspace_bytes(self, grid, n_events, limits=None):
+        return rd_workspace_bytes(self.ctx, grid, n_events, limits)
+
+    def prepare(self, grid, events, limits=None, workspace=None):
+        """Binds events (numpy (N,4) uint32 on the host, or a torch tensor (N,4) int32/uint32 on the
+        device) to a workspace.  Returns (trace handle, workspace tensor, events tensor or None)."""
+        torch = self.torch
+        n = int(events.shape[0])
+        nbytes = self.workspace_bytes(grid, n, limits)
+        if workspace is None or workspace.numel() < nbytes:
+            workspace = torch.empty(max(nbytes, 256), dtype=torch.uint8, device=f"cuda:{self.device}")
+        stream = torch.cuda.current_stream(self.device).cuda_stream
+        keep = None
+        if isinstance(events, np.ndarray):
+            ev = np.ascontiguousarray(events, dtype=np.uint32)
+            keep = ev
+            st, tr = rd_trace_upload(self.ctx, grid, ev.ctypes.data if n else None, n, 0, workspace.data_ptr(),
+                                     workspace.numel(), limits, stream)
+        else:
+            ev = events.contiguous()
+            keep = ev
+            st, tr = rd_trace_upload(self.ctx, grid, ev.data_ptr() if n else None, n, 1, workspace.data_ptr(),
+                                     workspace.numel(), limits, stream)
+        if st != RD_OK:
+            raise RdError(st, f"rd_trace_upload: {rd_last_error(self.ctx)[1]}")
+        return tr, workspace, keep
+
+    def run(self, trace, capacity=None):
+        stream = self.torch.cuda.current_stream(self.device).cuda_stream
+        st = rd_check(self.ctx, trace, stream)
+        if st != RD_OK:
+            raise RdError(st, f"rd_check: {rd_last_error(self.ctx)[1]}")
+        return self.report(trace, capacity)
+
+    def report(self, trace, capacity=None):
+        st, n = rd_races(self.ctx, trace, None, 0)
+        if st not in (RD_OK, RD_ETRUNC):
+            idx, msg = rd_last_error(self.ctx)
+            return CheckResult(st, np.zeros((0, 2), np.uint32), idx, msg)
+        cap = n if capacity is None else capacity
+        out = np.zeros((max(cap, 1), 2), dtype=np.uint32)
+        st, n = rd_races(self.ctx, trace, out.ctypes.data, cap)
+        if st not in (RD_OK, RD_ETRUNC):
+            idx, msg = rd_last_error(self.ctx)
+            return CheckResult(st, np.zeros((0, 2), np.uint32), idx, msg)
+        return CheckResult(st, out[: min(cap, n)].copy())
+
+    def check(self, grid, events, limits=None, capacity=None):
+        tr, ws, keep = self.prepare(grid, events, limits)
+        try:
+            return self.run(tr, capacity)
+        finally:
+            rd_trace_free(self.ctx, tr)
+            del ws, keep

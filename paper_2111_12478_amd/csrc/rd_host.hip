@@ -1,0 +1,388 @@
+// rd_host.hip -- workspace layout, pipeline orchestration and the C interface of include/rd.h.
+#include <mutex>
+#include <new>
+#include <string.h>
+#include <string>
+#include <vector>
+
+#include "rd_internal.h"
+#include "rd_kernels.h"
+
+namespace rd {
+
+static u64 align_up(u64 x, u64 a) { return (x + a - 1) / a * a; }
+static u32 next_pow2(u64 x) {
+    u64 p = 1;
+    while (p < x) p <<= 1;
+    return (u32)p;
+}
+
+u32 sort_pairs_host(const Bufs &b, u32 m, hipStream_t s);
+
+struct Plan {
+    Layout L;
+    u64 off_masks, off_rt_scan;
+    u32 n_tiles, T, B, radix_bits, pair_tiles, part_words;
+    u64 hist_words;
+};
+
+static Plan make_plan(u64 n, u32 nb, u32 tpb, const rd_limits *lim, bool copy_events, u32 radix_bits) {
+    Plan P;
+    memset(&P, 0, sizeof(P));
+    Layout &L = P.L;
+    const u64 T = (u64)nb * tpb, B = nb;
+    const u32 n_tiles = (u32)((n + TILE - 1) / TILE);
+    u64 max_pairs = lim && lim->max_pairs ? lim->max_pairs : (n / 4 > (1u << 20) ? n / 4 : (1u << 20));
+    if (max_pairs > 0xfffffff0ull) max_pairs = 0xfffffff0ull;
+    const u64 pool_bytes = lim && lim->clock_bytes ? lim->clock_bytes : (256ull << 20);
+    const u64 N1 = n ? n : 1;
+    P.n_tiles = n_tiles; P.T = (u32)T; P.B = nb; P.radix_bits = radix_bits;
+    P.pair_tiles = (u32)((max_pairs + TILE - 1) / TILE);
+    const u64 hist_tiles = n_tiles > P.pair_tiles ? n_tiles : P.pair_tiles;
+    P.hist_words = (hist_tiles ? hist_tiles : 1) << (radix_bits > 8 ? radix_bits : 8);
+    u64 scan_max = P.hist_words;
+    if (T + 1 > scan_max) scan_max = T + 1;
+    P.part_words = (u32)((scan_max + 4095) / 4096 + 16);
+    L.sv_cap = next_pow2(2 * N1 < (1u << 22) ? 2 * N1 + 64 : (1u << 22));
+    L.wo_cap = next_pow2(N1 / 4 < (1u << 18) ? N1 / 4 + 64 : (1u << 18));
+    L.pool_bytes = pool_bytes;
+    L.max_pairs = max_pairs;
+
+    u64 o = 0;
+    auto take = [&](u64 bytes) { const u64 r = o; o = align_up(o + (bytes ? bytes : 4), 256); return r; };
+    L.off_params = take(sizeof(DevParams));
+    L.off_ev = copy_events ? take(16 * N1) : 0;
+    L.off_act = take(T);
+    L.off_s_cnt = take(4 * (T + 1));
+    L.off_s_fill = take(4 * T);
+    L.off_tile_s = take(4 * 2 * ((u64)n_tiles + 1));
+    P.off_masks = take(8 * 2 * (u64)n_tiles * 64);
+    L.off_s_tidx = take(4 * N1);
+    L.off_s_pidx = take(4 * N1);
+    L.off_s_pq = take(4 * N1);
+    L.off_s_inv = take(4 * N1);
+    L.off_s_phase = take(4 * N1);
+    L.off_s_kind = take(N1);
+    L.off_s_flags = take(N1);
+    L.off_s_scope = take(N1);
+    L.off_s_imin = take(4 * N1);
+    L.off_s_know = take(4 * N1);
+    L.off_s_khandle = take(4 * N1);
+    L.off_s_winst = take(4 * N1);
+    L.off_blk_maxbar = take(4 * (B + 1));
+    L.off_inst_cnt = take(4 * N1);
+    L.off_inst_last = take(4 * N1);
+    L.off_inst_handle = take(4 * N1);
+    L.off_n_active = take(4 * B);
+    P.off_rt_scan = take(4 * (T + 1));
+    L.off_priv = take(4 * T);
+    L.off_priv_next = take(4 * T);
+    L.off_bk = take(4 * B);
+    L.off_priv_head = take(4 * B);
+    L.off_sv_key = take(8ull * L.sv_cap);
+    L.off_sv_tag = take(4ull * L.sv_cap);
+    L.off_sv_handle = take(4ull * L.sv_cap);
+    L.off_wo_key = take(8ull * L.wo_cap);
+    L.off_wo_val = take(4ull * L.wo_cap);
+    L.off_wi_key = take(8ull * L.wo_cap);
+    L.off_wi_occ = take(4ull * L.wo_cap);
+    L.off_wi_inst = take(4ull * L.wo_cap);
+    L.off_winst_mask = take(4ull * L.wo_cap);
+    L.off_winst_arrived = take(4ull * L.wo_cap);
+    L.off_winst_last = take(4ull * L.wo_cap);
+    L.off_winst_nar = take(4ull * L.wo_cap);
+    L.off_winst_arr = take(4ull * 32 * L.wo_cap);
+    L.off_pool = take(pool_bytes);
+    for (int c = 0; c < 2; c++) {
+        L.off_ekey[c] = take(4 * N1);
+        L.off_eidx[c] = take(4 * N1);
+        L.off_etid[c] = take(4 * N1);
+        L.off_einfo[c] = take(4 * N1);
+    }
+    L.off_hist = take(4 * P.hist_words);
+    L.off_part = take(4ull * P.part_words);
+    L.off_tile_agg = take(agg_bytes() * ((u64)n_tiles + 1));
+    for (int c = 0; c < 2; c++) {
+        L.off_pfirst[c] = take(4 * max_pairs);
+        L.off_psecond[c] = take(4 * max_pairs);
+    }
+    L.total = o;
+    return P;
+}
+
+static Bufs make_bufs(const Plan &P, char *ws, const void *events_dev, u64 n, u32 nb, u32 tpb, u32 warp_size) {
+    const Layout &L = P.L;
+    Bufs b;
+    memset(&b, 0, sizeof(b));
+    b.ev = (const uint4 *)(events_dev ? events_dev : ws + L.off_ev);
+    b.prm = (DevParams *)(ws + L.off_params);
+    b.act = (uint8_t *)(ws + L.off_act);
+    b.s_cnt = (u32 *)(ws + L.off_s_cnt);
+    b.s_fill = (u32 *)(ws + L.off_s_fill);
+    b.tile_s = (u32 *)(ws + L.off_tile_s);
+    b.s_tidx = (u32 *)(ws + L.off_s_tidx);
+    b.s_pidx = (u32 *)(ws + L.off_s_pidx);
+    b.s_pq = (u32 *)(ws + L.off_s_pq);
+    b.s_inv = (u32 *)(ws + L.off_s_inv);
+    b.s_phase = (u32 *)(ws + L.off_s_phase);
+    b.s_kind = (uint8_t *)(ws + L.off_s_kind);
+    b.s_flags = (uint8_t *)(ws + L.off_s_flags);
+    b.s_scope = (uint8_t *)(ws + L.off_s_scope);
+    b.s_imin = (u32 *)(ws + L.off_s_imin);
+    b.s_know = (u32 *)(ws + L.off_s_know);
+    b.s_khandle = (u32 *)(ws + L.off_s_khandle);
+    b.s_winst = (u32 *)(ws + L.off_s_winst);
+    b.blk_maxbar = (u32 *)(ws + L.off_blk_maxbar);
+    b.inst_off = b.blk_maxbar;  // scanned in place
+    b.inst_cnt = (u32 *)(ws + L.off_inst_cnt);
+    b.inst_last = (u32 *)(ws + L.off_inst_last);
+    b.inst_handle = (u32 *)(ws + L.off_inst_handle);
+    b.n_active = (u32 *)(ws + L.off_n_active);
+    b.priv = (u32 *)(ws + L.off_priv);
+    b.priv_next = (u32 *)(ws + L.off_priv_next);
+    b.bk = (u32 *)(ws + L.off_bk);
+    b.priv_head = (u32 *)(ws + L.off_priv_head);
+    b.sv_key = (u64 *)(ws + L.off_sv_key);
+    b.sv_tag = (u32 *)(ws + L.off_sv_tag);
+    b.sv_handle = (u32 *)(ws + L.off_sv_handle);
+    b.sv_cap = L.sv_cap;
+    b.wo_key = (u64 *)(ws + L.off_wo_key);
+    b.wo_val = (u32 *)(ws + L.off_wo_val);
+    b.wo_cap = L.wo_cap;
+    b.wi_key = (u64 *)(ws + L.off_wi_key);
+    b.wi_occ = (u32 *)(ws + L.off_wi_occ);
+    b.wi_inst = (u32 *)(ws + L.off_wi_inst);
+    b.winst_mask = (u32 *)(ws + L.off_winst_mask);
+    b.winst_arrived = (u32 *)(ws + L.off_winst_arrived);
+    b.winst_last = (u32 *)(ws + L.off_winst_last);
+    b.winst_nar = (u32 *)(ws + L.off_winst_nar);
+    b.winst_arr = (u32 *)(ws + L.off_winst_arr);
+    b.pool = (u32 *)(ws + L.off_pool);
+    b.pool_words = L.pool_bytes / 4;
+    for (int c = 0; c < 2; c++) {
+        b.ekey[c] = (u32 *)(ws + L.off_ekey[c]);
+        b.eidx[c] = (u32 *)(ws + L.off_eidx[c]);
+        b.etid[c] = (u32 *)(ws + L.off_etid[c]);
+        b.einfo[c] = (u32 *)(ws + L.off_einfo[c]);
+        b.pfirst[c] = (u32 *)(ws + L.off_pfirst[c]);
+        b.psecond[c] = (u32 *)(ws + L.off_psecond[c]);
+    }
+    b.hist = (u32 *)(ws + L.off_hist);
+    b.part = (u32 *)(ws + L.off_part);
+    b.tile_agg = ws + L.off_tile_agg;
+    b.max_pairs = L.max_pairs;
+    b.N = (u32)n;
+    b.T = nb * tpb;
+    b.B = nb;
+    b.tpb = tpb;
+    b.ws = warp_size;
+    b.n_tiles = P.n_tiles;
+    b.radix_bits = P.radix_bits;
+    return b;
+}
+
+hipError_t enqueue_check(const Bufs &b, u64 *masks, u32 *rt_scan, hipStream_t s) {
+    u64 *sync_mask = masks, *acc_mask = masks + (u64)b.n_tiles * 64;
+    prep_init(b, s);
+    prep_ingest(b, sync_mask, acc_mask, s);
+    prep_sync_lists(b, sync_mask, s);
+    prep_elements(b, acc_mask, s);
+    prep_thread_sync(b, rt_scan, s);
+    interp_run(b, rt_scan, s);
+    prep_validate_wbar(b, s);
+    sort_elements(b, s);
+    segcheck_run(b, rt_scan, s);
+    return hipGetLastError();
+}
+
+}  // namespace rd
+
+// ================================================================ C interface
+
+using namespace rd;
+
+struct rd_ctx_s {
+    int device;
+    std::mutex mu;
+    uint64_t last_index;
+    std::string last_msg;
+};
+
+struct rd_trace_s {
+    Plan plan;
+    Bufs bufs;
+    char *ws;
+    u64 *masks;
+    u32 *rt_scan;
+    hipStream_t stream;
+    int checked;
+    rd_grid grid;
+    uint64_t n;
+};
+
+static rd_status set_err(rd_ctx ctx, rd_status st, uint64_t index, const char *msg) {
+    if (ctx) {
+        std::lock_guard<std::mutex> g(ctx->mu);
+        ctx->last_index = index;
+        ctx->last_msg = msg ? msg : "";
+    }
+    return st;
+}
+
+static bool grid_ok(const rd_grid *g, uint64_t n) {
+    if (!g || g->n_blocks == 0 || g->threads_per_block == 0 || g->threads_per_block > 1024) return false;
+    if (g->warp_size > 32 || g->reserved != 0) return false;
+    if ((uint64_t)g->n_blocks * g->threads_per_block >= (1ull << 32)) return false;
+    if (n >= (1ull << 32)) return false;
+    return true;
+}
+
+static u32 env_radix_bits() {
+    const char *e = getenv("RD_RADIX_BITS");
+    if (e && atoi(e) == 11) return 11;
+    return 8;
+}
+
+extern "C" {
+
+rd_status rd_init(int hip_device, rd_ctx *out) {
+    if (!out) return RD_EINVAL;
+    *out = nullptr;
+    int n = 0;
+    if (hipGetDeviceCount(&n) != hipSuccess || hip_device < 0 || hip_device >= n) return RD_EINVAL;
+    rd_ctx c = new (std::nothrow) rd_ctx_s;
+    if (!c) return RD_ENOMEM;
+    c->device = hip_device;
+    c->last_index = UINT64_MAX;
+    *out = c;
+    return RD_OK;
+}
+
+rd_status rd_shutdown(rd_ctx ctx) {
+    if (!ctx) return RD_EINVAL;
+    delete ctx;
+    return RD_OK;
+}
+
+rd_status rd_workspace_bytes(rd_ctx ctx, const rd_grid *grid, uint64_t n_events, const rd_limits *limits,
+                             uint64_t *bytes) {
+    if (!ctx || !bytes) return RD_EINVAL;
+    if (!grid_ok(grid, n_events)) return set_err(ctx, RD_EINVAL, UINT64_MAX, "bad grid or event count");
+    const Plan P = make_plan(n_events, grid->n_blocks, grid->threads_per_block, limits, true, env_radix_bits());
+    *bytes = P.L.total;
+    return RD_OK;
+}
+
+rd_status rd_trace_upload(rd_ctx ctx, const rd_grid *grid, const rd_event *events, uint64_t n_events,
+                          int events_on_device, void *workspace, uint64_t workspace_bytes, const rd_limits *limits,
+                          hipStream_t stream, rd_trace *out) {
+    if (!ctx || !out) return RD_EINVAL;
+    *out = nullptr;
+    if (!grid_ok(grid, n_events)) return set_err(ctx, RD_EINVAL, UINT64_MAX, "bad grid or event count");
+    if (!workspace || ((uintptr_t)workspace & 255)) return set_err(ctx, RD_EINVAL, UINT64_MAX, "workspace null or not 256-byte aligned");
+    if (n_events && !events) return set_err(ctx, RD_EINVAL, UINT64_MAX, "null events");
+    const Plan P = make_plan(n_events, grid->n_blocks, grid->threads_per_block, limits, true, env_radix_bits());
+    if (workspace_bytes < P.L.total) return set_err(ctx, RD_ENOMEM, UINT64_MAX, "workspace too small");
+    if (hipSetDevice(ctx->device) != hipSuccess) return set_err(ctx, RD_EHIP, UINT64_MAX, "hipSetDevice failed");
+    rd_trace t = new (std::nothrow) rd_trace_s;
+    if (!t) return RD_ENOMEM;
+    t->plan = P;
+    t->ws = (char *)workspace;
+    t->grid = *grid;
+    t->n = n_events;
+    t->stream = stream;
+    t->checked = 0;
+    const u32 ws = grid->warp_size ? grid->warp_size : 32;
+    const void *dev_events = nullptr;
+    if (events_on_device) dev_events = events;
+    else if (n_events) {
+        if (hipMemcpyAsync(t->ws + P.L.off_ev, events, 16 * n_events, hipMemcpyHostToDevice, stream) != hipSuccess) {
+            delete t;
+            return set_err(ctx, RD_EHIP, UINT64_MAX, "hipMemcpyAsync of the events failed");
+        }
+    }
+    t->bufs = make_bufs(P, t->ws, dev_events, n_events, grid->n_blocks, grid->threads_per_block, ws);
+    t->masks = (u64 *)(t->ws + P.off_masks);
+    t->rt_scan = (u32 *)(t->ws + P.off_rt_scan);
+    *out = t;
+    return RD_OK;
+}
+
+rd_status rd_check(rd_ctx ctx, rd_trace trace, hipStream_t stream) {
+    if (!ctx || !trace) return RD_EINVAL;
+    if (hipSetDevice(ctx->device) != hipSuccess) return set_err(ctx, RD_EHIP, UINT64_MAX, "hipSetDevice failed");
+    trace->stream = stream;
+    const hipError_t e = enqueue_check(trace->bufs, trace->masks, trace->rt_scan, stream);
+    if (e != hipSuccess) return set_err(ctx, RD_EHIP, UINT64_MAX, hipGetErrorString(e));
+    trace->checked = 1;
+    return RD_OK;
+}
+
+rd_status rd_races(rd_ctx ctx, rd_trace trace, rd_pair *out, uint64_t capacity, uint64_t *n_races) {
+    if (!ctx || !trace || !n_races) return RD_EINVAL;
+    *n_races = 0;
+    if (!trace->checked) return set_err(ctx, RD_ESTATE, UINT64_MAX, "rd_races before rd_check");
+    if (hipSetDevice(ctx->device) != hipSuccess) return set_err(ctx, RD_EHIP, UINT64_MAX, "hipSetDevice failed");
+    hipStream_t s = trace->stream;
+    DevParams prm;
+    if (hipMemcpyAsync(&prm, trace->bufs.prm, sizeof(prm), hipMemcpyDeviceToHost, s) != hipSuccess ||
+        hipStreamSynchronize(s) != hipSuccess)
+        return set_err(ctx, RD_EHIP, UINT64_MAX, "reading the check state failed");
+    if (prm.first_bad_record != NONE) return set_err(ctx, RD_ETRACE, prm.first_bad_record, "malformed record");
+    if (prm.err & ERR_PHASE) return set_err(ctx, RD_EINVAL, UINT64_MAX, "a thread passed more than 2^30 barriers");
+    if (prm.first_bad_sync != NONE)
+        return set_err(ctx, RD_ETRACE, prm.first_bad_sync, "event runs ahead of an unfinished barrier");
+    if (prm.err & ERR_KEYSPAN)
+        return set_err(ctx, RD_EINVAL, UINT64_MAX, "address span too large for a 32-bit location key");
+    if (prm.err & ERR_POOL) return set_err(ctx, RD_ENOMEM, UINT64_MAX, "knowledge-vector pool exhausted (rd_limits.clock_bytes)");
+    if (prm.err & ERR_TABLE) return set_err(ctx, RD_ENOMEM, UINT64_MAX, "sync-variable or warp-barrier table full");
+    if (prm.err & ERR_PAIRS) {
+        *n_races = prm.n_pairs;
+        return set_err(ctx, RD_ENOMEM, UINT64_MAX, "race pairs exceed rd_limits.max_pairs");
+    }
+    const u32 m = prm.n_pairs_kept;
+    *n_races = m;
+    if (!out || !capacity || !m) return m > capacity ? set_err(ctx, RD_ETRUNC, UINT64_MAX, "capacity") : RD_OK;
+    const u32 buf = sort_pairs_host(trace->bufs, m, s);
+    const u64 k = capacity < m ? capacity : m;
+    std::vector<u32> f(k), sec(k);
+    if (hipMemcpyAsync(f.data(), trace->bufs.pfirst[buf], 4 * k, hipMemcpyDeviceToHost, s) != hipSuccess ||
+        hipMemcpyAsync(sec.data(), trace->bufs.psecond[buf], 4 * k, hipMemcpyDeviceToHost, s) != hipSuccess ||
+        hipStreamSynchronize(s) != hipSuccess)
+        return set_err(ctx, RD_EHIP, UINT64_MAX, "copying the pairs failed");
+    for (u64 q = 0; q < k; q++) { out[q].first = f[q]; out[q].second = sec[q]; }
+    if (capacity < m) return set_err(ctx, RD_ETRUNC, UINT64_MAX, "more races than capacity");
+    return RD_OK;
+}
+
+rd_status rd_trace_free(rd_ctx ctx, rd_trace trace) {
+    if (!ctx || !trace) return RD_EINVAL;
+    delete trace;
+    return RD_OK;
+}
+
+const char *rd_strerror(rd_status s) {
+    switch (s) {
+    case RD_OK: return "ok";
+    case RD_EINVAL: return "invalid argument";
+    case RD_ENOMEM: return "capacity exceeded";
+    case RD_ETRACE: return "invalid trace";
+    case RD_ETRUNC: return "output truncated";
+    case RD_EHIP: return "HIP runtime error";
+    case RD_ESTATE: return "call out of order";
+    default: return "unknown status";
+    }
+}
+
+rd_status rd_last_error(rd_ctx ctx, uint64_t *event_index, char *msg, uint64_t msg_len) {
+    if (!ctx) return RD_EINVAL;
+    std::lock_guard<std::mutex> g(ctx->mu);
+    if (event_index) *event_index = ctx->last_index;
+    if (msg && msg_len) {
+        strncpy(msg, ctx->last_msg.c_str(), msg_len - 1);
+        msg[msg_len - 1] = 0;
+    }
+    return RD_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,182 @@
+// rd_internal.h -- shared definitions of the gfx950 race checker (device state, workspace layout,
+// wavefront helpers, kernel launchers).  Not part of the public interface (include/rd.h).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "rd.h"
+
+namespace rd {
+
+typedef uint32_t u32;
+typedef uint64_t u64;
+
+constexpr u32 NONE = 0xffffffffu;
+
+// Tiles: a workgroup of WG_THREADS threads (4 wavefronts of 64) owns TILE consecutive items; wave w
+// of the workgroup owns the contiguous range [w*ITEMS*64, (w+1)*ITEMS*64) of the tile and walks it
+// in ITEMS steps of 64 consecutive items, so "wave, step, lane" is the input order.
+constexpr int WG_THREADS = 256;
+constexpr int WAVES = WG_THREADS / 64;
+constexpr int ITEMS = 16;
+constexpr int TILE = WG_THREADS * ITEMS;  // 4096
+
+// element categories (conflict classes of an access)
+enum { CAT_R = 0, CAT_W = 1, CAT_AD = 2, CAT_AB = 3 };  // read, write, device/system atomic, block atomic
+
+// element info word: category in bits 0-1, phase (block barriers passed) in bits 2-31
+__host__ __device__ inline u32 info_make(u32 cat, u32 phase) { return cat | (phase << 2); }
+__host__ __device__ inline u32 info_cat(u32 info) { return info & 3u; }
+__host__ __device__ inline u32 info_phase(u32 info) { return info >> 2; }
+
+// sync-entry flags (per entry of the per-thread sync lists)
+enum : uint8_t {
+    SF_REL = 1,       // release (explicit, or an atomic right after a fence)
+    SF_ACQ = 2,       // acquire (explicit, or an atomic right before a fence)
+    SF_BAD_ARRIVAL = 4,  // warp-barrier arrival with a bad mask
+};
+
+// error flags (DevParams::err)
+enum : u32 {
+    ERR_POOL = 1,       // knowledge-vector pool exhausted
+    ERR_KEYSPAN = 2,    // address span does not fit a 32-bit location key
+    ERR_PAIRS = 4,      // internal pair buffer overflowed
+    ERR_TABLE = 8,      // sync-variable or warp-barrier table overflowed
+    ERR_PHASE = 16,     // a thread passed more than 2^30 barriers
+};
+
+// Device-side state of one check.  Zeroed (and the "min" fields set to NONE) by k_init.
+struct DevParams {
+    u32 first_bad_record;  // smallest index breaking a record rule
+    u32 first_bad_sync;    // smallest index breaking a barrier rule
+    u32 err;
+    u32 n_sync;            // events in the sync lists (everything but plain reads and writes)
+    u32 kind_count[8];
+    u32 gmin, gmax, smin, smax;  // address ranges of global / shared accesses
+    u32 n_acc;             // accesses (= elements)
+    u32 key_bits;          // significant bits of the location key
+    u32 g_span, s_span;    // key = addr - gmin (global) | g_span + block * s_span + addr - smin
+    u32 gbase, sbase;      // gmin, smin used for keys
+    u32 mode;              // MODE_* bits
+    u32 n_rt;              // threads with a column in knowledge vectors (releasers, warp-barrier lanes)
+    u32 D;                 // knowledge vector width = n_blocks + n_rt
+    u32 pool_next;         // next free knowledge vector (0 is the empty vector)
+    u32 pool_cap;          // vectors in the pool
+    u32 n_pairs;           // pairs found (may exceed the buffer)
+    u32 n_pairs_kept;      // min(n_pairs, capacity)
+    u32 n_winst;           // warp-barrier instances
+    u32 pad[3];
+};
+
+enum : u32 {
+    MODE_BAR = 1,    // block barriers present
+    MODE_SYNC = 2,   // releases/acquires/warp barriers possible: knowledge vectors needed
+    MODE_WBAR = 4,
+};
+
+// Device buffers of one trace (carved out of the caller's workspace).
+struct Bufs {
+    const uint4 *ev;        // events
+    DevParams *prm;
+    uint8_t *act;           // [T] thread has >= 1 event
+    u32 *s_cnt;             // [T+1] sync entries per thread -> exclusive offsets
+    u32 *s_fill;            // [T]
+    u32 *tile_s;            // [n_tiles+1] sync events per ingest tile -> offsets
+    u32 *s_tidx;            // [N] sync events in trace order (event index)
+    u32 *s_pidx;            // [N] per-thread sync lists (event index), trace order inside a thread
+    u32 *s_pq;              // [N] trace-order position of each list entry
+    u32 *s_inv;             // [N] list position of each trace-order sync event
+    u32 *s_phase;           // [N] barriers passed up to and including the entry
+    uint8_t *s_kind;        // [N]
+    uint8_t *s_flags;       // [N]
+    uint8_t *s_scope;       // [N] release scope (bits 0-1), acquire scope (bits 2-3)
+    u32 *s_imin;            // [N] smallest access index between the entry and the thread's next entry
+    u32 *s_know;            // [N] knowledge vector after the entry
+    u32 *s_khandle;         // [N] knowledge vector created at the entry (interpreter output)
+    u32 *s_winst;           // [N] warp-barrier instance of the entry
+    u32 *blk_maxbar;        // [B]
+    u32 *inst_off;          // [B+1]
+    u32 *inst_cnt;          // [N]
+    u32 *inst_last;         // [N]
+    u32 *inst_handle;       // [N]
+    u32 *n_active;          // [B]
+    u32 *rt;                // [T] knowledge column of a thread, or NONE
+    u32 *priv;              // [T] private knowledge vector of a thread (since its last barrier)
+    u32 *priv_next;         // [T]
+    u32 *bk;                // [B] knowledge vector of a block after its latest barrier
+    u32 *priv_head;         // [B]
+    // sync-variable table (open addressing)
+    u64 *sv_key;            // [SV] location key | tag
+    u32 *sv_tag;            // [SV]
+    u32 *sv_handle;         // [SV]
+    u32 sv_cap;
+    // warp-barrier tables
+    u64 *wo_key;            // [WO] (tid, id) -> occurrences so far
+    u32 *wo_val;
+    u32 wo_cap;
+    u64 *wi_key;            // [WO] (warp lane-0 tid, id) hashed with occurrence -> instance
+    u32 *wi_occ;
+    u32 *wi_inst;
+    u32 *winst_mask, *winst_arrived, *winst_last, *winst_nar;  // [WO]
+    u32 *winst_arr;         // [WO*32] arrival list entries
+    u32 *pool;              // knowledge vectors
+    u64 pool_words;
+    // elements (ping-pong)
+    u32 *ekey[2], *eidx[2], *etid[2], *einfo[2];
+    // radix sort
+    u32 *hist;              // [RADIX_MAX * n_tiles]
+    u32 *part;              // [scan partials]
+    // segment check
+    void *tile_agg;         // [n_tiles] aggregates -> exclusive prefixes
+    // pairs (ping-pong)
+    u32 *pfirst[2], *psecond[2];
+    u64 max_pairs;
+    // shape
+    u32 N, T, B, tpb, ws;
+    u32 n_tiles;            // ceil(N / TILE)
+    u32 radix_bits;         // 8 or 11
+    u32 sorted_buf;         // which element buffer holds the sorted elements (set by the host plan)
+    u32 pair_buf;
+};
+
+// ---------------------------------------------------------------- wavefront helpers (wave64)
+
+__device__ inline u32 lane_id() { return __lane_id(); }
+__device__ inline u64 lanemask_lt() { return (u64(1) << lane_id()) - 1; }
+__device__ inline u64 ballot(bool p) { return __ballot(p); }
+__device__ inline u32 popc64(u64 x) { return (u32)__popcll(x); }
+
+// ---------------------------------------------------------------- host side
+
+struct Layout {
+    u64 total;
+    u64 off_params, off_ev, off_act, off_s_cnt, off_s_fill, off_tile_s, off_s_tidx, off_s_pidx,
+        off_s_pq, off_s_inv, off_s_phase, off_s_kind, off_s_flags, off_s_scope, off_s_imin,
+        off_s_know, off_s_khandle, off_s_winst, off_blk_maxbar, off_inst_off, off_inst_cnt,
+        off_inst_last, off_inst_handle, off_n_active, off_rt, off_priv, off_priv_next, off_bk,
+        off_priv_head, off_sv_key, off_sv_tag, off_sv_handle, off_wo_key, off_wo_val, off_wi_key,
+        off_wi_occ, off_wi_inst, off_winst_mask, off_winst_arrived, off_winst_last, off_winst_nar,
+        off_winst_arr, off_pool, off_ekey[2], off_eidx[2], off_etid[2], off_einfo[2], off_hist,
+        off_part, off_tile_agg, off_pfirst[2], off_psecond[2];
+    u32 sv_cap, wo_cap, pool_cap_bytes_hi;
+    u64 pool_bytes, max_pairs;
+};
+
+size_t agg_bytes();
+
+}  // namespace rd
+
+namespace rd {
+// Last entry of thread t's sync list with event index < idx, or NONE.
+__device__ inline u32 list_search(const Bufs &b, u32 t, u32 idx) {
+    u32 lo = b.s_cnt[t], hi = b.s_cnt[t + 1];
+    const u32 first = lo;
+    while (lo < hi) {
+        const u32 mid = (lo + hi) >> 1;
+        if (b.s_pidx[mid] < idx) lo = mid + 1;
+        else hi = mid;
+    }
+    return lo == first ? NONE : lo - 1;
+}
+}  // namespace rd

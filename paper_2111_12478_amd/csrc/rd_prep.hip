@@ -1,0 +1,499 @@
+// rd_prep.hip -- trace ingest, per-thread sync lists, barrier instances, access elements,
+// release/acquire inference and barrier validation (gfx950).
+//
+// Everything here streams the 16-byte records once or twice with coalesced dwordx4 loads, or
+// walks the short per-thread lists of synchronisation events (one lane per program thread).
+#include "rd_internal.h"
+#include "rd_kernels.h"
+
+namespace rd {
+
+// ---------------------------------------------------------------- fills and scans
+
+__global__ void k_fill_u32(u32 *p, u64 n, u32 v) {
+    for (u64 i = (u64)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (u64)gridDim.x * blockDim.x) p[i] = v;
+}
+__global__ void k_fill_u8(uint8_t *p, u64 n, uint8_t v) {
+    for (u64 i = (u64)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (u64)gridDim.x * blockDim.x) p[i] = v;
+}
+// fill n = *count entries (count read on the device)
+__global__ void k_fill_u32_dyn(u32 *p, const u32 *count, u32 v) {
+    u32 n = *count;
+    for (u32 i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) p[i] = v;
+}
+
+static inline unsigned grid_for(u64 n, unsigned per = 256, unsigned cap = 4096) {
+    u64 g = (n + per - 1) / per;
+    if (g < 1) g = 1;
+    if (g > cap) g = cap;
+    return (unsigned)g;
+}
+
+void fill_u32(u32 *p, u64 n, u32 v, hipStream_t s) {
+    if (n) hipLaunchKernelGGL(k_fill_u32, dim3(grid_for(n)), dim3(256), 0, s, p, n, v);
+}
+void fill_u8(uint8_t *p, u64 n, uint8_t v, hipStream_t s) {
+    if (n) hipLaunchKernelGGL(k_fill_u8, dim3(grid_for(n)), dim3(256), 0, s, p, n, v);
+}
+void fill_u32_dyn(u32 *p, const u32 *count, u32 v, u64 max_n, hipStream_t s) {
+    hipLaunchKernelGGL(k_fill_u32_dyn, dim3(grid_for(max_n)), dim3(256), 0, s, p, count, v);
+}
+
+// Block-wide exclusive scan of one value per thread (256 threads).  Returns the exclusive prefix;
+// *total gets the block total.
+__device__ inline u32 block_exscan_256(u32 v, u32 *total, u32 *lds /* >= 8 words */) {
+    const u32 lane = lane_id(), w = threadIdx.x >> 6;
+    u32 x = v;
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+        u32 y = __shfl_up(x, d, 64);
+        if (lane >= (u32)d) x += y;
+    }
+    if (lane == 63) lds[w] = x;
+    __syncthreads();
+    u32 wbase = 0, tot = 0;
+    for (u32 q = 0; q < WAVES; q++) {
+        u32 s = lds[q];
+        if (q < w) wbase += s;
+        tot += s;
+    }
+    __syncthreads();
+    *total = tot;
+    return wbase + x - v;
+}
+
+constexpr u32 SCAN_CHUNK = 4096;  // 256 threads x 16
+
+// partial sums of SCAN_CHUNK-sized chunks
+__global__ __launch_bounds__(256) void k_scan_reduce(const u32 *in, u64 n, u32 *part) {
+    __shared__ u32 lds[8];
+    u64 base = (u64)blockIdx.x * SCAN_CHUNK;
+    u32 s = 0;
+    for (u32 k = 0; k < 16; k++) {
+        u64 i = base + k * 256 + threadIdx.x;
+        if (i < n) s += in[i];
+    }
+    u32 tot;
+    block_exscan_256(s, &tot, lds);
+    if (threadIdx.x == 0) part[blockIdx.x] = tot;
+}
+// exclusive scan of the partials in one workgroup of 1024 threads
+__global__ __launch_bounds__(1024) void k_scan_top(u32 *part, u32 np) {
+    __shared__ u32 lds[1024];
+    u32 per = (np + 1023) / 1024;
+    u32 lo = threadIdx.x * per, hi = lo + per < np ? lo + per : np;
+    u32 s = 0;
+    for (u32 i = lo; i < hi; i++) s += part[i];
+    lds[threadIdx.x] = s;
+    __syncthreads();
+    for (u32 d = 1; d < 1024; d <<= 1) {
+        u32 y = threadIdx.x >= d ? lds[threadIdx.x - d] : 0;
+        __syncthreads();
+        lds[threadIdx.x] += y;
+        __syncthreads();
+    }
+    u32 run = lds[threadIdx.x] - s;
+    for (u32 i = lo; i < hi; i++) { u32 v = part[i]; part[i] = run; run += v; }
+}
+// in-place exclusive scan of each chunk plus its carry
+__global__ __launch_bounds__(256) void k_scan_apply(u32 *data, u64 n, const u32 *part) {
+    __shared__ u32 lds[8];
+    u64 base = (u64)blockIdx.x * SCAN_CHUNK + (u64)threadIdx.x * 16;
+    u32 v[16], s = 0;
+    for (u32 k = 0; k < 16; k++) { u64 i = base + k; v[k] = i < n ? data[i] : 0; s += v[k]; }
+    u32 tot;
+    u32 run = block_exscan_256(s, &tot, lds) + part[blockIdx.x];
+    for (u32 k = 0; k < 16; k++) { u64 i = base + k; if (i < n) data[i] = run; run += v[k]; }
+}
+
+// Exclusive scan of data[0..n) in place; `part` needs ceil(n / 4096) words (<= 2^20).
+void scan_exclusive(u32 *data, u64 n, u32 *part, hipStream_t s) {
+    if (!n) return;
+    u32 np = (u32)((n + SCAN_CHUNK - 1) / SCAN_CHUNK);
+    hipLaunchKernelGGL(k_scan_reduce, dim3(np), dim3(256), 0, s, data, n, part);
+    hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(1024), 0, s, part, np);
+    hipLaunchKernelGGL(k_scan_apply, dim3(np), dim3(256), 0, s, data, n, part);
+}
+
+// ---------------------------------------------------------------- init
+
+__global__ void k_init_params(DevParams *p) {
+    if (threadIdx.x == 0) {
+        DevParams z = {};
+        z.first_bad_record = NONE;
+        z.first_bad_sync = NONE;
+        z.gmin = NONE;
+        z.smin = NONE;
+        *p = z;
+    }
+}
+
+// ---------------------------------------------------------------- ingest
+
+__device__ inline bool is_access_kind(u32 k) { return k <= 2u || k == 6u || k == 7u; }
+
+// Record checks, kind histogram, address ranges, activity, sync counts per thread, and two
+// bitmasks (sync events, accesses) with per-tile counts for the compactions that follow.
+__global__ __launch_bounds__(WG_THREADS) void k_ingest(Bufs b, u64 *sync_mask, u64 *acc_mask) {
+    __shared__ u32 lds_cnt[8][WAVES];
+    __shared__ u32 lds_misc[WAVES][8];
+    const u32 w = threadIdx.x >> 6, lane = lane_id();
+    const u64 base = (u64)blockIdx.x * TILE + (u64)w * ITEMS * 64;
+    u32 bad = NONE, ns = 0, na = 0;
+    u32 kc[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    u32 gmin = NONE, gmax = 0, smin = NONE, smax = 0;
+#pragma unroll 4
+    for (int k = 0; k < ITEMS; k++) {
+        const u64 i = base + (u64)k * 64 + lane;
+        const bool in = i < b.N;
+        uint4 e = in ? b.ev[i] : make_uint4(0, 0, 0, 0);
+        const u32 kind = e.z & 15u, scope = (e.z >> 4) & 3u, space = (e.z >> 6) & 1u;
+        bool ok = in && (e.z >> 7) == 0 && kind <= 7u && scope <= 2u && e.y < b.T &&
+                  !((kind == 3u || kind == 4u || kind == 5u) && space);
+        if (in && !ok && (u32)i < bad) bad = (u32)i;
+        if (in && e.y < b.T) b.act[e.y] = 1;
+        const bool is_sync = ok && kind >= 2u;
+        const bool is_acc = ok && is_access_kind(kind);
+        if (ok) {
+#pragma unroll
+            for (u32 q = 0; q < 8; q++) kc[q] += (kind == q);
+        }
+        if (is_acc) {
+            if (space) { smin = min(smin, e.x); smax = max(smax, e.x); }
+            else { gmin = min(gmin, e.x); gmax = max(gmax, e.x); }
+        }
+        if (is_sync) atomicAdd(&b.s_cnt[e.y], 1u);
+        const u64 ms = ballot(is_sync), ma = ballot(is_acc);
+        if (lane == 0) {
+            const u64 word = (base + (u64)k * 64) >> 6;
+            sync_mask[word] = ms;
+            acc_mask[word] = ma;
+        }
+        ns += popc64(ms);
+        na += popc64(ma);
+    }
+    // wave reductions
+#pragma unroll
+    for (int d = 32; d >= 1; d >>= 1) {
+        bad = min(bad, (u32)__shfl_xor((int)bad, d, 64));
+        gmin = min(gmin, (u32)__shfl_xor((int)gmin, d, 64));
+        gmax = max(gmax, (u32)__shfl_xor((int)gmax, d, 64));
+        smin = min(smin, (u32)__shfl_xor((int)smin, d, 64));
+        smax = max(smax, (u32)__shfl_xor((int)smax, d, 64));
+#pragma unroll
+        for (int q = 0; q < 8; q++) kc[q] += __shfl_xor((int)kc[q], d, 64);
+    }
+    if (lane == 0) {
+        for (int q = 0; q < 8; q++) lds_cnt[q][w] = kc[q];
+        lds_misc[w][0] = bad; lds_misc[w][1] = gmin; lds_misc[w][2] = gmax;
+        lds_misc[w][3] = smin; lds_misc[w][4] = smax; lds_misc[w][5] = ns; lds_misc[w][6] = na;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        u32 tb = NONE, tg0 = NONE, tg1 = 0, ts0 = NONE, ts1 = 0, tns = 0, tna = 0;
+        for (int q = 0; q < WAVES; q++) {
+            tb = min(tb, lds_misc[q][0]); tg0 = min(tg0, lds_misc[q][1]); tg1 = max(tg1, lds_misc[q][2]);
+            ts0 = min(ts0, lds_misc[q][3]); ts1 = max(ts1, lds_misc[q][4]);
+            tns += lds_misc[q][5]; tna += lds_misc[q][6];
+        }
+        DevParams *p = b.prm;
+        if (tb != NONE) atomicMin(&p->first_bad_record, tb);
+        if (tg0 != NONE) { atomicMin(&p->gmin, tg0); atomicMax(&p->gmax, tg1); }
+        if (ts0 != NONE) { atomicMin(&p->smin, ts0); atomicMax(&p->smax, ts1); }
+        for (int q = 0; q < 8; q++) {
+            u32 c = 0;
+            for (int ww = 0; ww < WAVES; ww++) c += lds_cnt[q][ww];
+            if (c) atomicAdd(&p->kind_count[q], c);
+        }
+        b.tile_s[blockIdx.x] = tns;
+        b.tile_s[b.n_tiles + 1 + blockIdx.x] = tna;  // access counts live after the sync counts
+    }
+}
+
+// Location-key plan and the mode of the check (one thread).
+__global__ void k_plan(Bufs b) {
+    if (threadIdx.x) return;
+    DevParams *p = b.prm;
+    p->n_sync = b.tile_s[b.n_tiles];
+    p->n_acc = b.tile_s[2 * b.n_tiles + 1];
+    u64 gs = p->gmin != NONE ? (u64)p->gmax - p->gmin + 1 : 0;
+    u64 ss = p->smin != NONE ? (u64)p->smax - p->smin + 1 : 0;
+    u64 total = gs + (u64)b.B * ss;
+    if (total > 0xffffffffull) { p->err |= ERR_KEYSPAN; total = 0xffffffffull; }
+    u32 bits = 0;
+    while (bits < 32 && ((u64)1 << bits) < total) bits++;
+    p->key_bits = bits;
+    p->g_span = (u32)gs;
+    p->s_span = (u32)ss;
+    p->gbase = p->gmin != NONE ? p->gmin : 0;
+    p->sbase = p->smin != NONE ? p->smin : 0;
+    u32 mode = 0;
+    if (p->kind_count[4]) mode |= MODE_BAR;
+    if (p->kind_count[3] || p->kind_count[5] || p->kind_count[6] || p->kind_count[7]) mode |= MODE_SYNC;
+    if (p->kind_count[5]) mode |= MODE_WBAR;
+    p->mode = mode;
+}
+
+// Position of item (lane, step) among the set bits of a tile's bitmask, in input order.
+// masks: the tile's ITEMS words of this wave are read by every lane.
+__device__ inline void wave_mask_prefix(const u64 *mask, u64 tile_word0, u32 w, u32 *wave_base_lds,
+                                        u32 tile_off, u64 m_items[ITEMS], u32 pre[ITEMS]) {
+    const u32 lane = lane_id();
+    u32 run = 0;
+#pragma unroll
+    for (int k = 0; k < ITEMS; k++) {
+        const u64 m = mask[tile_word0 + (u64)w * ITEMS + k];
+        m_items[k] = m;
+        pre[k] = run + popc64(m & lanemask_lt());
+        run += popc64(m);
+    }
+    if (lane == 0) wave_base_lds[w] = run;
+    __syncthreads();
+    u32 wb = tile_off;
+    for (u32 q = 0; q < w; q++) wb += wave_base_lds[q];
+#pragma unroll
+    for (int k = 0; k < ITEMS; k++) pre[k] += wb;
+}
+
+// Sync events in trace order: s_tidx[q] = event index.
+__global__ __launch_bounds__(WG_THREADS) void k_sync_compact(Bufs b, const u64 *sync_mask) {
+    __shared__ u32 wbase[WAVES];
+    const u32 w = threadIdx.x >> 6, lane = lane_id();
+    const u64 word0 = (u64)blockIdx.x * (TILE / 64);
+    u64 m[ITEMS];
+    u32 pre[ITEMS];
+    wave_mask_prefix(sync_mask, word0, w, wbase, b.tile_s[blockIdx.x], m, pre);
+    const u64 base = (u64)blockIdx.x * TILE + (u64)w * ITEMS * 64;
+#pragma unroll
+    for (int k = 0; k < ITEMS; k++)
+        if ((m[k] >> lane) & 1) b.s_tidx[pre[k]] = (u32)(base + (u64)k * 64 + lane);
+}
+
+// Scatter the sync events into per-thread lists (unordered inside a list; sorted next).
+__global__ void k_sync_scatter(Bufs b) {
+    const u32 n = b.prm->n_sync;
+    for (u32 q = blockIdx.x * blockDim.x + threadIdx.x; q < n; q += gridDim.x * blockDim.x) {
+        const u32 idx = b.s_tidx[q];
+        const uint4 e = b.ev[idx];
+        const u32 p = b.s_cnt[e.y] + atomicAdd(&b.s_fill[e.y], 1u);
+        b.s_pidx[p] = idx;
+        b.s_pq[p] = q;
+        b.s_kind[p] = (uint8_t)(e.z & 15u);
+    }
+}
+
+// One lane per program thread: sort its list by trace index, number its barriers.
+__device__ inline void list_swap(Bufs &b, u32 x, u32 y) {
+    u32 t0 = b.s_pidx[x]; b.s_pidx[x] = b.s_pidx[y]; b.s_pidx[y] = t0;
+    u32 t1 = b.s_pq[x]; b.s_pq[x] = b.s_pq[y]; b.s_pq[y] = t1;
+    uint8_t t2 = b.s_kind[x]; b.s_kind[x] = b.s_kind[y]; b.s_kind[y] = t2;
+}
+__device__ inline void sift_down(Bufs &b, u32 lo, u32 root, u32 n) {
+    for (;;) {
+        u32 c = 2 * root + 1;
+        if (c >= n) return;
+        if (c + 1 < n && b.s_pidx[lo + c + 1] > b.s_pidx[lo + c]) c++;
+        if (b.s_pidx[lo + root] >= b.s_pidx[lo + c]) return;
+        list_swap(b, lo + root, lo + c);
+        root = c;
+    }
+}
+__global__ void k_thread_lists(Bufs b) {
+    for (u32 t = blockIdx.x * blockDim.x + threadIdx.x; t < b.T; t += gridDim.x * blockDim.x) {
+        const u32 lo = b.s_cnt[t], hi = b.s_cnt[t + 1], n = hi - lo;
+        if (n > 1) {
+            if (n <= 32) {
+                for (u32 i = lo + 1; i < hi; i++)
+                    for (u32 j = i; j > lo && b.s_pidx[j - 1] > b.s_pidx[j]; j--) list_swap(b, j - 1, j);
+            } else {
+                for (u32 r = n / 2; r-- > 0;) sift_down(b, lo, r, n);
+                for (u32 e = n - 1; e > 0; e--) { list_swap(b, lo, lo + e); sift_down(b, lo, 0, e); }
+            }
+        }
+        u32 ph = 0;
+        for (u32 p = lo; p < hi; p++) {
+            if (b.s_kind[p] == 4) ph++;
+            b.s_phase[p] = ph;
+            b.s_inv[b.s_pq[p]] = p;
+            b.s_imin[p] = NONE;
+            b.s_flags[p] = 0;
+            b.s_scope[p] = 0;
+        }
+        if (ph >= (1u << 30)) atomicOr(&b.prm->err, ERR_PHASE);
+        if (ph) atomicMax(&b.blk_maxbar[t / b.tpb], ph);
+    }
+}
+
+// Barrier arrivals per (block, instance) and active threads per block.
+__global__ void k_bar_register(Bufs b) {
+    for (u32 t = blockIdx.x * blockDim.x + threadIdx.x; t < b.T; t += gridDim.x * blockDim.x) {
+        const u32 blk = t / b.tpb;
+        if (b.act[t]) atomicAdd(&b.n_active[blk], 1u);
+        const u32 lo = b.s_cnt[t], hi = b.s_cnt[t + 1];
+        u32 k = 0;
+        for (u32 p = lo; p < hi; p++) {
+            if (b.s_kind[p] != 4) continue;
+            const u32 slot = b.inst_off[blk] + k;
+            k++;
+            atomicAdd(&b.inst_cnt[slot], 1u);
+            atomicMax(&b.inst_last[slot], b.s_pidx[p]);
+        }
+    }
+}
+
+// Access elements (location key, index, tid, category | phase), compacted in trace order.  Plain
+// reads and writes also record, per list entry, the first access that follows it.
+__global__ __launch_bounds__(WG_THREADS) void k_elements(Bufs b, const u64 *acc_mask) {
+    __shared__ u32 wbase[WAVES];
+    const u32 w = threadIdx.x >> 6, lane = lane_id();
+    const u64 word0 = (u64)blockIdx.x * (TILE / 64);
+    u64 m[ITEMS];
+    u32 pre[ITEMS];
+    wave_mask_prefix(acc_mask, word0, w, wbase, b.tile_s[b.n_tiles + 1 + blockIdx.x], m, pre);
+    const DevParams *p = b.prm;
+    const u32 gbase = p->gbase, sbase = p->sbase, g_span = p->g_span, s_span = p->s_span;
+    const u32 mode = p->mode;
+    u32 *ekey = b.ekey[0], *eidx = b.eidx[0], *etid = b.etid[0], *einfo = b.einfo[0];
+    const u64 base = (u64)blockIdx.x * TILE + (u64)w * ITEMS * 64;
+#pragma unroll 2
+    for (int k = 0; k < ITEMS; k++) {
+        if (!((m[k] >> lane) & 1)) continue;
+        const u32 idx = (u32)(base + (u64)k * 64 + lane);
+        const uint4 e = b.ev[idx];
+        const u32 kind = e.z & 15u, scope = (e.z >> 4) & 3u, space = (e.z >> 6) & 1u, t = e.y;
+        const u32 blk = t / b.tpb;
+        const u32 key = space ? g_span + blk * s_span + (e.x - sbase) : e.x - gbase;
+        u32 cat;
+        if (kind == 0) cat = CAT_R;
+        else if (kind == 1) cat = CAT_W;
+        else cat = scope == 0 ? CAT_AB : CAT_AD;
+        u32 ph = 0;
+        if (mode & (MODE_BAR | MODE_SYNC)) {
+            const u32 j = list_search(b, t, idx);
+            if (j != NONE) {
+                ph = b.s_phase[j];
+                if (kind <= 1 && b.s_imin[j] > idx) atomicMin(&b.s_imin[j], idx);
+            }
+        }
+        const u32 o = pre[k];
+        ekey[o] = key;
+        eidx[o] = idx;
+        etid[o] = t;
+        einfo[o] = info_make(cat, ph);
+    }
+}
+
+// One lane per program thread: releases/acquires (explicit, or atomics next to a fence with no
+// access in between), knowledge-column flags, and the block-barrier rule for the first event after
+// each of the thread's barriers.
+__global__ void k_thread_sync(Bufs b, u32 *rt_flag) {
+    const u32 mode = b.prm->mode;
+    for (u32 t = blockIdx.x * blockDim.x + threadIdx.x; t < b.T; t += gridDim.x * blockDim.x) {
+        const u32 lo = b.s_cnt[t], hi = b.s_cnt[t + 1], blk = t / b.tpb;
+        u32 has_rt = 0, k = 0;
+        for (u32 p = lo; p < hi; p++) {
+            const u32 kind = b.s_kind[p];
+            if (mode & MODE_SYNC) {
+                uint8_t f = 0, sc = 0;
+                if (kind == 7) { f |= SF_REL; sc |= (uint8_t)((b.ev[b.s_pidx[p]].z >> 4) & 3u); }
+                if (kind == 6) { f |= SF_ACQ; sc |= (uint8_t)(((b.ev[b.s_pidx[p]].z >> 4) & 3u) << 2); }
+                if (kind == 2) {
+                    if (p > lo && b.s_kind[p - 1] == 3 && b.s_imin[p - 1] == NONE) {
+                        f |= SF_REL;
+                        sc |= (uint8_t)((b.ev[b.s_pidx[p - 1]].z >> 4) & 3u);
+                    }
+                    if (p + 1 < hi && b.s_kind[p + 1] == 3 && b.s_imin[p] == NONE) {
+                        f |= SF_ACQ;
+                        sc |= (uint8_t)(((b.ev[b.s_pidx[p + 1]].z >> 4) & 3u) << 2);
+                    }
+                }
+                if (kind == 5) has_rt = 1;
+                if (f & SF_REL) has_rt = 1;
+                b.s_flags[p] = f;
+                b.s_scope[p] = sc;
+            }
+            if (kind == 4) {
+                // the first event of t after its k-th barrier must follow the instance's last arrival
+                const u32 slot = b.inst_off[blk] + k;
+                k++;
+                u32 next = b.s_imin[p];
+                if (p + 1 < hi) next = min(next, b.s_pidx[p + 1]);
+                if (next != NONE) {
+                    const bool complete = b.inst_cnt[slot] == b.n_active[blk];
+                    if (!complete || next < b.inst_last[slot]) atomicMin(&b.prm->first_bad_sync, next);
+                }
+            }
+        }
+        if (rt_flag) rt_flag[t] = has_rt;
+    }
+}
+
+// The warp-barrier rule, once the instances are known (interpreter output): a bad arrival, or the
+// first event after an arrival at an instance that is incomplete or completes later.
+__global__ void k_validate_wbar(Bufs b) {
+    if (!(b.prm->mode & MODE_WBAR)) return;
+    for (u32 t = blockIdx.x * blockDim.x + threadIdx.x; t < b.T; t += gridDim.x * blockDim.x) {
+        const u32 lo = b.s_cnt[t], hi = b.s_cnt[t + 1];
+        for (u32 p = lo; p < hi; p++) {
+            if (b.s_kind[p] != 5) continue;
+            const u32 idx = b.s_pidx[p];
+            if (b.s_flags[p] & SF_BAD_ARRIVAL) { atomicMin(&b.prm->first_bad_sync, idx); continue; }
+            const u32 inst = b.s_winst[p];
+            u32 next = b.s_imin[p];
+            if (p + 1 < hi) next = min(next, b.s_pidx[p + 1]);
+            if (next == NONE) continue;
+            if (inst == NONE) { atomicMin(&b.prm->first_bad_sync, next); continue; }
+            const bool complete = b.winst_arrived[inst] == b.winst_mask[inst];
+            if (!complete || next < b.winst_last[inst]) atomicMin(&b.prm->first_bad_sync, next);
+        }
+    }
+}
+
+// ---------------------------------------------------------------- launchers
+
+void prep_init(const Bufs &b, hipStream_t s) {
+    hipLaunchKernelGGL(k_init_params, dim3(1), dim3(64), 0, s, b.prm);
+    fill_u8(b.act, b.T, 0, s);
+    fill_u32(b.s_cnt, (u64)b.T + 1, 0, s);
+    fill_u32(b.s_fill, b.T, 0, s);
+    fill_u32(b.blk_maxbar, (u64)b.B + 1, 0, s);
+    fill_u32(b.n_active, b.B, 0, s);
+    fill_u32(b.tile_s, 2 * ((u64)b.n_tiles + 1), 0, s);
+}
+
+// ingest + tile scans + plan
+void prep_ingest(const Bufs &b, u64 *sync_mask, u64 *acc_mask, hipStream_t s) {
+    if (b.N) hipLaunchKernelGGL(k_ingest, dim3(b.n_tiles), dim3(WG_THREADS), 0, s, b, sync_mask, acc_mask);
+    scan_exclusive(b.tile_s, (u64)b.n_tiles + 1, b.part, s);
+    scan_exclusive(b.tile_s + b.n_tiles + 1, (u64)b.n_tiles + 1, b.part, s);
+    hipLaunchKernelGGL(k_plan, dim3(1), dim3(64), 0, s, b);
+}
+
+// per-thread sync lists and block-barrier instances
+void prep_sync_lists(const Bufs &b, const u64 *sync_mask, hipStream_t s) {
+    if (b.N) hipLaunchKernelGGL(k_sync_compact, dim3(b.n_tiles), dim3(WG_THREADS), 0, s, b, sync_mask);
+    scan_exclusive(b.s_cnt, (u64)b.T + 1, b.part, s);
+    hipLaunchKernelGGL(k_sync_scatter, dim3(grid_for(b.N)), dim3(256), 0, s, b);
+    hipLaunchKernelGGL(k_thread_lists, dim3(grid_for(b.T, 64)), dim3(64), 0, s, b);
+    scan_exclusive(b.blk_maxbar, (u64)b.B + 1, b.part, s);  // -> instance offsets (inst_off)
+    fill_u32_dyn(b.inst_cnt, b.inst_off + b.B, 0, b.N, s);
+    fill_u32_dyn(b.inst_last, b.inst_off + b.B, 0, b.N, s);
+    hipLaunchKernelGGL(k_bar_register, dim3(grid_for(b.T, 64)), dim3(64), 0, s, b);
+}
+
+void prep_elements(const Bufs &b, const u64 *acc_mask, hipStream_t s) {
+    if (b.N) hipLaunchKernelGGL(k_elements, dim3(b.n_tiles), dim3(WG_THREADS), 0, s, b, acc_mask);
+}
+
+// releases/acquires, knowledge columns (rt_scan gets T+1 words), block-barrier validation
+void prep_thread_sync(const Bufs &b, u32 *rt_scan, hipStream_t s) {
+    fill_u32(rt_scan, (u64)b.T + 1, 0, s);
+    hipLaunchKernelGGL(k_thread_sync, dim3(grid_for(b.T, 64)), dim3(64), 0, s, b, rt_scan);
+    scan_exclusive(rt_scan, (u64)b.T + 1, b.part, s);
+}
+
+void prep_validate_wbar(const Bufs &b, hipStream_t s) {
+    hipLaunchKernelGGL(k_validate_wbar, dim3(grid_for(b.T, 64)), dim3(64), 0, s, b);
+}
+
+}  // namespace rd

@@ -1,0 +1,136 @@
+"""Parity of the HIP checker (through the C ABI) with the CPU oracle, element by element."""
+import os
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+import tracegen
+from golden_io import all_cases
+from tracegen.format import KIND, make_meta
+
+pytestmark = pytest.mark.gpu
+
+CASES = all_cases()
+
+
+@pytest.fixture(scope="module")
+def rc():
+    from paper_2111_12478_amd import RaceChecker
+    c = RaceChecker(0)
+    yield c
+    c.close()
+
+
+def _say(msg):
+    print(msg, flush=True)
+
+
+@pytest.mark.parametrize("case", CASES, ids=[c.name for c in CASES])
+def test_golden(rc, case):
+    _say(f"golden {case.name}")
+    got = rc.check(case.grid, case.events)
+    assert got.status == 0, got
+    np.testing.assert_array_equal(got.pairs, case.expected)
+
+
+@pytest.mark.parametrize("seed", list(range(0, 400)))
+def test_random_traces(rc, seed):
+    grid, ev = tracegen.random_trace(seed)
+    want = oracle.check(grid, ev)
+    got = rc.check(grid, ev)
+    assert got.status == want.status == 0, (seed, got, want)
+    np.testing.assert_array_equal(got.pairs, want.pairs, err_msg=f"seed {seed}")
+
+
+@pytest.mark.parametrize("seed", list(range(1000, 1040)))
+def test_random_traces_larger(rc, seed):
+    grid, ev = tracegen.random_trace(seed, max_blocks=6, max_tpb=40, max_events=6000)
+    want = oracle.check(grid, ev)
+    got = rc.check(grid, ev)
+    assert got.status == want.status == 0, (seed, got, want)
+    np.testing.assert_array_equal(got.pairs, want.pairs, err_msg=f"seed {seed}")
+
+
+def test_tiny_workload_matches_oracle_and_bruteforce(rc):
+    grid, ev, st, plants = tracegen.generate(tracegen.tiny())
+    bf = oracle.bruteforce(grid, ev)
+    want = oracle.check(grid, ev)
+    np.testing.assert_array_equal(bf.pairs, want.pairs)
+    got = rc.check(grid, ev)
+    assert got.status == 0
+    np.testing.assert_array_equal(got.pairs, want.pairs)
+    assert len(plants) == 3 and set(plants.tolist()) <= set(got.pairs.ravel().tolist())
+
+
+@pytest.mark.parametrize("scale", [64, 16])
+def test_large_workload_scaled(rc, scale):
+    cfg = tracegen.large(seed=2, scale=scale)
+    grid, ev, st, plants = tracegen.generate(cfg)
+    _say(f"large/{scale}: {len(ev)} events")
+    want = oracle.check(grid, ev)
+    got = rc.check(grid, ev)
+    assert got.status == want.status == 0
+    np.testing.assert_array_equal(got.pairs, want.pairs)
+    assert set(plants.tolist()) <= set(got.pairs.ravel().tolist())
+
+
+def test_repeat_check_same_trace(rc):
+    grid, ev = tracegen.random_trace(77, max_events=2000)
+    tr, ws, keep = rc.prepare(grid, ev)
+    try:
+        a = rc.run(tr)
+        b = rc.run(tr)
+    finally:
+        from paper_2111_12478_amd import rd_trace_free
+        rd_trace_free(rc.ctx, tr)
+    np.testing.assert_array_equal(a.pairs, b.pairs)
+    np.testing.assert_array_equal(a.pairs, oracle.check(grid, ev).pairs)
+
+
+def test_device_resident_events(rc):
+    import torch
+    grid, ev, _, _ = tracegen.generate(tracegen.tiny(seed=9))
+    dev = torch.from_numpy(ev.view(np.int32)).cuda()
+    got = rc.check(grid, dev)
+    np.testing.assert_array_equal(got.pairs, oracle.check(grid, ev).pairs)
+
+
+def test_empty_and_single(rc):
+    got = rc.check((1, 4), np.zeros((0, 4), np.uint32))
+    assert got.status == 0 and len(got.pairs) == 0
+    got = rc.check((1, 4), np.array([[5, 0, make_meta(KIND["W"]), 0]], np.uint32))
+    assert got.status == 0 and len(got.pairs) == 0
+
+
+def test_one_hot_location_ragged(rc):
+    # every event on one word, sizes that leave ragged tiles
+    for n in (4095, 4097, 12289):
+        rng = np.random.default_rng(n)
+        ev = np.zeros((n, 4), np.uint32)
+        ev[:, 0] = 9
+        ev[:, 1] = rng.integers(0, 64, n)
+        ev[:, 2] = np.where(rng.random(n) < 0.01, make_meta(KIND["W"]), make_meta(KIND["R"]))
+        want = oracle.check((2, 32), ev)
+        got = rc.check((2, 32), ev)
+        np.testing.assert_array_equal(got.pairs, want.pairs)
+
+
+def test_truncated_report(rc):
+    grid, ev, _, _ = tracegen.generate(tracegen.tiny())
+    want = oracle.check(grid, ev).pairs
+    got = rc.check(grid, ev, capacity=5)
+    assert got.status == -4
+    np.testing.assert_array_equal(got.pairs, want[:5])
+
+
+from test_oracle_validation import CASES as VCASES  # noqa: E402
+
+
+@pytest.mark.parametrize("name,grid,events,status,bad", [c for c in VCASES if c[3] != -1 or True][:-0 or None],
+                         ids=[c[0] for c in VCASES])
+def test_validation_matches_oracle(rc, name, grid, events, status, bad):
+    got = rc.check(grid, events)
+    assert got.status == status, (name, got)
+    assert got.bad_index == bad, (name, got)
