@@ -125,6 +125,18 @@ const char *rd_strerror(rd_status status);
  * (UINT64_MAX otherwise) and a message. */
 rd_status rd_last_error(rd_ctx ctx, uint64_t *event_index, char *msg, uint64_t msg_len);
 
+/* Per-kernel timing (diagnostics).  rd_profile_enable(ctx, name) brackets every later launch of the
+ * named kernel ("*" = every kernel, NULL = off) made by rd_check/rd_races on this context with HIP
+ * events on the launch stream; rd_profile_read() waits for them and returns, per kernel name, the
+ * number of launches and their summed duration since the last read (and resets the counters). */
+typedef struct {
+    char name[48];
+    uint32_t launches;
+    double total_ms;
+} rd_kernel_time;
+rd_status rd_profile_enable(rd_ctx ctx, const char *kernel);
+rd_status rd_profile_read(rd_ctx ctx, rd_kernel_time *out, uint32_t capacity, uint32_t *n_out);
+
 #ifdef __cplusplus
 }
 #endif

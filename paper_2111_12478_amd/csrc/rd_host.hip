@@ -181,6 +181,48 @@ static Bufs make_bufs(const Plan &P, char *ws, const void *events_dev, u64 n, u3
     return b;
 }
 
+// ---------------------------------------------------------------- per-kernel timing
+
+struct Profiler {
+    std::string filter;  // "" off, "*" every kernel, else one kernel name
+    struct Rec { const char *name; hipEvent_t a, b; };
+    std::vector<Rec> recs;
+    std::vector<hipEvent_t> pool;
+    size_t used = 0;
+    const char *open_name = nullptr;
+    hipEvent_t open_ev = nullptr;
+    hipEvent_t get() {
+        if (used == pool.size()) {
+            hipEvent_t e;
+            if (hipEventCreate(&e) != hipSuccess) return nullptr;
+            pool.push_back(e);
+        }
+        return pool[used++];
+    }
+};
+static thread_local Profiler *g_prof = nullptr;
+
+void prof_begin(const char *name, hipStream_t s) {
+    Profiler *p = g_prof;
+    if (!p || p->filter.empty()) return;
+    if (p->filter != "*" && p->filter != name) return;
+    hipEvent_t e = p->get();
+    if (!e) return;
+    hipEventRecord(e, s);
+    p->open_name = name;
+    p->open_ev = e;
+}
+void prof_end(hipStream_t s) {
+    Profiler *p = g_prof;
+    if (!p || !p->open_name) return;
+    hipEvent_t e = p->get();
+    if (e) {
+        hipEventRecord(e, s);
+        p->recs.push_back({p->open_name, p->open_ev, e});
+    }
+    p->open_name = nullptr;
+}
+
 hipError_t enqueue_check(const Bufs &b, u64 *masks, u32 *rt_scan, hipStream_t s) {
     u64 *sync_mask = masks, *acc_mask = masks + (u64)b.n_tiles * 64;
     prep_init(b, s);
@@ -206,6 +248,7 @@ struct rd_ctx_s {
     std::mutex mu;
     uint64_t last_index;
     std::string last_msg;
+    Profiler prof;
 };
 
 struct rd_trace_s {
@@ -260,6 +303,7 @@ rd_status rd_init(int hip_device, rd_ctx *out) {
 
 rd_status rd_shutdown(rd_ctx ctx) {
     if (!ctx) return RD_EINVAL;
+    for (hipEvent_t e : ctx->prof.pool) hipEventDestroy(e);
     delete ctx;
     return RD_OK;
 }
@@ -312,7 +356,10 @@ rd_status rd_check(rd_ctx ctx, rd_trace trace, hipStream_t stream) {
     if (!ctx || !trace) return RD_EINVAL;
     if (hipSetDevice(ctx->device) != hipSuccess) return set_err(ctx, RD_EHIP, UINT64_MAX, "hipSetDevice failed");
     trace->stream = stream;
+    Profiler *saved = g_prof;
+    g_prof = ctx->prof.filter.empty() ? nullptr : &ctx->prof;
     const hipError_t e = enqueue_check(trace->bufs, trace->masks, trace->rt_scan, stream);
+    g_prof = saved;
     if (e != hipSuccess) return set_err(ctx, RD_EHIP, UINT64_MAX, hipGetErrorString(e));
     trace->checked = 1;
     return RD_OK;
@@ -343,7 +390,10 @@ rd_status rd_races(rd_ctx ctx, rd_trace trace, rd_pair *out, uint64_t capacity, 
     const u32 m = prm.n_pairs_kept;
     *n_races = m;
     if (!out || !capacity || !m) return m > capacity ? set_err(ctx, RD_ETRUNC, UINT64_MAX, "capacity") : RD_OK;
+    Profiler *saved = g_prof;
+    g_prof = ctx->prof.filter.empty() ? nullptr : &ctx->prof;
     const u32 buf = sort_pairs_host(trace->bufs, m, s);
+    g_prof = saved;
     const u64 k = capacity < m ? capacity : m;
     std::vector<u32> f(k), sec(k);
     if (hipMemcpyAsync(f.data(), trace->bufs.pfirst[buf], 4 * k, hipMemcpyDeviceToHost, s) != hipSuccess ||
@@ -358,6 +408,40 @@ rd_status rd_races(rd_ctx ctx, rd_trace trace, rd_pair *out, uint64_t capacity, 
 rd_status rd_trace_free(rd_ctx ctx, rd_trace trace) {
     if (!ctx || !trace) return RD_EINVAL;
     delete trace;
+    return RD_OK;
+}
+
+rd_status rd_profile_enable(rd_ctx ctx, const char *kernel) {
+    if (!ctx) return RD_EINVAL;
+    ctx->prof.filter = kernel ? kernel : "";
+    ctx->prof.recs.clear();
+    ctx->prof.used = 0;
+    return RD_OK;
+}
+
+rd_status rd_profile_read(rd_ctx ctx, rd_kernel_time *out, uint32_t capacity, uint32_t *n_out) {
+    if (!ctx || !n_out) return RD_EINVAL;
+    Profiler &p = ctx->prof;
+    std::vector<rd_kernel_time> acc;
+    for (auto &r : p.recs) {
+        if (hipEventSynchronize(r.b) != hipSuccess) return RD_EHIP;
+        float ms = 0.f;
+        if (hipEventElapsedTime(&ms, r.a, r.b) != hipSuccess) return RD_EHIP;
+        size_t k = 0;
+        while (k < acc.size() && strcmp(acc[k].name, r.name) != 0) k++;
+        if (k == acc.size()) {
+            rd_kernel_time z;
+            memset(&z, 0, sizeof(z));
+            strncpy(z.name, r.name, sizeof(z.name) - 1);
+            acc.push_back(z);
+        }
+        acc[k].launches++;
+        acc[k].total_ms += ms;
+    }
+    p.recs.clear();
+    p.used = 0;
+    *n_out = (uint32_t)acc.size();
+    for (uint32_t k = 0; k < acc.size() && k < capacity && out; k++) out[k] = acc[k];
     return RD_OK;
 }
 

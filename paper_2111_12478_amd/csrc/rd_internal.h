@@ -165,6 +165,18 @@ struct Layout {
 
 size_t agg_bytes();
 
+// Optional per-kernel timing: when a profiler is active on this host thread, every launch made
+// through RD_LAUNCH whose name matches the profiler's filter is bracketed by two HIP events on the
+// launch stream.
+void prof_begin(const char *name, hipStream_t s);
+void prof_end(hipStream_t s);
+#define RD_LAUNCH(NAME, KERNEL, GRID, BLOCK, SHMEM, STREAM, ...)                       \
+    do {                                                                               \
+        ::rd::prof_begin(NAME, STREAM);                                                \
+        hipLaunchKernelGGL(KERNEL, GRID, BLOCK, SHMEM, STREAM, __VA_ARGS__);            \
+        ::rd::prof_end(STREAM);                                                        \
+    } while (0)
+
 }  // namespace rd
 
 namespace rd {

@@ -364,17 +364,17 @@ static inline unsigned grid_n(u64 n) {
 void interp_run(const Bufs &b, const u32 *rt_scan, hipStream_t s) {
     const DevParams *P = b.prm;
     // tables, only in traces with releases/acquires/warp barriers
-    hipLaunchKernelGGL(k_fill_u32_if, dim3(grid_n(b.T)), dim3(256), 0, s, b.priv, (u64)b.T, 0u, P, MODE_SYNC);
-    hipLaunchKernelGGL(k_fill_u32_if, dim3(grid_n(b.B)), dim3(256), 0, s, b.bk, (u64)b.B, 0u, P, MODE_SYNC);
-    hipLaunchKernelGGL(k_fill_u32_if, dim3(grid_n(b.B)), dim3(256), 0, s, b.priv_head, (u64)b.B, NONE, P, MODE_SYNC);
-    hipLaunchKernelGGL(k_fill_u32_if, dim3(grid_n(b.sv_cap)), dim3(256), 0, s, b.sv_handle, (u64)b.sv_cap, 0u, P, MODE_SYNC);
-    hipLaunchKernelGGL(k_fill_u64_if, dim3(grid_n(b.wo_cap)), dim3(256), 0, s, b.wo_key, (u64)b.wo_cap, ~0ull, P, MODE_WBAR);
-    hipLaunchKernelGGL(k_fill_u32_if, dim3(grid_n(b.wo_cap)), dim3(256), 0, s, b.wi_inst, (u64)b.wo_cap, NONE, P, MODE_WBAR);
-    hipLaunchKernelGGL(k_fill_dyn_if, dim3(grid_n(b.N)), dim3(256), 0, s, b.s_khandle, &P->n_sync, 0u, P, MODE_SYNC);
-    hipLaunchKernelGGL(k_fill_dyn_if, dim3(grid_n(b.N)), dim3(256), 0, s, b.s_winst, &P->n_sync, NONE, P, MODE_WBAR);
-    hipLaunchKernelGGL(k_fill_dyn_if, dim3(grid_n(b.N)), dim3(256), 0, s, b.inst_handle, b.inst_off + b.B, 0u, P, MODE_SYNC);
-    hipLaunchKernelGGL(k_interp, dim3(1), dim3(IT), 0, s, b, rt_scan);
-    hipLaunchKernelGGL(k_know, dim3(grid_n(b.T)), dim3(256), 0, s, b);
+    RD_LAUNCH("k_fill_u32_if", k_fill_u32_if, dim3(grid_n(b.T)), dim3(256), 0, s, b.priv, (u64)b.T, 0u, P, MODE_SYNC);
+    RD_LAUNCH("k_fill_u32_if", k_fill_u32_if, dim3(grid_n(b.B)), dim3(256), 0, s, b.bk, (u64)b.B, 0u, P, MODE_SYNC);
+    RD_LAUNCH("k_fill_u32_if", k_fill_u32_if, dim3(grid_n(b.B)), dim3(256), 0, s, b.priv_head, (u64)b.B, NONE, P, MODE_SYNC);
+    RD_LAUNCH("k_fill_u32_if", k_fill_u32_if, dim3(grid_n(b.sv_cap)), dim3(256), 0, s, b.sv_handle, (u64)b.sv_cap, 0u, P, MODE_SYNC);
+    RD_LAUNCH("k_fill_u64_if", k_fill_u64_if, dim3(grid_n(b.wo_cap)), dim3(256), 0, s, b.wo_key, (u64)b.wo_cap, ~0ull, P, MODE_WBAR);
+    RD_LAUNCH("k_fill_u32_if", k_fill_u32_if, dim3(grid_n(b.wo_cap)), dim3(256), 0, s, b.wi_inst, (u64)b.wo_cap, NONE, P, MODE_WBAR);
+    RD_LAUNCH("k_fill_dyn_if", k_fill_dyn_if, dim3(grid_n(b.N)), dim3(256), 0, s, b.s_khandle, &P->n_sync, 0u, P, MODE_SYNC);
+    RD_LAUNCH("k_fill_dyn_if", k_fill_dyn_if, dim3(grid_n(b.N)), dim3(256), 0, s, b.s_winst, &P->n_sync, NONE, P, MODE_WBAR);
+    RD_LAUNCH("k_fill_dyn_if", k_fill_dyn_if, dim3(grid_n(b.N)), dim3(256), 0, s, b.inst_handle, b.inst_off + b.B, 0u, P, MODE_SYNC);
+    RD_LAUNCH("k_interp", k_interp, dim3(1), dim3(IT), 0, s, b, rt_scan);
+    RD_LAUNCH("k_know", k_know, dim3(grid_n(b.T)), dim3(256), 0, s, b);
 }
 
 }  // namespace rd

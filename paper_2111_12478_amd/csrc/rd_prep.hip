@@ -30,13 +30,13 @@ static inline unsigned grid_for(u64 n, unsigned per = 256, unsigned cap = 4096) 
 }
 
 void fill_u32(u32 *p, u64 n, u32 v, hipStream_t s) {
-    if (n) hipLaunchKernelGGL(k_fill_u32, dim3(grid_for(n)), dim3(256), 0, s, p, n, v);
+    if (n) RD_LAUNCH("k_fill_u32", k_fill_u32, dim3(grid_for(n)), dim3(256), 0, s, p, n, v);
 }
 void fill_u8(uint8_t *p, u64 n, uint8_t v, hipStream_t s) {
-    if (n) hipLaunchKernelGGL(k_fill_u8, dim3(grid_for(n)), dim3(256), 0, s, p, n, v);
+    if (n) RD_LAUNCH("k_fill_u8", k_fill_u8, dim3(grid_for(n)), dim3(256), 0, s, p, n, v);
 }
 void fill_u32_dyn(u32 *p, const u32 *count, u32 v, u64 max_n, hipStream_t s) {
-    hipLaunchKernelGGL(k_fill_u32_dyn, dim3(grid_for(max_n)), dim3(256), 0, s, p, count, v);
+    RD_LAUNCH("k_fill_u32_dyn", k_fill_u32_dyn, dim3(grid_for(max_n)), dim3(256), 0, s, p, count, v);
 }
 
 // Block-wide exclusive scan of one value per thread (256 threads).  Returns the exclusive prefix;
@@ -110,9 +110,9 @@ __global__ __launch_bounds__(256) void k_scan_apply(u32 *data, u64 n, const u32 
 void scan_exclusive(u32 *data, u64 n, u32 *part, hipStream_t s) {
     if (!n) return;
     u32 np = (u32)((n + SCAN_CHUNK - 1) / SCAN_CHUNK);
-    hipLaunchKernelGGL(k_scan_reduce, dim3(np), dim3(256), 0, s, data, n, part);
-    hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(1024), 0, s, part, np);
-    hipLaunchKernelGGL(k_scan_apply, dim3(np), dim3(256), 0, s, data, n, part);
+    RD_LAUNCH("k_scan_reduce", k_scan_reduce, dim3(np), dim3(256), 0, s, data, n, part);
+    RD_LAUNCH("k_scan_top", k_scan_top, dim3(1), dim3(1024), 0, s, part, np);
+    RD_LAUNCH("k_scan_apply", k_scan_apply, dim3(np), dim3(256), 0, s, data, n, part);
 }
 
 // ---------------------------------------------------------------- init
@@ -452,7 +452,7 @@ __global__ void k_validate_wbar(Bufs b) {
 // ---------------------------------------------------------------- launchers
 
 void prep_init(const Bufs &b, hipStream_t s) {
-    hipLaunchKernelGGL(k_init_params, dim3(1), dim3(64), 0, s, b.prm);
+    RD_LAUNCH("k_init_params", k_init_params, dim3(1), dim3(64), 0, s, b.prm);
     fill_u8(b.act, b.T, 0, s);
     fill_u32(b.s_cnt, (u64)b.T + 1, 0, s);
     fill_u32(b.s_fill, b.T, 0, s);
@@ -463,37 +463,37 @@ void prep_init(const Bufs &b, hipStream_t s) {
 
 // ingest + tile scans + plan
 void prep_ingest(const Bufs &b, u64 *sync_mask, u64 *acc_mask, hipStream_t s) {
-    if (b.N) hipLaunchKernelGGL(k_ingest, dim3(b.n_tiles), dim3(WG_THREADS), 0, s, b, sync_mask, acc_mask);
+    if (b.N) RD_LAUNCH("k_ingest", k_ingest, dim3(b.n_tiles), dim3(WG_THREADS), 0, s, b, sync_mask, acc_mask);
     scan_exclusive(b.tile_s, (u64)b.n_tiles + 1, b.part, s);
     scan_exclusive(b.tile_s + b.n_tiles + 1, (u64)b.n_tiles + 1, b.part, s);
-    hipLaunchKernelGGL(k_plan, dim3(1), dim3(64), 0, s, b);
+    RD_LAUNCH("k_plan", k_plan, dim3(1), dim3(64), 0, s, b);
 }
 
 // per-thread sync lists and block-barrier instances
 void prep_sync_lists(const Bufs &b, const u64 *sync_mask, hipStream_t s) {
-    if (b.N) hipLaunchKernelGGL(k_sync_compact, dim3(b.n_tiles), dim3(WG_THREADS), 0, s, b, sync_mask);
+    if (b.N) RD_LAUNCH("k_sync_compact", k_sync_compact, dim3(b.n_tiles), dim3(WG_THREADS), 0, s, b, sync_mask);
     scan_exclusive(b.s_cnt, (u64)b.T + 1, b.part, s);
-    hipLaunchKernelGGL(k_sync_scatter, dim3(grid_for(b.N)), dim3(256), 0, s, b);
-    hipLaunchKernelGGL(k_thread_lists, dim3(grid_for(b.T, 64)), dim3(64), 0, s, b);
+    RD_LAUNCH("k_sync_scatter", k_sync_scatter, dim3(grid_for(b.N)), dim3(256), 0, s, b);
+    RD_LAUNCH("k_thread_lists", k_thread_lists, dim3(grid_for(b.T, 64)), dim3(64), 0, s, b);
     scan_exclusive(b.blk_maxbar, (u64)b.B + 1, b.part, s);  // -> instance offsets (inst_off)
     fill_u32_dyn(b.inst_cnt, b.inst_off + b.B, 0, b.N, s);
     fill_u32_dyn(b.inst_last, b.inst_off + b.B, 0, b.N, s);
-    hipLaunchKernelGGL(k_bar_register, dim3(grid_for(b.T, 64)), dim3(64), 0, s, b);
+    RD_LAUNCH("k_bar_register", k_bar_register, dim3(grid_for(b.T, 64)), dim3(64), 0, s, b);
 }
 
 void prep_elements(const Bufs &b, const u64 *acc_mask, hipStream_t s) {
-    if (b.N) hipLaunchKernelGGL(k_elements, dim3(b.n_tiles), dim3(WG_THREADS), 0, s, b, acc_mask);
+    if (b.N) RD_LAUNCH("k_elements", k_elements, dim3(b.n_tiles), dim3(WG_THREADS), 0, s, b, acc_mask);
 }
 
 // releases/acquires, knowledge columns (rt_scan gets T+1 words), block-barrier validation
 void prep_thread_sync(const Bufs &b, u32 *rt_scan, hipStream_t s) {
     fill_u32(rt_scan, (u64)b.T + 1, 0, s);
-    hipLaunchKernelGGL(k_thread_sync, dim3(grid_for(b.T, 64)), dim3(64), 0, s, b, rt_scan);
+    RD_LAUNCH("k_thread_sync", k_thread_sync, dim3(grid_for(b.T, 64)), dim3(64), 0, s, b, rt_scan);
     scan_exclusive(rt_scan, (u64)b.T + 1, b.part, s);
 }
 
 void prep_validate_wbar(const Bufs &b, hipStream_t s) {
-    hipLaunchKernelGGL(k_validate_wbar, dim3(grid_for(b.T, 64)), dim3(64), 0, s, b);
+    RD_LAUNCH("k_validate_wbar", k_validate_wbar, dim3(grid_for(b.T, 64)), dim3(64), 0, s, b);
 }
 
 }  // namespace rd

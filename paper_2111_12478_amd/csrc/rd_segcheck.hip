@@ -289,11 +289,11 @@ __global__ void k_pairs_kept(Bufs b) {
 }
 
 void segcheck_run(const Bufs &b, const u32 *rt_scan, hipStream_t s) {
-    if (!b.N) { hipLaunchKernelGGL(k_pairs_kept, dim3(1), dim3(64), 0, s, b); return; }
-    hipLaunchKernelGGL(k_seg_reduce, dim3(b.n_tiles), dim3(WG_THREADS), 0, s, b);
-    hipLaunchKernelGGL(k_seg_scan, dim3(1), dim3(WG_THREADS), 0, s, b);
-    hipLaunchKernelGGL(k_seg_check, dim3(b.n_tiles), dim3(WG_THREADS), 0, s, b, rt_scan);
-    hipLaunchKernelGGL(k_pairs_kept, dim3(1), dim3(64), 0, s, b);
+    if (!b.N) { RD_LAUNCH("k_pairs_kept", k_pairs_kept, dim3(1), dim3(64), 0, s, b); return; }
+    RD_LAUNCH("k_seg_reduce", k_seg_reduce, dim3(b.n_tiles), dim3(WG_THREADS), 0, s, b);
+    RD_LAUNCH("k_seg_scan", k_seg_scan, dim3(1), dim3(WG_THREADS), 0, s, b);
+    RD_LAUNCH("k_seg_check", k_seg_check, dim3(b.n_tiles), dim3(WG_THREADS), 0, s, b, rt_scan);
+    RD_LAUNCH("k_pairs_kept", k_pairs_kept, dim3(1), dim3(64), 0, s, b);
 }
 
 }  // namespace rd

@@ -159,10 +159,10 @@ template <int R>
 static void radix_pass(const u32 *kin, const u32 *p0, const u32 *p1, const u32 *p2, u32 *kout, u32 *q0, u32 *q1,
                        u32 *q2, const u32 *n_dev, u32 n_host, u32 shift, const u32 *bits_dev, u32 *hist, u32 *part,
                        u32 n_tiles, hipStream_t s) {
-    hipLaunchKernelGGL(k_radix_hist<R>, dim3(n_tiles), dim3(WG_THREADS), 0, s, kin, n_dev, n_host, shift, bits_dev,
+    RD_LAUNCH("k_radix_hist", k_radix_hist<R>, dim3(n_tiles), dim3(WG_THREADS), 0, s, kin, n_dev, n_host, shift, bits_dev,
                        hist, n_tiles);
     scan_exclusive(hist, (u64)n_tiles << R, part, s);
-    hipLaunchKernelGGL(k_radix_scatter<R>, dim3(n_tiles), dim3(WG_THREADS), 0, s, kin, p0, p1, p2, kout, q0, q1, q2,
+    RD_LAUNCH("k_radix_scatter", k_radix_scatter<R>, dim3(n_tiles), dim3(WG_THREADS), 0, s, kin, p0, p1, p2, kout, q0, q1, q2,
                        n_dev, n_host, shift, bits_dev, hist, n_tiles);
 }
 
