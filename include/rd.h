@@ -126,7 +126,8 @@ const char *rd_strerror(rd_status status);
 rd_status rd_last_error(rd_ctx ctx, uint64_t *event_index, char *msg, uint64_t msg_len);
 
 /* Per-kernel timing (diagnostics).  rd_profile_enable(ctx, name) brackets every later launch of the
- * named kernel ("*" = every kernel, NULL = off) made by rd_check/rd_races on this context with HIP
+ * named kernel ("prefix*" = every kernel whose name starts with prefix, "*" = every kernel, NULL =
+ * off) made by rd_check/rd_races on this context with HIP
  * events on the launch stream; rd_profile_read() waits for them and returns, per kernel name, the
  * number of launches and their summed duration since the last read (and resets the counters). */
 typedef struct {

@@ -21,7 +21,7 @@ u32 sort_pairs_host(const Bufs &b, u32 m, hipStream_t s);
 
 struct Plan {
     Layout L;
-    u64 off_masks, off_rt_scan;
+    u64 off_masks, off_rt_scan, off_tile_stats;
     u32 n_tiles, T, B, radix_bits, pair_tiles, part_words;
     u64 hist_words;
 };
@@ -56,6 +56,7 @@ static Plan make_plan(u64 n, u32 nb, u32 tpb, const rd_limits *lim, bool copy_ev
     L.off_s_cnt = take(4 * (T + 1));
     L.off_s_fill = take(4 * T);
     L.off_tile_s = take(4 * 2 * ((u64)n_tiles + 1));
+    P.off_tile_stats = take(4ull * TILE_STATS * ((u64)n_tiles + 1));
     P.off_masks = take(8 * 2 * (u64)n_tiles * 64);
     L.off_s_tidx = take(4 * N1);
     L.off_s_pidx = take(4 * N1);
@@ -120,6 +121,7 @@ static Bufs make_bufs(const Plan &P, char *ws, const void *events_dev, u64 n, u3
     b.s_cnt = (u32 *)(ws + L.off_s_cnt);
     b.s_fill = (u32 *)(ws + L.off_s_fill);
     b.tile_s = (u32 *)(ws + L.off_tile_s);
+    b.tile_stats = (u32 *)(ws + P.off_tile_stats);
     b.s_tidx = (u32 *)(ws + L.off_s_tidx);
     b.s_pidx = (u32 *)(ws + L.off_s_pidx);
     b.s_pq = (u32 *)(ws + L.off_s_pq);
@@ -178,6 +180,11 @@ static Bufs make_bufs(const Plan &P, char *ws, const void *events_dev, u64 n, u3
     b.ws = warp_size;
     b.n_tiles = P.n_tiles;
     b.radix_bits = P.radix_bits;
+    u32 l = 0;
+    while (((u64)1 << l) < tpb) l++;
+    b.div_m = (u32)((((u64)1 << 32) * (((u64)1 << l) - tpb)) / tpb + 1);
+    b.div_s1 = l < 1 ? l : 1;
+    b.div_s2 = l > 1 ? l - 1 : 0;
     return b;
 }
 
@@ -205,7 +212,12 @@ static thread_local Profiler *g_prof = nullptr;
 void prof_begin(const char *name, hipStream_t s) {
     Profiler *p = g_prof;
     if (!p || p->filter.empty()) return;
-    if (p->filter != "*" && p->filter != name) return;
+    const std::string &f = p->filter;
+    if (f.back() == '*') {  // prefix match ("*" alone matches every kernel)
+        if (strncmp(name, f.c_str(), f.size() - 1) != 0) return;
+    } else if (f != name) {
+        return;
+    }
     hipEvent_t e = p->get();
     if (!e) return;
     hipEventRecord(e, s);

@@ -21,6 +21,7 @@ constexpr int WG_THREADS = 256;
 constexpr int WAVES = WG_THREADS / 64;
 constexpr int ITEMS = 16;
 constexpr int TILE = WG_THREADS * ITEMS;  // 4096
+constexpr int TILE_STATS = 16;            // per-tile ingest statistics (words)
 
 // element categories (conflict classes of an access)
 enum { CAT_R = 0, CAT_W = 1, CAT_AD = 2, CAT_AB = 3 };  // read, write, device/system atomic, block atomic
@@ -66,7 +67,8 @@ struct DevParams {
     u32 n_pairs;           // pairs found (may exceed the buffer)
     u32 n_pairs_kept;      // min(n_pairs, capacity)
     u32 n_winst;           // warp-barrier instances
-    u32 pad[3];
+    u32 pad0;
+    unsigned long long n_chunks;  // queued slow-path chunks of the segment check (8-byte aligned)
 };
 
 enum : u32 {
@@ -83,6 +85,7 @@ struct Bufs {
     u32 *s_cnt;             // [T+1] sync entries per thread -> exclusive offsets
     u32 *s_fill;            // [T]
     u32 *tile_s;            // [n_tiles+1] sync events per ingest tile -> offsets
+    u32 *tile_stats;        // [n_tiles * TILE_STATS] ingest statistics per tile
     u32 *s_tidx;            // [N] sync events in trace order (event index)
     u32 *s_pidx;            // [N] per-thread sync lists (event index), trace order inside a thread
     u32 *s_pq;              // [N] trace-order position of each list entry
@@ -134,6 +137,7 @@ struct Bufs {
     u64 max_pairs;
     // shape
     u32 N, T, B, tpb, ws;
+    u32 div_m, div_s1, div_s2;  // tid / tpb as a multiply-high and shifts
     u32 n_tiles;            // ceil(N / TILE)
     u32 radix_bits;         // 8 or 11
     u32 sorted_buf;         // which element buffer holds the sorted elements (set by the host plan)
@@ -146,6 +150,14 @@ __device__ inline u32 lane_id() { return __lane_id(); }
 __device__ inline u64 lanemask_lt() { return (u64(1) << lane_id()) - 1; }
 __device__ inline u64 ballot(bool p) { return __ballot(p); }
 __device__ inline u32 popc64(u64 x) { return (u32)__popcll(x); }
+
+// Block of a thread: tid / tpb by multiplication (division by an invariant integer: with
+// l = ceil(log2 tpb) and m = floor(2^32 (2^l - tpb) / tpb) + 1, q = (t1 + ((n - t1) >> s1)) >> s2
+// where t1 = mulhi(m, n), s1 = min(l, 1), s2 = max(l - 1, 0); exact for every 32-bit n).
+__device__ inline u32 block_of(const Bufs &b, u32 tid) {
+    const u32 t1 = __umulhi(b.div_m, tid);
+    return (t1 + ((tid - t1) >> b.div_s1)) >> b.div_s2;
+}
 
 // ---------------------------------------------------------------- host side
 

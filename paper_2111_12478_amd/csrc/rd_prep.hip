@@ -196,24 +196,43 @@ __global__ __launch_bounds__(WG_THREADS) void k_ingest(Bufs b, u64 *sync_mask, u
             ts0 = min(ts0, lds_misc[q][3]); ts1 = max(ts1, lds_misc[q][4]);
             tns += lds_misc[q][5]; tna += lds_misc[q][6];
         }
-        DevParams *p = b.prm;
-        if (tb != NONE) atomicMin(&p->first_bad_record, tb);
-        if (tg0 != NONE) { atomicMin(&p->gmin, tg0); atomicMax(&p->gmax, tg1); }
-        if (ts0 != NONE) { atomicMin(&p->smin, ts0); atomicMax(&p->smax, ts1); }
+        // per-tile statistics, reduced by k_plan (no same-address atomics across tiles)
+        u32 *st = b.tile_stats + (u64)blockIdx.x * TILE_STATS;
+        st[0] = tb; st[1] = tg0; st[2] = tg1; st[3] = ts0; st[4] = ts1;
         for (int q = 0; q < 8; q++) {
             u32 c = 0;
             for (int ww = 0; ww < WAVES; ww++) c += lds_cnt[q][ww];
-            if (c) atomicAdd(&p->kind_count[q], c);
+            st[5 + q] = c;
         }
         b.tile_s[blockIdx.x] = tns;
         b.tile_s[b.n_tiles + 1 + blockIdx.x] = tna;  // access counts live after the sync counts
     }
 }
 
-// Location-key plan and the mode of the check (one thread).
-__global__ void k_plan(Bufs b) {
+// Reduces the per-tile ingest statistics, then plans the location key and the mode of the check.
+__global__ __launch_bounds__(256) void k_plan(Bufs b) {
+    __shared__ u32 red[256][TILE_STATS];
+    u32 acc[TILE_STATS];
+    acc[0] = NONE; acc[1] = NONE; acc[2] = 0; acc[3] = NONE; acc[4] = 0;
+    for (int q = 5; q < TILE_STATS; q++) acc[q] = 0;
+    for (u32 t = threadIdx.x; t < b.n_tiles; t += 256) {
+        const u32 *st = b.tile_stats + (u64)t * TILE_STATS;
+        acc[0] = min(acc[0], st[0]); acc[1] = min(acc[1], st[1]); acc[2] = max(acc[2], st[2]);
+        acc[3] = min(acc[3], st[3]); acc[4] = max(acc[4], st[4]);
+        for (int q = 5; q < 13; q++) acc[q] += st[q];
+    }
+    for (int q = 0; q < TILE_STATS; q++) red[threadIdx.x][q] = acc[q];
+    __syncthreads();
     if (threadIdx.x) return;
+    for (u32 x = 1; x < 256; x++) {
+        acc[0] = min(acc[0], red[x][0]); acc[1] = min(acc[1], red[x][1]); acc[2] = max(acc[2], red[x][2]);
+        acc[3] = min(acc[3], red[x][3]); acc[4] = max(acc[4], red[x][4]);
+        for (int q = 5; q < 13; q++) acc[q] += red[x][q];
+    }
     DevParams *p = b.prm;
+    p->first_bad_record = acc[0];
+    p->gmin = acc[1]; p->gmax = acc[2]; p->smin = acc[3]; p->smax = acc[4];
+    for (int q = 0; q < 8; q++) p->kind_count[q] = acc[5 + q];
     p->n_sync = b.tile_s[b.n_tiles];
     p->n_acc = b.tile_s[2 * b.n_tiles + 1];
     u64 gs = p->gmin != NONE ? (u64)p->gmax - p->gmin + 1 : 0;
@@ -324,19 +343,51 @@ __global__ void k_thread_lists(Bufs b) {
     }
 }
 
-// Barrier arrivals per (block, instance) and active threads per block.
+// Barrier arrivals per (block, instance) and active threads per block.  Lanes of a wavefront are
+// consecutive threads, mostly of one block, so arrivals are aggregated per (instance) across the
+// wave before the device atomics.
 __global__ void k_bar_register(Bufs b) {
-    for (u32 t = blockIdx.x * blockDim.x + threadIdx.x; t < b.T; t += gridDim.x * blockDim.x) {
-        const u32 blk = t / b.tpb;
-        if (b.act[t]) atomicAdd(&b.n_active[blk], 1u);
-        const u32 lo = b.s_cnt[t], hi = b.s_cnt[t + 1];
-        u32 k = 0;
-        for (u32 p = lo; p < hi; p++) {
-            if (b.s_kind[p] != 4) continue;
-            const u32 slot = b.inst_off[blk] + k;
-            k++;
-            atomicAdd(&b.inst_cnt[slot], 1u);
-            atomicMax(&b.inst_last[slot], b.s_pidx[p]);
+    const u32 lane = lane_id();
+    for (u32 t0 = blockIdx.x * blockDim.x; t0 < b.T; t0 += gridDim.x * blockDim.x) {
+        const u32 t = t0 + threadIdx.x;
+        const bool in = t < b.T;
+        const u32 blk = in ? block_of(b, t) : 0;
+        // active threads per block
+        {
+            bool a = in && b.act[t];
+            u64 pending = ballot(a);
+            while (pending) {
+                const u32 leader = __builtin_ctzll(pending);
+                const u32 lb = __shfl(blk, leader, 64);
+                const u64 m = ballot(a && blk == lb);
+                if (lane == leader) atomicAdd(&b.n_active[lb], popc64(m));
+                if (blk == lb) a = false;
+                pending &= ~m;
+            }
+        }
+        u32 p = in ? b.s_cnt[t] : 0;
+        const u32 hi = in ? b.s_cnt[t + 1] : 0;
+        for (u32 k = 0;; k++) {
+            // this lane's k-th barrier arrival, if any
+            while (p < hi && b.s_kind[p] != 4) p++;
+            bool has = p < hi;
+            if (!__any(has)) break;
+            const u32 slot = has ? b.inst_off[blk] + k : 0;
+            const u32 idx = has ? b.s_pidx[p] : 0;
+            u64 pending = ballot(has);
+            while (pending) {
+                const u32 leader = __builtin_ctzll(pending);
+                const u32 ls = __shfl(slot, leader, 64);
+                const bool mine = has && slot == ls;
+                const u64 m = ballot(mine);
+                u32 mx = mine ? idx : 0;
+#pragma unroll
+                for (int d = 32; d >= 1; d >>= 1) mx = max(mx, (u32)__shfl_xor((int)mx, d, 64));
+                if (lane == leader) { atomicAdd(&b.inst_cnt[ls], popc64(m)); atomicMax(&b.inst_last[ls], mx); }
+                if (mine) has = false;
+                pending &= ~m;
+            }
+            if (p < hi) p++;
         }
     }
 }
@@ -361,7 +412,7 @@ __global__ __launch_bounds__(WG_THREADS) void k_elements(Bufs b, const u64 *acc_
         const u32 idx = (u32)(base + (u64)k * 64 + lane);
         const uint4 e = b.ev[idx];
         const u32 kind = e.z & 15u, scope = (e.z >> 4) & 3u, space = (e.z >> 6) & 1u, t = e.y;
-        const u32 blk = t / b.tpb;
+        const u32 blk = block_of(b, t);
         const u32 key = space ? g_span + blk * s_span + (e.x - sbase) : e.x - gbase;
         u32 cat;
         if (kind == 0) cat = CAT_R;
@@ -466,7 +517,7 @@ void prep_ingest(const Bufs &b, u64 *sync_mask, u64 *acc_mask, hipStream_t s) {
     if (b.N) RD_LAUNCH("k_ingest", k_ingest, dim3(b.n_tiles), dim3(WG_THREADS), 0, s, b, sync_mask, acc_mask);
     scan_exclusive(b.tile_s, (u64)b.n_tiles + 1, b.part, s);
     scan_exclusive(b.tile_s + b.n_tiles + 1, (u64)b.n_tiles + 1, b.part, s);
-    RD_LAUNCH("k_plan", k_plan, dim3(1), dim3(64), 0, s, b);
+    RD_LAUNCH("k_plan", k_plan, dim3(1), dim3(256), 0, s, b);
 }
 
 // per-thread sync lists and block-barrier instances

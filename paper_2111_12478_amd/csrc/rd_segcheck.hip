@@ -10,89 +10,109 @@
 //                                                 -> ordered (rule iv, composed with i and iii)
 //   otherwise                                     -> race.
 //
-// Most accesses cannot race at all, and a prefix summary decides that in O(1): for the part of the
-// segment before b it keeps, per conflict category (read, write, device atomic, block atomic), up to
-// two distinct blocks, and for the trailing run of accesses with b's block and phase, up to two
-// distinct threads.  If every earlier access of the segment is in b's block, only accesses of b's
-// run (same block and phase) can race with b, and they can only if a conflicting category has a
-// thread other than b's.  Otherwise b is checked against the earlier accesses one by one.
-// The summaries are a segmented scan: per-tile totals, one scan over tiles, then the tile pass.
+// Most accesses cannot race at all, and a prefix summary decides that in O(1).  For the part of the
+// segment before b it keeps the categories present (read, write, device atomic, block atomic) and
+// whether more than one block appears; for the trailing run of accesses with b's block and phase it
+// keeps, for write-ish, plain and all accesses, one thread and whether a second one appears.  If
+// every earlier access of the segment is in b's block, only b's run can race with b (earlier phases
+// of a block happen before later ones), and only if a conflicting class there has another thread.
+// Otherwise b is checked against the earlier accesses one by one (the exact predicate above).
+// The summaries form a segmented scan: per-tile totals, one scan over tiles, then the tile pass.
 #include "rd_internal.h"
 #include "rd_kernels.h"
 
 namespace rd {
 
+enum : u32 {
+    F_NONEMPTY = 1u,
+    F_HEAD = 2u,        // a location change between two elements of the range
+    F_RUNWHOLE = 4u,    // every element of the range is in one run (location, block, phase)
+    F_BLKMULTI = 8u,    // two or more blocks in the last segment of the range
+    F_CAT0 = 16u,       // bit (4 + category): category present in the last segment
+    F_TWA_MULTI = 256u, // two or more threads among the write-ish accesses of the trailing run
+    F_TNA_MULTI = 512u, // ... among the plain (non-atomic) accesses
+    F_TALL_MULTI = 1024u,
+    F_CATS = 0xf0u,
+};
+
 struct Agg {
-    u32 nonempty;
-    u32 head_inside;     // a location change between two elements of the range
     u32 first_key, last_key;
     u32 run_blk, run_ph;
-    u32 run_whole;       // every element of the range has the same location, block and phase
-    u32 cb[4][2];        // per category: up to two distinct blocks in the last segment of the range
-    u32 rt[4][2];        // per category: up to two distinct threads in the trailing run
+    u32 blk;             // a block of the last segment
+    u32 twa, tna, tall;  // a thread of the trailing run: write-ish, plain, any (NONE if none)
+    u32 fl;
+    u32 first_pos;       // sorted position of the first element of the range
+    u32 seg_pos;         // ... of the first element of the last segment
+    u32 run_pos;         // ... of the first element of the trailing run
 };
 
 size_t agg_bytes() { return sizeof(Agg); }
 
-__device__ inline void set2_add(u32 s[2], u32 v) {
-    if (v == NONE) return;
-    if (s[0] == NONE) s[0] = v;
-    else if (s[0] != v && s[1] == NONE) s[1] = v;
+// a set summarised by one member and a "more than one member" flag
+__device__ inline void set1_merge(u32 &v, u32 &fl, u32 multi_bit, u32 ov, u32 ofl) {
+    if ((ofl & multi_bit) || (ov != NONE && v != NONE && ov != v)) fl |= multi_bit;
+    if (v == NONE) v = ov;
 }
-__device__ inline bool set2_has_other(const u32 s[2], u32 v) {
-    return (s[0] != NONE && s[0] != v) || (s[1] != NONE && s[1] != v);
+__device__ inline bool set1_has_other(u32 v, u32 fl, u32 multi_bit, u32 x) {
+    return (fl & multi_bit) || (v != NONE && v != x);
 }
-__device__ inline bool set2_empty(const u32 s[2]) { return s[0] == NONE; }
 
 __device__ inline void agg_empty(Agg &a) {
-    a.nonempty = 0; a.head_inside = 0; a.first_key = a.last_key = 0;
-    a.run_blk = a.run_ph = 0; a.run_whole = 1;
-#pragma unroll
-    for (int c = 0; c < 4; c++) { a.cb[c][0] = a.cb[c][1] = NONE; a.rt[c][0] = a.rt[c][1] = NONE; }
+    a.first_key = a.last_key = 0;
+    a.run_blk = a.run_ph = 0;
+    a.blk = a.twa = a.tna = a.tall = NONE;
+    a.fl = F_RUNWHOLE;
+    a.first_pos = a.seg_pos = a.run_pos = 0;
 }
-__device__ inline void agg_one(Agg &a, u32 key, u32 blk, u32 ph, u32 tid, u32 cat) {
-    agg_empty(a);
-    a.nonempty = 1; a.first_key = a.last_key = key; a.run_blk = blk; a.run_ph = ph;
-    a.cb[cat][0] = blk; a.rt[cat][0] = tid;
+__device__ inline void agg_one(Agg &a, u32 key, u32 blk, u32 ph, u32 tid, u32 cat, u32 pos) {
+    a.first_pos = a.seg_pos = a.run_pos = pos;
+    a.first_key = a.last_key = key;
+    a.run_blk = blk; a.run_ph = ph; a.blk = blk;
+    a.tall = tid;
+    a.twa = cat != CAT_R ? tid : NONE;
+    a.tna = cat <= CAT_W ? tid : NONE;
+    a.fl = F_NONEMPTY | F_RUNWHOLE | (F_CAT0 << cat);
 }
 // r := l (+) r, l before r
 __device__ inline void agg_combine(const Agg &l, Agg &r) {
-    if (!l.nonempty) return;
-    if (!r.nonempty) { r = l; return; }
-    const bool boundary = r.head_inside || r.first_key != l.last_key;
-    const bool extend = !boundary && r.run_whole && r.run_blk == l.run_blk && r.run_ph == l.run_ph;
+    if (!(l.fl & F_NONEMPTY)) return;
+    if (!(r.fl & F_NONEMPTY)) { r = l; return; }
+    const bool keychange = r.first_key != l.last_key;
+    const bool boundary = (r.fl & F_HEAD) || keychange;
+    const bool extend = !boundary && (r.fl & F_RUNWHOLE) && r.run_blk == l.run_blk && r.run_ph == l.run_ph;
+    u32 fl = F_NONEMPTY | ((l.fl | r.fl) & F_HEAD) | (keychange ? F_HEAD : 0u);
     if (!boundary) {
-#pragma unroll
-        for (int c = 0; c < 4; c++) {
-            u32 s[2] = {l.cb[c][0], l.cb[c][1]};
-            set2_add(s, r.cb[c][0]); set2_add(s, r.cb[c][1]);
-            r.cb[c][0] = s[0]; r.cb[c][1] = s[1];
-        }
+        u32 bfl = (l.fl | r.fl) & F_BLKMULTI;
+        u32 bv = l.blk;
+        set1_merge(bv, bfl, F_BLKMULTI, r.blk, 0);
+        fl |= bfl | ((l.fl | r.fl) & F_CATS);
+        r.blk = bv;
+    } else {
+        fl |= r.fl & (F_BLKMULTI | F_CATS);
     }
     if (extend) {
-#pragma unroll
-        for (int c = 0; c < 4; c++) {
-            u32 s[2] = {l.rt[c][0], l.rt[c][1]};
-            set2_add(s, r.rt[c][0]); set2_add(s, r.rt[c][1]);
-            r.rt[c][0] = s[0]; r.rt[c][1] = s[1];
-        }
+        u32 tfl = (l.fl | r.fl) & (F_TWA_MULTI | F_TNA_MULTI | F_TALL_MULTI);
+        u32 a = l.twa, b = l.tna, c = l.tall;
+        set1_merge(a, tfl, F_TWA_MULTI, r.twa, 0);
+        set1_merge(b, tfl, F_TNA_MULTI, r.tna, 0);
+        set1_merge(c, tfl, F_TALL_MULTI, r.tall, 0);
+        r.twa = a; r.tna = b; r.tall = c;
+        fl |= tfl | (l.fl & F_RUNWHOLE);
+    } else {
+        fl |= r.fl & (F_TWA_MULTI | F_TNA_MULTI | F_TALL_MULTI);
     }
-    r.run_whole = l.run_whole && extend;
-    r.head_inside = l.head_inside || r.head_inside || (r.first_key != l.last_key);
+    r.fl = fl;
     r.first_key = l.first_key;
-}
-
-struct Elem { u32 key, idx, tid, info; };
-
-__device__ inline Elem load_elem(const u32 *k, const u32 *i, const u32 *t, const u32 *f, u32 pos) {
-    Elem e; e.key = k[pos]; e.idx = i[pos]; e.tid = t[pos]; e.info = f[pos];
-    return e;
+    if (!boundary) r.seg_pos = l.seg_pos;
+    if (extend) r.run_pos = l.run_pos;
+    r.first_pos = l.first_pos;
 }
 
 // ---------------------------------------------------------------- shared pieces
 
 struct SegCtx {
     const u32 *k, *i, *t, *f;
+    u32 *cpos, *clo, *chi;  // slow-path chunks: b's position, and the range [lo, hi) of earlier positions
     u32 n;
 };
 
@@ -101,25 +121,54 @@ __device__ inline SegCtx seg_ctx(const Bufs &b) {
     const u32 bits = b.prm->key_bits, passes = (bits + b.radix_bits - 1) / b.radix_bits;
     const u32 c = passes & 1;
     SegCtx s; s.k = b.ekey[c]; s.i = b.eidx[c]; s.t = b.etid[c]; s.f = b.einfo[c]; s.n = b.prm->n_acc;
+    s.cpos = b.ekey[c ^ 1]; s.clo = b.etid[c ^ 1]; s.chi = b.einfo[c ^ 1];
     return s;
 }
 
-// Per-thread contiguous run of items: thread x of tile owns [tile*TILE + x*ITEMS, +ITEMS).
-__device__ inline void thread_agg(const SegCtx &s, const Bufs &b, u64 base, Agg &acc) {
-    agg_empty(acc);
-    for (int q = 0; q < ITEMS; q++) {
-        const u64 pos = base + q;
-        if (pos >= s.n) break;
-        const u32 info = s.f[pos], tid = s.t[pos];
-        Agg one;
-        agg_one(one, s.k[pos], tid / b.tpb, info_phase(info), tid, info_cat(info));
-        agg_combine(acc, one);
-        acc = one;
+// Thread x of a tile owns the ITEMS consecutive elements [tile*TILE + x*ITEMS, +ITEMS).
+struct Items {
+    u32 key[ITEMS], tid[ITEMS], info[ITEMS];
+};
+
+__device__ inline void load_items(const SegCtx &s, u64 base, Items &it) {
+    if (base + ITEMS <= s.n) {
+#pragma unroll
+        for (int q = 0; q < ITEMS; q += 4) {
+            const uint4 k4 = *(const uint4 *)(s.k + base + q);
+            const uint4 t4 = *(const uint4 *)(s.t + base + q);
+            const uint4 f4 = *(const uint4 *)(s.f + base + q);
+            it.key[q] = k4.x; it.key[q + 1] = k4.y; it.key[q + 2] = k4.z; it.key[q + 3] = k4.w;
+            it.tid[q] = t4.x; it.tid[q + 1] = t4.y; it.tid[q + 2] = t4.z; it.tid[q + 3] = t4.w;
+            it.info[q] = f4.x; it.info[q + 1] = f4.y; it.info[q + 2] = f4.z; it.info[q + 3] = f4.w;
+        }
+    } else {
+#pragma unroll
+        for (int q = 0; q < ITEMS; q++) {
+            const u64 pos = base + q;
+            const bool in = pos < s.n;
+            it.key[q] = in ? s.k[pos] : 0;
+            it.tid[q] = in ? s.t[pos] : 0;
+            it.info[q] = in ? s.f[pos] : 0;
+        }
     }
 }
 
-// Block-wide (256 threads) exclusive scan of Aggs in LDS; returns this thread's exclusive prefix
-// and writes the block total into *total (when non-null).
+__device__ inline void items_agg(const Bufs &b, const Items &it, u32 cnt, u32 base, Agg &acc) {
+    agg_empty(acc);
+#pragma unroll
+    for (int q = 0; q < ITEMS; q++) {
+        if ((u32)q < cnt) {
+            Agg one;
+            agg_one(one, it.key[q], block_of(b, it.tid[q]), info_phase(it.info[q]), it.tid[q], info_cat(it.info[q]),
+                    base + q);
+            agg_combine(acc, one);
+            acc = one;
+        }
+    }
+}
+
+// Block-wide (256 threads) exclusive scan of Aggs in LDS; `mine` becomes this thread's exclusive
+// prefix, *total (when non-null) the block total.
 __device__ inline void block_exscan_agg(Agg &mine, Agg *buf /* 2*256 */, Agg *total) {
     const u32 x = threadIdx.x;
     buf[x] = mine;
@@ -140,17 +189,27 @@ __device__ inline void block_exscan_agg(Agg &mine, Agg *buf /* 2*256 */, Agg *to
     mine = ex;
 }
 
+__device__ inline u32 items_in(const SegCtx &s, u64 base) {
+    return base >= s.n ? 0u : (u32)min((u64)ITEMS, s.n - base);
+}
+
 __global__ __launch_bounds__(WG_THREADS) void k_seg_reduce(Bufs b) {
     __shared__ Agg buf[2 * WG_THREADS];
     const SegCtx s = seg_ctx(b);
     Agg *tile_agg = (Agg *)b.tile_agg;
     const u64 tile0 = (u64)blockIdx.x * TILE;
     if (tile0 >= s.n) return;
+    const u64 base = tile0 + (u64)threadIdx.x * ITEMS;
+    Items it;
+    load_items(s, base, it);
     Agg mine;
-    thread_agg(s, b, tile0 + (u64)threadIdx.x * ITEMS, mine);
-    Agg total;
-    block_exscan_agg(mine, buf, &total);
-    if (threadIdx.x == 0) tile_agg[blockIdx.x] = total;
+    items_agg(b, it, items_in(s, base), (u32)base, mine);
+    Agg own = mine;
+    block_exscan_agg(mine, buf, nullptr);
+    if (threadIdx.x == WG_THREADS - 1) {  // tile total = last thread's prefix (+) its own items
+        agg_combine(mine, own);
+        tile_agg[blockIdx.x] = own;
+    }
 }
 
 // exclusive scan over the tile totals (one workgroup)
@@ -179,20 +238,25 @@ __device__ inline bool conflicts(u32 ca, u32 ba, u32 cb, u32 bb) {
     return true;
 }
 
-struct BCtx {
-    u32 idx, tid, blk, ph, cat;
-    u32 h;        // knowledge vector of b's thread at b (NONE until looked up)
-};
+// categories of earlier accesses that can conflict with an access of category c
+__device__ inline u32 conflict_cats(u32 c) {
+    // R: W AD AB ; W: all ; AD: R W ; AB: R W AB (block atomics of other blocks)
+    const u32 R = F_CAT0 << CAT_R, W = F_CAT0 << CAT_W, AD = F_CAT0 << CAT_AD, AB = F_CAT0 << CAT_AB;
+    return c == CAT_R ? (W | AD | AB) : c == CAT_W ? (R | W | AD | AB) : c == CAT_AD ? (R | W) : (R | W | AB);
+}
 
-__device__ inline bool happens_before(const Bufs &b, const u32 *rt_scan, BCtx &bc, u32 ta, u32 ba, u32 pha, u32 ia) {
-    if (ba == bc.blk && pha < bc.ph) return true;
+// Does a (thread ta, block ba, phase pha, index ia) happen before b?  h: knowledge vector of b's
+// thread at b, looked up on first use (NONE until then).
+__device__ inline bool happens_before(const Bufs &b, const u32 *rt_scan, u32 bidx, u32 btid, u32 bblk, u32 bph,
+                                      u32 &h, u32 ta, u32 ba, u32 pha, u32 ia) {
+    if (ba == bblk && pha < bph) return true;
     if (!(b.prm->mode & MODE_SYNC)) return false;
-    if (bc.h == NONE) {
-        const u32 j = list_search(b, bc.tid, bc.idx);
-        bc.h = j == NONE ? 0u : b.s_know[j];
+    if (h == NONE) {
+        const u32 j = list_search(b, btid, bidx);
+        h = j == NONE ? 0u : b.s_know[j];
     }
-    if (!bc.h) return false;
-    const u32 *V = b.pool + (u64)bc.h * b.prm->D;
+    if (!h) return false;
+    const u32 *V = b.pool + (u64)h * b.prm->D;
     if (V[ba] > pha) return true;
     if (rt_scan[ta + 1] > rt_scan[ta]) {
         const u32 col = b.B + rt_scan[ta];
@@ -201,83 +265,226 @@ __device__ inline bool happens_before(const Bufs &b, const u32 *rt_scan, BCtx &b
     return false;
 }
 
-__device__ inline void emit(const Bufs &b, u32 first, u32 second) {
-    const u32 slot = atomicAdd(&b.prm->n_pairs, 1u);
-    if (slot < b.max_pairs) { b.pfirst[0][slot] = first; b.psecond[0][slot] = second; }
-    else atomicOr(&b.prm->err, ERR_PAIRS);
-}
-
-// Checks b against earlier accesses of its segment, walking back from pos-1.
-// group_only: stop at the first access outside b's (block, phase) run.
-__device__ inline void slow_check(const Bufs &b, const SegCtx &s, const u32 *rt_scan, u32 pos, u32 key, BCtx &bc,
-                                  bool group_only) {
-    for (u32 q = pos; q-- > 0;) {
-        if (s.k[q] != key) break;
-        const u32 ta = s.t[q], info = s.f[q];
-        const u32 ba = ta / b.tpb, pha = info_phase(info), ca = info_cat(info);
-        if (group_only && (ba != bc.blk || pha != bc.ph)) break;
-        if (ta == bc.tid) continue;
-        if (!conflicts(ca, ba, bc.cat, bc.blk)) continue;
-        const u32 ia = s.i[q];
-        if (happens_before(b, rt_scan, bc, ta, ba, pha, ia)) continue;
-        emit(b, ia, bc.idx);
+// Appends (first, second) for every lane with `want`; one atomic per wavefront.  All lanes of the
+// wavefront must call it.
+__device__ inline void emit_wave(const Bufs &b, bool want, u32 first, u32 second) {
+    const u64 m = ballot(want);
+    if (!m) return;
+    const u32 leader = (u32)__builtin_ctzll(m);
+    u32 base = 0;
+    if (lane_id() == leader) base = atomicAdd(&b.prm->n_pairs, popc64(m));
+    base = __shfl(base, leader, 64);
+    if (want) {
+        const u32 slot = base + popc64(m & lanemask_lt());
+        if (slot < b.max_pairs) { b.pfirst[0][slot] = first; b.psecond[0][slot] = second; }
+        else atomicOr(&b.prm->err, ERR_PAIRS);
     }
 }
 
+// Checks b (at sorted position pos) against the earlier accesses of its segment, with the whole
+// wavefront: each step examines the 64 positions below `top` at once, a ballot finds the first
+// position that leaves the segment (or b's block-and-phase run when group_only), and the lanes
+// before it apply the exact predicate.  Every lane calls this with the same arguments.
+__device__ inline void wave_slow_check(const Bufs &b, const SegCtx &s, const u32 *rt_scan, u32 pos, u32 key,
+                                       u32 btid, u32 bblk, u32 bph, u32 bcat, bool group_only) {
+    const u32 lane = lane_id();
+    const u32 bidx = s.i[pos];
+    u32 h = NONE;
+    for (u32 top = pos; top > 0; top = top > 64 ? top - 64 : 0) {
+        const bool valid = lane < top;
+        const u32 q = valid ? top - 1 - lane : 0;
+        bool stop = !valid;
+        u32 ta = 0, info = 0, ba = 0, pha = 0;
+        if (valid) {
+            stop = s.k[q] != key;
+            if (!stop) {
+                ta = s.t[q];
+                info = s.f[q];
+                ba = block_of(b, ta);
+                pha = info_phase(info);
+                if (group_only && (ba != bblk || pha != bph)) stop = true;
+            }
+        }
+        const u64 sm = ballot(stop);
+        const u32 first_stop = sm ? (u32)__builtin_ctzll(sm) : 64u;
+        bool want = false;
+        u32 ia = 0;
+        if (lane < first_stop && ta != btid && conflicts(info_cat(info), ba, bcat, bblk)) {
+            ia = s.i[q];
+            want = !happens_before(b, rt_scan, bidx, btid, bblk, bph, h, ta, ba, pha, ia);
+        }
+        emit_wave(b, want, ia, bidx);
+        if (sm) break;
+    }
+}
+
+constexpr u32 SLOW_CAP = 512;  // slow items listed per workgroup before falling back to wave scans
+
+struct CheckLds {
+    Agg buf[2 * WG_THREADS];
+    u32 item_pos[SLOW_CAP], item_start[SLOW_CAP], item_off[SLOW_CAP];
+    u32 n_items, n_chunks, overflow, base;
+};
+
 __global__ __launch_bounds__(WG_THREADS) void k_seg_check(Bufs b, const u32 *rt_scan) {
-    __shared__ Agg buf[2 * WG_THREADS];
+    __shared__ CheckLds L;
     const SegCtx s = seg_ctx(b);
     const Agg *tile_agg = (const Agg *)b.tile_agg;
     const u64 tile0 = (u64)blockIdx.x * TILE;
     if (tile0 >= s.n) return;
+    if (threadIdx.x == 0) { L.n_items = 0; L.n_chunks = 0; L.overflow = 0; }
     const u64 base = tile0 + (u64)threadIdx.x * ITEMS;
-    Agg mine;
-    thread_agg(s, b, base, mine);
-    block_exscan_agg(mine, buf, nullptr);
-    // prefix of everything before this thread's first item
-    Agg P = tile_agg[blockIdx.x];
-    agg_combine(P, mine);
-    P = mine;
-    for (int q = 0; q < ITEMS; q++) {
-        const u64 pos = base + q;
-        if (pos >= s.n) break;
-        const Elem e = load_elem(s.k, s.i, s.t, s.f, (u32)pos);
-        const u32 cat = info_cat(e.info), ph = info_phase(e.info), blk = e.tid / b.tpb;
-        if (P.nonempty && P.last_key == e.key) {
-            // conflicting categories of b
-            const bool cR = cat != CAT_R && true;   // a read conflicts with b unless b is a read
-            const bool cW = true;                   // a write always conflicts
-            const bool cAD = !cat_atomic(cat);      // device atomics conflict with plain accesses only
-            const bool cAB_same = !cat_atomic(cat); // block atomics of b's block: with plain accesses
-            bool single = true;
+    Items it;
+    load_items(s, base, it);
+    const u32 cnt = items_in(s, base);
+    Agg P;
+    items_agg(b, it, cnt, (u32)base, P);
+    block_exscan_agg(P, L.buf, nullptr);  // (its barriers also publish the counters above)
+    {
+        Agg T = tile_agg[blockIdx.x];  // everything before this tile
+        agg_combine(T, P);             // P := T (+) P
+    }
+    // decisions in O(1) per item; an item that needs the exact check is listed with the range
+    // [start, pos) of earlier positions it must be checked against
 #pragma unroll
-            for (int c = 0; c < 4; c++) single = single && !set2_has_other(P.cb[c], blk);
-            bool slow = false, group_only = false;
+    for (int q = 0; q < ITEMS; q++) {
+        if ((u32)q >= cnt) continue;
+        const u32 key = it.key[q], tid = it.tid[q], info = it.info[q];
+        const u32 cat = info_cat(info), ph = info_phase(info), blk = block_of(b, tid);
+        if ((P.fl & F_NONEMPTY) && P.last_key == key) {
+            const bool single = !(P.fl & F_BLKMULTI) && P.blk == blk;
+            bool slow = false, group = false;
             if (single) {
                 if (P.run_blk == blk && P.run_ph == ph) {
-                    slow = (cR && set2_has_other(P.rt[CAT_R], e.tid)) || (cW && set2_has_other(P.rt[CAT_W], e.tid)) ||
-                           (cAD && set2_has_other(P.rt[CAT_AD], e.tid)) ||
-                           (cAB_same && set2_has_other(P.rt[CAT_AB], e.tid));
-                    group_only = true;
+                    if (cat == CAT_R) slow = set1_has_other(P.twa, P.fl, F_TWA_MULTI, tid);
+                    else if (cat == CAT_W) slow = set1_has_other(P.tall, P.fl, F_TALL_MULTI, tid);
+                    else slow = set1_has_other(P.tna, P.fl, F_TNA_MULTI, tid);
+                    group = true;
                 }
             } else {
-                // some earlier access of the segment is in another block
-                const bool cAB_other = cat != CAT_AD;  // block atomics of other blocks: all but device atomics
-                slow = (cR && !set2_empty(P.cb[CAT_R])) || (cW && !set2_empty(P.cb[CAT_W])) ||
-                       (cAD && !set2_empty(P.cb[CAT_AD])) ||
-                       (cAB_same && !set2_empty(P.cb[CAT_AB])) ||
-                       (cAB_other && set2_has_other(P.cb[CAT_AB], blk));
+                slow = (P.fl & conflict_cats(cat)) != 0;
             }
             if (slow) {
-                BCtx bc;
-                bc.idx = e.idx; bc.tid = e.tid; bc.blk = blk; bc.ph = ph; bc.cat = cat; bc.h = NONE;
-                slow_check(b, s, rt_scan, (u32)pos, e.key, bc, group_only);
+                const u32 pos = (u32)(base + q), start = group ? P.run_pos : P.seg_pos;
+                const u32 k = atomicAdd(&L.n_items, 1u);
+                if (k < SLOW_CAP) {
+                    L.item_pos[k] = pos;
+                    L.item_start[k] = start;
+                    L.item_off[k] = atomicAdd(&L.n_chunks, (pos - start + 63) / 64);
+                } else {
+                    L.overflow = 1;
+                }
             }
         }
         Agg one;
-        agg_one(one, e.key, blk, ph, e.tid, cat);
+        agg_one(one, key, blk, ph, tid, cat, (u32)(base + q));
         agg_combine(P, one);
         P = one;
+    }
+    __syncthreads();
+    const u32 n_items = min(L.n_items, SLOW_CAP);
+    if (!n_items && !L.overflow) return;
+    if (threadIdx.x == 0) {
+        L.base = NONE;
+        if (!L.overflow && L.n_chunks) {
+            const u64 c0 = atomicAdd(&b.prm->n_chunks, (unsigned long long)L.n_chunks);
+            if (c0 + L.n_chunks <= s.n) L.base = (u32)c0;
+            else {
+                // no room: neutralise the reserved slots below the capacity (the chunk kernel reads
+                // min(counter, capacity) slots) and scan here
+                for (u64 c = c0; c < c0 + L.n_chunks && c < s.n; c++) { s.cpos[c] = 0; s.clo[c] = 0; s.chi[c] = 0; }
+            }
+        }
+    }
+    __syncthreads();
+    if (L.base != NONE) {
+        // queue every listed item as chunks of 64 earlier positions
+        for (u32 k = threadIdx.x; k < n_items; k += WG_THREADS) {
+            const u32 pos = L.item_pos[k], start = L.item_start[k], c0 = L.base + L.item_off[k];
+            for (u32 c = 0; start + 64 * c < pos; c++) {
+                s.cpos[c0 + c] = pos;
+                s.clo[c0 + c] = start + 64 * c;
+                s.chi[c0 + c] = min(start + 64 * (c + 1), pos);
+            }
+        }
+        return;
+    }
+    // fallback (item list or chunk buffer full): the wavefronts check the items themselves; with an
+    // overflowing list, every item of the tile is re-decided by a full scan of its segment prefix
+    const u32 w = threadIdx.x >> 6;
+    if (!L.overflow) {
+        for (u32 k = w; k < n_items; k += WAVES) {
+            const u32 pos = L.item_pos[k], tid = s.t[pos], info = s.f[pos];
+            const bool group_only = false;  // scanning the whole prefix is exact, only slower
+            wave_slow_check(b, s, rt_scan, pos, s.k[pos], tid, block_of(b, tid), info_phase(info), info_cat(info),
+                            group_only);
+        }
+    } else {
+        for (u32 k = w; k < TILE; k += WAVES) {
+            const u64 pos = tile0 + k;
+            if (pos >= s.n) break;
+            const u32 tid = s.t[pos], info = s.f[pos];
+            wave_slow_check(b, s, rt_scan, (u32)pos, s.k[pos], tid, block_of(b, tid), info_phase(info),
+                            info_cat(info), false);
+        }
+    }
+}
+
+// One wavefront per queued chunk: lane l checks position lo + l against b.  Pairs are gathered in
+// LDS and appended with one device atomic per flush of the workgroup.
+constexpr u32 PAIR_LDS = 2048;
+
+__global__ __launch_bounds__(WG_THREADS) void k_seg_slow(Bufs b, const u32 *rt_scan) {
+    __shared__ u32 pf[PAIR_LDS], ps[PAIR_LDS];
+    __shared__ u32 fill, gbase;
+    const SegCtx s = seg_ctx(b);
+    const u32 n_chunks = (u32)min(b.prm->n_chunks, (unsigned long long)s.n);
+    const u32 lane = lane_id(), w = threadIdx.x >> 6;
+    if (threadIdx.x == 0) fill = 0;
+    __syncthreads();
+    const u32 stride = gridDim.x * WAVES;
+    for (u32 c0 = blockIdx.x * WAVES; c0 < n_chunks; c0 += stride) {
+        const u32 c = c0 + w;
+        bool want = false;
+        u32 ia = 0, bidx = 0;
+        if (c < n_chunks) {
+            const u32 pos = s.cpos[c], lo = s.clo[c], hi = s.chi[c];
+            const u32 q = lo + lane;
+            if (q < hi) {
+                const u32 btid = s.t[pos], binfo = s.f[pos];
+                const u32 bblk = block_of(b, btid), bph = info_phase(binfo), bcat = info_cat(binfo);
+                const u32 ta = s.t[q], info = s.f[q];
+                const u32 ba = block_of(b, ta), pha = info_phase(info);
+                if (ta != btid && conflicts(info_cat(info), ba, bcat, bblk)) {
+                    u32 h = NONE;
+                    ia = s.i[q];
+                    bidx = s.i[pos];
+                    want = !happens_before(b, rt_scan, bidx, btid, bblk, bph, h, ta, ba, pha, ia);
+                }
+            }
+        }
+        const u64 m = ballot(want);
+        if (m) {
+            u32 off = 0;
+            const u32 leader = (u32)__builtin_ctzll(m);
+            if (lane == leader) off = atomicAdd(&fill, popc64(m));
+            off = __shfl(off, leader, 64) + popc64(m & lanemask_lt());
+            if (want) { pf[off] = ia; ps[off] = bidx; }
+        }
+        __syncthreads();
+        if (fill > PAIR_LDS - WG_THREADS || c0 + stride >= n_chunks) {
+            // flush
+            if (threadIdx.x == 0) gbase = fill ? atomicAdd(&b.prm->n_pairs, fill) : 0;
+            __syncthreads();
+            for (u32 k = threadIdx.x; k < fill; k += WG_THREADS) {
+                const u32 slot = gbase + k;
+                if (slot < b.max_pairs) { b.pfirst[0][slot] = pf[k]; b.psecond[0][slot] = ps[k]; }
+                else atomicOr(&b.prm->err, ERR_PAIRS);
+            }
+            __syncthreads();
+            if (threadIdx.x == 0) fill = 0;
+            __syncthreads();
+        }
     }
 }
 
@@ -293,6 +500,7 @@ void segcheck_run(const Bufs &b, const u32 *rt_scan, hipStream_t s) {
     RD_LAUNCH("k_seg_reduce", k_seg_reduce, dim3(b.n_tiles), dim3(WG_THREADS), 0, s, b);
     RD_LAUNCH("k_seg_scan", k_seg_scan, dim3(1), dim3(WG_THREADS), 0, s, b);
     RD_LAUNCH("k_seg_check", k_seg_check, dim3(b.n_tiles), dim3(WG_THREADS), 0, s, b, rt_scan);
+    RD_LAUNCH("k_seg_slow", k_seg_slow, dim3(b.n_tiles < 1024 ? b.n_tiles : 1024), dim3(WG_THREADS), 0, s, b, rt_scan);
     RD_LAUNCH("k_pairs_kept", k_pairs_kept, dim3(1), dim3(64), 0, s, b);
 }
 

@@ -155,14 +155,18 @@ __global__ __launch_bounds__(WG_THREADS) void k_radix_scatter(
     }
 }
 
+static const char *const kScatterName[2][4] = {
+    {"k_sort_scatter_p0", "k_sort_scatter_p1", "k_sort_scatter_p2", "k_sort_scatter_p3"},
+    {"k_pair_scatter", "k_pair_scatter", "k_pair_scatter", "k_pair_scatter"}};
+
 template <int R>
 static void radix_pass(const u32 *kin, const u32 *p0, const u32 *p1, const u32 *p2, u32 *kout, u32 *q0, u32 *q1,
                        u32 *q2, const u32 *n_dev, u32 n_host, u32 shift, const u32 *bits_dev, u32 *hist, u32 *part,
-                       u32 n_tiles, hipStream_t s) {
-    RD_LAUNCH("k_radix_hist", k_radix_hist<R>, dim3(n_tiles), dim3(WG_THREADS), 0, s, kin, n_dev, n_host, shift, bits_dev,
+                       u32 n_tiles, hipStream_t s, int pairs, int pass) {
+    RD_LAUNCH(pairs ? "k_pair_hist" : "k_sort_hist", k_radix_hist<R>, dim3(n_tiles), dim3(WG_THREADS), 0, s, kin, n_dev, n_host, shift, bits_dev,
                        hist, n_tiles);
     scan_exclusive(hist, (u64)n_tiles << R, part, s);
-    RD_LAUNCH("k_radix_scatter", k_radix_scatter<R>, dim3(n_tiles), dim3(WG_THREADS), 0, s, kin, p0, p1, p2, kout, q0, q1, q2,
+    RD_LAUNCH(kScatterName[pairs][pass & 3], k_radix_scatter<R>, dim3(n_tiles), dim3(WG_THREADS), 0, s, kin, p0, p1, p2, kout, q0, q1, q2,
                        n_dev, n_host, shift, bits_dev, hist, n_tiles);
 }
 
@@ -177,10 +181,10 @@ void sort_elements(const Bufs &b, hipStream_t s) {
         const u32 c = pass & 1, o = c ^ 1;
         if (R == 11)
             radix_pass<11>(b.ekey[c], b.eidx[c], b.etid[c], b.einfo[c], b.ekey[o], b.eidx[o], b.etid[o], b.einfo[o],
-                           n_dev, 0, pass * R, bits, b.hist, b.part, b.n_tiles, s);
+                           n_dev, 0, pass * R, bits, b.hist, b.part, b.n_tiles, s, 0, pass);
         else
             radix_pass<8>(b.ekey[c], b.eidx[c], b.etid[c], b.einfo[c], b.ekey[o], b.eidx[o], b.etid[o], b.einfo[o],
-                          n_dev, 0, pass * R, bits, b.hist, b.part, b.n_tiles, s);
+                          n_dev, 0, pass * R, bits, b.hist, b.part, b.n_tiles, s, 0, pass);
     }
 }
 
@@ -196,10 +200,10 @@ u32 sort_pairs_host(const Bufs &b, u32 m, hipStream_t s) {
             const u32 o = cur ^ 1;
             if (half == 0)
                 radix_pass<8>(b.psecond[cur], b.pfirst[cur], nullptr, nullptr, b.psecond[o], b.pfirst[o], nullptr,
-                              nullptr, nullptr, m, pass * R, nullptr, b.hist, b.part, n_tiles, s);
+                              nullptr, nullptr, m, pass * R, nullptr, b.hist, b.part, n_tiles, s, 1, pass);
             else
                 radix_pass<8>(b.pfirst[cur], b.psecond[cur], nullptr, nullptr, b.pfirst[o], b.psecond[o], nullptr,
-                              nullptr, nullptr, m, pass * R, nullptr, b.hist, b.part, n_tiles, s);
+                              nullptr, nullptr, m, pass * R, nullptr, b.hist, b.part, n_tiles, s, 1, pass);
             cur = o;
         }
     }
