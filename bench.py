@@ -60,6 +60,88 @@ def key_passes(ev: np.ndarray, n_blocks: int, tpb: int, radix_bits: int) -> int:
     return (bits + radix_bits - 1) // radix_bits
 
 
+def source_digest() -> str:
+    """Digest of the HIP sources: a stored traffic figure is used only for the kernels it measured."""
+    import hashlib
+    h = hashlib.sha256()
+    csrc = os.path.join(ROOT, "paper_2111_12478_amd", "csrc")
+    for f in sorted(os.listdir(csrc)):
+        if f.endswith((".hip", ".h")):
+            h.update(open(os.path.join(csrc, f), "rb").read())
+    return h.hexdigest()[:16]
+
+
+def summarize_profiles(trace_csv: str, fetch_csv: str, write_csv: str, command: str) -> None:
+    """Turns rocprofv3 CSV output (the kernel trace of a --kernel-trace --stats run, then FETCH_SIZE
+    and WRITE_SIZE counter runs of the same command with a 1 GiB plain copy first) into the
+    summaries under profiles/.  Kernels are keyed by (name, grid size); launches that did no work
+    (a sort pass past the key width: under 10% of the kernel's longest launch) are left out."""
+    import csv
+    from collections import defaultdict
+    out_dir = os.path.join(ROOT, "profiles")
+    os.makedirs(out_dir, exist_ok=True)
+
+    def short(name):
+        return name.split("(")[0].replace("void ", "").replace("rd::", "")
+
+    dur = defaultdict(list)
+    for r in csv.DictReader(open(trace_csv)):
+        g = int(r["Grid_Size_X"]) * int(r["Grid_Size_Y"]) * int(r["Grid_Size_Z"])
+        dur[(short(r["Kernel_Name"]), g)].append((int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) / 1e3)
+    total = sum(sum(v) for v in dur.values())
+    lines = ["# per-kernel durations from rocprofv3 --kernel-trace --stats, large trace (16,777,216 events), MI355X",
+             f"# command: {command}",
+             "# keyed by (kernel, grid); 'worked' = launches above 10% of the kernel's longest (a radix pass",
+             "# past the key width exits at once)", "",
+             f"{'kernel':30s} {'grid':>9s} {'calls':>6s} {'worked':>6s} {'avg_us':>9s} {'sum_ms':>8s} {'pct':>6s}"]
+    for (k, g), v in sorted(dur.items(), key=lambda kv: -sum(kv[1])):
+        hi = max(v)
+        w = [x for x in v if x > 0.1 * hi]
+        lines.append(f"{k[:30]:30s} {g:9d} {len(v):6d} {len(w):6d} {sum(w)/len(w):9.1f} {sum(v)/1e3:8.3f} "
+                     f"{100*sum(v)/total:6.2f}")
+    lines.append(f"\n# total kernel time {total/1e3:.3f} ms over the profiled steps")
+    open(os.path.join(out_dir, "large_trace_kernel_stats.txt"), "w").write("\n".join(lines) + "\n")
+
+    def per_kernel(path):
+        agg = defaultdict(list)
+        for r in csv.DictReader(open(path)):
+            agg[(short(r["Kernel_Name"]), int(r["Grid_Size"]))].append(float(r["Counter_Value"]))
+        return agg
+
+    fetch, write = per_kernel(fetch_csv), per_kernel(write_csv)
+    copy_f = [v for (k, g), vs in fetch.items() if "copyBuffer" in k for v in vs]
+    copy_w = [v for (k, g), vs in write.items() if "copyBuffer" in k for v in vs]
+    gib_kib = 1024 * 1024
+    sf = gib_kib / max(copy_f) if copy_f else 1.0
+    sw = gib_kib / max(copy_w) if copy_w else 1.0
+    lines = ["# HBM traffic per dispatch from rocprofv3 --pmc FETCH_SIZE and --pmc WRITE_SIZE (KiB),",
+             "# scaled by a 1 GiB plain copy (__amd_rocclr_copyBuffer) of the same run:",
+             f"#   copy FETCH_SIZE = {max(copy_f) if copy_f else 0:.0f} KiB -> read scale {sf:.3f};"
+             f" copy WRITE_SIZE = {max(copy_w) if copy_w else 0:.0f} KiB -> write scale {sw:.3f}",
+             f"# command: {command}", "# averages over launches that did work (above 10% of the largest)", "",
+             f"{'kernel':30s} {'grid':>9s} {'n':>3s} {'read_MB':>9s} {'write_MB':>9s}"]
+    result = {}
+    for key in sorted(set(fetch) | set(write), key=lambda k: -(sum(fetch.get(k, [0])) + sum(write.get(k, [0])))):
+        fv, wv = fetch.get(key, []), write.get(key, [])
+        f = [v for v in fv if v > 0.1 * max(fv)] if fv else []
+        w = [v for v in wv if v > 0.1 * max(wv)] if wv else []
+        rd_mb = (sum(f) / len(f) if f else 0) * sf * 1024 / 1e6
+        wr_mb = (sum(w) / len(w) if w else 0) * sw * 1024 / 1e6
+        if rd_mb + wr_mb < 0.5:
+            continue
+        lines.append(f"{key[0][:30]:30s} {key[1]:9d} {max(len(f), len(w)):3d} {rd_mb:9.1f} {wr_mb:9.1f}")
+        result[key] = (rd_mb, wr_mb)
+    open(os.path.join(out_dir, "large_trace_hbm_traffic.txt"), "w").write("\n".join(lines) + "\n")
+    # the element-sort scatter: the launches over all accesses (the largest grid)
+    sc = [(g, v) for (k, g), v in result.items() if k.startswith("k_radix_scatter")]
+    if sc:
+        g, (r_mb, w_mb) = max(sc)
+        json.dump({"kernel": "k_sort_scatter", "workload_events": 16777216, "source_digest": source_digest(),
+                   "bytes_per_launch": (r_mb + w_mb) * 1e6, "read_bytes": r_mb * 1e6, "write_bytes": w_mb * 1e6,
+                   "read_scale": sf, "write_scale": sw},
+                  open(os.path.join(out_dir, "traffic.json"), "w"), indent=1)
+
+
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -68,6 +150,8 @@ def parse():
     ap.add_argument("--scale", type=int, default=1, help="shrink the workload (tests only)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--profile-all", action="store_true", help="print every kernel's time to stderr")
+    ap.add_argument("--summarize-profiles", nargs=4, metavar=("TRACE_CSV", "FETCH_CSV", "WRITE_CSV", "COMMAND"),
+                    help="write profiles/ summaries from rocprofv3 CSV files and exit")
     ap.add_argument("--copy-bytes", type=int, default=0,
                     help="run one plain device copy of this many bytes first (calibrates HBM counters)")
     return ap.parse_args()
@@ -75,6 +159,9 @@ def parse():
 
 def main():
     args = parse()
+    if args.summarize_profiles:
+        summarize_profiles(*args.summarize_profiles)
+        return
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the checker has no "
               f"multi-GPU path in this build", file=sys.stderr)
@@ -174,7 +261,7 @@ def main():
     if os.path.exists(tfile):
         try:
             t = json.load(open(tfile))
-            if t.get("kernel") == dom and t.get("workload_events") == n:
+            if t.get("kernel") == dom and t.get("workload_events") == n and t.get("source_digest") == source_digest():
                 traffic = t.get("bytes_per_launch")
         except Exception:
             traffic = None
