@@ -21,7 +21,7 @@ u32 sort_pairs_host(const Bufs &b, u32 m, hipStream_t s);
 
 struct Plan {
     Layout L;
-    u64 off_masks, off_rt_scan, off_tile_stats;
+    u64 off_masks, off_rt_scan, off_tile_stats, off_a_cnt;
     u32 n_tiles, T, B, radix_bits, pair_tiles, part_words;
     u64 hist_words;
 };
@@ -55,9 +55,10 @@ static Plan make_plan(u64 n, u32 nb, u32 tpb, const rd_limits *lim, bool copy_ev
     L.off_act = take(T);
     L.off_s_cnt = take(4 * (T + 1));
     L.off_s_fill = take(4 * T);
-    L.off_tile_s = take(4 * 2 * ((u64)n_tiles + 1));
+    L.off_tile_s = take(4 * 3 * ((u64)n_tiles + 1));
+    P.off_a_cnt = take(4 * T);
     P.off_tile_stats = take(4ull * TILE_STATS * ((u64)n_tiles + 1));
-    P.off_masks = take(8 * 2 * (u64)n_tiles * 64);
+    P.off_masks = take(8 * 3 * (u64)n_tiles * 64);
     L.off_s_tidx = take(4 * N1);
     L.off_s_pidx = take(4 * N1);
     L.off_s_pq = take(4 * N1);
@@ -120,6 +121,7 @@ static Bufs make_bufs(const Plan &P, char *ws, const void *events_dev, u64 n, u3
     b.act = (uint8_t *)(ws + L.off_act);
     b.s_cnt = (u32 *)(ws + L.off_s_cnt);
     b.s_fill = (u32 *)(ws + L.off_s_fill);
+    b.a_cnt = (u32 *)(ws + P.off_a_cnt);
     b.tile_s = (u32 *)(ws + L.off_tile_s);
     b.tile_stats = (u32 *)(ws + P.off_tile_stats);
     b.s_tidx = (u32 *)(ws + L.off_s_tidx);
@@ -236,10 +238,10 @@ void prof_end(hipStream_t s) {
 }
 
 hipError_t enqueue_check(const Bufs &b, u64 *masks, u32 *rt_scan, hipStream_t s) {
-    u64 *sync_mask = masks, *acc_mask = masks + (u64)b.n_tiles * 64;
+    u64 *sync_mask = masks, *acc_mask = masks + (u64)b.n_tiles * 64, *atom_mask = masks + 2 * (u64)b.n_tiles * 64;
     prep_init(b, s);
-    prep_ingest(b, sync_mask, acc_mask, s);
-    prep_sync_lists(b, sync_mask, s);
+    prep_ingest(b, sync_mask, acc_mask, atom_mask, s);
+    prep_sync_lists(b, sync_mask, atom_mask, s);
     prep_elements(b, acc_mask, s);
     prep_thread_sync(b, rt_scan, s);
     interp_run(b, rt_scan, s);

@@ -84,6 +84,7 @@ struct Bufs {
     uint8_t *act;           // [T] thread has >= 1 event
     u32 *s_cnt;             // [T+1] sync entries per thread -> exclusive offsets
     u32 *s_fill;            // [T]
+    u32 *a_cnt;             // [T] atomics per thread
     u32 *tile_s;            // [n_tiles+1] sync events per ingest tile -> offsets
     u32 *tile_stats;        // [n_tiles * TILE_STATS] ingest statistics per tile
     u32 *s_tidx;            // [N] sync events in trace order (event index)

@@ -9,8 +9,8 @@ void fill_u32_dyn(u32 *p, const u32 *count, u32 v, u64 max_n, hipStream_t s);
 void scan_exclusive(u32 *data, u64 n, u32 *part, hipStream_t s);
 
 void prep_init(const Bufs &b, hipStream_t s);
-void prep_ingest(const Bufs &b, u64 *sync_mask, u64 *acc_mask, hipStream_t s);
-void prep_sync_lists(const Bufs &b, const u64 *sync_mask, hipStream_t s);
+void prep_ingest(const Bufs &b, u64 *sync_mask, u64 *acc_mask, u64 *atom_mask, hipStream_t s);
+void prep_sync_lists(const Bufs &b, const u64 *sync_mask, const u64 *atom_mask, hipStream_t s);
 void prep_elements(const Bufs &b, const u64 *acc_mask, hipStream_t s);
 void prep_thread_sync(const Bufs &b, u32 *rt_scan, hipStream_t s);
 void prep_validate_wbar(const Bufs &b, hipStream_t s);

@@ -134,12 +134,12 @@ __device__ inline bool is_access_kind(u32 k) { return k <= 2u || k == 6u || k ==
 
 // Record checks, kind histogram, address ranges, activity, sync counts per thread, and two
 // bitmasks (sync events, accesses) with per-tile counts for the compactions that follow.
-__global__ __launch_bounds__(WG_THREADS) void k_ingest(Bufs b, u64 *sync_mask, u64 *acc_mask) {
+__global__ __launch_bounds__(WG_THREADS) void k_ingest(Bufs b, u64 *sync_mask, u64 *acc_mask, u64 *atom_mask) {
     __shared__ u32 lds_cnt[8][WAVES];
     __shared__ u32 lds_misc[WAVES][8];
     const u32 w = threadIdx.x >> 6, lane = lane_id();
     const u64 base = (u64)blockIdx.x * TILE + (u64)w * ITEMS * 64;
-    u32 bad = NONE, ns = 0, na = 0;
+    u32 bad = NONE, ns = 0, na = 0, nt = 0;
     u32 kc[8] = {0, 0, 0, 0, 0, 0, 0, 0};
     u32 gmin = NONE, gmax = 0, smin = NONE, smax = 0;
 #pragma unroll 4
@@ -152,7 +152,10 @@ __global__ __launch_bounds__(WG_THREADS) void k_ingest(Bufs b, u64 *sync_mask, u
                   !((kind == 3u || kind == 4u || kind == 5u) && space);
         if (in && !ok && (u32)i < bad) bad = (u32)i;
         if (in && e.y < b.T) b.act[e.y] = 1;
-        const bool is_sync = ok && kind >= 2u;
+        // sync lists hold fences, barriers, warp barriers and locks; atomics join them only when the
+        // trace has something that can make an atomic a release or an acquire (decided in k_plan)
+        const bool is_sync = ok && kind >= 3u;
+        const bool is_atom = ok && kind == 2u;
         const bool is_acc = ok && is_access_kind(kind);
         if (ok) {
 #pragma unroll
@@ -163,14 +166,17 @@ __global__ __launch_bounds__(WG_THREADS) void k_ingest(Bufs b, u64 *sync_mask, u
             else { gmin = min(gmin, e.x); gmax = max(gmax, e.x); }
         }
         if (is_sync) atomicAdd(&b.s_cnt[e.y], 1u);
-        const u64 ms = ballot(is_sync), ma = ballot(is_acc);
+        if (is_atom) atomicAdd(&b.a_cnt[e.y], 1u);
+        const u64 ms = ballot(is_sync), ma = ballot(is_acc), mt = ballot(is_atom);
         if (lane == 0) {
             const u64 word = (base + (u64)k * 64) >> 6;
             sync_mask[word] = ms;
             acc_mask[word] = ma;
+            atom_mask[word] = mt;
         }
         ns += popc64(ms);
         na += popc64(ma);
+        nt += popc64(mt);
     }
     // wave reductions
 #pragma unroll
@@ -187,14 +193,15 @@ __global__ __launch_bounds__(WG_THREADS) void k_ingest(Bufs b, u64 *sync_mask, u
         for (int q = 0; q < 8; q++) lds_cnt[q][w] = kc[q];
         lds_misc[w][0] = bad; lds_misc[w][1] = gmin; lds_misc[w][2] = gmax;
         lds_misc[w][3] = smin; lds_misc[w][4] = smax; lds_misc[w][5] = ns; lds_misc[w][6] = na;
+        lds_misc[w][7] = nt;
     }
     __syncthreads();
     if (threadIdx.x == 0) {
-        u32 tb = NONE, tg0 = NONE, tg1 = 0, ts0 = NONE, ts1 = 0, tns = 0, tna = 0;
+        u32 tb = NONE, tg0 = NONE, tg1 = 0, ts0 = NONE, ts1 = 0, tns = 0, tna = 0, tnt = 0;
         for (int q = 0; q < WAVES; q++) {
             tb = min(tb, lds_misc[q][0]); tg0 = min(tg0, lds_misc[q][1]); tg1 = max(tg1, lds_misc[q][2]);
             ts0 = min(ts0, lds_misc[q][3]); ts1 = max(ts1, lds_misc[q][4]);
-            tns += lds_misc[q][5]; tna += lds_misc[q][6];
+            tns += lds_misc[q][5]; tna += lds_misc[q][6]; tnt += lds_misc[q][7];
         }
         // per-tile statistics, reduced by k_plan (no same-address atomics across tiles)
         u32 *st = b.tile_stats + (u64)blockIdx.x * TILE_STATS;
@@ -204,8 +211,10 @@ __global__ __launch_bounds__(WG_THREADS) void k_ingest(Bufs b, u64 *sync_mask, u
             for (int ww = 0; ww < WAVES; ww++) c += lds_cnt[q][ww];
             st[5 + q] = c;
         }
+        // three regions of n_tiles + 1 words: sync events, accesses, atomics
         b.tile_s[blockIdx.x] = tns;
-        b.tile_s[b.n_tiles + 1 + blockIdx.x] = tna;  // access counts live after the sync counts
+        b.tile_s[(b.n_tiles + 1) + blockIdx.x] = tna;
+        b.tile_s[2 * (b.n_tiles + 1) + blockIdx.x] = tnt;
     }
 }
 
@@ -233,7 +242,7 @@ __global__ __launch_bounds__(256) void k_plan(Bufs b) {
     p->first_bad_record = acc[0];
     p->gmin = acc[1]; p->gmax = acc[2]; p->smin = acc[3]; p->smax = acc[4];
     for (int q = 0; q < 8; q++) p->kind_count[q] = acc[5 + q];
-    p->n_sync = b.tile_s[b.n_tiles];
+    const u32 n_other = b.tile_s[b.n_tiles], n_atom = b.tile_s[3 * b.n_tiles + 2];
     p->n_acc = b.tile_s[2 * b.n_tiles + 1];
     u64 gs = p->gmin != NONE ? (u64)p->gmax - p->gmin + 1 : 0;
     u64 ss = p->smin != NONE ? (u64)p->smax - p->smin + 1 : 0;
@@ -251,17 +260,19 @@ __global__ __launch_bounds__(256) void k_plan(Bufs b) {
     if (p->kind_count[3] || p->kind_count[5] || p->kind_count[6] || p->kind_count[7]) mode |= MODE_SYNC;
     if (p->kind_count[5]) mode |= MODE_WBAR;
     p->mode = mode;
+    p->n_sync = n_other + ((mode & MODE_SYNC) ? n_atom : 0u);
 }
 
 // Position of item (lane, step) among the set bits of a tile's bitmask, in input order.
 // masks: the tile's ITEMS words of this wave are read by every lane.
-__device__ inline void wave_mask_prefix(const u64 *mask, u64 tile_word0, u32 w, u32 *wave_base_lds,
+__device__ inline void wave_mask_prefix(const u64 *mask, const u64 *mask2, u64 tile_word0, u32 w, u32 *wave_base_lds,
                                         u32 tile_off, u64 m_items[ITEMS], u32 pre[ITEMS]) {
     const u32 lane = lane_id();
     u32 run = 0;
 #pragma unroll
     for (int k = 0; k < ITEMS; k++) {
-        const u64 m = mask[tile_word0 + (u64)w * ITEMS + k];
+        const u64 wi = tile_word0 + (u64)w * ITEMS + k;
+        const u64 m = mask[wi] | (mask2 ? mask2[wi] : 0ull);
         m_items[k] = m;
         pre[k] = run + popc64(m & lanemask_lt());
         run += popc64(m);
@@ -275,13 +286,15 @@ __device__ inline void wave_mask_prefix(const u64 *mask, u64 tile_word0, u32 w, 
 }
 
 // Sync events in trace order: s_tidx[q] = event index.
-__global__ __launch_bounds__(WG_THREADS) void k_sync_compact(Bufs b, const u64 *sync_mask) {
+__global__ __launch_bounds__(WG_THREADS) void k_sync_compact(Bufs b, const u64 *sync_mask, const u64 *atom_mask) {
     __shared__ u32 wbase[WAVES];
     const u32 w = threadIdx.x >> 6, lane = lane_id();
     const u64 word0 = (u64)blockIdx.x * (TILE / 64);
+    const bool with_atomics = (b.prm->mode & MODE_SYNC) != 0;
+    const u32 off = b.tile_s[blockIdx.x] + (with_atomics ? b.tile_s[2 * (b.n_tiles + 1) + blockIdx.x] : 0u);
     u64 m[ITEMS];
     u32 pre[ITEMS];
-    wave_mask_prefix(sync_mask, word0, w, wbase, b.tile_s[blockIdx.x], m, pre);
+    wave_mask_prefix(sync_mask, with_atomics ? atom_mask : nullptr, word0, w, wbase, off, m, pre);
     const u64 base = (u64)blockIdx.x * TILE + (u64)w * ITEMS * 64;
 #pragma unroll
     for (int k = 0; k < ITEMS; k++)
@@ -400,7 +413,7 @@ __global__ __launch_bounds__(WG_THREADS) void k_elements(Bufs b, const u64 *acc_
     const u64 word0 = (u64)blockIdx.x * (TILE / 64);
     u64 m[ITEMS];
     u32 pre[ITEMS];
-    wave_mask_prefix(acc_mask, word0, w, wbase, b.tile_s[b.n_tiles + 1 + blockIdx.x], m, pre);
+    wave_mask_prefix(acc_mask, nullptr, word0, w, wbase, b.tile_s[b.n_tiles + 1 + blockIdx.x], m, pre);
     const DevParams *p = b.prm;
     const u32 gbase = p->gbase, sbase = p->sbase, g_span = p->g_span, s_span = p->s_span;
     const u32 mode = p->mode;
@@ -419,11 +432,21 @@ __global__ __launch_bounds__(WG_THREADS) void k_elements(Bufs b, const u64 *acc_
         else if (kind == 1) cat = CAT_W;
         else cat = scope == 0 ? CAT_AB : CAT_AD;
         u32 ph = 0;
-        if (mode & (MODE_BAR | MODE_SYNC)) {
+        if (mode & MODE_SYNC) {
             const u32 j = list_search(b, t, idx);
             if (j != NONE) {
                 ph = b.s_phase[j];
                 if (kind <= 1 && b.s_imin[j] > idx) atomicMin(&b.s_imin[j], idx);
+            }
+        } else if (mode & MODE_BAR) {
+            // the thread's list holds only its barriers: the phase is the number of entries before idx,
+            // and the block-barrier rule is checked here, for the access itself
+            const u32 j = list_search(b, t, idx);
+            if (j != NONE) {
+                ph = j - b.s_cnt[t] + 1;
+                const u32 slot = b.inst_off[blk] + ph - 1;
+                if (b.inst_cnt[slot] != b.n_active[blk] || b.inst_last[slot] > idx)
+                    atomicMin(&b.prm->first_bad_sync, idx);
             }
         }
         const u32 o = pre[k];
@@ -500,6 +523,12 @@ __global__ void k_validate_wbar(Bufs b) {
     }
 }
 
+// With releases/acquires possible, atomics join the sync lists: add their per-thread counts.
+__global__ void k_merge_counts(Bufs b) {
+    if (!(b.prm->mode & MODE_SYNC)) return;
+    for (u32 t = blockIdx.x * blockDim.x + threadIdx.x; t < b.T; t += gridDim.x * blockDim.x) b.s_cnt[t] += b.a_cnt[t];
+}
+
 // ---------------------------------------------------------------- launchers
 
 void prep_init(const Bufs &b, hipStream_t s) {
@@ -509,20 +538,23 @@ void prep_init(const Bufs &b, hipStream_t s) {
     fill_u32(b.s_fill, b.T, 0, s);
     fill_u32(b.blk_maxbar, (u64)b.B + 1, 0, s);
     fill_u32(b.n_active, b.B, 0, s);
-    fill_u32(b.tile_s, 2 * ((u64)b.n_tiles + 1), 0, s);
+    fill_u32(b.tile_s, 3 * ((u64)b.n_tiles + 1), 0, s);
+    fill_u32(b.a_cnt, b.T, 0, s);
 }
 
 // ingest + tile scans + plan
-void prep_ingest(const Bufs &b, u64 *sync_mask, u64 *acc_mask, hipStream_t s) {
-    if (b.N) RD_LAUNCH("k_ingest", k_ingest, dim3(b.n_tiles), dim3(WG_THREADS), 0, s, b, sync_mask, acc_mask);
+void prep_ingest(const Bufs &b, u64 *sync_mask, u64 *acc_mask, u64 *atom_mask, hipStream_t s) {
+    if (b.N) RD_LAUNCH("k_ingest", k_ingest, dim3(b.n_tiles), dim3(WG_THREADS), 0, s, b, sync_mask, acc_mask, atom_mask);
     scan_exclusive(b.tile_s, (u64)b.n_tiles + 1, b.part, s);
     scan_exclusive(b.tile_s + b.n_tiles + 1, (u64)b.n_tiles + 1, b.part, s);
+    scan_exclusive(b.tile_s + 2 * ((u64)b.n_tiles + 1), (u64)b.n_tiles + 1, b.part, s);
     RD_LAUNCH("k_plan", k_plan, dim3(1), dim3(256), 0, s, b);
 }
 
 // per-thread sync lists and block-barrier instances
-void prep_sync_lists(const Bufs &b, const u64 *sync_mask, hipStream_t s) {
-    if (b.N) RD_LAUNCH("k_sync_compact", k_sync_compact, dim3(b.n_tiles), dim3(WG_THREADS), 0, s, b, sync_mask);
+void prep_sync_lists(const Bufs &b, const u64 *sync_mask, const u64 *atom_mask, hipStream_t s) {
+    RD_LAUNCH("k_merge_counts", k_merge_counts, dim3(grid_for(b.T)), dim3(256), 0, s, b);
+    if (b.N) RD_LAUNCH("k_sync_compact", k_sync_compact, dim3(b.n_tiles), dim3(WG_THREADS), 0, s, b, sync_mask, atom_mask);
     scan_exclusive(b.s_cnt, (u64)b.T + 1, b.part, s);
     RD_LAUNCH("k_sync_scatter", k_sync_scatter, dim3(grid_for(b.N)), dim3(256), 0, s, b);
     RD_LAUNCH("k_thread_lists", k_thread_lists, dim3(grid_for(b.T, 64)), dim3(64), 0, s, b);
