@@ -35,9 +35,7 @@ def algorithmic_bytes(name: str, n_events: int, n_acc: int, n_sync: int) -> int 
         # every record read once, one 16-byte element written per access
         "k_elements": 16 * n_events + 16 * n_acc,
         # one pass of the location sort: each element (key, index, tid, info) read and written once
-        "k_sort_scatter": 32 * n_acc,
-        # the key of each element read once
-        "k_sort_hist": 4 * n_acc,
+        "k_sort_sweep": 32 * n_acc,
         # the summaries read key, tid and info of each sorted element once
         "k_seg_reduce": 12 * n_acc,
         "k_seg_check": 12 * n_acc,
@@ -132,11 +130,11 @@ def summarize_profiles(trace_csv: str, fetch_csv: str, write_csv: str, command: 
         lines.append(f"{key[0][:30]:30s} {key[1]:9d} {max(len(f), len(w)):3d} {rd_mb:9.1f} {wr_mb:9.1f}")
         result[key] = (rd_mb, wr_mb)
     open(os.path.join(out_dir, "large_trace_hbm_traffic.txt"), "w").write("\n".join(lines) + "\n")
-    # the element-sort scatter: the launches over all accesses (the largest grid)
-    sc = [(g, v) for (k, g), v in result.items() if k.startswith("k_radix_scatter")]
+    # the element-sort sweep: the launches over all accesses (the largest grid)
+    sc = [(g, v) for (k, g), v in result.items() if k.startswith("k_sort_sweep<3>")]
     if sc:
         g, (r_mb, w_mb) = max(sc)
-        json.dump({"kernel": "k_sort_scatter", "workload_events": 16777216, "source_digest": source_digest(),
+        json.dump({"kernel": "k_sort_sweep", "workload_events": 16777216, "source_digest": source_digest(),
                    "bytes_per_launch": (r_mb + w_mb) * 1e6, "read_bytes": r_mb * 1e6, "write_bytes": w_mb * 1e6,
                    "read_scale": sf, "write_scale": sw},
                   open(os.path.join(out_dir, "traffic.json"), "w"), indent=1)
@@ -152,9 +150,238 @@ def parse():
     ap.add_argument("--profile-all", action="store_true", help="print every kernel's time to stderr")
     ap.add_argument("--summarize-profiles", nargs=4, metavar=("TRACE_CSV", "FETCH_CSV", "WRITE_CSV", "COMMAND"),
                     help="write profiles/ summaries from rocprofv3 CSV files and exit")
+    ap.add_argument("--workload", choices=("large", "batched", "served"), default="large",
+                    help="large: one 16M-event trace (default); batched: 512 traces, one pass vs one per trace; "
+                         "served: Poisson arrivals through the request loop")
+    ap.add_argument("--batch-traces", type=int, default=512)
+    ap.add_argument("--served-seconds", type=float, default=60.0, help="arrival window of the served workload")
+    ap.add_argument("--served-rate", type=float, default=200.0, help="requests per second")
+    ap.add_argument("--served-distinct", type=int, default=96,
+                    help="distinct traces the requests draw from (each generated once)")
     ap.add_argument("--copy-bytes", type=int, default=0,
                     help="run one plain device copy of this many bytes first (calibrates HBM counters)")
     return ap.parse_args()
+
+
+def _gen_member(cfg):
+    import tracegen
+    g, ev, _, _ = tracegen.generate(cfg)
+    return g, ev
+
+
+def _oracle_member(item):
+    import oracle
+    g, ev = item
+    t0 = time.perf_counter()
+    r = oracle.check(g, ev)
+    return r.status, r.pairs, time.perf_counter() - t0
+
+
+def bench_batched(args):
+    """512 independent traces (lengths lognormal around 200K events) checked two ways on the same
+    resident events: one rd_check + rd_races per trace, in turn (plain), and one rd_check_many +
+    rd_races_many over all of them (batched).  The JSON line reports the batched rate."""
+    import concurrent.futures as cf
+    import torch
+    import tracegen
+    import paper_2111_12478_amd as rd
+
+    cfgs = tracegen.batch(seed=4, n_traces=args.batch_traces, scale=args.scale)
+    workers = min(16, os.cpu_count() or 1)
+    with cf.ProcessPoolExecutor(max_workers=workers) as ex:
+        items = list(ex.map(_gen_member, cfgs, chunksize=4))
+    n_total = sum(int(ev.shape[0]) for _, ev in items)
+    print(f"batched: {len(items)} traces, {n_total:,} events generated", file=sys.stderr, flush=True)
+    rc = rd.RaceChecker(0)
+    limits = {"clock_bytes": 16 << 20}
+    bound = [rc.prepare(g, torch.from_numpy(ev.view(np.int32)).cuda(), limits) for g, ev in items]
+    traces = [b[0] for b in bound]
+    bws_bytes = rd.rd_batch_workspace_bytes(rc.ctx, traces, None)
+    bws = torch.empty(bws_bytes, dtype=torch.uint8, device="cuda")
+    stream = torch.cuda.current_stream().cuda_stream
+    print(f"batched: bound, member workspaces {sum(b[1].numel() for b in bound) / 2**30:.1f} GiB, "
+          f"batch workspace {bws_bytes / 2**30:.1f} GiB", file=sys.stderr, flush=True)
+
+    def plain_step():
+        return [rc.run(t) for t in traces]
+
+    def batched_step():
+        st = rd.rd_check_many(rc.ctx, traces, bws.data_ptr(), bws.numel(), None, stream)
+        if st != rd.RD_OK:
+            raise RuntimeError(f"rd_check_many failed: {st}")
+        return rc.report_many(traces)
+
+    def timed(fn, steps):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            res = fn()
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t0) / steps, res
+
+    steps = max(1, min(args.steps, 5))
+    for _ in range(max(1, min(args.warmup, 2))):
+        plain_res = plain_step()
+        batch_res = batched_step()
+    t_plain, plain_res = timed(plain_step, steps)
+    print(f"batched: plain {t_plain * 1e3:.2f} ms/step", file=sys.stderr, flush=True)
+    t_batch, batch_res = timed(batched_step, steps)
+    print(f"batched: batched {t_batch * 1e3:.2f} ms/step", file=sys.stderr, flush=True)
+    same = all(a.status == b.status == 0 and np.array_equal(a.pairs, b.pairs) for a, b in zip(plain_res, batch_res))
+    n_pairs = sum(len(r.pairs) for r in batch_res)
+    out = {
+        "metric": "memory events checked/sec (bit-exact race set) and % of HBM peak; batched vs plain",
+        "value": n_total / t_batch,
+        "unit": "events/s",
+        "n_gpus": 1,
+        "steps": steps,
+        "warmup": max(1, min(args.warmup, 2)),
+        "ms_per_step": t_batch * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "u32",
+        "data": "synthetic (seeded generator, same shape as the workload)",
+        "config": {
+            "workload": f"batched form: {len(items)} traces, lengths lognormal(median 204,800, sigma 1) in "
+                        f"[10,240, 4,194,304], 2^U{{6..11}} blocks x 128|256 threads, mix of the 16M-event "
+                        f"trace, seed 4; one rd_check_many + rd_races_many",
+            "events": n_total,
+            "race_pairs": int(n_pairs),
+        },
+        "plain": {"value": n_total / t_plain, "unit": "events/s", "ms_per_step": t_plain * 1e3,
+                  "form": "one rd_check + rd_races per trace, in turn, same resident events"},
+        "batched_vs_plain": t_plain / t_batch,
+        "batched_equals_plain": bool(same),
+    }
+    if not args.no_cpu_baseline:
+        # oracle on a bounded sample of the members, in a process pool over the host's cores
+        rng = np.random.default_rng(4)
+        order = rng.permutation(len(items))
+        sample, budget = [], 0
+        for j in order:
+            if budget + int(items[j][1].shape[0]) > 40_000_000:
+                continue
+            sample.append(int(j))
+            budget += int(items[j][1].shape[0])
+        c0 = time.perf_counter()
+        with cf.ProcessPoolExecutor(max_workers=workers) as ex:
+            res = list(ex.map(_oracle_member, [items[j] for j in sample], chunksize=1))
+        c1 = time.perf_counter()
+        ok = all(st == 0 and np.array_equal(p, batch_res[j].pairs) for j, (st, p, _) in zip(sample, res))
+        out["cpu_baseline"] = {
+            "value": budget / (c1 - c0),
+            "unit": "events/s",
+            "cores": workers,
+            "kind": "oracle",
+            "sample": f"{len(sample)} of the {len(items)} traces ({budget:,} events), one trace per process",
+        }
+        out["parity"] = "bit-exact" if ok and same else "MISMATCH"
+    for t in traces:
+        rd.rd_trace_free(rc.ctx, t)
+    print(json.dumps(out), flush=True)
+
+
+def _served_cfg(i, n):
+    import tracegen
+    return tracegen.MixConfig(n_blocks=max(1, -(-n // 16384)), tpb=256, n_events=n, n_global=max(16, (n // 16) * 4 // 5),
+                              n_shared=max(1, (n // 16 - (n // 16) * 4 // 5) // max(1, -(-n // 16384))),
+                              zipf_s=1.1, p_write=0.30, p_atomic_block=0.01, p_atomic_device=0.01, bar_period=64,
+                              fence_period=512, plant_rate=1e-4, p_plant_same_block=0.5, plant_victim_cap=256,
+                              frac_ro=0.3, frac_da=0.05, frac_priv=0.7, frac_pro=0.25, p_read_ro=0.3, seed=5,
+                              trace_index=i)
+
+
+def bench_served(args):
+    """Poisson arrivals (rate, window) of check requests with sizes log-uniform on [102,400,
+    8,388,608] events (256 threads per block, one block per 16,384 events, the mix of the 16M-event
+    trace, seed 5), answered by the request loop under a 64 GiB arena.  The same arrival list is
+    replayed with one request per pass and one pass in flight (plain) for comparison.  Requests
+    draw their traces from a pool of distinct generated traces."""
+    import concurrent.futures as cf
+    import threading
+    import torch
+    import paper_2111_12478_amd as rd
+
+    rng = np.random.default_rng(5)
+    n_req = int(rng.poisson(args.served_rate * args.served_seconds))
+    arrivals = np.sort(rng.uniform(0.0, args.served_seconds, n_req))
+    sizes = np.exp(rng.uniform(np.log(102_400), np.log(8_388_608), args.served_distinct)).astype(np.int64)
+    pick = rng.integers(0, args.served_distinct, n_req)
+    cfgs = [_served_cfg(i, int(sizes[i]) // args.scale) for i in range(args.served_distinct)]
+    workers = min(16, os.cpu_count() or 1)
+    with cf.ProcessPoolExecutor(max_workers=workers) as ex:
+        pool = list(ex.map(_gen_member, cfgs, chunksize=1))
+    print(f"served: {n_req} requests over {args.served_seconds:.0f} s from {len(pool)} distinct traces",
+          file=sys.stderr, flush=True)
+    rc = rd.RaceChecker(0)
+    alone = [rc.check(g, ev) for g, ev in pool]  # each distinct trace checked alone (plain)
+    budget = 64 << 30
+
+    def run(max_batch, max_inflight):
+        srv = rd.Server(rc, budget, max_batch=max_batch, max_inflight=max_inflight)
+        tickets = [None] * n_req
+        results = [None] * n_req
+        t_base = [0.0]
+
+        def submitter():
+            t0 = time.perf_counter()
+            for i in range(n_req):
+                d = arrivals[i] - (time.perf_counter() - t0)
+                if d > 0:
+                    time.sleep(d)
+                tickets[i] = srv.submit(*pool[pick[i]])
+                ready[i].set()
+
+        ready = [threading.Event() for _ in range(n_req)]
+
+        def waiter():
+            for i in range(n_req):
+                ready[i].wait()
+                results[i] = srv.wait(tickets[i])
+
+        ts = threading.Thread(target=submitter)
+        tw = threading.Thread(target=waiter)
+        ts.start(); tw.start(); ts.join(); tw.join()
+        passes, done = srv.stats()
+        srv.close()
+        lat = np.array([r[1].done_s - r[1].submit_s for r in results])
+        t_first = min(r[1].submit_s for r in results)
+        t_last = max(r[1].done_s for r in results)
+        ok = all(r[0].status == 0 and np.array_equal(r[0].pairs, alone[pick[i]].pairs) for i, r in enumerate(results))
+        return {"p50_ms": float(np.percentile(lat, 50) * 1e3), "p99_ms": float(np.percentile(lat, 99) * 1e3),
+                "events_per_s": float(sum(int(pool[j][1].shape[0]) for j in pick) / (t_last - t_first)),
+                "makespan_s": float(t_last - t_first), "passes": int(passes), "same_as_alone": bool(ok)}
+
+    served = run(256, 2)
+    print(f"served: {served}", file=sys.stderr, flush=True)
+    plain = run(1, 1)
+    print(f"served (plain, one request per pass): {plain}", file=sys.stderr, flush=True)
+    n_events = int(sum(int(pool[j][1].shape[0]) for j in pick))
+    out = {
+        "metric": "memory events checked/sec (bit-exact race set) and % of HBM peak; batched vs plain",
+        "value": served["events_per_s"],
+        "unit": "events/s",
+        "n_gpus": 1,
+        "steps": 1,
+        "warmup": 0,
+        "ms_per_step": served["makespan_s"] * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "u32",
+        "data": "synthetic (seeded generator, same shape as the workload)",
+        "config": {
+            "workload": f"served form: Poisson {args.served_rate:.0f} req/s for {args.served_seconds:.0f} s "
+                        f"({n_req} requests, {n_events:,} events), sizes log-uniform [102,400, 8,388,608], "
+                        f"{args.served_distinct} distinct traces, 64 GiB arena, seed 5",
+            "requests": n_req,
+            "events": n_events,
+        },
+        "served": served,
+        "plain": plain,
+    }
+    print(json.dumps(out), flush=True)
 
 
 def main():
@@ -166,6 +393,12 @@ def main():
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the checker has no "
               f"multi-GPU path in this build", file=sys.stderr)
         sys.exit(2)
+    if args.workload == "batched":
+        bench_batched(args)
+        return
+    if args.workload == "served":
+        bench_served(args)
+        return
     import torch
     import tracegen
     import paper_2111_12478_amd as rd
@@ -219,18 +452,18 @@ def main():
     if args.profile_all:
         for k, (c, ms) in sorted(prof.items(), key=lambda kv: -kv[1][1]):
             print(f"  {k:28s} launches={c:3d} total={ms:8.3f} ms", file=sys.stderr)
-    # the element sort runs one scatter per key digit; its passes count as one kernel
-    radix_bits = int(os.environ.get("RD_RADIX_BITS", "8"))
+    # the element sort runs one sweep per key digit; its passes count as one kernel
+    radix_bits = 8
     passes = key_passes(ev, grid[0], grid[1], radix_bits)
-    pass_names = [f"k_sort_scatter_p{p}" for p in range(passes)]
+    pass_names = [f"k_sort_sweep_p{p}" for p in range(passes)]
 
     def merged(prof):
         out = {}
         for k, (c, ms) in prof.items():
-            if k.startswith("k_sort_scatter_p"):
+            if k.startswith("k_sort_sweep_p"):
                 if k not in pass_names:
                     continue  # a pass the key width makes empty
-                k = "k_sort_scatter"
+                k = "k_sort_sweep"
             c0, m0 = out.get(k, (0, 0.0))
             out[k] = (c0 + c, m0 + ms)
         return out
@@ -239,7 +472,7 @@ def main():
     dom = max(candidates)[1]
 
     # timed region: K steps, the dominant kernel bracketed by HIP events on its stream
-    lib.rd_profile_enable(rc.ctx, b"k_sort_scatter_p*" if dom == "k_sort_scatter" else dom.encode())
+    lib.rd_profile_enable(rc.ctx, b"k_sort_sweep_p*" if dom == "k_sort_sweep" else dom.encode())
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for _ in range(args.steps):

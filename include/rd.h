@@ -103,7 +103,10 @@ rd_status rd_workspace_bytes(rd_ctx ctx, const rd_grid *grid, uint64_t n_events,
 /* Binds a trace to a caller-owned workspace of at least rd_workspace_bytes() bytes (256-byte
  * aligned).  events_on_device = 0: `events` is host memory; it is copied into the workspace on
  * `stream` and may be freed when the call returns.  events_on_device = 1: `events` is device
- * memory the library reads until rd_trace_free().  No validation of the contents happens here. */
+ * memory the library reads until rd_trace_free().  No validation of the contents happens here.
+ * With events_on_device = 1 the workspace may be NULL: such a trace can only be checked as a member
+ * of rd_check_many (rd_check returns RD_ESTATE); when its batch cannot answer for it, it is checked
+ * alone in the batch's workspace. */
 rd_status rd_trace_upload(rd_ctx ctx, const rd_grid *grid, const rd_event *events, uint64_t n_events,
                           int events_on_device, void *workspace, uint64_t workspace_bytes,
                           const rd_limits *limits, hipStream_t stream, rd_trace *out);
@@ -117,7 +120,72 @@ rd_status rd_check(rd_ctx ctx, rd_trace trace, hipStream_t stream);
  * trace, RD_ENOMEM when a device-side capacity overflowed, RD_ETRUNC when capacity < total. */
 rd_status rd_races(rd_ctx ctx, rd_trace trace, rd_pair *out, uint64_t capacity, uint64_t *n_races);
 
+/* Batched form (the same check, many traces per pass).  The members are independent traces, each
+ * bound by rd_trace_upload to its own workspace as for rd_check.  rd_check_many enqueues one pass
+ * of the pipeline over their concatenation: every trace keeps its own blocks, threads and words
+ * (blocks and global words are renumbered apart, trace indices shifted), so no pair and no
+ * happens-before edge crosses traces and the merged report, sorted, is every member's report in a
+ * run of its own.  Afterwards rd_races(ctx, traces[j], ...) returns exactly what rd_check followed
+ * by rd_races would for traces[j], errors included: when the merged pass cannot answer for a member
+ * (some member is invalid, a capacity of the merged pass overflowed, or the member has more pairs
+ * than its own rd_limits.max_pairs) that rd_races checks the member on its own first.  Members with
+ * different warp sizes, or more than 2^32 - 1 events or threads in all, are checked one by one.
+ *
+ * `workspace` (caller-owned device memory, 256-byte aligned, rd_batch_workspace_bytes() bytes) holds
+ * the merged trace and its check; it and the members' workspaces and events must stay valid until
+ * the members' reports have been read.  `limits` (may be NULL) applies to the merged pass; its
+ * default max_pairs is the sum of the members' limits, at most the default of one trace of the
+ * merged length.  Asynchronous on `stream`. */
+/* *bytes = 0 when the members cannot share one pass (rd_check_many then needs no workspace). */
+rd_status rd_batch_workspace_bytes(rd_ctx ctx, const rd_trace *traces, uint32_t n, const rd_limits *limits,
+                                   uint64_t *bytes);
+rd_status rd_check_many(rd_ctx ctx, const rd_trace *traces, uint32_t n, void *workspace, uint64_t workspace_bytes,
+                        const rd_limits *limits, hipStream_t stream);
+
+/* Reports of n checked traces in one call: member j's pairs follow member j-1's in `out` (canonical
+ * order inside each member), counts[j] = member j's total, statuses[j] = what rd_races would return
+ * for it (RD_ETRUNC when its pairs did not all fit in what was left of `capacity`).  Members of one
+ * batch are copied from the device in one transfer.  Returns RD_OK, or the first member status that
+ * is not RD_OK. */
+rd_status rd_races_many(rd_ctx ctx, const rd_trace *traces, uint32_t n, rd_pair *out, uint64_t capacity,
+                        uint64_t *counts, rd_status *statuses);
+
 rd_status rd_trace_free(rd_ctx ctx, rd_trace trace);
+
+/* Served form: a request loop with continuous batching under an HBM budget.  The caller hands over
+ * one device arena (its size is the budget for the requests' events and the passes' workspaces,
+ * reused from pass to pass; the server allocates no other device memory).  Requests queue in
+ * submission order; each of max_inflight workers (own thread, own HIP stream) takes, whenever it is
+ * free, every waiting request that fits the arena and shares the first one's warp size (up to
+ * max_batch) and checks them in one rd_check_many pass, so passes of different workers overlap on
+ * the device and requests that arrive while others run are admitted as memory comes back.  Every
+ * request's result is the one rd_check + rd_races gives for it alone (pairs, status, first offending
+ * index).  A request larger than the whole arena fails with RD_ENOMEM. */
+typedef struct {
+    uint64_t device_bytes;  /* bytes of the arena (>= 4096) */
+    uint32_t max_batch;     /* most requests in one pass (0: 256) */
+    uint32_t max_inflight;  /* passes in flight at once (0: 2) */
+} rd_server_config;
+typedef struct {
+    uint64_t n_races;    /* pairs of the request (RD_OK) */
+    uint64_t bad_index;  /* first offending event (RD_ETRACE), else UINT64_MAX */
+    double submit_s, start_s, done_s;  /* server clock (seconds since open): submitted, admitted, answered */
+} rd_request_info;
+typedef struct rd_server_s *rd_server;
+
+/* device_arena: caller-owned device memory, 256-byte aligned, cfg->device_bytes long, valid until
+ * rd_server_close returns. */
+rd_status rd_server_open(rd_ctx ctx, void *device_arena, const rd_server_config *cfg, rd_server *out);
+/* events: host memory, read until the request has been answered.  Thread safe. */
+rd_status rd_server_submit(rd_server srv, const rd_grid *grid, const rd_event *events, uint64_t n_events,
+                           uint64_t *ticket);
+/* Blocks until the request is answered; copies min(capacity, n) pairs in canonical order, fills
+ * *info (may be NULL) and forgets the ticket.  Returns the request's status (RD_ETRUNC when
+ * capacity < n).  Thread safe. */
+rd_status rd_server_wait(rd_server srv, uint64_t ticket, rd_pair *out, uint64_t capacity, rd_request_info *info);
+rd_status rd_server_stats(rd_server srv, uint64_t *passes, uint64_t *requests_done);
+/* Waits for every submitted request, stops the workers. */
+rd_status rd_server_close(rd_server srv);
 
 const char *rd_strerror(rd_status status);
 

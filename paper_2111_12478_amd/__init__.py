@@ -35,6 +35,15 @@ class rd_pair(ctypes.Structure):
     _fields_ = [("first", ctypes.c_uint32), ("second", ctypes.c_uint32)]
 
 
+class rd_server_config(ctypes.Structure):
+    _fields_ = [("device_bytes", ctypes.c_uint64), ("max_batch", ctypes.c_uint32), ("max_inflight", ctypes.c_uint32)]
+
+
+class rd_request_info(ctypes.Structure):
+    _fields_ = [("n_races", ctypes.c_uint64), ("bad_index", ctypes.c_uint64), ("submit_s", ctypes.c_double),
+                ("start_s", ctypes.c_double), ("done_s", ctypes.c_double)]
+
+
 class RdError(RuntimeError):
     def __init__(self, status, msg, event_index=None):
         super().__init__(f"{msg} (status {status})")
@@ -62,6 +71,14 @@ def load_library():
             "rd_check": ([vp, vp, vp], i32),
             "rd_races": ([vp, vp, vp, u64, P(u64)], i32),
             "rd_trace_free": ([vp, vp], i32),
+            "rd_batch_workspace_bytes": ([vp, P(vp), u32, P(rd_limits), P(u64)], i32),
+            "rd_check_many": ([vp, P(vp), u32, vp, u64, P(rd_limits), vp], i32),
+            "rd_races_many": ([vp, P(vp), u32, vp, u64, P(u64), P(i32)], i32),
+            "rd_server_open": ([vp, vp, P(rd_server_config), P(vp)], i32),
+            "rd_server_submit": ([vp, P(rd_grid), vp, u64, P(u64)], i32),
+            "rd_server_wait": ([vp, u64, vp, u64, P(rd_request_info)], i32),
+            "rd_server_stats": ([vp, P(u64), P(u64)], i32),
+            "rd_server_close": ([vp], i32),
             "rd_strerror": ([i32], ctypes.c_char_p),
             "rd_last_error": ([vp, P(u64), ctypes.c_char_p, u64], i32),
         }
@@ -127,6 +144,72 @@ def rd_races(ctx, trace, out_ptr, capacity) -> tuple[int, int]:
     n = ctypes.c_uint64()
     st = load_library().rd_races(ctx, trace, out_ptr, capacity, ctypes.byref(n))
     return st, n.value
+
+
+def _trace_array(traces):
+    arr = (ctypes.c_void_p * max(1, len(traces)))()
+    for j, t in enumerate(traces):
+        arr[j] = t
+    return arr
+
+
+def rd_batch_workspace_bytes(ctx, traces, limits=None) -> int:
+    out = ctypes.c_uint64()
+    st = load_library().rd_batch_workspace_bytes(ctx, _trace_array(traces), len(traces), _limits(limits),
+                                                 ctypes.byref(out))
+    if st != RD_OK:
+        raise RdError(st, "rd_batch_workspace_bytes failed")
+    return out.value
+
+
+def rd_check_many(ctx, traces, workspace_ptr, workspace_bytes, limits, stream) -> int:
+    return load_library().rd_check_many(ctx, _trace_array(traces), len(traces), workspace_ptr, workspace_bytes,
+                                        _limits(limits), stream)
+
+
+def rd_races_many(ctx, traces, out_ptr, capacity):
+    """Returns (status, counts (n,) uint64, statuses (n,) int32)."""
+    n = len(traces)
+    counts = np.zeros(max(n, 1), dtype=np.uint64)
+    sts = np.zeros(max(n, 1), dtype=np.int32)
+    st = load_library().rd_races_many(ctx, _trace_array(traces), n, out_ptr, capacity,
+                                      counts.ctypes.data_as(ctypes.POINTER(ctypes.c_uint64)),
+                                      sts.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)))
+    return st, counts[:n], sts[:n]
+
+
+def rd_server_open(ctx, arena_ptr, device_bytes, max_batch=0, max_inflight=0) -> int:
+    srv = ctypes.c_void_p()
+    cfg = rd_server_config(int(device_bytes), int(max_batch), int(max_inflight))
+    st = load_library().rd_server_open(ctx, arena_ptr, ctypes.byref(cfg), ctypes.byref(srv))
+    if st != RD_OK:
+        raise RdError(st, "rd_server_open failed")
+    return srv.value
+
+
+def rd_server_submit(srv, grid, events_ptr, n_events) -> int:
+    t = ctypes.c_uint64()
+    g = _grid(grid)
+    st = load_library().rd_server_submit(srv, ctypes.byref(g), events_ptr, n_events, ctypes.byref(t))
+    if st != RD_OK:
+        raise RdError(st, "rd_server_submit failed")
+    return t.value
+
+
+def rd_server_wait(srv, ticket, out_ptr, capacity) -> tuple[int, rd_request_info]:
+    info = rd_request_info()
+    st = load_library().rd_server_wait(srv, ticket, out_ptr, capacity, ctypes.byref(info))
+    return st, info
+
+
+def rd_server_stats(srv) -> tuple[int, int]:
+    p, r = ctypes.c_uint64(), ctypes.c_uint64()
+    load_library().rd_server_stats(srv, ctypes.byref(p), ctypes.byref(r))
+    return p.value, r.value
+
+
+def rd_server_close(srv) -> int:
+    return load_library().rd_server_close(srv)
 
 
 def rd_trace_free(ctx, trace) -> int:
@@ -227,6 +310,43 @@ class RaceChecker:
             return CheckResult(st, np.zeros((0, 2), np.uint32), idx, msg)
         return CheckResult(st, out[: min(cap, n)].copy())
 
+    def check_many(self, items, limits=None, batch_limits=None, workspace=None):
+        """Batched form: items = [(grid, events), ...]; one rd_check_many over all of them, then
+        one report per item, in order.  Returns a list of CheckResult."""
+        torch = self.torch
+        bound = [self.prepare(g, ev, limits) for g, ev in items]
+        traces = [b[0] for b in bound]
+        try:
+            nbytes = rd_batch_workspace_bytes(self.ctx, traces, batch_limits)
+            if workspace is None or workspace.numel() < nbytes:
+                workspace = torch.empty(max(nbytes, 256), dtype=torch.uint8, device=f"cuda:{self.device}")
+            stream = torch.cuda.current_stream(self.device).cuda_stream
+            st = rd_check_many(self.ctx, traces, workspace.data_ptr(), workspace.numel(), batch_limits, stream)
+            if st != RD_OK:
+                raise RdError(st, f"rd_check_many: {rd_last_error(self.ctx)[1]}")
+            return self.report_many(traces)
+        finally:
+            for t in traces:
+                rd_trace_free(self.ctx, t)
+            del bound, workspace
+
+    def report_many(self, traces):
+        """Reports of several checked traces through rd_races_many (one transfer per batch); a member
+        whose status is an error is reported again through rd_races for its error details."""
+        st, counts, sts = rd_races_many(self.ctx, traces, None, 0)
+        total = int(counts[(sts == RD_OK) | (sts == RD_ETRUNC)].sum()) if len(traces) else 0
+        out = np.zeros((max(total, 1), 2), dtype=np.uint32)
+        st, counts, sts = rd_races_many(self.ctx, traces, out.ctypes.data, total)
+        res, used = [], 0
+        for t, c, s in zip(traces, counts, sts):
+            c, s = int(c), int(s)
+            if s == RD_OK:
+                res.append(CheckResult(s, out[used: used + c].copy()))
+                used += c
+            else:
+                res.append(self.report(t))
+        return res
+
     def check(self, grid, events, limits=None, capacity=None):
         tr, ws, keep = self.prepare(grid, events, limits)
         try:
@@ -234,3 +354,42 @@ class RaceChecker:
         finally:
             rd_trace_free(self.ctx, tr)
             del ws, keep
+
+
+class Server:
+    """Served form on a RaceChecker's device: ``submit`` (host events, kept alive here until answered)
+    returns a ticket; ``wait`` returns (CheckResult, rd_request_info).  The arena is a torch
+    allocation of ``budget_bytes`` made once at open."""
+
+    def __init__(self, checker: RaceChecker, budget_bytes: int, max_batch: int = 0, max_inflight: int = 0):
+        torch = checker.torch
+        self.checker = checker
+        self.arena = torch.empty(budget_bytes, dtype=torch.uint8, device=f"cuda:{checker.device}")
+        self.srv = rd_server_open(checker.ctx, self.arena.data_ptr(), budget_bytes, max_batch, max_inflight)
+        self._keep = {}
+
+    def submit(self, grid, events) -> int:
+        ev = np.ascontiguousarray(events, dtype=np.uint32)
+        n = int(ev.shape[0])
+        t = rd_server_submit(self.srv, grid, ev.ctypes.data if n else None, n)
+        self._keep[t] = ev
+        return t
+
+    def wait(self, ticket, capacity=1 << 20):
+        out = np.zeros((max(capacity, 1), 2), dtype=np.uint32)
+        st, info = rd_server_wait(self.srv, ticket, out.ctypes.data, capacity)
+        self._keep.pop(ticket, None)
+        n = int(info.n_races)
+        bad = -1 if info.bad_index == (1 << 64) - 1 else int(info.bad_index)
+        return CheckResult(st, out[: min(n, capacity)].copy() if st in (RD_OK, RD_ETRUNC) else
+                           np.zeros((0, 2), np.uint32), bad), info
+
+    def stats(self):
+        return rd_server_stats(self.srv)
+
+    def close(self):
+        if self.srv:
+            rd_server_close(self.srv)
+            self.srv = None
+            self._keep.clear()
+            del self.arena

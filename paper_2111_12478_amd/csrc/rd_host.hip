@@ -1,4 +1,5 @@
 // rd_host.hip -- workspace layout, pipeline orchestration and the C interface of include/rd.h.
+#include <memory>
 #include <mutex>
 #include <new>
 #include <string.h>
@@ -17,16 +18,14 @@ static u32 next_pow2(u64 x) {
     return (u32)p;
 }
 
-u32 sort_pairs_host(const Bufs &b, u32 m, hipStream_t s);
-
 struct Plan {
     Layout L;
     u64 off_masks, off_rt_scan, off_tile_stats, off_a_cnt;
-    u32 n_tiles, T, B, radix_bits, pair_tiles, part_words;
-    u64 hist_words;
+    u32 n_tiles, T, B, radix_bits, pair_tiles, part_words, sort_tiles;
+    u64 partial_words;
 };
 
-static Plan make_plan(u64 n, u32 nb, u32 tpb, const rd_limits *lim, bool copy_events, u32 radix_bits) {
+static Plan make_plan(u64 n, u32 nb, u32 tpb, const rd_limits *lim, bool copy_events) {
     Plan P;
     memset(&P, 0, sizeof(P));
     Layout &L = P.L;
@@ -36,12 +35,17 @@ static Plan make_plan(u64 n, u32 nb, u32 tpb, const rd_limits *lim, bool copy_ev
     if (max_pairs > 0xfffffff0ull) max_pairs = 0xfffffff0ull;
     const u64 pool_bytes = lim && lim->clock_bytes ? lim->clock_bytes : (256ull << 20);
     const u64 N1 = n ? n : 1;
-    P.n_tiles = n_tiles; P.T = (u32)T; P.B = nb; P.radix_bits = radix_bits;
+    P.n_tiles = n_tiles; P.T = (u32)T; P.B = nb; P.radix_bits = SORT_RB;
     P.pair_tiles = (u32)((max_pairs + TILE - 1) / TILE);
-    const u64 hist_tiles = n_tiles > P.pair_tiles ? n_tiles : P.pair_tiles;
-    P.hist_words = (hist_tiles ? hist_tiles : 1) << (radix_bits > 8 ? radix_bits : 8);
-    u64 scan_max = P.hist_words;
+    P.sort_tiles = n_tiles > P.pair_tiles ? n_tiles : P.pair_tiles;
+    if (!P.sort_tiles) P.sort_tiles = 1;
+    {
+        const u64 e = (u64)n_tiles * ELEM_SORT_PASSES, q = (u64)P.pair_tiles * MAX_SORT_PASSES;
+        P.partial_words = (e > q ? e : q) * SORT_ND;
+    }
+    u64 scan_max = (u64)n_tiles + 1;
     if (T + 1 > scan_max) scan_max = T + 1;
+    if (B + 1 > scan_max) scan_max = B + 1;
     P.part_words = (u32)((scan_max + 4095) / 4096 + 16);
     L.sv_cap = next_pow2(2 * N1 < (1u << 22) ? 2 * N1 + 64 : (1u << 22));
     L.wo_cap = next_pow2(N1 / 4 < (1u << 18) ? N1 / 4 + 64 : (1u << 18));
@@ -101,7 +105,9 @@ static Plan make_plan(u64 n, u32 nb, u32 tpb, const rd_limits *lim, bool copy_ev
         L.off_etid[c] = take(4 * N1);
         L.off_einfo[c] = take(4 * N1);
     }
-    L.off_hist = take(4 * P.hist_words);
+    L.off_sort_status = take(2 * 8ull * SORT_ND * P.sort_tiles);
+    L.off_sort_partial = take(4ull * P.partial_words);
+    L.off_sort_tot = take(4ull * (MAX_SORT_PASSES * SORT_ND + MAX_SORT_PASSES));
     L.off_part = take(4ull * P.part_words);
     L.off_tile_agg = take(agg_bytes() * ((u64)n_tiles + 1));
     for (int c = 0; c < 2; c++) {
@@ -171,7 +177,11 @@ static Bufs make_bufs(const Plan &P, char *ws, const void *events_dev, u64 n, u3
         b.pfirst[c] = (u32 *)(ws + L.off_pfirst[c]);
         b.psecond[c] = (u32 *)(ws + L.off_psecond[c]);
     }
-    b.hist = (u32 *)(ws + L.off_hist);
+    b.sort_status = (u64 *)(ws + L.off_sort_status);
+    b.sort_status_stride = (u64)SORT_ND * P.sort_tiles;
+    b.sort_partial = (u32 *)(ws + L.off_sort_partial);
+    b.sort_tot = (u32 *)(ws + L.off_sort_tot);
+    b.sort_ctr = b.sort_tot + MAX_SORT_PASSES * SORT_ND;
     b.part = (u32 *)(ws + L.off_part);
     b.tile_agg = ws + L.off_tile_agg;
     b.max_pairs = L.max_pairs;
@@ -239,7 +249,7 @@ void prof_end(hipStream_t s) {
 
 hipError_t enqueue_check(const Bufs &b, u64 *masks, u32 *rt_scan, hipStream_t s) {
     u64 *sync_mask = masks, *acc_mask = masks + (u64)b.n_tiles * 64, *atom_mask = masks + 2 * (u64)b.n_tiles * 64;
-    prep_init(b, s);
+    prep_init(b, rt_scan, s);
     prep_ingest(b, sync_mask, acc_mask, atom_mask, s);
     prep_sync_lists(b, sync_mask, atom_mask, s);
     prep_elements(b, acc_mask, s);
@@ -265,6 +275,25 @@ struct rd_ctx_s {
     Profiler prof;
 };
 
+// A batched check: the merged trace's workspace and the member table.  Shared by the member traces
+// (each keeps its index); the first rd_races of a member reads the batch's state once.
+struct Batch {
+    Plan plan;
+    Bufs bufs;
+    char *ws;
+    u64 *masks;
+    u32 *rt_scan;
+    BatchTrace *tr_dev;
+    u32 *off_dev, *bad_dev;
+    std::vector<BatchTrace> tr_host;
+    std::vector<u32> off_host;
+    u32 zero = 0;
+    u64 ws_bytes;
+    hipStream_t stream;
+    std::mutex mu, ws_mu;  // ws_mu: members checked alone in this workspace, one at a time
+    bool read = false, failed = false;
+};
+
 struct rd_trace_s {
     Plan plan;
     Bufs bufs;
@@ -275,7 +304,58 @@ struct rd_trace_s {
     int checked;
     rd_grid grid;
     uint64_t n;
+    std::shared_ptr<Batch> batch;  // set by rd_check_many until the next rd_check
+    u32 batch_idx;
+    rd_limits lim;
+    // a member without a workspace of its own whose batch could not answer for it is checked alone
+    // in the batch's workspace once; its report is kept here
+    int cached;
+    rd_status cache_st;
+    uint64_t cache_idx, cache_n;
+    std::string cache_msg;
+    std::vector<rd_pair> cache;
 };
+
+// Shape of the merged trace of a batch; false when the members cannot be merged (different warp
+// sizes, or more than 2^32 - 1 events or threads in all).
+struct BatchShape {
+    u64 N, B;
+    u32 tpb, ws;
+    rd_limits lim;
+    u64 table_off, off_off, bad_off, total;
+    Plan plan;
+};
+static bool batch_shape(const rd_trace *traces, uint32_t n, const rd_limits *limits, BatchShape &S) {
+    S.N = 0;
+    S.B = 0;
+    S.tpb = 1;
+    S.ws = 0;
+    u64 pairs = 0;
+    for (uint32_t j = 0; j < n; j++) {
+        const rd_trace t = traces[j];
+        const u32 ws = t->grid.warp_size ? t->grid.warp_size : 32;
+        if (j == 0) S.ws = ws;
+        else if (ws != S.ws) return false;
+        S.N += t->n;
+        S.B += t->grid.n_blocks;
+        if (t->grid.threads_per_block > S.tpb) S.tpb = t->grid.threads_per_block;
+        pairs += t->bufs.max_pairs;
+    }
+    if (S.N >= (1ull << 32) || S.B * S.tpb >= (1ull << 32)) return false;
+    const u64 dflt = S.N / 4 > (1u << 20) ? S.N / 4 : (1u << 20);  // as for one trace of N events
+    S.lim.max_pairs = limits && limits->max_pairs ? limits->max_pairs : (pairs < dflt ? pairs : dflt);
+    S.lim.clock_bytes = limits && limits->clock_bytes ? limits->clock_bytes : 0;
+    S.plan = make_plan(S.N, (u32)S.B, S.tpb, &S.lim, true);
+    S.table_off = align_up(S.plan.L.total, 256);
+    S.off_off = align_up(S.table_off + sizeof(BatchTrace) * (u64)n, 256);
+    S.bad_off = align_up(S.off_off + 4ull * (n + 1), 256);
+    S.total = S.bad_off + 256;
+    return true;
+}
+
+namespace rd {
+int ctx_device(rd_ctx c) { return c->device; }
+}  // namespace rd
 
 static rd_status set_err(rd_ctx ctx, rd_status st, uint64_t index, const char *msg) {
     if (ctx) {
@@ -292,12 +372,6 @@ static bool grid_ok(const rd_grid *g, uint64_t n) {
     if ((uint64_t)g->n_blocks * g->threads_per_block >= (1ull << 32)) return false;
     if (n >= (1ull << 32)) return false;
     return true;
-}
-
-static u32 env_radix_bits() {
-    const char *e = getenv("RD_RADIX_BITS");
-    if (e && atoi(e) == 11) return 11;
-    return 8;
 }
 
 extern "C" {
@@ -326,7 +400,7 @@ rd_status rd_workspace_bytes(rd_ctx ctx, const rd_grid *grid, uint64_t n_events,
                              uint64_t *bytes) {
     if (!ctx || !bytes) return RD_EINVAL;
     if (!grid_ok(grid, n_events)) return set_err(ctx, RD_EINVAL, UINT64_MAX, "bad grid or event count");
-    const Plan P = make_plan(n_events, grid->n_blocks, grid->threads_per_block, limits, true, env_radix_bits());
+    const Plan P = make_plan(n_events, grid->n_blocks, grid->threads_per_block, limits, true);
     *bytes = P.L.total;
     return RD_OK;
 }
@@ -337,9 +411,31 @@ rd_status rd_trace_upload(rd_ctx ctx, const rd_grid *grid, const rd_event *event
     if (!ctx || !out) return RD_EINVAL;
     *out = nullptr;
     if (!grid_ok(grid, n_events)) return set_err(ctx, RD_EINVAL, UINT64_MAX, "bad grid or event count");
-    if (!workspace || ((uintptr_t)workspace & 255)) return set_err(ctx, RD_EINVAL, UINT64_MAX, "workspace null or not 256-byte aligned");
     if (n_events && !events) return set_err(ctx, RD_EINVAL, UINT64_MAX, "null events");
-    const Plan P = make_plan(n_events, grid->n_blocks, grid->threads_per_block, limits, true, env_radix_bits());
+    const u32 ws = grid->warp_size ? grid->warp_size : 32;
+    if (!workspace && events_on_device) {
+        // a batch member only: its events stay where they are, no workspace of its own
+        rd_trace t = new (std::nothrow) rd_trace_s;
+        if (!t) return RD_ENOMEM;
+        t->plan = make_plan(n_events, grid->n_blocks, grid->threads_per_block, limits, false);
+        memset(&t->bufs, 0, sizeof(t->bufs));
+        t->bufs.ev = (const uint4 *)events;
+        t->bufs.max_pairs = t->plan.L.max_pairs;
+        t->bufs.N = (u32)n_events;
+        t->ws = nullptr;
+        t->masks = nullptr;
+        t->rt_scan = nullptr;
+        t->grid = *grid;
+        t->n = n_events;
+        t->stream = stream;
+        t->checked = 0;
+        t->cached = 0;
+        t->lim = limits ? *limits : rd_limits{0, 0};
+        *out = t;
+        return RD_OK;
+    }
+    if (!workspace || ((uintptr_t)workspace & 255)) return set_err(ctx, RD_EINVAL, UINT64_MAX, "workspace null or not 256-byte aligned");
+    const Plan P = make_plan(n_events, grid->n_blocks, grid->threads_per_block, limits, true);
     if (workspace_bytes < P.L.total) return set_err(ctx, RD_ENOMEM, UINT64_MAX, "workspace too small");
     if (hipSetDevice(ctx->device) != hipSuccess) return set_err(ctx, RD_EHIP, UINT64_MAX, "hipSetDevice failed");
     rd_trace t = new (std::nothrow) rd_trace_s;
@@ -350,7 +446,8 @@ rd_status rd_trace_upload(rd_ctx ctx, const rd_grid *grid, const rd_event *event
     t->n = n_events;
     t->stream = stream;
     t->checked = 0;
-    const u32 ws = grid->warp_size ? grid->warp_size : 32;
+    t->cached = 0;
+    t->lim = limits ? *limits : rd_limits{0, 0};
     const void *dev_events = nullptr;
     if (events_on_device) dev_events = events;
     else if (n_events) {
@@ -368,8 +465,11 @@ rd_status rd_trace_upload(rd_ctx ctx, const rd_grid *grid, const rd_event *event
 
 rd_status rd_check(rd_ctx ctx, rd_trace trace, hipStream_t stream) {
     if (!ctx || !trace) return RD_EINVAL;
+    if (!trace->ws) return set_err(ctx, RD_ESTATE, UINT64_MAX, "the trace has no workspace: check it with rd_check_many");
     if (hipSetDevice(ctx->device) != hipSuccess) return set_err(ctx, RD_EHIP, UINT64_MAX, "hipSetDevice failed");
     trace->stream = stream;
+    trace->batch.reset();
+    trace->cached = 0;
     Profiler *saved = g_prof;
     g_prof = ctx->prof.filter.empty() ? nullptr : &ctx->prof;
     const hipError_t e = enqueue_check(trace->bufs, trace->masks, trace->rt_scan, stream);
@@ -379,20 +479,73 @@ rd_status rd_check(rd_ctx ctx, rd_trace trace, hipStream_t stream) {
     return RD_OK;
 }
 
-rd_status rd_races(rd_ctx ctx, rd_trace trace, rd_pair *out, uint64_t capacity, uint64_t *n_races) {
-    if (!ctx || !trace || !n_races) return RD_EINVAL;
-    *n_races = 0;
-    if (!trace->checked) return set_err(ctx, RD_ESTATE, UINT64_MAX, "rd_races before rd_check");
-    if (hipSetDevice(ctx->device) != hipSuccess) return set_err(ctx, RD_EHIP, UINT64_MAX, "hipSetDevice failed");
-    hipStream_t s = trace->stream;
+// Report of a member of a batched check.  Returns false when the batch cannot answer for the trace
+// (some member was invalid, a capacity of the merged check overflowed, or the trace has more pairs
+// than its own limit): the caller then checks the trace on its own, which gives the plain result,
+// errors included.
+// Waits for the batch and reads its state once; false when that fails (HIP error, status set).
+static bool batch_read_state(rd_ctx ctx, Batch &B, rd_status *st) {
+    std::lock_guard<std::mutex> g(B.mu);
+    if (B.read) return true;
     DevParams prm;
-    if (hipMemcpyAsync(&prm, trace->bufs.prm, sizeof(prm), hipMemcpyDeviceToHost, s) != hipSuccess ||
+    u32 bad = 0;
+    if (hipMemcpyAsync(&prm, B.bufs.prm, sizeof(prm), hipMemcpyDeviceToHost, B.stream) != hipSuccess ||
+        hipMemcpyAsync(&bad, B.bad_dev, 4, hipMemcpyDeviceToHost, B.stream) != hipSuccess ||
+        hipMemcpyAsync(B.tr_host.data(), B.tr_dev, sizeof(BatchTrace) * B.tr_host.size(), hipMemcpyDeviceToHost,
+                       B.stream) != hipSuccess ||
+        hipStreamSynchronize(B.stream) != hipSuccess) {
+        *st = set_err(ctx, RD_EHIP, UINT64_MAX, "reading the batch state failed");
+        return false;
+    }
+    B.failed = bad || prm.err || prm.first_bad_record != NONE || prm.first_bad_sync != NONE;
+    B.read = true;
+    return true;
+}
+
+static bool batch_races(rd_ctx ctx, rd_trace trace, rd_pair *out, uint64_t capacity, uint64_t *n_races,
+                        rd_status *st) {
+    Batch &B = *trace->batch;
+    if (!batch_read_state(ctx, B, st)) return true;
+    if (B.failed) return false;
+    const BatchTrace &t = B.tr_host[trace->batch_idx];
+    const u64 m = t.pair_hi - t.pair_lo;
+    *n_races = m;
+    if (m > trace->bufs.max_pairs) {  // what the member's own check reports
+        *st = set_err(ctx, RD_ENOMEM, UINT64_MAX, "race pairs exceed rd_limits.max_pairs");
+        return true;
+    }
+    *st = RD_OK;
+    if (!out || !capacity || !m) {
+        if (m > capacity) *st = set_err(ctx, RD_ETRUNC, UINT64_MAX, "capacity");
+        return true;
+    }
+    const u64 k = capacity < m ? capacity : m;
+    std::vector<u32> f(k), sec(k);
+    if (hipMemcpyAsync(f.data(), B.bufs.pfirst[0] + t.pair_lo, 4 * k, hipMemcpyDeviceToHost, B.stream) != hipSuccess ||
+        hipMemcpyAsync(sec.data(), B.bufs.psecond[0] + t.pair_lo, 4 * k, hipMemcpyDeviceToHost, B.stream) !=
+            hipSuccess ||
+        hipStreamSynchronize(B.stream) != hipSuccess) {
+        *st = set_err(ctx, RD_EHIP, UINT64_MAX, "copying the pairs failed");
+        return true;
+    }
+    const u32 base = B.off_host[trace->batch_idx];
+    for (u64 q = 0; q < k; q++) { out[q].first = f[q] - base; out[q].second = sec[q] - base; }
+    if (capacity < m) *st = set_err(ctx, RD_ETRUNC, UINT64_MAX, "more races than capacity");
+    return true;
+}
+
+// The report of a check enqueued on `s` over buffers `b` (waits for it).
+static rd_status plain_races(rd_ctx ctx, const Bufs &b, hipStream_t s, rd_pair *out, uint64_t capacity,
+                             uint64_t *n_races) {
+    DevParams prm;
+    if (hipMemcpyAsync(&prm, b.prm, sizeof(prm), hipMemcpyDeviceToHost, s) != hipSuccess ||
         hipStreamSynchronize(s) != hipSuccess)
         return set_err(ctx, RD_EHIP, UINT64_MAX, "reading the check state failed");
     if (prm.first_bad_record != NONE) return set_err(ctx, RD_ETRACE, prm.first_bad_record, "malformed record");
     if (prm.err & ERR_PHASE) return set_err(ctx, RD_EINVAL, UINT64_MAX, "a thread passed more than 2^30 barriers");
     if (prm.first_bad_sync != NONE)
         return set_err(ctx, RD_ETRACE, prm.first_bad_sync, "event runs ahead of an unfinished barrier");
+    if (prm.err & ERR_SORT) return set_err(ctx, RD_EHIP, UINT64_MAX, "location sort look-back did not finish");
     if (prm.err & ERR_KEYSPAN)
         return set_err(ctx, RD_EINVAL, UINT64_MAX, "address span too large for a 32-bit location key");
     if (prm.err & ERR_POOL) return set_err(ctx, RD_ENOMEM, UINT64_MAX, "knowledge-vector pool exhausted (rd_limits.clock_bytes)");
@@ -406,17 +559,234 @@ rd_status rd_races(rd_ctx ctx, rd_trace trace, rd_pair *out, uint64_t capacity, 
     if (!out || !capacity || !m) return m > capacity ? set_err(ctx, RD_ETRUNC, UINT64_MAX, "capacity") : RD_OK;
     Profiler *saved = g_prof;
     g_prof = ctx->prof.filter.empty() ? nullptr : &ctx->prof;
-    const u32 buf = sort_pairs_host(trace->bufs, m, s);
+    sort_pairs(b, nullptr, m, m, s);
     g_prof = saved;
     const u64 k = capacity < m ? capacity : m;
     std::vector<u32> f(k), sec(k);
-    if (hipMemcpyAsync(f.data(), trace->bufs.pfirst[buf], 4 * k, hipMemcpyDeviceToHost, s) != hipSuccess ||
-        hipMemcpyAsync(sec.data(), trace->bufs.psecond[buf], 4 * k, hipMemcpyDeviceToHost, s) != hipSuccess ||
+    u32 err_after = 0;
+    if (hipMemcpyAsync(f.data(), b.pfirst[0], 4 * k, hipMemcpyDeviceToHost, s) != hipSuccess ||
+        hipMemcpyAsync(sec.data(), b.psecond[0], 4 * k, hipMemcpyDeviceToHost, s) != hipSuccess ||
+        hipMemcpyAsync(&err_after, &b.prm->err, 4, hipMemcpyDeviceToHost, s) != hipSuccess ||
         hipStreamSynchronize(s) != hipSuccess)
         return set_err(ctx, RD_EHIP, UINT64_MAX, "copying the pairs failed");
+    if (err_after & ERR_SORT) return set_err(ctx, RD_EHIP, UINT64_MAX, "pair sort look-back did not finish");
     for (u64 q = 0; q < k; q++) { out[q].first = f[q]; out[q].second = sec[q]; }
     if (capacity < m) return set_err(ctx, RD_ETRUNC, UINT64_MAX, "more races than capacity");
     return RD_OK;
+}
+
+// A member without a workspace whose batch cannot answer for it: checked alone in the batch's
+// workspace (which is at least as large as the member's own would be), once; the report is kept.
+static rd_status member_alone(rd_ctx ctx, rd_trace trace, rd_pair *out, uint64_t capacity, uint64_t *n_races) {
+    Batch &B = *trace->batch;
+    if (!trace->cached) {
+        std::lock_guard<std::mutex> g(B.ws_mu);
+        const u32 ws = trace->grid.warp_size ? trace->grid.warp_size : 32;
+        const Plan P = make_plan(trace->n, trace->grid.n_blocks, trace->grid.threads_per_block, &trace->lim, false);
+        if (P.L.total > B.ws_bytes)
+            return set_err(ctx, RD_ENOMEM, UINT64_MAX, "the batch workspace cannot hold this member's own check");
+        const Bufs b = make_bufs(P, B.ws, trace->bufs.ev, trace->n, trace->grid.n_blocks,
+                                 trace->grid.threads_per_block, ws);
+        Profiler *saved = g_prof;
+        g_prof = ctx->prof.filter.empty() ? nullptr : &ctx->prof;
+        const hipError_t e = enqueue_check(b, (u64 *)(B.ws + P.off_masks), (u32 *)(B.ws + P.off_rt_scan), B.stream);
+        g_prof = saved;
+        if (e != hipSuccess) return set_err(ctx, RD_EHIP, UINT64_MAX, hipGetErrorString(e));
+        uint64_t n = 0;
+        rd_status st = plain_races(ctx, b, B.stream, nullptr, 0, &n);
+        trace->cache.clear();
+        if (st == RD_OK || st == RD_ETRUNC) {
+            trace->cache.resize(n);
+            st = plain_races(ctx, b, B.stream, trace->cache.data(), n, &n);
+        }
+        if (st == RD_EHIP) return st;
+        trace->cache_st = st;
+        trace->cache_n = n;
+        {
+            std::lock_guard<std::mutex> g2(ctx->mu);
+            trace->cache_idx = ctx->last_index;
+            trace->cache_msg = ctx->last_msg;
+        }
+        trace->cached = 1;
+    }
+    *n_races = trace->cache_n;
+    if (trace->cache_st != RD_OK) return set_err(ctx, trace->cache_st, trace->cache_idx, trace->cache_msg.c_str());
+    const u64 k = out ? (capacity < trace->cache_n ? capacity : trace->cache_n) : 0;
+    for (u64 q = 0; q < k; q++) out[q] = trace->cache[q];
+    if (capacity < trace->cache_n) return set_err(ctx, RD_ETRUNC, UINT64_MAX, "more races than capacity");
+    return RD_OK;
+}
+
+rd_status rd_races(rd_ctx ctx, rd_trace trace, rd_pair *out, uint64_t capacity, uint64_t *n_races) {
+    if (!ctx || !trace || !n_races) return RD_EINVAL;
+    *n_races = 0;
+    if (!trace->checked) return set_err(ctx, RD_ESTATE, UINT64_MAX, "rd_races before rd_check");
+    if (hipSetDevice(ctx->device) != hipSuccess) return set_err(ctx, RD_EHIP, UINT64_MAX, "hipSetDevice failed");
+    if (trace->batch) {
+        rd_status st = RD_OK;
+        if (batch_races(ctx, trace, out, capacity, n_races, &st)) return st;
+        if (!trace->ws) return member_alone(ctx, trace, out, capacity, n_races);
+        const rd_status c = rd_check(ctx, trace, trace->batch->stream);  // on its own; drops the batch
+        if (c != RD_OK) return c;
+    }
+    return plain_races(ctx, trace->bufs, trace->stream, out, capacity, n_races);
+}
+
+rd_status rd_batch_workspace_bytes(rd_ctx ctx, const rd_trace *traces, uint32_t n, const rd_limits *limits,
+                                   uint64_t *bytes) {
+    if (!ctx || !bytes || (n && !traces)) return RD_EINVAL;
+    for (uint32_t j = 0; j < n; j++)
+        if (!traces[j]) return set_err(ctx, RD_EINVAL, UINT64_MAX, "null trace in the batch");
+    BatchShape S;
+    *bytes = !n ? 256 : batch_shape(traces, n, limits, S) ? S.total : 0;
+    return RD_OK;
+}
+
+rd_status rd_check_many(rd_ctx ctx, const rd_trace *traces, uint32_t n, void *workspace, uint64_t workspace_bytes,
+                        const rd_limits *limits, hipStream_t stream) {
+    if (!ctx || (n && !traces)) return RD_EINVAL;
+    for (uint32_t j = 0; j < n; j++)
+        if (!traces[j]) return set_err(ctx, RD_EINVAL, UINT64_MAX, "null trace in the batch");
+    if (!n) return RD_OK;
+    if (hipSetDevice(ctx->device) != hipSuccess) return set_err(ctx, RD_EHIP, UINT64_MAX, "hipSetDevice failed");
+    BatchShape S;
+    if (!batch_shape(traces, n, limits, S)) {
+        // members that cannot share one merged trace are checked one by one, in order
+        for (uint32_t j = 0; j < n; j++)
+            if (!traces[j]->ws)
+                return set_err(ctx, RD_EINVAL, UINT64_MAX,
+                               "members cannot share one pass (warp sizes or sizes) and one has no workspace");
+        for (uint32_t j = 0; j < n; j++) {
+            const rd_status st = rd_check(ctx, traces[j], stream);
+            if (st != RD_OK) return st;
+        }
+        return RD_OK;
+    }
+    if (!workspace || ((uintptr_t)workspace & 255))
+        return set_err(ctx, RD_EINVAL, UINT64_MAX, "workspace null or not 256-byte aligned");
+    if (workspace_bytes < S.total) return set_err(ctx, RD_ENOMEM, UINT64_MAX, "batch workspace too small");
+    std::shared_ptr<Batch> B(new (std::nothrow) Batch);
+    if (!B) return RD_ENOMEM;
+    char *ws = (char *)workspace;
+    B->plan = S.plan;
+    B->ws = ws;
+    B->ws_bytes = workspace_bytes;
+    B->bufs = make_bufs(S.plan, ws, nullptr, S.N, (u32)S.B, S.tpb, S.ws);
+    B->masks = (u64 *)(ws + S.plan.off_masks);
+    B->rt_scan = (u32 *)(ws + S.plan.off_rt_scan);
+    B->tr_dev = (BatchTrace *)(ws + S.table_off);
+    B->off_dev = (u32 *)(ws + S.off_off);
+    B->bad_dev = (u32 *)(ws + S.bad_off);
+    B->stream = stream;
+    B->tr_host.resize(n);
+    B->off_host.resize(n + 1);
+    u32 off = 0, blk = 0;
+    for (uint32_t j = 0; j < n; j++) {
+        const rd_trace t = traces[j];
+        BatchTrace &d = B->tr_host[j];
+        memset(&d, 0, sizeof(d));
+        d.ev = t->bufs.ev;
+        d.n = (u32)t->n;
+        d.n_blocks = t->grid.n_blocks;
+        d.tpb = t->grid.threads_per_block;
+        d.blk_off = blk;
+        d.gmin = NONE;
+        d.gmax = 0;
+        B->off_host[j] = off;
+        off += (u32)t->n;
+        blk += t->grid.n_blocks;
+    }
+    B->off_host[n] = off;
+    Profiler *saved = g_prof;
+    g_prof = ctx->prof.filter.empty() ? nullptr : &ctx->prof;
+    hipError_t e = hipMemcpyAsync(B->tr_dev, B->tr_host.data(), sizeof(BatchTrace) * n, hipMemcpyHostToDevice, stream);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(B->off_dev, B->off_host.data(), 4ull * (n + 1), hipMemcpyHostToDevice, stream);
+    if (e == hipSuccess) e = hipMemcpyAsync(B->bad_dev, &B->zero, 4, hipMemcpyHostToDevice, stream);
+    if (e == hipSuccess) {
+        batch_merge(B->tr_dev, B->off_dev, n, (u32)S.N, S.tpb, (uint4 *)B->bufs.ev, B->bad_dev, stream);
+        e = enqueue_check(B->bufs, B->masks, B->rt_scan, stream);
+    }
+    if (e == hipSuccess) {
+        sort_pairs(B->bufs, &B->bufs.prm->n_pairs_kept, 0, B->bufs.max_pairs, stream);
+        batch_pair_ranges(B->tr_dev, B->off_dev, n, B->bufs, stream);
+        e = hipGetLastError();
+    }
+    g_prof = saved;
+    if (e != hipSuccess) return set_err(ctx, RD_EHIP, UINT64_MAX, hipGetErrorString(e));
+    for (uint32_t j = 0; j < n; j++) {
+        traces[j]->batch = B;
+        traces[j]->batch_idx = j;
+        traces[j]->checked = 1;
+        traces[j]->cached = 0;
+        traces[j]->stream = stream;
+    }
+    return RD_OK;
+}
+
+rd_status rd_races_many(rd_ctx ctx, const rd_trace *traces, uint32_t n, rd_pair *out, uint64_t capacity,
+                        uint64_t *counts, rd_status *statuses) {
+    if (!ctx || (n && (!traces || !counts || !statuses))) return RD_EINVAL;
+    for (uint32_t j = 0; j < n; j++)
+        if (!traces[j]) return set_err(ctx, RD_EINVAL, UINT64_MAX, "null trace");
+    if (hipSetDevice(ctx->device) != hipSuccess) return set_err(ctx, RD_EHIP, UINT64_MAX, "hipSetDevice failed");
+    // one copy of the merged report when every member comes from the same healthy batch
+    std::shared_ptr<Batch> B = n ? traces[0]->batch : nullptr;
+    for (uint32_t j = 0; j < n && B; j++)
+        if (traces[j]->batch != B) B = nullptr;
+    std::vector<u32> f, sec;
+    if (B) {
+        rd_status st = RD_OK;
+        if (!batch_read_state(ctx, *B, &st)) return st;
+        if (B->failed) {
+            B = nullptr;  // members answer one by one below
+        } else {
+            u64 total = 0;
+            for (uint32_t j = 0; j < n; j++) {
+                const BatchTrace &t = B->tr_host[traces[j]->batch_idx];
+                if (t.pair_hi > total) total = t.pair_hi;
+            }
+            f.resize(total);
+            sec.resize(total);
+            if (total && (hipMemcpyAsync(f.data(), B->bufs.pfirst[0], 4 * total, hipMemcpyDeviceToHost, B->stream) !=
+                              hipSuccess ||
+                          hipMemcpyAsync(sec.data(), B->bufs.psecond[0], 4 * total, hipMemcpyDeviceToHost,
+                                         B->stream) != hipSuccess ||
+                          hipStreamSynchronize(B->stream) != hipSuccess))
+                return set_err(ctx, RD_EHIP, UINT64_MAX, "copying the pairs failed");
+        }
+    }
+    rd_status worst = RD_OK;
+    u64 used = 0;
+    for (uint32_t j = 0; j < n; j++) {
+        const rd_trace tr = traces[j];
+        rd_pair *dst = out ? out + used : nullptr;
+        const u64 room = out && capacity > used ? capacity - used : 0;
+        rd_status st;
+        uint64_t m = 0;
+        if (B) {
+            const BatchTrace &t = B->tr_host[tr->batch_idx];
+            m = t.pair_hi - t.pair_lo;
+            if (m > tr->bufs.max_pairs) {
+                st = RD_ENOMEM;  // what the member's own check reports: more pairs than its limit
+            } else {
+                const u64 k = room < m ? room : m;
+                const u32 base = B->off_host[tr->batch_idx];
+                for (u64 q = 0; q < k; q++) {
+                    dst[q].first = f[t.pair_lo + q] - base;
+                    dst[q].second = sec[t.pair_lo + q] - base;
+                }
+                st = k < m ? RD_ETRUNC : RD_OK;
+            }
+        } else {
+            st = rd_races(ctx, tr, dst, room, &m);
+        }
+        counts[j] = m;
+        statuses[j] = st;
+        if (st == RD_OK || st == RD_ETRUNC) used += m < room ? m : room;
+        if (st != RD_OK && worst == RD_OK) worst = st;
+    }
+    return worst;
 }
 
 rd_status rd_trace_free(rd_ctx ctx, rd_trace trace) {

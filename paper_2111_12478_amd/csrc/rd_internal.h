@@ -45,7 +45,17 @@ enum : u32 {
     ERR_PAIRS = 4,      // internal pair buffer overflowed
     ERR_TABLE = 8,      // sync-variable or warp-barrier table overflowed
     ERR_PHASE = 16,     // a thread passed more than 2^30 barriers
+    ERR_SORT = 32,      // a radix-sort look-back wait hit its spin limit
 };
+
+// Radix sort: 8-bit digits, at most 8 passes per sort (32-bit keys, or two 32-bit halves of a pair
+// key of up to 2 x 32 bits).
+constexpr u32 SORT_RB = 8, SORT_ND = 1u << SORT_RB;
+constexpr u32 MAX_SORT_PASSES = 8;
+constexpr u32 ELEM_SORT_PASSES = 4;  // 32-bit location keys
+// Digit counts: every tile writes one row of partial counts ([pass][digit], ELEM_SORT_PASSES rows
+// of digits for the location sort, MAX_SORT_PASSES for the pair sort); a reduction adds the rows
+// into per-pass totals.
 
 // Device-side state of one check.  Zeroed (and the "min" fields set to NONE) by k_init.
 struct DevParams {
@@ -129,7 +139,11 @@ struct Bufs {
     // elements (ping-pong)
     u32 *ekey[2], *eidx[2], *etid[2], *einfo[2];
     // radix sort
-    u32 *hist;              // [RADIX_MAX * n_tiles]
+    u64 *sort_status;       // [2][status_tiles][SORT_ND] look-back words (flag << 62 | count)
+    u64 sort_status_stride; // status_tiles * SORT_ND
+    u32 *sort_partial;      // [tiles][passes][SORT_ND] per-tile digit counts
+    u32 *sort_tot;          // [MAX_SORT_PASSES][SORT_ND] digit totals of each pass
+    u32 *sort_ctr;          // [MAX_SORT_PASSES] tile tickets of each pass
     u32 *part;              // [scan partials]
     // segment check
     void *tile_agg;         // [n_tiles] aggregates -> exclusive prefixes
@@ -140,9 +154,18 @@ struct Bufs {
     u32 N, T, B, tpb, ws;
     u32 div_m, div_s1, div_s2;  // tid / tpb as a multiply-high and shifts
     u32 n_tiles;            // ceil(N / TILE)
-    u32 radix_bits;         // 8 or 11
+    u32 radix_bits;         // digit width of the location sort (SORT_RB)
     u32 sorted_buf;         // which element buffer holds the sorted elements (set by the host plan)
     u32 pair_buf;
+};
+
+// One member of a batched check (device table): where its events are, its grid and its place in
+// the merged trace; the global-word range and pair run are filled in on the device.
+struct BatchTrace {
+    const uint4 *ev;
+    u32 n, n_blocks, tpb, blk_off;
+    u32 gmin, gmax, goff;   // global words of its accesses: [gmin, gmax] -> [goff, goff + span)
+    u32 pair_lo, pair_hi;   // its run in the merged, sorted report
 };
 
 // ---------------------------------------------------------------- wavefront helpers (wave64)
@@ -170,8 +193,8 @@ struct Layout {
         off_inst_last, off_inst_handle, off_n_active, off_rt, off_priv, off_priv_next, off_bk,
         off_priv_head, off_sv_key, off_sv_tag, off_sv_handle, off_wo_key, off_wo_val, off_wi_key,
         off_wi_occ, off_wi_inst, off_winst_mask, off_winst_arrived, off_winst_last, off_winst_nar,
-        off_winst_arr, off_pool, off_ekey[2], off_eidx[2], off_etid[2], off_einfo[2], off_hist,
-        off_part, off_tile_agg, off_pfirst[2], off_psecond[2];
+        off_winst_arr, off_pool, off_ekey[2], off_eidx[2], off_etid[2], off_einfo[2], off_sort_status,
+        off_sort_partial, off_sort_tot, off_part, off_tile_agg, off_pfirst[2], off_psecond[2];
     u32 sv_cap, wo_cap, pool_cap_bytes_hi;
     u64 pool_bytes, max_pairs;
 };

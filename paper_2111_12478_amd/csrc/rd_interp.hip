@@ -342,20 +342,6 @@ __global__ void k_know(Bufs b) {
     }
 }
 
-__global__ void k_fill_u32_if(u32 *p, u64 n, u32 v, const DevParams *P, u32 mode_mask) {
-    if (!(P->mode & mode_mask)) return;
-    for (u64 i = (u64)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (u64)gridDim.x * blockDim.x) p[i] = v;
-}
-__global__ void k_fill_u64_if(u64 *p, u64 n, u64 v, const DevParams *P, u32 mode_mask) {
-    if (!(P->mode & mode_mask)) return;
-    for (u64 i = (u64)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (u64)gridDim.x * blockDim.x) p[i] = v;
-}
-__global__ void k_fill_dyn_if(u32 *p, const u32 *count, u32 v, const DevParams *P, u32 mode_mask) {
-    if (!(P->mode & mode_mask)) return;
-    const u32 n = *count;
-    for (u32 i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) p[i] = v;
-}
-
 static inline unsigned grid_n(u64 n) {
     u64 g = (n + 255) / 256;
     return (unsigned)(g < 1 ? 1 : (g > 2048 ? 2048 : g));
@@ -364,15 +350,18 @@ static inline unsigned grid_n(u64 n) {
 void interp_run(const Bufs &b, const u32 *rt_scan, hipStream_t s) {
     const DevParams *P = b.prm;
     // tables, only in traces with releases/acquires/warp barriers
-    RD_LAUNCH("k_fill_u32_if", k_fill_u32_if, dim3(grid_n(b.T)), dim3(256), 0, s, b.priv, (u64)b.T, 0u, P, MODE_SYNC);
-    RD_LAUNCH("k_fill_u32_if", k_fill_u32_if, dim3(grid_n(b.B)), dim3(256), 0, s, b.bk, (u64)b.B, 0u, P, MODE_SYNC);
-    RD_LAUNCH("k_fill_u32_if", k_fill_u32_if, dim3(grid_n(b.B)), dim3(256), 0, s, b.priv_head, (u64)b.B, NONE, P, MODE_SYNC);
-    RD_LAUNCH("k_fill_u32_if", k_fill_u32_if, dim3(grid_n(b.sv_cap)), dim3(256), 0, s, b.sv_handle, (u64)b.sv_cap, 0u, P, MODE_SYNC);
-    RD_LAUNCH("k_fill_u64_if", k_fill_u64_if, dim3(grid_n(b.wo_cap)), dim3(256), 0, s, b.wo_key, (u64)b.wo_cap, ~0ull, P, MODE_WBAR);
-    RD_LAUNCH("k_fill_u32_if", k_fill_u32_if, dim3(grid_n(b.wo_cap)), dim3(256), 0, s, b.wi_inst, (u64)b.wo_cap, NONE, P, MODE_WBAR);
-    RD_LAUNCH("k_fill_dyn_if", k_fill_dyn_if, dim3(grid_n(b.N)), dim3(256), 0, s, b.s_khandle, &P->n_sync, 0u, P, MODE_SYNC);
-    RD_LAUNCH("k_fill_dyn_if", k_fill_dyn_if, dim3(grid_n(b.N)), dim3(256), 0, s, b.s_winst, &P->n_sync, NONE, P, MODE_WBAR);
-    RD_LAUNCH("k_fill_dyn_if", k_fill_dyn_if, dim3(grid_n(b.N)), dim3(256), 0, s, b.inst_handle, b.inst_off + b.B, 0u, P, MODE_SYNC);
+    FillJobs f = {};
+    f.P = P;
+    f.add(b.priv, b.T, 0, 4, MODE_SYNC);
+    f.add(b.bk, b.B, 0, 4, MODE_SYNC);
+    f.add(b.priv_head, b.B, NONE, 4, MODE_SYNC);
+    f.add(b.sv_handle, b.sv_cap, 0, 4, MODE_SYNC);
+    f.add(b.wo_key, b.wo_cap, ~0ull, 8, MODE_WBAR);
+    f.add(b.wi_inst, b.wo_cap, NONE, 4, MODE_WBAR);
+    f.add(b.s_khandle, b.N, 0, 4, MODE_SYNC, &P->n_sync);
+    f.add(b.s_winst, b.N, NONE, 4, MODE_WBAR, &P->n_sync);
+    f.add(b.inst_handle, b.N, 0, 4, MODE_SYNC, b.inst_off + b.B);
+    fill_many(f, "k_fill_tables", s);
     RD_LAUNCH("k_interp", k_interp, dim3(1), dim3(IT), 0, s, b, rt_scan);
     RD_LAUNCH("k_know", k_know, dim3(grid_n(b.T)), dim3(256), 0, s, b);
 }

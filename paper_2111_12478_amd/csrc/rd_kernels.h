@@ -3,12 +3,27 @@
 #include "rd_internal.h"
 
 namespace rd {
-void fill_u32(u32 *p, u64 n, u32 v, hipStream_t s);
-void fill_u8(uint8_t *p, u64 n, uint8_t v, hipStream_t s);
-void fill_u32_dyn(u32 *p, const u32 *count, u32 v, u64 max_n, hipStream_t s);
 void scan_exclusive(u32 *data, u64 n, u32 *part, hipStream_t s);
+void scan_exclusive_multi(u32 *data, u64 n, u32 regions, u32 *part, hipStream_t s);
 
-void prep_init(const Bufs &b, hipStream_t s);
+// several fills in one launch
+constexpr u32 MAX_FILL_JOBS = 10;
+struct FillJob {
+    void *p;
+    const u32 *dyn_n;  // non-null: fill min(*dyn_n, n) entries (read on the device)
+    u64 n, v;
+    u32 esize;         // 1, 4 or 8 bytes
+    u32 mode_mask;     // non-zero: only when DevParams::mode has one of these bits
+};
+struct FillJobs {
+    FillJob j[MAX_FILL_JOBS];
+    const DevParams *P;
+    u32 count;
+    void add(void *p, u64 n, u64 v, u32 esize, u32 mode_mask = 0, const u32 *dyn_n = nullptr);
+};
+void fill_many(const FillJobs &jobs, const char *name, hipStream_t s);
+
+void prep_init(const Bufs &b, u32 *rt_scan, hipStream_t s);
 void prep_ingest(const Bufs &b, u64 *sync_mask, u64 *acc_mask, u64 *atom_mask, hipStream_t s);
 void prep_sync_lists(const Bufs &b, const u64 *sync_mask, const u64 *atom_mask, hipStream_t s);
 void prep_elements(const Bufs &b, const u64 *acc_mask, hipStream_t s);
@@ -18,10 +33,17 @@ void prep_validate_wbar(const Bufs &b, hipStream_t s);
 // knowledge vectors (releases, acquires, warp barriers)
 void interp_run(const Bufs &b, const u32 *rt_scan, hipStream_t s);
 
-// radix sort of the access elements by location key; returns nothing, sets the device-side
-// buffer choice through Bufs::sorted_buf (fixed by the number of passes)
+// radix sort of the access elements by location key; the sorted elements end in buffer
+// (passes % 2), passes = ceil(key_bits / 8) read on the device
 void sort_elements(const Bufs &b, hipStream_t s);
-void sort_pairs(const Bufs &b, hipStream_t s);
+// radix sort of the kept race pairs by (first, second), result in buffer 0; the count is *m_dev
+// (launches sized for max_m) or m_host
+void sort_pairs(const Bufs &b, const u32 *m_dev, u32 m_host, u64 max_m, hipStream_t s);
 
 void segcheck_run(const Bufs &b, const u32 *rt_scan, hipStream_t s);
+
+// batched form: merged trace from the members' events; each member's run of the merged report
+void batch_merge(BatchTrace *tr, const u32 *off, u32 n_traces, u32 N, u32 tpb_merged, uint4 *out, u32 *bad,
+                 hipStream_t s);
+void batch_pair_ranges(BatchTrace *tr, const u32 *off, u32 n_traces, const Bufs &b, hipStream_t s);
 }  // namespace rd

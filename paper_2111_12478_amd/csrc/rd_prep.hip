@@ -10,17 +10,6 @@ namespace rd {
 
 // ---------------------------------------------------------------- fills and scans
 
-__global__ void k_fill_u32(u32 *p, u64 n, u32 v) {
-    for (u64 i = (u64)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (u64)gridDim.x * blockDim.x) p[i] = v;
-}
-__global__ void k_fill_u8(uint8_t *p, u64 n, uint8_t v) {
-    for (u64 i = (u64)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (u64)gridDim.x * blockDim.x) p[i] = v;
-}
-// fill n = *count entries (count read on the device)
-__global__ void k_fill_u32_dyn(u32 *p, const u32 *count, u32 v) {
-    u32 n = *count;
-    for (u32 i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) p[i] = v;
-}
 
 static inline unsigned grid_for(u64 n, unsigned per = 256, unsigned cap = 4096) {
     u64 g = (n + per - 1) / per;
@@ -29,15 +18,34 @@ static inline unsigned grid_for(u64 n, unsigned per = 256, unsigned cap = 4096) 
     return (unsigned)g;
 }
 
-void fill_u32(u32 *p, u64 n, u32 v, hipStream_t s) {
-    if (n) RD_LAUNCH("k_fill_u32", k_fill_u32, dim3(grid_for(n)), dim3(256), 0, s, p, n, v);
+// Several fills in one launch: blockIdx.y picks the job.  A job with a mode mask runs only when the
+// trace's mode (DevParams::mode, set by k_plan) has one of its bits; a job with dyn_n fills
+// min(*dyn_n, n) entries.
+__global__ void k_fill_many(FillJobs L) {
+    const FillJob f = L.j[blockIdx.y];
+    if (f.mode_mask && !(L.P->mode & f.mode_mask)) return;
+    u64 n = f.n;
+    if (f.dyn_n && (u64)*f.dyn_n < n) n = *f.dyn_n;
+    const u64 step = (u64)gridDim.x * blockDim.x;
+    u64 i = (u64)blockIdx.x * blockDim.x + threadIdx.x;
+    if (f.esize == 1)
+        for (; i < n; i += step) ((uint8_t *)f.p)[i] = (uint8_t)f.v;
+    else if (f.esize == 4)
+        for (; i < n; i += step) ((u32 *)f.p)[i] = (u32)f.v;
+    else
+        for (; i < n; i += step) ((u64 *)f.p)[i] = f.v;
 }
-void fill_u8(uint8_t *p, u64 n, uint8_t v, hipStream_t s) {
-    if (n) RD_LAUNCH("k_fill_u8", k_fill_u8, dim3(grid_for(n)), dim3(256), 0, s, p, n, v);
+
+void fill_many(const FillJobs &jobs, const char *name, hipStream_t s) {
+    u64 mx = 1;
+    for (u32 k = 0; k < jobs.count; k++) mx = jobs.j[k].n > mx ? jobs.j[k].n : mx;
+    if (jobs.count) RD_LAUNCH(name, k_fill_many, dim3(grid_for(mx, 256, 1024), jobs.count), dim3(256), 0, s, jobs);
 }
-void fill_u32_dyn(u32 *p, const u32 *count, u32 v, u64 max_n, hipStream_t s) {
-    RD_LAUNCH("k_fill_u32_dyn", k_fill_u32_dyn, dim3(grid_for(max_n)), dim3(256), 0, s, p, count, v);
+
+void FillJobs::add(void *p, u64 n, u64 v, u32 esize, u32 mode_mask, const u32 *dyn_n) {
+    if (count < MAX_FILL_JOBS && n) j[count++] = FillJob{p, dyn_n, n, v, esize, mode_mask};
 }
+
 
 // Block-wide exclusive scan of one value per thread (256 threads).  Returns the exclusive prefix;
 // *total gets the block total.
@@ -106,9 +114,54 @@ __global__ __launch_bounds__(256) void k_scan_apply(u32 *data, u64 n, const u32 
     for (u32 k = 0; k < 16; k++) { u64 i = base + k; if (i < n) data[i] = run; run += v[k]; }
 }
 
+// Small arrays in one workgroup each: region blockIdx.x of `regions` consecutive arrays of n words,
+// n <= SCAN_SMALL; every thread scans a run of up to 16 consecutive words.
+constexpr u32 SCAN_SMALL = 1024 * 16;
+__global__ __launch_bounds__(1024) void k_scan_small(u32 *data, u32 n) {
+    __shared__ u32 wsum[16];
+    u32 *d = data + (u64)blockIdx.x * n;
+    const u32 per = (n + 1023) / 1024, lo = threadIdx.x * per, hi = lo + per < n ? lo + per : n;
+    const u32 lane = lane_id(), w = threadIdx.x >> 6;
+    u32 v[16], sum = 0;
+#pragma unroll
+    for (u32 k = 0; k < 16; k++) {
+        v[k] = lo + k < hi ? d[lo + k] : 0;
+        sum += v[k];
+    }
+    u32 x = sum;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        const u32 y = __shfl_up(x, o, 64);
+        if (lane >= (u32)o) x += y;
+    }
+    if (lane == 63) wsum[w] = x;
+    __syncthreads();
+    u32 run = x - sum;
+    for (u32 q = 0; q < w; q++) run += wsum[q];
+#pragma unroll
+    for (u32 k = 0; k < 16; k++) {
+        if (lo + k < hi) d[lo + k] = run;
+        run += v[k];
+    }
+}
+
+// Exclusive scans of `regions` consecutive arrays of n words each, in place.
+void scan_exclusive_multi(u32 *data, u64 n, u32 regions, u32 *part, hipStream_t s) {
+    if (!n || !regions) return;
+    if (n <= SCAN_SMALL) {
+        RD_LAUNCH("k_scan_small", k_scan_small, dim3(regions), dim3(1024), 0, s, data, (u32)n);
+        return;
+    }
+    for (u32 r = 0; r < regions; r++) scan_exclusive(data + (u64)r * n, n, part, s);
+}
+
 // Exclusive scan of data[0..n) in place; `part` needs ceil(n / 4096) words (<= 2^20).
 void scan_exclusive(u32 *data, u64 n, u32 *part, hipStream_t s) {
     if (!n) return;
+    if (n <= SCAN_SMALL) {
+        RD_LAUNCH("k_scan_small", k_scan_small, dim3(1), dim3(1024), 0, s, data, (u32)n);
+        return;
+    }
     u32 np = (u32)((n + SCAN_CHUNK - 1) / SCAN_CHUNK);
     RD_LAUNCH("k_scan_reduce", k_scan_reduce, dim3(np), dim3(256), 0, s, data, n, part);
     RD_LAUNCH("k_scan_top", k_scan_top, dim3(1), dim3(1024), 0, s, part, np);
@@ -117,7 +170,8 @@ void scan_exclusive(u32 *data, u64 n, u32 *part, hipStream_t s) {
 
 // ---------------------------------------------------------------- init
 
-__global__ void k_init_params(DevParams *p) {
+__global__ void k_init_params(DevParams *p, u32 *sort_tot) {
+    for (u32 i = threadIdx.x; i < MAX_SORT_PASSES * (SORT_ND + 1); i += blockDim.x) sort_tot[i] = 0;  // + tickets
     if (threadIdx.x == 0) {
         DevParams z = {};
         z.first_bad_record = NONE;
@@ -407,9 +461,15 @@ __global__ void k_bar_register(Bufs b) {
 
 // Access elements (location key, index, tid, category | phase), compacted in trace order.  Plain
 // reads and writes also record, per list entry, the first access that follows it.
+// Also counts the digits of every location-sort pass (one row of per-tile counts) and clears the
+// tile's look-back words of the first sort pass.
 __global__ __launch_bounds__(WG_THREADS) void k_elements(Bufs b, const u64 *acc_mask) {
     __shared__ u32 wbase[WAVES];
+    __shared__ u32 dcnt[ELEM_SORT_PASSES][SORT_ND];
     const u32 w = threadIdx.x >> 6, lane = lane_id();
+#pragma unroll
+    for (u32 q = 0; q < ELEM_SORT_PASSES; q++) dcnt[q][threadIdx.x] = 0;
+    b.sort_status[(u64)blockIdx.x * SORT_ND + threadIdx.x] = 0;
     const u64 word0 = (u64)blockIdx.x * (TILE / 64);
     u64 m[ITEMS];
     u32 pre[ITEMS];
@@ -417,6 +477,7 @@ __global__ __launch_bounds__(WG_THREADS) void k_elements(Bufs b, const u64 *acc_
     const DevParams *p = b.prm;
     const u32 gbase = p->gbase, sbase = p->sbase, g_span = p->g_span, s_span = p->s_span;
     const u32 mode = p->mode;
+    const u32 np = (p->key_bits + SORT_RB - 1) / SORT_RB;
     u32 *ekey = b.ekey[0], *eidx = b.eidx[0], *etid = b.etid[0], *einfo = b.einfo[0];
     const u64 base = (u64)blockIdx.x * TILE + (u64)w * ITEMS * 64;
 #pragma unroll 2
@@ -454,7 +515,11 @@ __global__ __launch_bounds__(WG_THREADS) void k_elements(Bufs b, const u64 *acc_
         eidx[o] = idx;
         etid[o] = t;
         einfo[o] = info_make(cat, ph);
+        for (u32 q = 0; q < np; q++) atomicAdd(&dcnt[q][(key >> (q * SORT_RB)) & (SORT_ND - 1)], 1u);
     }
+    __syncthreads();
+    u32 *row = b.sort_partial + (u64)blockIdx.x * ELEM_SORT_PASSES * SORT_ND;
+    for (u32 q = 0; q < np; q++) row[q * SORT_ND + threadIdx.x] = dcnt[q][threadIdx.x];
 }
 
 // One lane per program thread: releases/acquires (explicit, or atomics next to a fence with no
@@ -531,23 +596,25 @@ __global__ void k_merge_counts(Bufs b) {
 
 // ---------------------------------------------------------------- launchers
 
-void prep_init(const Bufs &b, hipStream_t s) {
-    RD_LAUNCH("k_init_params", k_init_params, dim3(1), dim3(64), 0, s, b.prm);
-    fill_u8(b.act, b.T, 0, s);
-    fill_u32(b.s_cnt, (u64)b.T + 1, 0, s);
-    fill_u32(b.s_fill, b.T, 0, s);
-    fill_u32(b.blk_maxbar, (u64)b.B + 1, 0, s);
-    fill_u32(b.n_active, b.B, 0, s);
-    fill_u32(b.tile_s, 3 * ((u64)b.n_tiles + 1), 0, s);
-    fill_u32(b.a_cnt, b.T, 0, s);
+void prep_init(const Bufs &b, u32 *rt_scan, hipStream_t s) {
+    RD_LAUNCH("k_init_params", k_init_params, dim3(1), dim3(256), 0, s, b.prm, b.sort_tot);
+    FillJobs f = {};
+    f.P = b.prm;
+    f.add(b.act, b.T, 0, 1);
+    f.add(b.s_cnt, (u64)b.T + 1, 0, 4);
+    f.add(b.s_fill, b.T, 0, 4);
+    f.add(b.blk_maxbar, (u64)b.B + 1, 0, 4);
+    f.add(b.n_active, b.B, 0, 4);
+    f.add(b.tile_s, 3 * ((u64)b.n_tiles + 1), 0, 4);
+    f.add(b.a_cnt, b.T, 0, 4);
+    f.add(rt_scan, (u64)b.T + 1, 0, 4);
+    fill_many(f, "k_fill_init", s);
 }
 
 // ingest + tile scans + plan
 void prep_ingest(const Bufs &b, u64 *sync_mask, u64 *acc_mask, u64 *atom_mask, hipStream_t s) {
     if (b.N) RD_LAUNCH("k_ingest", k_ingest, dim3(b.n_tiles), dim3(WG_THREADS), 0, s, b, sync_mask, acc_mask, atom_mask);
-    scan_exclusive(b.tile_s, (u64)b.n_tiles + 1, b.part, s);
-    scan_exclusive(b.tile_s + b.n_tiles + 1, (u64)b.n_tiles + 1, b.part, s);
-    scan_exclusive(b.tile_s + 2 * ((u64)b.n_tiles + 1), (u64)b.n_tiles + 1, b.part, s);
+    scan_exclusive_multi(b.tile_s, (u64)b.n_tiles + 1, 3, b.part, s);
     RD_LAUNCH("k_plan", k_plan, dim3(1), dim3(256), 0, s, b);
 }
 
@@ -559,8 +626,11 @@ void prep_sync_lists(const Bufs &b, const u64 *sync_mask, const u64 *atom_mask, 
     RD_LAUNCH("k_sync_scatter", k_sync_scatter, dim3(grid_for(b.N)), dim3(256), 0, s, b);
     RD_LAUNCH("k_thread_lists", k_thread_lists, dim3(grid_for(b.T, 64)), dim3(64), 0, s, b);
     scan_exclusive(b.blk_maxbar, (u64)b.B + 1, b.part, s);  // -> instance offsets (inst_off)
-    fill_u32_dyn(b.inst_cnt, b.inst_off + b.B, 0, b.N, s);
-    fill_u32_dyn(b.inst_last, b.inst_off + b.B, 0, b.N, s);
+    FillJobs f = {};
+    f.P = b.prm;
+    f.add(b.inst_cnt, b.N, 0, 4, 0, b.inst_off + b.B);
+    f.add(b.inst_last, b.N, 0, 4, 0, b.inst_off + b.B);
+    fill_many(f, "k_fill_inst", s);
     RD_LAUNCH("k_bar_register", k_bar_register, dim3(grid_for(b.T, 64)), dim3(64), 0, s, b);
 }
 
@@ -570,7 +640,6 @@ void prep_elements(const Bufs &b, const u64 *acc_mask, hipStream_t s) {
 
 // releases/acquires, knowledge columns (rt_scan gets T+1 words), block-barrier validation
 void prep_thread_sync(const Bufs &b, u32 *rt_scan, hipStream_t s) {
-    fill_u32(rt_scan, (u64)b.T + 1, 0, s);
     RD_LAUNCH("k_thread_sync", k_thread_sync, dim3(grid_for(b.T, 64)), dim3(64), 0, s, b, rt_scan);
     scan_exclusive(rt_scan, (u64)b.T + 1, b.part, s);
 }

@@ -1,68 +1,150 @@
-// rd_sort.hip -- stable LSD radix sort of u32 keys with up to three u32 payload arrays (gfx950).
+// rd_sort.hip -- stable LSD radix sort (8-bit digits) of u32 keys with one or three u32 payload
+// arrays (gfx950), one sweep kernel per pass.
 //
-// Each pass: (1) every tile of TILE keys writes its digit histogram, digit-major, (2) one exclusive
-// scan over the (digit, tile) matrix gives every (digit, tile) its output base, (3) every tile ranks
-// its keys stably -- wavefront ballots find the lanes that share a digit, per-wave running counts in
-// LDS order the steps, per-digit wave prefixes order the waves -- stages keys and payloads through
-// LDS in sorted order and writes them out as contiguous runs per digit.
-// Stability across passes keeps trace order inside a location, which the segment check relies on.
+// Digit totals come first: every tile writes one row of per-tile digit counts for all passes (the
+// location sort counts in k_elements, which produces the keys; the pair sort in k_pair_count), and
+// k_sort_reduce adds the rows into per-pass totals.  Each pass is then a single kernel: a workgroup
+// takes the next tile ticket from a counter (so every earlier tile is already being worked on),
+// ranks its keys stably -- wavefront ballots find the lanes that share a digit, per-wave running
+// counts in LDS order the steps, per-digit wave prefixes order the waves -- publishes its per-digit
+// counts and looks back over the earlier tiles' published counts for its output offsets (decoupled
+// look-back, four predecessor words per round).  Keys and payloads go through LDS in sorted order and
+// out as contiguous runs per digit.  The look-back words carry all the information exchanged between
+// workgroups (no other data is published through them), so they are relaxed device-scope atomics:
+// coherent across the XCDs without the L2 write-back / invalidate an acquire or release would add
+// to every access.  Every wait is bounded: a look-back that does not finish within its spin limit
+// sets ERR_SORT and goes on, so the kernel always ends.  Two arrays of look-back words alternate
+// between passes; each pass clears its tiles' words in the other array for the next pass.
+// Stability keeps trace order inside a location, which the segment check relies on.
 #include "rd_internal.h"
 #include "rd_kernels.h"
 
 namespace rd {
 
-template <int R>
-__global__ __launch_bounds__(WG_THREADS) void k_radix_hist(const u32 *keys, const u32 *n_dev, u32 n_host,
-                                                          u32 shift, const u32 *bits_dev, u32 *hist, u32 n_tiles) {
-    constexpr u32 ND = 1u << R;
-    __shared__ u32 h[ND];
-    const u32 n = n_dev ? *n_dev : n_host;
-    if (bits_dev && shift >= *bits_dev) return;  // pass not needed
-    for (u32 d = threadIdx.x; d < ND; d += WG_THREADS) h[d] = 0;
-    __syncthreads();
+constexpr u32 DMASK = SORT_ND - 1;
+constexpr u64 ST_AGG = 1ull << 62, ST_PRE = 2ull << 62, ST_FLAGS = 3ull << 62, ST_VAL = (1ull << 62) - 1;
+constexpr u32 SPIN_LIMIT = 1u << 20;
+
+static_assert(WG_THREADS == SORT_ND, "one digit per thread");
+
+// Pair sort digit counts: tile t writes row t ([pass][digit]) of the per-tile counts and clears its
+// look-back words of the first pass; workgroup 0 clears the totals (added up by the next kernel).
+// Pass p < half takes digit p of `second`, pass p >= half digit p - half of `first`.
+// The pair count m is *m_dev when m_dev is set (workgroups past the last tile only exit), else m_host.
+__global__ __launch_bounds__(WG_THREADS) void k_pair_count(const u32 *first, const u32 *second, const u32 *m_dev,
+                                                           u32 m_host, u32 half, u32 *partial, u64 *status0,
+                                                           u32 *tot) {
+    __shared__ u32 h[MAX_SORT_PASSES][SORT_ND];
+    const u32 np = 2 * half;
+    const u32 m = m_dev ? *m_dev : m_host;
+    if (blockIdx.x == 0)  // totals and the tile tickets that follow them
+        for (u32 q = threadIdx.x; q < MAX_SORT_PASSES * (SORT_ND + 1); q += WG_THREADS) tot[q] = 0;
     const u64 base = (u64)blockIdx.x * TILE;
-    for (u32 k = 0; k < ITEMS; k++) {
+    if (base >= m) return;
+#pragma unroll
+    for (u32 q = 0; q < MAX_SORT_PASSES; q++) h[q][threadIdx.x] = 0;
+    status0[(u64)blockIdx.x * SORT_ND + threadIdx.x] = 0;
+    __syncthreads();
+    u32 f[ITEMS], sc[ITEMS];
+#pragma unroll
+    for (int k = 0; k < ITEMS; k++) {
         const u64 i = base + (u64)k * WG_THREADS + threadIdx.x;
-        if (i < n) atomicAdd(&h[(keys[i] >> shift) & (ND - 1)], 1u);
+        f[k] = i < m ? first[i] : 0;
+        sc[k] = i < m ? second[i] : 0;
+    }
+#pragma unroll
+    for (int k = 0; k < ITEMS; k++) {
+        if (base + (u64)k * WG_THREADS + threadIdx.x >= m) continue;
+        for (u32 q = 0; q < np; q++) {
+            const u32 key = q < half ? sc[k] : f[k];
+            const u32 sh = SORT_RB * (q < half ? q : q - half);
+            atomicAdd(&h[q][(key >> sh) & DMASK], 1u);
+        }
     }
     __syncthreads();
-    for (u32 d = threadIdx.x; d < ND; d += WG_THREADS) hist[(u64)d * n_tiles + blockIdx.x] = h[d];
+    u32 *row = partial + (u64)blockIdx.x * MAX_SORT_PASSES * SORT_ND;
+    for (u32 q = 0; q < np; q++) row[q * SORT_ND + threadIdx.x] = h[q][threadIdx.x];
 }
 
-template <int R>
-struct ScatterLds {
-    u32 wcnt[WAVES][1u << R];  // per-wave counts -> tile-local start of (wave, digit)
-    u32 dg[1u << R];           // global output base minus tile-local start, per digit
+// Adds the rows of per-tile counts into the pass totals: workgroup (p, c) sums rows
+// [64c, 64c + 64) of pass p, one digit per thread.  Passes past the key width (bits_dev) are skipped.
+// The number of rows is n_rows, or ceil(*items_dev / TILE) when items_dev is set.
+__global__ __launch_bounds__(WG_THREADS) void k_sort_reduce(const u32 *partial, u32 row_passes, u32 n_rows,
+                                                            const u32 *items_dev, const u32 *bits_dev, u32 *tot) {
+    const u32 p = blockIdx.x, d = threadIdx.x;
+    if (bits_dev && p >= (*bits_dev + SORT_RB - 1) / SORT_RB) return;
+    if (items_dev) n_rows = (u32)(((u64)*items_dev + TILE - 1) / TILE);
+    const u32 r0 = blockIdx.y * 64, r1 = r0 + 64 < n_rows ? r0 + 64 : n_rows;
+    if (r0 >= r1) return;
+    const u64 stride = (u64)row_passes * SORT_ND;
+    const u32 *src = partial + (u64)p * SORT_ND + d;
+    u32 acc = 0, r = r0;
+    for (; r + 16 <= r1; r += 16) {
+        u32 v[16];
+#pragma unroll
+        for (int j = 0; j < 16; j++) v[j] = src[(u64)(r + j) * stride];
+#pragma unroll
+        for (int j = 0; j < 16; j++) acc += v[j];
+    }
+    for (; r < r1; r++) acc += src[(u64)r * stride];
+    if (acc) atomicAdd(&tot[p * SORT_ND + d], acc);
+}
+
+struct SweepLds {
+    u32 wcnt[WAVES][SORT_ND];  // per-wave digit counts -> tile-local start of (wave, digit)
+    u32 dg[SORT_ND];           // global output position minus tile-local position, per digit
     u32 stage[TILE];
-    u32 wtot[WAVES];
+    u32 wtot[2][WAVES];
+    u32 tile;
 };
 
-template <int R>
-__global__ __launch_bounds__(WG_THREADS) void k_radix_scatter(
-    const u32 *kin, const u32 *p0in, const u32 *p1in, const u32 *p2in, u32 *kout, u32 *p0out, u32 *p1out,
-    u32 *p2out, const u32 *n_dev, u32 n_host, u32 shift, const u32 *bits_dev, const u32 *hist, u32 n_tiles) {
-    constexpr u32 ND = 1u << R, MASK = ND - 1;
-    __shared__ ScatterLds<R> L;
-    const u32 n = n_dev ? *n_dev : n_host;
-    if (bits_dev && shift >= *bits_dev) return;
-    const u64 tile0 = (u64)blockIdx.x * TILE;
-    if (tile0 >= n) return;
-    const u32 w = threadIdx.x >> 6, lane = lane_id();
-    for (u32 d = threadIdx.x; d < ND; d += WG_THREADS)
-        for (u32 q = 0; q < WAVES; q++) L.wcnt[q][d] = 0;
+struct SweepArgs {
+    const u32 *kin, *pin[3];
+    u32 *kout, *pout[3];
+    const u32 *n_dev;
+    u32 n_host, shift, pass;
+    const u32 *bits_dev;  // non-null: skip the pass when shift >= *bits_dev
+    u64 *status_cur, *status_next;
+    const u32 *tot;       // digit totals of the pass ([pass][digit])
+    u32 *ctr, *err;
+};
+
+constexpr int LOOKBACK = 4;  // predecessor words read at once per digit
+
+template <int NP>
+__global__ __launch_bounds__(WG_THREADS) void k_sort_sweep(SweepArgs a) {
+    __shared__ SweepLds L;
+    if (a.bits_dev && a.shift >= *a.bits_dev) return;  // past the key width: the pass is not needed
+    const u32 n = a.n_dev ? *a.n_dev : a.n_host;
+    const u32 n_tiles = (u32)(((u64)n + TILE - 1) / TILE);
+    const u32 w = threadIdx.x >> 6, lane = lane_id(), dme = threadIdx.x;  // one digit per thread
+    if (threadIdx.x == 0) L.tile = atomicAdd(&a.ctr[a.pass], 1u);
+#pragma unroll
+    for (u32 q = 0; q < WAVES; q++) L.wcnt[q][dme] = 0;
     __syncthreads();
+    const u32 tile = L.tile;
+    if (tile >= n_tiles) return;  // no tile for this workgroup; no later tile waits on it
+    const u64 tile0 = (u64)tile * TILE;
     const u64 wbase = tile0 + (u64)w * ITEMS * 64;
-    u32 key[ITEMS], off[ITEMS];
-    // ---- rank: position of each key among the equal digits of its wave, in input order
+    const u32 shift = a.shift;
+    const u32 total = a.tot[a.pass * SORT_ND + dme];
+    u32 key[ITEMS], off[ITEMS], pay[NP][ITEMS];
 #pragma unroll
     for (int k = 0; k < ITEMS; k++) {
         const u64 i = wbase + (u64)k * 64 + lane;
         const bool valid = i < n;
-        key[k] = valid ? kin[i] : 0;
-        const u32 d = (key[k] >> shift) & MASK;
+        key[k] = valid ? a.kin[i] : 0;
+#pragma unroll
+        for (int q = 0; q < NP; q++) pay[q][k] = valid ? a.pin[q][i] : 0;
+    }
+    // rank: position of each key among the equal digits of its wave, in input order
+#pragma unroll
+    for (int k = 0; k < ITEMS; k++) {
+        const bool valid = wbase + (u64)k * 64 + lane < n;
+        const u32 d = (key[k] >> shift) & DMASK;
         u64 m = ballot(valid);
 #pragma unroll
-        for (int bit = 0; bit < R; bit++) {
+        for (int bit = 0; bit < (int)SORT_RB; bit++) {
             const u64 bb = ballot((d >> bit) & 1u);
             m &= ((d >> bit) & 1u) ? bb : ~bb;
         }
@@ -76,138 +158,171 @@ __global__ __launch_bounds__(WG_THREADS) void k_radix_scatter(
         off[k] = old + rank;
     }
     __syncthreads();
-    // ---- per digit: wave prefixes and tile totals; tile-local digit starts
-    constexpr u32 DPT = ND / WG_THREADS > 0 ? ND / WG_THREADS : 1;  // digits per thread
-    u32 tot[DPT];
-    u32 mysum = 0;
+    // digit dme: exclusive wave prefixes and the tile's count
+    u32 cnt = 0;
 #pragma unroll
-    for (u32 j = 0; j < DPT; j++) {
-        const u32 d = threadIdx.x * DPT + j;
-        u32 run = 0;
-        if (d < ND) {
-            for (u32 q = 0; q < WAVES; q++) { const u32 c = L.wcnt[q][d]; L.wcnt[q][d] = run; run += c; }
+    for (u32 q = 0; q < WAVES; q++) {
+        const u32 c = L.wcnt[q][dme];
+        L.wcnt[q][dme] = cnt;
+        cnt += c;
+    }
+    u64 *my = a.status_cur + (u64)tile * SORT_ND + dme;
+    __hip_atomic_store(my, (tile == 0 ? ST_PRE : ST_AGG) | (u64)cnt, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    // the next pass's look-back words of this tile start cleared
+    if (a.status_next) a.status_next[(u64)tile * SORT_ND + dme] = 0;
+    // exclusive scans over the digits: tile-local starts (cnt) and global digit bases (total)
+    u32 x = cnt, y = total;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        const u32 xs = __shfl_up(x, o, 64), ys = __shfl_up(y, o, 64);
+        if (lane >= (u32)o) { x += xs; y += ys; }
+    }
+    if (lane == 63) { L.wtot[0][w] = x; L.wtot[1][w] = y; }
+    // look back: digit dme's count in all earlier tiles, LOOKBACK predecessor words per round
+    u64 excl = 0;
+    if (tile > 0) {
+        int i = (int)tile - 1;
+        u32 spins = 0;
+        for (;;) {
+            u64 v[LOOKBACK];
+#pragma unroll
+            for (int j = 0; j < LOOKBACK; j++)
+                v[j] = i - j >= 0 ? __hip_atomic_load(a.status_cur + (u64)(i - j) * SORT_ND + dme, __ATOMIC_RELAXED,
+                                                      __HIP_MEMORY_SCOPE_AGENT)
+                                  : ST_PRE;  // before tile 0: nothing
+            bool done = false, stall = false;
+#pragma unroll
+            for (int j = 0; j < LOOKBACK; j++) {
+                if (done || stall) continue;
+                const u64 f = v[j] & ST_FLAGS;
+                if (f != ST_AGG && f != ST_PRE) { stall = true; continue; }
+                excl += v[j] & ST_VAL;
+                i--;
+                if (f == ST_PRE) done = true;
+            }
+            if (done) break;
+            if (stall) {
+                if (++spins > SPIN_LIMIT) {
+                    atomicOr(a.err, ERR_SORT);
+                    break;
+                }
+                __builtin_amdgcn_s_sleep(1);
+            }
         }
-        tot[j] = run;
-        mysum += run;
+        __hip_atomic_store(my, ST_PRE | (excl + cnt), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }
-    // exclusive scan of mysum over the 256 threads
-    u32 x = mysum;
-#pragma unroll
-    for (int dd = 1; dd < 64; dd <<= 1) {
-        const u32 y = __shfl_up(x, dd, 64);
-        if (lane >= (u32)dd) x += y;
-    }
-    if (lane == 63) L.wtot[w] = x;
     __syncthreads();
-    u32 pre = x - mysum;
-    for (u32 q = 0; q < w; q++) pre += L.wtot[q];
+    u32 pre = x - cnt, gb = y - total;
+    for (u32 q = 0; q < w; q++) { pre += L.wtot[0][q]; gb += L.wtot[1][q]; }
 #pragma unroll
-    for (u32 j = 0; j < DPT; j++) {
-        const u32 d = threadIdx.x * DPT + j;
-        if (d < ND) {
-            for (u32 q = 0; q < WAVES; q++) L.wcnt[q][d] += pre;
-            L.dg[d] = hist[(u64)d * n_tiles + blockIdx.x] - pre;
-        }
-        pre += tot[j];
-    }
+    for (u32 q = 0; q < WAVES; q++) L.wcnt[q][dme] += pre;
+    L.dg[dme] = gb + (u32)excl - pre;
     __syncthreads();
     const u32 cnt_tile = (u32)((n - tile0) < (u64)TILE ? (n - tile0) : (u64)TILE);
-    // ---- local sorted positions
-    u32 lpos[ITEMS];
+    // local sorted positions
 #pragma unroll
     for (int k = 0; k < ITEMS; k++) {
-        const u64 i = wbase + (u64)k * 64 + lane;
-        const u32 d = (key[k] >> shift) & MASK;
-        lpos[k] = i < n ? L.wcnt[w][d] + off[k] : NONE;
+        const bool valid = wbase + (u64)k * 64 + lane < n;
+        off[k] = valid ? L.wcnt[w][(key[k] >> shift) & DMASK] + off[k] : NONE;
     }
-    // ---- keys through LDS, then each payload array
-    u32 gpos[ITEMS];
+    // keys through LDS, then each payload array
 #pragma unroll
-    for (int k = 0; k < ITEMS; k++) if (lpos[k] != NONE) L.stage[lpos[k]] = key[k];
+    for (int k = 0; k < ITEMS; k++)
+        if (off[k] != NONE) L.stage[off[k]] = key[k];
     __syncthreads();
+    u32 gpos[ITEMS];
 #pragma unroll
     for (int r = 0; r < ITEMS; r++) {
         const u32 j = r * WG_THREADS + threadIdx.x;
         gpos[r] = NONE;
         if (j < cnt_tile) {
-            const u32 kk = L.stage[j], d = (kk >> shift) & MASK;
-            gpos[r] = L.dg[d] + j;
-            kout[gpos[r]] = kk;
+            const u32 kk = L.stage[j];
+            gpos[r] = L.dg[(kk >> shift) & DMASK] + j;
+            a.kout[gpos[r]] = kk;
         }
     }
-    const u32 *pin[3] = {p0in, p1in, p2in};
-    u32 *pout[3] = {p0out, p1out, p2out};
 #pragma unroll
-    for (int a = 0; a < 3; a++) {
-        if (!pin[a]) continue;
+    for (int q = 0; q < NP; q++) {
         __syncthreads();
 #pragma unroll
-        for (int k = 0; k < ITEMS; k++) {
-            const u64 i = wbase + (u64)k * 64 + lane;
-            if (lpos[k] != NONE) L.stage[lpos[k]] = pin[a][i];
-        }
+        for (int k = 0; k < ITEMS; k++)
+            if (off[k] != NONE) L.stage[off[k]] = pay[q][k];
         __syncthreads();
 #pragma unroll
-        for (int r = 0; r < ITEMS; r++) {
-            const u32 j = r * WG_THREADS + threadIdx.x;
-            if (gpos[r] != NONE) pout[a][gpos[r]] = L.stage[j];
-        }
+        for (int r = 0; r < ITEMS; r++)
+            if (gpos[r] != NONE) a.pout[q][gpos[r]] = L.stage[r * WG_THREADS + threadIdx.x];
     }
 }
 
-static const char *const kScatterName[2][4] = {
-    {"k_sort_scatter_p0", "k_sort_scatter_p1", "k_sort_scatter_p2", "k_sort_scatter_p3"},
-    {"k_pair_scatter", "k_pair_scatter", "k_pair_scatter", "k_pair_scatter"}};
+static const char *const kSweepName[ELEM_SORT_PASSES] = {"k_sort_sweep_p0", "k_sort_sweep_p1", "k_sort_sweep_p2",
+                                                         "k_sort_sweep_p3"};
 
-template <int R>
-static void radix_pass(const u32 *kin, const u32 *p0, const u32 *p1, const u32 *p2, u32 *kout, u32 *q0, u32 *q1,
-                       u32 *q2, const u32 *n_dev, u32 n_host, u32 shift, const u32 *bits_dev, u32 *hist, u32 *part,
-                       u32 n_tiles, hipStream_t s, int pairs, int pass) {
-    RD_LAUNCH(pairs ? "k_pair_hist" : "k_sort_hist", k_radix_hist<R>, dim3(n_tiles), dim3(WG_THREADS), 0, s, kin, n_dev, n_host, shift, bits_dev,
-                       hist, n_tiles);
-    scan_exclusive(hist, (u64)n_tiles << R, part, s);
-    RD_LAUNCH(kScatterName[pairs][pass & 3], k_radix_scatter<R>, dim3(n_tiles), dim3(WG_THREADS), 0, s, kin, p0, p1, p2, kout, q0, q1, q2,
-                       n_dev, n_host, shift, bits_dev, hist, n_tiles);
+static SweepArgs sweep_args(const Bufs &b, u32 pass, u32 n_passes, u32 shift, const u32 *n_dev, u32 n_host,
+                            const u32 *bits_dev) {
+    SweepArgs a = {};
+    a.n_dev = n_dev;
+    a.n_host = n_host;
+    a.shift = shift;
+    a.pass = pass;
+    a.bits_dev = bits_dev;
+    a.status_cur = b.sort_status + (pass & 1) * b.sort_status_stride;
+    a.status_next = pass + 1 < n_passes ? b.sort_status + ((pass + 1) & 1) * b.sort_status_stride : nullptr;
+    a.tot = b.sort_tot;
+    a.ctr = b.sort_ctr;
+    a.err = &b.prm->err;
+    return a;
 }
 
-// Elements: key = location, payloads = index, tid, info.  The number of passes follows the key width
-// found on the device; passes past it do nothing, so the result is in buffer (passes % 2).
+// Elements: key = location, payloads = index, tid, info.  The digit counts (per-tile rows), the
+// cleared look-back words of pass 0, the zeroed totals and tickets come from earlier kernels
+// (k_elements, k_init_params).  Passes past the key width found on the device do nothing, so the
+// result is in buffer (passes % 2), passes = ceil(key_bits / 8).
 void sort_elements(const Bufs &b, hipStream_t s) {
     if (!b.N) return;
     const u32 *n_dev = &b.prm->n_acc, *bits = &b.prm->key_bits;
-    const u32 R = b.radix_bits;
-    const u32 max_passes = (32 + R - 1) / R;
-    for (u32 pass = 0; pass < max_passes; pass++) {
+    RD_LAUNCH("k_sort_reduce", k_sort_reduce, dim3(ELEM_SORT_PASSES, (b.n_tiles + 63) / 64), dim3(WG_THREADS), 0, s,
+              b.sort_partial, ELEM_SORT_PASSES, b.n_tiles, (const u32 *)nullptr, bits, b.sort_tot);
+    for (u32 pass = 0; pass < ELEM_SORT_PASSES; pass++) {
         const u32 c = pass & 1, o = c ^ 1;
-        if (R == 11)
-            radix_pass<11>(b.ekey[c], b.eidx[c], b.etid[c], b.einfo[c], b.ekey[o], b.eidx[o], b.etid[o], b.einfo[o],
-                           n_dev, 0, pass * R, bits, b.hist, b.part, b.n_tiles, s, 0, pass);
-        else
-            radix_pass<8>(b.ekey[c], b.eidx[c], b.etid[c], b.einfo[c], b.ekey[o], b.eidx[o], b.etid[o], b.einfo[o],
-                          n_dev, 0, pass * R, bits, b.hist, b.part, b.n_tiles, s, 0, pass);
+        SweepArgs a = sweep_args(b, pass, ELEM_SORT_PASSES, pass * SORT_RB, n_dev, 0, bits);
+        a.kin = b.ekey[c];
+        a.pin[0] = b.eidx[c];
+        a.pin[1] = b.etid[c];
+        a.pin[2] = b.einfo[c];
+        a.kout = b.ekey[o];
+        a.pout[0] = b.eidx[o];
+        a.pout[1] = b.etid[o];
+        a.pout[2] = b.einfo[o];
+        RD_LAUNCH(kSweepName[pass], k_sort_sweep<3>, dim3(b.n_tiles), dim3(WG_THREADS), 0, s, a);
     }
 }
 
-// Pairs: sort by (first, second) -- LSD over second, then over first.  m is known on the host.
-u32 sort_pairs_host(const Bufs &b, u32 m, hipStream_t s) {
+// Pairs: sort by (first, second) -- LSD over second, then over first.  The pair count is *m_dev
+// (device-driven launches sized for max_m pairs) or m_host.  An even number of passes leaves the
+// result in buffer 0.
+void sort_pairs(const Bufs &b, const u32 *m_dev, u32 m_host, u64 max_m, hipStream_t s) {
     u32 bits = 0;
     while (bits < 32 && ((u64)1 << bits) < (u64)b.N) bits++;
-    const u32 R = 8, per_half = (bits + R - 1) / R;
-    const u32 n_tiles = (m + TILE - 1) / TILE;
+    const u32 half = (bits + SORT_RB - 1) / SORT_RB;
+    const u32 passes = 2 * half;
+    if (!max_m || !passes) return;
+    const u32 n_tiles = (u32)((max_m + TILE - 1) / TILE);
+    RD_LAUNCH("k_pair_count", k_pair_count, dim3(n_tiles), dim3(WG_THREADS), 0, s, b.pfirst[0], b.psecond[0], m_dev,
+              m_host, half, b.sort_partial, b.sort_status, b.sort_tot);
+    RD_LAUNCH("k_pair_reduce", k_sort_reduce, dim3(passes, (n_tiles + 63) / 64), dim3(WG_THREADS), 0, s,
+              b.sort_partial, MAX_SORT_PASSES, n_tiles, m_dev, (const u32 *)nullptr, b.sort_tot);
     u32 cur = 0;
-    for (u32 half = 0; half < 2; half++) {
-        for (u32 pass = 0; pass < per_half; pass++) {
-            const u32 o = cur ^ 1;
-            if (half == 0)
-                radix_pass<8>(b.psecond[cur], b.pfirst[cur], nullptr, nullptr, b.psecond[o], b.pfirst[o], nullptr,
-                              nullptr, nullptr, m, pass * R, nullptr, b.hist, b.part, n_tiles, s, 1, pass);
-            else
-                radix_pass<8>(b.pfirst[cur], b.psecond[cur], nullptr, nullptr, b.pfirst[o], b.psecond[o], nullptr,
-                              nullptr, nullptr, m, pass * R, nullptr, b.hist, b.part, n_tiles, s, 1, pass);
-            cur = o;
-        }
+    for (u32 pass = 0; pass < passes; pass++) {
+        const u32 o = cur ^ 1;
+        const bool lo = pass < half;
+        SweepArgs a = sweep_args(b, pass, passes, (lo ? pass : pass - half) * SORT_RB, m_dev, m_host, nullptr);
+        a.kin = lo ? b.psecond[cur] : b.pfirst[cur];
+        a.pin[0] = lo ? b.pfirst[cur] : b.psecond[cur];
+        a.kout = lo ? b.psecond[o] : b.pfirst[o];
+        a.pout[0] = lo ? b.pfirst[o] : b.psecond[o];
+        RD_LAUNCH("k_pair_sweep", k_sort_sweep<1>, dim3(n_tiles), dim3(WG_THREADS), 0, s, a);
+        cur = o;
     }
-    return cur;
 }
 
 }  // namespace rd

@@ -144,3 +144,26 @@ def test_validation_matches_oracle(rc, name, grid, events, status, bad):
     got = rc.check(grid, events)
     assert got.status == status, (name, got)
     assert got.bad_index == bad, (name, got)
+
+
+# ---------------------------------------------------------------- halo-exchange stencil traces
+
+@pytest.mark.parametrize("seed,shape", [(s, sh) for s in range(4) for sh in
+                                        [(2, 2, 8, 2, 3), (4, 4, 32, 3, 4), (3, 5, 16, 4, 5), (8, 8, 64, 5, 3)]])
+def test_stencil_traces(rc, seed, shape):
+    rb, cb, tpb, rows, sweeps = shape
+    cfg = tracegen.stencil_small(seed=seed, rb=rb, cb=cb, tpb=tpb, rows=rows, sweeps=sweeps, plant_rate=0.08)
+    grid, ev, st, plants = tracegen.generate_stencil(cfg)
+    _say(f"stencil seed {seed} shape {shape}: {len(ev)} events, {len(plants)} plants")
+    want = oracle.check(grid, ev)
+    got = rc.check(grid, ev)
+    assert got.status == want.status == 0, (got, want)
+    np.testing.assert_array_equal(got.pairs, want.pairs)
+
+
+def test_stencil_unplanted_is_race_free(rc):
+    cfg = tracegen.stencil_small(seed=9, rb=16, cb=16, tpb=64, rows=4, sweeps=4, plant_rate=0.0)
+    grid, ev, st, plants = tracegen.generate_stencil(cfg)
+    _say(f"unplanted stencil: {len(ev)} events")
+    got = rc.check(grid, ev)
+    assert got.status == 0 and len(got.pairs) == 0, got
