@@ -10,7 +10,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "librd.so")
-SOURCES = ["rd_prep.hip", "rd_sort.hip", "rd_interp.hip", "rd_segcheck.hip", "rd_batch.hip", "rd_host.hip",
+SOURCES = ["rd_prep.hip", "rd_sort.hip", "rd_interp.hip", "rd_engine.hip", "rd_segcheck.hip", "rd_batch.hip", "rd_host.hip",
            "rd_server.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [

@@ -1,0 +1,628 @@
+// rd_engine.hip -- parallel computation of the happens-before knowledge carried by releases,
+// acquires and block barriers (traces without warp barriers), on gfx950.
+//
+// The knowledge vectors are the sequential interpreter's (rd_interp.hip): Algorithm 1's H clock
+// with block floors KB[blk] and per-releaser columns KT[col], rule (iv) of Section 2.2 with the
+// scoped tags of a sync variable -- device scope, block scope of one block, every block.  Instead
+// of walking the sync events one by one, every operation's inputs are resolved up front:
+//   * a release on location X extends the chain (X, DEV), or the chains (X, its block) and
+//     (X, ALL); its input is the previous release of each chain.  Segmented scans over the
+//     release/acquire accesses in (location, trace) order -- the location sort's order -- find
+//     them; the per-block chains come from a stable re-sort of the block-scoped ones by block and
+//     then location;
+//   * an acquire reads the latest release of (X, DEV) and of (X, its block) or (X, ALL);
+//   * a thread's knowledge before an entry is its last acquire since its last barrier, else its
+//     block's knowledge after that barrier (one lane per thread walks its own list);
+//   * a completed block barrier joins the block's knowledge with its participants' acquires.
+// Every input precedes its operation in trace order, so the operations split greedily, in trace
+// order, into groups without a dependency inside a group.  One cooperative kernel evaluates the
+// groups in order: a group with many operations is spread over every workgroup, a run of small
+// groups (a lock handed from block to block) is evaluated by one workgroup in order; grid barriers
+// with bounded waits separate them.  An operation joins a few vectors of D words.
+#include "rd_internal.h"
+#include "rd_kernels.h"
+
+namespace rd {
+
+constexpr u32 BK_MARK = 0x80000000u;  // e_cur: the block's knowledge after (value & ~BK_MARK) barriers
+constexpr u32 ENG_WIDE = 16;          // groups with at least this many operations run on every workgroup
+constexpr u32 ENG_THREADS = 512;
+constexpr u32 ENG_SPIN = 1u << 22;
+constexpr u32 BL_MAX = 1u << 20;      // block-scoped release/acquire accesses re-sorted at most
+
+__device__ inline bool eng_active(const DevParams *P) {
+    return (P->mode & MODE_SYNC) && !(P->mode & MODE_WBAR) && P->first_bad_record == NONE &&
+           !(P->err & ERR_PHASE);
+}
+__device__ inline bool eng_on(const DevParams *P) { return eng_active(P) && !(P->eng & ENG_FALLBACK); }
+
+__device__ inline u32 sorted_buf(const DevParams *P) { return ((P->key_bits + SORT_RB - 1) / SORT_RB) & 1u; }
+
+// ---------------------------------------------------------------- release/acquire accesses
+
+// e_scan0[i] = 1 when sorted element i is a release/acquire access; i <= n_acc (scanned next).
+__global__ void k_eng_flag(Bufs b) {
+    const DevParams *P = b.prm;
+    if (!eng_active(P)) return;
+    const u32 n = P->n_acc, c = sorted_buf(P);
+    for (u32 i = blockIdx.x * blockDim.x + threadIdx.x; i <= n; i += gridDim.x * blockDim.x) {
+        u32 f = 0;
+        if (i < n) {
+            const u32 idx = b.eidx[c][i];
+            const u32 kind = b.ev[idx].z & 15u;
+            if (kind == 2u || kind == 6u || kind == 7u) {
+                const u32 j = list_search(b, b.etid[c][i], idx + 1);
+                if (j != NONE && b.s_pidx[j] == idx && (b.s_flags[j] & (SF_REL | SF_ACQ))) f = 1;
+            }
+        }
+        b.e_scan0[i] = f;
+    }
+}
+
+// ral_p / ral_key: the release/acquire accesses in (location, trace) order; fallback if too many.
+__global__ void k_eng_compact(Bufs b) {
+    DevParams *P = b.prm;
+    if (!eng_active(P)) return;
+    const u32 n = P->n_acc, c = sorted_buf(P), total = b.e_scan0[n];
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        P->n_ral = total > b.ecap ? 0u : total;
+        if (total > b.ecap) atomicOr(&P->eng, ENG_FALLBACK);
+    }
+    if (total > b.ecap) return;
+    for (u32 i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
+        const u32 r = b.e_scan0[i];
+        if (b.e_scan0[i + 1] == r) continue;
+        const u32 idx = b.eidx[c][i];
+        b.ral_p[r] = list_search(b, b.etid[c][i], idx + 1);
+        b.ral_key[r] = b.ekey[c][i];
+    }
+}
+
+// One workgroup scans a list in chunks of 1024 lanes for "the latest marked item before this one in
+// the same run" (segmented by run heads).  The carry holds the latest marked item of the run that
+// is still open at the end of the previous chunk.  Every lane of the workgroup calls it.
+struct SegLds {
+    u32 v[1024];
+    uint8_t h[1024];
+    u32 carry;
+};
+
+__device__ inline u32 seg_scan_chunk(SegLds &L, bool head, u32 val, u32 nin) {
+    const u32 i = threadIdx.x;
+    L.v[i] = val;
+    L.h[i] = head ? 1 : 0;
+    __syncthreads();
+    for (u32 off = 1; off < 1024; off <<= 1) {
+        u32 pv = NONE;
+        uint8_t ph = 0;
+        if (i >= off) { pv = L.v[i - off]; ph = L.h[i - off]; }
+        __syncthreads();
+        if (i >= off) {
+            // left segment (pv, ph) then this one: the left value survives unless this one has a
+            // head or a value of its own
+            if (!L.h[i] && L.v[i] == NONE) L.v[i] = pv;
+            L.h[i] |= ph;
+        }
+        __syncthreads();
+    }
+    u32 ex = NONE;
+    if (!head) {
+        if (i > 0) {
+            ex = L.v[i - 1];
+            if (ex == NONE && !L.h[i - 1]) ex = L.carry;  // the run started before this chunk
+        } else {
+            ex = L.carry;
+        }
+    }
+    __syncthreads();
+    if (i == 0) {
+        const u32 last = nin - 1;
+        const u32 vl = L.v[last];
+        L.carry = vl != NONE ? vl : (L.h[last] ? NONE : L.carry);
+    }
+    __syncthreads();
+    return ex;
+}
+
+// Chains (X, DEV) and (X, ALL) over ral (runs: equal locations).  Flags block-scoped items in
+// e_scan1 for the per-block chains.
+__global__ __launch_bounds__(1024) void k_eng_chains(Bufs b) {
+    DevParams *P = b.prm;
+    if (!eng_on(P)) return;
+    const u32 n = P->n_ral;
+    __shared__ SegLds Ld, La;
+    if (threadIdx.x == 0) { Ld.carry = NONE; La.carry = NONE; }
+    __syncthreads();
+    for (u32 c0 = 0; c0 < n; c0 += 1024) {
+        const u32 k = c0 + threadIdx.x, nin = n - c0 < 1024 ? n - c0 : 1024;
+        u32 p = NONE;
+        uint8_t f = 0, sc = 0;
+        bool head = true;
+        if (k < n) {
+            p = b.ral_p[k];
+            f = b.s_flags[p];
+            sc = b.s_scope[p];
+            head = k == 0 || b.ral_key[k - 1] != b.ral_key[k];
+        }
+        const bool acq = f & SF_ACQ;
+        const bool rel_dev = (f & SF_REL) && (sc & 3u) != 0, rel_blk = (f & SF_REL) && (sc & 3u) == 0;
+        const u32 ex_dev = seg_scan_chunk(Ld, head, rel_dev ? p : NONE, nin);
+        const u32 ex_all = seg_scan_chunk(La, head, rel_blk ? p : NONE, nin);
+        if (k < n) {
+            if (rel_dev) { b.e_prev0[p] = ex_dev; b.e_prev1[p] = NONE; }
+            if (rel_blk) { b.e_prev0[p] = NONE; b.e_prev1[p] = ex_all; }  // e_prev0: block chain, later
+            if (acq) {
+                // an entry that is both releases first: its own release counts for its chains
+                b.e_src0[p] = rel_dev ? p : ex_dev;
+                b.e_src1[p] = ((sc >> 2) & 3u) != 0 ? (rel_blk ? p : ex_all) : NONE;  // block scope: later
+            }
+            b.e_scan1[k] = (rel_blk || (acq && ((sc >> 2) & 3u) == 0)) ? 1u : 0u;
+        }
+    }
+    if (threadIdx.x == 0) b.e_scan1[n] = 0;
+}
+
+// Block-scoped items: keys (block) and values (ral index) into pfirst[0] / psecond[0].
+__global__ void k_eng_blk_items(Bufs b) {
+    DevParams *P = b.prm;
+    if (!eng_on(P)) return;
+    const u32 n = P->n_ral, total = b.e_scan1[n];
+    const bool over = total > BL_MAX || total > b.max_pairs;
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        P->n_bl = over ? 0u : total;  // the sorts that follow read n_bl items
+        if (over) atomicOr(&P->eng, ENG_FALLBACK);
+    }
+    if (over) return;
+    for (u32 k = blockIdx.x * blockDim.x + threadIdx.x; k < n; k += gridDim.x * blockDim.x) {
+        const u32 m = b.e_scan1[k];
+        if (b.e_scan1[k + 1] == m) continue;
+        b.pfirst[0][m] = block_of(b, b.ev[b.s_pidx[b.ral_p[k]]].y);
+        b.psecond[0][m] = k;
+    }
+}
+
+// After the sort by block (result in buffer c): keys become the location of each item.
+__global__ void k_eng_blk_rekey(Bufs b, u32 c) {
+    const DevParams *P = b.prm;
+    if (!eng_on(P)) return;
+    const u32 n = P->n_bl;
+    for (u32 m = blockIdx.x * blockDim.x + threadIdx.x; m < n; m += gridDim.x * blockDim.x) {
+        const u32 k = b.psecond[c][m];
+        b.pfirst[0][m] = b.ral_key[k];
+        b.psecond[0][m] = k;
+    }
+}
+
+// Per-block chains over the items in (location, block, trace) order -- the second sort's result is
+// in buffer ceil(key_bits / 8) % 2; runs: equal (location, block).
+__global__ __launch_bounds__(1024) void k_eng_blk_chains(Bufs b) {
+    DevParams *P = b.prm;
+    if (!eng_on(P)) return;
+    const u32 n = P->n_bl, c = sorted_buf(P);
+    __shared__ SegLds L;
+    if (threadIdx.x == 0) L.carry = NONE;
+    __syncthreads();
+    for (u32 c0 = 0; c0 < n; c0 += 1024) {
+        const u32 m = c0 + threadIdx.x, nin = n - c0 < 1024 ? n - c0 : 1024;
+        u32 p = NONE;
+        uint8_t f = 0, sc = 0;
+        bool head = true;
+        if (m < n) {
+            const u32 k = b.psecond[c][m];
+            p = b.ral_p[k];
+            f = b.s_flags[p];
+            sc = b.s_scope[p];
+            if (m > 0) {
+                const u32 kp = b.psecond[c][m - 1];
+                head = b.ral_key[kp] != b.ral_key[k] ||
+                       block_of(b, b.ev[b.s_pidx[b.ral_p[kp]]].y) != block_of(b, b.ev[b.s_pidx[p]].y);
+            }
+        }
+        const bool rel_blk = (f & SF_REL) && (sc & 3u) == 0;
+        const bool acq_blk = (f & SF_ACQ) && ((sc >> 2) & 3u) == 0;
+        const u32 ex = seg_scan_chunk(L, head, rel_blk ? p : NONE, nin);
+        if (m < n) {
+            if (rel_blk) b.e_prev0[p] = ex;
+            if (acq_blk) b.e_src1[p] = rel_blk ? p : ex;
+        }
+    }
+}
+
+// ---------------------------------------------------------------- engine state
+
+// Decides whether the parallel engine runs (sets ENG_PARALLEL), and its vector width.
+__global__ void k_eng_init(Bufs b, const u32 *rt_scan) {
+    DevParams *P = b.prm;
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    if (!eng_active(P)) return;
+    P->eng |= ENG_PARALLEL;
+    const u32 n_rt = rt_scan[b.T], D = b.B + n_rt;
+    P->n_rt = n_rt;
+    P->D = D;
+    const u64 cap = (u64)b.pool_words / D;
+    P->pool_cap = cap > 0xffffffffull ? 0xffffffffu : (u32)cap;
+}
+
+// ---------------------------------------------------------------- per-thread walk
+
+// One lane per program thread, over its sync list in program order: the knowledge an entry starts
+// from (e_cur), and for each barrier arrival the thread's latest acquire of the phase it ends
+// (e_src0 of the arrival); a barrier instance records its latest such acquire (trace index + 1)
+// in inst_coff.
+__global__ void k_eng_walk(Bufs b) {
+    const DevParams *P = b.prm;
+    if (!eng_on(P)) return;
+    for (u32 t = blockIdx.x * blockDim.x + threadIdx.x; t < b.T; t += gridDim.x * blockDim.x) {
+        const u32 lo = b.s_cnt[t], hi = b.s_cnt[t + 1];
+        if (lo == hi) continue;
+        const u32 blk = block_of(b, t);
+        u32 last = NONE;
+        for (u32 p = lo; p < hi; p++) {
+            const u32 kind = b.s_kind[p];
+            const uint8_t f = b.s_flags[p];
+            if (kind == 4u) {
+                b.e_src0[p] = last;
+                if (last != NONE) atomicMax(&b.inst_coff[b.inst_off[blk] + b.s_phase[p] - 1], b.s_pidx[last] + 1);
+                last = NONE;
+            } else if (f & (SF_REL | SF_ACQ)) {
+                b.e_cur[p] = last != NONE ? last : (BK_MARK | b.s_phase[p]);
+                if ((f & SF_ACQ) && (b.e_src0[p] != NONE || b.e_src1[p] != NONE)) last = p;
+            }
+        }
+    }
+}
+
+// ---------------------------------------------------------------- operations
+
+__device__ inline bool inst_complete(const Bufs &b, u32 blk, u32 slot) {
+    return b.inst_cnt[slot] == b.n_active[blk];
+}
+
+// Per trace-ordered sync entry q (and the padding up to N): is it an operation, and how many
+// vectors does it write.  e_scan0 / e_scan1 get 0/1 and the count (scanned next).
+__global__ void k_eng_mark(Bufs b) {
+    const DevParams *P = b.prm;
+    if (!eng_on(P)) return;
+    const u32 n_sync = P->n_sync;
+    for (u32 q = blockIdx.x * blockDim.x + threadIdx.x; q <= b.N; q += gridDim.x * blockDim.x) {
+        u32 nout = 0;
+        if (q < n_sync) {
+            const u32 p = b.s_inv[q];
+            const uint8_t f = b.s_flags[p];
+            const u32 kind = b.s_kind[p];
+            if (f & SF_REL) nout += (b.s_scope[p] & 3u) == 0 ? 2u : 1u;
+            if ((f & SF_ACQ) && (b.e_src0[p] != NONE || b.e_src1[p] != NONE)) nout += 1;
+            if (kind == 4u) {
+                const u32 idx = b.s_pidx[p], blk = block_of(b, b.ev[idx].y);
+                const u32 slot = b.inst_off[blk] + b.s_phase[p] - 1;
+                if (b.inst_last[slot] == idx && inst_complete(b, blk, slot) && b.inst_coff[slot] != 0) nout += 1;
+            }
+        }
+        b.e_scan0[q] = nout ? 1u : 0u;
+        b.e_scan1[q] = nout;
+    }
+}
+
+// Operation indices and vector handles (handle 0 is the empty knowledge).
+__global__ void k_eng_assign(Bufs b) {
+    DevParams *P = b.prm;
+    if (!eng_on(P)) return;
+    const u32 n_sync = P->n_sync, n_ops = b.e_scan0[n_sync], n_vec = b.e_scan1[n_sync];
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        P->n_ops = n_ops;
+        P->n_handles = n_vec + 1;
+        if (n_ops > b.ecap) atomicOr(&P->eng, ENG_FALLBACK);
+        else if ((u64)n_vec + 1 > P->pool_cap) atomicOr(&P->err, ERR_POOL);
+    }
+    if (n_ops > b.ecap || (u64)n_vec + 1 > P->pool_cap) return;
+    for (u32 q = blockIdx.x * blockDim.x + threadIdx.x; q < n_sync; q += gridDim.x * blockDim.x) {
+        const u32 o = b.e_scan0[q];
+        if (b.e_scan0[q + 1] == o) continue;
+        const u32 p = b.s_inv[q], h = 1 + b.e_scan1[q];
+        const uint8_t f = b.s_flags[p];
+        u32 used = 0;
+        b.op_p[o] = p;
+        b.e_op[p] = o;
+        if (f & SF_REL) {
+            b.e_relh[p] = h;
+            used = (b.s_scope[p] & 3u) == 0 ? 2u : 1u;
+        }
+        if ((f & SF_ACQ) && (b.e_src0[p] != NONE || b.e_src1[p] != NONE)) {
+            b.s_khandle[p] = h + used;
+            used++;
+        }
+        if (b.s_kind[p] == 4u) {
+            const u32 blk = block_of(b, b.ev[b.s_pidx[p]].y), slot = b.inst_off[blk] + b.s_phase[p] - 1;
+            b.inst_opo[slot] = o;
+            b.inst_handle[slot] = h + used;
+        }
+    }
+}
+
+// One lane per block: the block's knowledge after each of its barrier instances (handle and the
+// operation that wrote it), inheriting through instances that add nothing.
+__global__ void k_eng_bk(Bufs b) {
+    const DevParams *P = b.prm;
+    if (!eng_on(P) || P->n_ops > b.ecap) return;
+    for (u32 blk = blockIdx.x * blockDim.x + threadIdx.x; blk < b.B; blk += gridDim.x * blockDim.x) {
+        u32 h = 0, o = NONE;
+        for (u32 slot = b.inst_off[blk]; slot < b.inst_off[blk + 1]; slot++) {
+            if (b.inst_opo[slot] != NONE) { h = b.inst_handle[slot]; o = b.inst_opo[slot]; }
+            b.inst_handle[slot] = h;
+            b.inst_bko[slot] = o;
+        }
+    }
+}
+
+// The operation of the sync entry with trace index x (it exists).
+__device__ inline u32 op_at_index(const Bufs &b, u32 n_ops, u32 x) {
+    u32 lo = 0, hi = n_ops;
+    while (lo < hi) {
+        const u32 mid = (lo + hi) >> 1;
+        if (b.s_pidx[b.op_p[mid]] < x) lo = mid + 1;
+        else hi = mid;
+    }
+    return lo;
+}
+
+__device__ inline u32 dmax(u32 a, u32 c) { return a == NONE ? c : (c == NONE ? a : (a > c ? a : c)); }
+
+// The latest operation each operation reads from (NONE: none).
+__global__ void k_eng_deps(Bufs b) {
+    const DevParams *P = b.prm;
+    if (!eng_on(P) || P->n_ops > b.ecap) return;
+    const u32 n_ops = P->n_ops;
+    for (u32 o = blockIdx.x * blockDim.x + threadIdx.x; o < n_ops; o += gridDim.x * blockDim.x) {
+        const u32 p = b.op_p[o], idx = b.s_pidx[p], blk = block_of(b, b.ev[idx].y);
+        u32 d = NONE;
+        if (b.s_kind[p] == 4u) {
+            const u32 k = b.s_phase[p], slot = b.inst_off[blk] + k - 1;
+            if (k > 1) d = dmax(d, b.inst_bko[slot - 1]);
+            d = dmax(d, op_at_index(b, n_ops, b.inst_coff[slot] - 1));
+        } else {
+            const u32 cur = b.e_cur[p];
+            if (cur & BK_MARK) {
+                const u32 ph = cur & ~BK_MARK;
+                if (ph > 0) d = dmax(d, b.inst_bko[b.inst_off[blk] + ph - 1]);
+            } else {
+                d = dmax(d, b.e_op[cur]);
+            }
+            const uint8_t f = b.s_flags[p];
+            if (f & SF_REL) {
+                if (b.e_prev0[p] != NONE) d = dmax(d, b.e_op[b.e_prev0[p]]);
+                if (b.e_prev1[p] != NONE) d = dmax(d, b.e_op[b.e_prev1[p]]);
+            }
+            if (f & SF_ACQ) {
+                if (b.e_src0[p] != NONE && b.e_src0[p] != p) d = dmax(d, b.e_op[b.e_src0[p]]);
+                if (b.e_src1[p] != NONE && b.e_src1[p] != p) d = dmax(d, b.e_op[b.e_src1[p]]);
+            }
+        }
+        b.op_dep[o] = d;
+    }
+}
+
+// Greedy groups in trace order (one wavefront): a new group starts at the first operation that
+// reads from the current group.  grp[0..n_groups] are the group starts and the end.
+__global__ __launch_bounds__(64) void k_eng_groups(Bufs b) {
+    DevParams *P = b.prm;
+    if (!eng_on(P) || P->n_ops > b.ecap) return;
+    const u32 n = P->n_ops, lane = lane_id();
+    u32 start = 0, ng = 0;
+    if (lane == 0) b.grp[0] = 0;
+    for (u32 c0 = 0; c0 < n; c0 += 64) {
+        const u32 o = c0 + lane;
+        const u32 d = o < n ? b.op_dep[o] : NONE;
+        u32 from = 0;  // lanes below `from` are settled
+        for (;;) {
+            const bool cut = lane >= from && o < n && d != NONE && d >= start;
+            const u64 m = ballot(cut);
+            if (!m) break;
+            const u32 first = (u32)__builtin_ctzll(m);
+            start = c0 + first;
+            ng++;
+            if (lane == 0) b.grp[ng] = start;
+            from = first + 1;
+        }
+    }
+    if (lane == 0) {
+        b.grp[ng + 1] = n;
+        P->n_groups = n ? ng + 1 : 0;
+    }
+}
+
+// ---------------------------------------------------------------- evaluation
+
+__device__ inline const u32 *vecp(const Bufs &b, u32 D, u32 h) { return b.pool + (u64)h * D; }
+
+// Block barrier operation: the block's previous knowledge joined with every participant's latest
+// acquire of the phase the barrier ends.
+__device__ void eval_bar(const Bufs &b, u32 p, u32 D, u32 *lds_list, u32 *lds_n) {
+    const u32 idx = b.s_pidx[p], blk = block_of(b, b.ev[idx].y), k = b.s_phase[p];
+    const u32 slot = b.inst_off[blk] + k - 1;
+    if (threadIdx.x == 0) *lds_n = 0;
+    __syncthreads();
+    for (u32 u = threadIdx.x; u < b.tpb; u += ENG_THREADS) {
+        const u32 t = blk * b.tpb + u;
+        u32 lo = b.s_cnt[t], hi = b.s_cnt[t + 1];
+        // first entry whose phase reaches k: the thread's k-th barrier arrival (if it has one)
+        while (lo < hi) {
+            const u32 mid = (lo + hi) >> 1;
+            if (b.s_phase[mid] < k) lo = mid + 1;
+            else hi = mid;
+        }
+        if (lo < b.s_cnt[t + 1] && b.s_kind[lo] == 4u && b.s_phase[lo] == k) {
+            const u32 c = b.e_src0[lo];
+            if (c != NONE) lds_list[atomicAdd(lds_n, 1u)] = b.s_khandle[c];
+        }
+    }
+    __syncthreads();
+    const u32 nc = *lds_n;
+    u32 *out = b.pool + (u64)b.inst_handle[slot] * D;
+    const u32 *prev = vecp(b, D, k > 1 ? b.inst_handle[slot - 1] : 0u);
+    for (u32 i = threadIdx.x; i < D; i += ENG_THREADS) {
+        u32 v = prev[i];
+        for (u32 c = 0; c < nc; c++) v = max(v, vecp(b, D, lds_list[c])[i]);
+        out[i] = v;
+    }
+}
+
+// Release and / or acquire of one sync entry (release first).
+__device__ void eval_ra(const Bufs &b, const u32 *rt_scan, u32 p, u32 D) {
+    const u32 idx = b.s_pidx[p], t = b.ev[idx].y, blk = block_of(b, t);
+    const uint8_t f = b.s_flags[p], sc = b.s_scope[p];
+    const u32 cur = b.e_cur[p];
+    u32 hc;
+    if (cur & BK_MARK) {
+        const u32 ph = cur & ~BK_MARK;
+        hc = ph > 0 ? b.inst_handle[b.inst_off[blk] + ph - 1] : 0u;
+    } else {
+        hc = b.s_khandle[cur];
+    }
+    const u32 *vc = vecp(b, D, hc);
+    if (f & SF_REL) {
+        const u32 kb = blk, kbv = b.s_phase[p], kt = b.B + rt_scan[t], ktv = idx + 1;
+        const u32 h0 = b.e_relh[p];
+        const u32 *v0 = vecp(b, D, b.e_prev0[p] != NONE ? b.e_relh[b.e_prev0[p]] : 0u);
+        u32 *o0 = b.pool + (u64)h0 * D;
+        const bool two = (sc & 3u) == 0;
+        const u32 *v1 = vecp(b, D, two && b.e_prev1[p] != NONE ? b.e_relh[b.e_prev1[p]] + 1 : 0u);
+        u32 *o1 = b.pool + (u64)(h0 + 1) * D;
+        for (u32 i = threadIdx.x; i < D; i += ENG_THREADS) {
+            u32 base = vc[i];
+            if (i == kb) base = max(base, kbv);
+            if (i == kt) base = max(base, ktv);
+            o0[i] = max(base, v0[i]);
+            if (two) o1[i] = max(base, v1[i]);
+        }
+        __syncthreads();
+    }
+    const u32 ha = (f & SF_ACQ) ? b.s_khandle[p] : 0u;
+    if (ha) {
+        const u32 s0 = b.e_src0[p], s1 = b.e_src1[p];
+        const bool blk_acq = ((sc >> 2) & 3u) == 0;
+        const u32 *a0 = vecp(b, D, s0 != NONE ? b.e_relh[s0] : 0u);
+        const u32 *a1 = vecp(b, D, s1 != NONE ? b.e_relh[s1] + (blk_acq ? 0u : 1u) : 0u);
+        u32 *oa = b.pool + (u64)ha * D;
+        for (u32 i = threadIdx.x; i < D; i += ENG_THREADS) oa[i] = max(vc[i], max(a0[i], a1[i]));
+    }
+}
+
+__device__ inline void eval_op(const Bufs &b, const u32 *rt_scan, u32 o, u32 D, u32 *lds_list, u32 *lds_n) {
+    const u32 p = b.op_p[o];
+    if (b.s_kind[p] == 4u) eval_bar(b, p, D, lds_list, lds_n);
+    else eval_ra(b, rt_scan, p, D);
+    __syncthreads();
+}
+
+// All workgroups meet; writes before are visible to every workgroup after (bounded wait).
+__device__ inline void grid_barrier(DevParams *P, u32 round) {
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        __threadfence();
+        atomicAdd(&P->gbar, 1u);
+        const u32 target = round * gridDim.x;
+        u32 spins = 0;
+        while (__hip_atomic_load(&P->gbar, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
+            if (++spins > ENG_SPIN) { atomicOr(&P->err, ERR_ENGINE); break; }
+            __builtin_amdgcn_s_sleep(2);
+        }
+        __threadfence();
+    }
+    __syncthreads();
+}
+
+// Cooperative: every workgroup runs the same group loop.
+__global__ __launch_bounds__(ENG_THREADS) void k_eng_eval(Bufs b, const u32 *rt_scan) {
+    DevParams *P = b.prm;
+    if (!eng_on(P) || P->n_ops > b.ecap || (P->err & ERR_POOL)) return;
+    __shared__ u32 lds_list[1024];
+    __shared__ u32 lds_n;
+    const u32 D = P->D, ng = P->n_groups;
+    u32 round = 0;
+    if (blockIdx.x == 0)
+        for (u32 i = threadIdx.x; i < D; i += ENG_THREADS) b.pool[i] = 0;  // the empty knowledge
+    grid_barrier(P, ++round);
+    u32 g = 0;
+    while (g < ng) {
+        const u32 g0 = b.grp[g], g1 = b.grp[g + 1];
+        if (g1 - g0 >= ENG_WIDE) {
+            for (u32 o = g0 + blockIdx.x; o < g1; o += gridDim.x) eval_op(b, rt_scan, o, D, lds_list, &lds_n);
+            g++;
+        } else {
+            u32 g2 = g + 1;
+            while (g2 < ng && b.grp[g2 + 1] - b.grp[g2] < ENG_WIDE) g2++;
+            if (blockIdx.x == 0)
+                for (u32 o = g0; o < b.grp[g2]; o++) eval_op(b, rt_scan, o, D, lds_list, &lds_n);
+            g = g2;
+        }
+        grid_barrier(P, ++round);
+    }
+}
+
+static unsigned grid_over(u64 n, unsigned cap = 4096) {
+    u64 g = (n + 255) / 256;
+    return (unsigned)(g < 1 ? 1 : (g > cap ? cap : g));
+}
+
+static int eng_grid(int device) {
+    static int cus[64] = {0};
+    if (device < 0 || device >= 64) return 64;
+    if (!cus[device]) {
+        int v = 0;
+        if (hipDeviceGetAttribute(&v, hipDeviceAttributeMultiprocessorCount, device) != hipSuccess || v <= 0) v = 64;
+        cus[device] = v;
+    }
+    return cus[device];
+}
+
+hipError_t engine_run(const Bufs &b, const u32 *rt_scan, hipStream_t s) {
+    const u32 *gate = &b.prm->eng;
+    RD_LAUNCH("k_eng_init", k_eng_init, dim3(1), dim3(64), 0, s, b, rt_scan);
+    FillJobs f = {};
+    f.P = b.prm;
+    f.add(b.s_khandle, b.N, 0, 4, MODE_SYNC, &b.prm->n_sync, 1);
+    f.add(b.inst_coff, b.N, 0, 4, MODE_SYNC, b.inst_off + b.B, 1);
+    f.add(b.inst_opo, b.N, NONE, 4, MODE_SYNC, b.inst_off + b.B, 1);
+    fill_many(f, "k_fill_engine", s);
+    // chains of releases, over the release/acquire accesses in (location, trace) order
+    RD_LAUNCH("k_eng_flag", k_eng_flag, dim3(grid_over(b.N + 1)), dim3(256), 0, s, b);
+    scan_exclusive(b.e_scan0, (u64)b.N + 1, b.part, s, gate);
+    RD_LAUNCH("k_eng_compact", k_eng_compact, dim3(grid_over(b.N)), dim3(256), 0, s, b);
+    RD_LAUNCH("k_eng_chains", k_eng_chains, dim3(1), dim3(1024), 0, s, b);
+    scan_exclusive(b.e_scan1, (u64)b.ecap + 1, b.part, s, gate);
+    RD_LAUNCH("k_eng_blk_items", k_eng_blk_items, dim3(grid_over(b.ecap)), dim3(256), 0, s, b);
+    {
+        u32 bits = 0;
+        while (bits < 32 && ((u64)1 << bits) < (u64)b.B) bits++;
+        const u32 passes_blk = (bits + SORT_RB - 1) / SORT_RB;
+        const u64 max_bl = b.max_pairs < BL_MAX ? b.max_pairs : BL_MAX;
+        u32 *const k[2] = {b.pfirst[0], b.pfirst[1]};
+        u32 *const v[2] = {b.psecond[0], b.psecond[1]};
+        if (passes_blk) sort_kv(b, k, v, &b.prm->n_bl, max_bl, passes_blk, nullptr, "k_eng_sort", s);
+        RD_LAUNCH("k_eng_blk_rekey", k_eng_blk_rekey, dim3(grid_over(max_bl)), dim3(256), 0, s, b, passes_blk & 1u);
+        sort_kv(b, k, v, &b.prm->n_bl, max_bl, ELEM_SORT_PASSES, &b.prm->key_bits, "k_eng_sort", s);
+    }
+    RD_LAUNCH("k_eng_blk_chains", k_eng_blk_chains, dim3(1), dim3(1024), 0, s, b);
+    // operations and their inputs
+    RD_LAUNCH("k_eng_walk", k_eng_walk, dim3(grid_over(b.T)), dim3(256), 0, s, b);
+    RD_LAUNCH("k_eng_mark", k_eng_mark, dim3(grid_over(b.N + 1)), dim3(256), 0, s, b);
+    scan_exclusive(b.e_scan0, (u64)b.N + 1, b.part, s, gate);
+    scan_exclusive(b.e_scan1, (u64)b.N + 1, b.part, s, gate);
+    RD_LAUNCH("k_eng_assign", k_eng_assign, dim3(grid_over(b.N)), dim3(256), 0, s, b);
+    RD_LAUNCH("k_eng_bk", k_eng_bk, dim3(grid_over(b.B)), dim3(256), 0, s, b);
+    RD_LAUNCH("k_eng_deps", k_eng_deps, dim3(grid_over(b.ecap)), dim3(256), 0, s, b);
+    RD_LAUNCH("k_eng_groups", k_eng_groups, dim3(1), dim3(64), 0, s, b);
+    // evaluation: one cooperative launch
+    int dev = 0;
+    (void)hipGetDevice(&dev);
+    Bufs bb = b;
+    const u32 *rs = rt_scan;
+    void *args[] = {&bb, &rs};
+    prof_begin("k_eng_eval", s);
+    const hipError_t e =
+        hipLaunchCooperativeKernel((const void *)k_eng_eval, dim3(eng_grid(dev)), dim3(ENG_THREADS), args, 0, s);
+    prof_end(s);
+    return e;
+}
+
+}  // namespace rd

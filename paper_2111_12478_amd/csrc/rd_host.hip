@@ -43,7 +43,7 @@ static Plan make_plan(u64 n, u32 nb, u32 tpb, const rd_limits *lim, bool copy_ev
         const u64 e = (u64)n_tiles * ELEM_SORT_PASSES, q = (u64)P.pair_tiles * MAX_SORT_PASSES;
         P.partial_words = (e > q ? e : q) * SORT_ND;
     }
-    u64 scan_max = (u64)n_tiles + 1;
+    u64 scan_max = N1 + 1;  // the knowledge engine scans per sync entry
     if (T + 1 > scan_max) scan_max = T + 1;
     if (B + 1 > scan_max) scan_max = B + 1;
     P.part_words = (u32)((scan_max + 4095) / 4096 + 16);
@@ -75,6 +75,25 @@ static Plan make_plan(u64 n, u32 nb, u32 tpb, const rd_limits *lim, bool copy_ev
     L.off_s_know = take(4 * N1);
     L.off_s_khandle = take(4 * N1);
     L.off_s_winst = take(4 * N1);
+    L.ecap = (u32)(N1 / 4 > (1u << 20) ? N1 / 4 : (N1 < (1u << 20) ? N1 : (1u << 20)));
+    L.off_e_prev0 = take(4 * N1);
+    L.off_e_prev1 = take(4 * N1);
+    L.off_e_src0 = take(4 * N1);
+    L.off_e_src1 = take(4 * N1);
+    L.off_e_cur = take(4 * N1);
+    L.off_e_relh = take(4 * N1);
+    L.off_e_op = take(4 * N1);
+    L.off_e_scan0 = take(4 * (N1 + 1));
+    L.off_e_scan1 = take(4 * (N1 + 1));
+    L.off_inst_opo = take(4 * N1);
+    L.off_inst_bko = take(4 * N1);
+    L.off_inst_coff = take(4 * (N1 + 1));
+    L.off_clist = take(4ull * L.ecap);
+    L.off_ral_p = take(4ull * L.ecap);
+    L.off_ral_key = take(4ull * L.ecap);
+    L.off_op_p = take(4ull * L.ecap);
+    L.off_op_dep = take(4ull * L.ecap);
+    L.off_grp = take(4ull * (L.ecap + 1));
     L.off_blk_maxbar = take(4 * (B + 1));
     L.off_inst_cnt = take(4 * N1);
     L.off_inst_last = take(4 * N1);
@@ -142,6 +161,25 @@ static Bufs make_bufs(const Plan &P, char *ws, const void *events_dev, u64 n, u3
     b.s_know = (u32 *)(ws + L.off_s_know);
     b.s_khandle = (u32 *)(ws + L.off_s_khandle);
     b.s_winst = (u32 *)(ws + L.off_s_winst);
+    b.e_prev0 = (u32 *)(ws + L.off_e_prev0);
+    b.e_prev1 = (u32 *)(ws + L.off_e_prev1);
+    b.e_src0 = (u32 *)(ws + L.off_e_src0);
+    b.e_src1 = (u32 *)(ws + L.off_e_src1);
+    b.e_cur = (u32 *)(ws + L.off_e_cur);
+    b.e_relh = (u32 *)(ws + L.off_e_relh);
+    b.e_op = (u32 *)(ws + L.off_e_op);
+    b.e_scan0 = (u32 *)(ws + L.off_e_scan0);
+    b.e_scan1 = (u32 *)(ws + L.off_e_scan1);
+    b.inst_opo = (u32 *)(ws + L.off_inst_opo);
+    b.inst_bko = (u32 *)(ws + L.off_inst_bko);
+    b.inst_coff = (u32 *)(ws + L.off_inst_coff);
+    b.clist = (u32 *)(ws + L.off_clist);
+    b.ral_p = (u32 *)(ws + L.off_ral_p);
+    b.ral_key = (u32 *)(ws + L.off_ral_key);
+    b.op_p = (u32 *)(ws + L.off_op_p);
+    b.op_dep = (u32 *)(ws + L.off_op_dep);
+    b.grp = (u32 *)(ws + L.off_grp);
+    b.ecap = L.ecap;
     b.blk_maxbar = (u32 *)(ws + L.off_blk_maxbar);
     b.inst_off = b.blk_maxbar;  // scanned in place
     b.inst_cnt = (u32 *)(ws + L.off_inst_cnt);
@@ -254,9 +292,11 @@ hipError_t enqueue_check(const Bufs &b, u64 *masks, u32 *rt_scan, hipStream_t s)
     prep_sync_lists(b, sync_mask, atom_mask, s);
     prep_elements(b, acc_mask, s);
     prep_thread_sync(b, rt_scan, s);
+    sort_elements(b, s);
+    const hipError_t e = engine_run(b, rt_scan, s);
+    if (e != hipSuccess) return e;
     interp_run(b, rt_scan, s);
     prep_validate_wbar(b, s);
-    sort_elements(b, s);
     segcheck_run(b, rt_scan, s);
     return hipGetLastError();
 }
@@ -546,6 +586,7 @@ static rd_status plain_races(rd_ctx ctx, const Bufs &b, hipStream_t s, rd_pair *
     if (prm.first_bad_sync != NONE)
         return set_err(ctx, RD_ETRACE, prm.first_bad_sync, "event runs ahead of an unfinished barrier");
     if (prm.err & ERR_SORT) return set_err(ctx, RD_EHIP, UINT64_MAX, "location sort look-back did not finish");
+    if (prm.err & ERR_ENGINE) return set_err(ctx, RD_EHIP, UINT64_MAX, "knowledge engine barrier did not finish");
     if (prm.err & ERR_KEYSPAN)
         return set_err(ctx, RD_EINVAL, UINT64_MAX, "address span too large for a 32-bit location key");
     if (prm.err & ERR_POOL) return set_err(ctx, RD_ENOMEM, UINT64_MAX, "knowledge-vector pool exhausted (rd_limits.clock_bytes)");

@@ -46,6 +46,7 @@ enum : u32 {
     ERR_TABLE = 8,      // sync-variable or warp-barrier table overflowed
     ERR_PHASE = 16,     // a thread passed more than 2^30 barriers
     ERR_SORT = 32,      // a radix-sort look-back wait hit its spin limit
+    ERR_ENGINE = 64,    // a grid barrier of the knowledge engine hit its spin limit
 };
 
 // Radix sort: 8-bit digits, at most 8 passes per sort (32-bit keys, or two 32-bit halves of a pair
@@ -77,8 +78,20 @@ struct DevParams {
     u32 n_pairs;           // pairs found (may exceed the buffer)
     u32 n_pairs_kept;      // min(n_pairs, capacity)
     u32 n_winst;           // warp-barrier instances
-    u32 pad0;
+    u32 eng;               // ENG_* bits: which knowledge engine runs
+    u32 n_ral;             // release/acquire accesses (engine)
+    u32 n_bl;              // block-scoped ones among them
+    u32 n_ops;             // engine operations
+    u32 n_handles;         // knowledge vectors the engine writes (+1 for the empty one)
+    u32 n_groups;          // dependency-free groups of operations
+    u32 gbar;              // grid-barrier arrivals of the engine kernel
     unsigned long long n_chunks;  // queued slow-path chunks of the segment check (8-byte aligned)
+};
+
+// knowledge engine selection (DevParams::eng)
+enum : u32 {
+    ENG_PARALLEL = 1,  // the parallel engine computes the knowledge vectors
+    ENG_FALLBACK = 2,  // too large for its buffers: the sequential interpreter does
 };
 
 enum : u32 {
@@ -109,6 +122,22 @@ struct Bufs {
     u32 *s_know;            // [N] knowledge vector after the entry
     u32 *s_khandle;         // [N] knowledge vector created at the entry (interpreter output)
     u32 *s_winst;           // [N] warp-barrier instance of the entry
+    // parallel knowledge engine (per sync entry p)
+    u32 *e_prev0, *e_prev1; // release: previous release of its chains (entry ids)
+    u32 *e_src0, *e_src1;   // acquire: latest release of the chains it reads; barrier: contribution
+    u32 *e_cur;             // knowledge before the entry: acquire entry id, or BK_MARK | phase
+    u32 *e_relh;            // first knowledge vector a release writes
+    u32 *e_op;              // operation index of the entry
+    u32 *e_scan0, *e_scan1; // [N+1] scan scratch
+    u32 *inst_opo;          // [N] barrier instance -> operation index (or NONE)
+    u32 *inst_bko;          // [N] operation that wrote the block knowledge after the instance
+    u32 *inst_coff;         // [N+1] contributions per instance -> offsets
+    u32 *clist;             // [ECAP] contributing acquire entries, by instance
+    u32 *ral_p, *ral_key;   // [ECAP] release/acquire accesses in (location, trace) order
+    u32 *op_p;              // [ECAP] operation -> entry
+    u32 *op_dep;            // [ECAP] largest operation index it depends on (NONE: none)
+    u32 *grp;               // [ECAP+1] group starts
+    u32 ecap;
     u32 *blk_maxbar;        // [B]
     u32 *inst_off;          // [B+1]
     u32 *inst_cnt;          // [N]
@@ -189,13 +218,15 @@ struct Layout {
     u64 total;
     u64 off_params, off_ev, off_act, off_s_cnt, off_s_fill, off_tile_s, off_s_tidx, off_s_pidx,
         off_s_pq, off_s_inv, off_s_phase, off_s_kind, off_s_flags, off_s_scope, off_s_imin,
-        off_s_know, off_s_khandle, off_s_winst, off_blk_maxbar, off_inst_off, off_inst_cnt,
+        off_s_know, off_s_khandle, off_s_winst, off_e_prev0, off_e_prev1, off_e_src0, off_e_src1, off_e_cur,
+        off_e_relh, off_e_op, off_e_scan0, off_e_scan1, off_inst_opo, off_inst_bko, off_inst_coff, off_clist,
+        off_ral_p, off_ral_key, off_op_p, off_op_dep, off_grp, off_blk_maxbar, off_inst_off, off_inst_cnt,
         off_inst_last, off_inst_handle, off_n_active, off_rt, off_priv, off_priv_next, off_bk,
         off_priv_head, off_sv_key, off_sv_tag, off_sv_handle, off_wo_key, off_wo_val, off_wi_key,
         off_wi_occ, off_wi_inst, off_winst_mask, off_winst_arrived, off_winst_last, off_winst_nar,
         off_winst_arr, off_pool, off_ekey[2], off_eidx[2], off_etid[2], off_einfo[2], off_sort_status,
         off_sort_partial, off_sort_tot, off_part, off_tile_agg, off_pfirst[2], off_psecond[2];
-    u32 sv_cap, wo_cap, pool_cap_bytes_hi;
+    u32 sv_cap, wo_cap, pool_cap_bytes_hi, ecap;
     u64 pool_bytes, max_pairs;
 };
 

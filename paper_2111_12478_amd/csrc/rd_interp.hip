@@ -115,6 +115,7 @@ __global__ __launch_bounds__(IT) void k_interp(Bufs b, const u32 *rt_scan) {
     __shared__ Shared sh;
     DevParams *P = b.prm;
     if (!(P->mode & MODE_SYNC) || P->first_bad_record != NONE || (P->err & ERR_PHASE)) return;
+    if ((P->eng & ENG_PARALLEL) && !(P->eng & ENG_FALLBACK)) return;  // the parallel engine did it
     const u32 n_rt = rt_scan[b.T], D = b.B + n_rt, n_sync = P->n_sync;
     if (threadIdx.x == 0) {
         P->n_rt = n_rt;
@@ -352,15 +353,15 @@ void interp_run(const Bufs &b, const u32 *rt_scan, hipStream_t s) {
     // tables, only in traces with releases/acquires/warp barriers
     FillJobs f = {};
     f.P = P;
-    f.add(b.priv, b.T, 0, 4, MODE_SYNC);
-    f.add(b.bk, b.B, 0, 4, MODE_SYNC);
-    f.add(b.priv_head, b.B, NONE, 4, MODE_SYNC);
-    f.add(b.sv_handle, b.sv_cap, 0, 4, MODE_SYNC);
-    f.add(b.wo_key, b.wo_cap, ~0ull, 8, MODE_WBAR);
-    f.add(b.wi_inst, b.wo_cap, NONE, 4, MODE_WBAR);
-    f.add(b.s_khandle, b.N, 0, 4, MODE_SYNC, &P->n_sync);
-    f.add(b.s_winst, b.N, NONE, 4, MODE_WBAR, &P->n_sync);
-    f.add(b.inst_handle, b.N, 0, 4, MODE_SYNC, b.inst_off + b.B);
+    f.add(b.priv, b.T, 0, 4, MODE_SYNC, nullptr, 2);
+    f.add(b.bk, b.B, 0, 4, MODE_SYNC, nullptr, 2);
+    f.add(b.priv_head, b.B, NONE, 4, MODE_SYNC, nullptr, 2);
+    f.add(b.sv_handle, b.sv_cap, 0, 4, MODE_SYNC, nullptr, 2);
+    f.add(b.wo_key, b.wo_cap, ~0ull, 8, MODE_WBAR, nullptr, 2);
+    f.add(b.wi_inst, b.wo_cap, NONE, 4, MODE_WBAR, nullptr, 2);
+    f.add(b.s_khandle, b.N, 0, 4, MODE_SYNC, &P->n_sync, 2);
+    f.add(b.s_winst, b.N, NONE, 4, MODE_WBAR, &P->n_sync, 2);
+    f.add(b.inst_handle, b.N, 0, 4, MODE_SYNC, b.inst_off + b.B, 2);
     fill_many(f, "k_fill_tables", s);
     RD_LAUNCH("k_interp", k_interp, dim3(1), dim3(IT), 0, s, b, rt_scan);
     RD_LAUNCH("k_know", k_know, dim3(grid_n(b.T)), dim3(256), 0, s, b);

@@ -3,7 +3,7 @@
 #include "rd_internal.h"
 
 namespace rd {
-void scan_exclusive(u32 *data, u64 n, u32 *part, hipStream_t s);
+void scan_exclusive(u32 *data, u64 n, u32 *part, hipStream_t s, const u32 *gate = nullptr);
 void scan_exclusive_multi(u32 *data, u64 n, u32 regions, u32 *part, hipStream_t s);
 
 // several fills in one launch
@@ -14,12 +14,13 @@ struct FillJob {
     u64 n, v;
     u32 esize;         // 1, 4 or 8 bytes
     u32 mode_mask;     // non-zero: only when DevParams::mode has one of these bits
+    u32 eng;           // 1: only when the parallel knowledge engine is on; 2: only when it is not
 };
 struct FillJobs {
     FillJob j[MAX_FILL_JOBS];
     const DevParams *P;
     u32 count;
-    void add(void *p, u64 n, u64 v, u32 esize, u32 mode_mask = 0, const u32 *dyn_n = nullptr);
+    void add(void *p, u64 n, u64 v, u32 esize, u32 mode_mask = 0, const u32 *dyn_n = nullptr, u32 eng = 0);
 };
 void fill_many(const FillJobs &jobs, const char *name, hipStream_t s);
 
@@ -39,6 +40,11 @@ void sort_elements(const Bufs &b, hipStream_t s);
 // radix sort of the kept race pairs by (first, second), result in buffer 0; the count is *m_dev
 // (launches sized for max_m) or m_host
 void sort_pairs(const Bufs &b, const u32 *m_dev, u32 m_host, u64 max_m, hipStream_t s);
+// stable sort of (key, value) pairs by key (see rd_sort.hip)
+void sort_kv(const Bufs &b, u32 *const k[2], u32 *const v[2], const u32 *n_dev, u64 max_n, u32 passes,
+             const u32 *bits_dev, const char *name, hipStream_t s);
+// parallel knowledge engine (traces without warp barriers); sets DevParams::eng
+hipError_t engine_run(const Bufs &b, const u32 *rt_scan, hipStream_t s);
 
 void segcheck_run(const Bufs &b, const u32 *rt_scan, hipStream_t s);
 

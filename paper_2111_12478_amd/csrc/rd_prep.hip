@@ -24,6 +24,8 @@ static inline unsigned grid_for(u64 n, unsigned per = 256, unsigned cap = 4096) 
 __global__ void k_fill_many(FillJobs L) {
     const FillJob f = L.j[blockIdx.y];
     if (f.mode_mask && !(L.P->mode & f.mode_mask)) return;
+    if (f.eng == 1 && !((L.P->eng & ENG_PARALLEL) && !(L.P->eng & ENG_FALLBACK))) return;  // engine only
+    if (f.eng == 2 && ((L.P->eng & ENG_PARALLEL) && !(L.P->eng & ENG_FALLBACK))) return;   // interpreter only
     u64 n = f.n;
     if (f.dyn_n && (u64)*f.dyn_n < n) n = *f.dyn_n;
     const u64 step = (u64)gridDim.x * blockDim.x;
@@ -42,8 +44,8 @@ void fill_many(const FillJobs &jobs, const char *name, hipStream_t s) {
     if (jobs.count) RD_LAUNCH(name, k_fill_many, dim3(grid_for(mx, 256, 1024), jobs.count), dim3(256), 0, s, jobs);
 }
 
-void FillJobs::add(void *p, u64 n, u64 v, u32 esize, u32 mode_mask, const u32 *dyn_n) {
-    if (count < MAX_FILL_JOBS && n) j[count++] = FillJob{p, dyn_n, n, v, esize, mode_mask};
+void FillJobs::add(void *p, u64 n, u64 v, u32 esize, u32 mode_mask, const u32 *dyn_n, u32 eng) {
+    if (count < MAX_FILL_JOBS && n) j[count++] = FillJob{p, dyn_n, n, v, esize, mode_mask, eng};
 }
 
 
@@ -73,8 +75,14 @@ __device__ inline u32 block_exscan_256(u32 v, u32 *total, u32 *lds /* >= 8 words
 constexpr u32 SCAN_CHUNK = 4096;  // 256 threads x 16
 
 // partial sums of SCAN_CHUNK-sized chunks
-__global__ __launch_bounds__(256) void k_scan_reduce(const u32 *in, u64 n, u32 *part) {
+// gate (optional): the scan runs only while the knowledge engine is on (see eng_gate_open)
+__device__ inline bool eng_gate_open(const u32 *gate) {
+    return !gate || ((*gate & ENG_PARALLEL) && !(*gate & ENG_FALLBACK));
+}
+
+__global__ __launch_bounds__(256) void k_scan_reduce(const u32 *in, u64 n, u32 *part, const u32 *gate) {
     __shared__ u32 lds[8];
+    if (!eng_gate_open(gate)) return;
     u64 base = (u64)blockIdx.x * SCAN_CHUNK;
     u32 s = 0;
     for (u32 k = 0; k < 16; k++) {
@@ -86,8 +94,9 @@ __global__ __launch_bounds__(256) void k_scan_reduce(const u32 *in, u64 n, u32 *
     if (threadIdx.x == 0) part[blockIdx.x] = tot;
 }
 // exclusive scan of the partials in one workgroup of 1024 threads
-__global__ __launch_bounds__(1024) void k_scan_top(u32 *part, u32 np) {
+__global__ __launch_bounds__(1024) void k_scan_top(u32 *part, u32 np, const u32 *gate) {
     __shared__ u32 lds[1024];
+    if (!eng_gate_open(gate)) return;
     u32 per = (np + 1023) / 1024;
     u32 lo = threadIdx.x * per, hi = lo + per < np ? lo + per : np;
     u32 s = 0;
@@ -104,8 +113,9 @@ __global__ __launch_bounds__(1024) void k_scan_top(u32 *part, u32 np) {
     for (u32 i = lo; i < hi; i++) { u32 v = part[i]; part[i] = run; run += v; }
 }
 // in-place exclusive scan of each chunk plus its carry
-__global__ __launch_bounds__(256) void k_scan_apply(u32 *data, u64 n, const u32 *part) {
+__global__ __launch_bounds__(256) void k_scan_apply(u32 *data, u64 n, const u32 *part, const u32 *gate) {
     __shared__ u32 lds[8];
+    if (!eng_gate_open(gate)) return;
     u64 base = (u64)blockIdx.x * SCAN_CHUNK + (u64)threadIdx.x * 16;
     u32 v[16], s = 0;
     for (u32 k = 0; k < 16; k++) { u64 i = base + k; v[k] = i < n ? data[i] : 0; s += v[k]; }
@@ -117,8 +127,9 @@ __global__ __launch_bounds__(256) void k_scan_apply(u32 *data, u64 n, const u32 
 // Small arrays in one workgroup each: region blockIdx.x of `regions` consecutive arrays of n words,
 // n <= SCAN_SMALL; every thread scans a run of up to 16 consecutive words.
 constexpr u32 SCAN_SMALL = 1024 * 16;
-__global__ __launch_bounds__(1024) void k_scan_small(u32 *data, u32 n) {
+__global__ __launch_bounds__(1024) void k_scan_small(u32 *data, u32 n, const u32 *gate) {
     __shared__ u32 wsum[16];
+    if (!eng_gate_open(gate)) return;
     u32 *d = data + (u64)blockIdx.x * n;
     const u32 per = (n + 1023) / 1024, lo = threadIdx.x * per, hi = lo + per < n ? lo + per : n;
     const u32 lane = lane_id(), w = threadIdx.x >> 6;
@@ -149,23 +160,24 @@ __global__ __launch_bounds__(1024) void k_scan_small(u32 *data, u32 n) {
 void scan_exclusive_multi(u32 *data, u64 n, u32 regions, u32 *part, hipStream_t s) {
     if (!n || !regions) return;
     if (n <= SCAN_SMALL) {
-        RD_LAUNCH("k_scan_small", k_scan_small, dim3(regions), dim3(1024), 0, s, data, (u32)n);
+        RD_LAUNCH("k_scan_small", k_scan_small, dim3(regions), dim3(1024), 0, s, data, (u32)n, (const u32 *)nullptr);
         return;
     }
     for (u32 r = 0; r < regions; r++) scan_exclusive(data + (u64)r * n, n, part, s);
 }
 
-// Exclusive scan of data[0..n) in place; `part` needs ceil(n / 4096) words (<= 2^20).
-void scan_exclusive(u32 *data, u64 n, u32 *part, hipStream_t s) {
+// Exclusive scan of data[0..n) in place; `part` needs ceil(n / 4096) words (<= 2^20).  With a gate,
+// nothing happens unless the knowledge engine is on.
+void scan_exclusive(u32 *data, u64 n, u32 *part, hipStream_t s, const u32 *gate) {
     if (!n) return;
     if (n <= SCAN_SMALL) {
-        RD_LAUNCH("k_scan_small", k_scan_small, dim3(1), dim3(1024), 0, s, data, (u32)n);
+        RD_LAUNCH("k_scan_small", k_scan_small, dim3(1), dim3(1024), 0, s, data, (u32)n, gate);
         return;
     }
     u32 np = (u32)((n + SCAN_CHUNK - 1) / SCAN_CHUNK);
-    RD_LAUNCH("k_scan_reduce", k_scan_reduce, dim3(np), dim3(256), 0, s, data, n, part);
-    RD_LAUNCH("k_scan_top", k_scan_top, dim3(1), dim3(1024), 0, s, part, np);
-    RD_LAUNCH("k_scan_apply", k_scan_apply, dim3(np), dim3(256), 0, s, data, n, part);
+    RD_LAUNCH("k_scan_reduce", k_scan_reduce, dim3(np), dim3(256), 0, s, data, n, part, gate);
+    RD_LAUNCH("k_scan_top", k_scan_top, dim3(1), dim3(1024), 0, s, part, np, gate);
+    RD_LAUNCH("k_scan_apply", k_scan_apply, dim3(np), dim3(256), 0, s, data, n, part, gate);
 }
 
 // ---------------------------------------------------------------- init

@@ -31,11 +31,11 @@ static_assert(WG_THREADS == SORT_ND, "one digit per thread");
 // look-back words of the first pass; workgroup 0 clears the totals (added up by the next kernel).
 // Pass p < half takes digit p of `second`, pass p >= half digit p - half of `first`.
 // The pair count m is *m_dev when m_dev is set (workgroups past the last tile only exit), else m_host.
+// np passes in all (a single-key sort passes first == second and half == np).
 __global__ __launch_bounds__(WG_THREADS) void k_pair_count(const u32 *first, const u32 *second, const u32 *m_dev,
-                                                           u32 m_host, u32 half, u32 *partial, u64 *status0,
-                                                           u32 *tot) {
+                                                           u32 m_host, u32 half, u32 np, u32 *partial,
+                                                           u64 *status0, u32 *tot) {
     __shared__ u32 h[MAX_SORT_PASSES][SORT_ND];
-    const u32 np = 2 * half;
     const u32 m = m_dev ? *m_dev : m_host;
     if (blockIdx.x == 0)  // totals and the tile tickets that follow them
         for (u32 q = threadIdx.x; q < MAX_SORT_PASSES * (SORT_ND + 1); q += WG_THREADS) tot[q] = 0;
@@ -308,7 +308,7 @@ void sort_pairs(const Bufs &b, const u32 *m_dev, u32 m_host, u64 max_m, hipStrea
     if (!max_m || !passes) return;
     const u32 n_tiles = (u32)((max_m + TILE - 1) / TILE);
     RD_LAUNCH("k_pair_count", k_pair_count, dim3(n_tiles), dim3(WG_THREADS), 0, s, b.pfirst[0], b.psecond[0], m_dev,
-              m_host, half, b.sort_partial, b.sort_status, b.sort_tot);
+              m_host, half, passes, b.sort_partial, b.sort_status, b.sort_tot);
     RD_LAUNCH("k_pair_reduce", k_sort_reduce, dim3(passes, (n_tiles + 63) / 64), dim3(WG_THREADS), 0, s,
               b.sort_partial, MAX_SORT_PASSES, n_tiles, m_dev, (const u32 *)nullptr, b.sort_tot);
     u32 cur = 0;
@@ -322,6 +322,29 @@ void sort_pairs(const Bufs &b, const u32 *m_dev, u32 m_host, u64 max_m, hipStrea
         a.pout[0] = lo ? b.pfirst[o] : b.psecond[o];
         RD_LAUNCH("k_pair_sweep", k_sort_sweep<1>, dim3(n_tiles), dim3(WG_THREADS), 0, s, a);
         cur = o;
+    }
+}
+
+// Stable sort of (key, value) pairs in k[0], v[0] by key: n = *n_dev items (launches sized for max_n),
+// at most `passes` 8-bit passes; with bits_dev the passes past *bits_dev bits do nothing (the result
+// is then in buffer ceil(*bits_dev / 8) % 2, else in buffer passes % 2).  Uses the sort state and
+// the digit-count rows of the workspace, sized for max_n <= max(elements, max_pairs).
+void sort_kv(const Bufs &b, u32 *const k[2], u32 *const v[2], const u32 *n_dev, u64 max_n, u32 passes,
+             const u32 *bits_dev, const char *name, hipStream_t s) {
+    if (!max_n || !passes) return;
+    const u32 n_tiles = (u32)((max_n + TILE - 1) / TILE);
+    RD_LAUNCH(name, k_pair_count, dim3(n_tiles), dim3(WG_THREADS), 0, s, k[0], k[0], n_dev, 0u, passes, passes,
+              b.sort_partial, b.sort_status, b.sort_tot);
+    RD_LAUNCH(name, k_sort_reduce, dim3(passes, (n_tiles + 63) / 64), dim3(WG_THREADS), 0, s, b.sort_partial,
+              MAX_SORT_PASSES, n_tiles, n_dev, bits_dev, b.sort_tot);
+    for (u32 pass = 0; pass < passes; pass++) {
+        const u32 c = pass & 1, o = c ^ 1;
+        SweepArgs a = sweep_args(b, pass, passes, pass * SORT_RB, n_dev, 0, bits_dev);
+        a.kin = k[c];
+        a.pin[0] = v[c];
+        a.kout = k[o];
+        a.pout[0] = v[o];
+        RD_LAUNCH(name, k_sort_sweep<1>, dim3(n_tiles), dim3(WG_THREADS), 0, s, a);
     }
 }
 

@@ -167,3 +167,28 @@ def test_stencil_unplanted_is_race_free(rc):
     _say(f"unplanted stencil: {len(ev)} events")
     got = rc.check(grid, ev)
     assert got.status == 0 and len(got.pairs) == 0, got
+
+
+# ---------------------------------------------------------------- traces without warp barriers
+# (their knowledge vectors come from the parallel engine; warp barriers use the interpreter)
+
+@pytest.mark.parametrize("seed", list(range(5000, 5300)))
+def test_random_traces_no_warp_barriers(rc, seed):
+    grid, ev = tracegen.random_trace(seed, wbar=False)
+    want = oracle.check(grid, ev)
+    got = rc.check(grid, ev)
+    assert got.status == want.status, (seed, got, want)
+    if want.status == 0:
+        np.testing.assert_array_equal(got.pairs, want.pairs, err_msg=f"seed {seed}")
+    else:
+        assert got.bad_index == want.bad_index
+
+
+@pytest.mark.parametrize("seed", list(range(6000, 6040)))
+def test_random_traces_no_warp_barriers_larger(rc, seed):
+    grid, ev = tracegen.random_trace(seed, max_blocks=8, max_tpb=48, max_events=8000, wbar=False)
+    want = oracle.check(grid, ev)
+    got = rc.check(grid, ev)
+    assert got.status == want.status, (seed, got, want)
+    if want.status == 0:
+        np.testing.assert_array_equal(got.pairs, want.pairs, err_msg=f"seed {seed}")

@@ -19,8 +19,9 @@ from .format import make_meta, KIND, SCOPE
 _KINDS_ACCESS = ("R", "W", "A")
 
 
-def random_trace(seed: int, max_blocks: int = 3, max_tpb: int = 6, max_events: int = 400):
-    """Returns (grid, events) with grid = (n_blocks, tpb, warp_size) and events (N, 4) uint32."""
+def random_trace(seed: int, max_blocks: int = 3, max_tpb: int = 6, max_events: int = 400, wbar: bool = True):
+    """Returns (grid, events) with grid = (n_blocks, tpb, warp_size) and events (N, 4) uint32.
+    wbar=False: no warp barriers."""
     rng = np.random.default_rng(seed)
     nb = int(rng.integers(1, max_blocks + 1))
     tpb = int(rng.integers(1, max_tpb + 1))
@@ -52,7 +53,7 @@ def random_trace(seed: int, max_blocks: int = 3, max_tpb: int = 6, max_events: i
             # steps of this phase; a step is either per-thread ops or a warp-barrier step
             n_steps = int(rng.integers(1, 4))
             for _step in range(n_steps):
-                if rng.random() < p_kind[7] * 2 and ws > 1:
+                if wbar and rng.random() < p_kind[7] * 2 and ws > 1:
                     # warp barrier step: one warp, a mask of its existing lanes.  Every warp
                     # barrier with a given (warp, id) uses one mask, so the lanes' occurrence
                     # counts of that id stay aligned.
