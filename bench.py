@@ -468,7 +468,7 @@ def bench_stencil(args):
     if not args.no_cpu_baseline:
         # the oracle on a prefix of the trace (a prefix of a valid trace is valid), against the GPU
         import oracle
-        m = min(n, 24_000_000)
+        m = min(n, 72_000_000)  # two sweeps: the first plants and the reads that race with them
         sub = np.ascontiguousarray(ev[:m])
         g_sub = rc.check(grid, sub, limits)
         c0 = time.perf_counter()

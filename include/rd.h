@@ -152,6 +152,24 @@ rd_status rd_races_many(rd_ctx ctx, const rd_trace *traces, uint32_t n, rd_pair 
 
 rd_status rd_trace_free(rd_ctx ctx, rd_trace trace);
 
+/* Tuning of the location sort (the dominant kernel): built-in variants that differ in digit width
+ * (7, 8 or 9 bits, hence passes), wavefronts per workgroup and items per lane (hence tile size).
+ * Results never depend on the variant.  rd_set_tuning selects one for every later check on the
+ * context (default 0); rd_autotune times every variant on the given traces -- one trace alone, or a
+ * batch when batch_workspace is given -- with rd_check / rd_check_many (one warm-up and three timed
+ * runs each, HIP events on `stream`), selects the fastest, returns its index in *best and the mean
+ * milliseconds of each variant in ms[] (may be NULL; rd_tuning_count() entries), and leaves the
+ * traces checked with the chosen variant.  Synchronous. */
+typedef struct {
+    uint32_t radix_bits, waves_per_block, items_per_lane, reserved;
+} rd_tuning;
+rd_status rd_tuning_count(uint32_t *n);
+rd_status rd_tuning_get(uint32_t index, rd_tuning *out);
+rd_status rd_set_tuning(rd_ctx ctx, uint32_t index);
+rd_status rd_get_tuning(rd_ctx ctx, uint32_t *index);
+rd_status rd_autotune(rd_ctx ctx, const rd_trace *traces, uint32_t n, void *batch_workspace, uint64_t batch_bytes,
+                      hipStream_t stream, uint32_t *best, double *ms);
+
 /* Served form: a request loop with continuous batching under an HBM budget.  The caller hands over
  * one device arena (its size is the budget for the requests' events and the passes' workspaces,
  * reused from pass to pass; the server allocates no other device memory).  Requests queue in

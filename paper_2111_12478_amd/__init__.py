@@ -44,6 +44,11 @@ class rd_request_info(ctypes.Structure):
                 ("start_s", ctypes.c_double), ("done_s", ctypes.c_double)]
 
 
+class rd_tuning(ctypes.Structure):
+    _fields_ = [("radix_bits", ctypes.c_uint32), ("waves_per_block", ctypes.c_uint32),
+                ("items_per_lane", ctypes.c_uint32), ("reserved", ctypes.c_uint32)]
+
+
 class RdError(RuntimeError):
     def __init__(self, status, msg, event_index=None):
         super().__init__(f"{msg} (status {status})")
@@ -74,6 +79,11 @@ def load_library():
             "rd_batch_workspace_bytes": ([vp, P(vp), u32, P(rd_limits), P(u64)], i32),
             "rd_check_many": ([vp, P(vp), u32, vp, u64, P(rd_limits), vp], i32),
             "rd_races_many": ([vp, P(vp), u32, vp, u64, P(u64), P(i32)], i32),
+            "rd_tuning_count": ([P(u32)], i32),
+            "rd_tuning_get": ([u32, P(rd_tuning)], i32),
+            "rd_set_tuning": ([vp, u32], i32),
+            "rd_get_tuning": ([vp, P(u32)], i32),
+            "rd_autotune": ([vp, P(vp), u32, vp, u64, vp, P(u32), P(ctypes.c_double)], i32),
             "rd_server_open": ([vp, vp, P(rd_server_config), P(vp)], i32),
             "rd_server_submit": ([vp, P(rd_grid), vp, u64, P(u64)], i32),
             "rd_server_wait": ([vp, u64, vp, u64, P(rd_request_info)], i32),
@@ -176,6 +186,40 @@ def rd_races_many(ctx, traces, out_ptr, capacity):
                                       counts.ctypes.data_as(ctypes.POINTER(ctypes.c_uint64)),
                                       sts.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)))
     return st, counts[:n], sts[:n]
+
+
+def rd_tuning_count() -> int:
+    n = ctypes.c_uint32()
+    load_library().rd_tuning_count(ctypes.byref(n))
+    return n.value
+
+
+def rd_tuning_get(index) -> tuple[int, int, int]:
+    t = rd_tuning()
+    st = load_library().rd_tuning_get(index, ctypes.byref(t))
+    if st != RD_OK:
+        raise RdError(st, "rd_tuning_get failed")
+    return t.radix_bits, t.waves_per_block, t.items_per_lane
+
+
+def rd_set_tuning(ctx, index) -> int:
+    return load_library().rd_set_tuning(ctx, index)
+
+
+def rd_get_tuning(ctx) -> int:
+    v = ctypes.c_uint32()
+    load_library().rd_get_tuning(ctx, ctypes.byref(v))
+    return v.value
+
+
+def rd_autotune(ctx, traces, workspace_ptr, workspace_bytes, stream):
+    """Returns (status, best index, ms per variant)."""
+    k = rd_tuning_count()
+    best = ctypes.c_uint32()
+    ms = (ctypes.c_double * k)()
+    st = load_library().rd_autotune(ctx, _trace_array(traces), len(traces), workspace_ptr, workspace_bytes or 0,
+                                    stream, ctypes.byref(best), ms)
+    return st, best.value, list(ms)
 
 
 def rd_server_open(ctx, arena_ptr, device_bytes, max_batch=0, max_inflight=0) -> int:

@@ -27,7 +27,7 @@ namespace rd {
 constexpr u32 BK_MARK = 0x80000000u;  // e_cur: the block's knowledge after (value & ~BK_MARK) barriers
 constexpr u32 ENG_WIDE = 16;          // groups with at least this many operations run on every workgroup
 constexpr u32 ENG_THREADS = 512;
-constexpr u32 ENG_SPIN = 1u << 22;
+constexpr u32 ENG_SPIN = 1u << 19;  // ~1 s of polling: far above any legitimate wait
 constexpr u32 BL_MAX = 1u << 20;      // block-scoped release/acquire accesses re-sorted at most
 
 __device__ inline bool eng_active(const DevParams *P) {
@@ -36,6 +36,9 @@ __device__ inline bool eng_active(const DevParams *P) {
 }
 __device__ inline bool eng_on(const DevParams *P) { return eng_active(P) && !(P->eng & ENG_FALLBACK); }
 
+// buffer of the location sort's result (digits of the context's variant), and of a key-value
+// sort by location key (8-bit digits)
+__device__ inline u32 elem_buf(const Bufs &b) { return ((b.prm->key_bits + b.radix_bits - 1) / b.radix_bits) & 1u; }
 __device__ inline u32 sorted_buf(const DevParams *P) { return ((P->key_bits + SORT_RB - 1) / SORT_RB) & 1u; }
 
 // ---------------------------------------------------------------- release/acquire accesses
@@ -44,7 +47,7 @@ __device__ inline u32 sorted_buf(const DevParams *P) { return ((P->key_bits + SO
 __global__ void k_eng_flag(Bufs b) {
     const DevParams *P = b.prm;
     if (!eng_active(P)) return;
-    const u32 n = P->n_acc, c = sorted_buf(P);
+    const u32 n = P->n_acc, c = elem_buf(b);
     for (u32 i = blockIdx.x * blockDim.x + threadIdx.x; i <= n; i += gridDim.x * blockDim.x) {
         u32 f = 0;
         if (i < n) {
@@ -63,7 +66,7 @@ __global__ void k_eng_flag(Bufs b) {
 __global__ void k_eng_compact(Bufs b) {
     DevParams *P = b.prm;
     if (!eng_active(P)) return;
-    const u32 n = P->n_acc, c = sorted_buf(P), total = b.e_scan0[n];
+    const u32 n = P->n_acc, c = elem_buf(b), total = b.e_scan0[n];
     if (blockIdx.x == 0 && threadIdx.x == 0) {
         P->n_ral = total > b.ecap ? 0u : total;
         if (total > b.ecap) atomicOr(&P->eng, ENG_FALLBACK);
@@ -600,7 +603,7 @@ hipError_t engine_run(const Bufs &b, const u32 *rt_scan, hipStream_t s) {
         u32 *const v[2] = {b.psecond[0], b.psecond[1]};
         if (passes_blk) sort_kv(b, k, v, &b.prm->n_bl, max_bl, passes_blk, nullptr, "k_eng_sort", s);
         RD_LAUNCH("k_eng_blk_rekey", k_eng_blk_rekey, dim3(grid_over(max_bl)), dim3(256), 0, s, b, passes_blk & 1u);
-        sort_kv(b, k, v, &b.prm->n_bl, max_bl, ELEM_SORT_PASSES, &b.prm->key_bits, "k_eng_sort", s);
+        sort_kv(b, k, v, &b.prm->n_bl, max_bl, 32 / SORT_RB, &b.prm->key_bits, "k_eng_sort", s);
     }
     RD_LAUNCH("k_eng_blk_chains", k_eng_blk_chains, dim3(1), dim3(1024), 0, s, b);
     // operations and their inputs

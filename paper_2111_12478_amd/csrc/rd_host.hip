@@ -21,8 +21,8 @@ static u32 next_pow2(u64 x) {
 struct Plan {
     Layout L;
     u64 off_masks, off_rt_scan, off_tile_stats, off_a_cnt;
-    u32 n_tiles, T, B, radix_bits, pair_tiles, part_words, sort_tiles;
-    u64 partial_words;
+    u32 n_tiles, T, B, radix_bits, pair_tiles, part_words;
+    u64 partial_words, status_words;
 };
 
 static Plan make_plan(u64 n, u32 nb, u32 tpb, const rd_limits *lim, bool copy_events) {
@@ -37,11 +37,17 @@ static Plan make_plan(u64 n, u32 nb, u32 tpb, const rd_limits *lim, bool copy_ev
     const u64 N1 = n ? n : 1;
     P.n_tiles = n_tiles; P.T = (u32)T; P.B = nb; P.radix_bits = SORT_RB;
     P.pair_tiles = (u32)((max_pairs + TILE - 1) / TILE);
-    P.sort_tiles = n_tiles > P.pair_tiles ? n_tiles : P.pair_tiles;
-    if (!P.sort_tiles) P.sort_tiles = 1;
     {
-        const u64 e = (u64)n_tiles * ELEM_SORT_PASSES, q = (u64)P.pair_tiles * MAX_SORT_PASSES;
-        P.partial_words = (e > q ? e : q) * SORT_ND;
+        // look-back words per array: the largest tiles x digits over the sort variants and the pairs
+        u64 w = (u64)P.pair_tiles * SORT_ND;
+        for (u32 v = 0; v < N_SORT_VARIANTS; v++) {
+            const u64 ts = (u64)kSortVariants[v].waves * 64 * kSortVariants[v].items;
+            const u64 x = ((N1 + ts - 1) / ts) << kSortVariants[v].rb;
+            if (x > w) w = x;
+        }
+        P.status_words = w;
+        const u64 e = (u64)n_tiles * ELEM_MAX_PASSES, q = (u64)P.pair_tiles * MAX_SORT_PASSES;
+        P.partial_words = (e > q ? e : q) * SORT_NDS;
     }
     u64 scan_max = N1 + 1;  // the knowledge engine scans per sync entry
     if (T + 1 > scan_max) scan_max = T + 1;
@@ -124,9 +130,9 @@ static Plan make_plan(u64 n, u32 nb, u32 tpb, const rd_limits *lim, bool copy_ev
         L.off_etid[c] = take(4 * N1);
         L.off_einfo[c] = take(4 * N1);
     }
-    L.off_sort_status = take(2 * 8ull * SORT_ND * P.sort_tiles);
+    L.off_sort_status = take(2 * 8ull * P.status_words);
     L.off_sort_partial = take(4ull * P.partial_words);
-    L.off_sort_tot = take(4ull * (MAX_SORT_PASSES * SORT_ND + MAX_SORT_PASSES));
+    L.off_sort_tot = take(4ull * (MAX_SORT_PASSES * SORT_NDS + MAX_SORT_PASSES));
     L.off_part = take(4ull * P.part_words);
     L.off_tile_agg = take(agg_bytes() * ((u64)n_tiles + 1));
     for (int c = 0; c < 2; c++) {
@@ -216,10 +222,10 @@ static Bufs make_bufs(const Plan &P, char *ws, const void *events_dev, u64 n, u3
         b.psecond[c] = (u32 *)(ws + L.off_psecond[c]);
     }
     b.sort_status = (u64 *)(ws + L.off_sort_status);
-    b.sort_status_stride = (u64)SORT_ND * P.sort_tiles;
+    b.sort_status_stride = P.status_words;
     b.sort_partial = (u32 *)(ws + L.off_sort_partial);
     b.sort_tot = (u32 *)(ws + L.off_sort_tot);
-    b.sort_ctr = b.sort_tot + MAX_SORT_PASSES * SORT_ND;
+    b.sort_ctr = b.sort_tot + MAX_SORT_PASSES * SORT_NDS;
     b.part = (u32 *)(ws + L.off_part);
     b.tile_agg = ws + L.off_tile_agg;
     b.max_pairs = L.max_pairs;
@@ -230,6 +236,7 @@ static Bufs make_bufs(const Plan &P, char *ws, const void *events_dev, u64 n, u3
     b.ws = warp_size;
     b.n_tiles = P.n_tiles;
     b.radix_bits = P.radix_bits;
+    b.sort_variant = 0;
     u32 l = 0;
     while (((u64)1 << l) < tpb) l++;
     b.div_m = (u32)((((u64)1 << 32) * (((u64)1 << l) - tpb)) / tpb + 1);
@@ -309,6 +316,7 @@ using namespace rd;
 
 struct rd_ctx_s {
     int device;
+    u32 sort_variant = 0;  // location-sort variant (rd_set_tuning / rd_autotune)
     std::mutex mu;
     uint64_t last_index;
     std::string last_msg;
@@ -510,6 +518,8 @@ rd_status rd_check(rd_ctx ctx, rd_trace trace, hipStream_t stream) {
     trace->stream = stream;
     trace->batch.reset();
     trace->cached = 0;
+    trace->bufs.sort_variant = ctx->sort_variant;
+    trace->bufs.radix_bits = kSortVariants[ctx->sort_variant].rb;
     Profiler *saved = g_prof;
     g_prof = ctx->prof.filter.empty() ? nullptr : &ctx->prof;
     const hipError_t e = enqueue_check(trace->bufs, trace->masks, trace->rt_scan, stream);
@@ -626,8 +636,10 @@ static rd_status member_alone(rd_ctx ctx, rd_trace trace, rd_pair *out, uint64_t
         const Plan P = make_plan(trace->n, trace->grid.n_blocks, trace->grid.threads_per_block, &trace->lim, false);
         if (P.L.total > B.ws_bytes)
             return set_err(ctx, RD_ENOMEM, UINT64_MAX, "the batch workspace cannot hold this member's own check");
-        const Bufs b = make_bufs(P, B.ws, trace->bufs.ev, trace->n, trace->grid.n_blocks,
-                                 trace->grid.threads_per_block, ws);
+        Bufs b = make_bufs(P, B.ws, trace->bufs.ev, trace->n, trace->grid.n_blocks,
+                           trace->grid.threads_per_block, ws);
+        b.sort_variant = ctx->sort_variant;
+        b.radix_bits = kSortVariants[ctx->sort_variant].rb;
         Profiler *saved = g_prof;
         g_prof = ctx->prof.filter.empty() ? nullptr : &ctx->prof;
         const hipError_t e = enqueue_check(b, (u64 *)(B.ws + P.off_masks), (u32 *)(B.ws + P.off_rt_scan), B.stream);
@@ -713,6 +725,8 @@ rd_status rd_check_many(rd_ctx ctx, const rd_trace *traces, uint32_t n, void *wo
     B->ws = ws;
     B->ws_bytes = workspace_bytes;
     B->bufs = make_bufs(S.plan, ws, nullptr, S.N, (u32)S.B, S.tpb, S.ws);
+    B->bufs.sort_variant = ctx->sort_variant;
+    B->bufs.radix_bits = kSortVariants[ctx->sort_variant].rb;
     B->masks = (u64 *)(ws + S.plan.off_masks);
     B->rt_scan = (u32 *)(ws + S.plan.off_rt_scan);
     B->tr_dev = (BatchTrace *)(ws + S.table_off);
@@ -828,6 +842,80 @@ rd_status rd_races_many(rd_ctx ctx, const rd_trace *traces, uint32_t n, rd_pair 
         if (st != RD_OK && worst == RD_OK) worst = st;
     }
     return worst;
+}
+
+rd_status rd_tuning_count(uint32_t *n) {
+    if (!n) return RD_EINVAL;
+    *n = N_SORT_VARIANTS;
+    return RD_OK;
+}
+
+rd_status rd_tuning_get(uint32_t index, rd_tuning *out) {
+    if (!out || index >= N_SORT_VARIANTS) return RD_EINVAL;
+    out->radix_bits = kSortVariants[index].rb;
+    out->waves_per_block = kSortVariants[index].waves;
+    out->items_per_lane = kSortVariants[index].items;
+    out->reserved = 0;
+    return RD_OK;
+}
+
+rd_status rd_set_tuning(rd_ctx ctx, uint32_t index) {
+    if (!ctx || index >= N_SORT_VARIANTS) return RD_EINVAL;
+    ctx->sort_variant = index;
+    return RD_OK;
+}
+
+rd_status rd_get_tuning(rd_ctx ctx, uint32_t *index) {
+    if (!ctx || !index) return RD_EINVAL;
+    *index = ctx->sort_variant;
+    return RD_OK;
+}
+
+rd_status rd_autotune(rd_ctx ctx, const rd_trace *traces, uint32_t n, void *batch_workspace, uint64_t batch_bytes,
+                      hipStream_t stream, uint32_t *best, double *ms) {
+    if (!ctx || !n || !traces) return RD_EINVAL;
+    if (hipSetDevice(ctx->device) != hipSuccess) return set_err(ctx, RD_EHIP, UINT64_MAX, "hipSetDevice failed");
+    hipEvent_t e0, e1;
+    if (hipEventCreate(&e0) != hipSuccess) return RD_EHIP;
+    if (hipEventCreate(&e1) != hipSuccess) { (void)hipEventDestroy(e0); return RD_EHIP; }
+    const u32 saved = ctx->sort_variant;
+    u32 arg = saved;
+    double tbest = 1e300;
+    rd_status st = RD_OK;
+    for (u32 v = 0; v < N_SORT_VARIANTS && st == RD_OK; v++) {
+        ctx->sort_variant = v;
+        auto run = [&]() -> rd_status {
+            return batch_workspace ? rd_check_many(ctx, traces, n, batch_workspace, batch_bytes, nullptr, stream)
+                                   : rd_check(ctx, traces[0], stream);
+        };
+        st = run();  // warm-up
+        float total = 0.f;
+        for (int r = 0; r < 3 && st == RD_OK; r++) {
+            if (hipEventRecord(e0, stream) != hipSuccess) { st = RD_EHIP; break; }
+            st = run();
+            if (st != RD_OK) break;
+            float msr = 0.f;
+            if (hipEventRecord(e1, stream) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+                hipEventElapsedTime(&msr, e0, e1) != hipSuccess) {
+                st = RD_EHIP;
+                break;
+            }
+            total += msr;
+        }
+        if (st != RD_OK) break;
+        const double avg = total / 3.0;
+        if (ms) ms[v] = avg;
+        if (avg < tbest) { tbest = avg; arg = v; }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    ctx->sort_variant = st == RD_OK ? arg : saved;
+    if (best) *best = ctx->sort_variant;
+    // leave the traces checked with the chosen variant
+    if (st == RD_OK)
+        st = batch_workspace ? rd_check_many(ctx, traces, n, batch_workspace, batch_bytes, nullptr, stream)
+                             : rd_check(ctx, traces[0], stream);
+    return st;
 }
 
 rd_status rd_trace_free(rd_ctx ctx, rd_trace trace) {

@@ -49,14 +49,24 @@ enum : u32 {
     ERR_ENGINE = 64,    // a grid barrier of the knowledge engine hit its spin limit
 };
 
-// Radix sort: 8-bit digits, at most 8 passes per sort (32-bit keys, or two 32-bit halves of a pair
-// key of up to 2 x 32 bits).
+// Radix sort: the pair and key-value sorts use 8-bit digits (at most 8 passes: two 32-bit halves);
+// the location sort uses 7-, 8- or 9-bit digits (a tuning choice), at most ELEM_MAX_PASSES passes.
 constexpr u32 SORT_RB = 8, SORT_ND = 1u << SORT_RB;
+constexpr u32 SORT_NDS = 512;        // digit stride of the count rows and totals (9-bit digits)
 constexpr u32 MAX_SORT_PASSES = 8;
-constexpr u32 ELEM_SORT_PASSES = 4;  // 32-bit location keys
-// Digit counts: every tile writes one row of partial counts ([pass][digit], ELEM_SORT_PASSES rows
-// of digits for the location sort, MAX_SORT_PASSES for the pair sort); a reduction adds the rows
-// into per-pass totals.
+constexpr u32 ELEM_MAX_PASSES = 5;   // ceil(32 / 7)
+// Digit counts: every tile writes one row of partial counts ([pass][digit], ELEM_MAX_PASSES passes
+// for the location sort, MAX_SORT_PASSES for the pair sort); a reduction adds the rows into
+// per-pass totals.
+
+// Location-sort variants (the tuner picks one per context): digit bits, wavefronts per
+// workgroup, items per lane.
+struct SortVariant {
+    u32 rb, waves, items;
+};
+constexpr u32 N_SORT_VARIANTS = 8;
+constexpr SortVariant kSortVariants[N_SORT_VARIANTS] = {
+    {8, 4, 16}, {8, 8, 8}, {8, 8, 16}, {7, 4, 16}, {7, 8, 16}, {9, 8, 16}, {9, 8, 8}, {8, 4, 8}};
 
 // Device-side state of one check.  Zeroed (and the "min" fields set to NONE) by k_init.
 struct DevParams {
@@ -168,10 +178,10 @@ struct Bufs {
     // elements (ping-pong)
     u32 *ekey[2], *eidx[2], *etid[2], *einfo[2];
     // radix sort
-    u64 *sort_status;       // [2][status_tiles][SORT_ND] look-back words (flag << 62 | count)
-    u64 sort_status_stride; // status_tiles * SORT_ND
+    u64 *sort_status;       // [2][words] look-back words (flag << 62 | count), [tile][digits of the variant]
+    u64 sort_status_stride; // words per array
     u32 *sort_partial;      // [tiles][passes][SORT_ND] per-tile digit counts
-    u32 *sort_tot;          // [MAX_SORT_PASSES][SORT_ND] digit totals of each pass
+    u32 *sort_tot;          // [MAX_SORT_PASSES][SORT_NDS] digit totals of each pass
     u32 *sort_ctr;          // [MAX_SORT_PASSES] tile tickets of each pass
     u32 *part;              // [scan partials]
     // segment check
@@ -183,7 +193,8 @@ struct Bufs {
     u32 N, T, B, tpb, ws;
     u32 div_m, div_s1, div_s2;  // tid / tpb as a multiply-high and shifts
     u32 n_tiles;            // ceil(N / TILE)
-    u32 radix_bits;         // digit width of the location sort (SORT_RB)
+    u32 radix_bits;         // digit width of the location sort (its variant's)
+    u32 sort_variant;       // index into kSortVariants
     u32 sorted_buf;         // which element buffer holds the sorted elements (set by the host plan)
     u32 pair_buf;
 };

@@ -183,7 +183,7 @@ void scan_exclusive(u32 *data, u64 n, u32 *part, hipStream_t s, const u32 *gate)
 // ---------------------------------------------------------------- init
 
 __global__ void k_init_params(DevParams *p, u32 *sort_tot) {
-    for (u32 i = threadIdx.x; i < MAX_SORT_PASSES * (SORT_ND + 1); i += blockDim.x) sort_tot[i] = 0;  // + tickets
+    for (u32 i = threadIdx.x; i < MAX_SORT_PASSES * (SORT_NDS + 1); i += blockDim.x) sort_tot[i] = 0;  // + tickets
     if (threadIdx.x == 0) {
         DevParams z = {};
         z.first_bad_record = NONE;
@@ -473,15 +473,14 @@ __global__ void k_bar_register(Bufs b) {
 
 // Access elements (location key, index, tid, category | phase), compacted in trace order.  Plain
 // reads and writes also record, per list entry, the first access that follows it.
-// Also counts the digits of every location-sort pass (one row of per-tile counts) and clears the
-// tile's look-back words of the first sort pass.
+// Also counts the digits of every location-sort pass (one row of per-tile counts; digits of the
+// context's sort variant, radix_bits wide).
 __global__ __launch_bounds__(WG_THREADS) void k_elements(Bufs b, const u64 *acc_mask) {
     __shared__ u32 wbase[WAVES];
-    __shared__ u32 dcnt[ELEM_SORT_PASSES][SORT_ND];
+    __shared__ u32 dcnt[ELEM_MAX_PASSES][SORT_NDS];
     const u32 w = threadIdx.x >> 6, lane = lane_id();
-#pragma unroll
-    for (u32 q = 0; q < ELEM_SORT_PASSES; q++) dcnt[q][threadIdx.x] = 0;
-    b.sort_status[(u64)blockIdx.x * SORT_ND + threadIdx.x] = 0;
+    const u32 rb = b.radix_bits, nd = 1u << rb;
+    for (u32 x = threadIdx.x; x < ELEM_MAX_PASSES * SORT_NDS; x += WG_THREADS) (&dcnt[0][0])[x] = 0;
     const u64 word0 = (u64)blockIdx.x * (TILE / 64);
     u64 m[ITEMS];
     u32 pre[ITEMS];
@@ -489,7 +488,7 @@ __global__ __launch_bounds__(WG_THREADS) void k_elements(Bufs b, const u64 *acc_
     const DevParams *p = b.prm;
     const u32 gbase = p->gbase, sbase = p->sbase, g_span = p->g_span, s_span = p->s_span;
     const u32 mode = p->mode;
-    const u32 np = (p->key_bits + SORT_RB - 1) / SORT_RB;
+    const u32 np = (p->key_bits + rb - 1) / rb;
     u32 *ekey = b.ekey[0], *eidx = b.eidx[0], *etid = b.etid[0], *einfo = b.einfo[0];
     const u64 base = (u64)blockIdx.x * TILE + (u64)w * ITEMS * 64;
 #pragma unroll 2
@@ -527,11 +526,12 @@ __global__ __launch_bounds__(WG_THREADS) void k_elements(Bufs b, const u64 *acc_
         eidx[o] = idx;
         etid[o] = t;
         einfo[o] = info_make(cat, ph);
-        for (u32 q = 0; q < np; q++) atomicAdd(&dcnt[q][(key >> (q * SORT_RB)) & (SORT_ND - 1)], 1u);
+        for (u32 q = 0; q < np; q++) atomicAdd(&dcnt[q][(key >> (q * rb)) & (nd - 1)], 1u);
     }
     __syncthreads();
-    u32 *row = b.sort_partial + (u64)blockIdx.x * ELEM_SORT_PASSES * SORT_ND;
-    for (u32 q = 0; q < np; q++) row[q * SORT_ND + threadIdx.x] = dcnt[q][threadIdx.x];
+    u32 *row = b.sort_partial + (u64)blockIdx.x * ELEM_MAX_PASSES * SORT_NDS;
+    for (u32 q = 0; q < np; q++)
+        for (u32 d = threadIdx.x; d < nd; d += WG_THREADS) row[q * SORT_NDS + d] = dcnt[q][d];
 }
 
 // One lane per program thread: releases/acquires (explicit, or atomics next to a fence with no

@@ -21,24 +21,23 @@
 
 namespace rd {
 
-constexpr u32 DMASK = SORT_ND - 1;
 constexpr u64 ST_AGG = 1ull << 62, ST_PRE = 2ull << 62, ST_FLAGS = 3ull << 62, ST_VAL = (1ull << 62) - 1;
 constexpr u32 SPIN_LIMIT = 1u << 20;
 
-static_assert(WG_THREADS == SORT_ND, "one digit per thread");
+static_assert(WG_THREADS == SORT_ND, "one digit per thread in the 8-bit counting kernels");
 
-// Pair sort digit counts: tile t writes row t ([pass][digit]) of the per-tile counts and clears its
-// look-back words of the first pass; workgroup 0 clears the totals (added up by the next kernel).
-// Pass p < half takes digit p of `second`, pass p >= half digit p - half of `first`.
-// The pair count m is *m_dev when m_dev is set (workgroups past the last tile only exit), else m_host.
-// np passes in all (a single-key sort passes first == second and half == np).
+// Pair sort digit counts (8-bit digits): tile t writes row t ([pass][digit]) of the per-tile
+// counts and clears its look-back words of the first pass; workgroup 0 clears the totals (added up
+// by the next kernel).  Pass p < half takes digit p of `second`, pass p >= half digit p - half of
+// `first`; np passes in all (a single-key sort passes first == second and half == np).  The count
+// is *m_dev when m_dev is set (workgroups past the last tile only exit), else m_host.
 __global__ __launch_bounds__(WG_THREADS) void k_pair_count(const u32 *first, const u32 *second, const u32 *m_dev,
                                                            u32 m_host, u32 half, u32 np, u32 *partial,
                                                            u64 *status0, u32 *tot) {
     __shared__ u32 h[MAX_SORT_PASSES][SORT_ND];
     const u32 m = m_dev ? *m_dev : m_host;
     if (blockIdx.x == 0)  // totals and the tile tickets that follow them
-        for (u32 q = threadIdx.x; q < MAX_SORT_PASSES * (SORT_ND + 1); q += WG_THREADS) tot[q] = 0;
+        for (u32 q = threadIdx.x; q < MAX_SORT_PASSES * SORT_NDS + MAX_SORT_PASSES; q += WG_THREADS) tot[q] = 0;
     const u64 base = (u64)blockIdx.x * TILE;
     if (base >= m) return;
 #pragma unroll
@@ -58,43 +57,53 @@ __global__ __launch_bounds__(WG_THREADS) void k_pair_count(const u32 *first, con
         for (u32 q = 0; q < np; q++) {
             const u32 key = q < half ? sc[k] : f[k];
             const u32 sh = SORT_RB * (q < half ? q : q - half);
-            atomicAdd(&h[q][(key >> sh) & DMASK], 1u);
+            atomicAdd(&h[q][(key >> sh) & (SORT_ND - 1)], 1u);
         }
     }
     __syncthreads();
-    u32 *row = partial + (u64)blockIdx.x * MAX_SORT_PASSES * SORT_ND;
-    for (u32 q = 0; q < np; q++) row[q * SORT_ND + threadIdx.x] = h[q][threadIdx.x];
+    u32 *row = partial + (u64)blockIdx.x * MAX_SORT_PASSES * SORT_NDS;
+    for (u32 q = 0; q < np; q++) row[q * SORT_NDS + threadIdx.x] = h[q][threadIdx.x];
 }
 
 // Adds the rows of per-tile counts into the pass totals: workgroup (p, c) sums rows
-// [64c, 64c + 64) of pass p, one digit per thread.  Passes past the key width (bits_dev) are skipped.
-// The number of rows is n_rows, or ceil(*items_dev / TILE) when items_dev is set.
+// [64c, 64c + 64) of pass p for the 2^rb digits.  Passes past the key width (bits_dev) are skipped.
+// The number of rows is n_rows, or ceil(*items_dev / TILE) when items_dev is set.  With clear_words,
+// the workgroups also clear the first look-back array (clear_words words).
 __global__ __launch_bounds__(WG_THREADS) void k_sort_reduce(const u32 *partial, u32 row_passes, u32 n_rows,
-                                                            const u32 *items_dev, const u32 *bits_dev, u32 *tot) {
-    const u32 p = blockIdx.x, d = threadIdx.x;
-    if (bits_dev && p >= (*bits_dev + SORT_RB - 1) / SORT_RB) return;
+                                                            const u32 *items_dev, const u32 *bits_dev, u32 rb,
+                                                            u32 *tot, u64 *status0, u64 clear_words) {
+    if (status0) {
+        const u64 nthreads = (u64)gridDim.x * gridDim.y * WG_THREADS;
+        const u64 me = ((u64)blockIdx.y * gridDim.x + blockIdx.x) * WG_THREADS + threadIdx.x;
+        for (u64 i = me; i < clear_words; i += nthreads) status0[i] = 0;
+    }
+    const u32 p = blockIdx.x, nd = 1u << rb;
+    if (bits_dev && p >= (*bits_dev + rb - 1) / rb) return;
     if (items_dev) n_rows = (u32)(((u64)*items_dev + TILE - 1) / TILE);
     const u32 r0 = blockIdx.y * 64, r1 = r0 + 64 < n_rows ? r0 + 64 : n_rows;
     if (r0 >= r1) return;
-    const u64 stride = (u64)row_passes * SORT_ND;
-    const u32 *src = partial + (u64)p * SORT_ND + d;
-    u32 acc = 0, r = r0;
-    for (; r + 16 <= r1; r += 16) {
-        u32 v[16];
+    const u64 stride = (u64)row_passes * SORT_NDS;
+    for (u32 d = threadIdx.x; d < nd; d += WG_THREADS) {
+        const u32 *src = partial + (u64)p * SORT_NDS + d;
+        u32 acc = 0, r = r0;
+        for (; r + 16 <= r1; r += 16) {
+            u32 v[16];
 #pragma unroll
-        for (int j = 0; j < 16; j++) v[j] = src[(u64)(r + j) * stride];
+            for (int j = 0; j < 16; j++) v[j] = src[(u64)(r + j) * stride];
 #pragma unroll
-        for (int j = 0; j < 16; j++) acc += v[j];
+            for (int j = 0; j < 16; j++) acc += v[j];
+        }
+        for (; r < r1; r++) acc += src[(u64)r * stride];
+        if (acc) atomicAdd(&tot[p * SORT_NDS + d], acc);
     }
-    for (; r < r1; r++) acc += src[(u64)r * stride];
-    if (acc) atomicAdd(&tot[p * SORT_ND + d], acc);
 }
 
+template <int RB, int NW, int NI>
 struct SweepLds {
-    u32 wcnt[WAVES][SORT_ND];  // per-wave digit counts -> tile-local start of (wave, digit)
-    u32 dg[SORT_ND];           // global output position minus tile-local position, per digit
-    u32 stage[TILE];
-    u32 wtot[2][WAVES];
+    u32 wcnt[NW][1 << RB];  // per-wave digit counts -> tile-local start of (wave, digit)
+    u32 dg[1 << RB];        // global output position minus tile-local position, per digit
+    u32 stage[NW * 64 * NI];
+    u32 wtot[2][NW];
     u32 tile;
 };
 
@@ -105,32 +114,39 @@ struct SweepArgs {
     u32 n_host, shift, pass;
     const u32 *bits_dev;  // non-null: skip the pass when shift >= *bits_dev
     u64 *status_cur, *status_next;
-    const u32 *tot;       // digit totals of the pass ([pass][digit])
+    const u32 *tot;       // digit totals of the pass ([pass][SORT_NDS])
     u32 *ctr, *err;
 };
 
 constexpr int LOOKBACK = 4;  // predecessor words read at once per digit
 
-template <int NP>
-__global__ __launch_bounds__(WG_THREADS) void k_sort_sweep(SweepArgs a) {
-    __shared__ SweepLds L;
+// One pass: 2^RB digits, NW wavefronts per workgroup, NI items per lane (tile NW * 64 * NI).
+// Look-back words of a tile: 2^RB, consecutive.
+template <int NP, int RB, int NW, int NI>
+__global__ __launch_bounds__(NW * 64) void k_sort_sweep(SweepArgs a) {
+    constexpr u32 ND = 1u << RB, DM = ND - 1, THREADS = NW * 64, TS = THREADS * NI;
+    static_assert(ND <= THREADS, "one digit per thread");
+    __shared__ SweepLds<RB, NW, NI> L;
     if (a.bits_dev && a.shift >= *a.bits_dev) return;  // past the key width: the pass is not needed
     const u32 n = a.n_dev ? *a.n_dev : a.n_host;
-    const u32 n_tiles = (u32)(((u64)n + TILE - 1) / TILE);
-    const u32 w = threadIdx.x >> 6, lane = lane_id(), dme = threadIdx.x;  // one digit per thread
+    const u32 n_tiles = (u32)(((u64)n + TS - 1) / TS);
+    const u32 w = threadIdx.x >> 6, lane = lane_id(), dme = threadIdx.x;  // digit dme when dme < ND
+    const bool has_d = dme < ND;
     if (threadIdx.x == 0) L.tile = atomicAdd(&a.ctr[a.pass], 1u);
+    if (has_d) {
 #pragma unroll
-    for (u32 q = 0; q < WAVES; q++) L.wcnt[q][dme] = 0;
+        for (u32 q = 0; q < NW; q++) L.wcnt[q][dme] = 0;
+    }
     __syncthreads();
     const u32 tile = L.tile;
     if (tile >= n_tiles) return;  // no tile for this workgroup; no later tile waits on it
-    const u64 tile0 = (u64)tile * TILE;
-    const u64 wbase = tile0 + (u64)w * ITEMS * 64;
+    const u64 tile0 = (u64)tile * TS;
+    const u64 wbase = tile0 + (u64)w * NI * 64;
     const u32 shift = a.shift;
-    const u32 total = a.tot[a.pass * SORT_ND + dme];
-    u32 key[ITEMS], off[ITEMS], pay[NP][ITEMS];
+    const u32 total = has_d ? a.tot[a.pass * SORT_NDS + dme] : 0u;
+    u32 key[NI], off[NI], pay[NP > 0 ? NP : 1][NI];
 #pragma unroll
-    for (int k = 0; k < ITEMS; k++) {
+    for (int k = 0; k < NI; k++) {
         const u64 i = wbase + (u64)k * 64 + lane;
         const bool valid = i < n;
         key[k] = valid ? a.kin[i] : 0;
@@ -139,12 +155,12 @@ __global__ __launch_bounds__(WG_THREADS) void k_sort_sweep(SweepArgs a) {
     }
     // rank: position of each key among the equal digits of its wave, in input order
 #pragma unroll
-    for (int k = 0; k < ITEMS; k++) {
+    for (int k = 0; k < NI; k++) {
         const bool valid = wbase + (u64)k * 64 + lane < n;
-        const u32 d = (key[k] >> shift) & DMASK;
+        const u32 d = (key[k] >> shift) & DM;
         u64 m = ballot(valid);
 #pragma unroll
-        for (int bit = 0; bit < (int)SORT_RB; bit++) {
+        for (int bit = 0; bit < RB; bit++) {
             const u64 bb = ballot((d >> bit) & 1u);
             m &= ((d >> bit) & 1u) ? bb : ~bb;
         }
@@ -160,16 +176,21 @@ __global__ __launch_bounds__(WG_THREADS) void k_sort_sweep(SweepArgs a) {
     __syncthreads();
     // digit dme: exclusive wave prefixes and the tile's count
     u32 cnt = 0;
+    if (has_d) {
 #pragma unroll
-    for (u32 q = 0; q < WAVES; q++) {
-        const u32 c = L.wcnt[q][dme];
-        L.wcnt[q][dme] = cnt;
-        cnt += c;
+        for (u32 q = 0; q < NW; q++) {
+            const u32 c = L.wcnt[q][dme];
+            L.wcnt[q][dme] = cnt;
+            cnt += c;
+        }
     }
-    u64 *my = a.status_cur + (u64)tile * SORT_ND + dme;
-    __hip_atomic_store(my, (tile == 0 ? ST_PRE : ST_AGG) | (u64)cnt, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    // the next pass's look-back words of this tile start cleared
-    if (a.status_next) a.status_next[(u64)tile * SORT_ND + dme] = 0;
+    u64 *my = a.status_cur + (u64)tile * ND + dme;
+    if (has_d) {
+        __hip_atomic_store(my, (tile == 0 ? ST_PRE : ST_AGG) | (u64)cnt, __ATOMIC_RELAXED,
+                           __HIP_MEMORY_SCOPE_AGENT);
+        // the next pass's look-back words of this tile start cleared
+        if (a.status_next) a.status_next[(u64)tile * ND + dme] = 0;
+    }
     // exclusive scans over the digits: tile-local starts (cnt) and global digit bases (total)
     u32 x = cnt, y = total;
 #pragma unroll
@@ -180,14 +201,14 @@ __global__ __launch_bounds__(WG_THREADS) void k_sort_sweep(SweepArgs a) {
     if (lane == 63) { L.wtot[0][w] = x; L.wtot[1][w] = y; }
     // look back: digit dme's count in all earlier tiles, LOOKBACK predecessor words per round
     u64 excl = 0;
-    if (tile > 0) {
+    if (has_d && tile > 0) {
         int i = (int)tile - 1;
         u32 spins = 0;
         for (;;) {
             u64 v[LOOKBACK];
 #pragma unroll
             for (int j = 0; j < LOOKBACK; j++)
-                v[j] = i - j >= 0 ? __hip_atomic_load(a.status_cur + (u64)(i - j) * SORT_ND + dme, __ATOMIC_RELAXED,
+                v[j] = i - j >= 0 ? __hip_atomic_load(a.status_cur + (u64)(i - j) * ND + dme, __ATOMIC_RELAXED,
                                                       __HIP_MEMORY_SCOPE_AGENT)
                                   : ST_PRE;  // before tile 0: nothing
             bool done = false, stall = false;
@@ -212,32 +233,34 @@ __global__ __launch_bounds__(WG_THREADS) void k_sort_sweep(SweepArgs a) {
         __hip_atomic_store(my, ST_PRE | (excl + cnt), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }
     __syncthreads();
-    u32 pre = x - cnt, gb = y - total;
-    for (u32 q = 0; q < w; q++) { pre += L.wtot[0][q]; gb += L.wtot[1][q]; }
+    if (has_d) {
+        u32 pre = x - cnt, gb = y - total;
+        for (u32 q = 0; q < w; q++) { pre += L.wtot[0][q]; gb += L.wtot[1][q]; }
 #pragma unroll
-    for (u32 q = 0; q < WAVES; q++) L.wcnt[q][dme] += pre;
-    L.dg[dme] = gb + (u32)excl - pre;
+        for (u32 q = 0; q < NW; q++) L.wcnt[q][dme] += pre;
+        L.dg[dme] = gb + (u32)excl - pre;
+    }
     __syncthreads();
-    const u32 cnt_tile = (u32)((n - tile0) < (u64)TILE ? (n - tile0) : (u64)TILE);
+    const u32 cnt_tile = (u32)((n - tile0) < (u64)TS ? (n - tile0) : (u64)TS);
     // local sorted positions
 #pragma unroll
-    for (int k = 0; k < ITEMS; k++) {
+    for (int k = 0; k < NI; k++) {
         const bool valid = wbase + (u64)k * 64 + lane < n;
-        off[k] = valid ? L.wcnt[w][(key[k] >> shift) & DMASK] + off[k] : NONE;
+        off[k] = valid ? L.wcnt[w][(key[k] >> shift) & DM] + off[k] : NONE;
     }
     // keys through LDS, then each payload array
 #pragma unroll
-    for (int k = 0; k < ITEMS; k++)
+    for (int k = 0; k < NI; k++)
         if (off[k] != NONE) L.stage[off[k]] = key[k];
     __syncthreads();
-    u32 gpos[ITEMS];
+    u32 gpos[NI];
 #pragma unroll
-    for (int r = 0; r < ITEMS; r++) {
-        const u32 j = r * WG_THREADS + threadIdx.x;
+    for (int r = 0; r < NI; r++) {
+        const u32 j = r * THREADS + threadIdx.x;
         gpos[r] = NONE;
         if (j < cnt_tile) {
             const u32 kk = L.stage[j];
-            gpos[r] = L.dg[(kk >> shift) & DMASK] + j;
+            gpos[r] = L.dg[(kk >> shift) & DM] + j;
             a.kout[gpos[r]] = kk;
         }
     }
@@ -245,17 +268,17 @@ __global__ __launch_bounds__(WG_THREADS) void k_sort_sweep(SweepArgs a) {
     for (int q = 0; q < NP; q++) {
         __syncthreads();
 #pragma unroll
-        for (int k = 0; k < ITEMS; k++)
+        for (int k = 0; k < NI; k++)
             if (off[k] != NONE) L.stage[off[k]] = pay[q][k];
         __syncthreads();
 #pragma unroll
-        for (int r = 0; r < ITEMS; r++)
-            if (gpos[r] != NONE) a.pout[q][gpos[r]] = L.stage[r * WG_THREADS + threadIdx.x];
+        for (int r = 0; r < NI; r++)
+            if (gpos[r] != NONE) a.pout[q][gpos[r]] = L.stage[r * THREADS + threadIdx.x];
     }
 }
 
-static const char *const kSweepName[ELEM_SORT_PASSES] = {"k_sort_sweep_p0", "k_sort_sweep_p1", "k_sort_sweep_p2",
-                                                         "k_sort_sweep_p3"};
+static const char *const kSweepName[ELEM_MAX_PASSES] = {"k_sort_sweep_p0", "k_sort_sweep_p1", "k_sort_sweep_p2",
+                                                        "k_sort_sweep_p3", "k_sort_sweep_p4"};
 
 static SweepArgs sweep_args(const Bufs &b, u32 pass, u32 n_passes, u32 shift, const u32 *n_dev, u32 n_host,
                             const u32 *bits_dev) {
@@ -273,18 +296,14 @@ static SweepArgs sweep_args(const Bufs &b, u32 pass, u32 n_passes, u32 shift, co
     return a;
 }
 
-// Elements: key = location, payloads = index, tid, info.  The digit counts (per-tile rows), the
-// cleared look-back words of pass 0, the zeroed totals and tickets come from earlier kernels
-// (k_elements, k_init_params).  Passes past the key width found on the device do nothing, so the
-// result is in buffer (passes % 2), passes = ceil(key_bits / 8).
-void sort_elements(const Bufs &b, hipStream_t s) {
-    if (!b.N) return;
-    const u32 *n_dev = &b.prm->n_acc, *bits = &b.prm->key_bits;
-    RD_LAUNCH("k_sort_reduce", k_sort_reduce, dim3(ELEM_SORT_PASSES, (b.n_tiles + 63) / 64), dim3(WG_THREADS), 0, s,
-              b.sort_partial, ELEM_SORT_PASSES, b.n_tiles, (const u32 *)nullptr, bits, b.sort_tot);
-    for (u32 pass = 0; pass < ELEM_SORT_PASSES; pass++) {
+template <int RB, int NW, int NI>
+static void elem_passes(const Bufs &b, const u32 *n_dev, const u32 *bits, hipStream_t s) {
+    constexpr u32 TS = NW * 64 * NI;
+    constexpr u32 PASSES = (32 + RB - 1) / RB;
+    const u32 tiles = (u32)(((u64)b.N + TS - 1) / TS);
+    for (u32 pass = 0; pass < PASSES; pass++) {
         const u32 c = pass & 1, o = c ^ 1;
-        SweepArgs a = sweep_args(b, pass, ELEM_SORT_PASSES, pass * SORT_RB, n_dev, 0, bits);
+        SweepArgs a = sweep_args(b, pass, PASSES, pass * RB, n_dev, 0, bits);
         a.kin = b.ekey[c];
         a.pin[0] = b.eidx[c];
         a.pin[1] = b.etid[c];
@@ -293,7 +312,32 @@ void sort_elements(const Bufs &b, hipStream_t s) {
         a.pout[0] = b.eidx[o];
         a.pout[1] = b.etid[o];
         a.pout[2] = b.einfo[o];
-        RD_LAUNCH(kSweepName[pass], k_sort_sweep<3>, dim3(b.n_tiles), dim3(WG_THREADS), 0, s, a);
+        RD_LAUNCH(kSweepName[pass], (k_sort_sweep<3, RB, NW, NI>), dim3(tiles), dim3(NW * 64), 0, s, a);
+    }
+}
+
+// Elements: key = location, payloads = index, tid, info, with the context's variant.  The digit
+// counts (per-tile rows), the zeroed totals and tickets come from earlier kernels (k_elements,
+// k_init_params); k_sort_reduce clears the first look-back array.  Passes past the key width found
+// on the device do nothing, so the result is in buffer (passes % 2), passes = ceil(key_bits / rb).
+void sort_elements(const Bufs &b, hipStream_t s) {
+    if (!b.N) return;
+    const SortVariant v = kSortVariants[b.sort_variant < N_SORT_VARIANTS ? b.sort_variant : 0];
+    const u32 *n_dev = &b.prm->n_acc, *bits = &b.prm->key_bits;
+    const u32 passes = (32 + v.rb - 1) / v.rb, ts = v.waves * 64 * v.items;
+    const u64 clear = (((u64)b.N + ts - 1) / ts) << v.rb;
+    RD_LAUNCH("k_sort_reduce", k_sort_reduce, dim3(passes, (b.n_tiles + 63) / 64), dim3(WG_THREADS), 0, s,
+              b.sort_partial, ELEM_MAX_PASSES, b.n_tiles, (const u32 *)nullptr, bits, v.rb, b.sort_tot,
+              b.sort_status, clear);
+    switch (b.sort_variant) {
+    case 1: elem_passes<8, 8, 8>(b, n_dev, bits, s); break;
+    case 2: elem_passes<8, 8, 16>(b, n_dev, bits, s); break;
+    case 3: elem_passes<7, 4, 16>(b, n_dev, bits, s); break;
+    case 4: elem_passes<7, 8, 16>(b, n_dev, bits, s); break;
+    case 5: elem_passes<9, 8, 16>(b, n_dev, bits, s); break;
+    case 6: elem_passes<9, 8, 8>(b, n_dev, bits, s); break;
+    case 7: elem_passes<8, 4, 8>(b, n_dev, bits, s); break;
+    default: elem_passes<8, 4, 16>(b, n_dev, bits, s); break;
     }
 }
 
@@ -310,7 +354,8 @@ void sort_pairs(const Bufs &b, const u32 *m_dev, u32 m_host, u64 max_m, hipStrea
     RD_LAUNCH("k_pair_count", k_pair_count, dim3(n_tiles), dim3(WG_THREADS), 0, s, b.pfirst[0], b.psecond[0], m_dev,
               m_host, half, passes, b.sort_partial, b.sort_status, b.sort_tot);
     RD_LAUNCH("k_pair_reduce", k_sort_reduce, dim3(passes, (n_tiles + 63) / 64), dim3(WG_THREADS), 0, s,
-              b.sort_partial, MAX_SORT_PASSES, n_tiles, m_dev, (const u32 *)nullptr, b.sort_tot);
+              b.sort_partial, MAX_SORT_PASSES, n_tiles, m_dev, (const u32 *)nullptr, SORT_RB, b.sort_tot,
+              (u64 *)nullptr, (u64)0);
     u32 cur = 0;
     for (u32 pass = 0; pass < passes; pass++) {
         const u32 o = cur ^ 1;
@@ -320,7 +365,7 @@ void sort_pairs(const Bufs &b, const u32 *m_dev, u32 m_host, u64 max_m, hipStrea
         a.pin[0] = lo ? b.pfirst[cur] : b.psecond[cur];
         a.kout = lo ? b.psecond[o] : b.pfirst[o];
         a.pout[0] = lo ? b.pfirst[o] : b.psecond[o];
-        RD_LAUNCH("k_pair_sweep", k_sort_sweep<1>, dim3(n_tiles), dim3(WG_THREADS), 0, s, a);
+        RD_LAUNCH("k_pair_sweep", (k_sort_sweep<1, 8, 4, 16>), dim3(n_tiles), dim3(WG_THREADS), 0, s, a);
         cur = o;
     }
 }
@@ -336,7 +381,7 @@ void sort_kv(const Bufs &b, u32 *const k[2], u32 *const v[2], const u32 *n_dev, 
     RD_LAUNCH(name, k_pair_count, dim3(n_tiles), dim3(WG_THREADS), 0, s, k[0], k[0], n_dev, 0u, passes, passes,
               b.sort_partial, b.sort_status, b.sort_tot);
     RD_LAUNCH(name, k_sort_reduce, dim3(passes, (n_tiles + 63) / 64), dim3(WG_THREADS), 0, s, b.sort_partial,
-              MAX_SORT_PASSES, n_tiles, n_dev, bits_dev, b.sort_tot);
+              MAX_SORT_PASSES, n_tiles, n_dev, bits_dev, SORT_RB, b.sort_tot, (u64 *)nullptr, (u64)0);
     for (u32 pass = 0; pass < passes; pass++) {
         const u32 c = pass & 1, o = c ^ 1;
         SweepArgs a = sweep_args(b, pass, passes, pass * SORT_RB, n_dev, 0, bits_dev);
@@ -344,7 +389,7 @@ void sort_kv(const Bufs &b, u32 *const k[2], u32 *const v[2], const u32 *n_dev, 
         a.pin[0] = v[c];
         a.kout = k[o];
         a.pout[0] = v[o];
-        RD_LAUNCH(name, k_sort_sweep<1>, dim3(n_tiles), dim3(WG_THREADS), 0, s, a);
+        RD_LAUNCH(name, (k_sort_sweep<1, 8, 4, 16>), dim3(n_tiles), dim3(WG_THREADS), 0, s, a);
     }
 }
 

@@ -192,3 +192,45 @@ def test_random_traces_no_warp_barriers_larger(rc, seed):
     assert got.status == want.status, (seed, got, want)
     if want.status == 0:
         np.testing.assert_array_equal(got.pairs, want.pairs, err_msg=f"seed {seed}")
+
+
+# ---------------------------------------------------------------- location-sort variants
+
+@pytest.mark.parametrize("variant", list(range(8)))
+def test_sort_variants_match_oracle(rc, variant):
+    import paper_2111_12478_amd as rd
+    assert rd.rd_tuning_count() == 8
+    rb, waves, items = rd.rd_tuning_get(variant)
+    _say(f"variant {variant}: {rb}-bit digits, {waves} waves x {items} items")
+    assert rd.rd_set_tuning(rc.ctx, variant) == 0
+    try:
+        cases = [tracegen.random_trace(s, max_blocks=6, max_tpb=40, max_events=6000) for s in range(7000, 7012)]
+        g, ev, _, _ = tracegen.generate(tracegen.large(seed=2, scale=32))
+        cases.append((g, ev))
+        cfg = tracegen.stencil_small(seed=variant, rb=8, cb=8, tpb=64, rows=4, sweeps=3, plant_rate=0.05)
+        g, ev, _, _ = tracegen.generate_stencil(cfg)
+        cases.append((g, ev))
+        for j, (g, ev) in enumerate(cases):
+            want = oracle.check(g, ev)
+            got = rc.check(g, ev)
+            assert got.status == want.status == 0, (variant, j, got, want)
+            np.testing.assert_array_equal(got.pairs, want.pairs, err_msg=f"variant {variant} case {j}")
+    finally:
+        rd.rd_set_tuning(rc.ctx, 0)
+
+
+def test_autotune_picks_a_variant_and_keeps_results(rc):
+    import torch
+    import paper_2111_12478_amd as rd
+    g, ev, _, _ = tracegen.generate(tracegen.large(seed=2, scale=16))
+    want = oracle.check(g, ev)
+    tr, ws, keep = rc.prepare(g, ev)
+    try:
+        st, best, ms = rd.rd_autotune(rc.ctx, [tr], None, 0, torch.cuda.current_stream().cuda_stream)
+        assert st == 0 and 0 <= best < 8 and all(m > 0 for m in ms), (st, best, ms)
+        assert rd.rd_get_tuning(rc.ctx) == best
+        got = rc.report(tr)
+        np.testing.assert_array_equal(got.pairs, want.pairs)
+    finally:
+        rd.rd_trace_free(rc.ctx, tr)
+        rd.rd_set_tuning(rc.ctx, 0)
