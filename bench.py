@@ -147,6 +147,7 @@ def parse():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--scale", type=int, default=1, help="shrink the workload (tests only)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-tune", action="store_true", help="keep the default location-sort variant")
     ap.add_argument("--profile-all", action="store_true", help="print every kernel's time to stderr")
     ap.add_argument("--summarize-profiles", nargs=4, metavar=("TRACE_CSV", "FETCH_CSV", "WRITE_CSV", "COMMAND"),
                     help="write profiles/ summaries from rocprofv3 CSV files and exit")
@@ -220,6 +221,14 @@ def bench_batched(args):
         return (time.perf_counter() - t0) / steps, res
 
     steps = max(1, min(args.steps, 5))
+    tune_ms = None
+    if not args.no_tune:
+        st, best, tune_ms = rd.rd_autotune(rc.ctx, traces, bws.data_ptr(), bws.numel(), stream)
+        if st != rd.RD_OK:
+            raise RuntimeError(f"rd_autotune failed: {st}")
+        print(f"batched: autotuned variant {best} {rd.rd_tuning_get(best)}: {['%.2f' % m for m in tune_ms]} ms",
+              file=sys.stderr, flush=True)
+    variant = rd.rd_get_tuning(rc.ctx)
     for _ in range(max(1, min(args.warmup, 2))):
         plain_res = plain_step()
         batch_res = batched_step()
@@ -248,6 +257,9 @@ def bench_batched(args):
                         f"trace, seed 4; one rd_check_many + rd_races_many",
             "events": n_total,
             "race_pairs": int(n_pairs),
+            "sort_variant": {"index": variant, "digit_bits": rd.rd_tuning_get(variant)[0],
+                             "waves": rd.rd_tuning_get(variant)[1], "items": rd.rd_tuning_get(variant)[2],
+                             "autotune_ms": tune_ms},
         },
         "plain": {"value": n_total / t_plain, "unit": "events/s", "ms_per_step": t_plain * 1e3,
                   "form": "one rd_check + rd_races per trace, in turn, same resident events"},
@@ -535,6 +547,13 @@ def main():
             raise RuntimeError(f"check failed: {res}")
         return res
 
+    # pick the location-sort variant for this trace (untimed), as a user of the library would
+    tune_ms = None
+    if not args.no_tune:
+        st, best, tune_ms = rd.rd_autotune(rc.ctx, [tr], None, 0, torch.cuda.current_stream().cuda_stream)
+        if st != rd.RD_OK:
+            raise RuntimeError(f"rd_autotune failed: {st}")
+    variant = rd.rd_get_tuning(rc.ctx)
     if args.copy_bytes:
         src_t = torch.empty(args.copy_bytes // 4, dtype=torch.int32, device="cuda")
         dst_t = torch.empty_like(src_t)
@@ -554,7 +573,7 @@ def main():
         for k, (c, ms) in sorted(prof.items(), key=lambda kv: -kv[1][1]):
             print(f"  {k:28s} launches={c:3d} total={ms:8.3f} ms", file=sys.stderr)
     # the element sort runs one sweep per key digit; its passes count as one kernel
-    radix_bits = 8
+    radix_bits = rd.rd_tuning_get(variant)[0]
     passes = key_passes(ev, grid[0], grid[1], radix_bits)
     pass_names = [f"k_sort_sweep_p{p}" for p in range(passes)]
 
@@ -622,6 +641,9 @@ def main():
             "race_pairs": int(len(gpu_pairs)),
             "radix_bits": radix_bits,
             "sort_passes": passes,
+            "sort_variant": {"index": variant, "digit_bits": rd.rd_tuning_get(variant)[0],
+                             "waves": rd.rd_tuning_get(variant)[1], "items": rd.rd_tuning_get(variant)[2],
+                             "autotune_ms": tune_ms},
         },
         "roofline": {
             "bound": "hbm",

@@ -142,6 +142,17 @@ rd_status rd_batch_workspace_bytes(rd_ctx ctx, const rd_trace *traces, uint32_t 
 rd_status rd_check_many(rd_ctx ctx, const rd_trace *traces, uint32_t n, void *workspace, uint64_t workspace_bytes,
                         const rd_limits *limits, hipStream_t stream);
 
+/* The batched pass captured once into a HIP graph (on a non-default `stream`), for members whose
+ * event buffers are refilled in place and checked again: rd_graph_launch replays the whole pass
+ * (table upload, merge, check, pair sort) with one launch, after which the members' reports are
+ * read as after rd_check_many.  The members, their events and the workspace must stay valid until
+ * rd_graph_free; the member set and sizes are those of the capture. */
+typedef struct rd_graph_s *rd_graph;
+rd_status rd_batch_capture(rd_ctx ctx, const rd_trace *traces, uint32_t n, void *workspace, uint64_t workspace_bytes,
+                           const rd_limits *limits, hipStream_t stream, rd_graph *out);
+rd_status rd_graph_launch(rd_ctx ctx, rd_graph graph, hipStream_t stream);
+rd_status rd_graph_free(rd_ctx ctx, rd_graph graph);
+
 /* Reports of n checked traces in one call: member j's pairs follow member j-1's in `out` (canonical
  * order inside each member), counts[j] = member j's total, statuses[j] = what rd_races would return
  * for it (RD_ETRUNC when its pairs did not all fit in what was left of `capacity`).  Members of one

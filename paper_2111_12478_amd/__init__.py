@@ -79,6 +79,9 @@ def load_library():
             "rd_batch_workspace_bytes": ([vp, P(vp), u32, P(rd_limits), P(u64)], i32),
             "rd_check_many": ([vp, P(vp), u32, vp, u64, P(rd_limits), vp], i32),
             "rd_races_many": ([vp, P(vp), u32, vp, u64, P(u64), P(i32)], i32),
+            "rd_batch_capture": ([vp, P(vp), u32, vp, u64, P(rd_limits), vp, P(vp)], i32),
+            "rd_graph_launch": ([vp, vp, vp], i32),
+            "rd_graph_free": ([vp, vp], i32),
             "rd_tuning_count": ([P(u32)], i32),
             "rd_tuning_get": ([u32, P(rd_tuning)], i32),
             "rd_set_tuning": ([vp, u32], i32),
@@ -186,6 +189,21 @@ def rd_races_many(ctx, traces, out_ptr, capacity):
                                       counts.ctypes.data_as(ctypes.POINTER(ctypes.c_uint64)),
                                       sts.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)))
     return st, counts[:n], sts[:n]
+
+
+def rd_batch_capture(ctx, traces, workspace_ptr, workspace_bytes, limits, stream) -> tuple[int, int]:
+    g = ctypes.c_void_p()
+    st = load_library().rd_batch_capture(ctx, _trace_array(traces), len(traces), workspace_ptr, workspace_bytes,
+                                         _limits(limits), stream, ctypes.byref(g))
+    return st, g.value
+
+
+def rd_graph_launch(ctx, graph, stream) -> int:
+    return load_library().rd_graph_launch(ctx, graph, stream)
+
+
+def rd_graph_free(ctx, graph) -> int:
+    return load_library().rd_graph_free(ctx, graph)
 
 
 def rd_tuning_count() -> int:

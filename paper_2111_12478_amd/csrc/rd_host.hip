@@ -333,7 +333,8 @@ struct Batch {
     u32 *rt_scan;
     BatchTrace *tr_dev;
     u32 *off_dev, *bad_dev;
-    std::vector<BatchTrace> tr_host;
+    std::vector<BatchTrace> tr_init;  // uploaded table (never changes: a captured graph reads it again)
+    std::vector<BatchTrace> tr_host;  // the table as read back after the pass
     std::vector<u32> off_host;
     u32 zero = 0;
     u64 ws_bytes;
@@ -362,6 +363,14 @@ struct rd_trace_s {
     uint64_t cache_idx, cache_n;
     std::string cache_msg;
     std::vector<rd_pair> cache;
+};
+
+// A captured batched pass: replayed by rd_graph_launch for the same members and workspace.
+struct rd_graph_s {
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    std::shared_ptr<Batch> batch;
+    std::vector<rd_trace> traces;
 };
 
 // Shape of the merged trace of a batch; false when the members cannot be merged (different warp
@@ -685,6 +694,85 @@ rd_status rd_races(rd_ctx ctx, rd_trace trace, rd_pair *out, uint64_t capacity, 
     return plain_races(ctx, trace->bufs, trace->stream, out, capacity, n_races);
 }
 
+// The merged pass's buffers and member table (host side) for members that can share one pass.
+static rd_status batch_prepare(rd_ctx ctx, const rd_trace *traces, uint32_t n, void *workspace,
+                               uint64_t workspace_bytes, const BatchShape &S, hipStream_t stream,
+                               std::shared_ptr<Batch> &out) {
+    if (!workspace || ((uintptr_t)workspace & 255))
+        return set_err(ctx, RD_EINVAL, UINT64_MAX, "workspace null or not 256-byte aligned");
+    if (workspace_bytes < S.total) return set_err(ctx, RD_ENOMEM, UINT64_MAX, "batch workspace too small");
+    std::shared_ptr<Batch> B(new (std::nothrow) Batch);
+    if (!B) return RD_ENOMEM;
+    char *ws = (char *)workspace;
+    B->plan = S.plan;
+    B->ws = ws;
+    B->ws_bytes = workspace_bytes;
+    B->bufs = make_bufs(S.plan, ws, nullptr, S.N, (u32)S.B, S.tpb, S.ws);
+    B->bufs.sort_variant = ctx->sort_variant;
+    B->bufs.radix_bits = kSortVariants[ctx->sort_variant].rb;
+    B->masks = (u64 *)(ws + S.plan.off_masks);
+    B->rt_scan = (u32 *)(ws + S.plan.off_rt_scan);
+    B->tr_dev = (BatchTrace *)(ws + S.table_off);
+    B->off_dev = (u32 *)(ws + S.off_off);
+    B->bad_dev = (u32 *)(ws + S.bad_off);
+    B->stream = stream;
+    B->tr_init.resize(n);
+    B->tr_host.resize(n);
+    B->off_host.resize(n + 1);
+    u32 off = 0, blk = 0;
+    for (uint32_t j = 0; j < n; j++) {
+        const rd_trace t = traces[j];
+        BatchTrace &d = B->tr_init[j];
+        memset(&d, 0, sizeof(d));
+        d.ev = t->bufs.ev;
+        d.n = (u32)t->n;
+        d.n_blocks = t->grid.n_blocks;
+        d.tpb = t->grid.threads_per_block;
+        d.blk_off = blk;
+        d.gmin = NONE;
+        d.gmax = 0;
+        B->off_host[j] = off;
+        off += (u32)t->n;
+        blk += t->grid.n_blocks;
+    }
+    B->off_host[n] = off;
+    out = B;
+    return RD_OK;
+}
+
+// The merged pass, enqueued on `stream` (also what a captured graph holds).
+static hipError_t batch_enqueue(Batch &B, uint32_t n, const BatchShape &S, hipStream_t stream) {
+    hipError_t e = hipMemcpyAsync(B.tr_dev, B.tr_init.data(), sizeof(BatchTrace) * n, hipMemcpyHostToDevice, stream);
+    if (e == hipSuccess) e = hipMemcpyAsync(B.off_dev, B.off_host.data(), 4ull * (n + 1), hipMemcpyHostToDevice, stream);
+    if (e == hipSuccess) e = hipMemcpyAsync(B.bad_dev, &B.zero, 4, hipMemcpyHostToDevice, stream);
+    if (e == hipSuccess) {
+        batch_merge(B.tr_dev, B.off_dev, n, (u32)S.N, S.tpb, (uint4 *)B.bufs.ev, B.bad_dev, stream);
+        e = enqueue_check(B.bufs, B.masks, B.rt_scan, stream);
+    }
+    if (e == hipSuccess) {
+        sort_pairs(B.bufs, &B.bufs.prm->n_pairs_kept, 0, B.bufs.max_pairs, stream);
+        batch_pair_ranges(B.tr_dev, B.off_dev, n, B.bufs, stream);
+        e = hipGetLastError();
+    }
+    return e;
+}
+
+static void batch_attach(const std::shared_ptr<Batch> &B, const rd_trace *traces, uint32_t n, hipStream_t stream) {
+    {
+        std::lock_guard<std::mutex> g(B->mu);
+        B->read = false;
+        B->failed = false;
+        B->stream = stream;
+    }
+    for (uint32_t j = 0; j < n; j++) {
+        traces[j]->batch = B;
+        traces[j]->batch_idx = j;
+        traces[j]->checked = 1;
+        traces[j]->cached = 0;
+        traces[j]->stream = stream;
+    }
+}
+
 rd_status rd_batch_workspace_bytes(rd_ctx ctx, const rd_trace *traces, uint32_t n, const rd_limits *limits,
                                    uint64_t *bytes) {
     if (!ctx || !bytes || (n && !traces)) return RD_EINVAL;
@@ -718,64 +806,15 @@ rd_status rd_check_many(rd_ctx ctx, const rd_trace *traces, uint32_t n, void *wo
     if (!workspace || ((uintptr_t)workspace & 255))
         return set_err(ctx, RD_EINVAL, UINT64_MAX, "workspace null or not 256-byte aligned");
     if (workspace_bytes < S.total) return set_err(ctx, RD_ENOMEM, UINT64_MAX, "batch workspace too small");
-    std::shared_ptr<Batch> B(new (std::nothrow) Batch);
-    if (!B) return RD_ENOMEM;
-    char *ws = (char *)workspace;
-    B->plan = S.plan;
-    B->ws = ws;
-    B->ws_bytes = workspace_bytes;
-    B->bufs = make_bufs(S.plan, ws, nullptr, S.N, (u32)S.B, S.tpb, S.ws);
-    B->bufs.sort_variant = ctx->sort_variant;
-    B->bufs.radix_bits = kSortVariants[ctx->sort_variant].rb;
-    B->masks = (u64 *)(ws + S.plan.off_masks);
-    B->rt_scan = (u32 *)(ws + S.plan.off_rt_scan);
-    B->tr_dev = (BatchTrace *)(ws + S.table_off);
-    B->off_dev = (u32 *)(ws + S.off_off);
-    B->bad_dev = (u32 *)(ws + S.bad_off);
-    B->stream = stream;
-    B->tr_host.resize(n);
-    B->off_host.resize(n + 1);
-    u32 off = 0, blk = 0;
-    for (uint32_t j = 0; j < n; j++) {
-        const rd_trace t = traces[j];
-        BatchTrace &d = B->tr_host[j];
-        memset(&d, 0, sizeof(d));
-        d.ev = t->bufs.ev;
-        d.n = (u32)t->n;
-        d.n_blocks = t->grid.n_blocks;
-        d.tpb = t->grid.threads_per_block;
-        d.blk_off = blk;
-        d.gmin = NONE;
-        d.gmax = 0;
-        B->off_host[j] = off;
-        off += (u32)t->n;
-        blk += t->grid.n_blocks;
-    }
-    B->off_host[n] = off;
+    std::shared_ptr<Batch> B;
+    const rd_status st = batch_prepare(ctx, traces, n, workspace, workspace_bytes, S, stream, B);
+    if (st != RD_OK) return st;
     Profiler *saved = g_prof;
     g_prof = ctx->prof.filter.empty() ? nullptr : &ctx->prof;
-    hipError_t e = hipMemcpyAsync(B->tr_dev, B->tr_host.data(), sizeof(BatchTrace) * n, hipMemcpyHostToDevice, stream);
-    if (e == hipSuccess)
-        e = hipMemcpyAsync(B->off_dev, B->off_host.data(), 4ull * (n + 1), hipMemcpyHostToDevice, stream);
-    if (e == hipSuccess) e = hipMemcpyAsync(B->bad_dev, &B->zero, 4, hipMemcpyHostToDevice, stream);
-    if (e == hipSuccess) {
-        batch_merge(B->tr_dev, B->off_dev, n, (u32)S.N, S.tpb, (uint4 *)B->bufs.ev, B->bad_dev, stream);
-        e = enqueue_check(B->bufs, B->masks, B->rt_scan, stream);
-    }
-    if (e == hipSuccess) {
-        sort_pairs(B->bufs, &B->bufs.prm->n_pairs_kept, 0, B->bufs.max_pairs, stream);
-        batch_pair_ranges(B->tr_dev, B->off_dev, n, B->bufs, stream);
-        e = hipGetLastError();
-    }
+    const hipError_t e = batch_enqueue(*B, n, S, stream);
     g_prof = saved;
     if (e != hipSuccess) return set_err(ctx, RD_EHIP, UINT64_MAX, hipGetErrorString(e));
-    for (uint32_t j = 0; j < n; j++) {
-        traces[j]->batch = B;
-        traces[j]->batch_idx = j;
-        traces[j]->checked = 1;
-        traces[j]->cached = 0;
-        traces[j]->stream = stream;
-    }
+    batch_attach(B, traces, n, stream);
     return RD_OK;
 }
 
@@ -842,6 +881,59 @@ rd_status rd_races_many(rd_ctx ctx, const rd_trace *traces, uint32_t n, rd_pair 
         if (st != RD_OK && worst == RD_OK) worst = st;
     }
     return worst;
+}
+
+rd_status rd_batch_capture(rd_ctx ctx, const rd_trace *traces, uint32_t n, void *workspace, uint64_t workspace_bytes,
+                           const rd_limits *limits, hipStream_t stream, rd_graph *out) {
+    if (!ctx || !out || !n || !traces || !stream) return RD_EINVAL;
+    *out = nullptr;
+    for (uint32_t j = 0; j < n; j++)
+        if (!traces[j]) return set_err(ctx, RD_EINVAL, UINT64_MAX, "null trace in the batch");
+    if (hipSetDevice(ctx->device) != hipSuccess) return set_err(ctx, RD_EHIP, UINT64_MAX, "hipSetDevice failed");
+    BatchShape S;
+    if (!batch_shape(traces, n, limits, S))
+        return set_err(ctx, RD_EINVAL, UINT64_MAX, "members cannot share one pass (warp sizes or sizes)");
+    std::shared_ptr<Batch> B;
+    const rd_status st = batch_prepare(ctx, traces, n, workspace, workspace_bytes, S, stream, B);
+    if (st != RD_OK) return st;
+    rd_graph g = new (std::nothrow) rd_graph_s;
+    if (!g) return RD_ENOMEM;
+    g->batch = B;
+    g->traces.assign(traces, traces + n);
+    Profiler *saved = g_prof;
+    g_prof = nullptr;  // no event records inside a captured graph
+    hipError_t e = hipStreamBeginCapture(stream, hipStreamCaptureModeThreadLocal);
+    hipError_t e2 = hipSuccess;
+    if (e == hipSuccess) {
+        e2 = batch_enqueue(*B, n, S, stream);
+        e = hipStreamEndCapture(stream, &g->graph);
+    }
+    g_prof = saved;
+    if (e == hipSuccess && e2 == hipSuccess) e = hipGraphInstantiate(&g->exec, g->graph, nullptr, nullptr, 0);
+    if (e != hipSuccess || e2 != hipSuccess) {
+        (void)hipGetLastError();
+        if (g->graph) (void)hipGraphDestroy(g->graph);
+        delete g;
+        return set_err(ctx, RD_EHIP, UINT64_MAX, hipGetErrorString(e != hipSuccess ? e : e2));
+    }
+    *out = g;
+    return RD_OK;
+}
+
+rd_status rd_graph_launch(rd_ctx ctx, rd_graph g, hipStream_t stream) {
+    if (!ctx || !g) return RD_EINVAL;
+    if (hipSetDevice(ctx->device) != hipSuccess) return set_err(ctx, RD_EHIP, UINT64_MAX, "hipSetDevice failed");
+    if (hipGraphLaunch(g->exec, stream) != hipSuccess) return set_err(ctx, RD_EHIP, UINT64_MAX, "hipGraphLaunch failed");
+    batch_attach(g->batch, g->traces.data(), (uint32_t)g->traces.size(), stream);
+    return RD_OK;
+}
+
+rd_status rd_graph_free(rd_ctx ctx, rd_graph g) {
+    if (!ctx || !g) return RD_EINVAL;
+    if (g->exec) (void)hipGraphExecDestroy(g->exec);
+    if (g->graph) (void)hipGraphDestroy(g->graph);
+    delete g;
+    return RD_OK;
 }
 
 rd_status rd_tuning_count(uint32_t *n) {

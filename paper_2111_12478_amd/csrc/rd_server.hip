@@ -267,6 +267,9 @@ rd_status rd_server_open(rd_ctx ctx, void *device_arena, const rd_server_config 
             delete s;
             return RD_EHIP;
         }
+        uint32_t tuning = 0;
+        rd_get_tuning(ctx, &tuning);
+        rd_set_tuning(c, tuning);  // the workers sort with the caller's chosen variant
         s->streams.push_back(st);
         s->wctx.push_back(c);
     }

@@ -131,3 +131,47 @@ def test_batch_repeated(rc):
     b = rc.check_many(items)
     for j, (x, y) in enumerate(zip(a, b)):
         _assert_same(x, y, f"member {j}")
+
+
+def test_batch_graph_replays(rc):
+    # one captured batched pass, replayed: first on traces A, then with B's events written in place
+    # (same sizes), with eager checks and synchronisation between the replays
+    import dataclasses
+    import torch
+    import paper_2111_12478_amd as rd
+    cfgs = tracegen.batch(seed=15, n_traces=6, scale=16)
+    a_items, b_items = [], []
+    for c in cfgs:
+        g, ev, _, _ = tracegen.generate(c)
+        a_items.append((g, ev))
+        g2, ev2, _, _ = tracegen.generate(dataclasses.replace(c, seed=c.seed + 1000))
+        assert ev2.shape == ev.shape
+        b_items.append((g2, ev2))
+    dev = [torch.from_numpy(ev.view(np.int32)).cuda() for _, ev in a_items]
+    bound = [rc.prepare(g, d) for (g, _), d in zip(a_items, dev)]
+    traces = [b[0] for b in bound]
+    stream = torch.cuda.Stream()
+    try:
+        nbytes = rd.rd_batch_workspace_bytes(rc.ctx, traces, None)
+        ws = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
+        with torch.cuda.stream(stream):
+            st, graph = rd.rd_batch_capture(rc.ctx, traces, ws.data_ptr(), nbytes, None, stream.cuda_stream)
+            assert st == 0, rd.rd_last_error(rc.ctx)
+            try:
+                for rep, items in enumerate([a_items, a_items, b_items, b_items, a_items]):
+                    for d, (_, ev) in zip(dev, items):
+                        d.copy_(torch.from_numpy(ev.view(np.int32)))
+                    stream.synchronize()
+                    assert rd.rd_graph_launch(rc.ctx, graph, stream.cuda_stream) == 0
+                    got = rc.report_many(traces)
+                    for j, ((g, ev), r) in enumerate(zip(items, got)):
+                        _assert_same(r, oracle.check(g, ev), f"replay {rep} member {j}")
+                    # eager work between replays
+                    other = rc.check(*b_items[0])
+                    _assert_same(other, oracle.check(*b_items[0]), "eager")
+                    torch.cuda.synchronize()
+            finally:
+                rd.rd_graph_free(rc.ctx, graph)
+    finally:
+        for t in traces:
+            rd.rd_trace_free(rc.ctx, t)
