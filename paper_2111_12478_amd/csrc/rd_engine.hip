@@ -8,8 +8,7 @@
 //   * a release on location X extends the chain (X, DEV), or the chains (X, its block) and
 //     (X, ALL); its input is the previous release of each chain.  Segmented scans over the
 //     release/acquire accesses in (location, trace) order -- the location sort's order -- find
-//     them; the per-block chains come from a stable re-sort of the block-scoped ones by block and
-//     then location;
+//     them; for the per-block chains a wavefront scans back over the location's run;
 //   * an acquire reads the latest release of (X, DEV) and of (X, its block) or (X, ALL);
 //   * a thread's knowledge before an entry is its last acquire since its last barrier, else its
 //     block's knowledge after that barrier (one lane per thread walks its own list);
@@ -28,7 +27,6 @@ constexpr u32 BK_MARK = 0x80000000u;  // e_cur: the block's knowledge after (val
 constexpr u32 ENG_WIDE = 16;          // groups with at least this many operations run on every workgroup
 constexpr u32 ENG_THREADS = 512;
 constexpr u32 ENG_SPIN = 1u << 19;  // ~1 s of polling: far above any legitimate wait
-constexpr u32 BL_MAX = 1u << 20;      // block-scoped release/acquire accesses re-sorted at most
 
 __device__ inline bool eng_active(const DevParams *P) {
     return (P->mode & MODE_SYNC) && !(P->mode & MODE_WBAR) && P->first_bad_record == NONE &&
@@ -127,8 +125,8 @@ __device__ inline u32 seg_scan_chunk(SegLds &L, bool head, u32 val, u32 nin) {
     return ex;
 }
 
-// Chains (X, DEV) and (X, ALL) over ral (runs: equal locations).  Flags block-scoped items in
-// e_scan1 for the per-block chains.
+// Chains (X, DEV) and (X, ALL) over ral (runs: equal locations).  Packs each item's block and
+// block-scope bits into e_scan1 for the per-block chains.
 __global__ __launch_bounds__(1024) void k_eng_chains(Bufs b) {
     DevParams *P = b.prm;
     if (!eng_on(P)) return;
@@ -159,74 +157,65 @@ __global__ __launch_bounds__(1024) void k_eng_chains(Bufs b) {
                 b.e_src0[p] = rel_dev ? p : ex_dev;
                 b.e_src1[p] = ((sc >> 2) & 3u) != 0 ? (rel_blk ? p : ex_all) : NONE;  // block scope: later
             }
-            b.e_scan1[k] = (rel_blk || (acq && ((sc >> 2) & 3u) == 0)) ? 1u : 0u;
+            // per-block chains, below: bit 31 block-scoped release, bit 30 needs its chain, low bits block
+            const u32 blk = block_of(b, b.ev[b.s_pidx[p]].y);
+            b.e_scan1[k] = (rel_blk ? 0x80000000u : 0u) |
+                           ((rel_blk || (acq && ((sc >> 2) & 3u) == 0)) ? 0x40000000u : 0u) | blk;
         }
     }
-    if (threadIdx.x == 0) b.e_scan1[n] = 0;
 }
 
-// Block-scoped items: keys (block) and values (ral index) into pfirst[0] / psecond[0].
-__global__ void k_eng_blk_items(Bufs b) {
+// Per-block chains (X, block): for every item that needs one, a whole wavefront scans backwards
+// over its location's run in the (location, trace)-ordered list, 64 positions per step, for the
+// latest block-scoped release of the same block.  Runs of one shared word belong to one block and
+// end at once; a global word that many blocks take with block scope may take longer: past WALK_MAX
+// steps the engine gives way to the sequential interpreter.
+constexpr u32 WALK_MAX = 1u << 14;
+
+__global__ __launch_bounds__(256) void k_eng_blk_walk(Bufs b) {
     DevParams *P = b.prm;
     if (!eng_on(P)) return;
-    const u32 n = P->n_ral, total = b.e_scan1[n];
-    const bool over = total > BL_MAX || total > b.max_pairs;
-    if (blockIdx.x == 0 && threadIdx.x == 0) {
-        P->n_bl = over ? 0u : total;  // the sorts that follow read n_bl items
-        if (over) atomicOr(&P->eng, ENG_FALLBACK);
-    }
-    if (over) return;
-    for (u32 k = blockIdx.x * blockDim.x + threadIdx.x; k < n; k += gridDim.x * blockDim.x) {
-        const u32 m = b.e_scan1[k];
-        if (b.e_scan1[k + 1] == m) continue;
-        b.pfirst[0][m] = block_of(b, b.ev[b.s_pidx[b.ral_p[k]]].y);
-        b.psecond[0][m] = k;
-    }
-}
-
-// After the sort by block (result in buffer c): keys become the location of each item.
-__global__ void k_eng_blk_rekey(Bufs b, u32 c) {
-    const DevParams *P = b.prm;
-    if (!eng_on(P)) return;
-    const u32 n = P->n_bl;
-    for (u32 m = blockIdx.x * blockDim.x + threadIdx.x; m < n; m += gridDim.x * blockDim.x) {
-        const u32 k = b.psecond[c][m];
-        b.pfirst[0][m] = b.ral_key[k];
-        b.psecond[0][m] = k;
-    }
-}
-
-// Per-block chains over the items in (location, block, trace) order -- the second sort's result is
-// in buffer ceil(key_bits / 8) % 2; runs: equal (location, block).
-__global__ __launch_bounds__(1024) void k_eng_blk_chains(Bufs b) {
-    DevParams *P = b.prm;
-    if (!eng_on(P)) return;
-    const u32 n = P->n_bl, c = sorted_buf(P);
-    __shared__ SegLds L;
-    if (threadIdx.x == 0) L.carry = NONE;
-    __syncthreads();
-    for (u32 c0 = 0; c0 < n; c0 += 1024) {
-        const u32 m = c0 + threadIdx.x, nin = n - c0 < 1024 ? n - c0 : 1024;
-        u32 p = NONE;
-        uint8_t f = 0, sc = 0;
-        bool head = true;
-        if (m < n) {
-            const u32 k = b.psecond[c][m];
-            p = b.ral_p[k];
-            f = b.s_flags[p];
-            sc = b.s_scope[p];
-            if (m > 0) {
-                const u32 kp = b.psecond[c][m - 1];
-                head = b.ral_key[kp] != b.ral_key[k] ||
-                       block_of(b, b.ev[b.s_pidx[b.ral_p[kp]]].y) != block_of(b, b.ev[b.s_pidx[p]].y);
+    const u32 n = P->n_ral, lane = lane_id();
+    const u32 wave = (blockIdx.x * blockDim.x + threadIdx.x) >> 6, n_waves = (gridDim.x * blockDim.x) >> 6;
+    for (u32 c0 = wave * 64; c0 < n; c0 += n_waves * 64) {
+        const u32 k = c0 + lane;
+        const u32 pk = k < n ? b.e_scan1[k] : 0u;
+        u64 todo = ballot((pk & 0x40000000u) != 0);
+        while (todo) {
+            const u32 src = (u32)__builtin_ctzll(todo);
+            todo &= todo - 1;
+            const u32 kk = c0 + src;
+            const u32 key = b.ral_key[kk], blk = b.e_scan1[kk] & 0x3fffffffu;
+            u32 found = NONE, steps = 0;
+            bool over = false;
+            for (u32 top = kk; top > 0; top = top > 64 ? top - 64 : 0) {
+                // lanes look at top-1-lane
+                const bool in = lane < top;
+                const u32 j = in ? top - 1 - lane : 0;
+                const bool same = in && b.ral_key[j] == key;
+                const u32 w = same ? b.e_scan1[j] : 0u;
+                const u64 hit = ballot(same && (w & 0x80000000u) && (w & 0x3fffffffu) == blk);
+                const u64 stop = ballot(in && !same);
+                if (hit) {
+                    const u32 first = (u32)__builtin_ctzll(hit);  // nearest position below
+                    if (!stop || first < (u32)__builtin_ctzll(stop)) found = top - 1 - first;
+                    break;
+                }
+                if (stop || top <= 64) break;
+                if (++steps > WALK_MAX) { over = true; break; }
             }
-        }
-        const bool rel_blk = (f & SF_REL) && (sc & 3u) == 0;
-        const bool acq_blk = (f & SF_ACQ) && ((sc >> 2) & 3u) == 0;
-        const u32 ex = seg_scan_chunk(L, head, rel_blk ? p : NONE, nin);
-        if (m < n) {
-            if (rel_blk) b.e_prev0[p] = ex;
-            if (acq_blk) b.e_src1[p] = rel_blk ? p : ex;
+            if (lane == 0) {
+                if (over) {
+                    atomicOr(&P->eng, ENG_FALLBACK);
+                } else {
+                    const u32 p = b.ral_p[kk];
+                    const uint8_t f = b.s_flags[p], sc = b.s_scope[p];
+                    const bool rel_blk = (f & SF_REL) && (sc & 3u) == 0;
+                    const u32 prev = found == NONE ? NONE : b.ral_p[found];
+                    if (rel_blk) b.e_prev0[p] = prev;
+                    if ((f & SF_ACQ) && ((sc >> 2) & 3u) == 0) b.e_src1[p] = rel_blk ? p : prev;
+                }
+            }
         }
     }
 }
@@ -592,20 +581,7 @@ hipError_t engine_run(const Bufs &b, const u32 *rt_scan, hipStream_t s) {
     scan_exclusive(b.e_scan0, (u64)b.N + 1, b.part, s, gate);
     RD_LAUNCH("k_eng_compact", k_eng_compact, dim3(grid_over(b.N)), dim3(256), 0, s, b);
     RD_LAUNCH("k_eng_chains", k_eng_chains, dim3(1), dim3(1024), 0, s, b);
-    scan_exclusive(b.e_scan1, (u64)b.ecap + 1, b.part, s, gate);
-    RD_LAUNCH("k_eng_blk_items", k_eng_blk_items, dim3(grid_over(b.ecap)), dim3(256), 0, s, b);
-    {
-        u32 bits = 0;
-        while (bits < 32 && ((u64)1 << bits) < (u64)b.B) bits++;
-        const u32 passes_blk = (bits + SORT_RB - 1) / SORT_RB;
-        const u64 max_bl = b.max_pairs < BL_MAX ? b.max_pairs : BL_MAX;
-        u32 *const k[2] = {b.pfirst[0], b.pfirst[1]};
-        u32 *const v[2] = {b.psecond[0], b.psecond[1]};
-        if (passes_blk) sort_kv(b, k, v, &b.prm->n_bl, max_bl, passes_blk, nullptr, "k_eng_sort", s);
-        RD_LAUNCH("k_eng_blk_rekey", k_eng_blk_rekey, dim3(grid_over(max_bl)), dim3(256), 0, s, b, passes_blk & 1u);
-        sort_kv(b, k, v, &b.prm->n_bl, max_bl, 32 / SORT_RB, &b.prm->key_bits, "k_eng_sort", s);
-    }
-    RD_LAUNCH("k_eng_blk_chains", k_eng_blk_chains, dim3(1), dim3(1024), 0, s, b);
+    RD_LAUNCH("k_eng_blk_walk", k_eng_blk_walk, dim3(grid_over(b.ecap, 1024)), dim3(256), 0, s, b);
     // operations and their inputs
     RD_LAUNCH("k_eng_walk", k_eng_walk, dim3(grid_over(b.T)), dim3(256), 0, s, b);
     RD_LAUNCH("k_eng_mark", k_eng_mark, dim3(grid_over(b.N + 1)), dim3(256), 0, s, b);
