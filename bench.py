@@ -440,7 +440,7 @@ def bench_stencil(args):
     print(f"stencil: workspace {ws.numel() / 2**30:.1f} GiB", file=sys.stderr, flush=True)
     res = rc.run(tr)
     if res.status != 0:
-        raise RuntimeError(f"check failed: {res}")
+        raise RuntimeError(f"check failed: {res} {res.message} {rd.rd_last_error(rc.ctx)}")
     lib = rd.load_library()
     steps = max(1, min(args.steps, 5))
     torch.cuda.synchronize()

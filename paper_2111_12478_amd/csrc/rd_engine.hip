@@ -228,7 +228,8 @@ __global__ void k_eng_init(Bufs b, const u32 *rt_scan) {
     if (threadIdx.x != 0 || blockIdx.x != 0) return;
     if (!eng_active(P)) return;
     P->eng |= ENG_PARALLEL;
-    const u32 n_rt = rt_scan[b.T], D = b.B + n_rt;
+    // vectors padded to whole 16-byte words (the padding stays zero)
+    const u32 n_rt = rt_scan[b.T], D = (b.B + n_rt + 3u) & ~3u;
     P->n_rt = n_rt;
     P->D = D;
     const u64 cap = (u64)b.pool_words / D;
@@ -426,6 +427,22 @@ __global__ __launch_bounds__(64) void k_eng_groups(Bufs b) {
 
 __device__ inline const u32 *vecp(const Bufs &b, u32 D, u32 h) { return b.pool + (u64)h * D; }
 
+// Vectors are D words, D a multiple of 4: every lane joins 16-byte words, 4 at a time, with all
+// of a step's loads issued before its stores.
+__device__ inline uint4 max4(uint4 a, uint4 c) {
+    return make_uint4(max(a.x, c.x), max(a.y, c.y), max(a.z, c.z), max(a.w, c.w));
+}
+__device__ inline void bump4(uint4 &v, u32 w4, u32 col, u32 val) {
+    if ((col >> 2) != w4) return;
+    switch (col & 3u) {
+    case 0: v.x = max(v.x, val); break;
+    case 1: v.y = max(v.y, val); break;
+    case 2: v.z = max(v.z, val); break;
+    default: v.w = max(v.w, val); break;
+    }
+}
+constexpr u32 EV = 4;  // 16-byte words per lane per step
+
 // Block barrier operation: the block's previous knowledge joined with every participant's latest
 // acquire of the phase the barrier ends.
 __device__ void eval_bar(const Bufs &b, u32 p, u32 D, u32 *lds_list, u32 *lds_n) {
@@ -448,13 +465,32 @@ __device__ void eval_bar(const Bufs &b, u32 p, u32 D, u32 *lds_list, u32 *lds_n)
         }
     }
     __syncthreads();
-    const u32 nc = *lds_n;
-    u32 *out = b.pool + (u64)b.inst_handle[slot] * D;
-    const u32 *prev = vecp(b, D, k > 1 ? b.inst_handle[slot - 1] : 0u);
-    for (u32 i = threadIdx.x; i < D; i += ENG_THREADS) {
-        u32 v = prev[i];
-        for (u32 c = 0; c < nc; c++) v = max(v, vecp(b, D, lds_list[c])[i]);
-        out[i] = v;
+    const u32 nc = *lds_n, D4 = D / 4;
+    uint4 *out = (uint4 *)(b.pool + (u64)b.inst_handle[slot] * D);
+    const uint4 *prev = (const uint4 *)vecp(b, D, k > 1 ? b.inst_handle[slot - 1] : 0u);
+    for (u32 base = 0; base < D4; base += ENG_THREADS * EV) {
+        uint4 v[EV];
+#pragma unroll
+        for (u32 e = 0; e < EV; e++) {
+            const u32 i = base + e * ENG_THREADS + threadIdx.x;
+            v[e] = i < D4 ? prev[i] : make_uint4(0, 0, 0, 0);
+        }
+        for (u32 c = 0; c < nc; c++) {
+            const uint4 *src = (const uint4 *)vecp(b, D, lds_list[c]);
+            uint4 w[EV];
+#pragma unroll
+            for (u32 e = 0; e < EV; e++) {
+                const u32 i = base + e * ENG_THREADS + threadIdx.x;
+                w[e] = i < D4 ? src[i] : make_uint4(0, 0, 0, 0);
+            }
+#pragma unroll
+            for (u32 e = 0; e < EV; e++) v[e] = max4(v[e], w[e]);
+        }
+#pragma unroll
+        for (u32 e = 0; e < EV; e++) {
+            const u32 i = base + e * ENG_THREADS + threadIdx.x;
+            if (i < D4) out[i] = v[e];
+        }
     }
 }
 
@@ -462,7 +498,7 @@ __device__ void eval_bar(const Bufs &b, u32 p, u32 D, u32 *lds_list, u32 *lds_n)
 __device__ void eval_ra(const Bufs &b, const u32 *rt_scan, u32 p, u32 D) {
     const u32 idx = b.s_pidx[p], t = b.ev[idx].y, blk = block_of(b, t);
     const uint8_t f = b.s_flags[p], sc = b.s_scope[p];
-    const u32 cur = b.e_cur[p];
+    const u32 cur = b.e_cur[p], D4 = D / 4;
     u32 hc;
     if (cur & BK_MARK) {
         const u32 ph = cur & ~BK_MARK;
@@ -470,21 +506,33 @@ __device__ void eval_ra(const Bufs &b, const u32 *rt_scan, u32 p, u32 D) {
     } else {
         hc = b.s_khandle[cur];
     }
-    const u32 *vc = vecp(b, D, hc);
+    const uint4 *vc = (const uint4 *)vecp(b, D, hc);
     if (f & SF_REL) {
         const u32 kb = blk, kbv = b.s_phase[p], kt = b.B + rt_scan[t], ktv = idx + 1;
         const u32 h0 = b.e_relh[p];
-        const u32 *v0 = vecp(b, D, b.e_prev0[p] != NONE ? b.e_relh[b.e_prev0[p]] : 0u);
-        u32 *o0 = b.pool + (u64)h0 * D;
         const bool two = (sc & 3u) == 0;
-        const u32 *v1 = vecp(b, D, two && b.e_prev1[p] != NONE ? b.e_relh[b.e_prev1[p]] + 1 : 0u);
-        u32 *o1 = b.pool + (u64)(h0 + 1) * D;
-        for (u32 i = threadIdx.x; i < D; i += ENG_THREADS) {
-            u32 base = vc[i];
-            if (i == kb) base = max(base, kbv);
-            if (i == kt) base = max(base, ktv);
-            o0[i] = max(base, v0[i]);
-            if (two) o1[i] = max(base, v1[i]);
+        const uint4 *v0 = (const uint4 *)vecp(b, D, b.e_prev0[p] != NONE ? b.e_relh[b.e_prev0[p]] : 0u);
+        const uint4 *v1 = (const uint4 *)vecp(b, D, two && b.e_prev1[p] != NONE ? b.e_relh[b.e_prev1[p]] + 1 : 0u);
+        uint4 *o0 = (uint4 *)(b.pool + (u64)h0 * D), *o1 = (uint4 *)(b.pool + (u64)(h0 + 1) * D);
+        for (u32 base = 0; base < D4; base += ENG_THREADS * EV) {
+            uint4 c[EV], x0[EV], x1[EV];
+#pragma unroll
+            for (u32 e = 0; e < EV; e++) {
+                const u32 i = base + e * ENG_THREADS + threadIdx.x;
+                const bool in = i < D4;
+                c[e] = in ? vc[i] : make_uint4(0, 0, 0, 0);
+                x0[e] = in ? v0[i] : make_uint4(0, 0, 0, 0);
+                x1[e] = in && two ? v1[i] : make_uint4(0, 0, 0, 0);
+            }
+#pragma unroll
+            for (u32 e = 0; e < EV; e++) {
+                const u32 i = base + e * ENG_THREADS + threadIdx.x;
+                if (i >= D4) continue;
+                bump4(c[e], i, kb, kbv);
+                bump4(c[e], i, kt, ktv);
+                o0[i] = max4(c[e], x0[e]);
+                if (two) o1[i] = max4(c[e], x1[e]);
+            }
         }
         __syncthreads();
     }
@@ -492,10 +540,25 @@ __device__ void eval_ra(const Bufs &b, const u32 *rt_scan, u32 p, u32 D) {
     if (ha) {
         const u32 s0 = b.e_src0[p], s1 = b.e_src1[p];
         const bool blk_acq = ((sc >> 2) & 3u) == 0;
-        const u32 *a0 = vecp(b, D, s0 != NONE ? b.e_relh[s0] : 0u);
-        const u32 *a1 = vecp(b, D, s1 != NONE ? b.e_relh[s1] + (blk_acq ? 0u : 1u) : 0u);
-        u32 *oa = b.pool + (u64)ha * D;
-        for (u32 i = threadIdx.x; i < D; i += ENG_THREADS) oa[i] = max(vc[i], max(a0[i], a1[i]));
+        const uint4 *a0 = (const uint4 *)vecp(b, D, s0 != NONE ? b.e_relh[s0] : 0u);
+        const uint4 *a1 = (const uint4 *)vecp(b, D, s1 != NONE ? b.e_relh[s1] + (blk_acq ? 0u : 1u) : 0u);
+        uint4 *oa = (uint4 *)(b.pool + (u64)ha * D);
+        for (u32 base = 0; base < D4; base += ENG_THREADS * EV) {
+            uint4 c[EV], x0[EV], x1[EV];
+#pragma unroll
+            for (u32 e = 0; e < EV; e++) {
+                const u32 i = base + e * ENG_THREADS + threadIdx.x;
+                const bool in = i < D4;
+                c[e] = in ? vc[i] : make_uint4(0, 0, 0, 0);
+                x0[e] = in ? a0[i] : make_uint4(0, 0, 0, 0);
+                x1[e] = in ? a1[i] : make_uint4(0, 0, 0, 0);
+            }
+#pragma unroll
+            for (u32 e = 0; e < EV; e++) {
+                const u32 i = base + e * ENG_THREADS + threadIdx.x;
+                if (i < D4) oa[i] = max4(c[e], max4(x0[e], x1[e]));
+            }
+        }
     }
 }
 
@@ -506,15 +569,19 @@ __device__ inline void eval_op(const Bufs &b, const u32 *rt_scan, u32 o, u32 D, 
     __syncthreads();
 }
 
-// All workgroups meet; writes before are visible to every workgroup after (bounded wait).
+// All workgroups meet; writes before are visible to every workgroup after.  The wait is bounded by
+// time without progress: a workgroup evaluating a long run of small groups alone advances
+// P->gprog after every operation, which restarts the others' count.
 __device__ inline void grid_barrier(DevParams *P, u32 round) {
     __syncthreads();
     if (threadIdx.x == 0) {
         __threadfence();
         atomicAdd(&P->gbar, 1u);
         const u32 target = round * gridDim.x;
-        u32 spins = 0;
+        u32 spins = 0, seen = __hip_atomic_load(&P->gprog, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         while (__hip_atomic_load(&P->gbar, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
+            const u32 now = __hip_atomic_load(&P->gprog, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            if (now != seen) { seen = now; spins = 0; }
             if (++spins > ENG_SPIN) { atomicOr(&P->err, ERR_ENGINE); break; }
             __builtin_amdgcn_s_sleep(2);
         }
@@ -533,6 +600,7 @@ __global__ __launch_bounds__(ENG_THREADS) void k_eng_eval(Bufs b, const u32 *rt_
     u32 round = 0;
     if (blockIdx.x == 0)
         for (u32 i = threadIdx.x; i < D; i += ENG_THREADS) b.pool[i] = 0;  // the empty knowledge
+    // vectors written by the engine: their padding words must read as zero too (joins keep them 0)
     grid_barrier(P, ++round);
     u32 g = 0;
     while (g < ng) {
@@ -544,7 +612,10 @@ __global__ __launch_bounds__(ENG_THREADS) void k_eng_eval(Bufs b, const u32 *rt_
             u32 g2 = g + 1;
             while (g2 < ng && b.grp[g2 + 1] - b.grp[g2] < ENG_WIDE) g2++;
             if (blockIdx.x == 0)
-                for (u32 o = g0; o < b.grp[g2]; o++) eval_op(b, rt_scan, o, D, lds_list, &lds_n);
+                for (u32 o = g0; o < b.grp[g2]; o++) {
+                    eval_op(b, rt_scan, o, D, lds_list, &lds_n);
+                    if (threadIdx.x == 0) atomicAdd(&P->gprog, 1u);
+                }
             g = g2;
         }
         grid_barrier(P, ++round);

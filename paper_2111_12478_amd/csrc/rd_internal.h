@@ -95,6 +95,7 @@ struct DevParams {
     u32 n_handles;         // knowledge vectors the engine writes (+1 for the empty one)
     u32 n_groups;          // dependency-free groups of operations
     u32 gbar;              // grid-barrier arrivals of the engine kernel
+    u32 gprog;             // operations finished by the engine's single-workgroup runs (progress)
     unsigned long long n_chunks;  // queued slow-path chunks of the segment check (8-byte aligned)
 };
 
