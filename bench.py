@@ -450,6 +450,23 @@ def bench_stencil(args):
     torch.cuda.synchronize()
     t2 = time.perf_counter()
     per = (t2 - t1) / steps
+    if args.profile_all:
+        lib.rd_profile_enable.argtypes = [ctypes.c_void_p, ctypes.c_char_p]
+
+        class KT(ctypes.Structure):
+            _fields_ = [("name", ctypes.c_char * 48), ("launches", ctypes.c_uint32), ("total_ms", ctypes.c_double)]
+
+        lib.rd_profile_read.argtypes = [ctypes.c_void_p, ctypes.POINTER(KT), ctypes.c_uint32,
+                                        ctypes.POINTER(ctypes.c_uint32)]
+        lib.rd_profile_enable(rc.ctx, b"*")
+        rc.run(tr)
+        buf = (KT * 96)()
+        cnt = ctypes.c_uint32()
+        lib.rd_profile_read(rc.ctx, buf, 96, ctypes.byref(cnt))
+        lib.rd_profile_enable(rc.ctx, None)
+        rows = sorted(((buf[i].total_ms, buf[i].launches, buf[i].name.decode()) for i in range(cnt.value)), reverse=True)
+        for ms, c, name in rows:
+            print(f"  {name:28s} launches={c:3d} total={ms:8.3f} ms", file=sys.stderr)
     pairs = res.pairs
     missing = _plants_hit(grid, ev, pairs, plants, cfg)
     print(f"stencil: {per * 1e3:.1f} ms/step, {len(pairs)} pairs, plants missing {missing}", file=sys.stderr,

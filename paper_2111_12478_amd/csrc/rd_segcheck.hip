@@ -32,13 +32,14 @@ enum : u32 {
     F_TWA_MULTI = 256u, // two or more threads among the write-ish accesses of the trailing run
     F_TNA_MULTI = 512u, // ... among the plain (non-atomic) accesses
     F_TALL_MULTI = 1024u,
+    F_BLK3 = 2048u,     // three or more blocks in the last segment of the range
     F_CATS = 0xf0u,
 };
 
 struct Agg {
     u32 first_key, last_key;
     u32 run_blk, run_ph;
-    u32 blk;             // a block of the last segment
+    u32 blk, blk2;       // up to two blocks of the last segment (blk2: a second one, or NONE)
     u32 twa, tna, tall;  // a thread of the trailing run: write-ish, plain, any (NONE if none)
     u32 fl;
     u32 first_pos;       // sorted position of the first element of the range
@@ -53,6 +54,13 @@ __device__ inline void set1_merge(u32 &v, u32 &fl, u32 multi_bit, u32 ov, u32 of
     if ((ofl & multi_bit) || (ov != NONE && v != NONE && ov != v)) fl |= multi_bit;
     if (v == NONE) v = ov;
 }
+// a set of up to two members and a "more than two" flag
+__device__ inline void set2_add(u32 &a, u32 &c, u32 &fl, u32 x) {
+    if (x == NONE || x == a || x == c) return;
+    if (a == NONE) a = x;
+    else if (c == NONE) c = x;
+    else fl |= F_BLK3;
+}
 __device__ inline bool set1_has_other(u32 v, u32 fl, u32 multi_bit, u32 x) {
     return (fl & multi_bit) || (v != NONE && v != x);
 }
@@ -60,14 +68,14 @@ __device__ inline bool set1_has_other(u32 v, u32 fl, u32 multi_bit, u32 x) {
 __device__ inline void agg_empty(Agg &a) {
     a.first_key = a.last_key = 0;
     a.run_blk = a.run_ph = 0;
-    a.blk = a.twa = a.tna = a.tall = NONE;
+    a.blk = a.blk2 = a.twa = a.tna = a.tall = NONE;
     a.fl = F_RUNWHOLE;
     a.first_pos = a.seg_pos = a.run_pos = 0;
 }
 __device__ inline void agg_one(Agg &a, u32 key, u32 blk, u32 ph, u32 tid, u32 cat, u32 pos) {
     a.first_pos = a.seg_pos = a.run_pos = pos;
     a.first_key = a.last_key = key;
-    a.run_blk = blk; a.run_ph = ph; a.blk = blk;
+    a.run_blk = blk; a.run_ph = ph; a.blk = blk; a.blk2 = NONE;
     a.tall = tid;
     a.twa = cat != CAT_R ? tid : NONE;
     a.tna = cat <= CAT_W ? tid : NONE;
@@ -82,13 +90,16 @@ __device__ inline void agg_combine(const Agg &l, Agg &r) {
     const bool extend = !boundary && (r.fl & F_RUNWHOLE) && r.run_blk == l.run_blk && r.run_ph == l.run_ph;
     u32 fl = F_NONEMPTY | ((l.fl | r.fl) & F_HEAD) | (keychange ? F_HEAD : 0u);
     if (!boundary) {
-        u32 bfl = (l.fl | r.fl) & F_BLKMULTI;
-        u32 bv = l.blk;
-        set1_merge(bv, bfl, F_BLKMULTI, r.blk, 0);
+        u32 bfl = (l.fl | r.fl) & (F_BLKMULTI | F_BLK3);
+        u32 bv = l.blk, bv2 = l.blk2;
+        set2_add(bv, bv2, bfl, r.blk);
+        set2_add(bv, bv2, bfl, r.blk2);
+        if (bv2 != NONE) bfl |= F_BLKMULTI;
         fl |= bfl | ((l.fl | r.fl) & F_CATS);
         r.blk = bv;
+        r.blk2 = bv2;
     } else {
-        fl |= r.fl & (F_BLKMULTI | F_CATS);
+        fl |= r.fl & (F_BLKMULTI | F_BLK3 | F_CATS);
     }
     if (extend) {
         u32 tfl = (l.fl | r.fl) & (F_TWA_MULTI | F_TNA_MULTI | F_TALL_MULTI);
@@ -112,7 +123,7 @@ __device__ inline void agg_combine(const Agg &l, Agg &r) {
 
 struct SegCtx {
     const u32 *k, *i, *t, *f;
-    u32 *cpos, *clo, *chi;  // slow-path chunks: b's position, and the range [lo, hi) of earlier positions
+    u32 *cpos, *clo, *chi, *cx;  // the queue of slow-path entries (in the sort's free buffers)
     u32 n;
 };
 
@@ -121,7 +132,7 @@ __device__ inline SegCtx seg_ctx(const Bufs &b) {
     const u32 bits = b.prm->key_bits, passes = (bits + b.radix_bits - 1) / b.radix_bits;
     const u32 c = passes & 1;
     SegCtx s; s.k = b.ekey[c]; s.i = b.eidx[c]; s.t = b.etid[c]; s.f = b.einfo[c]; s.n = b.prm->n_acc;
-    s.cpos = b.ekey[c ^ 1]; s.clo = b.etid[c ^ 1]; s.chi = b.einfo[c ^ 1];
+    s.cpos = b.ekey[c ^ 1]; s.clo = b.etid[c ^ 1]; s.chi = b.einfo[c ^ 1]; s.cx = b.eidx[c ^ 1];
     return s;
 }
 
@@ -318,174 +329,382 @@ __device__ inline void wave_slow_check(const Bufs &b, const SegCtx &s, const u32
     }
 }
 
-constexpr u32 SLOW_CAP = 512;  // slow items listed per workgroup before falling back to wave scans
+// How an access b is checked against the earlier accesses of its segment.
+enum : u32 {
+    SLOW_NONE = 0,  // no earlier access can race with b
+    SLOW_RUN = 1,   // only b's run (same block and phase) can: chunks over the run
+    SLOW_SEG = 2,   // three or more blocks before b: chunks over the whole segment prefix
+    SLOW_WALK = 3,  // one or two blocks before b: a backward walk that stops early
+};
 
-struct CheckLds {
+// P: summary of everything before b (b's own segment when P.last_key == key).
+__device__ inline u32 decide(const Agg &P, u32 key, u32 tid, u32 blk, u32 ph, u32 cat) {
+    if (!(P.fl & F_NONEMPTY) || P.last_key != key) return SLOW_NONE;
+    if (!(P.fl & F_BLKMULTI) && P.blk == blk) {
+        // every earlier access is in b's block: only b's run is unordered with b
+        if (P.run_blk != blk || P.run_ph != ph) return SLOW_NONE;
+        bool slow;
+        if (cat == CAT_R) slow = set1_has_other(P.twa, P.fl, F_TWA_MULTI, tid);
+        else if (cat == CAT_W) slow = set1_has_other(P.tall, P.fl, F_TALL_MULTI, tid);
+        else slow = set1_has_other(P.tna, P.fl, F_TNA_MULTI, tid);
+        return slow ? SLOW_RUN : SLOW_NONE;
+    }
+    if (!(P.fl & conflict_cats(cat))) return SLOW_NONE;
+    return (P.fl & F_BLK3) ? SLOW_SEG : SLOW_WALK;
+}
+
+// Queue entries, one wavefront each.  Chunk (pos, lo, hi): check b at pos against positions
+// [lo, hi).  Walk (pos, below, WALK, nb): the backward walk of b at pos over a prefix with nb
+// blocks, reporting pairs at positions below `below` only (the positions above were walked by a
+// lane of the check kernel).
+constexpr u32 WALK = 0xffffffffu;
+constexpr u32 LANE_WALK_CAP = 32;  // positions a lane walks before handing the walk to a wavefront
+
+// Pairs found by one wavefront, gathered in LDS and appended with one device atomic per flush.
+constexpr u32 WAVE_PAIRS = 512;
+
+struct WavePairs {
+    u32 *pf, *ps;
+    u32 fill;  // the same in every lane
+};
+
+__device__ inline void wp_flush(const Bufs &b, WavePairs &w) {
+    if (!w.fill) return;
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    u32 g = 0;
+    if (lane_id() == 0) g = atomicAdd(&b.prm->n_pairs, w.fill);
+    g = __shfl(g, 0, 64);
+    for (u32 k = lane_id(); k < w.fill; k += 64) {
+        const u32 slot = g + k;
+        if (slot < b.max_pairs) { b.pfirst[0][slot] = w.pf[k]; b.psecond[0][slot] = w.ps[k]; }
+        else atomicOr(&b.prm->err, ERR_PAIRS);
+    }
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    w.fill = 0;
+}
+
+// Every lane of the wavefront calls this.
+__device__ inline void wp_add(const Bufs &b, WavePairs &w, bool want, u32 first, u32 second) {
+    const u64 m = ballot(want);
+    if (!m) return;
+    if (w.fill + popc64(m) > WAVE_PAIRS) wp_flush(b, w);
+    if (want) {
+        const u32 o = w.fill + popc64(m & lanemask_lt());
+        w.pf[o] = first;
+        w.ps[o] = second;
+    }
+    w.fill += popc64(m);
+}
+
+// The access b at sorted position pos, for the walks.
+struct Walker {
+    u32 pos, key, btid, bidx, bblk, bph, bcat;
+    u32 h;          // knowledge handle of b's thread at b (0: none)
+    const u32 *V;   // its vector, or null
+};
+
+__device__ inline Walker walker_at(const Bufs &b, const SegCtx &s, u32 pos) {
+    Walker w;
+    w.pos = pos;
+    w.key = s.k[pos];
+    w.btid = s.t[pos];
+    w.bidx = s.i[pos];
+    const u32 info = s.f[pos];
+    w.bblk = block_of(b, w.btid);
+    w.bph = info_phase(info);
+    w.bcat = info_cat(info);
+    w.h = 0;
+    if (b.prm->mode & MODE_SYNC) {
+        const u32 j = list_search(b, w.btid, w.bidx);
+        w.h = j == NONE ? 0u : b.s_know[j];
+    }
+    w.V = w.h ? b.pool + (u64)w.h * b.prm->D : nullptr;
+    return w;
+}
+
+// The walks rest on one fact: the accesses of one block to one location appear in trace order with
+// non-decreasing phase, because a valid trace completes every arrival at a barrier instance before
+// any event after that instance (Section 5).  So once a backward walk meets an access of block X
+// that happens before b through a barrier or through b's block knowledge -- X is b's block and
+// the phase is lower, or b's thread knows a later phase of X -- every earlier access of X happens
+// before b as well: X is settled.  The walk ends when all nb blocks of the prefix are settled.
+__device__ inline bool settles(const Walker &w, u32 ba, u32 pha) {
+    return ba == w.bblk ? pha < w.bph : (w.V != nullptr && w.V[ba] > pha);
+}
+
+// Is a (thread ta, block ba, phase pha, category ca, sorted position q) a race with b?
+__device__ inline bool walk_race(const Bufs &b, const SegCtx &s, const u32 *rt_scan, const Walker &w, u32 q,
+                                 u32 ta, u32 ba, u32 pha, u32 ca, u32 &ia) {
+    if (ta == w.btid || !conflicts(ca, ba, w.bcat, w.bblk)) return false;
+    ia = s.i[q];
+    u32 h = w.h;
+    return !happens_before(b, rt_scan, w.bidx, w.btid, w.bblk, w.bph, h, ta, ba, pha, ia);
+}
+
+// The walk with a whole wavefront, 64 positions per step.  The blocks of the prefix are learnt on
+// the way (x1 first, x2 the other one).
+__device__ inline void wave_walk(const Bufs &b, const SegCtx &s, const u32 *rt_scan, u32 pos, u32 below, u32 nb,
+                                 WavePairs &wp) {
+    const u32 lane = lane_id();
+    const Walker w = walker_at(b, s, pos);
+    u32 x1 = NONE, x2 = NONE;
+    bool d1 = false, d2 = false;
+    for (u32 top = pos; top > 0; top = top > 64 ? top - 64 : 0) {
+        const bool valid = lane < top;
+        const u32 q = valid ? top - 1 - lane : 0;
+        bool stop = !valid;
+        u32 ta = 0, info = 0, ba = NONE, pha = 0;
+        if (valid) {
+            stop = s.k[q] != w.key;
+            if (!stop) {
+                ta = s.t[q];
+                info = s.f[q];
+                ba = block_of(b, ta);
+                pha = info_phase(info);
+            }
+        }
+        const u64 sm = ballot(stop);
+        const u32 first_stop = sm ? (u32)__builtin_ctzll(sm) : 64u;
+        const bool in = lane < first_stop;
+        // name the (at most two) blocks
+        if (x1 == NONE && first_stop > 0) x1 = __shfl(ba, 0, 64);
+        if (x2 == NONE) {
+            const u64 o = ballot(in && ba != x1);
+            if (o) x2 = __shfl(ba, (int)__builtin_ctzll(o), 64);
+        }
+        const bool st = in && settles(w, ba, pha);
+        const u64 m1 = ballot(st && ba == x1), m2 = ballot(st && ba == x2);
+        // lanes past the point where every block is settled hold settled accesses only
+        const u32 e1 = d1 ? 0u : (m1 ? (u32)__builtin_ctzll(m1) : 64u);
+        const u32 e2 = nb < 2 || d2 ? 0u : (m2 ? (u32)__builtin_ctzll(m2) : 64u);
+        const u32 lim = min(first_stop, max(e1, e2) + 1);
+        bool want = false;
+        u32 ia = 0;
+        if (lane < lim && q < below) want = walk_race(b, s, rt_scan, w, q, ta, ba, pha, info_cat(info), ia);
+        wp_add(b, wp, want, ia, w.bidx);
+        d1 = d1 || m1 != 0;
+        d2 = d2 || m2 != 0;
+        if (sm || (d1 && (nb < 2 || d2))) break;
+    }
+}
+
+// Block-wide (256 threads) exclusive scan of one u64 per thread; *total gets the sum.
+__device__ inline u64 block_exscan_u64(u64 v, u64 *wsum /* WAVES */, u64 &total) {
+    const u32 lane = lane_id(), w = threadIdx.x >> 6;
+    u64 incl = v;
+    for (u32 d = 1; d < 64; d <<= 1) {
+        const u64 o = __shfl_up(incl, d, 64);
+        if (lane >= d) incl += o;
+    }
+    if (lane == 63) wsum[w] = incl;
+    __syncthreads();
+    u64 off = 0;
+    total = 0;
+    for (u32 k = 0; k < (u32)WAVES; k++) {
+        const u64 x = wsum[k];
+        if (k < w) off += x;
+        total += x;
+    }
+    return off + incl - v;
+}
+
+// Queues one entry; false when the queue is full.
+__device__ inline bool queue_push(const Bufs &b, const SegCtx &s, u32 pos, u32 lo, u32 hi, u32 x) {
+    const u64 c = atomicAdd(&b.prm->n_chunks, 1ull);
+    if (c >= s.n) return false;
+    s.cpos[c] = pos; s.clo[c] = lo; s.chi[c] = hi; s.cx[c] = x;
+    return true;
+}
+
+union CheckLds {
     Agg buf[2 * WG_THREADS];
-    u32 item_pos[SLOW_CAP], item_start[SLOW_CAP], item_off[SLOW_CAP];
-    u32 n_items, n_chunks, overflow, base;
+    struct { u32 pf[WAVES][WAVE_PAIRS], ps[WAVES][WAVE_PAIRS]; } pairs;
 };
 
 __global__ __launch_bounds__(WG_THREADS) void k_seg_check(Bufs b, const u32 *rt_scan) {
     __shared__ CheckLds L;
+    __shared__ u64 wsum[WAVES];
+    __shared__ u64 qbase;
     const SegCtx s = seg_ctx(b);
     const Agg *tile_agg = (const Agg *)b.tile_agg;
     const u64 tile0 = (u64)blockIdx.x * TILE;
     if (tile0 >= s.n) return;
-    if (threadIdx.x == 0) { L.n_items = 0; L.n_chunks = 0; L.overflow = 0; }
     const u64 base = tile0 + (u64)threadIdx.x * ITEMS;
+    const u32 lane = lane_id(), wv = threadIdx.x >> 6;
     Items it;
     load_items(s, base, it);
     const u32 cnt = items_in(s, base);
-    Agg P;
-    items_agg(b, it, cnt, (u32)base, P);
-    block_exscan_agg(P, L.buf, nullptr);  // (its barriers also publish the counters above)
+    Agg P0;
+    items_agg(b, it, cnt, (u32)base, P0);
+    block_exscan_agg(P0, L.buf, nullptr);
     {
         Agg T = tile_agg[blockIdx.x];  // everything before this tile
-        agg_combine(T, P);             // P := T (+) P
+        agg_combine(T, P0);            // P0 := T (+) P0: everything before this thread's items
     }
-    // decisions in O(1) per item; an item that needs the exact check is listed with the range
-    // [start, pos) of earlier positions it must be checked against
+    // pass 1: decisions in O(1) per item; chunks needed by run and many-block items
+    u64 need = 0;
+    u32 chunk_bits = 0, run_bits = 0, walk_bits = 0, two_bits = 0;
+    {
+        Agg P = P0;
 #pragma unroll
-    for (int q = 0; q < ITEMS; q++) {
-        if ((u32)q >= cnt) continue;
-        const u32 key = it.key[q], tid = it.tid[q], info = it.info[q];
-        const u32 cat = info_cat(info), ph = info_phase(info), blk = block_of(b, tid);
-        if ((P.fl & F_NONEMPTY) && P.last_key == key) {
-            const bool single = !(P.fl & F_BLKMULTI) && P.blk == blk;
-            bool slow = false, group = false;
-            if (single) {
-                if (P.run_blk == blk && P.run_ph == ph) {
-                    if (cat == CAT_R) slow = set1_has_other(P.twa, P.fl, F_TWA_MULTI, tid);
-                    else if (cat == CAT_W) slow = set1_has_other(P.tall, P.fl, F_TALL_MULTI, tid);
-                    else slow = set1_has_other(P.tna, P.fl, F_TNA_MULTI, tid);
-                    group = true;
-                }
-            } else {
-                slow = (P.fl & conflict_cats(cat)) != 0;
+        for (int q = 0; q < ITEMS; q++) {
+            if ((u32)q >= cnt) continue;
+            const u32 key = it.key[q], tid = it.tid[q], info = it.info[q];
+            const u32 cat = info_cat(info), ph = info_phase(info), blk = block_of(b, tid);
+            const u32 mode = decide(P, key, tid, blk, ph, cat);
+            const u32 pos = (u32)(base + q);
+            if (mode == SLOW_WALK) {
+                walk_bits |= 1u << q;
+                if (P.fl & F_BLKMULTI) two_bits |= 1u << q;
+            } else if (mode != SLOW_NONE) {
+                need += (pos - (mode == SLOW_RUN ? P.run_pos : P.seg_pos) + 63) / 64;
+                chunk_bits |= 1u << q;
+                if (mode == SLOW_RUN) run_bits |= 1u << q;
             }
-            if (slow) {
-                const u32 pos = (u32)(base + q), start = group ? P.run_pos : P.seg_pos;
-                const u32 k = atomicAdd(&L.n_items, 1u);
-                if (k < SLOW_CAP) {
-                    L.item_pos[k] = pos;
-                    L.item_start[k] = start;
-                    L.item_off[k] = atomicAdd(&L.n_chunks, (pos - start + 63) / 64);
-                } else {
-                    L.overflow = 1;
-                }
-            }
+            Agg one;
+            agg_one(one, key, blk, ph, tid, cat, pos);
+            agg_combine(P, one);
+            P = one;
         }
-        Agg one;
-        agg_one(one, key, blk, ph, tid, cat, (u32)(base + q));
-        agg_combine(P, one);
-        P = one;
     }
-    __syncthreads();
-    const u32 n_items = min(L.n_items, SLOW_CAP);
-    if (!n_items && !L.overflow) return;
+    u64 total;
+    const u64 off = block_exscan_u64(need, wsum, total);
+    const bool any_walk = __syncthreads_or(walk_bits != 0);  // (also ends the use of L.buf)
+    if (!total && !any_walk) return;
     if (threadIdx.x == 0) {
-        L.base = NONE;
-        if (!L.overflow && L.n_chunks) {
-            const u64 c0 = atomicAdd(&b.prm->n_chunks, (unsigned long long)L.n_chunks);
-            if (c0 + L.n_chunks <= s.n) L.base = (u32)c0;
+        qbase = ~0ull;
+        if (total) {
+            const u64 c0 = atomicAdd(&b.prm->n_chunks, (unsigned long long)total);
+            if (c0 + total <= s.n) qbase = c0;
             else {
                 // no room: neutralise the reserved slots below the capacity (the chunk kernel reads
-                // min(counter, capacity) slots) and scan here
-                for (u64 c = c0; c < c0 + L.n_chunks && c < s.n; c++) { s.cpos[c] = 0; s.clo[c] = 0; s.chi[c] = 0; }
+                // min(counter, capacity) slots) and check this tile's chunk items here
+                for (u64 c = c0; c < c0 + total && c < s.n; c++) { s.cpos[c] = 0; s.clo[c] = 0; s.chi[c] = 0; }
             }
         }
     }
     __syncthreads();
-    if (L.base != NONE) {
-        // queue every listed item as chunks of 64 earlier positions
-        for (u32 k = threadIdx.x; k < n_items; k += WG_THREADS) {
-            const u32 pos = L.item_pos[k], start = L.item_start[k], c0 = L.base + L.item_off[k];
-            for (u32 c = 0; start + 64 * c < pos; c++) {
-                s.cpos[c0 + c] = pos;
-                s.clo[c0 + c] = start + 64 * c;
-                s.chi[c0 + c] = min(start + 64 * (c + 1), pos);
+    if (qbase != ~0ull) {
+        // pass 2: the same decisions, chunks written to the queue at this thread's offset
+        u64 e = qbase + off;
+        Agg P = P0;
+#pragma unroll
+        for (int q = 0; q < ITEMS; q++) {
+            if ((u32)q >= cnt) continue;
+            const u32 key = it.key[q], tid = it.tid[q], info = it.info[q];
+            const u32 cat = info_cat(info), ph = info_phase(info), blk = block_of(b, tid);
+            const u32 pos = (u32)(base + q);
+            if (chunk_bits & (1u << q)) {
+                const u32 start = (run_bits & (1u << q)) ? P.run_pos : P.seg_pos;
+                for (u32 lo = start; lo < pos; lo += 64, e++) {
+                    s.cpos[e] = pos; s.clo[e] = lo; s.chi[e] = min(lo + 64, pos);
+                }
+            }
+            Agg one;
+            agg_one(one, key, blk, ph, tid, cat, pos);
+            agg_combine(P, one);
+            P = one;
+        }
+        chunk_bits = 0;
+    }
+    WavePairs wp;
+    wp.pf = L.pairs.pf[wv];
+    wp.ps = L.pairs.ps[wv];
+    wp.fill = 0;
+    // queue full: each wavefront checks its lanes' chunk items by exact scans, of the run or of the
+    // whole segment prefix
+    for (u32 q = 0; q < (u32)ITEMS; q++) {
+        u64 m = ballot((chunk_bits >> q) & 1u);
+        const u64 mr = ballot((run_bits >> q) & 1u);
+        while (m) {
+            const u32 l = (u32)__builtin_ctzll(m);
+            m &= m - 1;
+            const u32 pos = (u32)(tile0 + (u64)(wv * 64 + l) * ITEMS + q);
+            const u32 tid = s.t[pos], info = s.f[pos];
+            wave_slow_check(b, s, rt_scan, pos, s.k[pos], tid, block_of(b, tid), info_phase(info), info_cat(info),
+                            (mr >> l) & 1u);
+        }
+    }
+    // the walks, one per lane at a time: a lane takes its next walk item when its walk ends
+    u32 todo = walk_bits;
+    bool act = false;
+    Walker w = {};
+    u32 nb = 1, x1 = NONE, top = 0, steps = 0;
+    bool d1 = false, d2 = false;
+    while (true) {
+        if (!act && todo) {
+            const u32 q = (u32)__builtin_ctz(todo);
+            todo &= todo - 1;
+            w = walker_at(b, s, (u32)(base + q));
+            nb = (two_bits >> q) & 1u ? 2u : 1u;
+            x1 = NONE; d1 = d2 = false;
+            top = w.pos;
+            steps = 0;
+            act = true;
+        }
+        if (!ballot(act)) break;
+        bool want = false;
+        u32 ia = 0;
+        if (act) {
+            const u32 q = top - 1;
+            if (top == 0 || s.k[q] != w.key) {
+                act = false;
+            } else {
+                const u32 ta = s.t[q], info = s.f[q];
+                const u32 ba = block_of(b, ta), pha = info_phase(info);
+                if (x1 == NONE) x1 = ba;
+                want = walk_race(b, s, rt_scan, w, q, ta, ba, pha, info_cat(info), ia);
+                if (settles(w, ba, pha)) {
+                    if (ba == x1) d1 = true;
+                    else d2 = true;
+                }
+                top = q;
+                if (d1 && (nb < 2 || d2)) act = false;
+                else if (++steps == LANE_WALK_CAP && queue_push(b, s, w.pos, top, WALK, nb)) act = false;
             }
         }
-        return;
+        wp_add(b, wp, want, ia, w.bidx);
     }
-    // fallback (item list or chunk buffer full): the wavefronts check the items themselves; with an
-    // overflowing list, every item of the tile is re-decided by a full scan of its segment prefix
-    const u32 w = threadIdx.x >> 6;
-    if (!L.overflow) {
-        for (u32 k = w; k < n_items; k += WAVES) {
-            const u32 pos = L.item_pos[k], tid = s.t[pos], info = s.f[pos];
-            const bool group_only = false;  // scanning the whole prefix is exact, only slower
-            wave_slow_check(b, s, rt_scan, pos, s.k[pos], tid, block_of(b, tid), info_phase(info), info_cat(info),
-                            group_only);
-        }
-    } else {
-        for (u32 k = w; k < TILE; k += WAVES) {
-            const u64 pos = tile0 + k;
-            if (pos >= s.n) break;
-            const u32 tid = s.t[pos], info = s.f[pos];
-            wave_slow_check(b, s, rt_scan, (u32)pos, s.k[pos], tid, block_of(b, tid), info_phase(info),
-                            info_cat(info), false);
-        }
-    }
+    wp_flush(b, wp);
 }
 
-// One wavefront per queued chunk: lane l checks position lo + l against b.  Pairs are gathered in
-// LDS and appended with one device atomic per flush of the workgroup.
-constexpr u32 PAIR_LDS = 2048;
-
+// One wavefront per queued entry.
 __global__ __launch_bounds__(WG_THREADS) void k_seg_slow(Bufs b, const u32 *rt_scan) {
-    __shared__ u32 pf[PAIR_LDS], ps[PAIR_LDS];
-    __shared__ u32 fill, gbase;
+    __shared__ u32 pf[WAVES][WAVE_PAIRS], ps[WAVES][WAVE_PAIRS];
     const SegCtx s = seg_ctx(b);
     const u32 n_chunks = (u32)min(b.prm->n_chunks, (unsigned long long)s.n);
     const u32 lane = lane_id(), w = threadIdx.x >> 6;
-    if (threadIdx.x == 0) fill = 0;
-    __syncthreads();
+    WavePairs wp;
+    wp.pf = pf[w];
+    wp.ps = ps[w];
+    wp.fill = 0;
     const u32 stride = gridDim.x * WAVES;
-    for (u32 c0 = blockIdx.x * WAVES; c0 < n_chunks; c0 += stride) {
-        const u32 c = c0 + w;
+    for (u32 c = blockIdx.x * WAVES + w; c < n_chunks; c += stride) {
+        const u32 pos = s.cpos[c], lo = s.clo[c], hi = s.chi[c];
+        if (hi == WALK) {
+            wave_walk(b, s, rt_scan, pos, lo, s.cx[c], wp);
+            continue;
+        }
         bool want = false;
         u32 ia = 0, bidx = 0;
-        if (c < n_chunks) {
-            const u32 pos = s.cpos[c], lo = s.clo[c], hi = s.chi[c];
-            const u32 q = lo + lane;
-            if (q < hi) {
-                const u32 btid = s.t[pos], binfo = s.f[pos];
-                const u32 bblk = block_of(b, btid), bph = info_phase(binfo), bcat = info_cat(binfo);
-                const u32 ta = s.t[q], info = s.f[q];
-                const u32 ba = block_of(b, ta), pha = info_phase(info);
-                if (ta != btid && conflicts(info_cat(info), ba, bcat, bblk)) {
-                    u32 h = NONE;
-                    ia = s.i[q];
-                    bidx = s.i[pos];
-                    want = !happens_before(b, rt_scan, bidx, btid, bblk, bph, h, ta, ba, pha, ia);
-                }
+        const u32 q = lo + lane;
+        if (q < hi) {
+            const u32 btid = s.t[pos], binfo = s.f[pos];
+            const u32 bblk = block_of(b, btid), bph = info_phase(binfo), bcat = info_cat(binfo);
+            const u32 ta = s.t[q], info = s.f[q];
+            const u32 ba = block_of(b, ta), pha = info_phase(info);
+            if (ta != btid && conflicts(info_cat(info), ba, bcat, bblk)) {
+                u32 h = NONE;
+                ia = s.i[q];
+                bidx = s.i[pos];
+                want = !happens_before(b, rt_scan, bidx, btid, bblk, bph, h, ta, ba, pha, ia);
             }
         }
-        const u64 m = ballot(want);
-        if (m) {
-            u32 off = 0;
-            const u32 leader = (u32)__builtin_ctzll(m);
-            if (lane == leader) off = atomicAdd(&fill, popc64(m));
-            off = __shfl(off, leader, 64) + popc64(m & lanemask_lt());
-            if (want) { pf[off] = ia; ps[off] = bidx; }
-        }
-        __syncthreads();
-        if (fill > PAIR_LDS - WG_THREADS || c0 + stride >= n_chunks) {
-            // flush
-            if (threadIdx.x == 0) gbase = fill ? atomicAdd(&b.prm->n_pairs, fill) : 0;
-            __syncthreads();
-            for (u32 k = threadIdx.x; k < fill; k += WG_THREADS) {
-                const u32 slot = gbase + k;
-                if (slot < b.max_pairs) { b.pfirst[0][slot] = pf[k]; b.psecond[0][slot] = ps[k]; }
-                else atomicOr(&b.prm->err, ERR_PAIRS);
-            }
-            __syncthreads();
-            if (threadIdx.x == 0) fill = 0;
-            __syncthreads();
-        }
+        wp_add(b, wp, want, ia, bidx);
     }
+    wp_flush(b, wp);
 }
 
 __global__ void k_pairs_kept(Bufs b) {

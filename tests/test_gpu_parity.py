@@ -118,6 +118,21 @@ def test_one_hot_location_ragged(rc):
         np.testing.assert_array_equal(got.pairs, want.pairs)
 
 
+def test_one_hot_location_many_blocks(rc):
+    # one word touched by four blocks: every access is checked against its whole prefix, and the
+    # n^2/128 chunks of that check overflow the chunk queue (capacity n)
+    for n in (4097, 9001):
+        rng = np.random.default_rng(n + 1)
+        ev = np.zeros((n, 4), np.uint32)
+        ev[:, 0] = 9
+        ev[:, 1] = rng.integers(0, 64, n)
+        ev[:, 2] = np.where(rng.random(n) < 0.01, make_meta(KIND["W"]), make_meta(KIND["R"]))
+        want = oracle.check((4, 16), ev)
+        got = rc.check((4, 16), ev, limits={"max_pairs": 1 << 25})
+        assert got.status == 0, got
+        np.testing.assert_array_equal(got.pairs, want.pairs)
+
+
 def test_pair_buffer_overflow_is_reported(rc):
     # 64 threads of one block each write one word: C(64, 2) = 2016 pairs, buffer of 1000
     ev = np.array([(3, t, make_meta(KIND["W"]), 0) for t in range(64)], np.uint32)
