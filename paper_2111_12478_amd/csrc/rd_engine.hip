@@ -443,9 +443,23 @@ __device__ inline void bump4(uint4 &v, u32 w4, u32 col, u32 val) {
 }
 constexpr u32 EV = 4;  // 16-byte words per lane per step
 
+// Inside a window of operations (a run of small dependent groups), inputs with handles at or
+// above `hint` are written by earlier operations of the same window.  The first phase joins the
+// other inputs into the outputs (partial results) and describes the rest in the operation's job:
+// three output slots (out, in0, in1, in2) and, for a barrier, a range of the window input list.
+// The second phase joins those.  Wide groups pass hint = NONE and no job.
+struct JobSink {
+    u32 *job;     // ENG_JOB_WORDS words, or null
+    u32 *list;    // ENG_WIN words
+    u32 *list_n;  // entries used
+};
+
+__device__ inline u32 ext(u32 h, u32 hint) { return h >= hint ? 0u : h; }
+__device__ inline u32 inn(u32 h, u32 hint) { return h >= hint ? h : 0u; }
+
 // Block barrier operation: the block's previous knowledge joined with every participant's latest
 // acquire of the phase the barrier ends.
-__device__ void eval_bar(const Bufs &b, u32 p, u32 D, u32 *lds_list, u32 *lds_n) {
+__device__ void eval_bar(const Bufs &b, u32 p, u32 D, u32 *lds_list, u32 *lds_n, u32 hint, JobSink js) {
     const u32 idx = b.s_pidx[p], blk = block_of(b, b.ev[idx].y), k = b.s_phase[p];
     const u32 slot = b.inst_off[blk] + k - 1;
     if (threadIdx.x == 0) *lds_n = 0;
@@ -466,8 +480,9 @@ __device__ void eval_bar(const Bufs &b, u32 p, u32 D, u32 *lds_list, u32 *lds_n)
     }
     __syncthreads();
     const u32 nc = *lds_n, D4 = D / 4;
-    uint4 *out = (uint4 *)(b.pool + (u64)b.inst_handle[slot] * D);
-    const uint4 *prev = (const uint4 *)vecp(b, D, k > 1 ? b.inst_handle[slot - 1] : 0u);
+    const u32 hout = b.inst_handle[slot], hprev = k > 1 ? b.inst_handle[slot - 1] : 0u;
+    uint4 *out = (uint4 *)(b.pool + (u64)hout * D);
+    const uint4 *prev = (const uint4 *)vecp(b, D, ext(hprev, hint));
     for (u32 base = 0; base < D4; base += ENG_THREADS * EV) {
         uint4 v[EV];
 #pragma unroll
@@ -476,7 +491,9 @@ __device__ void eval_bar(const Bufs &b, u32 p, u32 D, u32 *lds_list, u32 *lds_n)
             v[e] = i < D4 ? prev[i] : make_uint4(0, 0, 0, 0);
         }
         for (u32 c = 0; c < nc; c++) {
-            const uint4 *src = (const uint4 *)vecp(b, D, lds_list[c]);
+            const u32 h = lds_list[c];
+            if (h >= hint) continue;
+            const uint4 *src = (const uint4 *)vecp(b, D, h);
             uint4 w[EV];
 #pragma unroll
             for (u32 e = 0; e < EV; e++) {
@@ -492,10 +509,26 @@ __device__ void eval_bar(const Bufs &b, u32 p, u32 D, u32 *lds_list, u32 *lds_n)
             if (i < D4) out[i] = v[e];
         }
     }
+    if (js.job && threadIdx.x == 0) {
+        u32 n_in = 0;
+        for (u32 c = 0; c < nc; c++) n_in += lds_list[c] >= hint;
+        // each acquire of the window feeds at most one barrier: the list never holds more than
+        // the window's operations
+        const u32 off = n_in ? atomicAdd(js.list_n, n_in) : 0u;
+        if (off + n_in > ENG_WIN) atomicOr(&b.prm->err, ERR_ENGINE);
+        else
+            for (u32 c = 0, m = 0; c < nc; c++)
+                if (lds_list[c] >= hint) js.list[off + m++] = lds_list[c];
+        uint4 *J = (uint4 *)js.job;
+        J[0] = make_uint4(hout, inn(hprev, hint), 0, 0);
+        J[1] = make_uint4(0, 0, 0, 0);
+        J[2] = make_uint4(0, 0, 0, 0);
+        J[3] = make_uint4(off, off + n_in > ENG_WIN ? 0u : n_in, 0, 0);
+    }
 }
 
 // Release and / or acquire of one sync entry (release first).
-__device__ void eval_ra(const Bufs &b, const u32 *rt_scan, u32 p, u32 D) {
+__device__ void eval_ra(const Bufs &b, const u32 *rt_scan, u32 p, u32 D, u32 hint, JobSink js) {
     const u32 idx = b.s_pidx[p], t = b.ev[idx].y, blk = block_of(b, t);
     const uint8_t f = b.s_flags[p], sc = b.s_scope[p];
     const u32 cur = b.e_cur[p], D4 = D / 4;
@@ -506,13 +539,16 @@ __device__ void eval_ra(const Bufs &b, const u32 *rt_scan, u32 p, u32 D) {
     } else {
         hc = b.s_khandle[cur];
     }
-    const uint4 *vc = (const uint4 *)vecp(b, D, hc);
+    const uint4 *vc = (const uint4 *)vecp(b, D, ext(hc, hint));
+    uint4 j0 = make_uint4(0, 0, 0, 0), j1 = j0, j2 = j0;
     if (f & SF_REL) {
         const u32 kb = blk, kbv = b.s_phase[p], kt = b.B + rt_scan[t], ktv = idx + 1;
         const u32 h0 = b.e_relh[p];
         const bool two = (sc & 3u) == 0;
-        const uint4 *v0 = (const uint4 *)vecp(b, D, b.e_prev0[p] != NONE ? b.e_relh[b.e_prev0[p]] : 0u);
-        const uint4 *v1 = (const uint4 *)vecp(b, D, two && b.e_prev1[p] != NONE ? b.e_relh[b.e_prev1[p]] + 1 : 0u);
+        const u32 hv0 = b.e_prev0[p] != NONE ? b.e_relh[b.e_prev0[p]] : 0u;
+        const u32 hv1 = two && b.e_prev1[p] != NONE ? b.e_relh[b.e_prev1[p]] + 1 : 0u;
+        const uint4 *v0 = (const uint4 *)vecp(b, D, ext(hv0, hint));
+        const uint4 *v1 = (const uint4 *)vecp(b, D, ext(hv1, hint));
         uint4 *o0 = (uint4 *)(b.pool + (u64)h0 * D), *o1 = (uint4 *)(b.pool + (u64)(h0 + 1) * D);
         for (u32 base = 0; base < D4; base += ENG_THREADS * EV) {
             uint4 c[EV], x0[EV], x1[EV];
@@ -534,14 +570,18 @@ __device__ void eval_ra(const Bufs &b, const u32 *rt_scan, u32 p, u32 D) {
                 if (two) o1[i] = max4(c[e], x1[e]);
             }
         }
-        __syncthreads();
+        j0 = make_uint4(h0, inn(hc, hint), inn(hv0, hint), 0);
+        if (two) j1 = make_uint4(h0 + 1, inn(hc, hint), inn(hv1, hint), 0);
+        __syncthreads();  // an atomic's acquire may read its own release
     }
     const u32 ha = (f & SF_ACQ) ? b.s_khandle[p] : 0u;
     if (ha) {
         const u32 s0 = b.e_src0[p], s1 = b.e_src1[p];
         const bool blk_acq = ((sc >> 2) & 3u) == 0;
-        const uint4 *a0 = (const uint4 *)vecp(b, D, s0 != NONE ? b.e_relh[s0] : 0u);
-        const uint4 *a1 = (const uint4 *)vecp(b, D, s1 != NONE ? b.e_relh[s1] + (blk_acq ? 0u : 1u) : 0u);
+        const u32 ha0 = s0 != NONE ? b.e_relh[s0] : 0u;
+        const u32 ha1 = s1 != NONE ? b.e_relh[s1] + (blk_acq ? 0u : 1u) : 0u;
+        const uint4 *a0 = (const uint4 *)vecp(b, D, ext(ha0, hint));
+        const uint4 *a1 = (const uint4 *)vecp(b, D, ext(ha1, hint));
         uint4 *oa = (uint4 *)(b.pool + (u64)ha * D);
         for (u32 base = 0; base < D4; base += ENG_THREADS * EV) {
             uint4 c[EV], x0[EV], x1[EV];
@@ -559,19 +599,128 @@ __device__ void eval_ra(const Bufs &b, const u32 *rt_scan, u32 p, u32 D) {
                 if (i < D4) oa[i] = max4(c[e], max4(x0[e], x1[e]));
             }
         }
+        j2 = make_uint4(ha, inn(hc, hint), inn(ha0, hint), inn(ha1, hint));
+    }
+    if (js.job && threadIdx.x == 0) {
+        uint4 *J = (uint4 *)js.job;
+        J[0] = j0;
+        J[1] = j1;
+        J[2] = j2;
+        J[3] = make_uint4(0, 0, 0, 0);
     }
 }
 
-__device__ inline void eval_op(const Bufs &b, const u32 *rt_scan, u32 o, u32 D, u32 *lds_list, u32 *lds_n) {
+__device__ inline void eval_op(const Bufs &b, const u32 *rt_scan, u32 o, u32 D, u32 *lds_list, u32 *lds_n, u32 hint,
+                               JobSink js) {
     const u32 p = b.op_p[o];
-    if (b.s_kind[p] == 4u) eval_bar(b, p, D, lds_list, lds_n);
-    else eval_ra(b, rt_scan, p, D);
+    if (b.s_kind[p] == 4u) eval_bar(b, p, D, lds_list, lds_n, hint, js);
+    else eval_ra(b, rt_scan, p, D, hint, js);
     __syncthreads();
 }
 
+// The smallest handle an operation writes (handles grow with the operation index).
+__device__ inline u32 first_handle(const Bufs &b, u32 o) {
+    const u32 p = b.op_p[o];
+    if (b.s_kind[p] == 4u) {
+        const u32 blk = block_of(b, b.ev[b.s_pidx[p]].y);
+        return b.inst_handle[b.inst_off[blk] + b.s_phase[p] - 1];
+    }
+    return (b.s_flags[p] & SF_REL) ? b.e_relh[p] : b.s_khandle[p];
+}
+
+// Second phase of a window.  Every output column of every operation depends only on the same
+// column of its inputs, so each thread owns 16-byte column slices and replays the window's jobs
+// in order over its slices: no barrier between operations, the chain's latest outputs stay in
+// registers, and the partial results of the next CH_NB operations are loaded ahead.
+
+__device__ inline u32 uni(u32 x) { return __builtin_amdgcn_readfirstlane(x); }
+__device__ inline uint4 uni4(uint4 v) { return make_uint4(uni(v.x), uni(v.y), uni(v.z), uni(v.w)); }
+
+// The latest four outputs of the replay (newest first); handle 0 is the empty vector.
+struct ChainCache {
+    u32 h0, h1, h2, h3;
+    uint4 v0, v1, v2, v3;
+};
+
+__device__ __attribute__((always_inline)) inline uint4 chain_get(const ChainCache &C, const uint4 *pool4, u32 D4,
+                                                                 u32 i, u32 h) {
+    // h is the same in every lane: the branches are uniform
+    if (h == C.h0) return C.v0;
+    if (h == C.h1) return C.v1;
+    if (h == C.h2) return C.v2;
+    if (h == C.h3) return C.v3;
+    return pool4[(u64)h * D4 + i];
+}
+
+__device__ __attribute__((always_inline)) inline void chain_put(ChainCache &C, u32 h, uint4 v) {
+    C.h3 = C.h2; C.v3 = C.v2;
+    C.h2 = C.h1; C.v2 = C.v1;
+    C.h1 = C.h0; C.v1 = C.v0;
+    C.h0 = h; C.v0 = v;
+}
+
+struct ChainJob {
+    uint4 q;     // (out, in0, in1, in2); out 0: no job
+    u32 lo, ln;  // window input list range (barrier outputs)
+    bool act;    // has inputs from the window
+};
+
+__device__ __attribute__((always_inline)) inline ChainJob chain_job(const u32 *jb, u32 k, bool in) {
+    ChainJob J;
+    J.q = uni4(in ? ((const uint4 *)jb)[k] : make_uint4(0, 0, 0, 0));
+    const uint4 l = in && k == 0 ? ((const uint4 *)jb)[3] : make_uint4(0, 0, 0, 0);
+    J.lo = uni(l.x);
+    J.ln = uni(l.y);
+    J.act = J.q.x && (J.q.y | J.q.z | J.q.w | J.ln);
+    return J;
+}
+
+__device__ __attribute__((always_inline)) inline uint4 chain_part(const ChainJob &J, const uint4 *pool4, u32 D4, u32 i) {
+    return J.act ? pool4[(u64)J.q.x * D4 + i] : make_uint4(0, 0, 0, 0);
+}
+
+__device__ __attribute__((always_inline)) inline void chain_run(ChainCache &C, const ChainJob &J, uint4 v, const u32 *list, uint4 *pool4, u32 D4,
+                                 u32 i) {
+    if (!J.act) return;
+    if (J.q.y) v = max4(v, chain_get(C, pool4, D4, i, J.q.y));
+    if (J.q.z) v = max4(v, chain_get(C, pool4, D4, i, J.q.z));
+    if (J.q.w) v = max4(v, chain_get(C, pool4, D4, i, J.q.w));
+    for (u32 l = 0; l < J.ln; l++) v = max4(v, chain_get(C, pool4, D4, i, uni(list[J.lo + l])));
+    pool4[(u64)J.q.x * D4 + i] = v;
+    chain_put(C, J.q.x, v);
+}
+
+__device__ void chain_window(const Bufs &b, u32 w0, u32 w1, u32 D4) {
+    const u32 *jobs = b.eng_jobs, *list = b.eng_jobs + ENG_WIN * ENG_JOB_WORDS;
+    uint4 *pool4 = (uint4 *)b.pool;
+    const bool reporter = blockIdx.x == 0 && threadIdx.x == 0;
+    for (u32 i = blockIdx.x * ENG_THREADS + threadIdx.x; i < D4; i += gridDim.x * ENG_THREADS) {
+        const uint4 z = make_uint4(0, 0, 0, 0);
+        ChainCache C = {0, 0, 0, 0, z, z, z, z};
+        // two operations per step: all six partial results are loaded before the joins
+        for (u32 o = w0; o < w1; o += 2) {
+            const u32 *ja = jobs + (u64)(o - w0) * ENG_JOB_WORDS, *jb = ja + ENG_JOB_WORDS;
+            const bool inb = o + 1 < w1;
+            const ChainJob a0 = chain_job(ja, 0, true), a1 = chain_job(ja, 1, true), a2 = chain_job(ja, 2, true);
+            const ChainJob b0 = chain_job(jb, 0, inb), b1 = chain_job(jb, 1, inb), b2 = chain_job(jb, 2, inb);
+            const uint4 pa0 = chain_part(a0, pool4, D4, i), pa1 = chain_part(a1, pool4, D4, i),
+                        pa2 = chain_part(a2, pool4, D4, i);
+            const uint4 pb0 = chain_part(b0, pool4, D4, i), pb1 = chain_part(b1, pool4, D4, i),
+                        pb2 = chain_part(b2, pool4, D4, i);
+            chain_run(C, a0, pa0, list, pool4, D4, i);
+            chain_run(C, a1, pa1, list, pool4, D4, i);
+            chain_run(C, a2, pa2, list, pool4, D4, i);
+            chain_run(C, b0, pb0, list, pool4, D4, i);
+            chain_run(C, b1, pb1, list, pool4, D4, i);
+            chain_run(C, b2, pb2, list, pool4, D4, i);
+            if (reporter) atomicAdd(&b.prm->gprog, 1u);
+        }
+    }
+}
+
 // All workgroups meet; writes before are visible to every workgroup after.  The wait is bounded by
-// time without progress: a workgroup evaluating a long run of small groups alone advances
-// P->gprog after every operation, which restarts the others' count.
+// time without progress: workgroup 0 advances P->gprog during the sequential phase of a window,
+// which restarts the others' count.
 __device__ inline void grid_barrier(DevParams *P, u32 round) {
     __syncthreads();
     if (threadIdx.x == 0) {
@@ -590,7 +739,8 @@ __device__ inline void grid_barrier(DevParams *P, u32 round) {
     __syncthreads();
 }
 
-// Cooperative: every workgroup runs the same group loop.
+// Cooperative: every workgroup runs the same group loop.  A wide group spreads its operations over
+// the workgroups; a run of small groups is evaluated in windows of two phases (above).
 __global__ __launch_bounds__(ENG_THREADS) void k_eng_eval(Bufs b, const u32 *rt_scan) {
     DevParams *P = b.prm;
     if (!eng_on(P) || P->n_ops > b.ecap || (P->err & ERR_POOL)) return;
@@ -598,27 +748,44 @@ __global__ __launch_bounds__(ENG_THREADS) void k_eng_eval(Bufs b, const u32 *rt_
     __shared__ u32 lds_n;
     const u32 D = P->D, ng = P->n_groups;
     u32 round = 0;
-    if (blockIdx.x == 0)
+    if (blockIdx.x == 0) {
         for (u32 i = threadIdx.x; i < D; i += ENG_THREADS) b.pool[i] = 0;  // the empty knowledge
+        if (threadIdx.x == 0) P->wlist = 0;
+    }
     // vectors written by the engine: their padding words must read as zero too (joins keep them 0)
     grid_barrier(P, ++round);
+    JobSink none = {nullptr, nullptr, nullptr};
     u32 g = 0;
     while (g < ng) {
         const u32 g0 = b.grp[g], g1 = b.grp[g + 1];
         if (g1 - g0 >= ENG_WIDE) {
-            for (u32 o = g0 + blockIdx.x; o < g1; o += gridDim.x) eval_op(b, rt_scan, o, D, lds_list, &lds_n);
+            for (u32 o = g0 + blockIdx.x; o < g1; o += gridDim.x) eval_op(b, rt_scan, o, D, lds_list, &lds_n, NONE, none);
             g++;
-        } else {
-            u32 g2 = g + 1;
-            while (g2 < ng && b.grp[g2 + 1] - b.grp[g2] < ENG_WIDE) g2++;
-            if (blockIdx.x == 0)
-                for (u32 o = g0; o < b.grp[g2]; o++) {
-                    eval_op(b, rt_scan, o, D, lds_list, &lds_n);
-                    if (threadIdx.x == 0) atomicAdd(&P->gprog, 1u);
-                }
-            g = g2;
+            grid_barrier(P, ++round);
+            continue;
         }
-        grid_barrier(P, ++round);
+        u32 g2 = g + 1;
+        while (g2 < ng && b.grp[g2 + 1] - b.grp[g2] < ENG_WIDE) g2++;
+        const u32 end = b.grp[g2];
+        for (u32 w0 = g0; w0 < end; w0 += ENG_WIN) {
+            const u32 w1 = min(w0 + ENG_WIN, end);
+            if (w1 - w0 == 1) {  // one operation: all its inputs are ready
+                if (blockIdx.x == 0) eval_op(b, rt_scan, w0, D, lds_list, &lds_n, NONE, none);
+                grid_barrier(P, ++round);
+                continue;
+            }
+            const u32 hint = first_handle(b, w0);
+            for (u32 o = w0 + blockIdx.x; o < w1; o += gridDim.x) {
+                JobSink js = {b.eng_jobs + (u64)(o - w0) * ENG_JOB_WORDS, b.eng_jobs + ENG_WIN * ENG_JOB_WORDS,
+                              &P->wlist};
+                eval_op(b, rt_scan, o, D, lds_list, &lds_n, hint, js);
+            }
+            grid_barrier(P, ++round);
+            chain_window(b, w0, w1, D / 4);
+            if (blockIdx.x == 0 && threadIdx.x == 0) P->wlist = 0;  // the next window's list starts empty
+            grid_barrier(P, ++round);
+        }
+        g = g2;
     }
 }
 

@@ -94,7 +94,7 @@ static Plan make_plan(u64 n, u32 nb, u32 tpb, const rd_limits *lim, bool copy_ev
     L.off_inst_opo = take(4 * N1);
     L.off_inst_bko = take(4 * N1);
     L.off_inst_coff = take(4 * (N1 + 1));
-    L.off_clist = take(4ull * L.ecap);
+    L.off_eng_jobs = take(4ull * ENG_WIN * (ENG_JOB_WORDS + 1));
     L.off_ral_p = take(4ull * L.ecap);
     L.off_ral_key = take(4ull * L.ecap);
     L.off_op_p = take(4ull * L.ecap);
@@ -108,6 +108,7 @@ static Plan make_plan(u64 n, u32 nb, u32 tpb, const rd_limits *lim, bool copy_ev
     P.off_rt_scan = take(4 * (T + 1));
     L.off_priv = take(4 * T);
     L.off_priv_next = take(4 * T);
+    L.off_t_kfirst = take(4 * T);
     L.off_bk = take(4 * B);
     L.off_priv_head = take(4 * B);
     L.off_sv_key = take(8ull * L.sv_cap);
@@ -179,7 +180,7 @@ static Bufs make_bufs(const Plan &P, char *ws, const void *events_dev, u64 n, u3
     b.inst_opo = (u32 *)(ws + L.off_inst_opo);
     b.inst_bko = (u32 *)(ws + L.off_inst_bko);
     b.inst_coff = (u32 *)(ws + L.off_inst_coff);
-    b.clist = (u32 *)(ws + L.off_clist);
+    b.eng_jobs = (u32 *)(ws + L.off_eng_jobs);
     b.ral_p = (u32 *)(ws + L.off_ral_p);
     b.ral_key = (u32 *)(ws + L.off_ral_key);
     b.op_p = (u32 *)(ws + L.off_op_p);
@@ -194,6 +195,7 @@ static Bufs make_bufs(const Plan &P, char *ws, const void *events_dev, u64 n, u3
     b.n_active = (u32 *)(ws + L.off_n_active);
     b.priv = (u32 *)(ws + L.off_priv);
     b.priv_next = (u32 *)(ws + L.off_priv_next);
+    b.t_kfirst = (u32 *)(ws + L.off_t_kfirst);
     b.bk = (u32 *)(ws + L.off_bk);
     b.priv_head = (u32 *)(ws + L.off_priv_head);
     b.sv_key = (u64 *)(ws + L.off_sv_key);

@@ -95,9 +95,15 @@ struct DevParams {
     u32 n_handles;         // knowledge vectors the engine writes (+1 for the empty one)
     u32 n_groups;          // dependency-free groups of operations
     u32 gbar;              // grid-barrier arrivals of the engine kernel
-    u32 gprog;             // operations finished by the engine's single-workgroup runs (progress)
+    u32 gprog;             // progress of the engine's sequential phases (bounds barrier waits)
+    u32 wlist;             // entries of the engine's window input list
     unsigned long long n_chunks;  // queued slow-path chunks of the segment check (8-byte aligned)
 };
+
+// The engine evaluates runs of small dependent groups in windows of ENG_WIN operations; each
+// operation of a window has ENG_JOB_WORDS words of job description.
+constexpr u32 ENG_WIN = 4096;
+constexpr u32 ENG_JOB_WORDS = 16;
 
 // knowledge engine selection (DevParams::eng)
 enum : u32 {
@@ -143,7 +149,7 @@ struct Bufs {
     u32 *inst_opo;          // [N] barrier instance -> operation index (or NONE)
     u32 *inst_bko;          // [N] operation that wrote the block knowledge after the instance
     u32 *inst_coff;         // [N+1] contributions per instance -> offsets
-    u32 *clist;             // [ECAP] contributing acquire entries, by instance
+    u32 *eng_jobs;          // [ENG_WIN * ENG_JOB_WORDS + ENG_WIN] window job table and list (engine)
     u32 *ral_p, *ral_key;   // [ECAP] release/acquire accesses in (location, trace) order
     u32 *op_p;              // [ECAP] operation -> entry
     u32 *op_dep;            // [ECAP] largest operation index it depends on (NONE: none)
@@ -158,6 +164,7 @@ struct Bufs {
     u32 *rt;                // [T] knowledge column of a thread, or NONE
     u32 *priv;              // [T] private knowledge vector of a thread (since its last barrier)
     u32 *priv_next;         // [T]
+    u32 *t_kfirst;          // [T] trace index of the thread's first sync entry with knowledge (NONE: none)
     u32 *bk;                // [B] knowledge vector of a block after its latest barrier
     u32 *priv_head;         // [B]
     // sync-variable table (open addressing)
@@ -231,7 +238,7 @@ struct Layout {
     u64 off_params, off_ev, off_act, off_s_cnt, off_s_fill, off_tile_s, off_s_tidx, off_s_pidx,
         off_s_pq, off_s_inv, off_s_phase, off_s_kind, off_s_flags, off_s_scope, off_s_imin,
         off_s_know, off_s_khandle, off_s_winst, off_e_prev0, off_e_prev1, off_e_src0, off_e_src1, off_e_cur,
-        off_e_relh, off_e_op, off_e_scan0, off_e_scan1, off_inst_opo, off_inst_bko, off_inst_coff, off_clist,
+        off_e_relh, off_e_op, off_e_scan0, off_e_scan1, off_inst_opo, off_inst_bko, off_inst_coff, off_eng_jobs, off_t_kfirst,
         off_ral_p, off_ral_key, off_op_p, off_op_dep, off_grp, off_blk_maxbar, off_inst_off, off_inst_cnt,
         off_inst_last, off_inst_handle, off_n_active, off_rt, off_priv, off_priv_next, off_bk,
         off_priv_head, off_sv_key, off_sv_tag, off_sv_handle, off_wo_key, off_wo_val, off_wi_key,

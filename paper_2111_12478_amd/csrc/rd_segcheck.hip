@@ -123,7 +123,7 @@ __device__ inline void agg_combine(const Agg &l, Agg &r) {
 
 struct SegCtx {
     const u32 *k, *i, *t, *f;
-    u32 *cpos, *clo, *chi, *cx;  // the queue of slow-path entries (in the sort's free buffers)
+    u32 *cpos, *clo, *chi;  // the queue of slow-path chunks (in the sort's free buffers)
     u32 n;
 };
 
@@ -132,7 +132,7 @@ __device__ inline SegCtx seg_ctx(const Bufs &b) {
     const u32 bits = b.prm->key_bits, passes = (bits + b.radix_bits - 1) / b.radix_bits;
     const u32 c = passes & 1;
     SegCtx s; s.k = b.ekey[c]; s.i = b.eidx[c]; s.t = b.etid[c]; s.f = b.einfo[c]; s.n = b.prm->n_acc;
-    s.cpos = b.ekey[c ^ 1]; s.clo = b.etid[c ^ 1]; s.chi = b.einfo[c ^ 1]; s.cx = b.eidx[c ^ 1];
+    s.cpos = b.ekey[c ^ 1]; s.clo = b.etid[c ^ 1]; s.chi = b.einfo[c ^ 1];
     return s;
 }
 
@@ -337,6 +337,12 @@ enum : u32 {
     SLOW_WALK = 3,  // one or two blocks before b: a backward walk that stops early
 };
 
+// Does b's thread have knowledge at b (at sorted position pos)?  Without it no other block can be
+// settled, and a walk would only be a slower way to scan the whole prefix.
+__device__ inline bool knows_at(const Bufs &b, const SegCtx &s, u32 tid, u32 pos) {
+    return (b.prm->mode & MODE_SYNC) && b.t_kfirst[tid] != NONE && b.t_kfirst[tid] < s.i[pos];
+}
+
 // P: summary of everything before b (b's own segment when P.last_key == key).
 __device__ inline u32 decide(const Agg &P, u32 key, u32 tid, u32 blk, u32 ph, u32 cat) {
     if (!(P.fl & F_NONEMPTY) || P.last_key != key) return SLOW_NONE;
@@ -353,12 +359,9 @@ __device__ inline u32 decide(const Agg &P, u32 key, u32 tid, u32 blk, u32 ph, u3
     return (P.fl & F_BLK3) ? SLOW_SEG : SLOW_WALK;
 }
 
-// Queue entries, one wavefront each.  Chunk (pos, lo, hi): check b at pos against positions
-// [lo, hi).  Walk (pos, below, WALK, nb): the backward walk of b at pos over a prefix with nb
-// blocks, reporting pairs at positions below `below` only (the positions above were walked by a
-// lane of the check kernel).
-constexpr u32 WALK = 0xffffffffu;
-constexpr u32 LANE_WALK_CAP = 32;  // positions a lane walks before handing the walk to a wavefront
+// Queue entries, one wavefront each: chunk (pos, lo, hi) = check b at pos against positions [lo, hi).
+constexpr u32 LANE_WALK_CAP = 16;  // positions a lane walks before the rest is queued as chunks
+constexpr u32 LANE_STEP = 4;       // positions a lane loads at once
 
 // Pairs found by one wavefront, gathered in LDS and appended with one device atomic per flush.
 constexpr u32 WAVE_PAIRS = 512;
@@ -443,53 +446,6 @@ __device__ inline bool walk_race(const Bufs &b, const SegCtx &s, const u32 *rt_s
     return !happens_before(b, rt_scan, w.bidx, w.btid, w.bblk, w.bph, h, ta, ba, pha, ia);
 }
 
-// The walk with a whole wavefront, 64 positions per step.  The blocks of the prefix are learnt on
-// the way (x1 first, x2 the other one).
-__device__ inline void wave_walk(const Bufs &b, const SegCtx &s, const u32 *rt_scan, u32 pos, u32 below, u32 nb,
-                                 WavePairs &wp) {
-    const u32 lane = lane_id();
-    const Walker w = walker_at(b, s, pos);
-    u32 x1 = NONE, x2 = NONE;
-    bool d1 = false, d2 = false;
-    for (u32 top = pos; top > 0; top = top > 64 ? top - 64 : 0) {
-        const bool valid = lane < top;
-        const u32 q = valid ? top - 1 - lane : 0;
-        bool stop = !valid;
-        u32 ta = 0, info = 0, ba = NONE, pha = 0;
-        if (valid) {
-            stop = s.k[q] != w.key;
-            if (!stop) {
-                ta = s.t[q];
-                info = s.f[q];
-                ba = block_of(b, ta);
-                pha = info_phase(info);
-            }
-        }
-        const u64 sm = ballot(stop);
-        const u32 first_stop = sm ? (u32)__builtin_ctzll(sm) : 64u;
-        const bool in = lane < first_stop;
-        // name the (at most two) blocks
-        if (x1 == NONE && first_stop > 0) x1 = __shfl(ba, 0, 64);
-        if (x2 == NONE) {
-            const u64 o = ballot(in && ba != x1);
-            if (o) x2 = __shfl(ba, (int)__builtin_ctzll(o), 64);
-        }
-        const bool st = in && settles(w, ba, pha);
-        const u64 m1 = ballot(st && ba == x1), m2 = ballot(st && ba == x2);
-        // lanes past the point where every block is settled hold settled accesses only
-        const u32 e1 = d1 ? 0u : (m1 ? (u32)__builtin_ctzll(m1) : 64u);
-        const u32 e2 = nb < 2 || d2 ? 0u : (m2 ? (u32)__builtin_ctzll(m2) : 64u);
-        const u32 lim = min(first_stop, max(e1, e2) + 1);
-        bool want = false;
-        u32 ia = 0;
-        if (lane < lim && q < below) want = walk_race(b, s, rt_scan, w, q, ta, ba, pha, info_cat(info), ia);
-        wp_add(b, wp, want, ia, w.bidx);
-        d1 = d1 || m1 != 0;
-        d2 = d2 || m2 != 0;
-        if (sm || (d1 && (nb < 2 || d2))) break;
-    }
-}
-
 // Block-wide (256 threads) exclusive scan of one u64 per thread; *total gets the sum.
 __device__ inline u64 block_exscan_u64(u64 v, u64 *wsum /* WAVES */, u64 &total) {
     const u32 lane = lane_id(), w = threadIdx.x >> 6;
@@ -510,12 +466,84 @@ __device__ inline u64 block_exscan_u64(u64 v, u64 *wsum /* WAVES */, u64 &total)
     return off + incl - v;
 }
 
-// Queues one entry; false when the queue is full.
-__device__ inline bool queue_push(const Bufs &b, const SegCtx &s, u32 pos, u32 lo, u32 hi, u32 x) {
-    const u64 c = atomicAdd(&b.prm->n_chunks, 1ull);
-    if (c >= s.n) return false;
-    s.cpos[c] = pos; s.clo[c] = lo; s.chi[c] = hi; s.cx[c] = x;
+// Queues the rest of a walk -- b against positions [segment start, top) -- as chunks; false when the
+// queue is full (the walk then goes on).  The segment start is found by a binary search.
+__device__ inline bool walk_spill(const Bufs &b, const SegCtx &s, const Walker &w, u32 top) {
+    u32 lo = 0, hi = top;
+    while (lo < hi) {
+        const u32 mid = (lo + hi) >> 1;
+        if (s.k[mid] < w.key) lo = mid + 1;
+        else hi = mid;
+    }
+    const u32 cnt = (top - lo + 63) / 64;
+    if (!cnt) return true;
+    const u64 c0 = atomicAdd(&b.prm->n_chunks, (unsigned long long)cnt);
+    if (c0 + cnt > s.n) {
+        // neutralise the reserved slots below the capacity (the chunk kernel reads them)
+        for (u64 c = c0; c < c0 + cnt && c < s.n; c++) { s.cpos[c] = 0; s.clo[c] = 0; s.chi[c] = 0; }
+        return false;
+    }
+    for (u32 k = 0; k < cnt; k++) {
+        const u32 c_lo = lo + 64 * k;
+        s.cpos[c0 + k] = w.pos; s.clo[c0 + k] = c_lo; s.chi[c0 + k] = min(c_lo + 64, top);
+    }
     return true;
+}
+
+// The walks of a lane's items (walk_bits; two_bits: the prefix has two blocks), one at a time: a
+// lane takes its next item when its walk ends, and loads LANE_STEP positions at once.  All lanes
+// of the wavefront call it.
+__device__ void lane_walks(const Bufs &b, const SegCtx &s, const u32 *rt_scan, u64 base, u32 walk_bits,
+                           u32 two_bits, WavePairs &wp) {
+    bool act = false, d1 = false, d2 = false;
+    Walker w = {};
+    u32 nb = 1, x1 = NONE, top = 0, steps = 0;
+    while (true) {
+        if (!act && walk_bits) {
+            const u32 q = (u32)__builtin_ctz(walk_bits);
+            walk_bits &= walk_bits - 1;
+            w = walker_at(b, s, (u32)(base + q));
+            nb = (two_bits >> q) & 1u ? 2u : 1u;
+            x1 = NONE;
+            d1 = d2 = false;
+            top = w.pos;
+            steps = 0;
+            act = true;
+        }
+        if (!ballot(act)) break;
+        u32 kq[LANE_STEP], tq[LANE_STEP], fq[LANE_STEP];
+#pragma unroll
+        for (u32 j = 0; j < LANE_STEP; j++) {
+            const bool ok = act && top > j;
+            const u32 q = ok ? top - 1 - j : 0u;
+            kq[j] = ok ? s.k[q] : w.key ^ 1u;
+            tq[j] = ok ? s.t[q] : 0u;
+            fq[j] = ok ? s.f[q] : 0u;
+        }
+#pragma unroll
+        for (u32 j = 0; j < LANE_STEP; j++) {
+            bool want = false;
+            u32 ia = 0;
+            if (act) {
+                if (kq[j] != w.key) {
+                    act = false;
+                } else {
+                    const u32 q = top - 1, ta = tq[j], info = fq[j];
+                    const u32 ba = block_of(b, ta), pha = info_phase(info);
+                    if (x1 == NONE) x1 = ba;
+                    want = walk_race(b, s, rt_scan, w, q, ta, ba, pha, info_cat(info), ia);
+                    if (settles(w, ba, pha)) {
+                        if (ba == x1) d1 = true;
+                        else d2 = true;
+                    }
+                    top = q;
+                    if ((d1 && (nb < 2 || d2)) || top == 0) act = false;
+                    else if (++steps == LANE_WALK_CAP && walk_spill(b, s, w, top)) act = false;
+                }
+            }
+            wp_add(b, wp, want, ia, w.bidx);
+        }
+    }
 }
 
 union CheckLds {
@@ -543,7 +571,7 @@ __global__ __launch_bounds__(WG_THREADS) void k_seg_check(Bufs b, const u32 *rt_
         Agg T = tile_agg[blockIdx.x];  // everything before this tile
         agg_combine(T, P0);            // P0 := T (+) P0: everything before this thread's items
     }
-    // pass 1: decisions in O(1) per item; chunks needed by run and many-block items
+    // pass 1: decisions in O(1) per item; the chunks that run, many-block and unsettleable items need
     u64 need = 0;
     u32 chunk_bits = 0, run_bits = 0, walk_bits = 0, two_bits = 0;
     {
@@ -555,7 +583,7 @@ __global__ __launch_bounds__(WG_THREADS) void k_seg_check(Bufs b, const u32 *rt_
             const u32 cat = info_cat(info), ph = info_phase(info), blk = block_of(b, tid);
             const u32 mode = decide(P, key, tid, blk, ph, cat);
             const u32 pos = (u32)(base + q);
-            if (mode == SLOW_WALK) {
+            if (mode == SLOW_WALK && knows_at(b, s, tid, pos)) {
                 walk_bits |= 1u << q;
                 if (P.fl & F_BLKMULTI) two_bits |= 1u << q;
             } else if (mode != SLOW_NONE) {
@@ -627,84 +655,67 @@ __global__ __launch_bounds__(WG_THREADS) void k_seg_check(Bufs b, const u32 *rt_
                             (mr >> l) & 1u);
         }
     }
-    // the walks, one per lane at a time: a lane takes its next walk item when its walk ends
-    u32 todo = walk_bits;
-    bool act = false;
-    Walker w = {};
-    u32 nb = 1, x1 = NONE, top = 0, steps = 0;
-    bool d1 = false, d2 = false;
-    while (true) {
-        if (!act && todo) {
-            const u32 q = (u32)__builtin_ctz(todo);
-            todo &= todo - 1;
-            w = walker_at(b, s, (u32)(base + q));
-            nb = (two_bits >> q) & 1u ? 2u : 1u;
-            x1 = NONE; d1 = d2 = false;
-            top = w.pos;
-            steps = 0;
-            act = true;
-        }
-        if (!ballot(act)) break;
-        bool want = false;
-        u32 ia = 0;
-        if (act) {
-            const u32 q = top - 1;
-            if (top == 0 || s.k[q] != w.key) {
-                act = false;
-            } else {
-                const u32 ta = s.t[q], info = s.f[q];
-                const u32 ba = block_of(b, ta), pha = info_phase(info);
-                if (x1 == NONE) x1 = ba;
-                want = walk_race(b, s, rt_scan, w, q, ta, ba, pha, info_cat(info), ia);
-                if (settles(w, ba, pha)) {
-                    if (ba == x1) d1 = true;
-                    else d2 = true;
-                }
-                top = q;
-                if (d1 && (nb < 2 || d2)) act = false;
-                else if (++steps == LANE_WALK_CAP && queue_push(b, s, w.pos, top, WALK, nb)) act = false;
-            }
-        }
-        wp_add(b, wp, want, ia, w.bidx);
-    }
+    // the walks
+    lane_walks(b, s, rt_scan, base, walk_bits, two_bits, wp);
     wp_flush(b, wp);
 }
 
-// One wavefront per queued entry.
+// One wavefront per queued chunk (lane l checks position lo + l against b), the four wavefronts of
+// a workgroup in step.  Pairs are gathered in LDS and appended with one device atomic per flush of
+// the workgroup.
+constexpr u32 PAIR_LDS = 2048;
+
 __global__ __launch_bounds__(WG_THREADS) void k_seg_slow(Bufs b, const u32 *rt_scan) {
-    __shared__ u32 pf[WAVES][WAVE_PAIRS], ps[WAVES][WAVE_PAIRS];
+    __shared__ u32 pf[PAIR_LDS], ps[PAIR_LDS];
+    __shared__ u32 fill, gbase;
     const SegCtx s = seg_ctx(b);
     const u32 n_chunks = (u32)min(b.prm->n_chunks, (unsigned long long)s.n);
     const u32 lane = lane_id(), w = threadIdx.x >> 6;
-    WavePairs wp;
-    wp.pf = pf[w];
-    wp.ps = ps[w];
-    wp.fill = 0;
+    if (threadIdx.x == 0) fill = 0;
+    __syncthreads();
     const u32 stride = gridDim.x * WAVES;
-    for (u32 c = blockIdx.x * WAVES + w; c < n_chunks; c += stride) {
-        const u32 pos = s.cpos[c], lo = s.clo[c], hi = s.chi[c];
-        if (hi == WALK) {
-            wave_walk(b, s, rt_scan, pos, lo, s.cx[c], wp);
-            continue;
-        }
+    for (u32 c0 = blockIdx.x * WAVES; c0 < n_chunks; c0 += stride) {
+        const u32 c = c0 + w;
         bool want = false;
         u32 ia = 0, bidx = 0;
-        const u32 q = lo + lane;
-        if (q < hi) {
-            const u32 btid = s.t[pos], binfo = s.f[pos];
-            const u32 bblk = block_of(b, btid), bph = info_phase(binfo), bcat = info_cat(binfo);
-            const u32 ta = s.t[q], info = s.f[q];
-            const u32 ba = block_of(b, ta), pha = info_phase(info);
-            if (ta != btid && conflicts(info_cat(info), ba, bcat, bblk)) {
-                u32 h = NONE;
-                ia = s.i[q];
-                bidx = s.i[pos];
-                want = !happens_before(b, rt_scan, bidx, btid, bblk, bph, h, ta, ba, pha, ia);
+        if (c < n_chunks) {
+            const u32 pos = s.cpos[c], lo = s.clo[c], hi = s.chi[c];
+            const u32 q = lo + lane;
+            if (q < hi) {
+                const u32 btid = s.t[pos], binfo = s.f[pos];
+                const u32 bblk = block_of(b, btid), bph = info_phase(binfo), bcat = info_cat(binfo);
+                const u32 ta = s.t[q], info = s.f[q];
+                const u32 ba = block_of(b, ta), pha = info_phase(info);
+                if (ta != btid && conflicts(info_cat(info), ba, bcat, bblk)) {
+                    u32 h = NONE;
+                    ia = s.i[q];
+                    bidx = s.i[pos];
+                    want = !happens_before(b, rt_scan, bidx, btid, bblk, bph, h, ta, ba, pha, ia);
+                }
             }
         }
-        wp_add(b, wp, want, ia, bidx);
+        const u64 m = ballot(want);
+        if (m) {
+            u32 off = 0;
+            const u32 leader = (u32)__builtin_ctzll(m);
+            if (lane == leader) off = atomicAdd(&fill, popc64(m));
+            off = __shfl(off, leader, 64) + popc64(m & lanemask_lt());
+            if (want) { pf[off] = ia; ps[off] = bidx; }
+        }
+        __syncthreads();
+        if (fill > PAIR_LDS - WG_THREADS || c0 + stride >= n_chunks) {
+            if (threadIdx.x == 0) gbase = fill ? atomicAdd(&b.prm->n_pairs, fill) : 0;
+            __syncthreads();
+            for (u32 k = threadIdx.x; k < fill; k += WG_THREADS) {
+                const u32 slot = gbase + k;
+                if (slot < b.max_pairs) { b.pfirst[0][slot] = pf[k]; b.psecond[0][slot] = ps[k]; }
+                else atomicOr(&b.prm->err, ERR_PAIRS);
+            }
+            __syncthreads();
+            if (threadIdx.x == 0) fill = 0;
+            __syncthreads();
+        }
     }
-    wp_flush(b, wp);
 }
 
 __global__ void k_pairs_kept(Bufs b) {
