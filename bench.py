@@ -69,6 +69,35 @@ def source_digest() -> str:
     return h.hexdigest()[:16]
 
 
+def summarize_trace(trace_csv: str, label: str, title: str, command: str) -> None:
+    """Writes profiles/<label>_kernel_stats.txt from the kernel trace CSV of a rocprofv3
+    --kernel-trace --stats run: per (kernel, grid) launches, average and total duration."""
+    import csv
+    from collections import defaultdict
+
+    def short(name):
+        return name.split("(")[0].replace("void ", "").replace("rd::", "")
+
+    dur = defaultdict(list)
+    for r in csv.DictReader(open(trace_csv)):
+        g = int(r["Grid_Size_X"]) * int(r["Grid_Size_Y"]) * int(r["Grid_Size_Z"])
+        dur[(short(r["Kernel_Name"]), g)].append((int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) / 1e3)
+    total = sum(sum(v) for v in dur.values())
+    lines = [f"# per-kernel durations from rocprofv3 --kernel-trace --stats, {title}, MI355X",
+             f"# command: {command}",
+             "# keyed by (kernel, grid); 'worked' = launches above 10% of the kernel's longest (a sort pass",
+             "# past the key width exits at once)", "",
+             f"{'kernel':34s} {'grid':>9s} {'calls':>6s} {'worked':>6s} {'avg_us':>9s} {'sum_ms':>8s} {'pct':>6s}"]
+    for (k, g), v in sorted(dur.items(), key=lambda kv: -sum(kv[1])):
+        hi = max(v)
+        w = [x for x in v if x > 0.1 * hi]
+        lines.append(f"{k[:34]:34s} {g:9d} {len(v):6d} {len(w):6d} {sum(w)/len(w):9.1f} {sum(v)/1e3:8.3f} "
+                     f"{100*sum(v)/total:6.2f}")
+    lines.append(f"\n# total kernel time {total/1e3:.3f} ms over the profiled run")
+    os.makedirs(os.path.join(ROOT, "profiles"), exist_ok=True)
+    open(os.path.join(ROOT, "profiles", f"{label}_kernel_stats.txt"), "w").write("\n".join(lines) + "\n")
+
+
 def summarize_profiles(trace_csv: str, fetch_csv: str, write_csv: str, command: str) -> None:
     """Turns rocprofv3 CSV output (the kernel trace of a --kernel-trace --stats run, then FETCH_SIZE
     and WRITE_SIZE counter runs of the same command with a 1 GiB plain copy first) into the
@@ -82,23 +111,7 @@ def summarize_profiles(trace_csv: str, fetch_csv: str, write_csv: str, command: 
     def short(name):
         return name.split("(")[0].replace("void ", "").replace("rd::", "")
 
-    dur = defaultdict(list)
-    for r in csv.DictReader(open(trace_csv)):
-        g = int(r["Grid_Size_X"]) * int(r["Grid_Size_Y"]) * int(r["Grid_Size_Z"])
-        dur[(short(r["Kernel_Name"]), g)].append((int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) / 1e3)
-    total = sum(sum(v) for v in dur.values())
-    lines = ["# per-kernel durations from rocprofv3 --kernel-trace --stats, large trace (16,777,216 events), MI355X",
-             f"# command: {command}",
-             "# keyed by (kernel, grid); 'worked' = launches above 10% of the kernel's longest (a radix pass",
-             "# past the key width exits at once)", "",
-             f"{'kernel':30s} {'grid':>9s} {'calls':>6s} {'worked':>6s} {'avg_us':>9s} {'sum_ms':>8s} {'pct':>6s}"]
-    for (k, g), v in sorted(dur.items(), key=lambda kv: -sum(kv[1])):
-        hi = max(v)
-        w = [x for x in v if x > 0.1 * hi]
-        lines.append(f"{k[:30]:30s} {g:9d} {len(v):6d} {len(w):6d} {sum(w)/len(w):9.1f} {sum(v)/1e3:8.3f} "
-                     f"{100*sum(v)/total:6.2f}")
-    lines.append(f"\n# total kernel time {total/1e3:.3f} ms over the profiled steps")
-    open(os.path.join(out_dir, "large_trace_kernel_stats.txt"), "w").write("\n".join(lines) + "\n")
+    summarize_trace(trace_csv, "large_trace", "large trace (16,777,216 events)", command)
 
     def per_kernel(path):
         agg = defaultdict(list)
@@ -130,11 +143,20 @@ def summarize_profiles(trace_csv: str, fetch_csv: str, write_csv: str, command: 
         lines.append(f"{key[0][:30]:30s} {key[1]:9d} {max(len(f), len(w)):3d} {rd_mb:9.1f} {wr_mb:9.1f}")
         result[key] = (rd_mb, wr_mb)
     open(os.path.join(out_dir, "large_trace_hbm_traffic.txt"), "w").write("\n".join(lines) + "\n")
-    # the element-sort sweep: the launches over all accesses (the largest grid)
-    sc = [(g, v) for (k, g), v in result.items() if k.startswith("k_sort_sweep<3>")]
-    if sc:
-        g, (r_mb, w_mb) = max(sc)
-        json.dump({"kernel": "k_sort_sweep", "workload_events": 16777216, "source_digest": source_digest(),
+    # the element-sort sweep the bench ran: of the variants (template arguments), the one with the
+    # most kernel time in the trace (the autotuner tries every variant a few times)
+    import csv
+    busy = {}
+    for r in csv.DictReader(open(trace_csv)):
+        k = short(r["Kernel_Name"])
+        if k.startswith("k_sort_sweep<3,"):
+            g = int(r["Grid_Size_X"]) * int(r["Grid_Size_Y"]) * int(r["Grid_Size_Z"])
+            busy[(k, g)] = busy.get((k, g), 0) + int(r["End_Timestamp"]) - int(r["Start_Timestamp"])
+    sc = max(busy, key=busy.get) if busy else None
+    if sc in result:
+        r_mb, w_mb = result[sc]
+        json.dump({"kernel": "k_sort_sweep", "variant": sc[0], "workload_events": 16777216,
+                   "source_digest": source_digest(),
                    "bytes_per_launch": (r_mb + w_mb) * 1e6, "read_bytes": r_mb * 1e6, "write_bytes": w_mb * 1e6,
                    "read_scale": sf, "write_scale": sw},
                   open(os.path.join(out_dir, "traffic.json"), "w"), indent=1)
@@ -151,6 +173,8 @@ def parse():
     ap.add_argument("--profile-all", action="store_true", help="print every kernel's time to stderr")
     ap.add_argument("--summarize-profiles", nargs=4, metavar=("TRACE_CSV", "FETCH_CSV", "WRITE_CSV", "COMMAND"),
                     help="write profiles/ summaries from rocprofv3 CSV files and exit")
+    ap.add_argument("--summarize-trace", nargs=4, metavar=("TRACE_CSV", "LABEL", "TITLE", "COMMAND"),
+                    help="write profiles/LABEL_kernel_stats.txt from a rocprofv3 kernel trace and exit")
     ap.add_argument("--workload", choices=("large", "batched", "served", "stencil"), default="large",
                     help="large: one 16M-event trace (default); batched: 512 traces, one pass vs one per trace; "
                          "served: Poisson arrivals through the request loop")
@@ -516,6 +540,9 @@ def main():
     if args.summarize_profiles:
         summarize_profiles(*args.summarize_profiles)
         return
+    if args.summarize_trace:
+        summarize_trace(*args.summarize_trace)
+        return
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the checker has no "
               f"multi-GPU path in this build", file=sys.stderr)
@@ -631,7 +658,10 @@ def main():
     if os.path.exists(tfile):
         try:
             t = json.load(open(tfile))
-            if t.get("kernel") == dom and t.get("workload_events") == n and t.get("source_digest") == source_digest():
+            rb, waves, items = rd.rd_tuning_get(variant)
+            same_variant = t.get("variant", "") == f"k_sort_sweep<3, {rb}, {waves}, {items}>"
+            if (t.get("kernel") == dom and same_variant and t.get("workload_events") == n
+                    and t.get("source_digest") == source_digest()):
                 traffic = t.get("bytes_per_launch")
         except Exception:
             traffic = None
