@@ -111,8 +111,14 @@ rd_status rd_trace_upload(rd_ctx ctx, const rd_grid *grid, const rd_event *event
                           int events_on_device, void *workspace, uint64_t workspace_bytes,
                           const rd_limits *limits, hipStream_t stream, rd_trace *out);
 
-/* Enqueues the whole check on `stream` and returns without waiting.  The workspace and the events
- * must stay valid until rd_races() returns or the stream is synchronised. */
+/* Enqueues the whole check on `stream` and returns without waiting; the report is sorted on the
+ * device as part of it.  The workspace and the events must stay valid until rd_races() returns or
+ * the stream is synchronised.  The first check of a trace is enqueued kernel by kernel; from the
+ * second on, the pass is captured once (on a stream of the context) into a HIP graph and each check
+ * is one graph launch on `stream`, captured again when the sort variant or the profiled kernels
+ * change (rd_set_tuning, rd_profile_enable).  The graph reads the events and the workspace at
+ * launch time, so device events rewritten in place are checked anew.  Checks of one trace must
+ * not overlap (they share its workspace). */
 rd_status rd_check(rd_ctx ctx, rd_trace trace, hipStream_t stream);
 
 /* Waits for the check and copies the report: min(capacity, total) pairs in canonical order into
@@ -224,9 +230,11 @@ rd_status rd_last_error(rd_ctx ctx, uint64_t *event_index, char *msg, uint64_t m
 
 /* Per-kernel timing (diagnostics).  rd_profile_enable(ctx, name) brackets every later launch of the
  * named kernel ("prefix*" = every kernel whose name starts with prefix, "*" = every kernel, NULL =
- * off) made by rd_check/rd_races on this context with HIP
- * events on the launch stream; rd_profile_read() waits for them and returns, per kernel name, the
- * number of launches and their summed duration since the last read (and resets the counters). */
+ * off) made by rd_check/rd_races on this context with HIP events on the launch stream (inside the
+ * captured graph for graph launches; a check collects the previous launch's times of that graph
+ * before launching it again, waiting for it); rd_profile_read() waits for them and returns, per
+ * kernel name, the number of launches and their summed duration since the last read or enable
+ * (and resets the counters). */
 typedef struct {
     char name[48];
     uint32_t launches;

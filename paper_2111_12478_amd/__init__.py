@@ -313,6 +313,7 @@ class RaceChecker:
         self.torch = torch
         self.device = device
         self.ctx = rd_init(device)
+        self._report_buf = np.zeros((1 << 16, 2), dtype=np.uint32)
 
     def close(self):
         if self.ctx:
@@ -360,17 +361,27 @@ class RaceChecker:
         return self.report(trace, capacity)
 
     def report(self, trace, capacity=None):
+        if capacity is None:
+            # one call into a reusable buffer; a second one only when the pairs do not fit
+            buf = self._report_buf
+            st, n = rd_races(self.ctx, trace, buf.ctypes.data, len(buf))
+            if st == RD_ETRUNC and n > len(buf):
+                buf = self._report_buf = np.zeros((n, 2), dtype=np.uint32)
+                st, n = rd_races(self.ctx, trace, buf.ctypes.data, len(buf))
+            if st != RD_OK:
+                idx, msg = rd_last_error(self.ctx)
+                return CheckResult(st, np.zeros((0, 2), np.uint32), idx, msg)
+            return CheckResult(st, buf[:n].copy())
         st, n = rd_races(self.ctx, trace, None, 0)
         if st not in (RD_OK, RD_ETRUNC):
             idx, msg = rd_last_error(self.ctx)
             return CheckResult(st, np.zeros((0, 2), np.uint32), idx, msg)
-        cap = n if capacity is None else capacity
-        out = np.zeros((max(cap, 1), 2), dtype=np.uint32)
-        st, n = rd_races(self.ctx, trace, out.ctypes.data, cap)
+        out = np.zeros((max(capacity, 1), 2), dtype=np.uint32)
+        st, n = rd_races(self.ctx, trace, out.ctypes.data, capacity)
         if st not in (RD_OK, RD_ETRUNC):
             idx, msg = rd_last_error(self.ctx)
             return CheckResult(st, np.zeros((0, 2), np.uint32), idx, msg)
-        return CheckResult(st, out[: min(cap, n)].copy())
+        return CheckResult(st, out[: min(capacity, n)].copy())
 
     def check_many(self, items, limits=None, batch_limits=None, workspace=None):
         """Batched form: items = [(grid, events), ...]; one rd_check_many over all of them, then

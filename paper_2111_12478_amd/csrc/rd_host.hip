@@ -1,4 +1,5 @@
 // rd_host.hip -- workspace layout, pipeline orchestration and the C interface of include/rd.h.
+#include <algorithm>
 #include <memory>
 #include <mutex>
 #include <new>
@@ -249,14 +250,35 @@ static Bufs make_bufs(const Plan &P, char *ws, const void *events_dev, u64 n, u3
 
 // ---------------------------------------------------------------- per-kernel timing
 
+struct ProfRec {
+    const char *name;
+    hipEvent_t a, b;
+    uint32_t launches;  // kernels between the two events
+};
+
+// A piece of a captured check.  Without profiling the whole check is one piece; with it, each
+// profiled kernel is a piece of its own (`name` set), so that a check brackets its launch with HIP
+// events on the launch stream.
+struct GraphSeg {
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    const char *name = nullptr;  // first profiled kernel of the piece
+    uint32_t launches = 0;       // profiled kernels in it (consecutive launches share a piece)
+};
+
 struct Profiler {
     std::string filter;  // "" off, "*" every kernel, else one kernel name
-    struct Rec { const char *name; hipEvent_t a, b; };
-    std::vector<Rec> recs;
+    std::vector<ProfRec> recs;
     std::vector<hipEvent_t> pool;
     size_t used = 0;
     const char *open_name = nullptr;
     hipEvent_t open_ev = nullptr;
+    std::vector<GraphSeg> *capture = nullptr;  // during a capture: where the pieces go
+    hipError_t cap_err = hipSuccess;
+    const char *group_name = nullptr;  // during a capture: the open piece of profiled kernels
+    uint32_t group_n = 0;
+    struct Acc { const char *name; uint32_t launches; double total_ms; };
+    std::vector<Acc> acc;  // collected times
     hipEvent_t get() {
         if (used == pool.size()) {
             hipEvent_t e;
@@ -265,6 +287,38 @@ struct Profiler {
         }
         return pool[used++];
     }
+    void add(const char *name, double ms, uint32_t launches) {
+        size_t k = 0;
+        while (k < acc.size() && strcmp(acc[k].name, name) != 0) k++;
+        if (k == acc.size()) acc.push_back({name, 0, 0.0});
+        acc[k].launches += launches;
+        acc[k].total_ms += ms;
+    }
+    // times of the records (waits for them)
+    bool collect() {
+        for (auto &r : recs) {
+            if (hipEventSynchronize(r.b) != hipSuccess) return false;
+            float ms = 0.f;
+            if (hipEventElapsedTime(&ms, r.a, r.b) != hipSuccess) return false;
+            add(r.name, ms, r.launches);
+        }
+        recs.clear();
+        used = 0;
+        return true;
+    }
+    // during a capture: close the piece so far and open the next one (`name`, `n`: the profiled
+    // kernels of the closed piece)
+    void cut(hipStream_t s, const char *name, uint32_t n) {
+        GraphSeg g;
+        hipError_t e = hipStreamEndCapture(s, &g.graph);
+        if (e == hipSuccess) {
+            g.name = name;
+            g.launches = n;
+            capture->push_back(g);
+            e = hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal);
+        }
+        if (e != hipSuccess && cap_err == hipSuccess) cap_err = e;
+    }
 };
 static thread_local Profiler *g_prof = nullptr;
 
@@ -272,11 +326,28 @@ void prof_begin(const char *name, hipStream_t s) {
     Profiler *p = g_prof;
     if (!p || p->filter.empty()) return;
     const std::string &f = p->filter;
-    if (f.back() == '*') {  // prefix match ("*" alone matches every kernel)
-        if (strncmp(name, f.c_str(), f.size() - 1) != 0) return;
-    } else if (f != name) {
+    bool match;
+    if (f.back() == '*') match = strncmp(name, f.c_str(), f.size() - 1) == 0;  // prefix ("*": every kernel)
+    else match = f == name;
+    if (p->capture) {
+        // consecutive profiled kernels form one piece, bracketed by one pair of events at launch
+        // (with "*", every kernel is a piece of its own)
+        if (match && p->group_name && f == "*") {
+            p->cut(s, p->group_name, p->group_n);
+            p->group_name = nullptr;
+        }
+        if (match && !p->group_name) {
+            p->cut(s, nullptr, 0);
+            p->group_name = name;
+            p->group_n = 0;
+        } else if (!match && p->group_name) {
+            p->cut(s, p->group_name, p->group_n);
+            p->group_name = nullptr;
+        }
+        if (match) p->group_n++;
         return;
     }
+    if (!match) return;
     hipEvent_t e = p->get();
     if (!e) return;
     hipEventRecord(e, s);
@@ -285,11 +356,11 @@ void prof_begin(const char *name, hipStream_t s) {
 }
 void prof_end(hipStream_t s) {
     Profiler *p = g_prof;
-    if (!p || !p->open_name) return;
+    if (!p || p->capture || !p->open_name) return;
     hipEvent_t e = p->get();
     if (e) {
         hipEventRecord(e, s);
-        p->recs.push_back({p->open_name, p->open_ev, e});
+        p->recs.push_back({p->open_name, p->open_ev, e, 1u});
     }
     p->open_name = nullptr;
 }
@@ -310,6 +381,15 @@ hipError_t enqueue_check(const Bufs &b, u64 *masks, u32 *rt_scan, hipStream_t s)
     return hipGetLastError();
 }
 
+// A check of one trace with its report sorted on the device (count read on the device too), so the
+// whole pass needs no host decision and can be captured.
+hipError_t enqueue_plain(const Bufs &b, u64 *masks, u32 *rt_scan, hipStream_t s) {
+    const hipError_t e = enqueue_check(b, masks, rt_scan, s);
+    if (e != hipSuccess) return e;
+    sort_pairs(b, &b.prm->n_pairs_kept, 0, b.max_pairs, s);
+    return hipGetLastError();
+}
+
 }  // namespace rd
 
 // ================================================================ C interface
@@ -323,6 +403,7 @@ struct rd_ctx_s {
     uint64_t last_index;
     std::string last_msg;
     Profiler prof;
+    hipStream_t cap_stream = nullptr;  // where checks are captured into graphs
 };
 
 // A batched check: the merged trace's workspace and the member table.  Shared by the member traces
@@ -365,6 +446,12 @@ struct rd_trace_s {
     uint64_t cache_idx, cache_n;
     std::string cache_msg;
     std::vector<rd_pair> cache;
+    // the plain check captured into a graph (replayed by later checks of the same trace)
+    std::vector<GraphSeg> segs;
+    u32 graph_variant = 0;
+    std::string graph_filter;
+    bool graph_off = false;  // capture failed once: checks are enqueued kernel by kernel
+    uint64_t n_checks = 0;
 };
 
 // A captured batched pass: replayed by rd_graph_launch for the same members and workspace.
@@ -451,6 +538,7 @@ rd_status rd_init(int hip_device, rd_ctx *out) {
 rd_status rd_shutdown(rd_ctx ctx) {
     if (!ctx) return RD_EINVAL;
     for (hipEvent_t e : ctx->prof.pool) hipEventDestroy(e);
+    if (ctx->cap_stream) (void)hipStreamDestroy(ctx->cap_stream);
     delete ctx;
     return RD_OK;
 }
@@ -522,6 +610,88 @@ rd_status rd_trace_upload(rd_ctx ctx, const rd_grid *grid, const rd_event *event
     return RD_OK;
 }
 
+// Releases a trace's captured check.
+static void graph_drop(rd_trace t) {
+    for (GraphSeg &g : t->segs) {
+        if (g.exec) (void)hipGraphExecDestroy(g.exec);
+        if (g.graph) (void)hipGraphDestroy(g.graph);
+    }
+    t->segs.clear();
+}
+
+// Captures the trace's plain check into graph pieces (cut around the profiled kernels).
+static bool graph_capture(rd_ctx ctx, rd_trace t) {
+    if (!ctx->cap_stream && hipStreamCreateWithFlags(&ctx->cap_stream, hipStreamNonBlocking) != hipSuccess) {
+        ctx->cap_stream = nullptr;
+        return false;
+    }
+    hipStream_t cs = ctx->cap_stream;
+    Profiler &p = ctx->prof;
+    Profiler *saved = g_prof;
+    g_prof = p.filter.empty() ? nullptr : &p;
+    p.capture = &t->segs;
+    p.cap_err = hipSuccess;
+    p.open_name = nullptr;
+    p.group_name = nullptr;
+    hipError_t e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
+    hipError_t e2 = hipSuccess;
+    if (e == hipSuccess) {
+        e2 = enqueue_plain(t->bufs, t->masks, t->rt_scan, cs);
+        GraphSeg last;
+        e = hipStreamEndCapture(cs, &last.graph);
+        last.name = p.group_name;
+        last.launches = p.group_name ? p.group_n : 0;
+        if (e == hipSuccess) t->segs.push_back(last);
+    }
+    p.group_name = nullptr;
+    if (e2 == hipSuccess) e2 = p.cap_err;
+    p.capture = nullptr;
+    p.open_name = nullptr;
+    g_prof = saved;
+    // pieces without a node (between two profiled kernels) are left out
+    std::vector<GraphSeg> kept;
+    for (GraphSeg &g : t->segs) {
+        size_t nodes = 0;
+        if (e == hipSuccess && e2 == hipSuccess && hipGraphGetNodes(g.graph, nullptr, &nodes) == hipSuccess && !nodes) {
+            (void)hipGraphDestroy(g.graph);
+            continue;
+        }
+        kept.push_back(g);
+    }
+    t->segs.swap(kept);
+    for (GraphSeg &g : t->segs) {
+        if (e != hipSuccess || e2 != hipSuccess) break;
+        e = hipGraphInstantiate(&g.exec, g.graph, nullptr, nullptr, 0);
+    }
+    if (e != hipSuccess || e2 != hipSuccess) {
+        (void)hipGetLastError();
+        graph_drop(t);
+        return false;
+    }
+    t->graph_variant = ctx->sort_variant;
+    t->graph_filter = p.filter;
+    return true;
+}
+
+// One check as launches of the captured pieces; a profiled kernel's piece is bracketed by events.
+static hipError_t graph_launch(rd_ctx ctx, rd_trace t, hipStream_t stream) {
+    Profiler &p = ctx->prof;
+    for (GraphSeg &g : t->segs) {
+        hipEvent_t a = nullptr, b = nullptr;
+        if (g.name && !p.filter.empty()) {
+            a = p.get();
+            if (a && hipEventRecord(a, stream) != hipSuccess) a = nullptr;
+        }
+        const hipError_t e = hipGraphLaunch(g.exec, stream);
+        if (e != hipSuccess) return e;
+        if (a) {
+            b = p.get();
+            if (b && hipEventRecord(b, stream) == hipSuccess) p.recs.push_back({g.name, a, b, g.launches});
+        }
+    }
+    return hipSuccess;
+}
+
 rd_status rd_check(rd_ctx ctx, rd_trace trace, hipStream_t stream) {
     if (!ctx || !trace) return RD_EINVAL;
     if (!trace->ws) return set_err(ctx, RD_ESTATE, UINT64_MAX, "the trace has no workspace: check it with rd_check_many");
@@ -531,9 +701,23 @@ rd_status rd_check(rd_ctx ctx, rd_trace trace, hipStream_t stream) {
     trace->cached = 0;
     trace->bufs.sort_variant = ctx->sort_variant;
     trace->bufs.radix_bits = kSortVariants[ctx->sort_variant].rb;
+    // from the second check of a trace on, the pass is one graph launch (captured again when the
+    // sort variant or the profiled kernels change)
+    if (trace->n_checks++ > 0 && !trace->graph_off) {
+        if (trace->segs.empty() || trace->graph_variant != ctx->sort_variant || trace->graph_filter != ctx->prof.filter) {
+            graph_drop(trace);
+            if (!graph_capture(ctx, trace)) trace->graph_off = true;
+        }
+        if (!trace->segs.empty()) {
+            const hipError_t e = graph_launch(ctx, trace, stream);
+            if (e != hipSuccess) return set_err(ctx, RD_EHIP, UINT64_MAX, hipGetErrorString(e));
+            trace->checked = 1;
+            return RD_OK;
+        }
+    }
     Profiler *saved = g_prof;
     g_prof = ctx->prof.filter.empty() ? nullptr : &ctx->prof;
-    const hipError_t e = enqueue_check(trace->bufs, trace->masks, trace->rt_scan, stream);
+    const hipError_t e = enqueue_plain(trace->bufs, trace->masks, trace->rt_scan, stream);
     g_prof = saved;
     if (e != hipSuccess) return set_err(ctx, RD_EHIP, UINT64_MAX, hipGetErrorString(e));
     trace->checked = 1;
@@ -619,19 +803,13 @@ static rd_status plain_races(rd_ctx ctx, const Bufs &b, hipStream_t s, rd_pair *
     const u32 m = prm.n_pairs_kept;
     *n_races = m;
     if (!out || !capacity || !m) return m > capacity ? set_err(ctx, RD_ETRUNC, UINT64_MAX, "capacity") : RD_OK;
-    Profiler *saved = g_prof;
-    g_prof = ctx->prof.filter.empty() ? nullptr : &ctx->prof;
-    sort_pairs(b, nullptr, m, m, s);
-    g_prof = saved;
+    // the check sorted the pairs (enqueue_plain)
     const u64 k = capacity < m ? capacity : m;
     std::vector<u32> f(k), sec(k);
-    u32 err_after = 0;
     if (hipMemcpyAsync(f.data(), b.pfirst[0], 4 * k, hipMemcpyDeviceToHost, s) != hipSuccess ||
         hipMemcpyAsync(sec.data(), b.psecond[0], 4 * k, hipMemcpyDeviceToHost, s) != hipSuccess ||
-        hipMemcpyAsync(&err_after, &b.prm->err, 4, hipMemcpyDeviceToHost, s) != hipSuccess ||
         hipStreamSynchronize(s) != hipSuccess)
         return set_err(ctx, RD_EHIP, UINT64_MAX, "copying the pairs failed");
-    if (err_after & ERR_SORT) return set_err(ctx, RD_EHIP, UINT64_MAX, "pair sort look-back did not finish");
     for (u64 q = 0; q < k; q++) { out[q].first = f[q]; out[q].second = sec[q]; }
     if (capacity < m) return set_err(ctx, RD_ETRUNC, UINT64_MAX, "more races than capacity");
     return RD_OK;
@@ -653,7 +831,7 @@ static rd_status member_alone(rd_ctx ctx, rd_trace trace, rd_pair *out, uint64_t
         b.radix_bits = kSortVariants[ctx->sort_variant].rb;
         Profiler *saved = g_prof;
         g_prof = ctx->prof.filter.empty() ? nullptr : &ctx->prof;
-        const hipError_t e = enqueue_check(b, (u64 *)(B.ws + P.off_masks), (u32 *)(B.ws + P.off_rt_scan), B.stream);
+        const hipError_t e = enqueue_plain(b, (u64 *)(B.ws + P.off_masks), (u32 *)(B.ws + P.off_rt_scan), B.stream);
         g_prof = saved;
         if (e != hipSuccess) return set_err(ctx, RD_EHIP, UINT64_MAX, hipGetErrorString(e));
         uint64_t n = 0;
@@ -1014,41 +1192,35 @@ rd_status rd_autotune(rd_ctx ctx, const rd_trace *traces, uint32_t n, void *batc
 
 rd_status rd_trace_free(rd_ctx ctx, rd_trace trace) {
     if (!ctx || !trace) return RD_EINVAL;
+    graph_drop(trace);
     delete trace;
     return RD_OK;
 }
 
 rd_status rd_profile_enable(rd_ctx ctx, const char *kernel) {
     if (!ctx) return RD_EINVAL;
-    ctx->prof.filter = kernel ? kernel : "";
-    ctx->prof.recs.clear();
-    ctx->prof.used = 0;
+    Profiler &p = ctx->prof;
+    p.filter = kernel ? kernel : "";
+    p.recs.clear();
+    p.used = 0;
+    p.acc.clear();
     return RD_OK;
 }
 
 rd_status rd_profile_read(rd_ctx ctx, rd_kernel_time *out, uint32_t capacity, uint32_t *n_out) {
     if (!ctx || !n_out) return RD_EINVAL;
     Profiler &p = ctx->prof;
-    std::vector<rd_kernel_time> acc;
-    for (auto &r : p.recs) {
-        if (hipEventSynchronize(r.b) != hipSuccess) return RD_EHIP;
-        float ms = 0.f;
-        if (hipEventElapsedTime(&ms, r.a, r.b) != hipSuccess) return RD_EHIP;
-        size_t k = 0;
-        while (k < acc.size() && strcmp(acc[k].name, r.name) != 0) k++;
-        if (k == acc.size()) {
-            rd_kernel_time z;
-            memset(&z, 0, sizeof(z));
-            strncpy(z.name, r.name, sizeof(z.name) - 1);
-            acc.push_back(z);
-        }
-        acc[k].launches++;
-        acc[k].total_ms += ms;
+    if (!p.collect()) return RD_EHIP;
+    *n_out = (uint32_t)p.acc.size();
+    for (uint32_t k = 0; k < p.acc.size() && k < capacity && out; k++) {
+        rd_kernel_time z;
+        memset(&z, 0, sizeof(z));
+        strncpy(z.name, p.acc[k].name, sizeof(z.name) - 1);
+        z.launches = p.acc[k].launches;
+        z.total_ms = p.acc[k].total_ms;
+        out[k] = z;
     }
-    p.recs.clear();
-    p.used = 0;
-    *n_out = (uint32_t)acc.size();
-    for (uint32_t k = 0; k < acc.size() && k < capacity && out; k++) out[k] = acc[k];
+    p.acc.clear();
     return RD_OK;
 }
 

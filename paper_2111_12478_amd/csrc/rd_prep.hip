@@ -508,7 +508,15 @@ __global__ __launch_bounds__(WG_THREADS) void k_elements(Bufs b, const u64 *acc_
             const u32 j = list_search(b, t, idx);
             if (j != NONE) {
                 ph = b.s_phase[j];
-                if (kind <= 1 && b.s_imin[j] > idx) atomicMin(&b.s_imin[j], idx);
+                // the first plain access after an atomic, a fence or a warp barrier (release/acquire
+                // inference, warp-barrier rule); after a block barrier the access checks the rule itself
+                const u32 kj = b.s_kind[j];
+                if (kind <= 1 && (kj == 2 || kj == 3 || kj == 5) && b.s_imin[j] > idx) atomicMin(&b.s_imin[j], idx);
+                if (ph > 0) {
+                    const u32 slot = b.inst_off[blk] + ph - 1;
+                    if (b.inst_cnt[slot] != b.n_active[blk] || b.inst_last[slot] > idx)
+                        atomicMin(&b.prm->first_bad_sync, idx);
+                }
             }
         } else if (mode & MODE_BAR) {
             // the thread's list holds only its barriers: the phase is the number of entries before idx,
@@ -526,7 +534,19 @@ __global__ __launch_bounds__(WG_THREADS) void k_elements(Bufs b, const u64 *acc_
         eidx[o] = idx;
         etid[o] = t;
         einfo[o] = info_make(cat, ph);
-        for (u32 q = 0; q < np; q++) atomicAdd(&dcnt[q][(key >> (q * rb)) & (nd - 1)], 1u);
+        // digit counts: where every active lane has the wavefront's first digit (high digits of
+        // clustered addresses), one lane adds them all instead of 64 atomics on one LDS word
+        const u64 act = ballot(true);
+        const u32 first = (u32)__builtin_ctzll(act);
+        for (u32 q = 0; q < np; q++) {
+            const u32 d = (key >> (q * rb)) & (nd - 1);
+            const u32 d0 = __shfl(d, first, 64);
+            if (ballot(d == d0) == act) {
+                if (lane == first) atomicAdd(&dcnt[q][d0], popc64(act));
+            } else {
+                atomicAdd(&dcnt[q][d], 1u);
+            }
+        }
     }
     __syncthreads();
     u32 *row = b.sort_partial + (u64)blockIdx.x * ELEM_MAX_PASSES * SORT_NDS;
@@ -565,6 +585,7 @@ __global__ void k_thread_sync(Bufs b, u32 *rt_flag) {
             }
             if (kind == 4) {
                 // the first event of t after its k-th barrier must follow the instance's last arrival
+                // (for the sync entries here; every access after a barrier checks this itself)
                 const u32 slot = b.inst_off[blk] + k;
                 k++;
                 u32 next = b.s_imin[p];

@@ -89,6 +89,44 @@ def test_repeat_check_same_trace(rc):
     np.testing.assert_array_equal(a.pairs, oracle.check(grid, ev).pairs)
 
 
+def test_graph_replays_follow_the_events(rc):
+    # from its second check on, a trace's check is one graph launch: replays with other sort
+    # variants, with and without profiled kernels, and over device events rewritten in place (the
+    # graph reads them again) all match the oracle
+    import ctypes
+    import torch
+    from paper_2111_12478_amd import load_library, rd_get_tuning, rd_set_tuning, rd_trace_free
+    grid, ev_a, _, _ = tracegen.generate(tracegen.tiny(seed=11))
+    grid_b, ev_b, _, _ = tracegen.generate(tracegen.tiny(seed=12))
+    assert tuple(grid_b) == tuple(grid) and ev_a.shape == ev_b.shape
+    want = {}
+    for name, e in (("a", ev_a), ("b", ev_b)):
+        want[name] = oracle.check(grid, e)
+    dev = torch.from_numpy(ev_a.view(np.int32).copy()).cuda()
+    tr, ws, keep = rc.prepare(grid, dev)
+    lib = load_library()
+    lib.rd_profile_enable.argtypes = [ctypes.c_void_p, ctypes.c_char_p]
+    saved = rd_get_tuning(rc.ctx)
+    try:
+        for step, (name, variant, prof) in enumerate([("a", 0, False), ("a", 0, False), ("b", 0, False),
+                                                      ("b", 3, False), ("a", 3, True), ("a", 3, True),
+                                                      ("b", 5, False), ("a", 0, False)]):
+            src = ev_a if name == "a" else ev_b
+            dev.copy_(torch.from_numpy(src.view(np.int32)))
+            rd_set_tuning(rc.ctx, variant)
+            lib.rd_profile_enable(rc.ctx, b"*" if prof else None)
+            got = rc.run(tr)
+            torch.cuda.synchronize()
+            w = want[name]
+            assert got.status == w.status, (step, got, w)
+            if w.status == 0:
+                np.testing.assert_array_equal(got.pairs, w.pairs, err_msg=f"step {step}")
+    finally:
+        lib.rd_profile_enable(rc.ctx, None)
+        rd_set_tuning(rc.ctx, saved)
+        rd_trace_free(rc.ctx, tr)
+
+
 def test_device_resident_events(rc):
     import torch
     grid, ev, _, _ = tracegen.generate(tracegen.tiny(seed=9))
