@@ -16,7 +16,9 @@
 // keeps, for write-ish, plain and all accesses, one thread and whether a second one appears.  If
 // every earlier access of the segment is in b's block, only b's run can race with b (earlier phases
 // of a block happen before later ones), and only if a conflicting class there has another thread.
-// Otherwise b is checked against the earlier accesses one by one (the exact predicate above).
+// Otherwise b is checked against the earlier accesses one by one (the exact predicate above): by a
+// backward walk that stops early when the prefix holds at most two blocks (see lane_walks), else
+// by queued chunks of 64 positions, one wavefront each.
 // The summaries form a segmented scan: per-tile totals, one scan over tiles, then the tile pass.
 #include "rd_internal.h"
 #include "rd_kernels.h"
