@@ -678,7 +678,7 @@ def main():
         try:
             t = json.load(open(tfile))
             rb, waves, items = rd.rd_tuning_get(variant)
-            same_variant = t.get("variant", "") == f"k_sort_sweep<3, {rb}, {waves}, {items}>"
+            same_variant = t.get("variant", "") == f"k_sort_sweep<3, {rb}, {waves}, {items}, false>"
             if (t.get("kernel") == dom and same_variant and t.get("workload_events") == n
                     and t.get("source_digest") == source_digest()):
                 traffic = t.get("bytes_per_launch")

@@ -36,46 +36,56 @@ __device__ inline bool eng_on(const DevParams *P) { return eng_active(P) && !(P-
 
 // buffer of the location sort's result (digits of the context's variant), and of a key-value
 // sort by location key (8-bit digits)
-__device__ inline u32 elem_buf(const Bufs &b) { return ((b.prm->key_bits + b.radix_bits - 1) / b.radix_bits) & 1u; }
-__device__ inline u32 sorted_buf(const DevParams *P) { return ((P->key_bits + SORT_RB - 1) / SORT_RB) & 1u; }
 
 // ---------------------------------------------------------------- release/acquire accesses
 
-// e_scan0[i] = 1 when sorted element i is a release/acquire access; i <= n_acc (scanned next).
+// e_scan0[q] = 1 when the trace-ordered sync entry q is a release/acquire access (an atomic, a lock
+// acquire or a lock release with a release or acquire role); q <= n_sync (scanned next).
 __global__ void k_eng_flag(Bufs b) {
     const DevParams *P = b.prm;
     if (!eng_active(P)) return;
-    const u32 n = P->n_acc, c = elem_buf(b);
-    for (u32 i = blockIdx.x * blockDim.x + threadIdx.x; i <= n; i += gridDim.x * blockDim.x) {
+    const u32 n = P->n_sync;
+    for (u32 q = blockIdx.x * blockDim.x + threadIdx.x; q <= n; q += gridDim.x * blockDim.x) {
         u32 f = 0;
-        if (i < n) {
-            const u32 idx = b.eidx[c][i];
-            const u32 kind = b.ev[idx].z & 15u;
-            if (kind == 2u || kind == 6u || kind == 7u) {
-                const u32 j = list_search(b, b.etid[c][i], idx + 1);
-                if (j != NONE && b.s_pidx[j] == idx && (b.s_flags[j] & (SF_REL | SF_ACQ))) f = 1;
-            }
+        if (q < n) {
+            const u32 p = b.s_inv[q], kind = b.s_kind[p];
+            if ((kind == 2u || kind == 6u || kind == 7u) && (b.s_flags[p] & (SF_REL | SF_ACQ))) f = 1;
         }
-        b.e_scan0[i] = f;
+        b.e_scan0[q] = f;
     }
 }
 
-// ral_p / ral_key: the release/acquire accesses in (location, trace) order; fallback if too many.
+// ral_p / ral_key: the release/acquire accesses in trace order with their location keys (sorted by
+// location next, stably, which gives (location, trace) order); fallback if too many.
 __global__ void k_eng_compact(Bufs b) {
     DevParams *P = b.prm;
     if (!eng_active(P)) return;
-    const u32 n = P->n_acc, c = elem_buf(b), total = b.e_scan0[n];
+    const u32 n = P->n_sync, total = b.e_scan0[n];
     if (blockIdx.x == 0 && threadIdx.x == 0) {
         P->n_ral = total > b.ecap ? 0u : total;
         if (total > b.ecap) atomicOr(&P->eng, ENG_FALLBACK);
     }
     if (total > b.ecap) return;
-    for (u32 i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
-        const u32 r = b.e_scan0[i];
-        if (b.e_scan0[i + 1] == r) continue;
-        const u32 idx = b.eidx[c][i];
-        b.ral_p[r] = list_search(b, b.etid[c][i], idx + 1);
-        b.ral_key[r] = b.ekey[c][i];
+    const u32 gbase = P->gbase, sbase = P->sbase, g_span = P->g_span, s_span = P->s_span;
+    for (u32 q = blockIdx.x * blockDim.x + threadIdx.x; q < n; q += gridDim.x * blockDim.x) {
+        const u32 r = b.e_scan0[q];
+        if (b.e_scan0[q + 1] == r) continue;
+        const u32 p = b.s_inv[q];
+        const uint4 e = b.ev[b.s_pidx[p]];
+        const u32 space = (e.z >> 6) & 1u;
+        b.ral_key[r] = space ? g_span + block_of(b, e.y) * s_span + (e.x - sbase) : e.x - gbase;
+        b.ral_p[r] = p;
+    }
+}
+
+// The location sort of the list leaves it in the second buffers when its passes are odd in number:
+// copy it back.
+__global__ void k_eng_ral_back(Bufs b) {
+    const DevParams *P = b.prm;
+    if (!eng_active(P) || !(((P->key_bits + SORT_RB - 1) / SORT_RB) & 1u)) return;
+    for (u32 r = blockIdx.x * blockDim.x + threadIdx.x; r < P->n_ral; r += gridDim.x * blockDim.x) {
+        b.ral_key[r] = b.op_dep[r];
+        b.ral_p[r] = b.op_p[r];
     }
 }
 
@@ -271,13 +281,13 @@ __device__ inline bool inst_complete(const Bufs &b, u32 blk, u32 slot) {
     return b.inst_cnt[slot] == b.n_active[blk];
 }
 
-// Per trace-ordered sync entry q (and the padding up to N): is it an operation, and how many
-// vectors does it write.  e_scan0 / e_scan1 get 0/1 and the count (scanned next).
+// Per trace-ordered sync entry q <= n_sync: is it an operation, and how many vectors does it
+// write.  e_scan0 / e_scan1 get 0/1 and the count (scanned next).
 __global__ void k_eng_mark(Bufs b) {
     const DevParams *P = b.prm;
     if (!eng_on(P)) return;
     const u32 n_sync = P->n_sync;
-    for (u32 q = blockIdx.x * blockDim.x + threadIdx.x; q <= b.N; q += gridDim.x * blockDim.x) {
+    for (u32 q = blockIdx.x * blockDim.x + threadIdx.x; q <= n_sync; q += gridDim.x * blockDim.x) {
         u32 nout = 0;
         if (q < n_sync) {
             const u32 p = b.s_inv[q];
@@ -814,17 +824,25 @@ hipError_t engine_run(const Bufs &b, const u32 *rt_scan, hipStream_t s) {
     f.add(b.inst_coff, b.N, 0, 4, MODE_SYNC, b.inst_off + b.B, 1);
     f.add(b.inst_opo, b.N, NONE, 4, MODE_SYNC, b.inst_off + b.B, 1);
     fill_many(f, "k_fill_engine", s);
-    // chains of releases, over the release/acquire accesses in (location, trace) order
+    // chains of releases, over the release/acquire accesses in (location, trace) order: taken from
+    // the sync entries in trace order, then sorted by location (op_dep and op_p, free until the
+    // operations are numbered, are the sort's second buffers)
+    const u32 *n_sync = &b.prm->n_sync;
     RD_LAUNCH("k_eng_flag", k_eng_flag, dim3(grid_over(b.N + 1)), dim3(256), 0, s, b);
-    scan_exclusive(b.e_scan0, (u64)b.N + 1, b.part, s, gate);
+    scan_exclusive(b.e_scan0, (u64)b.N + 1, b.part, s, gate, n_sync);
     RD_LAUNCH("k_eng_compact", k_eng_compact, dim3(grid_over(b.N)), dim3(256), 0, s, b);
+    {
+        u32 *const k2[2] = {b.ral_key, b.op_dep}, *const v2[2] = {b.ral_p, b.op_p};
+        sort_kv(b, k2, v2, &b.prm->n_ral, b.ecap, 4, &b.prm->key_bits, "k_eng_ral_sort", s);
+    }
+    RD_LAUNCH("k_eng_ral_back", k_eng_ral_back, dim3(grid_over(b.ecap)), dim3(256), 0, s, b);
     RD_LAUNCH("k_eng_chains", k_eng_chains, dim3(1), dim3(1024), 0, s, b);
     RD_LAUNCH("k_eng_blk_walk", k_eng_blk_walk, dim3(grid_over(b.ecap, 1024)), dim3(256), 0, s, b);
     // operations and their inputs
     RD_LAUNCH("k_eng_walk", k_eng_walk, dim3(grid_over(b.T)), dim3(256), 0, s, b);
     RD_LAUNCH("k_eng_mark", k_eng_mark, dim3(grid_over(b.N + 1)), dim3(256), 0, s, b);
-    scan_exclusive(b.e_scan0, (u64)b.N + 1, b.part, s, gate);
-    scan_exclusive(b.e_scan1, (u64)b.N + 1, b.part, s, gate);
+    scan_exclusive(b.e_scan0, (u64)b.N + 1, b.part, s, gate, n_sync);
+    scan_exclusive(b.e_scan1, (u64)b.N + 1, b.part, s, gate, n_sync);
     RD_LAUNCH("k_eng_assign", k_eng_assign, dim3(grid_over(b.N)), dim3(256), 0, s, b);
     RD_LAUNCH("k_eng_bk", k_eng_bk, dim3(grid_over(b.B)), dim3(256), 0, s, b);
     RD_LAUNCH("k_eng_deps", k_eng_deps, dim3(grid_over(b.ecap)), dim3(256), 0, s, b);

@@ -38,16 +38,19 @@ static Plan make_plan(u64 n, u32 nb, u32 tpb, const rd_limits *lim, bool copy_ev
     const u64 N1 = n ? n : 1;
     P.n_tiles = n_tiles; P.T = (u32)T; P.B = nb; P.radix_bits = SORT_RB;
     P.pair_tiles = (u32)((max_pairs + TILE - 1) / TILE);
+    const u64 ecap = N1 / 4 > (1u << 20) ? N1 / 4 : (N1 < (1u << 20) ? N1 : (1u << 20));
     {
-        // look-back words per array: the largest tiles x digits over the sort variants and the pairs
-        u64 w = (u64)P.pair_tiles * SORT_ND;
+        // look-back words per array: the largest tiles x digits over the sort variants, the pairs and
+        // the knowledge engine's sort of its release/acquire list (at most ecap items)
+        const u64 small_tiles = (P.pair_tiles > (ecap + TILE - 1) / TILE ? P.pair_tiles : (ecap + TILE - 1) / TILE);
+        u64 w = small_tiles * SORT_ND;
         for (u32 v = 0; v < N_SORT_VARIANTS; v++) {
             const u64 ts = (u64)kSortVariants[v].waves * 64 * kSortVariants[v].items;
             const u64 x = ((N1 + ts - 1) / ts) << kSortVariants[v].rb;
             if (x > w) w = x;
         }
         P.status_words = w;
-        const u64 e = (u64)n_tiles * ELEM_MAX_PASSES, q = (u64)P.pair_tiles * MAX_SORT_PASSES;
+        const u64 e = (u64)n_tiles * ELEM_MAX_PASSES, q = small_tiles * MAX_SORT_PASSES;
         P.partial_words = (e > q ? e : q) * SORT_NDS;
     }
     u64 scan_max = N1 + 1;  // the knowledge engine scans per sync entry
@@ -82,7 +85,7 @@ static Plan make_plan(u64 n, u32 nb, u32 tpb, const rd_limits *lim, bool copy_ev
     L.off_s_know = take(4 * N1);
     L.off_s_khandle = take(4 * N1);
     L.off_s_winst = take(4 * N1);
-    L.ecap = (u32)(N1 / 4 > (1u << 20) ? N1 / 4 : (N1 < (1u << 20) ? N1 : (1u << 20)));
+    L.ecap = (u32)ecap;
     L.off_e_prev0 = take(4 * N1);
     L.off_e_prev1 = take(4 * N1);
     L.off_e_src0 = take(4 * N1);
@@ -350,7 +353,7 @@ void prof_begin(const char *name, hipStream_t s) {
     if (!match) return;
     hipEvent_t e = p->get();
     if (!e) return;
-    hipEventRecord(e, s);
+    (void)hipEventRecord(e, s);
     p->open_name = name;
     p->open_ev = e;
 }
@@ -359,7 +362,7 @@ void prof_end(hipStream_t s) {
     if (!p || p->capture || !p->open_name) return;
     hipEvent_t e = p->get();
     if (e) {
-        hipEventRecord(e, s);
+        (void)hipEventRecord(e, s);
         p->recs.push_back({p->open_name, p->open_ev, e, 1u});
     }
     p->open_name = nullptr;
@@ -537,7 +540,7 @@ rd_status rd_init(int hip_device, rd_ctx *out) {
 
 rd_status rd_shutdown(rd_ctx ctx) {
     if (!ctx) return RD_EINVAL;
-    for (hipEvent_t e : ctx->prof.pool) hipEventDestroy(e);
+    for (hipEvent_t e : ctx->prof.pool) (void)hipEventDestroy(e);
     if (ctx->cap_stream) (void)hipStreamDestroy(ctx->cap_stream);
     delete ctx;
     return RD_OK;

@@ -3,7 +3,8 @@
 #include "rd_internal.h"
 
 namespace rd {
-void scan_exclusive(u32 *data, u64 n, u32 *part, hipStream_t s, const u32 *gate = nullptr);
+void scan_exclusive(u32 *data, u64 n, u32 *part, hipStream_t s, const u32 *gate = nullptr,
+                    const u32 *n_dev = nullptr);
 void scan_exclusive_multi(u32 *data, u64 n, u32 regions, u32 *part, hipStream_t s);
 
 // several fills in one launch

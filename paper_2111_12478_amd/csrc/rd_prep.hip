@@ -80,10 +80,20 @@ __device__ inline bool eng_gate_open(const u32 *gate) {
     return !gate || ((*gate & ENG_PARALLEL) && !(*gate & ENG_FALLBACK));
 }
 
-__global__ __launch_bounds__(256) void k_scan_reduce(const u32 *in, u64 n, u32 *part, const u32 *gate) {
+// the length of a scan: n, or with n_dev the first *n_dev + 1 words (at most n)
+__device__ inline u64 scan_len(u64 n, const u32 *n_dev) {
+    if (!n_dev) return n;
+    const u64 m = (u64)*n_dev + 1;
+    return m < n ? m : n;
+}
+
+__global__ __launch_bounds__(256) void k_scan_reduce(const u32 *in, u64 n, u32 *part, const u32 *gate,
+                                                      const u32 *n_dev) {
     __shared__ u32 lds[8];
     if (!eng_gate_open(gate)) return;
+    n = scan_len(n, n_dev);
     u64 base = (u64)blockIdx.x * SCAN_CHUNK;
+    if (base >= n) return;
     u32 s = 0;
     for (u32 k = 0; k < 16; k++) {
         u64 i = base + k * 256 + threadIdx.x;
@@ -94,9 +104,13 @@ __global__ __launch_bounds__(256) void k_scan_reduce(const u32 *in, u64 n, u32 *
     if (threadIdx.x == 0) part[blockIdx.x] = tot;
 }
 // exclusive scan of the partials in one workgroup of 1024 threads
-__global__ __launch_bounds__(1024) void k_scan_top(u32 *part, u32 np, const u32 *gate) {
+__global__ __launch_bounds__(1024) void k_scan_top(u32 *part, u32 np, const u32 *gate, u64 n, const u32 *n_dev) {
     __shared__ u32 lds[1024];
     if (!eng_gate_open(gate)) return;
+    {
+        const u64 npe = (scan_len(n, n_dev) + SCAN_CHUNK - 1) / SCAN_CHUNK;
+        if (npe < np) np = (u32)npe;
+    }
     u32 per = (np + 1023) / 1024;
     u32 lo = threadIdx.x * per, hi = lo + per < np ? lo + per : np;
     u32 s = 0;
@@ -113,9 +127,12 @@ __global__ __launch_bounds__(1024) void k_scan_top(u32 *part, u32 np, const u32 
     for (u32 i = lo; i < hi; i++) { u32 v = part[i]; part[i] = run; run += v; }
 }
 // in-place exclusive scan of each chunk plus its carry
-__global__ __launch_bounds__(256) void k_scan_apply(u32 *data, u64 n, const u32 *part, const u32 *gate) {
+__global__ __launch_bounds__(256) void k_scan_apply(u32 *data, u64 n, const u32 *part, const u32 *gate,
+                                                     const u32 *n_dev) {
     __shared__ u32 lds[8];
     if (!eng_gate_open(gate)) return;
+    n = scan_len(n, n_dev);
+    if ((u64)blockIdx.x * SCAN_CHUNK >= n) return;
     u64 base = (u64)blockIdx.x * SCAN_CHUNK + (u64)threadIdx.x * 16;
     u32 v[16], s = 0;
     for (u32 k = 0; k < 16; k++) { u64 i = base + k; v[k] = i < n ? data[i] : 0; s += v[k]; }
@@ -127,9 +144,10 @@ __global__ __launch_bounds__(256) void k_scan_apply(u32 *data, u64 n, const u32 
 // Small arrays in one workgroup each: region blockIdx.x of `regions` consecutive arrays of n words,
 // n <= SCAN_SMALL; every thread scans a run of up to 16 consecutive words.
 constexpr u32 SCAN_SMALL = 1024 * 16;
-__global__ __launch_bounds__(1024) void k_scan_small(u32 *data, u32 n, const u32 *gate) {
+__global__ __launch_bounds__(1024) void k_scan_small(u32 *data, u32 n, const u32 *gate, const u32 *n_dev) {
     __shared__ u32 wsum[16];
     if (!eng_gate_open(gate)) return;
+    n = (u32)scan_len(n, n_dev);
     u32 *d = data + (u64)blockIdx.x * n;
     const u32 per = (n + 1023) / 1024, lo = threadIdx.x * per, hi = lo + per < n ? lo + per : n;
     const u32 lane = lane_id(), w = threadIdx.x >> 6;
@@ -160,24 +178,26 @@ __global__ __launch_bounds__(1024) void k_scan_small(u32 *data, u32 n, const u32
 void scan_exclusive_multi(u32 *data, u64 n, u32 regions, u32 *part, hipStream_t s) {
     if (!n || !regions) return;
     if (n <= SCAN_SMALL) {
-        RD_LAUNCH("k_scan_small", k_scan_small, dim3(regions), dim3(1024), 0, s, data, (u32)n, (const u32 *)nullptr);
+        RD_LAUNCH("k_scan_small", k_scan_small, dim3(regions), dim3(1024), 0, s, data, (u32)n, (const u32 *)nullptr,
+                  (const u32 *)nullptr);
         return;
     }
     for (u32 r = 0; r < regions; r++) scan_exclusive(data + (u64)r * n, n, part, s);
 }
 
 // Exclusive scan of data[0..n) in place; `part` needs ceil(n / 4096) words (<= 2^20).  With a gate,
-// nothing happens unless the knowledge engine is on.
-void scan_exclusive(u32 *data, u64 n, u32 *part, hipStream_t s, const u32 *gate) {
+// nothing happens unless the knowledge engine is on.  With n_dev, only the first *n_dev + 1 words
+// (at most n) are scanned: launches are sized for n, the workgroups past the length exit at once.
+void scan_exclusive(u32 *data, u64 n, u32 *part, hipStream_t s, const u32 *gate, const u32 *n_dev) {
     if (!n) return;
     if (n <= SCAN_SMALL) {
-        RD_LAUNCH("k_scan_small", k_scan_small, dim3(1), dim3(1024), 0, s, data, (u32)n, gate);
+        RD_LAUNCH("k_scan_small", k_scan_small, dim3(1), dim3(1024), 0, s, data, (u32)n, gate, n_dev);
         return;
     }
     u32 np = (u32)((n + SCAN_CHUNK - 1) / SCAN_CHUNK);
-    RD_LAUNCH("k_scan_reduce", k_scan_reduce, dim3(np), dim3(256), 0, s, data, n, part, gate);
-    RD_LAUNCH("k_scan_top", k_scan_top, dim3(1), dim3(1024), 0, s, part, np, gate);
-    RD_LAUNCH("k_scan_apply", k_scan_apply, dim3(np), dim3(256), 0, s, data, n, part, gate);
+    RD_LAUNCH("k_scan_reduce", k_scan_reduce, dim3(np), dim3(256), 0, s, data, n, part, gate, n_dev);
+    RD_LAUNCH("k_scan_top", k_scan_top, dim3(1), dim3(1024), 0, s, part, np, gate, n, n_dev);
+    RD_LAUNCH("k_scan_apply", k_scan_apply, dim3(np), dim3(256), 0, s, data, n, part, gate, n_dev);
 }
 
 // ---------------------------------------------------------------- init

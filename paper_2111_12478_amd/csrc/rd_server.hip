@@ -218,7 +218,7 @@ static void worker(rd_server s, uint32_t k, int dev) {
                 final_st[j] = rs;
             }
         }
-        hipStreamSynchronize(st);
+        (void)hipStreamSynchronize(st);
         {
             std::lock_guard<std::mutex> g(s->mu);
             const double t = s->now();
@@ -262,7 +262,7 @@ rd_status rd_server_open(rd_ctx ctx, void *device_arena, const rd_server_config 
         hipStream_t st;
         rd_ctx c = nullptr;
         if (hipStreamCreate(&st) != hipSuccess || rd_init(dev, &c) != RD_OK) {
-            for (hipStream_t x : s->streams) hipStreamDestroy(x);
+            for (hipStream_t x : s->streams) (void)hipStreamDestroy(x);
             for (rd_ctx x : s->wctx) rd_shutdown(x);
             delete s;
             return RD_EHIP;
@@ -347,7 +347,7 @@ rd_status rd_server_close(rd_server s) {
     }
     s->cv_work.notify_all();
     for (auto &w : s->workers) w.join();
-    for (hipStream_t x : s->streams) hipStreamDestroy(x);
+    for (hipStream_t x : s->streams) (void)hipStreamDestroy(x);
     for (rd_ctx x : s->wctx) rd_shutdown(x);
     for (auto &kv : s->all) delete kv.second;
     delete s;

@@ -38,11 +38,11 @@ __global__ __launch_bounds__(WG_THREADS) void k_pair_count(const u32 *first, con
     const u32 m = m_dev ? *m_dev : m_host;
     if (blockIdx.x == 0)  // totals and the tile tickets that follow them
         for (u32 q = threadIdx.x; q < MAX_SORT_PASSES * SORT_NDS + MAX_SORT_PASSES; q += WG_THREADS) tot[q] = 0;
-    const u64 base = (u64)blockIdx.x * TILE;
-    if (base >= m) return;
+    for (u32 tile = blockIdx.x; (u64)tile * TILE < m; tile += gridDim.x) {
+    const u64 base = (u64)tile * TILE;
 #pragma unroll
     for (u32 q = 0; q < MAX_SORT_PASSES; q++) h[q][threadIdx.x] = 0;
-    status0[(u64)blockIdx.x * SORT_ND + threadIdx.x] = 0;
+    status0[(u64)tile * SORT_ND + threadIdx.x] = 0;
     __syncthreads();
     u32 f[ITEMS], sc[ITEMS];
 #pragma unroll
@@ -61,8 +61,10 @@ __global__ __launch_bounds__(WG_THREADS) void k_pair_count(const u32 *first, con
         }
     }
     __syncthreads();
-    u32 *row = partial + (u64)blockIdx.x * MAX_SORT_PASSES * SORT_NDS;
+    u32 *row = partial + (u64)tile * MAX_SORT_PASSES * SORT_NDS;
     for (u32 q = 0; q < np; q++) row[q * SORT_NDS + threadIdx.x] = h[q][threadIdx.x];
+    __syncthreads();
+    }
 }
 
 // Adds the rows of per-tile counts into the pass totals: workgroup (p, c) sums rows
@@ -122,7 +124,7 @@ constexpr int LOOKBACK = 4;  // predecessor words read at once per digit
 
 // One pass: 2^RB digits, NW wavefronts per workgroup, NI items per lane (tile NW * 64 * NI).
 // Look-back words of a tile: 2^RB, consecutive.
-template <int NP, int RB, int NW, int NI>
+template <int NP, int RB, int NW, int NI, bool LOOP = false>
 __global__ __launch_bounds__(NW * 64) void k_sort_sweep(SweepArgs a) {
     constexpr u32 ND = 1u << RB, DM = ND - 1, THREADS = NW * 64, TS = THREADS * NI;
     static_assert(ND <= THREADS, "one digit per thread");
@@ -132,7 +134,14 @@ __global__ __launch_bounds__(NW * 64) void k_sort_sweep(SweepArgs a) {
     const u32 n_tiles = (u32)(((u64)n + TS - 1) / TS);
     const u32 w = threadIdx.x >> 6, lane = lane_id(), dme = threadIdx.x;  // digit dme when dme < ND
     const bool has_d = dme < ND;
-    if (threadIdx.x == 0) L.tile = atomicAdd(&a.ctr[a.pass], 1u);
+    // tiles by ticket, in order; with LOOP, until none is left (a grid smaller than the tile count)
+    do {
+    if (threadIdx.x == 0) {
+        // looping grids outnumber the tiles of small sorts: the ticket counter only grows, so once
+        // it is past the tiles a workgroup leaves without taking one
+        const u32 seen = LOOP ? __hip_atomic_load(&a.ctr[a.pass], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) : 0u;
+        L.tile = seen >= n_tiles && LOOP ? seen : atomicAdd(&a.ctr[a.pass], 1u);
+    }
     if (has_d) {
 #pragma unroll
         for (u32 q = 0; q < NW; q++) L.wcnt[q][dme] = 0;
@@ -275,6 +284,8 @@ __global__ __launch_bounds__(NW * 64) void k_sort_sweep(SweepArgs a) {
         for (int r = 0; r < NI; r++)
             if (gpos[r] != NONE) a.pout[q][gpos[r]] = L.stage[r * THREADS + threadIdx.x];
     }
+    if (LOOP) __syncthreads();  // the LDS is reused for the next tile
+    } while (LOOP);
 }
 
 static const char *const kSweepName[ELEM_MAX_PASSES] = {"k_sort_sweep_p0", "k_sort_sweep_p1", "k_sort_sweep_p2",
@@ -344,14 +355,18 @@ void sort_elements(const Bufs &b, hipStream_t s) {
 // Pairs: sort by (first, second) -- LSD over second, then over first.  The pair count is *m_dev
 // (device-driven launches sized for max_m pairs) or m_host.  An even number of passes leaves the
 // result in buffer 0.
+// Sorts whose item count is read on the device are launched with at most this many workgroups;
+// their kernels loop over the tiles.
+constexpr u32 SMALL_SORT_GRID = 256;
+
 void sort_pairs(const Bufs &b, const u32 *m_dev, u32 m_host, u64 max_m, hipStream_t s) {
     u32 bits = 0;
     while (bits < 32 && ((u64)1 << bits) < (u64)b.N) bits++;
     const u32 half = (bits + SORT_RB - 1) / SORT_RB;
     const u32 passes = 2 * half;
     if (!max_m || !passes) return;
-    const u32 n_tiles = (u32)((max_m + TILE - 1) / TILE);
-    RD_LAUNCH("k_pair_count", k_pair_count, dim3(n_tiles), dim3(WG_THREADS), 0, s, b.pfirst[0], b.psecond[0], m_dev,
+    const u32 n_tiles = (u32)((max_m + TILE - 1) / TILE), grid = n_tiles < SMALL_SORT_GRID ? n_tiles : SMALL_SORT_GRID;
+    RD_LAUNCH("k_pair_count", k_pair_count, dim3(grid), dim3(WG_THREADS), 0, s, b.pfirst[0], b.psecond[0], m_dev,
               m_host, half, passes, b.sort_partial, b.sort_status, b.sort_tot);
     RD_LAUNCH("k_pair_reduce", k_sort_reduce, dim3(passes, (n_tiles + 63) / 64), dim3(WG_THREADS), 0, s,
               b.sort_partial, MAX_SORT_PASSES, n_tiles, m_dev, (const u32 *)nullptr, SORT_RB, b.sort_tot,
@@ -365,7 +380,7 @@ void sort_pairs(const Bufs &b, const u32 *m_dev, u32 m_host, u64 max_m, hipStrea
         a.pin[0] = lo ? b.pfirst[cur] : b.psecond[cur];
         a.kout = lo ? b.psecond[o] : b.pfirst[o];
         a.pout[0] = lo ? b.pfirst[o] : b.psecond[o];
-        RD_LAUNCH("k_pair_sweep", (k_sort_sweep<1, 8, 4, 16>), dim3(n_tiles), dim3(WG_THREADS), 0, s, a);
+        RD_LAUNCH("k_pair_sweep", (k_sort_sweep<1, 8, 4, 16, true>), dim3(grid), dim3(WG_THREADS), 0, s, a);
         cur = o;
     }
 }
@@ -377,8 +392,8 @@ void sort_pairs(const Bufs &b, const u32 *m_dev, u32 m_host, u64 max_m, hipStrea
 void sort_kv(const Bufs &b, u32 *const k[2], u32 *const v[2], const u32 *n_dev, u64 max_n, u32 passes,
              const u32 *bits_dev, const char *name, hipStream_t s) {
     if (!max_n || !passes) return;
-    const u32 n_tiles = (u32)((max_n + TILE - 1) / TILE);
-    RD_LAUNCH(name, k_pair_count, dim3(n_tiles), dim3(WG_THREADS), 0, s, k[0], k[0], n_dev, 0u, passes, passes,
+    const u32 n_tiles = (u32)((max_n + TILE - 1) / TILE), grid = n_tiles < SMALL_SORT_GRID ? n_tiles : SMALL_SORT_GRID;
+    RD_LAUNCH(name, k_pair_count, dim3(grid), dim3(WG_THREADS), 0, s, k[0], k[0], n_dev, 0u, passes, passes,
               b.sort_partial, b.sort_status, b.sort_tot);
     RD_LAUNCH(name, k_sort_reduce, dim3(passes, (n_tiles + 63) / 64), dim3(WG_THREADS), 0, s, b.sort_partial,
               MAX_SORT_PASSES, n_tiles, n_dev, bits_dev, SORT_RB, b.sort_tot, (u64 *)nullptr, (u64)0);
@@ -389,7 +404,7 @@ void sort_kv(const Bufs &b, u32 *const k[2], u32 *const v[2], const u32 *n_dev, 
         a.pin[0] = v[c];
         a.kout = k[o];
         a.pout[0] = v[o];
-        RD_LAUNCH(name, (k_sort_sweep<1, 8, 4, 16>), dim3(n_tiles), dim3(WG_THREADS), 0, s, a);
+        RD_LAUNCH(name, (k_sort_sweep<1, 8, 4, 16, true>), dim3(grid), dim3(WG_THREADS), 0, s, a);
     }
 }
 
