@@ -153,14 +153,12 @@ __global__ __launch_bounds__(NW * 64) void k_sort_sweep(SweepArgs a) {
     const u64 wbase = tile0 + (u64)w * NI * 64;
     const u32 shift = a.shift;
     const u32 total = has_d ? a.tot[a.pass * SORT_NDS + dme] : 0u;
-    u32 key[NI], off[NI], pay[NP > 0 ? NP : 1][NI];
+    // keys now; each payload array is read when it goes through the LDS (fewer live registers)
+    u32 key[NI], off[NI];
 #pragma unroll
     for (int k = 0; k < NI; k++) {
         const u64 i = wbase + (u64)k * 64 + lane;
-        const bool valid = i < n;
-        key[k] = valid ? a.kin[i] : 0;
-#pragma unroll
-        for (int q = 0; q < NP; q++) pay[q][k] = valid ? a.pin[q][i] : 0;
+        key[k] = i < n ? a.kin[i] : 0;
     }
     // rank: position of each key among the equal digits of its wave, in input order
 #pragma unroll
@@ -275,10 +273,13 @@ __global__ __launch_bounds__(NW * 64) void k_sort_sweep(SweepArgs a) {
     }
 #pragma unroll
     for (int q = 0; q < NP; q++) {
+        u32 pay[NI];
+#pragma unroll
+        for (int k = 0; k < NI; k++) pay[k] = off[k] != NONE ? a.pin[q][wbase + (u64)k * 64 + lane] : 0u;
         __syncthreads();
 #pragma unroll
         for (int k = 0; k < NI; k++)
-            if (off[k] != NONE) L.stage[off[k]] = pay[q][k];
+            if (off[k] != NONE) L.stage[off[k]] = pay[k];
         __syncthreads();
 #pragma unroll
         for (int r = 0; r < NI; r++)
