@@ -349,6 +349,7 @@ void sort_elements(const Bufs &b, hipStream_t s) {
     case 5: elem_passes<9, 8, 16>(b, n_dev, bits, s); break;
     case 6: elem_passes<9, 8, 8>(b, n_dev, bits, s); break;
     case 7: elem_passes<8, 4, 8>(b, n_dev, bits, s); break;
+    case 8: elem_passes<7, 8, 8>(b, n_dev, bits, s); break;
     default: elem_passes<8, 4, 16>(b, n_dev, bits, s); break;
     }
 }
