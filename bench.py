@@ -27,20 +27,45 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E
 
 
-def algorithmic_bytes(name: str, n_events: int, n_acc: int, n_sync: int) -> int | None:
-    """Bytes a kernel must move per launch by what it computes (not what it happens to move)."""
+def algorithmic_bytes(name: str, n_events: int, n_acc: int, n_sync: int, packed: bool = False) -> int | None:
+    """Bytes a kernel must move per launch by what it computes (not what it happens to move).
+    Packed elements (category and phase in the key word) are 12 bytes, else 16."""
+    e = 12 if packed else 16
     table = {
         # every record read once
         "k_ingest": 16 * n_events,
-        # every record read once, one 16-byte element written per access
-        "k_elements": 16 * n_events + 16 * n_acc,
-        # one pass of the location sort: each element (key, index, tid, info) read and written once
-        "k_sort_sweep": 32 * n_acc,
-        # the summaries read key, tid and info of each sorted element once
-        "k_seg_reduce": 12 * n_acc,
-        "k_seg_check": 12 * n_acc,
+        # every record read once, one element written per access
+        "k_elements": 16 * n_events + e * n_acc,
+        # one pass of the location sort: each element read and written once
+        "k_sort_sweep": 2 * e * n_acc,
+        # the summaries read each sorted element once, its index aside
+        "k_seg_reduce": (e - 4) * n_acc,
+        "k_seg_check": (e - 4) * n_acc,
     }
     return table.get(name)
+
+
+def key_bits(ev: np.ndarray, n_blocks: int) -> int:
+    """Bits of the location-key span (global words, then each block's shared words), as the checker
+    computes it on the device."""
+    kind = ev[:, 2] & 15
+    acc = np.isin(kind, (0, 1, 2, 6, 7))
+    sh = ((ev[:, 2] >> 6) & 1) == 1
+    g = ev[acc & ~sh, 0]
+    s = ev[acc & sh, 0]
+    gs = int(g.max()) - int(g.min()) + 1 if len(g) else 0
+    ss = int(s.max()) - int(s.min()) + 1 if len(s) else 0
+    total = gs + n_blocks * ss
+    return max(0, int(total - 1).bit_length()) if total > 1 else 0
+
+
+def packed_elements(ev: np.ndarray, n_blocks: int) -> bool:
+    """Whether the checker packs category and phase into the key word: key bits + 2 + bits of the
+    largest phase (a thread's barrier count) fit in 32 bits."""
+    kind = ev[:, 2] & 15
+    bars = ev[kind == 4, 1]
+    max_phase = int(np.bincount(bars).max()) if len(bars) else 0
+    return key_bits(ev, n_blocks) + 2 + max_phase.bit_length() <= 32
 
 
 def key_passes(ev: np.ndarray, n_blocks: int, tpb: int, radix_bits: int) -> int:
@@ -642,7 +667,9 @@ def main():
             out[k] = (c0 + c, m0 + ms)
         return out
 
-    candidates = [(ms, k) for k, (c, ms) in merged(prof).items() if algorithmic_bytes(k, n, n_acc, n_sync) is not None]
+    packed = packed_elements(ev, grid[0])
+    candidates = [(ms, k) for k, (c, ms) in merged(prof).items()
+                  if algorithmic_bytes(k, n, n_acc, n_sync, packed) is not None]
     dom = max(candidates)[1]
 
     # timed region: K steps, the dominant kernel bracketed by HIP events on its stream (recorded
@@ -666,7 +693,7 @@ def main():
         # count as launches (a conservative average)
         launches = passes * args.steps
     avg_s = (total_ms / max(1, launches)) / 1e3
-    alg = algorithmic_bytes(dom, n, n_acc, n_sync)
+    alg = algorithmic_bytes(dom, n, n_acc, n_sync, packed)
     achieved = alg / avg_s / 1e9 if avg_s > 0 else 0.0
     elapsed = t1 - t0
     ms_per_step = elapsed * 1e3 / args.steps
@@ -707,6 +734,7 @@ def main():
             "race_pairs": int(len(gpu_pairs)),
             "radix_bits": radix_bits,
             "sort_passes": passes,
+            "packed_elements": bool(packed),
             "sort_variant": {"index": variant, "digit_bits": rd.rd_tuning_get(variant)[0],
                              "waves": rd.rd_tuning_get(variant)[1], "items": rd.rd_tuning_get(variant)[2],
                              "autotune_ms": tune_ms},

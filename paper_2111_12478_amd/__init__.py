@@ -65,6 +65,9 @@ def load_library():
     if _lib is None:
         if not os.path.exists(LIB_PATH):
             raise RuntimeError(f"{LIB_PATH} is missing: build it with paper_2111_12478_amd/build.py")
+        # torch first: the library then binds to the HIP runtime torch has loaded, so the process
+        # holds one runtime whichever of the two is used first
+        import torch  # noqa: F401
         lib = ctypes.CDLL(LIB_PATH)
         vp, u64, i32, u32 = ctypes.c_void_p, ctypes.c_uint64, ctypes.c_int32, ctypes.c_uint32
         P = ctypes.POINTER

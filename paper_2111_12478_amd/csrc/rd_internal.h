@@ -31,6 +31,25 @@ __host__ __device__ inline u32 info_make(u32 cat, u32 phase) { return cat | (pha
 __host__ __device__ inline u32 info_cat(u32 info) { return info & 3u; }
 __host__ __device__ inline u32 info_phase(u32 info) { return info >> 2; }
 
+// Packed elements: when the location key, the category and the largest phase fit in 32 bits
+// together, an element's key word holds key | category << key_bits | phase << (key_bits + 2) and
+// its info array is not written (the location sort then moves three arrays instead of four).
+__host__ __device__ inline u32 bits_of(u32 x) {
+    u32 n = 0;
+    while (n < 32 && (x >> n)) n++;
+    return n;
+}
+__host__ __device__ inline u32 key_mask(u32 key_bits) { return key_bits >= 32 ? ~0u : (1u << key_bits) - 1u; }
+__host__ __device__ inline bool packed_elements(u32 key_bits, u32 max_phase) {
+    return key_bits + 2 + bits_of(max_phase) <= 32;
+}
+__host__ __device__ inline u32 pack_element(u32 key, u32 key_bits, u32 cat, u32 phase) {
+    return key | (cat << key_bits) | (key_bits + 2 >= 32 ? 0u : phase << (key_bits + 2));
+}
+__host__ __device__ inline u32 packed_info(u32 word, u32 key_bits) {
+    return info_make((word >> key_bits) & 3u, key_bits + 2 >= 32 ? 0u : word >> (key_bits + 2));
+}
+
 // sync-entry flags (per entry of the per-thread sync lists)
 enum : uint8_t {
     SF_REL = 1,       // release (explicit, or an atomic right after a fence)
@@ -97,6 +116,7 @@ struct DevParams {
     u32 gbar;              // grid-barrier arrivals of the engine kernel
     u32 gprog;             // progress of the engine's sequential phases (bounds barrier waits)
     u32 wlist;             // entries of the engine's window input list
+    u32 max_phase;         // the largest barrier phase of any thread
     unsigned long long n_chunks;  // queued slow-path chunks of the segment check (8-byte aligned)
 };
 

@@ -417,6 +417,7 @@ __device__ inline void sift_down(Bufs &b, u32 lo, u32 root, u32 n) {
     }
 }
 __global__ void k_thread_lists(Bufs b) {
+    u32 top = 0;  // this lane's largest phase
     for (u32 t = blockIdx.x * blockDim.x + threadIdx.x; t < b.T; t += gridDim.x * blockDim.x) {
         const u32 lo = b.s_cnt[t], hi = b.s_cnt[t + 1], n = hi - lo;
         if (n > 1) {
@@ -439,7 +440,11 @@ __global__ void k_thread_lists(Bufs b) {
         }
         if (ph >= (1u << 30)) atomicOr(&b.prm->err, ERR_PHASE);
         if (ph) atomicMax(&b.blk_maxbar[t / b.tpb], ph);
+        top = max(top, ph);
     }
+#pragma unroll
+    for (int d = 32; d >= 1; d >>= 1) top = max(top, (u32)__shfl_xor((int)top, d, 64));
+    if (lane_id() == 0 && top) atomicMax(&b.prm->max_phase, top);
 }
 
 // Barrier arrivals per (block, instance) and active threads per block.  Lanes of a wavefront are
@@ -491,7 +496,8 @@ __global__ void k_bar_register(Bufs b) {
     }
 }
 
-// Access elements (location key, index, tid, category | phase), compacted in trace order.  Plain
+// Access elements (location key, index, tid, category | phase), compacted in trace order; packed
+// (category and phase above the key bits of the key word, no info array) when they fit.  Plain
 // reads and writes also record, per list entry, the first access that follows it.
 // Also counts the digits of every location-sort pass (one row of per-tile counts; digits of the
 // context's sort variant, radix_bits wide).
@@ -509,6 +515,7 @@ __global__ __launch_bounds__(WG_THREADS) void k_elements(Bufs b, const u64 *acc_
     const u32 gbase = p->gbase, sbase = p->sbase, g_span = p->g_span, s_span = p->s_span;
     const u32 mode = p->mode;
     const u32 np = (p->key_bits + rb - 1) / rb;
+    const bool packed = packed_elements(p->key_bits, p->max_phase);
     u32 *ekey = b.ekey[0], *eidx = b.eidx[0], *etid = b.etid[0], *einfo = b.einfo[0];
     const u64 base = (u64)blockIdx.x * TILE + (u64)w * ITEMS * 64;
 #pragma unroll 2
@@ -550,10 +557,14 @@ __global__ __launch_bounds__(WG_THREADS) void k_elements(Bufs b, const u64 *acc_
             }
         }
         const u32 o = pre[k];
-        ekey[o] = key;
+        if (packed) {
+            ekey[o] = pack_element(key, p->key_bits, cat, ph);
+        } else {
+            ekey[o] = key;
+            einfo[o] = info_make(cat, ph);
+        }
         eidx[o] = idx;
         etid[o] = t;
-        einfo[o] = info_make(cat, ph);
         // digit counts: where every active lane has the wavefront's first digit (high digits of
         // clustered addresses), one lane adds them all instead of 64 atomics on one LDS word
         const u64 act = ballot(true);

@@ -127,6 +127,8 @@ struct SegCtx {
     const u32 *k, *i, *t, *f;
     u32 *cpos, *clo, *chi;  // the queue of slow-path chunks (in the sort's free buffers)
     u32 n;
+    bool packed;            // category and phase in the key word, above key_bits
+    u32 key_bits, kmask;
 };
 
 __device__ inline SegCtx seg_ctx(const Bufs &b) {
@@ -135,7 +137,16 @@ __device__ inline SegCtx seg_ctx(const Bufs &b) {
     const u32 c = passes & 1;
     SegCtx s; s.k = b.ekey[c]; s.i = b.eidx[c]; s.t = b.etid[c]; s.f = b.einfo[c]; s.n = b.prm->n_acc;
     s.cpos = b.ekey[c ^ 1]; s.clo = b.etid[c ^ 1]; s.chi = b.einfo[c ^ 1];
+    s.packed = packed_elements(bits, b.prm->max_phase);
+    s.key_bits = bits;
+    s.kmask = s.packed ? key_mask(bits) : ~0u;
     return s;
+}
+
+// the location key and the info (category | phase) of sorted element p
+__device__ inline u32 seg_key(const SegCtx &s, u64 p) { return s.k[p] & s.kmask; }
+__device__ inline u32 seg_info(const SegCtx &s, u64 p) {
+    return s.packed ? packed_info(s.k[p], s.key_bits) : s.f[p];
 }
 
 // Thread x of a tile owns the ITEMS consecutive elements [tile*TILE + x*ITEMS, +ITEMS).
@@ -149,10 +160,12 @@ __device__ inline void load_items(const SegCtx &s, u64 base, Items &it) {
         for (int q = 0; q < ITEMS; q += 4) {
             const uint4 k4 = *(const uint4 *)(s.k + base + q);
             const uint4 t4 = *(const uint4 *)(s.t + base + q);
-            const uint4 f4 = *(const uint4 *)(s.f + base + q);
             it.key[q] = k4.x; it.key[q + 1] = k4.y; it.key[q + 2] = k4.z; it.key[q + 3] = k4.w;
             it.tid[q] = t4.x; it.tid[q + 1] = t4.y; it.tid[q + 2] = t4.z; it.tid[q + 3] = t4.w;
-            it.info[q] = f4.x; it.info[q + 1] = f4.y; it.info[q + 2] = f4.z; it.info[q + 3] = f4.w;
+            if (!s.packed) {
+                const uint4 f4 = *(const uint4 *)(s.f + base + q);
+                it.info[q] = f4.x; it.info[q + 1] = f4.y; it.info[q + 2] = f4.z; it.info[q + 3] = f4.w;
+            }
         }
     } else {
 #pragma unroll
@@ -161,7 +174,14 @@ __device__ inline void load_items(const SegCtx &s, u64 base, Items &it) {
             const bool in = pos < s.n;
             it.key[q] = in ? s.k[pos] : 0;
             it.tid[q] = in ? s.t[pos] : 0;
-            it.info[q] = in ? s.f[pos] : 0;
+            it.info[q] = in && !s.packed ? s.f[pos] : 0;
+        }
+    }
+    if (s.packed) {
+#pragma unroll
+        for (int q = 0; q < ITEMS; q++) {
+            it.info[q] = packed_info(it.key[q], s.key_bits);
+            it.key[q] &= s.kmask;
         }
     }
 }
@@ -309,10 +329,10 @@ __device__ inline void wave_slow_check(const Bufs &b, const SegCtx &s, const u32
         bool stop = !valid;
         u32 ta = 0, info = 0, ba = 0, pha = 0;
         if (valid) {
-            stop = s.k[q] != key;
+            stop = seg_key(s, q) != key;
             if (!stop) {
                 ta = s.t[q];
-                info = s.f[q];
+                info = seg_info(s, q);
                 ba = block_of(b, ta);
                 pha = info_phase(info);
                 if (group_only && (ba != bblk || pha != bph)) stop = true;
@@ -413,10 +433,10 @@ struct Walker {
 __device__ inline Walker walker_at(const Bufs &b, const SegCtx &s, u32 pos) {
     Walker w;
     w.pos = pos;
-    w.key = s.k[pos];
+    w.key = seg_key(s, pos);
     w.btid = s.t[pos];
     w.bidx = s.i[pos];
-    const u32 info = s.f[pos];
+    const u32 info = seg_info(s, pos);
     w.bblk = block_of(b, w.btid);
     w.bph = info_phase(info);
     w.bcat = info_cat(info);
@@ -474,7 +494,7 @@ __device__ inline bool walk_spill(const Bufs &b, const SegCtx &s, const Walker &
     u32 lo = 0, hi = top;
     while (lo < hi) {
         const u32 mid = (lo + hi) >> 1;
-        if (s.k[mid] < w.key) lo = mid + 1;
+        if (seg_key(s, mid) < w.key) lo = mid + 1;
         else hi = mid;
     }
     const u32 cnt = (top - lo + 63) / 64;
@@ -518,9 +538,9 @@ __device__ void lane_walks(const Bufs &b, const SegCtx &s, const u32 *rt_scan, u
         for (u32 j = 0; j < LANE_STEP; j++) {
             const bool ok = act && top > j;
             const u32 q = ok ? top - 1 - j : 0u;
-            kq[j] = ok ? s.k[q] : w.key ^ 1u;
+            kq[j] = ok ? seg_key(s, q) : w.key ^ 1u;
             tq[j] = ok ? s.t[q] : 0u;
-            fq[j] = ok ? s.f[q] : 0u;
+            fq[j] = ok ? seg_info(s, q) : 0u;
         }
 #pragma unroll
         for (u32 j = 0; j < LANE_STEP; j++) {
@@ -652,9 +672,9 @@ __global__ __launch_bounds__(WG_THREADS) void k_seg_check(Bufs b, const u32 *rt_
             const u32 l = (u32)__builtin_ctzll(m);
             m &= m - 1;
             const u32 pos = (u32)(tile0 + (u64)(wv * 64 + l) * ITEMS + q);
-            const u32 tid = s.t[pos], info = s.f[pos];
-            wave_slow_check(b, s, rt_scan, pos, s.k[pos], tid, block_of(b, tid), info_phase(info), info_cat(info),
-                            (mr >> l) & 1u);
+            const u32 tid = s.t[pos], info = seg_info(s, pos);
+            wave_slow_check(b, s, rt_scan, pos, seg_key(s, pos), tid, block_of(b, tid), info_phase(info),
+                            info_cat(info), (mr >> l) & 1u);
         }
     }
     // the walks
@@ -684,9 +704,9 @@ __global__ __launch_bounds__(WG_THREADS) void k_seg_slow(Bufs b, const u32 *rt_s
             const u32 pos = s.cpos[c], lo = s.clo[c], hi = s.chi[c];
             const u32 q = lo + lane;
             if (q < hi) {
-                const u32 btid = s.t[pos], binfo = s.f[pos];
+                const u32 btid = s.t[pos], binfo = seg_info(s, pos);
                 const u32 bblk = block_of(b, btid), bph = info_phase(binfo), bcat = info_cat(binfo);
-                const u32 ta = s.t[q], info = s.f[q];
+                const u32 ta = s.t[q], info = seg_info(s, q);
                 const u32 ba = block_of(b, ta), pha = info_phase(info);
                 if (ta != btid && conflicts(info_cat(info), ba, bcat, bblk)) {
                     u32 h = NONE;

@@ -118,6 +118,7 @@ struct SweepArgs {
     u64 *status_cur, *status_next;
     const u32 *tot;       // digit totals of the pass ([pass][SORT_NDS])
     u32 *ctr, *err;
+    const DevParams *prm;  // the element sort: packed elements move their first two payloads only
 };
 
 constexpr int LOOKBACK = 4;  // predecessor words read at once per digit
@@ -130,6 +131,9 @@ __global__ __launch_bounds__(NW * 64) void k_sort_sweep(SweepArgs a) {
     static_assert(ND <= THREADS, "one digit per thread");
     __shared__ SweepLds<RB, NW, NI> L;
     if (a.bits_dev && a.shift >= *a.bits_dev) return;  // past the key width: the pass is not needed
+    // digits come from the key bits only (packed elements carry more above them)
+    const u32 kmask = a.bits_dev ? key_mask(*a.bits_dev) : ~0u;
+    const u32 np_run = NP == 3 && a.prm && packed_elements(a.prm->key_bits, a.prm->max_phase) ? 2u : (u32)NP;
     const u32 n = a.n_dev ? *a.n_dev : a.n_host;
     const u32 n_tiles = (u32)(((u64)n + TS - 1) / TS);
     const u32 w = threadIdx.x >> 6, lane = lane_id(), dme = threadIdx.x;  // digit dme when dme < ND
@@ -164,7 +168,7 @@ __global__ __launch_bounds__(NW * 64) void k_sort_sweep(SweepArgs a) {
 #pragma unroll
     for (int k = 0; k < NI; k++) {
         const bool valid = wbase + (u64)k * 64 + lane < n;
-        const u32 d = (key[k] >> shift) & DM;
+        const u32 d = ((key[k] & kmask) >> shift) & DM;
         u64 m = ballot(valid);
 #pragma unroll
         for (int bit = 0; bit < RB; bit++) {
@@ -253,7 +257,7 @@ __global__ __launch_bounds__(NW * 64) void k_sort_sweep(SweepArgs a) {
 #pragma unroll
     for (int k = 0; k < NI; k++) {
         const bool valid = wbase + (u64)k * 64 + lane < n;
-        off[k] = valid ? L.wcnt[w][(key[k] >> shift) & DM] + off[k] : NONE;
+        off[k] = valid ? L.wcnt[w][((key[k] & kmask) >> shift) & DM] + off[k] : NONE;
     }
     // keys through LDS, then each payload array
 #pragma unroll
@@ -267,12 +271,13 @@ __global__ __launch_bounds__(NW * 64) void k_sort_sweep(SweepArgs a) {
         gpos[r] = NONE;
         if (j < cnt_tile) {
             const u32 kk = L.stage[j];
-            gpos[r] = L.dg[(kk >> shift) & DM] + j;
+            gpos[r] = L.dg[((kk & kmask) >> shift) & DM] + j;
             a.kout[gpos[r]] = kk;
         }
     }
 #pragma unroll
     for (int q = 0; q < NP; q++) {
+        if ((u32)q >= np_run) break;
         u32 pay[NI];
 #pragma unroll
         for (int k = 0; k < NI; k++) pay[k] = off[k] != NONE ? a.pin[q][wbase + (u64)k * 64 + lane] : 0u;
@@ -324,6 +329,7 @@ static void elem_passes(const Bufs &b, const u32 *n_dev, const u32 *bits, hipStr
         a.pout[0] = b.eidx[o];
         a.pout[1] = b.etid[o];
         a.pout[2] = b.einfo[o];
+        a.prm = b.prm;
         RD_LAUNCH(kSweepName[pass], (k_sort_sweep<3, RB, NW, NI>), dim3(tiles), dim3(NW * 64), 0, s, a);
     }
 }
