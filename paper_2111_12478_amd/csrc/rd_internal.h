@@ -83,9 +83,10 @@ constexpr u32 ELEM_MAX_PASSES = 5;   // ceil(32 / 7)
 struct SortVariant {
     u32 rb, waves, items;
 };
-constexpr u32 N_SORT_VARIANTS = 9;
+constexpr u32 N_SORT_VARIANTS = 11;
 constexpr SortVariant kSortVariants[N_SORT_VARIANTS] = {
-    {8, 4, 16}, {8, 8, 8}, {8, 8, 16}, {7, 4, 16}, {7, 8, 16}, {9, 8, 16}, {9, 8, 8}, {8, 4, 8}, {7, 8, 8}};
+    {8, 4, 16}, {8, 8, 8}, {8, 8, 16}, {7, 4, 16}, {7, 8, 16}, {9, 8, 16},
+    {9, 8, 8},  {8, 4, 8}, {7, 8, 8},  {7, 16, 16}, {8, 16, 16}};
 
 // Device-side state of one check.  Zeroed (and the "min" fields set to NONE) by k_init.
 struct DevParams {

@@ -356,6 +356,8 @@ void sort_elements(const Bufs &b, hipStream_t s) {
     case 6: elem_passes<9, 8, 8>(b, n_dev, bits, s); break;
     case 7: elem_passes<8, 4, 8>(b, n_dev, bits, s); break;
     case 8: elem_passes<7, 8, 8>(b, n_dev, bits, s); break;
+    case 9: elem_passes<7, 16, 16>(b, n_dev, bits, s); break;
+    case 10: elem_passes<8, 16, 16>(b, n_dev, bits, s); break;
     default: elem_passes<8, 4, 16>(b, n_dev, bits, s); break;
     }
 }
