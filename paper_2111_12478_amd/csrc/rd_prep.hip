@@ -416,12 +416,44 @@ __device__ inline void sift_down(Bufs &b, u32 lo, u32 root, u32 n) {
         root = c;
     }
 }
-__global__ void k_thread_lists(Bufs b) {
+// One wavefront per workgroup; every lane runs the same iterations (lanes past the threads idle),
+// so the per-block barrier counts can be combined across lanes before the atomics.
+__global__ __launch_bounds__(64) void k_thread_lists(Bufs b) {
     u32 top = 0;  // this lane's largest phase
-    for (u32 t = blockIdx.x * blockDim.x + threadIdx.x; t < b.T; t += gridDim.x * blockDim.x) {
-        const u32 lo = b.s_cnt[t], hi = b.s_cnt[t + 1], n = hi - lo;
+    const u32 lane = lane_id();
+    for (u32 base = blockIdx.x * 64; base < b.T; base += gridDim.x * 64) {
+        const u32 t = base + lane;
+        const bool valid = t < b.T;
+        const u32 lo = valid ? b.s_cnt[t] : 0u, hi = valid ? b.s_cnt[t + 1] : 0u, n = hi - lo;
         if (n > 1) {
-            if (n <= 32) {
+            if (n <= 8) {
+                // in registers: one read and one write per entry, a fixed sorting network between
+                u32 x[8], y[8], z[8];
+#pragma unroll
+                for (u32 i = 0; i < 8; i++) {
+                    const bool in = i < n;
+                    x[i] = in ? b.s_pidx[lo + i] : NONE;
+                    y[i] = in ? b.s_pq[lo + i] : 0u;
+                    z[i] = in ? b.s_kind[lo + i] : 0u;
+                }
+                auto ce = [&](int i, int j) {
+                    if (x[j] < x[i]) {
+                        u32 t0 = x[i]; x[i] = x[j]; x[j] = t0;
+                        u32 t1 = y[i]; y[i] = y[j]; y[j] = t1;
+                        u32 t2 = z[i]; z[i] = z[j]; z[j] = t2;
+                    }
+                };
+                // Batcher's odd-even merge network for 8 keys (19 comparators)
+                ce(0, 1); ce(2, 3); ce(4, 5); ce(6, 7);
+                ce(0, 2); ce(1, 3); ce(4, 6); ce(5, 7);
+                ce(1, 2); ce(5, 6);
+                ce(0, 4); ce(1, 5); ce(2, 6); ce(3, 7);
+                ce(2, 4); ce(3, 5);
+                ce(1, 2); ce(3, 4); ce(5, 6);
+#pragma unroll
+                for (u32 i = 0; i < 8; i++)
+                    if (i < n) { b.s_pidx[lo + i] = x[i]; b.s_pq[lo + i] = y[i]; b.s_kind[lo + i] = (uint8_t)z[i]; }
+            } else if (n <= 32) {
                 for (u32 i = lo + 1; i < hi; i++)
                     for (u32 j = i; j > lo && b.s_pidx[j - 1] > b.s_pidx[j]; j--) list_swap(b, j - 1, j);
             } else {
@@ -439,12 +471,24 @@ __global__ void k_thread_lists(Bufs b) {
             b.s_scope[p] = 0;
         }
         if (ph >= (1u << 30)) atomicOr(&b.prm->err, ERR_PHASE);
-        if (ph) atomicMax(&b.blk_maxbar[t / b.tpb], ph);
         top = max(top, ph);
+        // the block's largest phase: one atomic per block present in the wavefront
+        const u32 blk = valid ? t / b.tpb : NONE;
+        u64 pending = ballot(ph != 0);
+        while (pending) {
+            const u32 leader = (u32)__builtin_ctzll(pending);
+            const u32 lb = __shfl(blk, leader, 64);
+            const bool mine = ph != 0 && blk == lb;
+            u32 mx = mine ? ph : 0u;
+#pragma unroll
+            for (int d = 32; d >= 1; d >>= 1) mx = max(mx, (u32)__shfl_xor((int)mx, d, 64));
+            if (lane == leader) atomicMax(&b.blk_maxbar[lb], mx);
+            pending &= ~ballot(mine);
+        }
     }
 #pragma unroll
     for (int d = 32; d >= 1; d >>= 1) top = max(top, (u32)__shfl_xor((int)top, d, 64));
-    if (lane_id() == 0 && top) atomicMax(&b.prm->max_phase, top);
+    if (lane == 0 && top) atomicMax(&b.prm->max_phase, top);
 }
 
 // Barrier arrivals per (block, instance) and active threads per block.  Lanes of a wavefront are

@@ -200,24 +200,25 @@ __device__ inline void items_agg(const Bufs &b, const Items &it, u32 cnt, u32 ba
     }
 }
 
-// Block-wide (256 threads) exclusive scan of Aggs in LDS; `mine` becomes this thread's exclusive
+// Block-wide (NT threads) exclusive scan of Aggs in LDS; `mine` becomes this thread's exclusive
 // prefix, *total (when non-null) the block total.
-__device__ inline void block_exscan_agg(Agg &mine, Agg *buf /* 2*256 */, Agg *total) {
+template <u32 NT = WG_THREADS>
+__device__ inline void block_exscan_agg(Agg &mine, Agg *buf /* 2*NT */, Agg *total) {
     const u32 x = threadIdx.x;
     buf[x] = mine;
     __syncthreads();
     u32 src = 0;
-    for (u32 d = 1; d < WG_THREADS; d <<= 1) {
-        Agg v = buf[src * WG_THREADS + x];
-        if (x >= d) agg_combine(buf[src * WG_THREADS + x - d], v);
-        buf[(src ^ 1) * WG_THREADS + x] = v;
+    for (u32 d = 1; d < NT; d <<= 1) {
+        Agg v = buf[src * NT + x];
+        if (x >= d) agg_combine(buf[src * NT + x - d], v);
+        buf[(src ^ 1) * NT + x] = v;
         __syncthreads();
         src ^= 1;
     }
-    if (total) *total = buf[src * WG_THREADS + WG_THREADS - 1];
+    if (total) *total = buf[src * NT + NT - 1];
     Agg ex;
     if (x == 0) agg_empty(ex);
-    else ex = buf[src * WG_THREADS + x - 1];
+    else ex = buf[src * NT + x - 1];
     __syncthreads();
     mine = ex;
 }
@@ -245,19 +246,38 @@ __global__ __launch_bounds__(WG_THREADS) void k_seg_reduce(Bufs b) {
     }
 }
 
-// exclusive scan over the tile totals (one workgroup)
-__global__ __launch_bounds__(WG_THREADS) void k_seg_scan(Bufs b) {
-    __shared__ Agg buf[2 * WG_THREADS];
+// exclusive scan over the tile totals (one workgroup of SCAN_THREADS; each thread a contiguous
+// range of tiles, read four at a time so that their loads overlap)
+constexpr u32 SCAN_THREADS = 1024;
+
+__global__ __launch_bounds__(SCAN_THREADS) void k_seg_scan(Bufs b) {
+    __shared__ Agg buf[2 * SCAN_THREADS];
     const SegCtx s = seg_ctx(b);
     Agg *tile_agg = (Agg *)b.tile_agg;
     const u32 nt = (u32)((s.n + TILE - 1) / TILE);
-    const u32 per = (nt + WG_THREADS - 1) / WG_THREADS;
+    const u32 per = (nt + SCAN_THREADS - 1) / SCAN_THREADS;
     const u32 lo = threadIdx.x * per, hi = min(lo + per, nt);
     Agg acc;
     agg_empty(acc);
-    for (u32 q = lo; q < hi; q++) { Agg v = tile_agg[q]; agg_combine(acc, v); acc = v; }
-    block_exscan_agg(acc, buf, nullptr);
-    for (u32 q = lo; q < hi; q++) { Agg v = tile_agg[q]; tile_agg[q] = acc; agg_combine(acc, v); acc = v; }
+    for (u32 q = lo; q < hi; q += 4) {
+        Agg v[4];
+#pragma unroll
+        for (u32 j = 0; j < 4; j++)
+            if (q + j < hi) v[j] = tile_agg[q + j];
+#pragma unroll
+        for (u32 j = 0; j < 4; j++)
+            if (q + j < hi) { agg_combine(acc, v[j]); acc = v[j]; }
+    }
+    block_exscan_agg<SCAN_THREADS>(acc, buf, nullptr);
+    for (u32 q = lo; q < hi; q += 4) {
+        Agg v[4];
+#pragma unroll
+        for (u32 j = 0; j < 4; j++)
+            if (q + j < hi) v[j] = tile_agg[q + j];
+#pragma unroll
+        for (u32 j = 0; j < 4; j++)
+            if (q + j < hi) { tile_agg[q + j] = acc; agg_combine(acc, v[j]); acc = v[j]; }
+    }
 }
 
 // ---------------------------------------------------------------- the check
@@ -750,7 +770,7 @@ __global__ void k_pairs_kept(Bufs b) {
 void segcheck_run(const Bufs &b, const u32 *rt_scan, hipStream_t s) {
     if (!b.N) { RD_LAUNCH("k_pairs_kept", k_pairs_kept, dim3(1), dim3(64), 0, s, b); return; }
     RD_LAUNCH("k_seg_reduce", k_seg_reduce, dim3(b.n_tiles), dim3(WG_THREADS), 0, s, b);
-    RD_LAUNCH("k_seg_scan", k_seg_scan, dim3(1), dim3(WG_THREADS), 0, s, b);
+    RD_LAUNCH("k_seg_scan", k_seg_scan, dim3(1), dim3(SCAN_THREADS), 0, s, b);
     RD_LAUNCH("k_seg_check", k_seg_check, dim3(b.n_tiles), dim3(WG_THREADS), 0, s, b, rt_scan);
     RD_LAUNCH("k_seg_slow", k_seg_slow, dim3(b.n_tiles < 1024 ? b.n_tiles : 1024), dim3(WG_THREADS), 0, s, b, rt_scan);
     RD_LAUNCH("k_pairs_kept", k_pairs_kept, dim3(1), dim3(64), 0, s, b);
