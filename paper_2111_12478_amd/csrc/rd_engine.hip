@@ -685,12 +685,13 @@ __device__ __attribute__((always_inline)) inline ChainJob chain_job(const u32 *j
     return J;
 }
 
-__device__ __attribute__((always_inline)) inline uint4 chain_part(const ChainJob &J, const uint4 *pool4, u32 D4, u32 i) {
+__device__ __attribute__((always_inline)) inline uint4 chain_part(const ChainJob &J, const uint4 *pool4, u32 D4,
+                                                                  u32 i) {
     return J.act ? pool4[(u64)J.q.x * D4 + i] : make_uint4(0, 0, 0, 0);
 }
 
-__device__ __attribute__((always_inline)) inline void chain_run(ChainCache &C, const ChainJob &J, uint4 v, const u32 *list, uint4 *pool4, u32 D4,
-                                 u32 i) {
+__device__ __attribute__((always_inline)) inline void chain_run(ChainCache &C, const ChainJob &J, uint4 v,
+                                                                const u32 *list, uint4 *pool4, u32 D4, u32 i) {
     if (!J.act) return;
     if (J.q.y) v = max4(v, chain_get(C, pool4, D4, i, J.q.y));
     if (J.q.z) v = max4(v, chain_get(C, pool4, D4, i, J.q.z));
@@ -700,30 +701,60 @@ __device__ __attribute__((always_inline)) inline void chain_run(ChainCache &C, c
     chain_put(C, J.q.x, v);
 }
 
-__device__ void chain_window(const Bufs &b, u32 w0, u32 w1, u32 D4) {
+// The workgroup stages the jobs of CH_BLK operations in LDS at once (one coalesced read); each
+// step then takes four operations, their partial results loaded together.
+constexpr u32 CH_BLK = 128;
+
+__device__ void chain_window(const Bufs &b, u32 w0, u32 w1, u32 D4, u32 *lj /* CH_BLK * ENG_JOB_WORDS */) {
     const u32 *jobs = b.eng_jobs, *list = b.eng_jobs + ENG_WIN * ENG_JOB_WORDS;
     uint4 *pool4 = (uint4 *)b.pool;
     const bool reporter = blockIdx.x == 0 && threadIdx.x == 0;
-    for (u32 i = blockIdx.x * ENG_THREADS + threadIdx.x; i < D4; i += gridDim.x * ENG_THREADS) {
-        const uint4 z = make_uint4(0, 0, 0, 0);
+    const uint4 z = make_uint4(0, 0, 0, 0);
+    // the slices of a workgroup's threads, in rounds every thread of the workgroup takes (the LDS
+    // staging needs them all at its barriers); threads past the last slice only help stage
+    for (u32 base = blockIdx.x * ENG_THREADS; base < D4; base += gridDim.x * ENG_THREADS) {
+        const u32 i = base + threadIdx.x;
+        const bool mine = i < D4;
+        const u32 ii = mine ? i : 0u;
         ChainCache C = {0, 0, 0, 0, z, z, z, z};
-        // two operations per step: all six partial results are loaded before the joins
-        for (u32 o = w0; o < w1; o += 2) {
-            const u32 *ja = jobs + (u64)(o - w0) * ENG_JOB_WORDS, *jb = ja + ENG_JOB_WORDS;
-            const bool inb = o + 1 < w1;
-            const ChainJob a0 = chain_job(ja, 0, true), a1 = chain_job(ja, 1, true), a2 = chain_job(ja, 2, true);
-            const ChainJob b0 = chain_job(jb, 0, inb), b1 = chain_job(jb, 1, inb), b2 = chain_job(jb, 2, inb);
-            const uint4 pa0 = chain_part(a0, pool4, D4, i), pa1 = chain_part(a1, pool4, D4, i),
-                        pa2 = chain_part(a2, pool4, D4, i);
-            const uint4 pb0 = chain_part(b0, pool4, D4, i), pb1 = chain_part(b1, pool4, D4, i),
-                        pb2 = chain_part(b2, pool4, D4, i);
-            chain_run(C, a0, pa0, list, pool4, D4, i);
-            chain_run(C, a1, pa1, list, pool4, D4, i);
-            chain_run(C, a2, pa2, list, pool4, D4, i);
-            chain_run(C, b0, pb0, list, pool4, D4, i);
-            chain_run(C, b1, pb1, list, pool4, D4, i);
-            chain_run(C, b2, pb2, list, pool4, D4, i);
-            if (reporter) atomicAdd(&b.prm->gprog, 1u);
+        for (u32 cb = w0; cb < w1; cb += CH_BLK) {
+            const u32 ce = min(cb + CH_BLK, w1);
+            __syncthreads();
+            for (u32 x = threadIdx.x; x < (ce - cb) * ENG_JOB_WORDS; x += ENG_THREADS)
+                lj[x] = jobs[(u64)(cb - w0) * ENG_JOB_WORDS + x];
+            __syncthreads();
+            for (u32 o = cb; o < ce; o += 4) {
+                const u32 *ja = lj + (o - cb) * ENG_JOB_WORDS, *jb = ja + ENG_JOB_WORDS, *jc = jb + ENG_JOB_WORDS,
+                          *jd = jc + ENG_JOB_WORDS;
+                const bool inb = o + 1 < ce, inc = o + 2 < ce, ind = o + 3 < ce;
+                const ChainJob a0 = chain_job(ja, 0, true), a1 = chain_job(ja, 1, true), a2 = chain_job(ja, 2, true);
+                const ChainJob b0 = chain_job(jb, 0, inb), b1 = chain_job(jb, 1, inb), b2 = chain_job(jb, 2, inb);
+                const ChainJob c0 = chain_job(jc, 0, inc), c1 = chain_job(jc, 1, inc), c2 = chain_job(jc, 2, inc);
+                const ChainJob d0 = chain_job(jd, 0, ind), d1 = chain_job(jd, 1, ind), d2 = chain_job(jd, 2, ind);
+                if (mine) {
+                    const uint4 pa0 = chain_part(a0, pool4, D4, ii), pa1 = chain_part(a1, pool4, D4, ii),
+                                pa2 = chain_part(a2, pool4, D4, ii);
+                    const uint4 pb0 = chain_part(b0, pool4, D4, ii), pb1 = chain_part(b1, pool4, D4, ii),
+                                pb2 = chain_part(b2, pool4, D4, ii);
+                    const uint4 pc0 = chain_part(c0, pool4, D4, ii), pc1 = chain_part(c1, pool4, D4, ii),
+                                pc2 = chain_part(c2, pool4, D4, ii);
+                    const uint4 pd0 = chain_part(d0, pool4, D4, ii), pd1 = chain_part(d1, pool4, D4, ii),
+                                pd2 = chain_part(d2, pool4, D4, ii);
+                    chain_run(C, a0, pa0, list, pool4, D4, ii);
+                    chain_run(C, a1, pa1, list, pool4, D4, ii);
+                    chain_run(C, a2, pa2, list, pool4, D4, ii);
+                    chain_run(C, b0, pb0, list, pool4, D4, ii);
+                    chain_run(C, b1, pb1, list, pool4, D4, ii);
+                    chain_run(C, b2, pb2, list, pool4, D4, ii);
+                    chain_run(C, c0, pc0, list, pool4, D4, ii);
+                    chain_run(C, c1, pc1, list, pool4, D4, ii);
+                    chain_run(C, c2, pc2, list, pool4, D4, ii);
+                    chain_run(C, d0, pd0, list, pool4, D4, ii);
+                    chain_run(C, d1, pd1, list, pool4, D4, ii);
+                    chain_run(C, d2, pd2, list, pool4, D4, ii);
+                }
+                if (reporter) atomicAdd(&b.prm->gprog, 1u);
+            }
         }
     }
 }
@@ -756,6 +787,7 @@ __global__ __launch_bounds__(ENG_THREADS) void k_eng_eval(Bufs b, const u32 *rt_
     if (!eng_on(P) || P->n_ops > b.ecap || (P->err & ERR_POOL)) return;
     __shared__ u32 lds_list[1024];
     __shared__ u32 lds_n;
+    __shared__ u32 lds_jobs[CH_BLK * ENG_JOB_WORDS];
     const u32 D = P->D, ng = P->n_groups;
     u32 round = 0;
     if (blockIdx.x == 0) {
@@ -769,7 +801,8 @@ __global__ __launch_bounds__(ENG_THREADS) void k_eng_eval(Bufs b, const u32 *rt_
     while (g < ng) {
         const u32 g0 = b.grp[g], g1 = b.grp[g + 1];
         if (g1 - g0 >= ENG_WIDE) {
-            for (u32 o = g0 + blockIdx.x; o < g1; o += gridDim.x) eval_op(b, rt_scan, o, D, lds_list, &lds_n, NONE, none);
+            for (u32 o = g0 + blockIdx.x; o < g1; o += gridDim.x)
+                eval_op(b, rt_scan, o, D, lds_list, &lds_n, NONE, none);
             g++;
             grid_barrier(P, ++round);
             continue;
@@ -791,7 +824,7 @@ __global__ __launch_bounds__(ENG_THREADS) void k_eng_eval(Bufs b, const u32 *rt_
                 eval_op(b, rt_scan, o, D, lds_list, &lds_n, hint, js);
             }
             grid_barrier(P, ++round);
-            chain_window(b, w0, w1, D / 4);
+            chain_window(b, w0, w1, D / 4, lds_jobs);
             if (blockIdx.x == 0 && threadIdx.x == 0) P->wlist = 0;  // the next window's list starts empty
             grid_barrier(P, ++round);
         }
