@@ -493,12 +493,13 @@ __device__ void eval_bar(const Bufs &b, u32 p, u32 D, u32 *lds_list, u32 *lds_n,
     const u32 hout = b.inst_handle[slot], hprev = k > 1 ? b.inst_handle[slot - 1] : 0u;
     uint4 *out = (uint4 *)(b.pool + (u64)hout * D);
     const uint4 *prev = (const uint4 *)vecp(b, D, ext(hprev, hint));
+    const bool lprev = ext(hprev, hint) != 0;  // the empty vector is not read
     for (u32 base = 0; base < D4; base += ENG_THREADS * EV) {
         uint4 v[EV];
 #pragma unroll
         for (u32 e = 0; e < EV; e++) {
             const u32 i = base + e * ENG_THREADS + threadIdx.x;
-            v[e] = i < D4 ? prev[i] : make_uint4(0, 0, 0, 0);
+            v[e] = lprev && i < D4 ? prev[i] : make_uint4(0, 0, 0, 0);
         }
         for (u32 c = 0; c < nc; c++) {
             const u32 h = lds_list[c];
@@ -550,6 +551,7 @@ __device__ void eval_ra(const Bufs &b, const u32 *rt_scan, u32 p, u32 D, u32 hin
         hc = b.s_khandle[cur];
     }
     const uint4 *vc = (const uint4 *)vecp(b, D, ext(hc, hint));
+    const bool lc = ext(hc, hint) != 0;  // (the empty vector, handle 0, is never read)
     uint4 j0 = make_uint4(0, 0, 0, 0), j1 = j0, j2 = j0;
     if (f & SF_REL) {
         const u32 kb = blk, kbv = b.s_phase[p], kt = b.B + rt_scan[t], ktv = idx + 1;
@@ -559,6 +561,7 @@ __device__ void eval_ra(const Bufs &b, const u32 *rt_scan, u32 p, u32 D, u32 hin
         const u32 hv1 = two && b.e_prev1[p] != NONE ? b.e_relh[b.e_prev1[p]] + 1 : 0u;
         const uint4 *v0 = (const uint4 *)vecp(b, D, ext(hv0, hint));
         const uint4 *v1 = (const uint4 *)vecp(b, D, ext(hv1, hint));
+        const bool l0 = ext(hv0, hint) != 0, l1 = two && ext(hv1, hint) != 0;
         uint4 *o0 = (uint4 *)(b.pool + (u64)h0 * D), *o1 = (uint4 *)(b.pool + (u64)(h0 + 1) * D);
         for (u32 base = 0; base < D4; base += ENG_THREADS * EV) {
             uint4 c[EV], x0[EV], x1[EV];
@@ -566,9 +569,9 @@ __device__ void eval_ra(const Bufs &b, const u32 *rt_scan, u32 p, u32 D, u32 hin
             for (u32 e = 0; e < EV; e++) {
                 const u32 i = base + e * ENG_THREADS + threadIdx.x;
                 const bool in = i < D4;
-                c[e] = in ? vc[i] : make_uint4(0, 0, 0, 0);
-                x0[e] = in ? v0[i] : make_uint4(0, 0, 0, 0);
-                x1[e] = in && two ? v1[i] : make_uint4(0, 0, 0, 0);
+                c[e] = in && lc ? vc[i] : make_uint4(0, 0, 0, 0);
+                x0[e] = in && l0 ? v0[i] : make_uint4(0, 0, 0, 0);
+                x1[e] = in && l1 ? v1[i] : make_uint4(0, 0, 0, 0);
             }
 #pragma unroll
             for (u32 e = 0; e < EV; e++) {
@@ -592,6 +595,7 @@ __device__ void eval_ra(const Bufs &b, const u32 *rt_scan, u32 p, u32 D, u32 hin
         const u32 ha1 = s1 != NONE ? b.e_relh[s1] + (blk_acq ? 0u : 1u) : 0u;
         const uint4 *a0 = (const uint4 *)vecp(b, D, ext(ha0, hint));
         const uint4 *a1 = (const uint4 *)vecp(b, D, ext(ha1, hint));
+        const bool la0 = ext(ha0, hint) != 0, la1 = ext(ha1, hint) != 0;
         uint4 *oa = (uint4 *)(b.pool + (u64)ha * D);
         for (u32 base = 0; base < D4; base += ENG_THREADS * EV) {
             uint4 c[EV], x0[EV], x1[EV];
@@ -599,9 +603,9 @@ __device__ void eval_ra(const Bufs &b, const u32 *rt_scan, u32 p, u32 D, u32 hin
             for (u32 e = 0; e < EV; e++) {
                 const u32 i = base + e * ENG_THREADS + threadIdx.x;
                 const bool in = i < D4;
-                c[e] = in ? vc[i] : make_uint4(0, 0, 0, 0);
-                x0[e] = in ? a0[i] : make_uint4(0, 0, 0, 0);
-                x1[e] = in ? a1[i] : make_uint4(0, 0, 0, 0);
+                c[e] = in && lc ? vc[i] : make_uint4(0, 0, 0, 0);
+                x0[e] = in && la0 ? a0[i] : make_uint4(0, 0, 0, 0);
+                x1[e] = in && la1 ? a1[i] : make_uint4(0, 0, 0, 0);
             }
 #pragma unroll
             for (u32 e = 0; e < EV; e++) {
