@@ -113,6 +113,7 @@ static Plan make_plan(u64 n, u32 nb, u32 tpb, const rd_limits *lim, bool copy_ev
     L.off_priv = take(4 * T);
     L.off_priv_next = take(4 * T);
     L.off_t_kfirst = take(4 * T);
+    L.off_t_acq = take(4 * T);
     L.off_bk = take(4 * B);
     L.off_priv_head = take(4 * B);
     L.off_sv_key = take(8ull * L.sv_cap);
@@ -200,6 +201,7 @@ static Bufs make_bufs(const Plan &P, char *ws, const void *events_dev, u64 n, u3
     b.priv = (u32 *)(ws + L.off_priv);
     b.priv_next = (u32 *)(ws + L.off_priv_next);
     b.t_kfirst = (u32 *)(ws + L.off_t_kfirst);
+    b.t_acq = (u32 *)(ws + L.off_t_acq);
     b.bk = (u32 *)(ws + L.off_bk);
     b.priv_head = (u32 *)(ws + L.off_priv_head);
     b.sv_key = (u64 *)(ws + L.off_sv_key);

@@ -186,6 +186,7 @@ struct Bufs {
     u32 *priv;              // [T] private knowledge vector of a thread (since its last barrier)
     u32 *priv_next;         // [T]
     u32 *t_kfirst;          // [T] trace index of the thread's first sync entry with knowledge (NONE: none)
+    u32 *t_acq;             // [T] 1 when the thread has an acquire that joins knowledge of its own
     u32 *bk;                // [B] knowledge vector of a block after its latest barrier
     u32 *priv_head;         // [B]
     // sync-variable table (open addressing)
@@ -259,7 +260,7 @@ struct Layout {
     u64 off_params, off_ev, off_act, off_s_cnt, off_s_fill, off_tile_s, off_s_tidx, off_s_pidx,
         off_s_pq, off_s_inv, off_s_phase, off_s_kind, off_s_flags, off_s_scope, off_s_imin,
         off_s_know, off_s_khandle, off_s_winst, off_e_prev0, off_e_prev1, off_e_src0, off_e_src1, off_e_cur,
-        off_e_relh, off_e_op, off_e_scan0, off_e_scan1, off_inst_opo, off_inst_bko, off_inst_coff, off_eng_jobs, off_t_kfirst,
+        off_e_relh, off_e_op, off_e_scan0, off_e_scan1, off_inst_opo, off_inst_bko, off_inst_coff, off_eng_jobs, off_t_kfirst, off_t_acq,
         off_ral_p, off_ral_key, off_op_p, off_op_dep, off_grp, off_blk_maxbar, off_inst_off, off_inst_cnt,
         off_inst_last, off_inst_handle, off_n_active, off_rt, off_priv, off_priv_next, off_bk,
         off_priv_head, off_sv_key, off_sv_tag, off_sv_handle, off_wo_key, off_wo_val, off_wi_key,
@@ -297,5 +298,14 @@ __device__ inline u32 list_search(const Bufs &b, u32 t, u32 idx) {
         else hi = mid;
     }
     return lo == first ? NONE : lo - 1;
+}
+
+// The knowledge handle of thread t at its access with trace index idx and barrier phase ph (block
+// blk), 0 for none.  A thread without acquires of its own knows, after its k-th barrier, what its
+// block knows after that barrier instance (no search); others search their sync list.
+__device__ inline u32 knowledge_at(const Bufs &b, u32 t, u32 idx, u32 blk, u32 ph) {
+    if (!b.t_acq[t]) return ph ? b.inst_handle[b.inst_off[blk] + ph - 1] : 0u;
+    const u32 j = list_search(b, t, idx);
+    return j == NONE ? 0u : b.s_know[j];
 }
 }  // namespace rd

@@ -334,15 +334,16 @@ __global__ void k_know(Bufs b) {
     if (!(P->mode & MODE_SYNC)) return;
     for (u32 t = blockIdx.x * blockDim.x + threadIdx.x; t < b.T; t += gridDim.x * blockDim.x) {
         const u32 lo = b.s_cnt[t], hi = b.s_cnt[t + 1], blk = t / b.tpb;
-        u32 cur = 0, first = NONE;
+        u32 cur = 0, first = NONE, acq = 0;
         for (u32 p = lo; p < hi; p++) {
             if (b.s_kind[p] == 4) cur = b.inst_handle[b.inst_off[blk] + b.s_phase[p] - 1];
-            else if (b.s_khandle[p]) cur = b.s_khandle[p];
+            else if (b.s_khandle[p]) { cur = b.s_khandle[p]; acq = 1; }
             b.s_know[p] = cur;
             if (cur && first == NONE) first = b.s_pidx[p];
         }
         // knowledge only grows along a thread's program order: accesses after `first` have some
         b.t_kfirst[t] = first;
+        b.t_acq[t] = acq;
     }
 }
 

@@ -304,10 +304,7 @@ __device__ inline bool happens_before(const Bufs &b, const u32 *rt_scan, u32 bid
                                       u32 &h, u32 ta, u32 ba, u32 pha, u32 ia) {
     if (ba == bblk && pha < bph) return true;
     if (!(b.prm->mode & MODE_SYNC)) return false;
-    if (h == NONE) {
-        const u32 j = list_search(b, btid, bidx);
-        h = j == NONE ? 0u : b.s_know[j];
-    }
+    if (h == NONE) h = knowledge_at(b, btid, bidx, bblk, bph);
     if (!h) return false;
     const u32 *V = b.pool + (u64)h * b.prm->D;
     if (V[ba] > pha) return true;
@@ -461,10 +458,7 @@ __device__ inline Walker walker_at(const Bufs &b, const SegCtx &s, u32 pos) {
     w.bph = info_phase(info);
     w.bcat = info_cat(info);
     w.h = 0;
-    if (b.prm->mode & MODE_SYNC) {
-        const u32 j = list_search(b, w.btid, w.bidx);
-        w.h = j == NONE ? 0u : b.s_know[j];
-    }
+    if (b.prm->mode & MODE_SYNC) w.h = knowledge_at(b, w.btid, w.bidx, w.bblk, w.bph);
     w.V = w.h ? b.pool + (u64)w.h * b.prm->D : nullptr;
     return w;
 }
