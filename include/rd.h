@@ -123,7 +123,11 @@ rd_status rd_check(rd_ctx ctx, rd_trace trace, hipStream_t stream);
 
 /* Waits for the check and copies the report: min(capacity, total) pairs in canonical order into
  * `out` (may be NULL to query the count), *n_races = total.  Returns RD_ETRACE for an invalid
- * trace, RD_ENOMEM when a device-side capacity overflowed, RD_ETRUNC when capacity < total. */
+ * trace, RD_ENOMEM when a device-side capacity overflowed, RD_ETRUNC when capacity < total.
+ * The check leaves the report on the device in this layout, and as many pairs as the trace's
+ * previous report held are copied together with the check's state (one wait when the report is no
+ * longer than the last one): entries of `out` past the returned pairs, up to `capacity`, may be
+ * overwritten, and so may `out` when an error is returned. */
 rd_status rd_races(rd_ctx ctx, rd_trace trace, rd_pair *out, uint64_t capacity, uint64_t *n_races);
 
 /* Batched form (the same check, many traces per pass).  The members are independent traces, each

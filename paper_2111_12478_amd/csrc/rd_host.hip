@@ -141,10 +141,11 @@ static Plan make_plan(u64 n, u32 nb, u32 tpb, const rd_limits *lim, bool copy_ev
     L.off_sort_tot = take(4ull * (MAX_SORT_PASSES * SORT_NDS + MAX_SORT_PASSES));
     L.off_part = take(4ull * P.part_words);
     L.off_tile_agg = take(agg_bytes() * ((u64)n_tiles + 1));
-    for (int c = 0; c < 2; c++) {
-        L.off_pfirst[c] = take(4 * max_pairs);
-        L.off_psecond[c] = take(4 * max_pairs);
-    }
+    L.off_pfirst[0] = take(4 * max_pairs);
+    L.off_psecond[0] = take(4 * max_pairs);
+    // the second pair buffer is one block: after the sort it holds the report as rd_pair records
+    L.off_pfirst[1] = take(8 * max_pairs);
+    L.off_psecond[1] = L.off_pfirst[1] + 4 * max_pairs;
     L.total = o;
     return P;
 }
@@ -229,6 +230,7 @@ static Bufs make_bufs(const Plan &P, char *ws, const void *events_dev, u64 n, u3
         b.pfirst[c] = (u32 *)(ws + L.off_pfirst[c]);
         b.psecond[c] = (u32 *)(ws + L.off_psecond[c]);
     }
+    b.preport = (u64 *)(ws + L.off_pfirst[1]);
     b.sort_status = (u64 *)(ws + L.off_sort_status);
     b.sort_status_stride = P.status_words;
     b.sort_partial = (u32 *)(ws + L.off_sort_partial);
@@ -392,6 +394,7 @@ hipError_t enqueue_plain(const Bufs &b, u64 *masks, u32 *rt_scan, hipStream_t s)
     const hipError_t e = enqueue_check(b, masks, rt_scan, s);
     if (e != hipSuccess) return e;
     sort_pairs(b, &b.prm->n_pairs_kept, 0, b.max_pairs, s);
+    pack_pairs(b, s);
     return hipGetLastError();
 }
 
@@ -457,6 +460,7 @@ struct rd_trace_s {
     std::string graph_filter;
     bool graph_off = false;  // capture failed once: checks are enqueued kernel by kernel
     uint64_t n_checks = 0;
+    u64 last_pairs = 0;  // the previous report's length: copied together with the check state
 };
 
 // A captured batched pass: replayed by rd_graph_launch for the same members and workspace.
@@ -786,9 +790,15 @@ static bool batch_races(rd_ctx ctx, rd_trace trace, rd_pair *out, uint64_t capac
 
 // The report of a check enqueued on `s` over buffers `b` (waits for it).
 static rd_status plain_races(rd_ctx ctx, const Bufs &b, hipStream_t s, rd_pair *out, uint64_t capacity,
-                             uint64_t *n_races) {
+                             uint64_t *n_races, u64 *hint) {
+    // the check left the sorted report as rd_pair records (pack_pairs); as many as the previous
+    // report of these buffers held are copied together with the state, so a report no longer than
+    // the last one takes a single wait
     DevParams prm;
+    const u64 lim = capacity < b.max_pairs ? capacity : b.max_pairs;
+    const u64 early = out && hint ? (*hint < lim ? *hint : lim) : 0;
     if (hipMemcpyAsync(&prm, b.prm, sizeof(prm), hipMemcpyDeviceToHost, s) != hipSuccess ||
+        (early && hipMemcpyAsync(out, b.preport, 8 * early, hipMemcpyDeviceToHost, s) != hipSuccess) ||
         hipStreamSynchronize(s) != hipSuccess)
         return set_err(ctx, RD_EHIP, UINT64_MAX, "reading the check state failed");
     if (prm.first_bad_record != NONE) return set_err(ctx, RD_ETRACE, prm.first_bad_record, "malformed record");
@@ -807,15 +817,13 @@ static rd_status plain_races(rd_ctx ctx, const Bufs &b, hipStream_t s, rd_pair *
     }
     const u32 m = prm.n_pairs_kept;
     *n_races = m;
+    if (hint) *hint = m;
     if (!out || !capacity || !m) return m > capacity ? set_err(ctx, RD_ETRUNC, UINT64_MAX, "capacity") : RD_OK;
-    // the check sorted the pairs (enqueue_plain)
     const u64 k = capacity < m ? capacity : m;
-    std::vector<u32> f(k), sec(k);
-    if (hipMemcpyAsync(f.data(), b.pfirst[0], 4 * k, hipMemcpyDeviceToHost, s) != hipSuccess ||
-        hipMemcpyAsync(sec.data(), b.psecond[0], 4 * k, hipMemcpyDeviceToHost, s) != hipSuccess ||
-        hipStreamSynchronize(s) != hipSuccess)
+    if (k > early && (hipMemcpyAsync(out + early, b.preport + early, 8 * (k - early), hipMemcpyDeviceToHost, s) !=
+                          hipSuccess ||
+                      hipStreamSynchronize(s) != hipSuccess))
         return set_err(ctx, RD_EHIP, UINT64_MAX, "copying the pairs failed");
-    for (u64 q = 0; q < k; q++) { out[q].first = f[q]; out[q].second = sec[q]; }
     if (capacity < m) return set_err(ctx, RD_ETRUNC, UINT64_MAX, "more races than capacity");
     return RD_OK;
 }
@@ -840,11 +848,11 @@ static rd_status member_alone(rd_ctx ctx, rd_trace trace, rd_pair *out, uint64_t
         g_prof = saved;
         if (e != hipSuccess) return set_err(ctx, RD_EHIP, UINT64_MAX, hipGetErrorString(e));
         uint64_t n = 0;
-        rd_status st = plain_races(ctx, b, B.stream, nullptr, 0, &n);
+        rd_status st = plain_races(ctx, b, B.stream, nullptr, 0, &n, nullptr);
         trace->cache.clear();
         if (st == RD_OK || st == RD_ETRUNC) {
             trace->cache.resize(n);
-            st = plain_races(ctx, b, B.stream, trace->cache.data(), n, &n);
+            st = plain_races(ctx, b, B.stream, trace->cache.data(), n, &n, nullptr);
         }
         if (st == RD_EHIP) return st;
         trace->cache_st = st;
@@ -876,7 +884,7 @@ rd_status rd_races(rd_ctx ctx, rd_trace trace, rd_pair *out, uint64_t capacity, 
         const rd_status c = rd_check(ctx, trace, trace->batch->stream);  // on its own; drops the batch
         if (c != RD_OK) return c;
     }
-    return plain_races(ctx, trace->bufs, trace->stream, out, capacity, n_races);
+    return plain_races(ctx, trace->bufs, trace->stream, out, capacity, n_races, &trace->last_pairs);
 }
 
 // The merged pass's buffers and member table (host side) for members that can share one pass.

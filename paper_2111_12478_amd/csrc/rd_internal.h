@@ -218,6 +218,7 @@ struct Bufs {
     void *tile_agg;         // [n_tiles] aggregates -> exclusive prefixes
     // pairs (ping-pong)
     u32 *pfirst[2], *psecond[2];
+    u64 *preport;           // [max_pairs] the sorted report as (first, second) records (over buffer 1)
     u64 max_pairs;
     // shape
     u32 N, T, B, tpb, ws;

@@ -41,6 +41,8 @@ void sort_elements(const Bufs &b, hipStream_t s);
 // radix sort of the kept race pairs by (first, second), result in buffer 0; the count is *m_dev
 // (launches sized for max_m) or m_host
 void sort_pairs(const Bufs &b, const u32 *m_dev, u32 m_host, u64 max_m, hipStream_t s);
+// The sorted pairs (buffer 0) as (first, second) records in b.preport, *n_pairs_kept of them.
+void pack_pairs(const Bufs &b, hipStream_t s);
 // stable sort of (key, value) pairs by key (see rd_sort.hip)
 void sort_kv(const Bufs &b, u32 *const k[2], u32 *const v[2], const u32 *n_dev, u64 max_n, u32 passes,
              const u32 *bits_dev, const char *name, hipStream_t s);

@@ -395,6 +395,22 @@ void sort_pairs(const Bufs &b, const u32 *m_dev, u32 m_host, u64 max_m, hipStrea
     }
 }
 
+// Interleaves the sorted pairs into (first, second) records, the report's host layout.
+__global__ __launch_bounds__(WG_THREADS) void k_pair_pack(const u32 *first, const u32 *second, const u32 *m_dev,
+                                                          u64 max_m, u64 *out) {
+    const u64 m = *m_dev < max_m ? *m_dev : max_m;
+    for (u64 i = (u64)blockIdx.x * WG_THREADS + threadIdx.x; i < m; i += (u64)gridDim.x * WG_THREADS)
+        out[i] = (u64)first[i] | ((u64)second[i] << 32);
+}
+
+void pack_pairs(const Bufs &b, hipStream_t s) {
+    if (!b.max_pairs) return;
+    const u64 tiles = (b.max_pairs + WG_THREADS - 1) / WG_THREADS;
+    const u32 grid = tiles < 1024 ? (u32)tiles : 1024u;
+    RD_LAUNCH("k_pair_pack", k_pair_pack, dim3(grid), dim3(WG_THREADS), 0, s, b.pfirst[0], b.psecond[0],
+              &b.prm->n_pairs_kept, b.max_pairs, b.preport);
+}
+
 // Stable sort of (key, value) pairs in k[0], v[0] by key: n = *n_dev items (launches sized for max_n),
 // at most `passes` 8-bit passes; with bits_dev the passes past *bits_dev bits do nothing (the result
 // is then in buffer ceil(*bits_dev / 8) % 2, else in buffer passes % 2).  Uses the sort state and

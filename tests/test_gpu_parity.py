@@ -127,6 +127,35 @@ def test_graph_replays_follow_the_events(rc):
         rd_trace_free(rc.ctx, tr)
 
 
+def test_report_length_changes_between_checks(rc):
+    # the report copy is sized by the trace's previous report: reports that grow, shrink, are cut
+    # by a small capacity or only counted all come out whole and in order
+    import torch
+    from paper_2111_12478_amd import rd_trace_free
+    cases = [tracegen.generate(tracegen.tiny(seed=s)) for s in (21, 22, 23, 24)]
+    grid = cases[0][0]
+    cases = [c for c in cases if tuple(c[0]) == tuple(grid) and c[1].shape == cases[0][1].shape]
+    want = [oracle.check(grid, c[1]) for c in cases]
+    counts = sorted({len(w.pairs) for w in want if w.status == 0})
+    assert len(counts) >= 2, counts
+    dev = torch.from_numpy(cases[0][1].view(np.int32).copy()).cuda()
+    tr, ws, keep = rc.prepare(grid, dev)
+    try:
+        order = [0, 1, 2, 3, 3, 2, 1, 0, 0]
+        for step, j in enumerate(order):
+            dev.copy_(torch.from_numpy(cases[j % len(cases)][1].view(np.int32)))
+            w = want[j % len(cases)]
+            cap = 2 if step in (4, 6) else None
+            got = rc.run(tr, cap) if cap else rc.run(tr)
+            torch.cuda.synchronize()
+            assert got.status == (w.status if w.status != 0 or not cap or len(w.pairs) <= cap else -4), (step, got)
+            if w.status == 0:
+                ref = w.pairs if not cap else w.pairs[:cap]
+                np.testing.assert_array_equal(got.pairs, ref, err_msg=f"step {step}")
+    finally:
+        rd_trace_free(rc.ctx, tr)
+
+
 @pytest.mark.parametrize("seed", list(range(7000, 7030)))
 def test_random_traces_wide_addresses(rc, seed):
     # global words spread over about 2^31 addresses: 32-bit location keys leave no room for the
