@@ -130,11 +130,12 @@ static Plan make_plan(u64 n, u32 nb, u32 tpb, const rd_limits *lim, bool copy_ev
     L.off_winst_nar = take(4ull * L.wo_cap);
     L.off_winst_arr = take(4ull * 32 * L.wo_cap);
     L.off_pool = take(pool_bytes);
+    const u64 NE = (N1 + SORT_MAX_TILE - 1) / SORT_MAX_TILE * SORT_MAX_TILE;
     for (int c = 0; c < 2; c++) {
-        L.off_ekey[c] = take(4 * N1);
-        L.off_eidx[c] = take(4 * N1);
-        L.off_etid[c] = take(4 * N1);
-        L.off_einfo[c] = take(4 * N1);
+        L.off_ekey[c] = take(4 * NE);
+        L.off_eidx[c] = take(4 * NE);
+        L.off_etid[c] = take(4 * NE);
+        L.off_einfo[c] = take(4 * NE);
     }
     L.off_sort_status = take(2 * 8ull * P.status_words);
     L.off_sort_partial = take(4ull * P.partial_words);

@@ -74,6 +74,9 @@ constexpr u32 SORT_RB = 8, SORT_ND = 1u << SORT_RB;
 constexpr u32 SORT_NDS = 512;        // digit stride of the count rows and totals (9-bit digits)
 constexpr u32 MAX_SORT_PASSES = 8;
 constexpr u32 ELEM_MAX_PASSES = 5;   // ceil(32 / 7)
+// the largest location-sort tile (16 wavefronts x 16 items): the element arrays are padded to a
+// whole number of such tiles, so the sort loads full tiles without a bounds test
+constexpr u32 SORT_MAX_TILE = 16384;
 // Digit counts: every tile writes one row of partial counts ([pass][digit], ELEM_MAX_PASSES passes
 // for the location sort, MAX_SORT_PASSES for the pair sort); a reduction adds the rows into
 // per-pass totals.

@@ -157,12 +157,16 @@ __global__ __launch_bounds__(NW * 64) void k_sort_sweep(SweepArgs a) {
     const u64 wbase = tile0 + (u64)w * NI * 64;
     const u32 shift = a.shift;
     const u32 total = has_d ? a.tot[a.pass * SORT_NDS + dme] : 0u;
+    // the element arrays are padded to whole tiles: their loads need no bounds test (items past n
+    // are loaded and never used)
+    constexpr bool PADDED = NP == 3;
+    static_assert(!PADDED || TS <= SORT_MAX_TILE, "element tiles fit the padding");
     // keys now; each payload array is read when it goes through the LDS (fewer live registers)
     u32 key[NI], off[NI];
 #pragma unroll
     for (int k = 0; k < NI; k++) {
         const u64 i = wbase + (u64)k * 64 + lane;
-        key[k] = i < n ? a.kin[i] : 0;
+        key[k] = PADDED || i < n ? a.kin[i] : 0;
     }
     // rank: position of each key among the equal digits of its wave, in input order
 #pragma unroll
@@ -182,7 +186,11 @@ __global__ __launch_bounds__(NW * 64) void k_sort_sweep(SweepArgs a) {
         __builtin_amdgcn_wave_barrier();
         if (valid && rank == 0) L.wcnt[w][d] = old + popc64(m);
         __builtin_amdgcn_wave_barrier();
-        off[k] = old + rank;
+        // tile-local rank below 2^14, the digit above bit 16 (one register per item)
+        off[k] = valid ? (old + rank) | (d << 16) : NONE;
+        // computed here: left to the compiler, the ballot masks of all items stay live until the
+        // ranks are used after the barrier (four registers per item instead of one)
+        __asm__ volatile("" : "+v"(off[k]));
     }
     __syncthreads();
     // digit dme: exclusive wave prefixes and the tile's count
@@ -210,6 +218,29 @@ __global__ __launch_bounds__(NW * 64) void k_sort_sweep(SweepArgs a) {
         if (lane >= (u32)o) { x += xs; y += ys; }
     }
     if (lane == 63) { L.wtot[0][w] = x; L.wtot[1][w] = y; }
+    __syncthreads();
+    // tile-local start (pre) and global base (gb) of digit dme; (wave, digit) starts in the tile
+    u32 pre = 0, gb = 0;
+    if (has_d) {
+        pre = x - cnt;
+        gb = y - total;
+        for (u32 q = 0; q < w; q++) { pre += L.wtot[0][q]; gb += L.wtot[1][q]; }
+#pragma unroll
+        for (u32 q = 0; q < NW; q++) L.wcnt[q][dme] += pre;
+    }
+    __syncthreads();
+    // local sorted positions, and the keys into the LDS: the key registers are free from here
+#pragma unroll
+    for (int k = 0; k < NI; k++) {
+        if (off[k] != NONE) {
+            off[k] = (off[k] & 0xffffu) + L.wcnt[w][off[k] >> 16];
+            L.stage[off[k]] = key[k];
+        }
+    }
+    // the first payload's loads are in flight during the look-back
+    u32 pay[NI];
+#pragma unroll
+    for (int k = 0; k < NI; k++) pay[k] = PADDED || off[k] != NONE ? a.pin[0][wbase + (u64)k * 64 + lane] : 0u;
     // look back: digit dme's count in all earlier tiles, LOOKBACK predecessor words per round
     u64 excl = 0;
     if (has_d && tile > 0) {
@@ -243,52 +274,46 @@ __global__ __launch_bounds__(NW * 64) void k_sort_sweep(SweepArgs a) {
         }
         __hip_atomic_store(my, ST_PRE | (excl + cnt), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }
-    __syncthreads();
-    if (has_d) {
-        u32 pre = x - cnt, gb = y - total;
-        for (u32 q = 0; q < w; q++) { pre += L.wtot[0][q]; gb += L.wtot[1][q]; }
-#pragma unroll
-        for (u32 q = 0; q < NW; q++) L.wcnt[q][dme] += pre;
-        L.dg[dme] = gb + (u32)excl - pre;
-    }
+    if (has_d) L.dg[dme] = gb + (u32)excl - pre;  // global position minus tile-local position
     __syncthreads();
     const u32 cnt_tile = (u32)((n - tile0) < (u64)TS ? (n - tile0) : (u64)TS);
-    // local sorted positions
+    // keys out, in runs per digit; each sorted position's digit is kept (packed) for the payloads
+    constexpr int DW = RB <= 8 ? 8 : 16, DPW = 32 / DW;
+    u32 dgt[(NI + DPW - 1) / DPW];
 #pragma unroll
-    for (int k = 0; k < NI; k++) {
-        const bool valid = wbase + (u64)k * 64 + lane < n;
-        off[k] = valid ? L.wcnt[w][((key[k] & kmask) >> shift) & DM] + off[k] : NONE;
-    }
-    // keys through LDS, then each payload array
-#pragma unroll
-    for (int k = 0; k < NI; k++)
-        if (off[k] != NONE) L.stage[off[k]] = key[k];
-    __syncthreads();
-    u32 gpos[NI];
+    for (int r = 0; r < (NI + DPW - 1) / DPW; r++) dgt[r] = 0;
 #pragma unroll
     for (int r = 0; r < NI; r++) {
         const u32 j = r * THREADS + threadIdx.x;
-        gpos[r] = NONE;
         if (j < cnt_tile) {
             const u32 kk = L.stage[j];
-            gpos[r] = L.dg[((kk & kmask) >> shift) & DM] + j;
-            a.kout[gpos[r]] = kk;
+            const u32 d = ((kk & kmask) >> shift) & DM;
+            dgt[r / DPW] |= d << (DW * (r % DPW));
+            a.kout[L.dg[d] + j] = kk;
         }
     }
+    // payloads through the LDS; the next one's loads are issued before this one is written out
 #pragma unroll
     for (int q = 0; q < NP; q++) {
         if ((u32)q >= np_run) break;
-        u32 pay[NI];
-#pragma unroll
-        for (int k = 0; k < NI; k++) pay[k] = off[k] != NONE ? a.pin[q][wbase + (u64)k * 64 + lane] : 0u;
         __syncthreads();
 #pragma unroll
         for (int k = 0; k < NI; k++)
             if (off[k] != NONE) L.stage[off[k]] = pay[k];
+        if ((u32)q + 1 < np_run) {
+#pragma unroll
+            for (int k = 0; k < NI; k++)
+                pay[k] = PADDED || off[k] != NONE ? a.pin[q + 1][wbase + (u64)k * 64 + lane] : 0u;
+        }
         __syncthreads();
 #pragma unroll
-        for (int r = 0; r < NI; r++)
-            if (gpos[r] != NONE) a.pout[q][gpos[r]] = L.stage[r * THREADS + threadIdx.x];
+        for (int r = 0; r < NI; r++) {
+            const u32 j = r * THREADS + threadIdx.x;
+            if (j < cnt_tile) {
+                const u32 d = (dgt[r / DPW] >> (DW * (r % DPW))) & ((1u << DW) - 1);
+                a.pout[q][L.dg[d] + j] = L.stage[j];
+            }
+        }
     }
     if (LOOP) __syncthreads();  // the LDS is reused for the next tile
     } while (LOOP);
