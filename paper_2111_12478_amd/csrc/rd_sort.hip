@@ -173,18 +173,24 @@ __global__ __launch_bounds__(NW * 64) void k_sort_sweep(SweepArgs a) {
     for (int k = 0; k < NI; k++) {
         const bool valid = wbase + (u64)k * 64 + lane < n;
         const u32 d = ((key[k] & kmask) >> shift) & DM;
-        u64 m = ballot(valid);
+        // lanes with the same digit: the intersection over the digit bits of the lanes that agree
+        // with this lane on the bit, in 32-bit halves: with s = 0 or ~0 the lane's bit, the lanes
+        // that agree are ~(ballot ^ s)
+        const u64 vm = ballot(valid);
+        u32 mlo = (u32)vm, mhi = (u32)(vm >> 32);
 #pragma unroll
         for (int bit = 0; bit < RB; bit++) {
-            const u64 bb = ballot((d >> bit) & 1u);
-            m &= ((d >> bit) & 1u) ? bb : ~bb;
+            const u32 sb = (u32)((int)(d << (31 - bit)) >> 31);
+            const u64 bb = ballot(sb != 0u);
+            mlo &= ~((u32)bb ^ sb);
+            mhi &= ~((u32)(bb >> 32) ^ sb);
         }
-        const u32 rank = popc64(m & lanemask_lt());
+        const u32 rank = __builtin_amdgcn_mbcnt_hi(mhi, __builtin_amdgcn_mbcnt_lo(mlo, 0u));
         u32 old = 0;
         if (valid) old = L.wcnt[w][d];
         // wave-synchronous: every lane of the group has read the old count before the leader writes
         __builtin_amdgcn_wave_barrier();
-        if (valid && rank == 0) L.wcnt[w][d] = old + popc64(m);
+        if (valid && rank == 0) L.wcnt[w][d] = old + __builtin_popcount(mlo) + __builtin_popcount(mhi);
         __builtin_amdgcn_wave_barrier();
         // tile-local rank below 2^14, the digit above bit 16 (one register per item)
         off[k] = valid ? (old + rank) | (d << 16) : NONE;
