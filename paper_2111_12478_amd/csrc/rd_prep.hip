@@ -552,74 +552,130 @@ __global__ __launch_bounds__(WG_THREADS) void k_elements(Bufs b, const u64 *acc_
     const u32 rb = b.radix_bits, nd = 1u << rb;
     for (u32 x = threadIdx.x; x < ELEM_MAX_PASSES * SORT_NDS; x += WG_THREADS) (&dcnt[0][0])[x] = 0;
     const u64 word0 = (u64)blockIdx.x * (TILE / 64);
-    u64 m[ITEMS];
-    u32 pre[ITEMS];
-    wave_mask_prefix(acc_mask, nullptr, word0, w, wbase, b.tile_s[b.n_tiles + 1 + blockIdx.x], m, pre);
+    // each item's output slot, NONE where the lane's event is not an access
+    u32 slot[ITEMS];
+    {
+        u64 m[ITEMS];
+        u32 pre[ITEMS];
+        wave_mask_prefix(acc_mask, nullptr, word0, w, wbase, b.tile_s[b.n_tiles + 1 + blockIdx.x], m, pre);
+#pragma unroll
+        for (int k = 0; k < ITEMS; k++) slot[k] = (m[k] >> lane) & 1 ? pre[k] : NONE;
+    }
     const DevParams *p = b.prm;
     const u32 gbase = p->gbase, sbase = p->sbase, g_span = p->g_span, s_span = p->s_span;
     const u32 mode = p->mode;
     const u32 np = (p->key_bits + rb - 1) / rb;
     const bool packed = packed_elements(p->key_bits, p->max_phase);
+    const bool lists = (mode & (MODE_SYNC | MODE_BAR)) != 0;
     u32 *ekey = b.ekey[0], *eidx = b.eidx[0], *etid = b.etid[0], *einfo = b.einfo[0];
     const u64 base = (u64)blockIdx.x * TILE + (u64)w * ITEMS * 64;
-#pragma unroll 2
-    for (int k = 0; k < ITEMS; k++) {
-        if (!((m[k] >> lane) & 1)) continue;
-        const u32 idx = (u32)(base + (u64)k * 64 + lane);
-        const uint4 e = b.ev[idx];
-        const u32 kind = e.z & 15u, scope = (e.z >> 4) & 3u, space = (e.z >> 6) & 1u, t = e.y;
-        const u32 blk = block_of(b, t);
-        const u32 key = space ? g_span + blk * s_span + (e.x - sbase) : e.x - gbase;
-        u32 cat;
-        if (kind == 0) cat = CAT_R;
-        else if (kind == 1) cat = CAT_W;
-        else cat = scope == 0 ? CAT_AB : CAT_AD;
-        u32 ph = 0;
-        if (mode & MODE_SYNC) {
-            const u32 j = list_search(b, t, idx);
-            if (j != NONE) {
-                ph = b.s_phase[j];
-                // the first plain access after an atomic, a fence or a warp barrier (release/acquire
-                // inference, warp-barrier rule); after a block barrier the access checks the rule itself
-                const u32 kj = b.s_kind[j];
-                if (kind <= 1 && (kj == 2 || kj == 3 || kj == 5) && b.s_imin[j] > idx) atomicMin(&b.s_imin[j], idx);
-                if (ph > 0) {
-                    const u32 slot = b.inst_off[blk] + ph - 1;
-                    if (b.inst_cnt[slot] != b.n_active[blk] || b.inst_last[slot] > idx)
-                        atomicMin(&b.prm->first_bad_sync, idx);
+    // items in groups of GI: the loads of a group's items are issued together (events, list bounds,
+    // one binary-search step for every item of the group at a time, entries, barrier instances),
+    // so a lane has GI dependent chains in flight instead of one
+    constexpr int GI = 4;
+    static_assert(ITEMS % GI == 0, "whole groups");
+    for (int k0 = 0; k0 < ITEMS; k0 += GI) {
+        u32 idx[GI], t[GI], meta[GI], addr[GI], lo[GI], hi[GI], j[GI];
+#pragma unroll
+        for (int i = 0; i < GI; i++) {
+            idx[i] = (u32)(base + (u64)(k0 + i) * 64 + lane);
+            t[i] = meta[i] = addr[i] = 0;
+            if (slot[k0 + i] != NONE) {
+                const uint4 e = b.ev[idx[i]];
+                addr[i] = e.x;
+                t[i] = e.y;
+                meta[i] = e.z;
+            }
+        }
+        // the last list entry of the thread before the access (a binary search in lockstep)
+#pragma unroll
+        for (int i = 0; i < GI; i++) {
+            lo[i] = hi[i] = 0;
+            if (lists && slot[k0 + i] != NONE) { lo[i] = b.s_cnt[t[i]]; hi[i] = b.s_cnt[t[i] + 1]; }
+            j[i] = lo[i];  // the list's first entry, for now
+        }
+        for (;;) {
+            u32 mid[GI], v[GI];
+            bool any = false;
+#pragma unroll
+            for (int i = 0; i < GI; i++) {
+                mid[i] = (lo[i] + hi[i]) >> 1;
+                v[i] = 0;
+                if (lo[i] < hi[i]) { v[i] = b.s_pidx[mid[i]]; any = true; }
+            }
+            if (!any) break;
+#pragma unroll
+            for (int i = 0; i < GI; i++) {
+                if (lo[i] < hi[i]) {
+                    if (v[i] < idx[i]) lo[i] = mid[i] + 1;
+                    else hi[i] = mid[i];
                 }
             }
-        } else if (mode & MODE_BAR) {
-            // the thread's list holds only its barriers: the phase is the number of entries before idx,
-            // and the block-barrier rule is checked here, for the access itself
-            const u32 j = list_search(b, t, idx);
-            if (j != NONE) {
-                ph = j - b.s_cnt[t] + 1;
-                const u32 slot = b.inst_off[blk] + ph - 1;
-                if (b.inst_cnt[slot] != b.n_active[blk] || b.inst_last[slot] > idx)
-                    atomicMin(&b.prm->first_bad_sync, idx);
+        }
+#pragma unroll
+        for (int i = 0; i < GI; i++) j[i] = lo[i] == j[i] ? NONE : lo[i] - 1;
+        // phases and the checks that need the entry
+        u32 ph[GI], blk[GI];
+#pragma unroll
+        for (int i = 0; i < GI; i++) {
+            blk[i] = block_of(b, t[i]);
+            ph[i] = 0;
+            if (slot[k0 + i] == NONE || j[i] == NONE) continue;
+            if (mode & MODE_SYNC) {
+                ph[i] = b.s_phase[j[i]];
+                // the first plain access after an atomic, a fence or a warp barrier (release/acquire
+                // inference, warp-barrier rule)
+                const u32 kj = b.s_kind[j[i]], kind = meta[i] & 15u;
+                if (kind <= 1 && (kj == 2 || kj == 3 || kj == 5) && b.s_imin[j[i]] > idx[i])
+                    atomicMin(&b.s_imin[j[i]], idx[i]);
+            } else {
+                // the thread's list holds only its barriers: the phase is the number of entries
+                // before idx
+                ph[i] = j[i] - b.s_cnt[t[i]] + 1;
             }
         }
-        const u32 o = pre[k];
-        if (packed) {
-            ekey[o] = pack_element(key, p->key_bits, cat, ph);
-        } else {
-            ekey[o] = key;
-            einfo[o] = info_make(cat, ph);
+        // after a block barrier the access checks the barrier rule itself
+#pragma unroll
+        for (int i = 0; i < GI; i++) {
+            if (ph[i] == 0) continue;
+            const u32 sl = b.inst_off[blk[i]] + ph[i] - 1;
+            if (b.inst_cnt[sl] != b.n_active[blk[i]] || b.inst_last[sl] > idx[i])
+                atomicMin(&b.prm->first_bad_sync, idx[i]);
         }
-        eidx[o] = idx;
-        etid[o] = t;
-        // digit counts: where every active lane has the wavefront's first digit (high digits of
-        // clustered addresses), one lane adds them all instead of 64 atomics on one LDS word
-        const u64 act = ballot(true);
-        const u32 first = (u32)__builtin_ctzll(act);
-        for (u32 q = 0; q < np; q++) {
-            const u32 d = (key >> (q * rb)) & (nd - 1);
-            const u32 d0 = __shfl(d, first, 64);
-            if (ballot(d == d0) == act) {
-                if (lane == first) atomicAdd(&dcnt[q][d0], popc64(act));
-            } else {
-                atomicAdd(&dcnt[q][d], 1u);
+#pragma unroll
+        for (int i = 0; i < GI; i++) {
+            const bool mine = slot[k0 + i] != NONE;
+            const u64 act = ballot(mine);
+            if (!act) continue;
+            u32 key = 0;
+            if (mine) {
+                const u32 kind = meta[i] & 15u, scope = (meta[i] >> 4) & 3u, space = (meta[i] >> 6) & 1u;
+                key = space ? g_span + blk[i] * s_span + (addr[i] - sbase) : addr[i] - gbase;
+                u32 cat;
+                if (kind == 0) cat = CAT_R;
+                else if (kind == 1) cat = CAT_W;
+                else cat = scope == 0 ? CAT_AB : CAT_AD;
+                const u32 o = slot[k0 + i];
+                if (packed) {
+                    ekey[o] = pack_element(key, p->key_bits, cat, ph[i]);
+                } else {
+                    ekey[o] = key;
+                    einfo[o] = info_make(cat, ph[i]);
+                }
+                eidx[o] = idx[i];
+                etid[o] = t[i];
+            }
+            // digit counts: where every active lane has the wavefront's first digit (high digits of
+            // clustered addresses), one lane adds them all instead of 64 atomics on one LDS word
+            const u32 first = (u32)__builtin_ctzll(act);
+            for (u32 q = 0; q < np; q++) {
+                const u32 d = (key >> (q * rb)) & (nd - 1);
+                const u32 d0 = __shfl(d, first, 64);
+                if (ballot(mine && d == d0) == act) {
+                    if (lane == first) atomicAdd(&dcnt[q][d0], popc64(act));
+                } else if (mine) {
+                    atomicAdd(&dcnt[q][d], 1u);
+                }
             }
         }
     }
