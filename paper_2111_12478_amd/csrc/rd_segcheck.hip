@@ -200,26 +200,62 @@ __device__ inline void items_agg(const Bufs &b, const Items &it, u32 cnt, u32 ba
     }
 }
 
-// Block-wide (NT threads) exclusive scan of Aggs in LDS; `mine` becomes this thread's exclusive
-// prefix, *total (when non-null) the block total.
-template <u32 NT = WG_THREADS>
-__device__ inline void block_exscan_agg(Agg &mine, Agg *buf /* 2*NT */, Agg *total) {
-    const u32 x = threadIdx.x;
-    buf[x] = mine;
-    __syncthreads();
-    u32 src = 0;
-    for (u32 d = 1; d < NT; d <<= 1) {
-        Agg v = buf[src * NT + x];
-        if (x >= d) agg_combine(buf[src * NT + x - d], v);
-        buf[(src ^ 1) * NT + x] = v;
-        __syncthreads();
-        src ^= 1;
+__device__ inline Agg shfl_up_agg(const Agg &a, u32 d) {
+    Agg r;
+    r.first_key = __shfl_up(a.first_key, d, 64);
+    r.last_key = __shfl_up(a.last_key, d, 64);
+    r.run_blk = __shfl_up(a.run_blk, d, 64);
+    r.run_ph = __shfl_up(a.run_ph, d, 64);
+    r.blk = __shfl_up(a.blk, d, 64);
+    r.blk2 = __shfl_up(a.blk2, d, 64);
+    r.twa = __shfl_up(a.twa, d, 64);
+    r.tna = __shfl_up(a.tna, d, 64);
+    r.tall = __shfl_up(a.tall, d, 64);
+    r.fl = __shfl_up(a.fl, d, 64);
+    r.first_pos = __shfl_up(a.first_pos, d, 64);
+    r.seg_pos = __shfl_up(a.seg_pos, d, 64);
+    r.run_pos = __shfl_up(a.run_pos, d, 64);
+    return r;
+}
+
+// Inclusive scan over the lanes of a wavefront: lane i gets a_0 (+) ... (+) a_i.
+__device__ inline void wave_inscan_agg(Agg &v) {
+    const u32 lane = lane_id();
+#pragma unroll
+    for (u32 d = 1; d < 64; d <<= 1) {
+        const Agg o = shfl_up_agg(v, d);
+        if (lane >= d) agg_combine(o, v);
     }
-    if (total) *total = buf[src * NT + NT - 1];
-    Agg ex;
-    if (x == 0) agg_empty(ex);
-    else ex = buf[src * NT + x - 1];
+}
+
+// Block-wide (NT threads) exclusive scan of Aggs: each wavefront scans its lanes with shuffles,
+// one wavefront scans the wavefront totals (wtot, NT / 64 entries of LDS).  `mine` becomes this
+// thread's exclusive prefix, *total (when non-null) the block total.
+template <u32 NT = WG_THREADS>
+__device__ inline void block_exscan_agg(Agg &mine, Agg *wtot /* NT / 64 */, Agg *total) {
+    constexpr u32 W = NT / 64;
+    static_assert(W >= 1 && W <= 64, "one wavefront scans the wavefront totals");
+    const u32 lane = lane_id(), w = threadIdx.x >> 6;
+    Agg inc = mine;
+    wave_inscan_agg(inc);
+    if (lane == 63) wtot[w] = inc;
     __syncthreads();
+    if (w == 0) {
+        Agg t;
+        if (lane < W) t = wtot[lane];
+        else agg_empty(t);
+        wave_inscan_agg(t);
+        if (lane < W) wtot[lane] = t;
+    }
+    __syncthreads();
+    Agg ex = shfl_up_agg(inc, 1);
+    if (lane == 0) agg_empty(ex);
+    if (w > 0) {
+        const Agg pw = wtot[w - 1];
+        agg_combine(pw, ex);
+    }
+    if (total) *total = wtot[W - 1];
+    __syncthreads();  // wtot is free for the caller again
     mine = ex;
 }
 
@@ -228,7 +264,7 @@ __device__ inline u32 items_in(const SegCtx &s, u64 base) {
 }
 
 __global__ __launch_bounds__(WG_THREADS) void k_seg_reduce(Bufs b) {
-    __shared__ Agg buf[2 * WG_THREADS];
+    __shared__ Agg buf[WAVES];
     const SegCtx s = seg_ctx(b);
     Agg *tile_agg = (Agg *)b.tile_agg;
     const u64 tile0 = (u64)blockIdx.x * TILE;
@@ -251,7 +287,7 @@ __global__ __launch_bounds__(WG_THREADS) void k_seg_reduce(Bufs b) {
 constexpr u32 SCAN_THREADS = 1024;
 
 __global__ __launch_bounds__(SCAN_THREADS) void k_seg_scan(Bufs b) {
-    __shared__ Agg buf[2 * SCAN_THREADS];
+    __shared__ Agg buf[SCAN_THREADS / 64];
     const SegCtx s = seg_ctx(b);
     Agg *tile_agg = (Agg *)b.tile_agg;
     const u32 nt = (u32)((s.n + TILE - 1) / TILE);
@@ -583,7 +619,7 @@ __device__ void lane_walks(const Bufs &b, const SegCtx &s, const u32 *rt_scan, u
 }
 
 union CheckLds {
-    Agg buf[2 * WG_THREADS];
+    Agg buf[WAVES];
     struct { u32 pf[WAVES][WAVE_PAIRS], ps[WAVES][WAVE_PAIRS]; } pairs;
 };
 
