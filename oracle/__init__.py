@@ -135,3 +135,23 @@ def validate(grid, events) -> OracleResult:
     bad = ctypes.c_uint64(0)
     rc = lib.orc_validate(nb, tpb, ws, ev.ctypes.data, ev.shape[0], ctypes.byref(bad))
     return OracleResult(rc, _bad(bad.value), np.zeros((0, 2), dtype=np.uint32))
+
+
+def race_kinds(events, pairs) -> np.ndarray:
+    """Unique race kinds of a report (the "unique kinds" counted in the paper's Table 2, Section 6).
+
+    The paper does not define a kind; the reading taken here: a kind is the unordered pair of the
+    two accesses' site ids (the records' ``aux`` words), so the same two program sites racing in
+    either order are one kind.  Returns a ``(K, 3)`` uint32 array of ``(site_lo, site_hi, count)``,
+    rows in ascending ``(site_lo, site_hi)`` order, ``count`` the number of racing pairs of the kind.
+    Parity pins: special cases only (every site distinct, every site equal, swapped order).
+    """
+    ev = _events(events)
+    pr = np.asarray(pairs, dtype=np.uint32).reshape(-1, 2)
+    if pr.shape[0] == 0:
+        return np.zeros((0, 3), dtype=np.uint32)
+    sa = ev[pr[:, 0], 3]
+    sb = ev[pr[:, 1], 3]
+    sites = np.stack([np.minimum(sa, sb), np.maximum(sa, sb)], axis=1)
+    kinds, counts = np.unique(sites, axis=0, return_counts=True)
+    return np.concatenate([kinds, counts.astype(np.uint32)[:, None]], axis=1).astype(np.uint32)
