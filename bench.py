@@ -759,6 +759,22 @@ def main():
         out["parity"] = "bit-exact" if np.array_equal(want.pairs, gpu_pairs) else \
             f"MISMATCH gpu={len(gpu_pairs)} oracle={len(want.pairs)}"
 
+    # unique race kinds of the report (site-id pairs), built on the device after the timed steps:
+    # wall time per call (it waits for the check's state, builds the kinds, copies them back)
+    st, kinds = rc.kinds(tr)
+    reps = 5
+    torch.cuda.synchronize()
+    k0 = time.perf_counter()
+    for _ in range(reps):
+        st, kinds = rc.kinds(tr)
+    k1 = time.perf_counter()
+    out["race_kinds"] = {"kinds": int(kinds.shape[0]), "pairs": int(len(gpu_pairs)), "status": int(st),
+                         "ms_per_call": (k1 - k0) * 1e3 / reps}
+    if not args.no_cpu_baseline:
+        wk = oracle.race_kinds(ev, want.pairs)
+        out["race_kinds"]["parity"] = "bit-exact" if np.array_equal(wk, kinds) else \
+            f"MISMATCH gpu={len(kinds)} oracle={len(wk)}"
+
     rd.rd_trace_free(rc.ctx, tr)
     print(json.dumps(out), flush=True)
 

@@ -130,6 +130,22 @@ rd_status rd_check(rd_ctx ctx, rd_trace trace, hipStream_t stream);
  * overwritten, and so may `out` when an error is returned. */
 rd_status rd_races(rd_ctx ctx, rd_trace trace, rd_pair *out, uint64_t capacity, uint64_t *n_races);
 
+/* One unique race kind: the unordered pair of the two racing accesses' site ids (the records'
+ * aux words, site_lo <= site_hi) and the number of racing pairs of that kind.  The paper counts
+ * unique kinds of races (Table 2, Section 6) without defining a kind; this is the reading taken. */
+typedef struct {
+    uint32_t site_lo, site_hi, count;
+} rd_race_kind;
+
+/* The unique race kinds of a checked trace, built on the device from its report: min(capacity,
+ * total) kinds in ascending (site_lo, site_hi) order into `out` (may be NULL with capacity 0 to
+ * query the count), *n_kinds = total.  Call after rd_check (rd_races need not come first); the
+ * events and the workspace must still be valid.  Waits for the check.  Errors: those of rd_races
+ * for the check itself, RD_ETRUNC when capacity < total, RD_ENOMEM when the context's device
+ * scratch (about 32 bytes per race pair, kept until rd_shutdown) cannot be allocated, RD_ESTATE
+ * for a batch member without a workspace of its own (a member with one is checked alone first). */
+rd_status rd_race_kinds(rd_ctx ctx, rd_trace trace, rd_race_kind *out, uint64_t capacity, uint64_t *n_kinds);
+
 /* Batched form (the same check, many traces per pass).  The members are independent traces, each
  * bound by rd_trace_upload to its own workspace as for rd_check.  rd_check_many enqueues one pass
  * of the pipeline over their concatenation: every trace keeps its own blocks, threads and words

@@ -78,6 +78,7 @@ def load_library():
             "rd_trace_upload": ([vp, P(rd_grid), vp, u64, ctypes.c_int, vp, u64, P(rd_limits), vp, P(vp)], i32),
             "rd_check": ([vp, vp, vp], i32),
             "rd_races": ([vp, vp, vp, u64, P(u64)], i32),
+            "rd_race_kinds": ([vp, vp, vp, u64, P(u64)], i32),
             "rd_trace_free": ([vp, vp], i32),
             "rd_batch_workspace_bytes": ([vp, P(vp), u32, P(rd_limits), P(u64)], i32),
             "rd_check_many": ([vp, P(vp), u32, vp, u64, P(rd_limits), vp], i32),
@@ -154,6 +155,14 @@ def rd_trace_upload(ctx, grid, events_ptr, n_events, events_on_device, workspace
 
 def rd_check(ctx, trace, stream) -> int:
     return load_library().rd_check(ctx, trace, stream)
+
+
+def rd_race_kinds(ctx, trace, out_ptr, capacity) -> tuple[int, int]:
+    """Unique race kinds of a checked trace into (capacity, 3) uint32 records (site_lo, site_hi,
+    count) at out_ptr.  Returns (status, total kinds)."""
+    n = ctypes.c_uint64()
+    st = load_library().rd_race_kinds(ctx, trace, out_ptr, capacity, ctypes.byref(n))
+    return st, n.value
 
 
 def rd_races(ctx, trace, out_ptr, capacity) -> tuple[int, int]:
@@ -405,6 +414,23 @@ class RaceChecker:
             for t in traces:
                 rd_trace_free(self.ctx, t)
             del bound, workspace
+
+    def kinds(self, trace, capacity=None):
+        """Unique race kinds of a checked trace: (status, (K, 3) uint32 array of (site_lo, site_hi,
+        count)), ascending; capacity None returns them all."""
+        if capacity is None:
+            # one call into a buffer of 4096 kinds; a second one only when they do not fit
+            out = np.zeros((4096, 3), dtype=np.uint32)
+            st, n = rd_race_kinds(self.ctx, trace, out.ctypes.data, len(out))
+            if st == RD_ETRUNC and n > len(out):
+                out = np.zeros((n, 3), dtype=np.uint32)
+                st, n = rd_race_kinds(self.ctx, trace, out.ctypes.data, len(out))
+            if st != RD_OK:
+                return st, np.zeros((0, 3), dtype=np.uint32)
+            return st, out[:n].copy()
+        out = np.zeros((max(capacity, 1), 3), dtype=np.uint32)
+        st, n = rd_race_kinds(self.ctx, trace, out.ctypes.data if capacity else None, capacity)
+        return st, out[: min(capacity, n)].copy()
 
     def report_many(self, traces):
         """Reports of several checked traces through rd_races_many (one transfer per batch); a member

@@ -11,7 +11,7 @@ CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "librd.so")
 SOURCES = ["rd_prep.hip", "rd_sort.hip", "rd_interp.hip", "rd_engine.hip", "rd_segcheck.hip", "rd_batch.hip", "rd_host.hip",
-           "rd_server.hip"]
+           "rd_server.hip", "rd_kinds.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [
     "--offload-arch=gfx950", "-O3", "-fPIC", "-std=c++17",

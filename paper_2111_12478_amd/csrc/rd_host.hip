@@ -409,10 +409,13 @@ struct rd_ctx_s {
     int device;
     u32 sort_variant = 0;  // location-sort variant (rd_set_tuning / rd_autotune)
     std::mutex mu;
+    std::mutex mu_kinds;  // one rd_race_kinds at a time per context (they share its scratch)
     uint64_t last_index;
     std::string last_msg;
     Profiler prof;
     hipStream_t cap_stream = nullptr;  // where checks are captured into graphs
+    void *kind_buf = nullptr;          // device scratch of rd_race_kinds (grown on demand)
+    u64 kind_bytes = 0;
 };
 
 // A batched check: the merged trace's workspace and the member table.  Shared by the member traces
@@ -549,6 +552,7 @@ rd_status rd_shutdown(rd_ctx ctx) {
     if (!ctx) return RD_EINVAL;
     for (hipEvent_t e : ctx->prof.pool) (void)hipEventDestroy(e);
     if (ctx->cap_stream) (void)hipStreamDestroy(ctx->cap_stream);
+    if (ctx->kind_buf) (void)hipFree(ctx->kind_buf);
     delete ctx;
     return RD_OK;
 }
@@ -886,6 +890,59 @@ rd_status rd_races(rd_ctx ctx, rd_trace trace, rd_pair *out, uint64_t capacity, 
         if (c != RD_OK) return c;
     }
     return plain_races(ctx, trace->bufs, trace->stream, out, capacity, n_races, &trace->last_pairs);
+}
+
+rd_status rd_race_kinds(rd_ctx ctx, rd_trace trace, rd_race_kind *out, uint64_t capacity, uint64_t *n_kinds) {
+    if (!ctx || !trace || !n_kinds || (capacity && !out)) return RD_EINVAL;
+    *n_kinds = 0;
+    if (!trace->checked) return set_err(ctx, RD_ESTATE, UINT64_MAX, "rd_race_kinds before rd_check");
+    if (hipSetDevice(ctx->device) != hipSuccess) return set_err(ctx, RD_EHIP, UINT64_MAX, "hipSetDevice failed");
+    if (trace->batch) {
+        // the kinds are built from the trace's own report
+        if (!trace->ws) return set_err(ctx, RD_ESTATE, UINT64_MAX, "race kinds of a batch member need its own workspace");
+        const rd_status c = rd_check(ctx, trace, trace->batch->stream);
+        if (c != RD_OK) return c;
+    }
+    uint64_t m = 0;
+    const rd_status st = plain_races(ctx, trace->bufs, trace->stream, nullptr, 0, &m, nullptr);
+    if (st != RD_OK && st != RD_ETRUNC) return st;
+    if (!m) return RD_OK;
+    std::lock_guard<std::mutex> g(ctx->mu_kinds);
+    // scratch: 5m + 1 words, scan partials, 3m record words, the count
+    const u64 parts = (m + 1 + 4095) / 4096 + 16;
+    const u64 words = 5 * m + 1 + parts + 3 * m + 1;
+    if (ctx->kind_bytes < 4 * words) {
+        if (ctx->kind_buf) (void)hipFree(ctx->kind_buf);
+        ctx->kind_buf = nullptr;
+        ctx->kind_bytes = 0;
+        if (hipMalloc(&ctx->kind_buf, 4 * words) != hipSuccess) {
+            (void)hipGetLastError();
+            return set_err(ctx, RD_ENOMEM, UINT64_MAX, "no device memory for the race-kind scratch");
+        }
+        ctx->kind_bytes = 4 * words;
+    }
+    u32 *scratch = (u32 *)ctx->kind_buf, *rec = scratch + 5 * m + 1 + parts, *n_out = rec + 3 * m;
+    Profiler *saved = g_prof;
+    g_prof = ctx->prof.filter.empty() ? nullptr : &ctx->prof;
+    race_kinds(trace->bufs, (u32)m, scratch, rec, n_out, trace->stream);
+    g_prof = saved;
+    u32 nk = 0;
+    if (hipGetLastError() != hipSuccess || hipMemcpyAsync(&nk, n_out, 4, hipMemcpyDeviceToHost, trace->stream) != hipSuccess ||
+        hipStreamSynchronize(trace->stream) != hipSuccess)
+        return set_err(ctx, RD_EHIP, UINT64_MAX, "building the race kinds failed");
+    {
+        DevParams prm;
+        if (hipMemcpy(&prm, trace->bufs.prm, sizeof(prm), hipMemcpyDeviceToHost) != hipSuccess)
+            return set_err(ctx, RD_EHIP, UINT64_MAX, "reading the check state failed");
+        if (prm.err & ERR_SORT) return set_err(ctx, RD_EHIP, UINT64_MAX, "race-kind sort look-back did not finish");
+    }
+    *n_kinds = nk;
+    const u64 k = capacity < nk ? capacity : nk;
+    if (k && (hipMemcpyAsync(out, rec, 12 * k, hipMemcpyDeviceToHost, trace->stream) != hipSuccess ||
+              hipStreamSynchronize(trace->stream) != hipSuccess))
+        return set_err(ctx, RD_EHIP, UINT64_MAX, "copying the race kinds failed");
+    if (capacity < nk) return set_err(ctx, RD_ETRUNC, UINT64_MAX, "more race kinds than capacity");
+    return RD_OK;
 }
 
 // The merged pass's buffers and member table (host side) for members that can share one pass.

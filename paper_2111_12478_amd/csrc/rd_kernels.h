@@ -41,6 +41,13 @@ void sort_elements(const Bufs &b, hipStream_t s);
 // radix sort of the kept race pairs by (first, second), result in buffer 0; the count is *m_dev
 // (launches sized for max_m) or m_host
 void sort_pairs(const Bufs &b, const u32 *m_dev, u32 m_host, u64 max_m, hipStream_t s);
+// The same sort over any two word arrays (ping-pong pairs f, s2), `half` 8-bit digits per word.
+void sort_pairs_in(const Bufs &b, u32 *const f[2], u32 *const s2[2], const u32 *m_dev, u32 m_host, u64 max_m,
+                   u32 half, const char *const names[3], hipStream_t s);
+// Race kinds of the packed report (b.preport, m pairs): sorted unique (site_lo, site_hi, count)
+// records in `rec` (3 words each) and their number in *n_out (device).  `scratch` holds
+// 5 * m + 1 words plus ceil((m + 1) / 4096) + 16 scan partials.
+void race_kinds(const Bufs &b, u32 m, u32 *scratch, u32 *rec, u32 *n_out, hipStream_t s);
 // The sorted pairs (buffer 0) as (first, second) records in b.preport, *n_pairs_kept of them.
 void pack_pairs(const Bufs &b, hipStream_t s);
 // stable sort of (key, value) pairs by key (see rd_sort.hip)

@@ -400,30 +400,40 @@ void sort_elements(const Bufs &b, hipStream_t s) {
 // their kernels loop over the tiles.
 constexpr u32 SMALL_SORT_GRID = 256;
 
-void sort_pairs(const Bufs &b, const u32 *m_dev, u32 m_host, u64 max_m, hipStream_t s) {
-    u32 bits = 0;
-    while (bits < 32 && ((u64)1 << bits) < (u64)b.N) bits++;
-    const u32 half = (bits + SORT_RB - 1) / SORT_RB;
+// Stable sort of (f[0][i], s2[0][i]) pairs by (first, second), `half` 8-bit digits per word (2 * half
+// passes: the result is back in buffer 0).  The count is *m_dev when set, else m_host; launches
+// are sized for max_m.  Uses the sort state of the workspace (sized for max_m <= max(elements,
+// max_pairs)).
+void sort_pairs_in(const Bufs &b, u32 *const f[2], u32 *const s2[2], const u32 *m_dev, u32 m_host, u64 max_m,
+                   u32 half, const char *const names[3], hipStream_t s) {
     const u32 passes = 2 * half;
     if (!max_m || !passes) return;
     const u32 n_tiles = (u32)((max_m + TILE - 1) / TILE), grid = n_tiles < SMALL_SORT_GRID ? n_tiles : SMALL_SORT_GRID;
-    RD_LAUNCH("k_pair_count", k_pair_count, dim3(grid), dim3(WG_THREADS), 0, s, b.pfirst[0], b.psecond[0], m_dev,
-              m_host, half, passes, b.sort_partial, b.sort_status, b.sort_tot);
-    RD_LAUNCH("k_pair_reduce", k_sort_reduce, dim3(passes, (n_tiles + 63) / 64), dim3(WG_THREADS), 0, s,
-              b.sort_partial, MAX_SORT_PASSES, n_tiles, m_dev, (const u32 *)nullptr, SORT_RB, b.sort_tot,
-              (u64 *)nullptr, (u64)0);
+    RD_LAUNCH(names[0], k_pair_count, dim3(grid), dim3(WG_THREADS), 0, s, f[0], s2[0], m_dev, m_host, half, passes,
+              b.sort_partial, b.sort_status, b.sort_tot);
+    RD_LAUNCH(names[1], k_sort_reduce, dim3(passes, (n_tiles + 63) / 64), dim3(WG_THREADS), 0, s, b.sort_partial,
+              MAX_SORT_PASSES, n_tiles, m_dev, (const u32 *)nullptr, SORT_RB, b.sort_tot, (u64 *)nullptr, (u64)0);
     u32 cur = 0;
     for (u32 pass = 0; pass < passes; pass++) {
         const u32 o = cur ^ 1;
         const bool lo = pass < half;
         SweepArgs a = sweep_args(b, pass, passes, (lo ? pass : pass - half) * SORT_RB, m_dev, m_host, nullptr);
-        a.kin = lo ? b.psecond[cur] : b.pfirst[cur];
-        a.pin[0] = lo ? b.pfirst[cur] : b.psecond[cur];
-        a.kout = lo ? b.psecond[o] : b.pfirst[o];
-        a.pout[0] = lo ? b.pfirst[o] : b.psecond[o];
-        RD_LAUNCH("k_pair_sweep", (k_sort_sweep<1, 8, 4, 16, true>), dim3(grid), dim3(WG_THREADS), 0, s, a);
+        a.kin = lo ? s2[cur] : f[cur];
+        a.pin[0] = lo ? f[cur] : s2[cur];
+        a.kout = lo ? s2[o] : f[o];
+        a.pout[0] = lo ? f[o] : s2[o];
+        RD_LAUNCH(names[2], (k_sort_sweep<1, 8, 4, 16, true>), dim3(grid), dim3(WG_THREADS), 0, s, a);
         cur = o;
     }
+}
+
+void sort_pairs(const Bufs &b, const u32 *m_dev, u32 m_host, u64 max_m, hipStream_t s) {
+    u32 bits = 0;
+    while (bits < 32 && ((u64)1 << bits) < (u64)b.N) bits++;
+    const u32 half = (bits + SORT_RB - 1) / SORT_RB;
+    u32 *const f[2] = {b.pfirst[0], b.pfirst[1]}, *const s2[2] = {b.psecond[0], b.psecond[1]};
+    static const char *const names[3] = {"k_pair_count", "k_pair_reduce", "k_pair_sweep"};
+    sort_pairs_in(b, f, s2, m_dev, m_host, max_m, half, names, s);
 }
 
 // Interleaves the sorted pairs into (first, second) records, the report's host layout.
