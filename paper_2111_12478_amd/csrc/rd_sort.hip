@@ -400,6 +400,12 @@ void sort_elements(const Bufs &b, hipStream_t s) {
 // their kernels loop over the tiles.
 constexpr u32 SMALL_SORT_GRID = 256;
 
+// Shape of the sweeps of the device-counted sorts (pairs, release/acquire entries): the tile is the
+// counting kernels' TILE, spread over 16 wavefronts of 4 items (a small sort's time is one tile's
+// latency, which more wavefronts per tile shorten).
+constexpr int SMALL_NW = 16, SMALL_NI = 4;
+static_assert(SMALL_NW * 64 * SMALL_NI == TILE, "the sweep's tiles are the counted tiles");
+
 // Stable sort of (f[0][i], s2[0][i]) pairs by (first, second), `half` 8-bit digits per word (2 * half
 // passes: the result is back in buffer 0).  The count is *m_dev when set, else m_host; launches
 // are sized for max_m.  Uses the sort state of the workspace (sized for max_m <= max(elements,
@@ -422,7 +428,7 @@ void sort_pairs_in(const Bufs &b, u32 *const f[2], u32 *const s2[2], const u32 *
         a.pin[0] = lo ? f[cur] : s2[cur];
         a.kout = lo ? s2[o] : f[o];
         a.pout[0] = lo ? f[o] : s2[o];
-        RD_LAUNCH(names[2], (k_sort_sweep<1, 8, 4, 16, true>), dim3(grid), dim3(WG_THREADS), 0, s, a);
+        RD_LAUNCH(names[2], (k_sort_sweep<1, 8, SMALL_NW, SMALL_NI, true>), dim3(grid), dim3(SMALL_NW * 64), 0, s, a);
         cur = o;
     }
 }
@@ -471,7 +477,7 @@ void sort_kv(const Bufs &b, u32 *const k[2], u32 *const v[2], const u32 *n_dev, 
         a.pin[0] = v[c];
         a.kout = k[o];
         a.pout[0] = v[o];
-        RD_LAUNCH(name, (k_sort_sweep<1, 8, 4, 16, true>), dim3(grid), dim3(WG_THREADS), 0, s, a);
+        RD_LAUNCH(name, (k_sort_sweep<1, 8, SMALL_NW, SMALL_NI, true>), dim3(grid), dim3(SMALL_NW * 64), 0, s, a);
     }
 }
 
