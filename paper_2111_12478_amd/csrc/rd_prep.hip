@@ -126,18 +126,29 @@ __global__ __launch_bounds__(1024) void k_scan_top(u32 *part, u32 np, const u32 
     u32 run = lds[threadIdx.x] - s;
     for (u32 i = lo; i < hi; i++) { u32 v = part[i]; part[i] = run; run += v; }
 }
-// in-place exclusive scan of each chunk plus its carry
+// in-place exclusive scan of each chunk plus its carry: part[blockIdx.x] after k_scan_top, or with
+// `direct` (at most SCAN_DIRECT chunks) the sum of the earlier chunks' totals, read by every
+// workgroup from L2 instead of a separate scan of the totals
+constexpr u32 SCAN_DIRECT = 8192;  // up to 33.5M words: at most 8192 totals summed per workgroup
 __global__ __launch_bounds__(256) void k_scan_apply(u32 *data, u64 n, const u32 *part, const u32 *gate,
-                                                     const u32 *n_dev) {
+                                                     const u32 *n_dev, bool direct) {
     __shared__ u32 lds[8];
     if (!eng_gate_open(gate)) return;
     n = scan_len(n, n_dev);
     if ((u64)blockIdx.x * SCAN_CHUNK >= n) return;
+    u32 carry;
+    if (direct) {
+        u32 c = 0;
+        for (u32 j = threadIdx.x; j < blockIdx.x; j += 256) c += part[j];
+        (void)block_exscan_256(c, &carry, lds);
+    } else {
+        carry = part[blockIdx.x];
+    }
     u64 base = (u64)blockIdx.x * SCAN_CHUNK + (u64)threadIdx.x * 16;
     u32 v[16], s = 0;
     for (u32 k = 0; k < 16; k++) { u64 i = base + k; v[k] = i < n ? data[i] : 0; s += v[k]; }
     u32 tot;
-    u32 run = block_exscan_256(s, &tot, lds) + part[blockIdx.x];
+    u32 run = block_exscan_256(s, &tot, lds) + carry;
     for (u32 k = 0; k < 16; k++) { u64 i = base + k; if (i < n) data[i] = run; run += v[k]; }
 }
 
@@ -195,9 +206,10 @@ void scan_exclusive(u32 *data, u64 n, u32 *part, hipStream_t s, const u32 *gate,
         return;
     }
     u32 np = (u32)((n + SCAN_CHUNK - 1) / SCAN_CHUNK);
+    const bool direct = np <= SCAN_DIRECT;
     RD_LAUNCH("k_scan_reduce", k_scan_reduce, dim3(np), dim3(256), 0, s, data, n, part, gate, n_dev);
-    RD_LAUNCH("k_scan_top", k_scan_top, dim3(1), dim3(1024), 0, s, part, np, gate, n, n_dev);
-    RD_LAUNCH("k_scan_apply", k_scan_apply, dim3(np), dim3(256), 0, s, data, n, part, gate, n_dev);
+    if (!direct) RD_LAUNCH("k_scan_top", k_scan_top, dim3(1), dim3(1024), 0, s, part, np, gate, n, n_dev);
+    RD_LAUNCH("k_scan_apply", k_scan_apply, dim3(np), dim3(256), 0, s, data, n, part, gate, n_dev, direct);
 }
 
 // ---------------------------------------------------------------- init
