@@ -438,6 +438,31 @@ struct Batch {
     bool read = false, failed = false;
 };
 
+// Page-locked host memory a report is copied into by DMA (no staging by the runtime), then to the
+// caller's buffer; grown on demand, released with its trace.
+struct HostStage {
+    char *p = nullptr;
+    u64 bytes = 0;
+    bool ensure(u64 n) {
+        if (n <= bytes) return true;
+        if (p) (void)hipHostFree(p);
+        p = nullptr;
+        bytes = 0;
+        if (hipHostMalloc((void **)&p, n, hipHostMallocDefault) != hipSuccess) {
+            (void)hipGetLastError();
+            p = nullptr;
+            return false;
+        }
+        bytes = n;
+        return true;
+    }
+    void release() {
+        if (p) (void)hipHostFree(p);
+        p = nullptr;
+        bytes = 0;
+    }
+};
+
 struct rd_trace_s {
     Plan plan;
     Bufs bufs;
@@ -465,6 +490,7 @@ struct rd_trace_s {
     bool graph_off = false;  // capture failed once: checks are enqueued kernel by kernel
     uint64_t n_checks = 0;
     u64 last_pairs = 0;  // the previous report's length: copied together with the check state
+    HostStage stage;     // where rd_races copies the state and the report to
 };
 
 // A captured batched pass: replayed by rd_graph_launch for the same members and workspace.
@@ -795,17 +821,24 @@ static bool batch_races(rd_ctx ctx, rd_trace trace, rd_pair *out, uint64_t capac
 
 // The report of a check enqueued on `s` over buffers `b` (waits for it).
 static rd_status plain_races(rd_ctx ctx, const Bufs &b, hipStream_t s, rd_pair *out, uint64_t capacity,
-                             uint64_t *n_races, u64 *hint) {
+                             uint64_t *n_races, u64 *hint, HostStage *stage = nullptr) {
     // the check left the sorted report as rd_pair records (pack_pairs); as many as the previous
     // report of these buffers held are copied together with the state, so a report no longer than
-    // the last one takes a single wait
+    // the last one takes a single wait.  With a stage, both go by DMA to page-locked memory and only
+    // the returned records are copied on to `out`.
+    constexpr u64 HDR = 256;
+    static_assert(sizeof(DevParams) <= HDR, "the state fits the stage's header");
     DevParams prm;
     const u64 lim = capacity < b.max_pairs ? capacity : b.max_pairs;
     const u64 early = out && hint ? (*hint < lim ? *hint : lim) : 0;
-    if (hipMemcpyAsync(&prm, b.prm, sizeof(prm), hipMemcpyDeviceToHost, s) != hipSuccess ||
-        (early && hipMemcpyAsync(out, b.preport, 8 * early, hipMemcpyDeviceToHost, s) != hipSuccess) ||
+    const bool staged = stage && stage->ensure(HDR + 8 * early);
+    rd_pair *early_dst = staged ? (rd_pair *)(stage->p + HDR) : out;
+    if (hipMemcpyAsync(staged ? (void *)stage->p : (void *)&prm, b.prm, sizeof(prm), hipMemcpyDeviceToHost, s) !=
+            hipSuccess ||
+        (early && hipMemcpyAsync(early_dst, b.preport, 8 * early, hipMemcpyDeviceToHost, s) != hipSuccess) ||
         hipStreamSynchronize(s) != hipSuccess)
         return set_err(ctx, RD_EHIP, UINT64_MAX, "reading the check state failed");
+    if (staged) memcpy(&prm, stage->p, sizeof(prm));
     if (prm.first_bad_record != NONE) return set_err(ctx, RD_ETRACE, prm.first_bad_record, "malformed record");
     if (prm.err & ERR_PHASE) return set_err(ctx, RD_EINVAL, UINT64_MAX, "a thread passed more than 2^30 barriers");
     if (prm.first_bad_sync != NONE)
@@ -825,6 +858,7 @@ static rd_status plain_races(rd_ctx ctx, const Bufs &b, hipStream_t s, rd_pair *
     if (hint) *hint = m;
     if (!out || !capacity || !m) return m > capacity ? set_err(ctx, RD_ETRUNC, UINT64_MAX, "capacity") : RD_OK;
     const u64 k = capacity < m ? capacity : m;
+    if (staged) memcpy(out, stage->p + HDR, 8 * (k < early ? k : early));
     if (k > early && (hipMemcpyAsync(out + early, b.preport + early, 8 * (k - early), hipMemcpyDeviceToHost, s) !=
                           hipSuccess ||
                       hipStreamSynchronize(s) != hipSuccess))
@@ -889,7 +923,7 @@ rd_status rd_races(rd_ctx ctx, rd_trace trace, rd_pair *out, uint64_t capacity, 
         const rd_status c = rd_check(ctx, trace, trace->batch->stream);  // on its own; drops the batch
         if (c != RD_OK) return c;
     }
-    return plain_races(ctx, trace->bufs, trace->stream, out, capacity, n_races, &trace->last_pairs);
+    return plain_races(ctx, trace->bufs, trace->stream, out, capacity, n_races, &trace->last_pairs, &trace->stage);
 }
 
 rd_status rd_race_kinds(rd_ctx ctx, rd_trace trace, rd_race_kind *out, uint64_t capacity, uint64_t *n_kinds) {
@@ -1264,6 +1298,7 @@ rd_status rd_autotune(rd_ctx ctx, const rd_trace *traces, uint32_t n, void *batc
 rd_status rd_trace_free(rd_ctx ctx, rd_trace trace) {
     if (!ctx || !trace) return RD_EINVAL;
     graph_drop(trace);
+    trace->stage.release();
     delete trace;
     return RD_OK;
 }
