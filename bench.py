@@ -84,13 +84,13 @@ def key_passes(ev: np.ndarray, n_blocks: int, tpb: int, radix_bits: int) -> int:
 
 
 def source_digest() -> str:
-    """Digest of the HIP sources: a stored traffic figure is used only for the kernels it measured."""
+    """Digest of the sources that define the location sort's sweep (its file and the headers it
+    includes): a stored traffic figure is used only for the kernel it measured."""
     import hashlib
     h = hashlib.sha256()
     csrc = os.path.join(ROOT, "paper_2111_12478_amd", "csrc")
-    for f in sorted(os.listdir(csrc)):
-        if f.endswith((".hip", ".h")):
-            h.update(open(os.path.join(csrc, f), "rb").read())
+    for f in ("rd_internal.h", "rd_kernels.h", "rd_sort.hip"):
+        h.update(open(os.path.join(csrc, f), "rb").read())
     return h.hexdigest()[:16]
 
 
