@@ -325,7 +325,7 @@ class RaceChecker:
         self.torch = torch
         self.device = device
         self.ctx = rd_init(device)
-        self._report_buf = np.zeros((1 << 16, 2), dtype=np.uint32)
+        self._report_len = {}  # trace handle -> length of its last report
 
     def close(self):
         if self.ctx:
@@ -374,16 +374,18 @@ class RaceChecker:
 
     def report(self, trace, capacity=None):
         if capacity is None:
-            # one call into a reusable buffer; a second one only when the pairs do not fit
-            buf = self._report_buf
+            # one call into a new array sized by the trace's previous report (the pairs are written
+            # straight into the array that is returned); a second one only when they do not fit
+            buf = np.empty((max(self._report_len.get(trace, 0), 1 << 12), 2), dtype=np.uint32)
             st, n = rd_races(self.ctx, trace, buf.ctypes.data, len(buf))
             if st == RD_ETRUNC and n > len(buf):
-                buf = self._report_buf = np.zeros((n, 2), dtype=np.uint32)
+                buf = np.empty((n, 2), dtype=np.uint32)
                 st, n = rd_races(self.ctx, trace, buf.ctypes.data, len(buf))
             if st != RD_OK:
                 idx, msg = rd_last_error(self.ctx)
                 return CheckResult(st, np.zeros((0, 2), np.uint32), idx, msg)
-            return CheckResult(st, buf[:n].copy())
+            self._report_len[trace] = n
+            return CheckResult(st, buf[:n])
         st, n = rd_races(self.ctx, trace, None, 0)
         if st not in (RD_OK, RD_ETRUNC):
             idx, msg = rd_last_error(self.ctx)
@@ -413,6 +415,7 @@ class RaceChecker:
         finally:
             for t in traces:
                 rd_trace_free(self.ctx, t)
+                self._report_len.pop(t, None)
             del bound, workspace
 
     def kinds(self, trace, capacity=None):
@@ -455,6 +458,7 @@ class RaceChecker:
             return self.run(tr, capacity)
         finally:
             rd_trace_free(self.ctx, tr)
+            self._report_len.pop(tr, None)
             del ws, keep
 
 
