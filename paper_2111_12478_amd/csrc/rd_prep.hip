@@ -317,25 +317,58 @@ __global__ __launch_bounds__(WG_THREADS) void k_ingest(Bufs b, u64 *sync_mask, u
 }
 
 // Reduces the per-tile ingest statistics, then plans the location key and the mode of the check.
-__global__ __launch_bounds__(256) void k_plan(Bufs b) {
-    __shared__ u32 red[256][TILE_STATS];
-    u32 acc[TILE_STATS];
+// fields 0..4 of a tile's statistics: min, min, max, min, max; 5..12: sums
+__device__ inline void plan_fold(u32 *acc, const u32 *v) {
+    acc[0] = min(acc[0], v[0]); acc[1] = min(acc[1], v[1]); acc[2] = max(acc[2], v[2]);
+    acc[3] = min(acc[3], v[3]); acc[4] = max(acc[4], v[4]);
+#pragma unroll
+    for (int q = 5; q < 13; q++) acc[q] += v[q];
+}
+
+constexpr u32 PLAN_THREADS = 1024;
+
+__global__ __launch_bounds__(PLAN_THREADS) void k_plan(Bufs b) {
+    constexpr int F = 13;  // the statistics of a row (rows are TILE_STATS words apart)
+    static_assert(TILE_STATS == 16, "rows of four 16-byte vectors");
+    __shared__ u32 red[PLAN_THREADS / 64][F];
+    const u32 lane = lane_id(), w = threadIdx.x >> 6;
+    u32 acc[F];
     acc[0] = NONE; acc[1] = NONE; acc[2] = 0; acc[3] = NONE; acc[4] = 0;
-    for (int q = 5; q < TILE_STATS; q++) acc[q] = 0;
-    for (u32 t = threadIdx.x; t < b.n_tiles; t += 256) {
-        const u32 *st = b.tile_stats + (u64)t * TILE_STATS;
-        acc[0] = min(acc[0], st[0]); acc[1] = min(acc[1], st[1]); acc[2] = max(acc[2], st[2]);
-        acc[3] = min(acc[3], st[3]); acc[4] = max(acc[4], st[4]);
-        for (int q = 5; q < 13; q++) acc[q] += st[q];
+    for (int q = 5; q < F; q++) acc[q] = 0;
+    // four tiles' rows in flight per thread
+    for (u32 t0 = threadIdx.x; t0 < b.n_tiles; t0 += 4 * PLAN_THREADS) {
+        u32 v[4][F];
+#pragma unroll
+        for (int j = 0; j < 4; j++) {
+            const u32 t = t0 + j * PLAN_THREADS;
+            if (t < b.n_tiles) {
+                // a row is 64 aligned bytes: four 16-byte loads
+                const uint4 *st = (const uint4 *)(b.tile_stats + (u64)t * TILE_STATS);
+                const uint4 r0 = st[0], r1 = st[1], r2 = st[2], r3 = st[3];
+                const u32 row[16] = {r0.x, r0.y, r0.z, r0.w, r1.x, r1.y, r1.z, r1.w,
+                                     r2.x, r2.y, r2.z, r2.w, r3.x, r3.y, r3.z, r3.w};
+#pragma unroll
+                for (int q = 0; q < F; q++) v[j][q] = row[q];
+            } else {
+#pragma unroll
+                for (int q = 0; q < F; q++) v[j][q] = q == 0 || q == 1 || q == 3 ? NONE : 0u;
+            }
+        }
+#pragma unroll
+        for (int j = 0; j < 4; j++) plan_fold(acc, v[j]);
     }
-    for (int q = 0; q < TILE_STATS; q++) red[threadIdx.x][q] = acc[q];
+#pragma unroll
+    for (int d = 32; d >= 1; d >>= 1) {
+        u32 o[F];
+#pragma unroll
+        for (int q = 0; q < F; q++) o[q] = (u32)__shfl_xor((int)acc[q], d, 64);
+        plan_fold(acc, o);
+    }
+    if (lane == 0)
+        for (int q = 0; q < F; q++) red[w][q] = acc[q];
     __syncthreads();
     if (threadIdx.x) return;
-    for (u32 x = 1; x < 256; x++) {
-        acc[0] = min(acc[0], red[x][0]); acc[1] = min(acc[1], red[x][1]); acc[2] = max(acc[2], red[x][2]);
-        acc[3] = min(acc[3], red[x][3]); acc[4] = max(acc[4], red[x][4]);
-        for (int q = 5; q < 13; q++) acc[q] += red[x][q];
-    }
+    for (u32 x = 1; x < PLAN_THREADS / 64; x++) plan_fold(acc, red[x]);
     DevParams *p = b.prm;
     p->first_bad_record = acc[0];
     p->gmin = acc[1]; p->gmax = acc[2]; p->smin = acc[3]; p->smax = acc[4];
@@ -791,7 +824,7 @@ void prep_init(const Bufs &b, u32 *rt_scan, hipStream_t s) {
 void prep_ingest(const Bufs &b, u64 *sync_mask, u64 *acc_mask, u64 *atom_mask, hipStream_t s) {
     if (b.N) RD_LAUNCH("k_ingest", k_ingest, dim3(b.n_tiles), dim3(WG_THREADS), 0, s, b, sync_mask, acc_mask, atom_mask);
     scan_exclusive_multi(b.tile_s, (u64)b.n_tiles + 1, 3, b.part, s);
-    RD_LAUNCH("k_plan", k_plan, dim3(1), dim3(256), 0, s, b);
+    RD_LAUNCH("k_plan", k_plan, dim3(1), dim3(PLAN_THREADS), 0, s, b);
 }
 
 // per-thread sync lists and block-barrier instances
