@@ -286,33 +286,79 @@ __global__ __launch_bounds__(WG_THREADS) void k_seg_reduce(Bufs b) {
 // range of tiles, read four at a time so that their loads overlap)
 constexpr u32 SCAN_THREADS = 1024;
 
+// Four consecutive summaries (a range starting at a multiple of four tiles) are 13 aligned 16-byte
+// vectors: loaded and stored as such.
+static_assert(sizeof(Agg) == 52, "four summaries are thirteen 16-byte vectors");
+__device__ inline void agg_load4(const Agg *src, Agg v[4]) {
+    u32 w[52];
+    const uint4 *p = (const uint4 *)src;
+#pragma unroll
+    for (int k = 0; k < 13; k++) {
+        const uint4 x = p[k];
+        w[4 * k] = x.x; w[4 * k + 1] = x.y; w[4 * k + 2] = x.z; w[4 * k + 3] = x.w;
+    }
+#pragma unroll
+    for (int j = 0; j < 4; j++) __builtin_memcpy(&v[j], &w[13 * j], sizeof(Agg));
+}
+__device__ inline void agg_store4(Agg *dst, const Agg v[4]) {
+    u32 w[52];
+#pragma unroll
+    for (int j = 0; j < 4; j++) __builtin_memcpy(&w[13 * j], &v[j], sizeof(Agg));
+    uint4 *p = (uint4 *)dst;
+#pragma unroll
+    for (int k = 0; k < 13; k++) p[k] = make_uint4(w[4 * k], w[4 * k + 1], w[4 * k + 2], w[4 * k + 3]);
+}
+
 __global__ __launch_bounds__(SCAN_THREADS) void k_seg_scan(Bufs b) {
     __shared__ Agg buf[SCAN_THREADS / 64];
     const SegCtx s = seg_ctx(b);
     Agg *tile_agg = (Agg *)b.tile_agg;
     const u32 nt = (u32)((s.n + TILE - 1) / TILE);
-    const u32 per = (nt + SCAN_THREADS - 1) / SCAN_THREADS;
-    const u32 lo = threadIdx.x * per, hi = min(lo + per, nt);
+    // each thread a range of a multiple of four tiles (16-byte aligned: the array is 256-aligned)
+    const u32 per = ((nt + SCAN_THREADS - 1) / SCAN_THREADS + 3) & ~3u;
+    const u32 lo = min(threadIdx.x * per, nt), hi = min(lo + per, nt);
     Agg acc;
     agg_empty(acc);
     for (u32 q = lo; q < hi; q += 4) {
         Agg v[4];
+        if (q + 4 <= hi) {
+            agg_load4(tile_agg + q, v);
+        } else {
 #pragma unroll
-        for (u32 j = 0; j < 4; j++)
-            if (q + j < hi) v[j] = tile_agg[q + j];
+            for (u32 j = 0; j < 4; j++)
+                if (q + j < hi) v[j] = tile_agg[q + j];
+        }
 #pragma unroll
         for (u32 j = 0; j < 4; j++)
             if (q + j < hi) { agg_combine(acc, v[j]); acc = v[j]; }
     }
     block_exscan_agg<SCAN_THREADS>(acc, buf, nullptr);
     for (u32 q = lo; q < hi; q += 4) {
-        Agg v[4];
+        Agg v[4];  // the totals in, the exclusive prefixes out
+        const bool whole = q + 4 <= hi;
+        if (whole) {
+            agg_load4(tile_agg + q, v);
+        } else {
 #pragma unroll
-        for (u32 j = 0; j < 4; j++)
-            if (q + j < hi) v[j] = tile_agg[q + j];
+            for (u32 j = 0; j < 4; j++)
+                if (q + j < hi) v[j] = tile_agg[q + j];
+        }
 #pragma unroll
-        for (u32 j = 0; j < 4; j++)
-            if (q + j < hi) { tile_agg[q + j] = acc; agg_combine(acc, v[j]); acc = v[j]; }
+        for (u32 j = 0; j < 4; j++) {
+            if (q + j < hi) {
+                Agg t = v[j];
+                v[j] = acc;
+                agg_combine(acc, t);
+                acc = t;
+            }
+        }
+        if (whole) {
+            agg_store4(tile_agg + q, v);
+        } else {
+#pragma unroll
+            for (u32 j = 0; j < 4; j++)
+                if (q + j < hi) tile_agg[q + j] = v[j];
+        }
     }
 }
 
