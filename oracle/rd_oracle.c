@@ -612,11 +612,13 @@ static inline uint32_t H_get(const clocks_t *C, uint32_t t, uint32_t u) {
     return C->vc[t] ? cvc_get(C->vc[t], u, C->tpb) : 0;
 }
 
-/* A sync-variable clock H_<l,s>.  It is kept per (location, releasing block, scope class) so
- * that each acquire can join exactly the releases whose scope reaches it; with the default reading
- * the device-scope clocks of all blocks together equal Algorithm 1's single H_<l,DEVICE>. */
+/* A sync-variable clock H_<l,s>: per location, one for its device/system-scoped releases
+ * (Algorithm 1's H_<l,DEVICE>) and one per block for block-scoped releases (H_<l,b>).  Under the
+ * inclusive reading the device-scoped ones are kept per releasing block as well, since there an
+ * acquire is reached only by releases whose scope covers its block. */
 typedef struct {
-    uint32_t blk;       /* block of the releasing threads */
+    uint32_t blk;       /* block of the releasing threads; UINT32_MAX: device-scoped releases of
+                         * every block (default reading) */
     uint32_t blk_scope; /* 1: block-scoped releases, 0: device/system-scoped releases */
     const cvc *v;       /* mode 0 */
     uint32_t *d;        /* mode 1 */
@@ -743,9 +745,13 @@ int orc_check(uint32_t n_blocks, uint32_t tpb, uint32_t warp_size, const orc_eve
             /* RELEASE(t, l, s): H_<l,s> := H_<l,s> join H_t; then increment t's own entry */
             uint32_t X = loc[i];
             uint32_t bs = p.rel_scope[i] == S_BLOCK ? 1u : 0u;
+            /* Algorithm 1 keeps one clock H_<l,DEVICE> that the device-scoped releases of every
+             * block join, and one H_<l,b> per block b for block-scoped releases; the inclusive
+             * reading also needs the releasing block of a device-scoped release */
+            uint32_t key_blk = (bs || g_inclusive) ? bt : UINT32_MAX;
             syncvar *s = NULL;
             for (uint32_t q = 0; q < loc_nsv[X]; q++)
-                if (loc_sv[X][q].blk == bt && loc_sv[X][q].blk_scope == bs) s = &loc_sv[X][q];
+                if (loc_sv[X][q].blk == key_blk && loc_sv[X][q].blk_scope == bs) s = &loc_sv[X][q];
             if (!s) {
                 if (loc_nsv[X] == loc_svcap[X]) {
                     uint32_t nc = loc_svcap[X] ? loc_svcap[X] * 2 : 4;
@@ -755,7 +761,7 @@ int orc_check(uint32_t n_blocks, uint32_t tpb, uint32_t warp_size, const orc_eve
                 }
                 s = &loc_sv[X][loc_nsv[X]++];
                 memset(s, 0, sizeof(*s));
-                s->blk = bt; s->blk_scope = bs;
+                s->blk = key_blk; s->blk_scope = bs;
                 if (dense) {
                     s->d = (uint32_t *)calloc(T, sizeof(uint32_t));
                     if (!s->d) { rc = ORC_ENOMEM; break; }
