@@ -12,12 +12,16 @@ GOLDEN_DIR = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
 
 
 class GoldenCase:
-    def __init__(self, name, grid, events, expected, header):
+    def __init__(self, name, grid, events, expected, header, by_reading=None):
         self.name = name
         self.grid = grid
         self.events = events
         self.expected = expected  # (M, 2) uint32, sorted
         self.header = header
+        # pairs expected under another reading of the paper ("inclusive": the other scope rule
+        # for atomics and release -> acquire edges; "gwcp": the predictive GWCP relation), when the
+        # file states them
+        self.by_reading = by_reading or {}
 
     def __repr__(self):
         return f"GoldenCase({self.name})"
@@ -30,6 +34,7 @@ def parse(path: str) -> GoldenCase:
     names = {}
     header = []
     none = False
+    other = {}  # reading -> list of pairs (an empty list: "none")
     for raw in open(path):
         line = raw.strip()
         if line.startswith("#"):
@@ -57,13 +62,20 @@ def parse(path: str) -> GoldenCase:
             expected.append((int(tok[1]), int(tok[2])))
         elif tok[0] == "expect-none":
             none = True
+        elif tok[0].startswith("expect-"):
+            reading = tok[0][len("expect-"):]
+            if reading.endswith("-none"):
+                other.setdefault(reading[:-len("-none")], [])
+            else:
+                other.setdefault(reading, []).append((int(tok[1]), int(tok[2])))
         else:
             raise ValueError(f"{path}: bad directive {tok[0]}")
     assert grid is not None, path
     assert none or expected, f"{path}: no expectation"
     exp = np.array(sorted(expected), dtype=np.uint32).reshape(-1, 2)
     ev = np.array(events, dtype=np.uint32).reshape(-1, 4)
-    return GoldenCase(os.path.basename(path)[:-4], grid, ev, exp, header)
+    by_reading = {r: np.array(sorted(v), dtype=np.uint32).reshape(-1, 2) for r, v in other.items()}
+    return GoldenCase(os.path.basename(path)[:-4], grid, ev, exp, header, by_reading)
 
 
 def all_cases():
