@@ -58,3 +58,27 @@ def test_validation(name, grid, events, status, bad):
 def test_bad_grid(grid):
     r = oracle.check(grid, ev((0, 0, make_meta(R), 0)))
     assert r.status == -1
+
+
+# ---------------------------------------------------------------- seeded malformed traces
+
+from tracegen import random_trace  # noqa: E402
+from tracegen.mutate import RECORD_KINDS, mutate  # noqa: E402
+
+
+@pytest.mark.parametrize("kind", RECORD_KINDS)
+@pytest.mark.parametrize("seed", range(40))
+def test_record_rule_mutations_first_index(kind, seed):
+    # a valid trace with one broken record: record rules are checked before barrier rules, so the
+    # first offending index is the changed record's, whatever the rest of the trace does
+    grid, ev0 = random_trace(seed)
+    assert oracle.validate(grid, ev0).status == 0
+    ev1, changed = mutate(grid, ev0, kind, seed + 1000)
+    r = oracle.validate(grid, ev1)
+    if not changed:
+        assert r.status == 0
+        return
+    assert r.status == -3 and r.bad_index == min(changed), (kind, seed, r, changed)
+    # the detector rejects it the same way
+    c = oracle.check(grid, ev1)
+    assert c.status == -3 and c.bad_index == min(changed)
