@@ -30,7 +30,7 @@ constexpr u32 ENG_SPIN = 1u << 19;  // ~1 s of polling: far above any legitimate
 
 __device__ inline bool eng_active(const DevParams *P) {
     return (P->mode & MODE_SYNC) && !(P->mode & MODE_WBAR) && P->first_bad_record == NONE &&
-           !(P->err & ERR_PHASE);
+           !(P->err & ERR_PHASE) && !check_abandoned(P);
 }
 __device__ inline bool eng_on(const DevParams *P) { return eng_active(P) && !(P->eng & ENG_FALLBACK); }
 
@@ -346,7 +346,7 @@ __global__ void k_eng_assign(Bufs b) {
 // operation that wrote it), inheriting through instances that add nothing.
 __global__ void k_eng_bk(Bufs b) {
     const DevParams *P = b.prm;
-    if (!eng_on(P) || P->n_ops > b.ecap) return;
+    if (!eng_on(P) || P->n_ops > b.ecap) return;  // also when the pool ran out: k_eng_assign numbered nothing
     for (u32 blk = blockIdx.x * blockDim.x + threadIdx.x; blk < b.B; blk += gridDim.x * blockDim.x) {
         u32 h = 0, o = NONE;
         for (u32 slot = b.inst_off[blk]; slot < b.inst_off[blk + 1]; slot++) {
@@ -373,7 +373,7 @@ __device__ inline u32 dmax(u32 a, u32 c) { return a == NONE ? c : (c == NONE ? a
 // The latest operation each operation reads from (NONE: none).
 __global__ void k_eng_deps(Bufs b) {
     const DevParams *P = b.prm;
-    if (!eng_on(P) || P->n_ops > b.ecap) return;
+    if (!eng_on(P) || P->n_ops > b.ecap) return;  // also when the pool ran out: k_eng_assign numbered nothing
     const u32 n_ops = P->n_ops;
     for (u32 o = blockIdx.x * blockDim.x + threadIdx.x; o < n_ops; o += gridDim.x * blockDim.x) {
         const u32 p = b.op_p[o], idx = b.s_pidx[p], blk = block_of(b, b.ev[idx].y);
@@ -408,7 +408,7 @@ __global__ void k_eng_deps(Bufs b) {
 // reads from the current group.  grp[0..n_groups] are the group starts and the end.
 __global__ __launch_bounds__(64) void k_eng_groups(Bufs b) {
     DevParams *P = b.prm;
-    if (!eng_on(P) || P->n_ops > b.ecap) return;
+    if (!eng_on(P) || P->n_ops > b.ecap) return;  // also when the pool ran out: k_eng_assign numbered nothing
     const u32 n = P->n_ops, lane = lane_id();
     u32 start = 0, ng = 0;
     if (lane == 0) b.grp[0] = 0;
@@ -788,7 +788,7 @@ __device__ inline void grid_barrier(DevParams *P, u32 round) {
 // the workgroups; a run of small groups is evaluated in windows of two phases (above).
 __global__ __launch_bounds__(ENG_THREADS) void k_eng_eval(Bufs b, const u32 *rt_scan) {
     DevParams *P = b.prm;
-    if (!eng_on(P) || P->n_ops > b.ecap || (P->err & ERR_POOL)) return;
+    if (!eng_on(P) || P->n_ops > b.ecap) return;
     __shared__ u32 lds_list[1024];
     __shared__ u32 lds_n;
     __shared__ u32 lds_jobs[CH_BLK * ENG_JOB_WORDS];

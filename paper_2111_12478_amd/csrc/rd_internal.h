@@ -124,6 +124,11 @@ struct DevParams {
     unsigned long long n_chunks;  // queued slow-path chunks of the segment check (8-byte aligned)
 };
 
+// Errors after which later stages must not read what the failed stage should have written (sorted
+// elements, operation tables, knowledge handles): the check's answer is the error, so they skip.
+constexpr u32 ERR_ABANDON = ERR_POOL | ERR_TABLE | ERR_SORT | ERR_ENGINE;
+__host__ __device__ inline bool check_abandoned(const DevParams *P) { return (P->err & ERR_ABANDON) != 0; }
+
 // The engine evaluates runs of small dependent groups in windows of ENG_WIN operations; each
 // operation of a window has ENG_JOB_WORDS words of job description.
 constexpr u32 ENG_WIN = 4096;

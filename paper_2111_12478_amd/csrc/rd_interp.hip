@@ -331,7 +331,7 @@ __global__ __launch_bounds__(IT) void k_interp(Bufs b, const u32 *rt_scan) {
 // One lane per program thread: knowledge after each of its sync entries.
 __global__ void k_know(Bufs b) {
     const DevParams *P = b.prm;
-    if (!(P->mode & MODE_SYNC)) return;
+    if (!(P->mode & MODE_SYNC) || check_abandoned(P)) return;
     for (u32 t = blockIdx.x * blockDim.x + threadIdx.x; t < b.T; t += gridDim.x * blockDim.x) {
         const u32 lo = b.s_cnt[t], hi = b.s_cnt[t + 1], blk = t / b.tpb;
         u32 cur = 0, first = NONE, acq = 0;

@@ -266,6 +266,7 @@ __device__ inline u32 items_in(const SegCtx &s, u64 base) {
 __global__ __launch_bounds__(WG_THREADS) void k_seg_reduce(Bufs b) {
     __shared__ Agg buf[WAVES];
     const SegCtx s = seg_ctx(b);
+    if (check_abandoned(b.prm)) return;  // the answer is that error: nothing here is read
     Agg *tile_agg = (Agg *)b.tile_agg;
     const u64 tile0 = (u64)blockIdx.x * TILE;
     if (tile0 >= s.n) return;
@@ -312,6 +313,7 @@ __device__ inline void agg_store4(Agg *dst, const Agg v[4]) {
 __global__ __launch_bounds__(SCAN_THREADS) void k_seg_scan(Bufs b) {
     __shared__ Agg buf[SCAN_THREADS / 64];
     const SegCtx s = seg_ctx(b);
+    if (check_abandoned(b.prm)) return;  // the answer is that error: nothing here is read
     Agg *tile_agg = (Agg *)b.tile_agg;
     const u32 nt = (u32)((s.n + TILE - 1) / TILE);
     // each thread a range of a multiple of four tiles (16-byte aligned: the array is 256-aligned)
@@ -674,6 +676,7 @@ __global__ __launch_bounds__(WG_THREADS) void k_seg_check(Bufs b, const u32 *rt_
     __shared__ u64 wsum[WAVES];
     __shared__ u64 qbase;
     const SegCtx s = seg_ctx(b);
+    if (check_abandoned(b.prm)) return;  // the answer is that error: nothing here is read
     const Agg *tile_agg = (const Agg *)b.tile_agg;
     const u64 tile0 = (u64)blockIdx.x * TILE;
     if (tile0 >= s.n) return;
@@ -787,6 +790,7 @@ __global__ __launch_bounds__(WG_THREADS) void k_seg_slow(Bufs b, const u32 *rt_s
     __shared__ u32 pf[PAIR_LDS], ps[PAIR_LDS];
     __shared__ u32 fill, gbase;
     const SegCtx s = seg_ctx(b);
+    if (check_abandoned(b.prm)) return;  // the answer is that error: nothing here is read
     const u32 n_chunks = (u32)min(b.prm->n_chunks, (unsigned long long)s.n);
     const u32 lane = lane_id(), w = threadIdx.x >> 6;
     if (threadIdx.x == 0) fill = 0;
