@@ -140,10 +140,12 @@ typedef struct {
 /* The unique race kinds of a checked trace, built on the device from its report: min(capacity,
  * total) kinds in ascending (site_lo, site_hi) order into `out` (may be NULL with capacity 0 to
  * query the count), *n_kinds = total.  Call after rd_check (rd_races need not come first); the
- * events and the workspace must still be valid.  Waits for the check.  Errors: those of rd_races
- * for the check itself, RD_ETRUNC when capacity < total, RD_ENOMEM when the context's device
- * scratch (about 32 bytes per race pair, kept until rd_shutdown) cannot be allocated, RD_ESTATE
- * for a batch member without a workspace of its own (a member with one is checked alone first). */
+ * events and the workspace must still be valid.  Waits for the check.  The scratch (32 bytes per
+ * race pair) is part of the trace's workspace, over memory the check no longer reads once it has
+ * ended, so the call allocates nothing; it runs on the trace's stream and must not overlap another
+ * call on the same trace.  Errors: those of rd_races for the check itself, RD_ETRUNC when
+ * capacity < total, RD_ESTATE for a batch member without a workspace of its own (a member with
+ * one is checked alone first). */
 rd_status rd_race_kinds(rd_ctx ctx, rd_trace trace, rd_race_kind *out, uint64_t capacity, uint64_t *n_kinds);
 
 /* Batched form (the same check, many traces per pass).  The members are independent traces, each

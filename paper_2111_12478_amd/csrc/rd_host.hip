@@ -22,6 +22,7 @@ static u32 next_pow2(u64 x) {
 struct Plan {
     Layout L;
     u64 off_masks, off_rt_scan, off_tile_stats, off_a_cnt;
+    u64 off_kinds;  // rd_race_kinds' scratch, over memory the check no longer needs when it ends
     u32 n_tiles, T, B, radix_bits, pair_tiles, part_words;
     u64 partial_words, status_words;
 };
@@ -136,6 +137,20 @@ static Plan make_plan(u64 n, u32 nb, u32 tpb, const rd_limits *lim, bool copy_ev
         L.off_eidx[c] = take(4 * NE);
         L.off_etid[c] = take(4 * NE);
         L.off_einfo[c] = take(4 * NE);
+    }
+    // rd_race_kinds (after a check) needs 8 words per race pair plus scan partials: the knowledge
+    // pool when it is large enough, else the element buffers, extended when they are too small
+    // (neither is read once the check has ended)
+    {
+        const u64 kparts = (max_pairs + 1 + 4095) / 4096 + 16;
+        const u64 kbytes = 4 * (8 * max_pairs + kparts + 2);
+        if (pool_bytes >= kbytes) {
+            P.off_kinds = L.off_pool;
+        } else {
+            P.off_kinds = L.off_ekey[0];
+            const u64 have = o - L.off_ekey[0];
+            if (kbytes > have) take(kbytes - have);
+        }
     }
     L.off_sort_status = take(2 * 8ull * P.status_words);
     L.off_sort_partial = take(4ull * P.partial_words);
@@ -409,13 +424,10 @@ struct rd_ctx_s {
     int device;
     u32 sort_variant = 0;  // location-sort variant (rd_set_tuning / rd_autotune)
     std::mutex mu;
-    std::mutex mu_kinds;  // one rd_race_kinds at a time per context (they share its scratch)
     uint64_t last_index;
     std::string last_msg;
     Profiler prof;
     hipStream_t cap_stream = nullptr;  // where checks are captured into graphs
-    void *kind_buf = nullptr;          // device scratch of rd_race_kinds (grown on demand)
-    u64 kind_bytes = 0;
 };
 
 // A batched check: the merged trace's workspace and the member table.  Shared by the member traces
@@ -578,7 +590,6 @@ rd_status rd_shutdown(rd_ctx ctx) {
     if (!ctx) return RD_EINVAL;
     for (hipEvent_t e : ctx->prof.pool) (void)hipEventDestroy(e);
     if (ctx->cap_stream) (void)hipStreamDestroy(ctx->cap_stream);
-    if (ctx->kind_buf) (void)hipFree(ctx->kind_buf);
     delete ctx;
     return RD_OK;
 }
@@ -941,35 +952,21 @@ rd_status rd_race_kinds(rd_ctx ctx, rd_trace trace, rd_race_kind *out, uint64_t 
     const rd_status st = plain_races(ctx, trace->bufs, trace->stream, nullptr, 0, &m, nullptr);
     if (st != RD_OK && st != RD_ETRUNC) return st;
     if (!m) return RD_OK;
-    std::lock_guard<std::mutex> g(ctx->mu_kinds);
-    // scratch: 5m + 1 words, scan partials, 3m record words, the count
+    // scratch in the trace's workspace (sized for max_pairs): 5m + 1 words, scan partials, 3m
+    // record words, the count
     const u64 parts = (m + 1 + 4095) / 4096 + 16;
-    const u64 words = 5 * m + 1 + parts + 3 * m + 1;
-    if (ctx->kind_bytes < 4 * words) {
-        if (ctx->kind_buf) (void)hipFree(ctx->kind_buf);
-        ctx->kind_buf = nullptr;
-        ctx->kind_bytes = 0;
-        if (hipMalloc(&ctx->kind_buf, 4 * words) != hipSuccess) {
-            (void)hipGetLastError();
-            return set_err(ctx, RD_ENOMEM, UINT64_MAX, "no device memory for the race-kind scratch");
-        }
-        ctx->kind_bytes = 4 * words;
-    }
-    u32 *scratch = (u32 *)ctx->kind_buf, *rec = scratch + 5 * m + 1 + parts, *n_out = rec + 3 * m;
+    u32 *scratch = (u32 *)(trace->ws + trace->plan.off_kinds), *rec = scratch + 5 * m + 1 + parts, *n_out = rec + 3 * m;
     Profiler *saved = g_prof;
     g_prof = ctx->prof.filter.empty() ? nullptr : &ctx->prof;
     race_kinds(trace->bufs, (u32)m, scratch, rec, n_out, trace->stream);
     g_prof = saved;
     u32 nk = 0;
+    DevParams prm;
     if (hipGetLastError() != hipSuccess || hipMemcpyAsync(&nk, n_out, 4, hipMemcpyDeviceToHost, trace->stream) != hipSuccess ||
+        hipMemcpyAsync(&prm, trace->bufs.prm, sizeof(prm), hipMemcpyDeviceToHost, trace->stream) != hipSuccess ||
         hipStreamSynchronize(trace->stream) != hipSuccess)
         return set_err(ctx, RD_EHIP, UINT64_MAX, "building the race kinds failed");
-    {
-        DevParams prm;
-        if (hipMemcpy(&prm, trace->bufs.prm, sizeof(prm), hipMemcpyDeviceToHost) != hipSuccess)
-            return set_err(ctx, RD_EHIP, UINT64_MAX, "reading the check state failed");
-        if (prm.err & ERR_SORT) return set_err(ctx, RD_EHIP, UINT64_MAX, "race-kind sort look-back did not finish");
-    }
+    if (prm.err & ERR_SORT) return set_err(ctx, RD_EHIP, UINT64_MAX, "race-kind sort look-back did not finish");
     *n_kinds = nk;
     const u64 k = capacity < nk ? capacity : nk;
     if (k && (hipMemcpyAsync(out, rec, 12 * k, hipMemcpyDeviceToHost, trace->stream) != hipSuccess ||
