@@ -8,8 +8,11 @@ if the library is not built, or there is no GPU, the calls raise.
 """
 from __future__ import annotations
 
+import atexit
 import ctypes
 import os
+import sys
+import weakref
 
 import numpy as np
 
@@ -57,6 +60,21 @@ class RdError(RuntimeError):
 
 
 _lib = None
+
+# Contexts and servers still open when the interpreter exits are closed by an exit handler, while
+# the HIP runtime (and any profiler attached to it) is still alive; a finaliser that runs during
+# interpreter shutdown makes no HIP call.
+_open = weakref.WeakSet()
+
+
+@atexit.register
+def _close_all():
+    # servers first: each holds its checker's context
+    for obj in sorted(list(_open), key=lambda o: 0 if isinstance(o, Server) else 1):
+        try:
+            obj.close()
+        except Exception:
+            pass
 
 
 def load_library():
@@ -326,6 +344,7 @@ class RaceChecker:
         self.device = device
         self.ctx = rd_init(device)
         self._report_len = {}  # trace handle -> length of its last report
+        _open.add(self)
 
     def close(self):
         if self.ctx:
@@ -333,6 +352,8 @@ class RaceChecker:
             self.ctx = None
 
     def __del__(self):
+        if sys.is_finalizing():
+            return
         try:
             self.close()
         except Exception:
@@ -473,6 +494,7 @@ class Server:
         self.arena = torch.empty(budget_bytes, dtype=torch.uint8, device=f"cuda:{checker.device}")
         self.srv = rd_server_open(checker.ctx, self.arena.data_ptr(), budget_bytes, max_batch, max_inflight)
         self._keep = {}
+        _open.add(self)
 
     def submit(self, grid, events) -> int:
         ev = np.ascontiguousarray(events, dtype=np.uint32)
