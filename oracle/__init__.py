@@ -14,6 +14,10 @@ computations of the race report:
 * :func:`check` -- the paper's per-event vector-clock detector (Algorithm 1 clock updates, epoch
   check against the per-location history of Section 4.1), with either dense vector clocks or
   block-floor + exception clocks with the forced barrier compression of Section 5.2.
+* :func:`gwcp` -- the predictive relation GWCP of Section 4 tracked by Algorithms 1 and 2 (P, N, C
+  and H clocks, Acq/Rel queues, locksets and lock-location clocks), dense clocks.
+* :func:`gwcp_bruteforce` -- GWCP's definition (rules (i)-(iv)) as a fixpoint over event pairs;
+  tiny traces only.
 
 Traces are ``(N, 4)`` uint32 arrays of records ``(addr, tid, meta, aux)``; pairs come back as an
 ``(M, 2)`` uint32 array of trace indices ``(first, second)``, first < second, sorted.
@@ -61,6 +65,10 @@ def _load():
         lib.orc_check.restype = i32
         lib.orc_bruteforce.argtypes = [u32, u32, u32, vp, u64, i32, ctypes.POINTER(u64), ctypes.POINTER(OraclePairs)]
         lib.orc_bruteforce.restype = i32
+        lib.orc_gwcp.argtypes = [u32, u32, u32, vp, u64, ctypes.POINTER(u64), ctypes.POINTER(OraclePairs)]
+        lib.orc_gwcp.restype = i32
+        lib.orc_gwcp_bruteforce.argtypes = [u32, u32, u32, vp, u64, ctypes.POINTER(u64), ctypes.POINTER(OraclePairs)]
+        lib.orc_gwcp_bruteforce.restype = i32
         lib.orc_validate.argtypes = [u32, u32, u32, vp, u64, ctypes.POINTER(u64)]
         lib.orc_validate.restype = i32
         lib.orc_pairs_free.argtypes = [ctypes.POINTER(OraclePairs)]
@@ -124,6 +132,28 @@ def bruteforce(grid, events, inclusive: bool = False) -> OracleResult:
     out = OraclePairs()
     rc = lib.orc_bruteforce(nb, tpb, ws, ev.ctypes.data, ev.shape[0], int(inclusive),
                             ctypes.byref(bad), ctypes.byref(out))
+    return OracleResult(rc, _bad(bad.value), _take_pairs(lib, out))
+
+
+def gwcp(grid, events) -> OracleResult:
+    """GWCP-predictable races by Algorithms 1 and 2 of Section 4.1 (<= 8192 threads)."""
+    lib = _load()
+    ev = _events(events)
+    nb, tpb, ws = (list(grid) + [32])[:3]
+    bad = ctypes.c_uint64(0)
+    out = OraclePairs()
+    rc = lib.orc_gwcp(nb, tpb, ws, ev.ctypes.data, ev.shape[0], ctypes.byref(bad), ctypes.byref(out))
+    return OracleResult(rc, _bad(bad.value), _take_pairs(lib, out))
+
+
+def gwcp_bruteforce(grid, events) -> OracleResult:
+    """GWCP-unordered conflicting pairs from the definition, rules (i)-(iv) (<= 4096 events)."""
+    lib = _load()
+    ev = _events(events)
+    nb, tpb, ws = (list(grid) + [32])[:3]
+    bad = ctypes.c_uint64(0)
+    out = OraclePairs()
+    rc = lib.orc_gwcp_bruteforce(nb, tpb, ws, ev.ctypes.data, ev.shape[0], ctypes.byref(bad), ctypes.byref(out))
     return OracleResult(rc, _bad(bad.value), _take_pairs(lib, out))
 
 

@@ -5,7 +5,8 @@
  * benchmark may load this library.  The product path (the HIP checker) never calls it, and the two
  * share no code: this file has its own record decoder, its own validation and its own analysis.
  *
- * It computes the same report two independent ways:
+ * It computes the scoped happens-before report two independent ways, and the GWCP report of
+ * Section 4 two ways (at the end of this file):
  *
  *   orc_bruteforce  The declarative definition.  It builds the happens-before graph of the trace
  *                   (program order; block and warp barriers; release -> acquire on one sync
@@ -178,8 +179,27 @@ static inline uint64_t mix64(uint64_t x) {
     x ^= x >> 33; x *= 0xff51afd7ed558ccdULL; x ^= x >> 33; x *= 0xc4ceb9fe1a85ec53ULL; x ^= x >> 33;
     return x;
 }
+/* Doubles the table when it is half full (keys keep their values). */
+static void hmap_grow(hmap *h) {
+    if (2 * (h->n + 1) + 16 <= h->cap) return;
+    uint64_t nc = h->cap * 2;
+    uint64_t *nk = (uint64_t *)malloc(nc * sizeof(uint64_t));
+    uint32_t *nv = (uint32_t *)calloc(nc, sizeof(uint32_t));
+    if (!nk || !nv) { free(nk); free(nv); return; } /* stays full: callers size generously */
+    for (uint64_t j = 0; j < h->cap; j++) {
+        if (!h->vals[j]) continue;
+        uint64_t q = mix64(h->keys[j]) & (nc - 1);
+        while (nv[q]) q = (q + 1) & (nc - 1);
+        nk[q] = h->keys[j];
+        nv[q] = h->vals[j];
+    }
+    free(h->keys); free(h->vals);
+    h->keys = nk; h->vals = nv; h->cap = nc;
+}
+
 /* Returns the index for key, inserting next_index if absent (and setting *inserted). */
 static uint32_t hmap_get(hmap *h, uint64_t key, uint32_t next_index, int *inserted) {
+    hmap_grow(h);
     uint64_t m = h->cap - 1, s = mix64(key) & m;
     for (;;) {
         if (h->vals[s] == 0) {
@@ -191,6 +211,35 @@ static uint32_t hmap_get(hmap *h, uint64_t key, uint32_t next_index, int *insert
         }
         if (h->keys[s] == key) { *inserted = 0; return h->vals[s] - 1; }
         s = (s + 1) & m;
+    }
+}
+
+/* Whether key is in the map. */
+static int hmap_has(const hmap *h, uint64_t key) {
+    uint64_t m = h->cap - 1, s = mix64(key) & m;
+    while (h->vals[s]) {
+        if (h->keys[s] == key) return 1;
+        s = (s + 1) & m;
+    }
+    return 0;
+}
+/* Removes key (linear probing: the rest of its cluster is inserted again). */
+static void hmap_unget(hmap *h, uint64_t key) {
+    uint64_t m = h->cap - 1, s = mix64(key) & m;
+    while (h->vals[s] && h->keys[s] != key) s = (s + 1) & m;
+    if (!h->vals[s]) return;
+    h->vals[s] = 0;
+    h->n--;
+    for (uint64_t j = (s + 1) & m; h->vals[j]; j = (j + 1) & m) {
+        uint64_t k = h->keys[j];
+        uint32_t v = h->vals[j];
+        h->vals[j] = 0;
+        h->n--;
+        uint64_t q = mix64(k) & m;
+        while (h->vals[q]) q = (q + 1) & m;
+        h->keys[q] = k;
+        h->vals[q] = v;
+        h->n++;
     }
 }
 
@@ -413,20 +462,18 @@ static inline int conflict(const prep_t *p, uint32_t i, uint32_t j) {
 
 /* ================================================================ brute-force closure */
 
-int orc_bruteforce(uint32_t n_blocks, uint32_t tpb, uint32_t warp_size, const orc_event *ev,
-                   uint64_t n, int inclusive, uint64_t *bad, orc_pairs *out) {
-    memset(out, 0, sizeof(*out));
-    *bad = UINT64_MAX;
-    if (!grid_ok(n_blocks, tpb, &warp_size, n)) return ORC_EINVAL;
-    if (n > 16384) return ORC_EINVAL; /* quadratic memory: tiny traces only */
-    g_inclusive = inclusive;
-    prep_t p;
-    int rc = prepare(&p, n_blocks, tpb, warp_size, ev, n, bad);
-    if (rc != ORC_OK) { prep_free(&p); return rc; }
-
-    uint64_t W = (n + 63) / 64;
+/* The scoped happens-before graph of a prepared trace closed transitively, as bitsets:
+ * reach[j * W + ...] holds every event i with a path i ->+ j (W = ceil(n / 64) words per row).
+ * Edges: program order (rule (i)); every participant's barrier arrival to each participant's next
+ * event (rule (iii)); a release to the event after an acquire of the same variable that its scope
+ * reaches (rule (iv)).  Trace order is a topological order, so one pass suffices. */
+static uint64_t *hb_reach(const prep_t *p0) {
+    uint64_t n = p0->n, W = (n + 63) / 64;
+    const orc_event *ev = p0->ev;
+    const prep_t p = *p0;
+    uint32_t tpb = p.tpb;
     uint64_t *reach = (uint64_t *)calloc(n * W + 1, sizeof(uint64_t)); /* reach[j]: events i ->* j */
-    if (!reach) { prep_free(&p); return ORC_ENOMEM; }
+    if (!reach) return NULL;
 
 #define SETBIT(row, i) (reach[(uint64_t)(row) * W + ((i) >> 6)] |= (uint64_t)1 << ((i) & 63))
 #define OR_ROW(dst, src)                                                                         \
@@ -467,6 +514,25 @@ int orc_bruteforce(uint32_t n_blocks, uint32_t tpb, uint32_t warp_size, const or
         }
     }
 #undef OR_ROW
+#undef SETBIT
+    return reach;
+}
+
+
+int orc_bruteforce(uint32_t n_blocks, uint32_t tpb, uint32_t warp_size, const orc_event *ev,
+                   uint64_t n, int inclusive, uint64_t *bad, orc_pairs *out) {
+    memset(out, 0, sizeof(*out));
+    *bad = UINT64_MAX;
+    if (!grid_ok(n_blocks, tpb, &warp_size, n)) return ORC_EINVAL;
+    if (n > 16384) return ORC_EINVAL; /* quadratic memory: tiny traces only */
+    g_inclusive = inclusive;
+    prep_t p;
+    int rc = prepare(&p, n_blocks, tpb, warp_size, ev, n, bad);
+    if (rc != ORC_OK) { prep_free(&p); return rc; }
+
+    uint64_t W = (n + 63) / 64;
+    uint64_t *reach = hb_reach(&p);
+    if (!reach) { prep_free(&p); return ORC_ENOMEM; }
     for (uint64_t jj = 0; jj < n; jj++) {
         uint32_t j = (uint32_t)jj;
         if (!is_access(kind_of(&ev[j]))) continue;
@@ -476,7 +542,6 @@ int orc_bruteforce(uint32_t n_blocks, uint32_t tpb, uint32_t warp_size, const or
             if (pairs_push(out, i, j) != ORC_OK) { free(reach); prep_free(&p); return ORC_ENOMEM; }
         }
     }
-#undef SETBIT
     free(reach);
     prep_free(&p);
     /* pairs were produced in (second, first) order; put them in canonical (first, second) order */
@@ -901,4 +966,658 @@ int orc_validate(uint32_t n_blocks, uint32_t tpb, uint32_t warp_size, const orc_
     int rc = prepare(&p, n_blocks, tpb, warp_size, ev, n, bad);
     prep_free(&p);
     return rc;
+}
+
+/* ================================================================ GWCP (Section 4)
+ *
+ * The predictive relation of Section 4: weak causal precedence for GPUs.  Two computations:
+ *
+ *   orc_gwcp             Algorithms 1 and 2 (Section 4.1) step by step, with dense vector clocks:
+ *                        per-thread local time N_t and clocks P_t (GWCP) and H_t (scoped HB), the
+ *                        logical time C_t = P_t{t := N_t}; per-lock clocks P_<l,s>, H_<l,s>;
+ *                        per-(lock, location) clocks L^r and L^w; per-thread locksets with the read
+ *                        and write sets of each held critical section; Acq_l / Rel_l queues.  An
+ *                        access by t of an earlier access a of thread u != t races when they
+ *                        conflict and a's local time is above C_t[u] (= P_t[u]).
+ *
+ *   orc_gwcp_bruteforce  The definition: rules (i)-(iv) as a least fixpoint over event pairs with
+ *                        bitsets (tiny traces only), every conflicting pair it leaves unordered.
+ *
+ * Readings (each also listed in the design notes):
+ *   G1 critical sections: a thread's acquire of a lock word it does not hold opens one (held with
+ *      the acquire's scope); the thread's next release of that word closes it.  An acquire of a
+ *      word already held opens nothing; a release of a word not held (a flag publication) closes
+ *      nothing; both keep their happens-before role (rule (iv)), and the P clock flows along every
+ *      release -> acquire edge as Algorithm 1 publishes and joins P_<l,s> for every release and
+ *      acquire.
+ *   G2 acquires and releases are lock operations, not reads or writes of critical sections
+ *      (Algorithm 2 runs for reads and writes); the race report still checks them as atomic
+ *      accesses of their word.  Atomics that are not lock operations are writes.
+ *   G3 rule (i)'s "conflicting" is the memory conflict of two accesses (same location, at least one
+ *      write), whatever their threads, as Algorithm 2 joins every earlier critical section's
+ *      L^r / L^w; the race report is over pairs of different threads.
+ *   G4 scopes: a lock held or released with device/system scope has key DEVICE, with block scope
+ *      the key of the thread's block; two keys overlap when either is DEVICE or they are equal
+ *      (Section 4, "scoped locks").  The queue join of Algorithm 1's RELEASE uses that overlap
+ *      between the dequeued release and the current one; Algorithm 2's joins and ACQUIRE's joins
+ *      are those printed (which are the same overlap).
+ *   G5 queues hold other threads' critical sections (Algorithm 1 enqueues for t' != t), paired
+ *      acquire with release of the same critical section; one whose release has not happened yet
+ *      stays at the front.  Rule (ii) is read for critical sections of different threads.
+ *   G6 lock clocks are joined, not overwritten, on release (as H_<l,s> in the detector above).
+ * The definition and the algorithm agree on traces whose synchronisation is locks (the WCP
+ * setting); with barriers the algorithm's SYNC joins only C_t, so it orders less than rule (iii)
+ * composed with happens-before (rule (iv)) on the left: its report contains the definition's.
+ */
+
+#define KEY_DEV UINT32_MAX
+static inline uint32_t scope_key(unsigned scope, uint32_t blk) { return scope == S_BLOCK ? blk : KEY_DEV; }
+static inline int keys_overlap(uint32_t a, uint32_t b) { return a == KEY_DEV || b == KEY_DEV || a == b; }
+static inline int is_lockop(const prep_t *p, uint32_t i) { return p->rel_scope[i] != 0xff || p->acq_scope[i] != 0xff; }
+
+typedef struct {
+    uint32_t tid, acq, rel;    /* events; rel = UINT32_MAX while open */
+    uint64_t word;             /* the lock word */
+    uint32_t acq_key, rel_key; /* scope keys */
+} orc_cs;
+
+typedef struct {
+    uint32_t n_cs;
+    orc_cs *cs;                /* in order of their acquires (trace order) */
+    uint32_t *open_cs;         /* per event: the critical section an acquire opens, or UINT32_MAX */
+    uint32_t *close_cs;        /* per event: the critical section a release closes, or UINT32_MAX */
+} cs_info;
+
+static void cs_free(cs_info *c) { free(c->cs); free(c->open_cs); free(c->close_cs); memset(c, 0, sizeof(*c)); }
+
+/* Critical sections (reading G1), numbered in trace order of their acquires. */
+static int cs_build(const prep_t *p, cs_info *c) {
+    memset(c, 0, sizeof(*c));
+    uint64_t n = p->n;
+    c->open_cs = (uint32_t *)malloc((n ? n : 1) * sizeof(uint32_t));
+    c->close_cs = (uint32_t *)malloc((n ? n : 1) * sizeof(uint32_t));
+    uint32_t n_acq = 0;
+    for (uint64_t i = 0; i < n; i++) n_acq += p->acq_scope[i] != 0xff;
+    c->cs = (orc_cs *)malloc((n_acq ? n_acq : 1) * sizeof(orc_cs));
+    uint32_t *held = (uint32_t *)malloc((n_acq ? n_acq : 1) * sizeof(uint32_t)); /* open ones, per thread */
+    uint32_t *held_n = (uint32_t *)calloc(p->n_threads ? p->n_threads : 1, sizeof(uint32_t));
+    uint32_t *held_off = (uint32_t *)malloc(((size_t)p->n_threads + 1) * sizeof(uint32_t));
+    if (!c->open_cs || !c->close_cs || !c->cs || !held || !held_n || !held_off) {
+        free(held); free(held_n); free(held_off); cs_free(c);
+        return ORC_ENOMEM;
+    }
+    /* room for each thread's open sections: at most its acquires */
+    held_off[0] = 0;
+    for (uint32_t t = 0; t < p->n_threads; t++) {
+        uint32_t a = 0;
+        for (uint32_t q = p->po_start[t]; q < p->po_start[t + 1]; q++) a += p->acq_scope[p->po_idx[q]] != 0xff;
+        held_off[t + 1] = held_off[t] + a;
+    }
+    for (uint64_t ii = 0; ii < n; ii++) {
+        uint32_t i = (uint32_t)ii, t = p->ev[i].tid, b = block_of(p, t);
+        c->open_cs[i] = c->close_cs[i] = UINT32_MAX;
+        uint64_t w = loc_key(p, &p->ev[i]);
+        uint32_t *h = &held[held_off[t]];
+        if (p->rel_scope[i] != 0xff) {
+            for (uint32_t q = held_n[t]; q-- > 0;) {
+                orc_cs *x = &c->cs[h[q]];
+                if (x->word != w) continue;
+                x->rel = i;
+                x->rel_key = scope_key(p->rel_scope[i], b);
+                c->close_cs[i] = h[q];
+                memmove(&h[q], &h[q + 1], (held_n[t] - q - 1) * sizeof(uint32_t));
+                held_n[t]--;
+                break;
+            }
+        }
+        if (p->acq_scope[i] != 0xff) {
+            int holding = 0;
+            for (uint32_t q = 0; q < held_n[t]; q++) holding |= c->cs[h[q]].word == w;
+            if (!holding) {
+                orc_cs *x = &c->cs[c->n_cs];
+                x->tid = t; x->acq = i; x->rel = UINT32_MAX; x->word = w;
+                x->acq_key = scope_key(p->acq_scope[i], b); x->rel_key = x->acq_key;
+                c->open_cs[i] = c->n_cs;
+                h[held_n[t]++] = c->n_cs++;
+            }
+        }
+    }
+    free(held); free(held_n); free(held_off);
+    return ORC_OK;
+}
+
+/* ---- growable arrays of dense clocks ---- */
+typedef struct { uint32_t **v; uint64_t n, cap; uint32_t T; } vecs;
+static uint32_t vecs_new(vecs *a) {
+    if (a->n == a->cap) {
+        uint64_t nc = a->cap ? 2 * a->cap : 64;
+        uint32_t **nv = (uint32_t **)realloc(a->v, nc * sizeof(uint32_t *));
+        if (!nv) return UINT32_MAX;
+        a->v = nv; a->cap = nc;
+    }
+    a->v[a->n] = (uint32_t *)calloc(a->T ? a->T : 1, sizeof(uint32_t));
+    if (!a->v[a->n]) return UINT32_MAX;
+    return (uint32_t)a->n++;
+}
+static void vecs_free(vecs *a) { for (uint64_t i = 0; i < a->n; i++) free(a->v[i]); free(a->v); memset(a, 0, sizeof(*a)); }
+static inline void vjoin(uint32_t *d, const uint32_t *s, uint32_t T) { for (uint32_t u = 0; u < T; u++) if (s[u] > d[u]) d[u] = s[u]; }
+
+/* growable u32 list */
+typedef struct { uint32_t *v; uint32_t n, cap; } ulist;
+static int ulist_push(ulist *l, uint32_t x) {
+    if (l->n == l->cap) {
+        uint32_t nc = l->cap ? 2 * l->cap : 8;
+        uint32_t *nv = (uint32_t *)realloc(l->v, nc * sizeof(uint32_t));
+        if (!nv) return ORC_ENOMEM;
+        l->v = nv; l->cap = nc;
+    }
+    l->v[l->n++] = x;
+    return ORC_OK;
+}
+
+int orc_gwcp(uint32_t n_blocks, uint32_t tpb, uint32_t warp_size, const orc_event *ev, uint64_t n,
+             uint64_t *bad, orc_pairs *out) {
+    memset(out, 0, sizeof(*out));
+    *bad = UINT64_MAX;
+    if (!grid_ok(n_blocks, tpb, &warp_size, n)) return ORC_EINVAL;
+    uint64_t T64 = (uint64_t)n_blocks * tpb;
+    if (T64 > 8192) return ORC_EINVAL; /* dense clocks */
+    g_inclusive = 0;
+    prep_t p;
+    int rc = prepare(&p, n_blocks, tpb, warp_size, ev, n, bad);
+    if (rc != ORC_OK) { prep_free(&p); return rc; }
+    cs_info C;
+    rc = cs_build(&p, &C);
+    if (rc != ORC_OK) { prep_free(&p); return rc; }
+    const uint32_t T = p.n_threads;
+
+    /* locations (dense ids) and their access histories in trace order */
+    hmap lmap = {0}, lkmap = {0}, wmap = {0}, lwmap = {0}, curmap = {0}, joinmap = {0};
+    uint32_t *loc = (uint32_t *)malloc((n ? n : 1) * sizeof(uint32_t));
+    uint32_t *epoch = (uint32_t *)malloc((n ? n : 1) * sizeof(uint32_t));
+    if (hmap_init(&lmap, n) != ORC_OK || !loc || !epoch) { rc = ORC_ENOMEM; }
+    uint32_t L = 0;
+    for (uint64_t i = 0; i < n && rc == ORC_OK; i++) {
+        int ins;
+        loc[i] = is_access(kind_of(&ev[i])) ? hmap_get(&lmap, loc_key(&p, &ev[i]), L, &ins) : UINT32_MAX;
+        if (loc[i] != UINT32_MAX && ins) L++;
+    }
+    ulist *hist = (ulist *)calloc(L ? L : 1, sizeof(ulist));
+
+    /* clocks */
+    uint32_t *N = (uint32_t *)malloc((T ? T : 1) * sizeof(uint32_t));
+    uint32_t *P = (uint32_t *)calloc((size_t)T * T + 1, sizeof(uint32_t));
+    uint32_t *H = (uint32_t *)calloc((size_t)T * T + 1, sizeof(uint32_t));
+    uint32_t *J = (uint32_t *)malloc(((size_t)T + 1) * sizeof(uint32_t));
+    uint32_t *JH = (uint32_t *)malloc(((size_t)T + 1) * sizeof(uint32_t));
+    if (!hist || !N || !P || !H || !J || !JH) rc = ORC_ENOMEM;
+    for (uint32_t t = 0; t < T && rc == ORC_OK; t++) { N[t] = 1; H[(uint64_t)t * T + t] = 1; }
+
+    /* lock clocks H_<l,s>, P_<l,s>: (word, key) -> index into hl/pl; each word's keys listed */
+    vecs hl = {0}, pl = {0}, lrw = {0}, csv = {0};
+    hl.T = pl.T = lrw.T = csv.T = T;
+    /* map sizes: lock words and lock clocks are at most the lock operations (two keys each), the
+     * queue cursors the closing releases, the L^r / L^w clocks the (access, held section) pairs */
+    uint64_t n_lockops = 0, inside = 0;
+    for (uint64_t i = 0; i < n; i++) n_lockops += is_lockop(&p, (uint32_t)i);
+    for (uint32_t t = 0; t < T; t++) {
+        uint64_t depth = 0;
+        for (uint32_t q = p.po_start[t]; q < p.po_start[t + 1]; q++) {
+            uint32_t i = p.po_idx[q];
+            if (is_access(kind_of(&ev[i])) && !is_lockop(&p, i)) inside += depth;
+            depth -= C.close_cs[i] != UINT32_MAX;
+            depth += C.open_cs[i] != UINT32_MAX;
+        }
+    }
+    if (rc == ORC_OK && (hmap_init(&lkmap, 2 * n_lockops + 1) != ORC_OK || hmap_init(&wmap, n_lockops + 1) != ORC_OK ||
+                         hmap_init(&lwmap, inside + 1) != ORC_OK))
+        rc = ORC_ENOMEM;
+    ulist *word_keys = NULL;   /* per lock word index: lock-clock indices present */
+    uint32_t n_words = 0, n_lk = 0, n_lw = 0, wcap = 0;
+    uint32_t *lk_key = NULL;   /* per lock-clock index: its scope key */
+    uint32_t lkcap = 0;
+    /* per critical section: C_t at its acquire, H_t at its release; read/write sets while open */
+    uint32_t *cs_acqC = (uint32_t *)malloc(((size_t)C.n_cs + 1) * sizeof(uint32_t));
+    uint32_t *cs_relH = (uint32_t *)malloc(((size_t)C.n_cs + 1) * sizeof(uint32_t));
+    ulist *cs_R = (ulist *)calloc((size_t)C.n_cs + 1, sizeof(ulist));
+    ulist *cs_W = (ulist *)calloc((size_t)C.n_cs + 1, sizeof(ulist));
+    /* per lock word: its critical sections in acquire order; per (thread, word): queue cursor */
+    ulist *word_cs = NULL;
+    ulist cursor = {0};
+    ulist *held = (ulist *)calloc(T ? T : 1, sizeof(ulist)); /* open critical sections per thread */
+    /* (thread, critical section) pairs joined by rule (ii): at most one per thread and section */
+    if (rc == ORC_OK && (!cs_acqC || !cs_relH || !cs_R || !cs_W || !held || hmap_init(&curmap, n_lockops + 1) != ORC_OK ||
+                         hmap_init(&joinmap, 1024) != ORC_OK))
+        rc = ORC_ENOMEM;
+
+#define WORD_INDEX(w, out_idx)                                                                   \
+    do {                                                                                         \
+        int ins_;                                                                                \
+        out_idx = hmap_get(&wmap, (w), n_words, &ins_);                                          \
+        if (ins_) {                                                                              \
+            if (n_words == wcap) {                                                               \
+                uint32_t nc_ = wcap ? 2 * wcap : 64;                                             \
+                ulist *a_ = (ulist *)realloc(word_keys, nc_ * sizeof(ulist));                    \
+                ulist *b_ = (ulist *)realloc(word_cs, nc_ * sizeof(ulist));                      \
+                if (!a_ || !b_) { if (a_) word_keys = a_; if (b_) word_cs = b_; rc = ORC_ENOMEM; break; } \
+                word_keys = a_; word_cs = b_;                                                    \
+                memset(&word_keys[wcap], 0, (nc_ - wcap) * sizeof(ulist));                       \
+                memset(&word_cs[wcap], 0, (nc_ - wcap) * sizeof(ulist));                         \
+                wcap = nc_;                                                                      \
+            }                                                                                    \
+            n_words++;                                                                           \
+        }                                                                                        \
+    } while (0)
+
+    /* the lock clock of (word index wi, key k), created on first use */
+#define LOCK_CLOCK(wi, k, out_idx)                                                               \
+    do {                                                                                         \
+        int ins_;                                                                                \
+        out_idx = hmap_get(&lkmap, ((uint64_t)(wi) << 32) | (k), n_lk, &ins_);                    \
+        if (ins_) {                                                                              \
+            if (vecs_new(&hl) == UINT32_MAX || vecs_new(&pl) == UINT32_MAX) { rc = ORC_ENOMEM; break; } \
+            if (n_lk == lkcap) {                                                                 \
+                uint32_t nc_ = lkcap ? 2 * lkcap : 64;                                           \
+                uint32_t *a_ = (uint32_t *)realloc(lk_key, nc_ * sizeof(uint32_t));             \
+                if (!a_) { rc = ORC_ENOMEM; break; }                                             \
+                lk_key = a_; lkcap = nc_;                                                        \
+            }                                                                                    \
+            lk_key[n_lk] = (k);                                                                  \
+            n_lk++;                                                                              \
+            if (ulist_push(&word_keys[wi], out_idx) != ORC_OK) { rc = ORC_ENOMEM; break; }       \
+        }                                                                                        \
+    } while (0)
+
+    /* L^r (rw = 0) / L^w (rw = 1) of lock clock lk and location x, created on first use when
+     * create is set; UINT32_MAX when absent */
+#define LRW(lk, x, rw, create, out_idx)                                                          \
+    do {                                                                                         \
+        uint64_t key_ = ((uint64_t)(lk) << 33) | ((uint64_t)(x) << 1) | (rw);                     \
+        int ins_;                                                                                \
+        if (!(create)) {                                                                         \
+            uint64_t m_ = lwmap.cap - 1, s_ = mix64(key_) & m_;                                  \
+            out_idx = UINT32_MAX;                                                                \
+            while (lwmap.vals[s_]) {                                                             \
+                if (lwmap.keys[s_] == key_) { out_idx = lwmap.vals[s_] - 1; break; }             \
+                s_ = (s_ + 1) & m_;                                                              \
+            }                                                                                    \
+        } else {                                                                                 \
+            out_idx = hmap_get(&lwmap, key_, n_lw, &ins_);                                       \
+            if (ins_) { if (vecs_new(&lrw) == UINT32_MAX) { rc = ORC_ENOMEM; break; } n_lw++; }  \
+        }                                                                                        \
+    } while (0)
+
+    /* barrier bookkeeping */
+    uint32_t n_inst = p.bar_off[n_blocks];
+    uint32_t *bar_n = (uint32_t *)calloc(n_inst ? n_inst : 1, sizeof(uint32_t));
+    uint32_t *bar_list_off = (uint32_t *)calloc((size_t)n_inst + 1, sizeof(uint32_t));
+    uint32_t *bar_list = NULL;
+    uint32_t *wbar_n = (uint32_t *)calloc(p.n_winst ? p.n_winst : 1, sizeof(uint32_t));
+    uint32_t *wbar_list = (uint32_t *)malloc(((size_t)p.n_winst * 32 + 1) * sizeof(uint32_t));
+    if (!bar_n || !bar_list_off || !wbar_n || !wbar_list) rc = ORC_ENOMEM;
+    if (rc == ORC_OK) {
+        for (uint32_t s = 0; s < n_inst; s++) bar_list_off[s + 1] = bar_list_off[s] + p.bar_cnt[s];
+        bar_list = (uint32_t *)malloc(((size_t)bar_list_off[n_inst] + 1) * sizeof(uint32_t));
+        if (!bar_list) rc = ORC_ENOMEM;
+    }
+
+    for (uint64_t ii = 0; ii < n && rc == ORC_OK; ii++) {
+        const uint32_t i = (uint32_t)ii, t = ev[i].tid, bt = t / tpb;
+        const unsigned k = kind_of(&ev[i]);
+        uint32_t *Pt = &P[(uint64_t)t * T], *Ht = &H[(uint64_t)t * T];
+
+        if (is_access(k)) {
+            const uint32_t x = loc[i];
+            const int lockop = is_lockop(&p, i);
+            /* Algorithm 2 READ / WRITE (reads and writes only, reading G2): for every held
+             * <l, s>, join L^w (and L^r for a write) of the lock clocks whose scope overlaps s */
+            if (!lockop) {
+                for (uint32_t q = 0; q < held[t].n && rc == ORC_OK; q++) {
+                    const orc_cs *c = &C.cs[held[t].v[q]];
+                    uint32_t wi;
+                    WORD_INDEX(c->word, wi);
+                    if (rc != ORC_OK) break;
+                    for (uint32_t kk = 0; kk < word_keys[wi].n; kk++) {
+                        uint32_t lk = word_keys[wi].v[kk], idx;
+                        if (!keys_overlap(lk_key[lk], c->acq_key)) continue;
+                        LRW(lk, x, 1, 0, idx);
+                        if (idx != UINT32_MAX) vjoin(Pt, lrw.v[idx], T);
+                        if (k != K_READ) {
+                            LRW(lk, x, 0, 0, idx);
+                            if (idx != UINT32_MAX) vjoin(Pt, lrw.v[idx], T);
+                        }
+                    }
+                }
+                if (rc != ORC_OK) break;
+            }
+            /* the check: an earlier conflicting access a of thread u races unless
+             * epoch(a) <= C_t[u] = P_t[u] */
+            for (uint32_t q = 0; q < hist[x].n; q++) {
+                uint32_t a = hist[x].v[q];
+                if (!conflict(&p, a, i)) continue;
+                if (epoch[a] <= Pt[ev[a].tid]) continue;
+                if (pairs_push(out, a, i) != ORC_OK) { rc = ORC_ENOMEM; break; }
+            }
+            if (rc != ORC_OK) break;
+            epoch[i] = N[t];
+            if (ulist_push(&hist[x], i) != ORC_OK) { rc = ORC_ENOMEM; break; }
+            /* the read and write sets of every held critical section */
+            if (!lockop)
+                for (uint32_t q = 0; q < held[t].n; q++) {
+                    uint32_t ci = held[t].v[q];
+                    if (ulist_push(k == K_READ ? &cs_R[ci] : &cs_W[ci], x) != ORC_OK) { rc = ORC_ENOMEM; break; }
+                }
+            if (rc != ORC_OK) break;
+        }
+
+        if (p.rel_scope[i] != 0xff) {
+            /* RELEASE(t, l, R, W, s) */
+            const uint32_t key = scope_key(p.rel_scope[i], bt), ci = C.close_cs[i];
+            uint32_t wi, lk;
+            WORD_INDEX(loc_key(&p, &ev[i]), wi);
+            if (rc != ORC_OK) break;
+            if (ci != UINT32_MAX) {
+                /* rule (ii): other threads' critical sections on l released before this one, in
+                 * acquire order, whose acquire time is below C_t: join the release's H when the
+                 * scopes overlap (G4).  Every queued entry is examined, not only the front (G5),
+                 * until a pass joins nothing more; entries joined, or of t itself, before the first
+                 * pending one are dropped from the queue. */
+                uint32_t cur;
+                {
+                    int ins;
+                    cur = hmap_get(&curmap, ((uint64_t)t << 32) | wi, cursor.n, &ins);
+                    if (ins && ulist_push(&cursor, 0) != ORC_OK) { rc = ORC_ENOMEM; break; }
+                }
+                const uint32_t Nt = N[t];
+                for (int more = 1; more && rc == ORC_OK;) {
+                    more = 0;
+                    for (uint32_t pos = cursor.v[cur]; pos < word_cs[wi].n; pos++) {
+                        const uint32_t fi = word_cs[wi].v[pos];
+                        const orc_cs *f = &C.cs[fi];
+                        if (f->tid == t || f->rel == UINT32_MAX || f->rel > i || !keys_overlap(f->rel_key, key)) continue;
+                        int ins;
+                        (void)hmap_get(&joinmap, ((uint64_t)t << 32) | fi, 0, &ins);
+                        if (!ins) continue; /* joined at an earlier release of t */
+                        const uint32_t *ac = csv.v[cs_acqC[fi]];
+                        int below = 1;
+                        for (uint32_t u = 0; u < T && below; u++) below = ac[u] <= (u == t ? Nt : Pt[u]);
+                        if (!below) { hmap_unget(&joinmap, ((uint64_t)t << 32) | fi); continue; }
+                        vjoin(Pt, csv.v[cs_relH[fi]], T);
+                        more = 1;
+                    }
+                }
+                {
+                    uint32_t pos = cursor.v[cur];
+                    while (pos < word_cs[wi].n) {
+                        const uint32_t fi = word_cs[wi].v[pos];
+                        if (C.cs[fi].tid != t && !hmap_has(&joinmap, ((uint64_t)t << 32) | fi)) break;
+                        pos++;
+                    }
+                    cursor.v[cur] = pos;
+                }
+                /* L^r_<l,s>,x and L^w_<l,s>,x join H_t for the section's reads and writes */
+                LOCK_CLOCK(wi, key, lk);
+                if (rc != ORC_OK) break;
+                for (int rw = 0; rw < 2 && rc == ORC_OK; rw++) {
+                    const ulist *S = rw ? &cs_W[ci] : &cs_R[ci];
+                    for (uint32_t q = 0; q < S->n; q++) {
+                        uint32_t idx;
+                        LRW(lk, S->v[q], rw, 1, idx);
+                        if (rc != ORC_OK) break;
+                        vjoin(lrw.v[idx], Ht, T);
+                    }
+                }
+                if (rc != ORC_OK) break;
+                /* Rel_l(t').enque(<H_t, s>) for t' != t: the section's release time */
+                uint32_t v = vecs_new(&csv);
+                if (v == UINT32_MAX) { rc = ORC_ENOMEM; break; }
+                memcpy(csv.v[v], Ht, (size_t)T * sizeof(uint32_t));
+                cs_relH[ci] = v;
+                /* the lockset loses the section */
+                for (uint32_t q = 0; q < held[t].n; q++)
+                    if (held[t].v[q] == ci) {
+                        memmove(&held[t].v[q], &held[t].v[q + 1], (held[t].n - q - 1) * sizeof(uint32_t));
+                        held[t].n--;
+                        break;
+                    }
+            } else {
+                LOCK_CLOCK(wi, key, lk);
+                if (rc != ORC_OK) break;
+            }
+            /* H_<l,s> and P_<l,s> publish t's clocks (joined, G6) */
+            vjoin(hl.v[lk], Ht, T);
+            vjoin(pl.v[lk], Pt, T);
+            N[t] += 1;
+            Ht[t] += 1;
+        }
+
+        if (p.acq_scope[i] != 0xff) {
+            /* ACQUIRE(t, l, s): join P and H of every lock clock of l whose scope reaches s */
+            const uint32_t key = scope_key(p.acq_scope[i], bt);
+            uint32_t wi;
+            WORD_INDEX(loc_key(&p, &ev[i]), wi);
+            if (rc != ORC_OK) break;
+            for (uint32_t kk = 0; kk < word_keys[wi].n; kk++) {
+                uint32_t lk = word_keys[wi].v[kk];
+                if (!keys_overlap(lk_key[lk], key)) continue;
+                vjoin(Pt, pl.v[lk], T);
+                vjoin(Ht, hl.v[lk], T);
+            }
+            const uint32_t ci = C.open_cs[i];
+            if (ci != UINT32_MAX) {
+                /* Acq_l(t').enque(<C_t, s>) for t' != t */
+                uint32_t v = vecs_new(&csv);
+                if (v == UINT32_MAX) { rc = ORC_ENOMEM; break; }
+                memcpy(csv.v[v], Pt, (size_t)T * sizeof(uint32_t));
+                csv.v[v][t] = N[t];
+                cs_acqC[ci] = v;
+                if (ulist_push(&word_cs[wi], ci) != ORC_OK || ulist_push(&held[t], ci) != ORC_OK) { rc = ORC_ENOMEM; break; }
+            }
+        }
+
+        /* SYNC(scope): at the last arrival of a block or warp barrier instance */
+        uint32_t *parts = NULL, np = 0;
+        if (k == K_BAR) {
+            uint32_t slot = p.bar_off[bt] + p.phase[i];
+            bar_list[bar_list_off[slot] + bar_n[slot]++] = t;
+            if (bar_n[slot] == p.n_active[bt]) { parts = &bar_list[bar_list_off[slot]]; np = bar_n[slot]; }
+        }
+        if (k == K_WBAR) {
+            uint32_t inst = p.wbar_inst[i];
+            wbar_list[(uint64_t)inst * 32 + wbar_n[inst]++] = t;
+            if (wbar_n[inst] == (uint32_t)__builtin_popcount(p.winst_mask[inst])) { parts = &wbar_list[(uint64_t)inst * 32]; np = wbar_n[inst]; }
+        }
+        if (parts) {
+            memset(J, 0, (size_t)T * sizeof(uint32_t));
+            memset(JH, 0, (size_t)T * sizeof(uint32_t));
+            for (uint32_t q = 0; q < np; q++) {
+                uint32_t u = parts[q];
+                uint32_t *Pu = &P[(uint64_t)u * T];
+                for (uint32_t w = 0; w < T; w++) {
+                    uint32_t cu = w == u ? N[u] : Pu[w]; /* C_u = P_u{u := N_u} */
+                    if (cu > J[w]) J[w] = cu;
+                }
+                vjoin(JH, &H[(uint64_t)u * T], T);
+            }
+            for (uint32_t q = 0; q < np; q++) {
+                uint32_t u = parts[q];
+                memcpy(&P[(uint64_t)u * T], J, (size_t)T * sizeof(uint32_t));
+                memcpy(&H[(uint64_t)u * T], JH, (size_t)T * sizeof(uint32_t));
+                N[u] += 1;
+                H[(uint64_t)u * T + u] += 1;
+            }
+        }
+    }
+#undef WORD_INDEX
+#undef LOCK_CLOCK
+#undef LRW
+
+    if (hist) for (uint32_t x = 0; x < L; x++) free(hist[x].v);
+    free(hist); free(loc); free(epoch); free(N); free(P); free(H); free(J); free(JH);
+    vecs_free(&hl); vecs_free(&pl); vecs_free(&lrw); vecs_free(&csv);
+    if (word_keys) for (uint32_t w = 0; w < n_words; w++) { free(word_keys[w].v); free(word_cs[w].v); }
+    free(word_keys); free(word_cs); free(lk_key); free(cursor.v);
+    if (cs_R) for (uint32_t c = 0; c < C.n_cs; c++) { free(cs_R[c].v); free(cs_W[c].v); }
+    if (held) for (uint32_t t = 0; t < T; t++) free(held[t].v);
+    free(cs_R); free(cs_W); free(cs_acqC); free(cs_relH); free(held);
+    free(bar_n); free(bar_list_off); free(bar_list); free(wbar_n); free(wbar_list);
+    hmap_free(&lmap); hmap_free(&lkmap); hmap_free(&wmap); hmap_free(&lwmap); hmap_free(&curmap);
+    hmap_free(&joinmap);
+    cs_free(&C);
+    prep_free(&p);
+    if (rc != ORC_OK) { orc_pairs_free(out); return rc; }
+    qsort(out->data, out->n, 2 * sizeof(uint32_t), cmp_pair);
+    return ORC_OK;
+}
+
+/* The definition (rules (i)-(iv)) on a tiny trace: base edges from rule (i) (a release r and a
+ * later read or write e inside a critical section of the same lock word, the sections' scopes
+ * overlapping, r's section holding an access of e's location with a write on either side), rule
+ * (iii) (every event before a participant's barrier arrival to every event after another
+ * participant's arrival) and rule (ii) (two releases of one lock word by different threads whose
+ * critical sections, acquire and release included, hold GWCP-ordered events, the releases' scopes
+ * overlapping); rule (iv) composes each base edge with happens-before on both sides; the relation
+ * is closed transitively, and rule (ii) is applied again until nothing changes.  The report is
+ * every conflicting pair of different threads left unordered. */
+int orc_gwcp_bruteforce(uint32_t n_blocks, uint32_t tpb, uint32_t warp_size, const orc_event *ev, uint64_t n,
+                        uint64_t *bad, orc_pairs *out) {
+    memset(out, 0, sizeof(*out));
+    *bad = UINT64_MAX;
+    if (!grid_ok(n_blocks, tpb, &warp_size, n)) return ORC_EINVAL;
+    if (n > 4096) return ORC_EINVAL; /* cubic work: tiny traces only */
+    g_inclusive = 0;
+    prep_t p;
+    int rc = prepare(&p, n_blocks, tpb, warp_size, ev, n, bad);
+    if (rc != ORC_OK) { prep_free(&p); return rc; }
+    cs_info C;
+    rc = cs_build(&p, &C);
+    if (rc != ORC_OK) { prep_free(&p); return rc; }
+    const uint64_t W = (n + 63) / 64;
+    uint64_t *hb = hb_reach(&p);                                         /* hb[j]: i ->+ j */
+    uint64_t *gw = (uint64_t *)calloc(n * W + 1, sizeof(uint64_t));     /* gw[j]: i <GWCP j */
+    uint32_t *esrc = NULL, *edst = NULL;                                 /* base edges */
+    uint64_t n_edges = 0, cap_edges = 0;
+    uint8_t *have_ii = (uint8_t *)calloc((size_t)C.n_cs * C.n_cs + 1, 1); /* rule (ii) edge added */
+    if (!hb || !gw || !have_ii) rc = ORC_ENOMEM;
+#define BIT(m, row, i) (((m)[(uint64_t)(row) * W + ((i) >> 6)] >> ((i) & 63)) & 1)
+#define HB(i, j) ((i) == (j) || BIT(hb, j, i))
+#define ADD_EDGE(a, b)                                                                           \
+    do {                                                                                         \
+        if (n_edges == cap_edges) {                                                              \
+            uint64_t nc_ = cap_edges ? 2 * cap_edges : 256;                                      \
+            uint32_t *s_ = (uint32_t *)realloc(esrc, nc_ * sizeof(uint32_t));                    \
+            uint32_t *d_ = (uint32_t *)realloc(edst, nc_ * sizeof(uint32_t));                    \
+            if (s_) esrc = s_;                                                                   \
+            if (d_) edst = d_;                                                                   \
+            if (!s_ || !d_) { rc = ORC_ENOMEM; break; }                                          \
+            cap_edges = nc_;                                                                     \
+        }                                                                                        \
+        esrc[n_edges] = (a); edst[n_edges] = (b); n_edges++;                                     \
+    } while (0)
+
+    /* po range of a critical section: [po_pos(acq), po_pos(rel)] of its thread (rel: to the end) */
+#define CS_LO(c) (p.po_start[(c)->tid] + p.po_pos[(c)->acq])
+#define CS_HI(c) ((c)->rel == UINT32_MAX ? p.po_start[(c)->tid + 1] - 1 : p.po_start[(c)->tid] + p.po_pos[(c)->rel])
+
+    /* rule (i) */
+    for (uint32_t c1i = 0; c1i < C.n_cs && rc == ORC_OK; c1i++) {
+        const orc_cs *c1 = &C.cs[c1i];
+        if (c1->rel == UINT32_MAX) continue;
+        for (uint64_t jj = c1->rel + 1; jj < n && rc == ORC_OK; jj++) {
+            uint32_t e = (uint32_t)jj;
+            if (!is_access(kind_of(&ev[e])) || is_lockop(&p, e)) continue;
+            /* e inside a critical section of its thread on c1's word, scopes overlapping */
+            int inside = 0;
+            for (uint32_t c2i = 0; c2i < C.n_cs && !inside; c2i++) {
+                const orc_cs *c2 = &C.cs[c2i];
+                if (c2->tid != ev[e].tid || c2->word != c1->word || c2i == c1i) continue;
+                uint32_t pe = p.po_start[c2->tid] + p.po_pos[e];
+                if (pe > CS_LO(c2) && pe < CS_HI(c2) + (c2->rel == UINT32_MAX)) inside = keys_overlap(c1->rel_key, c2->acq_key);
+            }
+            if (!inside) continue;
+            int hit = 0;
+            for (uint32_t q = CS_LO(c1) + 1; q < CS_HI(c1) && !hit; q++) {
+                uint32_t a = p.po_idx[q];
+                if (!is_access(kind_of(&ev[a])) || is_lockop(&p, a)) continue;
+                if (loc_key(&p, &ev[a]) != loc_key(&p, &ev[e])) continue;
+                hit = is_writeish(kind_of(&ev[a])) || is_writeish(kind_of(&ev[e]));
+            }
+            if (hit) ADD_EDGE(c1->rel, e);
+        }
+    }
+    /* rule (iii): block barriers (participants' k-th BAR) and warp barriers (an instance's WBARs) */
+    for (uint64_t jj = 0; jj < n && rc == ORC_OK; jj++) {
+        uint32_t bu = (uint32_t)jj;
+        unsigned kb = kind_of(&ev[bu]);
+        if (kb != K_BAR && kb != K_WBAR) continue;
+        uint32_t u = ev[bu].tid;
+        if (p.po_pos[bu] == 0) continue;
+        uint32_t before = p.po_idx[p.po_start[u] + p.po_pos[bu] - 1];
+        for (uint64_t kk = 0; kk < n && rc == ORC_OK; kk++) {
+            uint32_t bv = (uint32_t)kk, v = ev[bv].tid;
+            if (kind_of(&ev[bv]) != kb) continue;
+            if (kb == K_BAR && (block_of(&p, v) != block_of(&p, u) || p.phase[bv] != p.phase[bu])) continue;
+            if (kb == K_WBAR && p.wbar_inst[bv] != p.wbar_inst[bu]) continue;
+            if (p.po_start[v] + p.po_pos[bv] + 1 >= p.po_start[v + 1]) continue;
+            ADD_EDGE(before, p.po_idx[p.po_start[v] + p.po_pos[bv] + 1]);
+        }
+    }
+    /* fixpoint with rule (ii) */
+    int changed = 1;
+    while (changed && rc == ORC_OK) {
+        changed = 0;
+        memset(gw, 0, n * W * sizeof(uint64_t));
+        /* rule (iv): x ->HB* x0 -> y0 ->HB* y */
+        for (uint64_t q = 0; q < n_edges; q++) {
+            uint32_t x0 = esrc[q], y0 = edst[q];
+            for (uint64_t yy = y0; yy < n; yy++) {
+                uint32_t y = (uint32_t)yy;
+                if (!HB(y0, y)) continue;
+                for (uint64_t w = 0; w < W; w++) gw[(uint64_t)y * W + w] |= hb[(uint64_t)x0 * W + w];
+                gw[(uint64_t)y * W + (x0 >> 6)] |= (uint64_t)1 << (x0 & 63);
+            }
+        }
+        /* transitive closure in trace order (every edge points forward) */
+        for (uint64_t yy = 0; yy < n; yy++)
+            for (uint64_t xx = 0; xx < yy; xx++)
+                if (BIT(gw, yy, xx))
+                    for (uint64_t w = 0; w < W; w++) gw[yy * W + w] |= gw[xx * W + w];
+        /* rule (ii) */
+        for (uint32_t c1i = 0; c1i < C.n_cs && rc == ORC_OK; c1i++) {
+            const orc_cs *c1 = &C.cs[c1i];
+            if (c1->rel == UINT32_MAX) continue;
+            for (uint32_t c2i = 0; c2i < C.n_cs; c2i++) {
+                const orc_cs *c2 = &C.cs[c2i];
+                if (c2->rel == UINT32_MAX || c2->tid == c1->tid || c2->word != c1->word || c2->rel <= c1->rel) continue;
+                if (!keys_overlap(c1->rel_key, c2->rel_key) || have_ii[(uint64_t)c1i * C.n_cs + c2i]) continue;
+                int ordered = 0;
+                for (uint32_t q1 = CS_LO(c1); q1 <= CS_HI(c1) && !ordered; q1++)
+                    for (uint32_t q2 = CS_LO(c2); q2 <= CS_HI(c2) && !ordered; q2++)
+                        ordered = BIT(gw, p.po_idx[q2], p.po_idx[q1]);
+                if (!ordered) continue;
+                have_ii[(uint64_t)c1i * C.n_cs + c2i] = 1;
+                ADD_EDGE(c1->rel, c2->rel);
+                changed = 1;
+            }
+        }
+    }
+    for (uint64_t jj = 0; jj < n && rc == ORC_OK; jj++) {
+        uint32_t j = (uint32_t)jj;
+        if (!is_access(kind_of(&ev[j]))) continue;
+        for (uint32_t i = 0; i < j; i++) {
+            if (!conflict(&p, i, j) || BIT(gw, j, i)) continue;
+            if (pairs_push(out, i, j) != ORC_OK) { rc = ORC_ENOMEM; break; }
+        }
+    }
+#undef BIT
+#undef HB
+#undef ADD_EDGE
+#undef CS_LO
+#undef CS_HI
+    free(hb); free(gw); free(esrc); free(edst); free(have_ii);
+    cs_free(&C);
+    prep_free(&p);
+    if (rc != ORC_OK) { orc_pairs_free(out); return rc; }
+    qsort(out->data, out->n, 2 * sizeof(uint32_t), cmp_pair);
+    return ORC_OK;
 }
