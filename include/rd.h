@@ -191,6 +191,30 @@ rd_status rd_races_many(rd_ctx ctx, const rd_trace *traces, uint32_t n, rd_pair 
 
 rd_status rd_trace_free(rd_ctx ctx, rd_trace trace);
 
+/* Figures of a trace's last check (diagnostics; waits for it).  The knowledge vectors are the
+ * happens-before clocks of Algorithm 1 (Section 4.1) stored with the compression of Section 5.2:
+ * one word per block (the block's barrier phase stands for every thread of the block) plus one word
+ * per thread that releases (or takes part in a warp barrier), instead of one word per thread. */
+typedef struct {
+    uint64_t n_events;          /* records */
+    uint64_t n_accesses;        /* reads, writes, atomics, lock acquires and releases */
+    uint64_t kind_count[8];     /* records of each kind */
+    uint32_t key_bits;          /* significant bits of the location key (sort passes follow from it) */
+    uint32_t max_phase;         /* the most block barriers any thread passed */
+    uint32_t engine;            /* 0: no knowledge vectors needed; 1: parallel engine; 2: interpreter */
+    uint32_t packed;            /* 1 when category and phase rode in the location key word */
+    uint64_t clock_vectors;     /* knowledge vectors written (the empty one included) */
+    uint64_t clock_words;       /* words per vector: blocks + threads with a column */
+    uint64_t clock_bytes;       /* clock_vectors * clock_words * 4: pool bytes the check used */
+    uint64_t dense_clock_bytes; /* the same vectors as one word per thread (no compression) */
+    uint64_t engine_ops;        /* operations of the parallel engine (releases, acquires, barriers) */
+    uint64_t engine_groups;     /* dependency-free groups they were evaluated in */
+    uint64_t slow_chunks;       /* 64-access chunks the segment check sent to its exact slow path */
+    uint64_t race_pairs;        /* pairs found (may exceed the pair buffer) */
+    uint64_t workspace_bytes;   /* the workspace the trace needs (rd_workspace_bytes) */
+} rd_stats;
+rd_status rd_trace_stats(rd_ctx ctx, rd_trace trace, rd_stats *out);
+
 /* Tuning of the location sort (the dominant kernel): built-in variants that differ in digit width
  * (7, 8 or 9 bits, hence passes), wavefronts per workgroup and items per lane (hence tile size).
  * Results never depend on the variant.  rd_set_tuning selects one for every later check on the

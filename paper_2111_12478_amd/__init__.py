@@ -52,6 +52,15 @@ class rd_tuning(ctypes.Structure):
                 ("items_per_lane", ctypes.c_uint32), ("reserved", ctypes.c_uint32)]
 
 
+class rd_stats(ctypes.Structure):
+    _fields_ = [("n_events", ctypes.c_uint64), ("n_accesses", ctypes.c_uint64), ("kind_count", ctypes.c_uint64 * 8),
+                ("key_bits", ctypes.c_uint32), ("max_phase", ctypes.c_uint32), ("engine", ctypes.c_uint32),
+                ("packed", ctypes.c_uint32), ("clock_vectors", ctypes.c_uint64), ("clock_words", ctypes.c_uint64),
+                ("clock_bytes", ctypes.c_uint64), ("dense_clock_bytes", ctypes.c_uint64),
+                ("engine_ops", ctypes.c_uint64), ("engine_groups", ctypes.c_uint64), ("slow_chunks", ctypes.c_uint64),
+                ("race_pairs", ctypes.c_uint64), ("workspace_bytes", ctypes.c_uint64)]
+
+
 class RdError(RuntimeError):
     def __init__(self, status, msg, event_index=None):
         super().__init__(f"{msg} (status {status})")
@@ -98,6 +107,7 @@ def load_library():
             "rd_races": ([vp, vp, vp, u64, P(u64)], i32),
             "rd_race_kinds": ([vp, vp, vp, u64, P(u64)], i32),
             "rd_trace_free": ([vp, vp], i32),
+            "rd_trace_stats": ([vp, vp, P(rd_stats)], i32),
             "rd_batch_workspace_bytes": ([vp, P(vp), u32, P(rd_limits), P(u64)], i32),
             "rd_check_many": ([vp, P(vp), u32, vp, u64, P(rd_limits), vp], i32),
             "rd_races_many": ([vp, P(vp), u32, vp, u64, P(u64), P(i32)], i32),
@@ -306,6 +316,17 @@ def rd_server_close(srv) -> int:
 
 def rd_trace_free(ctx, trace) -> int:
     return load_library().rd_trace_free(ctx, trace)
+
+
+def rd_trace_stats(ctx, trace) -> dict:
+    """Figures of the trace's last check (see rd_stats in include/rd.h) as a dict."""
+    out = rd_stats()
+    st = load_library().rd_trace_stats(ctx, trace, ctypes.byref(out))
+    if st != RD_OK:
+        raise RdError(st, "rd_trace_stats failed")
+    d = {name: getattr(out, name) for name, _ in rd_stats._fields_}
+    d["kind_count"] = list(out.kind_count)
+    return d
 
 
 def rd_strerror(status: int) -> str:

@@ -24,6 +24,7 @@
 namespace rd {
 
 constexpr u32 BK_MARK = 0x80000000u;  // e_cur: the block's knowledge after (value & ~BK_MARK) barriers
+constexpr u32 OP_SKIPPED = 0xfffffffeu;  // op_dep during evaluation: the operation wrote no vector
 constexpr u32 ENG_WIDE = 16;          // groups with at least this many operations run on every workgroup
 constexpr u32 ENG_THREADS = 512;
 constexpr u32 ENG_SPIN = 1u << 19;  // ~1 s of polling: far above any legitimate wait
@@ -135,26 +136,107 @@ __device__ inline u32 seg_scan_chunk(SegLds &L, bool head, u32 val, u32 nin) {
     return ex;
 }
 
-// Chains (X, DEV) and (X, ALL) over ral (runs: equal locations).  Packs each item's block and
+// Chains (X, DEV) and (X, ALL) over ral (runs: equal locations), in chunks of 1024 items, one
+// workgroup per chunk.  A chunk's scan starts from the latest release of the run still open at its
+// start (its carry): k_eng_chain_sums summarises each chunk (the latest release of its last run,
+// whether a run starts in it), k_eng_chain_carry composes the summaries in order.  The summaries
+// and carries live in op_dep and op_p (free until the operations are numbered).
+constexpr u32 CHAIN_CHUNK = 1024;
+
+__device__ inline void chain_item(const Bufs &b, u32 n, u32 k, u32 &p, uint8_t &f, uint8_t &sc, bool &head) {
+    p = NONE;
+    f = 0;
+    sc = 0;
+    head = true;
+    if (k < n) {
+        p = b.ral_p[k];
+        f = b.s_flags[p];
+        sc = b.s_scope[p];
+        head = k == 0 || b.ral_key[k - 1] != b.ral_key[k];
+    }
+}
+
+__global__ __launch_bounds__(1024) void k_eng_chain_sums(Bufs b) {
+    DevParams *P = b.prm;
+    if (!eng_on(P)) return;
+    const u32 n = P->n_ral, nch = (n + CHAIN_CHUNK - 1) / CHAIN_CHUNK;
+    __shared__ int mh, md, ma;
+    for (u32 c = blockIdx.x; c < nch; c += gridDim.x) {
+        if (threadIdx.x == 0) { mh = -1; md = -1; ma = -1; }
+        __syncthreads();
+        const u32 k = c * CHAIN_CHUNK + threadIdx.x;
+        u32 p;
+        uint8_t f, sc;
+        bool head;
+        chain_item(b, n, k, p, f, sc, head);
+        if (k < n) {
+            if (head) atomicMax(&mh, (int)threadIdx.x);
+            if ((f & SF_REL) && (sc & 3u) != 0) atomicMax(&md, (int)threadIdx.x);
+            if ((f & SF_REL) && (sc & 3u) == 0) atomicMax(&ma, (int)threadIdx.x);
+        }
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            // the latest release at or after the last run head (a head's own release counts)
+            b.op_dep[3 * c] = md >= 0 && md >= mh ? b.ral_p[c * CHAIN_CHUNK + md] : NONE;
+            b.op_dep[3 * c + 1] = ma >= 0 && ma >= mh ? b.ral_p[c * CHAIN_CHUNK + ma] : NONE;
+            b.op_dep[3 * c + 2] = mh >= 0 ? 1u : 0u;
+        }
+        __syncthreads();
+    }
+}
+
+// Summary composition (earlier, later): the later one's release, else nothing if a run starts in
+// the later one, else the earlier one's.
+__device__ inline uint4 chain_compose(uint4 l, uint4 r) {
+    return make_uint4(r.x != NONE ? r.x : (r.z ? NONE : l.x), r.y != NONE ? r.y : (r.z ? NONE : l.y), l.z | r.z, 0u);
+}
+
+// One workgroup: carry of every chunk = composition of the summaries of the chunks before it
+// (op_p[2c], op_p[2c + 1]), 1024 chunks per round of an inclusive scan in LDS.
+__global__ __launch_bounds__(1024) void k_eng_chain_carry(Bufs b) {
+    DevParams *P = b.prm;
+    if (!eng_on(P)) return;
+    const u32 n = P->n_ral, nch = (n + CHAIN_CHUNK - 1) / CHAIN_CHUNK, i = threadIdx.x;
+    __shared__ uint4 S[1024];
+    uint4 run = make_uint4(NONE, NONE, 0u, 0u);  // the summaries of the rounds before
+    for (u32 base = 0; base < nch; base += 1024) {
+        const u32 c = base + i;
+        uint4 v = c < nch ? make_uint4(b.op_dep[3 * c], b.op_dep[3 * c + 1], b.op_dep[3 * c + 2], 0u)
+                          : make_uint4(NONE, NONE, 0u, 0u);
+        S[i] = v;
+        __syncthreads();
+        for (u32 off = 1; off < 1024; off <<= 1) {
+            const uint4 l = i >= off ? S[i - off] : make_uint4(NONE, NONE, 0u, 0u);
+            __syncthreads();
+            if (i >= off) S[i] = chain_compose(l, S[i]);
+            __syncthreads();
+        }
+        const uint4 ex = i == 0 ? run : chain_compose(run, S[i - 1]);
+        if (c < nch) {
+            b.op_p[2 * c] = ex.x;
+            b.op_p[2 * c + 1] = ex.y;
+        }
+        run = chain_compose(run, S[1023]);
+        __syncthreads();
+    }
+}
+
+// The chains themselves: each chunk's segmented scans from its carry.  Packs each item's block and
 // block-scope bits into e_scan1 for the per-block chains.
 __global__ __launch_bounds__(1024) void k_eng_chains(Bufs b) {
     DevParams *P = b.prm;
     if (!eng_on(P)) return;
-    const u32 n = P->n_ral;
+    const u32 n = P->n_ral, nch = (n + CHAIN_CHUNK - 1) / CHAIN_CHUNK;
     __shared__ SegLds Ld, La;
-    if (threadIdx.x == 0) { Ld.carry = NONE; La.carry = NONE; }
-    __syncthreads();
-    for (u32 c0 = 0; c0 < n; c0 += 1024) {
-        const u32 k = c0 + threadIdx.x, nin = n - c0 < 1024 ? n - c0 : 1024;
-        u32 p = NONE;
-        uint8_t f = 0, sc = 0;
-        bool head = true;
-        if (k < n) {
-            p = b.ral_p[k];
-            f = b.s_flags[p];
-            sc = b.s_scope[p];
-            head = k == 0 || b.ral_key[k - 1] != b.ral_key[k];
-        }
+    for (u32 c = blockIdx.x; c < nch; c += gridDim.x) {
+        if (threadIdx.x == 0) { Ld.carry = b.op_p[2 * c]; La.carry = b.op_p[2 * c + 1]; }
+        __syncthreads();
+        const u32 c0 = c * CHAIN_CHUNK;
+        const u32 k = c0 + threadIdx.x, nin = n - c0 < CHAIN_CHUNK ? n - c0 : CHAIN_CHUNK;
+        u32 p;
+        uint8_t f, sc;
+        bool head;
+        chain_item(b, n, k, p, f, sc, head);
         const bool acq = f & SF_ACQ;
         const bool rel_dev = (f & SF_REL) && (sc & 3u) != 0, rel_blk = (f & SF_REL) && (sc & 3u) == 0;
         const u32 ex_dev = seg_scan_chunk(Ld, head, rel_dev ? p : NONE, nin);
@@ -172,6 +254,7 @@ __global__ __launch_bounds__(1024) void k_eng_chains(Bufs b) {
             b.e_scan1[k] = (rel_blk ? 0x80000000u : 0u) |
                            ((rel_blk || (acq && ((sc >> 2) & 3u) == 0)) ? 0x40000000u : 0u) | blk;
         }
+        __syncthreads();
     }
 }
 
@@ -251,7 +334,8 @@ __global__ void k_eng_init(Bufs b, const u32 *rt_scan) {
 // One lane per program thread, over its sync list in program order: the knowledge an entry starts
 // from (e_cur), and for each barrier arrival the thread's latest acquire of the phase it ends
 // (e_src0 of the arrival); a barrier instance records its latest such acquire (trace index + 1)
-// in inst_coff.
+// in inst_coff.  An acquire that nothing but that barrier reads (no access, and no sync entry but
+// fences, before it) is marked SF_NOMAT.
 __global__ void k_eng_walk(Bufs b) {
     const DevParams *P = b.prm;
     if (!eng_on(P)) return;
@@ -262,14 +346,21 @@ __global__ void k_eng_walk(Bufs b) {
         u32 last = NONE;
         for (u32 p = lo; p < hi; p++) {
             const u32 kind = b.s_kind[p];
-            const uint8_t f = b.s_flags[p];
+            uint8_t f = b.s_flags[p];
             if (kind == 4u) {
                 b.e_src0[p] = last;
                 if (last != NONE) atomicMax(&b.inst_coff[b.inst_off[blk] + b.s_phase[p] - 1], b.s_pidx[last] + 1);
                 last = NONE;
             } else if (f & (SF_REL | SF_ACQ)) {
                 b.e_cur[p] = last != NONE ? last : (BK_MARK | b.s_phase[p]);
-                if ((f & SF_ACQ) && (b.e_src0[p] != NONE || b.e_src1[p] != NONE)) last = p;
+                if ((f & SF_ACQ) && (b.e_src0[p] != NONE || b.e_src1[p] != NONE)) {
+                    last = p;
+                    if (!(f & SF_REL) && b.s_imin[p] == NONE) {
+                        u32 q = p + 1;
+                        while (q < hi && b.s_kind[q] == 3u && b.s_imin[q] == NONE) q++;
+                        if (q < hi && b.s_kind[q] == 4u) b.s_flags[p] = f | SF_NOMAT;
+                    }
+                }
             }
         }
     }
@@ -404,30 +495,49 @@ __global__ void k_eng_deps(Bufs b) {
     }
 }
 
-// Greedy groups in trace order (one wavefront): a new group starts at the first operation that
-// reads from the current group.  grp[0..n_groups] are the group starts and the end.
-__global__ __launch_bounds__(64) void k_eng_groups(Bufs b) {
+// Greedy groups in trace order: a new group starts at the first operation that reads from the
+// current group.  One wavefront takes the decisions over the dependencies staged in LDS, 4,096 at a
+// time, while the workgroup's other wavefronts load the next 4,096.  grp[0..n_groups] are the group
+// starts and the end.
+constexpr u32 GRP_BLK = 4096;
+__global__ __launch_bounds__(1024) void k_eng_groups(Bufs b) {
     DevParams *P = b.prm;
     if (!eng_on(P) || P->n_ops > b.ecap) return;  // also when the pool ran out: k_eng_assign numbered nothing
-    const u32 n = P->n_ops, lane = lane_id();
-    u32 start = 0, ng = 0;
-    if (lane == 0) b.grp[0] = 0;
-    for (u32 c0 = 0; c0 < n; c0 += 64) {
-        const u32 o = c0 + lane;
-        const u32 d = o < n ? b.op_dep[o] : NONE;
-        u32 from = 0;  // lanes below `from` are settled
-        for (;;) {
-            const bool cut = lane >= from && o < n && d != NONE && d >= start;
-            const u64 m = ballot(cut);
-            if (!m) break;
-            const u32 first = (u32)__builtin_ctzll(m);
-            start = c0 + first;
-            ng++;
-            if (lane == 0) b.grp[ng] = start;
-            from = first + 1;
+    __shared__ u32 deps[2][GRP_BLK];
+    const u32 n = P->n_ops, lane = lane_id(), wave = threadIdx.x >> 6;
+    for (u32 i = threadIdx.x; i < GRP_BLK; i += blockDim.x) deps[0][i] = i < n ? b.op_dep[i] : NONE;
+    __syncthreads();
+    u32 start = 0, ng = 0;  // wave 0's
+    if (threadIdx.x == 0) b.grp[0] = 0;
+    u32 cur = 0;
+    for (u32 blk = 0; blk < n; blk += GRP_BLK, cur ^= 1u) {
+        if (wave != 0) {
+            const u32 nxt = blk + GRP_BLK;
+            for (u32 i = threadIdx.x - 64; i < GRP_BLK; i += blockDim.x - 64) {
+                const u32 o = nxt + i;
+                deps[cur ^ 1u][i] = o < n ? b.op_dep[o] : NONE;
+            }
+        } else {
+            const u32 lim = n - blk < GRP_BLK ? n - blk : GRP_BLK;
+            for (u32 c0 = 0; c0 < lim; c0 += 64) {
+                const u32 o = blk + c0 + lane;
+                const u32 d = deps[cur][c0 + lane];
+                u32 from = 0;  // lanes below `from` are settled
+                for (;;) {
+                    const bool cut = lane >= from && o < n && d != NONE && d >= start;
+                    const u64 m = ballot(cut);
+                    if (!m) break;
+                    const u32 first = (u32)__builtin_ctzll(m);
+                    start = blk + c0 + first;
+                    ng++;
+                    if (lane == 0) b.grp[ng] = start;
+                    from = first + 1;
+                }
+            }
         }
+        __syncthreads();
     }
-    if (lane == 0) {
+    if (threadIdx.x == 0) {
         b.grp[ng + 1] = n;
         P->n_groups = n ? ng + 1 : 0;
     }
@@ -485,7 +595,19 @@ __device__ void eval_bar(const Bufs &b, u32 p, u32 D, u32 *lds_list, u32 *lds_n,
         }
         if (lo < b.s_cnt[t + 1] && b.s_kind[lo] == 4u && b.s_phase[lo] == k) {
             const u32 c = b.e_src0[lo];
-            if (c != NONE) lds_list[atomicAdd(lds_n, 1u)] = b.s_khandle[c];
+            if (c != NONE) {
+                if (b.op_dep[b.e_op[c]] == OP_SKIPPED) {
+                    // the acquire wrote no vector: its inputs instead (its block knowledge before
+                    // it is this barrier's previous one, joined below)
+                    const u32 s0 = b.e_src0[c], s1 = b.e_src1[c], cur = b.e_cur[c];
+                    const bool blk_acq = ((b.s_scope[c] >> 2) & 3u) == 0;
+                    if (!(cur & BK_MARK)) lds_list[atomicAdd(lds_n, 1u)] = b.s_khandle[cur];
+                    if (s0 != NONE) lds_list[atomicAdd(lds_n, 1u)] = b.e_relh[s0];
+                    if (s1 != NONE) lds_list[atomicAdd(lds_n, 1u)] = b.e_relh[s1] + (blk_acq ? 0u : 1u);
+                } else {
+                    lds_list[atomicAdd(lds_n, 1u)] = b.s_khandle[c];
+                }
+            }
         }
     }
     __syncthreads();
@@ -538,8 +660,10 @@ __device__ void eval_bar(const Bufs &b, u32 p, u32 D, u32 *lds_list, u32 *lds_n,
     }
 }
 
-// Release and / or acquire of one sync entry (release first).
-__device__ void eval_ra(const Bufs &b, const u32 *rt_scan, u32 p, u32 D, u32 hint, JobSink js) {
+// Release and / or acquire of one sync entry (release first).  In a wide group (no window) an
+// acquire marked SF_NOMAT writes no vector: its operation is marked OP_SKIPPED and the barrier
+// that reads it joins its inputs.
+__device__ void eval_ra(const Bufs &b, const u32 *rt_scan, u32 o, u32 p, u32 D, u32 hint, JobSink js) {
     const u32 idx = b.s_pidx[p], t = b.ev[idx].y, blk = block_of(b, t);
     const uint8_t f = b.s_flags[p], sc = b.s_scope[p];
     const u32 cur = b.e_cur[p], D4 = D / 4;
@@ -588,7 +712,9 @@ __device__ void eval_ra(const Bufs &b, const u32 *rt_scan, u32 p, u32 D, u32 hin
         __syncthreads();  // an atomic's acquire may read its own release
     }
     const u32 ha = (f & SF_ACQ) ? b.s_khandle[p] : 0u;
-    if (ha) {
+    if (ha && (f & SF_NOMAT) && !(f & SF_REL) && hint == NONE) {
+        if (threadIdx.x == 0) b.op_dep[o] = OP_SKIPPED;
+    } else if (ha) {
         const u32 s0 = b.e_src0[p], s1 = b.e_src1[p];
         const bool blk_acq = ((sc >> 2) & 3u) == 0;
         const u32 ha0 = s0 != NONE ? b.e_relh[s0] : 0u;
@@ -628,7 +754,7 @@ __device__ inline void eval_op(const Bufs &b, const u32 *rt_scan, u32 o, u32 D, 
                                JobSink js) {
     const u32 p = b.op_p[o];
     if (b.s_kind[p] == 4u) eval_bar(b, p, D, lds_list, lds_n, hint, js);
-    else eval_ra(b, rt_scan, p, D, hint, js);
+    else eval_ra(b, rt_scan, o, p, D, hint, js);
     __syncthreads();
 }
 
@@ -789,7 +915,7 @@ __device__ inline void grid_barrier(DevParams *P, u32 round) {
 __global__ __launch_bounds__(ENG_THREADS) void k_eng_eval(Bufs b, const u32 *rt_scan) {
     DevParams *P = b.prm;
     if (!eng_on(P) || P->n_ops > b.ecap) return;
-    __shared__ u32 lds_list[1024];
+    __shared__ u32 lds_list[3 * 1024];  // a barrier's inputs: up to three per participant
     __shared__ u32 lds_n;
     __shared__ u32 lds_jobs[CH_BLK * ENG_JOB_WORDS];
     const u32 D = P->D, ng = P->n_groups;
@@ -873,7 +999,13 @@ hipError_t engine_run(const Bufs &b, const u32 *rt_scan, hipStream_t s) {
         sort_kv(b, k2, v2, &b.prm->n_ral, b.ecap, 4, &b.prm->key_bits, "k_eng_ral_sort", s);
     }
     RD_LAUNCH("k_eng_ral_back", k_eng_ral_back, dim3(grid_over(b.ecap)), dim3(256), 0, s, b);
-    RD_LAUNCH("k_eng_chains", k_eng_chains, dim3(1), dim3(1024), 0, s, b);
+    {
+        const u64 nch = (b.ecap + CHAIN_CHUNK - 1) / CHAIN_CHUNK;
+        const unsigned g = (unsigned)(nch < 1 ? 1 : (nch > 2048 ? 2048 : nch));
+        RD_LAUNCH("k_eng_chain_sums", k_eng_chain_sums, dim3(g), dim3(1024), 0, s, b);
+        RD_LAUNCH("k_eng_chain_carry", k_eng_chain_carry, dim3(1), dim3(1024), 0, s, b);
+        RD_LAUNCH("k_eng_chains", k_eng_chains, dim3(g), dim3(1024), 0, s, b);
+    }
     RD_LAUNCH("k_eng_blk_walk", k_eng_blk_walk, dim3(grid_over(b.ecap, 1024)), dim3(256), 0, s, b);
     // operations and their inputs
     RD_LAUNCH("k_eng_walk", k_eng_walk, dim3(grid_over(b.T)), dim3(256), 0, s, b);
@@ -883,7 +1015,7 @@ hipError_t engine_run(const Bufs &b, const u32 *rt_scan, hipStream_t s) {
     RD_LAUNCH("k_eng_assign", k_eng_assign, dim3(grid_over(b.N)), dim3(256), 0, s, b);
     RD_LAUNCH("k_eng_bk", k_eng_bk, dim3(grid_over(b.B)), dim3(256), 0, s, b);
     RD_LAUNCH("k_eng_deps", k_eng_deps, dim3(grid_over(b.ecap)), dim3(256), 0, s, b);
-    RD_LAUNCH("k_eng_groups", k_eng_groups, dim3(1), dim3(64), 0, s, b);
+    RD_LAUNCH("k_eng_groups", k_eng_groups, dim3(1), dim3(1024), 0, s, b);
     // evaluation: one cooperative launch
     int dev = 0;
     (void)hipGetDevice(&dev);

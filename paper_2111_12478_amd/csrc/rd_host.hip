@@ -1292,6 +1292,43 @@ rd_status rd_autotune(rd_ctx ctx, const rd_trace *traces, uint32_t n, void *batc
     return st;
 }
 
+rd_status rd_trace_stats(rd_ctx ctx, rd_trace trace, rd_stats *out) {
+    if (!ctx || !trace || !out) return RD_EINVAL;
+    if (!trace->checked) return set_err(ctx, RD_ESTATE, UINT64_MAX, "rd_trace_stats before rd_check");
+    if (!trace->ws) return set_err(ctx, RD_ESTATE, UINT64_MAX, "the trace has no workspace of its own");
+    if (hipSetDevice(ctx->device) != hipSuccess) return set_err(ctx, RD_EHIP, UINT64_MAX, "hipSetDevice failed");
+    if (trace->batch) {
+        const rd_status c = rd_check(ctx, trace, trace->batch->stream);  // its own figures
+        if (c != RD_OK) return c;
+    }
+    DevParams prm;
+    if (hipMemcpyAsync(&prm, trace->bufs.prm, sizeof(prm), hipMemcpyDeviceToHost, trace->stream) != hipSuccess ||
+        hipStreamSynchronize(trace->stream) != hipSuccess)
+        return set_err(ctx, RD_EHIP, UINT64_MAX, "reading the check state failed");
+    memset(out, 0, sizeof(*out));
+    out->n_events = trace->n;
+    out->n_accesses = prm.n_acc;
+    for (int k = 0; k < 8; k++) out->kind_count[k] = prm.kind_count[k];
+    out->key_bits = prm.key_bits;
+    out->max_phase = prm.max_phase;
+    out->packed = packed_elements(prm.key_bits, prm.max_phase) ? 1u : 0u;
+    const bool sync = (prm.mode & MODE_SYNC) != 0;
+    const bool par = sync && (prm.eng & ENG_PARALLEL) && !(prm.eng & ENG_FALLBACK);
+    out->engine = !sync ? 0u : (par ? 1u : 2u);
+    if (sync) {
+        out->clock_vectors = par ? prm.n_handles : prm.pool_next;
+        out->clock_words = prm.D;
+        out->clock_bytes = out->clock_vectors * out->clock_words * 4;
+        out->dense_clock_bytes = out->clock_vectors * (u64)trace->bufs.T * 4;
+    }
+    out->engine_ops = par ? prm.n_ops : 0;
+    out->engine_groups = par ? prm.n_groups : 0;
+    out->slow_chunks = prm.n_chunks;
+    out->race_pairs = prm.n_pairs;
+    out->workspace_bytes = trace->plan.L.total;
+    return RD_OK;
+}
+
 rd_status rd_trace_free(rd_ctx ctx, rd_trace trace) {
     if (!ctx || !trace) return RD_EINVAL;
     graph_drop(trace);

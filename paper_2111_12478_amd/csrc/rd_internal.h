@@ -55,6 +55,9 @@ enum : uint8_t {
     SF_REL = 1,       // release (explicit, or an atomic right after a fence)
     SF_ACQ = 2,       // acquire (explicit, or an atomic right before a fence)
     SF_BAD_ARRIVAL = 4,  // warp-barrier arrival with a bad mask
+    SF_NOMAT = 8,     // acquire whose knowledge only its thread's next barrier reads (no access or
+                      // other sync entry but fences in between): a barrier evaluated after it may
+                      // join the acquire's inputs instead of its vector
 };
 
 // error flags (DevParams::err)

@@ -668,10 +668,10 @@ __global__ __launch_bounds__(WG_THREADS) void k_elements(Bufs b, const u64 *acc_
             if (slot[k0 + i] == NONE || j[i] == NONE) continue;
             if (mode & MODE_SYNC) {
                 ph[i] = b.s_phase[j[i]];
-                // the first plain access after an atomic, a fence or a warp barrier (release/acquire
-                // inference, warp-barrier rule)
+                // the first plain access after an atomic, a fence, a warp barrier or a lock acquire
+                // (release/acquire inference, warp-barrier rule, acquires only a barrier reads)
                 const u32 kj = b.s_kind[j[i]], kind = meta[i] & 15u;
-                if (kind <= 1 && (kj == 2 || kj == 3 || kj == 5) && b.s_imin[j[i]] > idx[i])
+                if (kind <= 1 && (kj == 2 || kj == 3 || kj == 5 || kj == 6) && b.s_imin[j[i]] > idx[i])
                     atomicMin(&b.s_imin[j[i]], idx[i]);
             } else {
                 // the thread's list holds only its barriers: the phase is the number of entries
