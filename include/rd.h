@@ -32,7 +32,9 @@
  *   when there is none, the smallest index of an event that breaks a barrier rule.
  *
  * Memory: every device buffer is owned by the caller.  rd_workspace_bytes() sizes one workspace
- * per trace; the library never allocates device memory.
+ * per trace; the library never allocates device memory.  The one exception is the fixed array that
+ * rd_check_static uses as its workspace (RD_STATIC_SCRATCH_BYTES per GPU, part of the library's
+ * code object, held until the process ends).
  *
  * Errors: every call returns an rd_status; nothing throws across this interface.  Errors found on
  * the device during rd_check (trace errors, capacity overflows) are reported by rd_races().
@@ -129,6 +131,33 @@ rd_status rd_check(rd_ctx ctx, rd_trace trace, hipStream_t stream);
  * longer than the last one): entries of `out` past the returned pairs, up to `capacity`, may be
  * overwritten, and so may `out` when an error is returned. */
 rd_status rd_races(rd_ctx ctx, rd_trace trace, rd_pair *out, uint64_t capacity, uint64_t *n_races);
+
+/* For callers that cannot allocate device memory -- code under HIP graph capture, tight serving
+ * loops, harnesses that forbid allocation: rd_trace_upload (events_on_device = 1) + rd_check +
+ * rd_races + rd_trace_free of one trace in one synchronous call, with the workspace taken from a
+ * fixed device array inside the library instead of a caller buffer.  The array is
+ * RD_STATIC_SCRATCH_BYTES on every GPU the library runs on (held until the process ends; its address
+ * is looked up by rd_init); the call allocates nothing (no hipMalloc or hipFree, no graph, no
+ * events, no page-locked staging) and makes no capture of its own.
+ *   events   device memory, n_events records, read during the call;
+ *   limits   as for rd_workspace_bytes (may be NULL), except that a zero clock_bytes means
+ *            RD_STATIC_CLOCK_BYTES here;
+ *   out      host memory for `capacity` pairs (NULL with capacity 0 asks for the count only);
+ *            min(capacity, total) pairs in canonical order, *n_races = total;
+ *   stream   the check runs on it; the call returns when it has ended.
+ * Results and errors are those of the four calls it stands for (RD_ETRACE with the first offending
+ * index in rd_last_error, RD_ETRUNC, ...).  RD_ENOMEM, before anything runs, when the workspace
+ * of such a check (rd_workspace_bytes(grid, n_events, limits as above) less the event copy and
+ * the race-kind scratch it does not need) exceeds RD_STATIC_SCRATCH_BYTES: about 400,000 events
+ * with the default limits.  Every call on one GPU uses that GPU's one array and
+ * leaves its contents behind (the check clears what it needs at its start): calls that overlap on
+ * one GPU -- from other threads or on other streams -- race with each other and give wrong results,
+ * so the caller runs them one at a time per GPU. */
+#define RD_STATIC_SCRATCH_BYTES (128ull << 20)
+#define RD_STATIC_CLOCK_BYTES (8ull << 20)
+rd_status rd_check_static(rd_ctx ctx, const rd_grid *grid, const rd_event *events, uint64_t n_events,
+                          const rd_limits *limits, rd_pair *out, uint64_t capacity, uint64_t *n_races,
+                          hipStream_t stream);
 
 /* One unique race kind: the unordered pair of the two racing accesses' site ids (the records'
  * aux words, site_lo <= site_hi) and the number of racing pairs of that kind.  The paper counts

@@ -105,6 +105,7 @@ def load_library():
             "rd_trace_upload": ([vp, P(rd_grid), vp, u64, ctypes.c_int, vp, u64, P(rd_limits), vp, P(vp)], i32),
             "rd_check": ([vp, vp, vp], i32),
             "rd_races": ([vp, vp, vp, u64, P(u64)], i32),
+            "rd_check_static": ([vp, P(rd_grid), vp, u64, P(rd_limits), vp, u64, P(u64), vp], i32),
             "rd_race_kinds": ([vp, vp, vp, u64, P(u64)], i32),
             "rd_trace_free": ([vp, vp], i32),
             "rd_trace_stats": ([vp, vp, P(rd_stats)], i32),
@@ -196,6 +197,16 @@ def rd_race_kinds(ctx, trace, out_ptr, capacity) -> tuple[int, int]:
 def rd_races(ctx, trace, out_ptr, capacity) -> tuple[int, int]:
     n = ctypes.c_uint64()
     st = load_library().rd_races(ctx, trace, out_ptr, capacity, ctypes.byref(n))
+    return st, n.value
+
+
+def rd_check_static(ctx, grid, events_ptr, n_events, limits, out_ptr, capacity, stream) -> tuple[int, int]:
+    """Check of device-resident events in the library's static scratch array (allocates nothing);
+    pairs into (capacity, 2) uint32 host memory at out_ptr.  Returns (status, total pairs)."""
+    n = ctypes.c_uint64()
+    g = _grid(grid)
+    st = load_library().rd_check_static(ctx, ctypes.byref(g), events_ptr, n_events, _limits(limits), out_ptr,
+                                        capacity, ctypes.byref(n), stream)
     return st, n.value
 
 

@@ -27,7 +27,7 @@ struct Plan {
     u64 partial_words, status_words;
 };
 
-static Plan make_plan(u64 n, u32 nb, u32 tpb, const rd_limits *lim, bool copy_events) {
+static Plan make_plan(u64 n, u32 nb, u32 tpb, const rd_limits *lim, bool copy_events, bool kinds = true) {
     Plan P;
     memset(&P, 0, sizeof(P));
     Layout &L = P.L;
@@ -144,7 +144,9 @@ static Plan make_plan(u64 n, u32 nb, u32 tpb, const rd_limits *lim, bool copy_ev
     {
         const u64 kparts = (max_pairs + 1 + 4095) / 4096 + 16;
         const u64 kbytes = 4 * (8 * max_pairs + kparts + 2);
-        if (pool_bytes >= kbytes) {
+        if (!kinds) {
+            P.off_kinds = 0;  // a workspace that rd_race_kinds never uses
+        } else if (pool_bytes >= kbytes) {
             P.off_kinds = L.off_pool;
         } else {
             P.off_kinds = L.off_ekey[0];
@@ -425,7 +427,7 @@ struct rd_ctx_s {
     u32 sort_variant = 0;  // location-sort variant (rd_set_tuning / rd_autotune)
     std::mutex mu;
     uint64_t last_index;
-    std::string last_msg;
+    char last_msg[192];  // fixed: recording an error allocates nothing
     Profiler prof;
     hipStream_t cap_stream = nullptr;  // where checks are captured into graphs
 };
@@ -558,9 +560,43 @@ static rd_status set_err(rd_ctx ctx, rd_status st, uint64_t index, const char *m
     if (ctx) {
         std::lock_guard<std::mutex> g(ctx->mu);
         ctx->last_index = index;
-        ctx->last_msg = msg ? msg : "";
+        strncpy(ctx->last_msg, msg ? msg : "", sizeof(ctx->last_msg) - 1);
+        ctx->last_msg[sizeof(ctx->last_msg) - 1] = 0;
     }
     return st;
+}
+
+// ---------------------------------------------------------------- checks that allocate nothing
+//
+// rd_check_static's workspace: one fixed array per GPU, reached through the device address that
+// rd_init looks up once per device (the array's name is a host-side stand-in, not that address).
+static_assert(RD_STATIC_SCRATCH_BYTES % 256 == 0, "whole 256-byte units");
+static __device__ __align__(256) unsigned char scratch[RD_STATIC_SCRATCH_BYTES];
+constexpr int MAX_DEVICES = 64;
+static std::mutex g_scratch_mu;
+static char *g_scratch[MAX_DEVICES];  // device address of `scratch` on each device, once looked up
+
+// Looks up the array's address on `dev` (with `dev` current) the first time a context is made
+// there; the calling thread's current device is restored.
+static bool static_scratch_setup(int dev) {
+    if (dev < 0 || dev >= MAX_DEVICES) return true;  // no static path on such a device
+    std::lock_guard<std::mutex> g(g_scratch_mu);
+    if (g_scratch[dev]) return true;
+    int prev = 0;
+    if (hipGetDevice(&prev) != hipSuccess) return false;
+    bool ok = hipSetDevice(dev) == hipSuccess;
+    void *ptr = nullptr;
+    if (ok && hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)) == hipSuccess && ptr) g_scratch[dev] = (char *)ptr;
+    else ok = false;
+    (void)hipGetLastError();
+    (void)hipSetDevice(prev);
+    return ok;
+}
+
+static char *static_scratch(int dev) {
+    if (dev < 0 || dev >= MAX_DEVICES) return nullptr;
+    std::lock_guard<std::mutex> g(g_scratch_mu);
+    return g_scratch[dev];
 }
 
 static bool grid_ok(const rd_grid *g, uint64_t n) {
@@ -578,10 +614,12 @@ rd_status rd_init(int hip_device, rd_ctx *out) {
     *out = nullptr;
     int n = 0;
     if (hipGetDeviceCount(&n) != hipSuccess || hip_device < 0 || hip_device >= n) return RD_EINVAL;
+    if (!static_scratch_setup(hip_device)) return RD_EHIP;
     rd_ctx c = new (std::nothrow) rd_ctx_s;
     if (!c) return RD_ENOMEM;
     c->device = hip_device;
     c->last_index = UINT64_MAX;
+    c->last_msg[0] = 0;
     *out = c;
     return RD_OK;
 }
@@ -935,6 +973,35 @@ rd_status rd_races(rd_ctx ctx, rd_trace trace, rd_pair *out, uint64_t capacity, 
         if (c != RD_OK) return c;
     }
     return plain_races(ctx, trace->bufs, trace->stream, out, capacity, n_races, &trace->last_pairs, &trace->stage);
+}
+
+rd_status rd_check_static(rd_ctx ctx, const rd_grid *grid, const rd_event *events, uint64_t n_events,
+                          const rd_limits *limits, rd_pair *out, uint64_t capacity, uint64_t *n_races,
+                          hipStream_t stream) {
+    if (!ctx || !n_races || (capacity && !out)) return RD_EINVAL;
+    *n_races = 0;
+    if (!grid_ok(grid, n_events)) return set_err(ctx, RD_EINVAL, UINT64_MAX, "bad grid or event count");
+    if (n_events && !events) return set_err(ctx, RD_EINVAL, UINT64_MAX, "null events");
+    char *ws = static_scratch(ctx->device);
+    if (!ws) return set_err(ctx, RD_EHIP, UINT64_MAX, "no device address for the static scratch array");
+    rd_limits lim = limits ? *limits : rd_limits{0, 0};
+    if (!lim.clock_bytes) lim.clock_bytes = RD_STATIC_CLOCK_BYTES;
+    const Plan P = make_plan(n_events, grid->n_blocks, grid->threads_per_block, &lim, false, false);
+    if (P.L.total > RD_STATIC_SCRATCH_BYTES)
+        return set_err(ctx, RD_ENOMEM, UINT64_MAX, "the trace needs more than the static scratch array");
+    if (hipSetDevice(ctx->device) != hipSuccess) return set_err(ctx, RD_EHIP, UINT64_MAX, "hipSetDevice failed");
+    const u32 wsz = grid->warp_size ? grid->warp_size : 32;
+    Bufs b = make_bufs(P, ws, n_events ? (const void *)events : (const void *)ws, n_events, grid->n_blocks,
+                       grid->threads_per_block, wsz);
+    b.sort_variant = ctx->sort_variant;
+    b.radix_bits = kSortVariants[ctx->sort_variant].rb;
+    // launched kernel by kernel on the caller's stream: no graph, no profiling events
+    Profiler *saved = g_prof;
+    g_prof = nullptr;
+    const hipError_t e = enqueue_plain(b, (u64 *)(ws + P.off_masks), (u32 *)(ws + P.off_rt_scan), stream);
+    g_prof = saved;
+    if (e != hipSuccess) return set_err(ctx, RD_EHIP, UINT64_MAX, hipGetErrorString(e));
+    return plain_races(ctx, b, stream, out, capacity, n_races, nullptr, nullptr);
 }
 
 rd_status rd_race_kinds(rd_ctx ctx, rd_trace trace, rd_race_kind *out, uint64_t capacity, uint64_t *n_kinds) {
@@ -1382,7 +1449,7 @@ rd_status rd_last_error(rd_ctx ctx, uint64_t *event_index, char *msg, uint64_t m
     std::lock_guard<std::mutex> g(ctx->mu);
     if (event_index) *event_index = ctx->last_index;
     if (msg && msg_len) {
-        strncpy(msg, ctx->last_msg.c_str(), msg_len - 1);
+        strncpy(msg, ctx->last_msg, msg_len - 1);
         msg[msg_len - 1] = 0;
     }
     return RD_OK;
