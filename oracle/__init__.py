@@ -18,6 +18,7 @@ computations of the race report:
   and H clocks, Acq/Rel queues, locksets and lock-location clocks), dense clocks.
 * :func:`gwcp_bruteforce` -- GWCP's definition (rules (i)-(iv)) as a fixpoint over event pairs;
   tiny traces only.
+* :func:`lockset` -- the lockset pass the paper describes for ScoRD (Section 2.2, Section 3).
 
 Traces are ``(N, 4)`` uint32 arrays of records ``(addr, tid, meta, aux)``; pairs come back as an
 ``(M, 2)`` uint32 array of trace indices ``(first, second)``, first < second, sorted.
@@ -69,6 +70,8 @@ def _load():
         lib.orc_gwcp.restype = i32
         lib.orc_gwcp_bruteforce.argtypes = [u32, u32, u32, vp, u64, ctypes.POINTER(u64), ctypes.POINTER(OraclePairs)]
         lib.orc_gwcp_bruteforce.restype = i32
+        lib.orc_lockset.argtypes = [u32, u32, u32, vp, u64, ctypes.POINTER(u64), ctypes.POINTER(OraclePairs)]
+        lib.orc_lockset.restype = i32
         lib.orc_validate.argtypes = [u32, u32, u32, vp, u64, ctypes.POINTER(u64)]
         lib.orc_validate.restype = i32
         lib.orc_pairs_free.argtypes = [ctypes.POINTER(OraclePairs)]
@@ -154,6 +157,19 @@ def gwcp_bruteforce(grid, events) -> OracleResult:
     bad = ctypes.c_uint64(0)
     out = OraclePairs()
     rc = lib.orc_gwcp_bruteforce(nb, tpb, ws, ev.ctypes.data, ev.shape[0], ctypes.byref(bad), ctypes.byref(out))
+    return OracleResult(rc, _bad(bad.value), _take_pairs(lib, out))
+
+
+def lockset(grid, events) -> OracleResult:
+    """The lockset pass of Section 2.2 / Section 3 (ScoRD after Eraser): each access against its
+    location's previous access, reported when they conflict, one of them holds a lock and no lock
+    is common to both."""
+    lib = _load()
+    ev = _events(events)
+    nb, tpb, ws = (list(grid) + [32])[:3]
+    bad = ctypes.c_uint64(0)
+    out = OraclePairs()
+    rc = lib.orc_lockset(nb, tpb, ws, ev.ctypes.data, ev.shape[0], ctypes.byref(bad), ctypes.byref(out))
     return OracleResult(rc, _bad(bad.value), _take_pairs(lib, out))
 
 

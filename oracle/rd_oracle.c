@@ -1621,3 +1621,106 @@ int orc_gwcp_bruteforce(uint32_t n_blocks, uint32_t tpb, uint32_t warp_size, con
     qsort(out->data, out->n, 2 * sizeof(uint32_t), cmp_pair);
     return ORC_OK;
 }
+
+/* ================================================================ lockset pass (Section 2.2, Section 3)
+ *
+ * The lockset analysis the paper describes for ScoRD (after Eraser): every access carries the set
+ * of locks its thread holds at it; the shadow of a location keeps its previous access, and each
+ * access is compared with that one.  The paper states when ScoRD reports: a pair whose locksets
+ * share no lock (Figure 3: the lockset at e6 holds l, the one at e1 is empty, so the race is
+ * reported), except that the analysis is skipped when neither access holds a lock (Figure 4 and
+ * Figure 5: both accesses unprotected, nothing reported).
+ *
+ *   orc_lockset  walks the trace in order with per-thread locksets and per-location previous
+ *                accesses, and reports (previous, current) for every access that
+ *                  - conflicts with the location's previous access (conflict() above),
+ *                  - where at least one of the two holds a lock,
+ *                  - and no lock word is held by both with overlapping scope keys.
+ *
+ * Readings (each also listed in the design notes):
+ *   L1 a lock held is a critical section of reading G1 that is open at the access, with the scope
+ *      key of its acquire (G4); lock operations (explicit or inferred acquires and releases) are not
+ *      compared and do not become a location's previous access: they are the locks;
+ *   L2 the previous access is the location's latest earlier access other than a lock operation,
+ *      whatever its thread (one shadow entry per location; a pair of one thread is never reported);
+ *   L3 two locksets share a lock when one word is held in both with keys that overlap (either is
+ *      device scoped, or both in one block).
+ */
+#define LS_NEST 64 /* nesting kept per access (a deeper trace is refused with ORC_ENOMEM) */
+typedef struct { uint32_t n; uint64_t word[LS_NEST]; uint32_t key[LS_NEST]; } lockset_t;
+
+static int locksets_share(const lockset_t *a, const lockset_t *b) {
+    for (uint32_t i = 0; i < a->n; i++)
+        for (uint32_t j = 0; j < b->n; j++)
+            if (a->word[i] == b->word[j] && keys_overlap(a->key[i], b->key[j])) return 1;
+    return 0;
+}
+
+int orc_lockset(uint32_t n_blocks, uint32_t tpb, uint32_t warp_size, const orc_event *ev, uint64_t n,
+                uint64_t *bad, orc_pairs *out) {
+    memset(out, 0, sizeof(*out));
+    *bad = UINT64_MAX;
+    if (!grid_ok(n_blocks, tpb, &warp_size, n)) return ORC_EINVAL;
+    prep_t p;
+    int rc = prepare(&p, n_blocks, tpb, warp_size, ev, n, bad);
+    if (rc != ORC_OK) { prep_free(&p); return rc; }
+    cs_info C;
+    rc = cs_build(&p, &C);
+    if (rc != ORC_OK) { prep_free(&p); return rc; }
+    const uint32_t T = p.n_threads;
+    lockset_t *held = (lockset_t *)calloc(T ? T : 1, sizeof(lockset_t));  /* per thread, open sections */
+    hmap lmap = {0};
+    uint32_t L = 0;
+    uint32_t *prev = NULL;       /* per location: previous access (UINT32_MAX: none) */
+    lockset_t *prev_ls = NULL;   /* ... and its lockset */
+    if (!held || hmap_init(&lmap, n) != ORC_OK) rc = ORC_ENOMEM;
+    uint64_t n_loc = 0;
+    for (uint64_t i = 0; i < n && rc == ORC_OK; i++) n_loc += is_access(kind_of(&ev[i])) && !is_lockop(&p, (uint32_t)i);
+    if (rc == ORC_OK) {
+        prev = (uint32_t *)malloc((n_loc ? n_loc : 1) * sizeof(uint32_t));
+        prev_ls = (lockset_t *)malloc((n_loc ? n_loc : 1) * sizeof(lockset_t));
+        if (!prev || !prev_ls) rc = ORC_ENOMEM;
+    }
+    for (uint64_t ii = 0; ii < n && rc == ORC_OK; ii++) {
+        const uint32_t i = (uint32_t)ii, t = ev[i].tid;
+        if (is_lockop(&p, i)) {
+            /* a release closes the section it closes (reading G1), then an acquire opens one */
+            lockset_t *h = &held[t];
+            const uint32_t cc = C.close_cs[i], oc = C.open_cs[i];
+            if (cc != UINT32_MAX) {
+                for (uint32_t q = 0; q < h->n; q++)
+                    if (h->word[q] == C.cs[cc].word) {
+                        memmove(&h->word[q], &h->word[q + 1], (h->n - q - 1) * sizeof(uint64_t));
+                        memmove(&h->key[q], &h->key[q + 1], (h->n - q - 1) * sizeof(uint32_t));
+                        h->n--;
+                        break;
+                    }
+            }
+            if (oc != UINT32_MAX) {
+                if (h->n == LS_NEST) { rc = ORC_ENOMEM; break; }
+                h->word[h->n] = C.cs[oc].word;
+                h->key[h->n] = C.cs[oc].acq_key;
+                h->n++;
+            }
+            continue;
+        }
+        if (!is_access(kind_of(&ev[i]))) continue;
+        int ins;
+        const uint32_t x = hmap_get(&lmap, loc_key(&p, &ev[i]), L, &ins);
+        if (ins) { prev[x] = UINT32_MAX; L++; }
+        const uint32_t a = prev[x];
+        if (a != UINT32_MAX && conflict(&p, a, i) && (prev_ls[x].n || held[t].n) &&
+            !locksets_share(&prev_ls[x], &held[t])) {
+            if (pairs_push(out, a, i) != ORC_OK) { rc = ORC_ENOMEM; break; }
+        }
+        prev[x] = i;
+        prev_ls[x] = held[t];
+    }
+    free(held); free(prev); free(prev_ls);
+    hmap_free(&lmap);
+    cs_free(&C);
+    prep_free(&p);
+    if (rc != ORC_OK) { orc_pairs_free(out); return rc; }
+    qsort(out->data, out->n, 2 * sizeof(uint32_t), cmp_pair);
+    return ORC_OK;
+}
