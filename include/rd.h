@@ -177,6 +177,25 @@ typedef struct {
  * one is checked alone first). */
 rd_status rd_race_kinds(rd_ctx ctx, rd_trace trace, rd_race_kind *out, uint64_t capacity, uint64_t *n_kinds);
 
+/* The lockset pass the paper describes for ScoRD (Section 2.2, Section 3; Eraser's analysis), a
+ * second workload over the same trace.  Every access carries the locks its thread holds at it: an
+ * acquire (explicit, or an atomic right before a fence) of a word the thread does not hold opens a
+ * critical section with the acquire's scope, the thread's next release of that word closes it.
+ * Each access that is not a lock operation is compared with the previous such access of its
+ * location in trace order, and the pair (previous, current) is reported when they conflict, at
+ * least one of the two holds a lock, and no word is held by both with overlapping scopes (either
+ * device/system scoped, or both in one block).  Unlike the happens-before report this is a
+ * heuristic: it misses races of two unprotected accesses and flags correctly published data read
+ * under a lock.
+ * Runs a check of the trace and the pass on the trace's stream and waits: min(capacity, total)
+ * pairs, sorted, into `out` (host memory; NULL with capacity 0 for the count), *n_pairs = total.
+ * The pass keeps its tables in the trace's knowledge-vector pool (24 bytes per rd_limits.max_pairs
+ * pair, 516 bytes per lock operation).  Errors: those of the check (RD_ETRACE ...), RD_ENOMEM when a
+ * thread holds more than 64 locks at once, the pool is too small, or the pairs exceed max_pairs,
+ * RD_ETRUNC when capacity < total, RD_ESTATE for a trace bound without a workspace.  Afterwards
+ * rd_races returns that check's report. */
+rd_status rd_lockset(rd_ctx ctx, rd_trace trace, rd_pair *out, uint64_t capacity, uint64_t *n_pairs);
+
 /* Batched form (the same check, many traces per pass).  The members are independent traces, each
  * bound by rd_trace_upload to its own workspace as for rd_check.  rd_check_many enqueues one pass
  * of the pipeline over their concatenation: every trace keeps its own blocks, threads and words

@@ -107,6 +107,7 @@ def load_library():
             "rd_races": ([vp, vp, vp, u64, P(u64)], i32),
             "rd_check_static": ([vp, P(rd_grid), vp, u64, P(rd_limits), vp, u64, P(u64), vp], i32),
             "rd_race_kinds": ([vp, vp, vp, u64, P(u64)], i32),
+            "rd_lockset": ([vp, vp, vp, u64, P(u64)], i32),
             "rd_trace_free": ([vp, vp], i32),
             "rd_trace_stats": ([vp, vp, P(rd_stats)], i32),
             "rd_batch_workspace_bytes": ([vp, P(vp), u32, P(rd_limits), P(u64)], i32),
@@ -191,6 +192,14 @@ def rd_race_kinds(ctx, trace, out_ptr, capacity) -> tuple[int, int]:
     count) at out_ptr.  Returns (status, total kinds)."""
     n = ctypes.c_uint64()
     st = load_library().rd_race_kinds(ctx, trace, out_ptr, capacity, ctypes.byref(n))
+    return st, n.value
+
+
+def rd_lockset(ctx, trace, out_ptr, capacity) -> tuple[int, int]:
+    """The lockset pass over a bound trace: pairs into (capacity, 2) uint32 host memory at out_ptr.
+    Returns (status, total pairs)."""
+    n = ctypes.c_uint64()
+    st = load_library().rd_lockset(ctx, trace, out_ptr, capacity, ctypes.byref(n))
     return st, n.value
 
 
@@ -384,9 +393,11 @@ class RaceChecker:
             self.ctx = None
 
     def __del__(self):
-        if sys.is_finalizing():
-            return
+        # during interpreter shutdown (module globals may already be gone) no HIP call is made: the
+        # exit handler has closed the context while the runtime was alive
         try:
+            if sys.is_finalizing():
+                return
             self.close()
         except Exception:
             pass
@@ -487,6 +498,19 @@ class RaceChecker:
         out = np.zeros((max(capacity, 1), 3), dtype=np.uint32)
         st, n = rd_race_kinds(self.ctx, trace, out.ctypes.data if capacity else None, capacity)
         return st, out[: min(capacity, n)].copy()
+
+    def lockset(self, trace):
+        """The lockset pass over a bound trace: CheckResult with the sorted pairs."""
+        st, n = rd_lockset(self.ctx, trace, None, 0)
+        if st not in (RD_OK, RD_ETRUNC):
+            idx, msg = rd_last_error(self.ctx)
+            return CheckResult(st, np.zeros((0, 2), np.uint32), idx, msg)
+        out = np.zeros((max(n, 1), 2), dtype=np.uint32)
+        st, n = rd_lockset(self.ctx, trace, out.ctypes.data, n)
+        if st != RD_OK:
+            idx, msg = rd_last_error(self.ctx)
+            return CheckResult(st, np.zeros((0, 2), np.uint32), idx, msg)
+        return CheckResult(st, out[:n].copy())
 
     def report_many(self, traces):
         """Reports of several checked traces through rd_races_many (one transfer per batch); a member

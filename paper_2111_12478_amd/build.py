@@ -10,8 +10,10 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "librd.so")
+DEMO_LIB = os.path.join(HERE, "librd_demo.so")
+DEMO_SOURCE = "rd_demo.hip"
 SOURCES = ["rd_prep.hip", "rd_sort.hip", "rd_interp.hip", "rd_engine.hip", "rd_segcheck.hip", "rd_batch.hip", "rd_host.hip",
-           "rd_server.hip", "rd_kinds.hip"]
+           "rd_server.hip", "rd_kinds.hip", "rd_lockset.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [
     "--offload-arch=gfx950", "-O3", "-fPIC", "-std=c++17",
@@ -30,11 +32,16 @@ def _compile(src: str) -> str:
 
 def build() -> str:
     os.makedirs(BUILD, exist_ok=True)
-    with cf.ThreadPoolExecutor(max_workers=min(8, len(SOURCES))) as ex:
-        objs = list(ex.map(_compile, SOURCES))
+    with cf.ThreadPoolExecutor(max_workers=min(8, len(SOURCES) + 1)) as ex:
+        objs = list(ex.map(_compile, SOURCES + [DEMO_SOURCE]))
+    demo_obj = objs.pop()
     tmp = LIB + ".tmp"
     subprocess.check_call([HIPCC, "--offload-arch=gfx950", "-shared", "-o", tmp, *objs])
     os.replace(tmp, LIB)
+    # the example kernels recorded with include/rd_device.h, a library of their own
+    tmp = DEMO_LIB + ".tmp"
+    subprocess.check_call([HIPCC, "--offload-arch=gfx950", "-shared", "-o", tmp, demo_obj])
+    os.replace(tmp, DEMO_LIB)
     return LIB
 
 

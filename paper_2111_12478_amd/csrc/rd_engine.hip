@@ -27,6 +27,8 @@ constexpr u32 BK_MARK = 0x80000000u;  // e_cur: the block's knowledge after (val
 constexpr u32 OP_SKIPPED = 0xfffffffeu;  // op_dep during evaluation: the operation wrote no vector
 constexpr u32 ENG_WIDE = 16;          // groups with at least this many operations run on every workgroup
 constexpr u32 ENG_THREADS = 512;
+constexpr u32 CH_BLK = 128;                  // operations whose jobs a window replay stages at once
+constexpr u32 CH_BLK_JOBS = 3 * CH_BLK;      // three job slots per operation
 constexpr u32 ENG_SPIN = 1u << 19;  // ~1 s of polling: far above any legitimate wait
 
 __device__ inline bool eng_active(const DevParams *P) {
@@ -769,122 +771,109 @@ __device__ inline u32 first_handle(const Bufs &b, u32 o) {
 }
 
 // Second phase of a window.  Every output column of every operation depends only on the same
-// column of its inputs, so each thread owns 16-byte column slices and replays the window's jobs
-// in order over its slices: no barrier between operations, the chain's latest outputs stay in
-// registers, and the partial results of the next CH_NB operations are loaded ahead.
+// column of its inputs, so a workgroup owns a slice of 64 columns and its first wavefront replays
+// the window's jobs in order over them, one column per lane: no barrier between operations, the
+// latest outputs stay in registers.  For each block of CH_BLK operations the workgroup stages their
+// jobs in LDS (one coalesced read), compacts the ones with inputs from the window, in order, and
+// loads all of their partial results for the slice into LDS with every lane before the replay.
 
 __device__ inline u32 uni(u32 x) { return __builtin_amdgcn_readfirstlane(x); }
-__device__ inline uint4 uni4(uint4 v) { return make_uint4(uni(v.x), uni(v.y), uni(v.z), uni(v.w)); }
 
 // The latest four outputs of the replay (newest first); handle 0 is the empty vector.
 struct ChainCache {
     u32 h0, h1, h2, h3;
-    uint4 v0, v1, v2, v3;
+    u32 v0, v1, v2, v3;
 };
 
-__device__ __attribute__((always_inline)) inline uint4 chain_get(const ChainCache &C, const uint4 *pool4, u32 D4,
-                                                                 u32 i, u32 h) {
+__device__ __attribute__((always_inline)) inline u32 chain_get(const ChainCache &C, const u32 *pool, u32 D, u32 col,
+                                                               u32 h) {
     // h is the same in every lane: the branches are uniform
     if (h == C.h0) return C.v0;
     if (h == C.h1) return C.v1;
     if (h == C.h2) return C.v2;
     if (h == C.h3) return C.v3;
-    return pool4[(u64)h * D4 + i];
+    return pool[(u64)h * D + col];
 }
 
-__device__ __attribute__((always_inline)) inline void chain_put(ChainCache &C, u32 h, uint4 v) {
+__device__ __attribute__((always_inline)) inline void chain_put(ChainCache &C, u32 h, u32 v) {
     C.h3 = C.h2; C.v3 = C.v2;
     C.h2 = C.h1; C.v2 = C.v1;
     C.h1 = C.h0; C.v1 = C.v0;
     C.h0 = h; C.v0 = v;
 }
 
-struct ChainJob {
-    uint4 q;     // (out, in0, in1, in2); out 0: no job
-    u32 lo, ln;  // window input list range (barrier outputs)
-    bool act;    // has inputs from the window
+// One job with inputs from the window: output handle, up to three input handles, and for a
+// barrier a range of the window input list.
+struct ChainLds {
+    uint4 q[CH_BLK_JOBS];
+    uint2 l[CH_BLK_JOBS];
+    u32 wave_n[ENG_THREADS / 64];
+    u32 n;
 };
 
-__device__ __attribute__((always_inline)) inline ChainJob chain_job(const u32 *jb, u32 k, bool in) {
-    ChainJob J;
-    J.q = uni4(in ? ((const uint4 *)jb)[k] : make_uint4(0, 0, 0, 0));
-    const uint4 l = in && k == 0 ? ((const uint4 *)jb)[3] : make_uint4(0, 0, 0, 0);
-    J.lo = uni(l.x);
-    J.ln = uni(l.y);
-    J.act = J.q.x && (J.q.y | J.q.z | J.q.w | J.ln);
-    return J;
+__device__ __attribute__((always_inline)) inline void chain_run(ChainCache &C, uint4 q, uint2 l, u32 v,
+                                                                const u32 *list, u32 *pool, u32 D, u32 col,
+                                                                bool mine) {
+    q = make_uint4(uni(q.x), uni(q.y), uni(q.z), uni(q.w));
+    if (q.y) v = max(v, chain_get(C, pool, D, col, q.y));
+    if (q.z) v = max(v, chain_get(C, pool, D, col, q.z));
+    if (q.w) v = max(v, chain_get(C, pool, D, col, q.w));
+    const u32 lo = uni(l.x), ln = uni(l.y);
+    for (u32 k = 0; k < ln; k++) v = max(v, chain_get(C, pool, D, col, uni(list[lo + k])));
+    if (mine) pool[(u64)q.x * D + col] = v;
+    chain_put(C, q.x, v);
 }
 
-__device__ __attribute__((always_inline)) inline uint4 chain_part(const ChainJob &J, const uint4 *pool4, u32 D4,
-                                                                  u32 i) {
-    return J.act ? pool4[(u64)J.q.x * D4 + i] : make_uint4(0, 0, 0, 0);
-}
-
-__device__ __attribute__((always_inline)) inline void chain_run(ChainCache &C, const ChainJob &J, uint4 v,
-                                                                const u32 *list, uint4 *pool4, u32 D4, u32 i) {
-    if (!J.act) return;
-    if (J.q.y) v = max4(v, chain_get(C, pool4, D4, i, J.q.y));
-    if (J.q.z) v = max4(v, chain_get(C, pool4, D4, i, J.q.z));
-    if (J.q.w) v = max4(v, chain_get(C, pool4, D4, i, J.q.w));
-    for (u32 l = 0; l < J.ln; l++) v = max4(v, chain_get(C, pool4, D4, i, uni(list[J.lo + l])));
-    pool4[(u64)J.q.x * D4 + i] = v;
-    chain_put(C, J.q.x, v);
-}
-
-// The workgroup stages the jobs of CH_BLK operations in LDS at once (one coalesced read); each
-// step then takes four operations, their partial results loaded together.
-constexpr u32 CH_BLK = 128;
-
-__device__ void chain_window(const Bufs &b, u32 w0, u32 w1, u32 D4, u32 *lj /* CH_BLK * ENG_JOB_WORDS */) {
+__device__ void chain_window(const Bufs &b, u32 w0, u32 w1, u32 D, u32 *lj /* CH_BLK * ENG_JOB_WORDS */,
+                             ChainLds &A, u32 *part /* CH_BLK_JOBS * 64 */) {
     const u32 *jobs = b.eng_jobs, *list = b.eng_jobs + ENG_WIN * ENG_JOB_WORDS;
-    uint4 *pool4 = (uint4 *)b.pool;
+    u32 *pool = b.pool;
     const bool reporter = blockIdx.x == 0 && threadIdx.x == 0;
-    const uint4 z = make_uint4(0, 0, 0, 0);
-    // the slices of a workgroup's threads, in rounds every thread of the workgroup takes (the LDS
-    // staging needs them all at its barriers); threads past the last slice only help stage
-    for (u32 base = blockIdx.x * ENG_THREADS; base < D4; base += gridDim.x * ENG_THREADS) {
-        const u32 i = base + threadIdx.x;
-        const bool mine = i < D4;
-        const u32 ii = mine ? i : 0u;
-        ChainCache C = {0, 0, 0, 0, z, z, z, z};
+    const u32 lane = lane_id(), wave = threadIdx.x >> 6, nsl = (D + 63) / 64;
+    for (u32 sl = blockIdx.x; sl < nsl; sl += gridDim.x) {
+        const u32 col = sl * 64 + lane;
+        const bool mine = col < D;
+        const u32 cc = mine ? col : 0u;
+        ChainCache C = {0, 0, 0, 0, 0, 0, 0, 0};
         for (u32 cb = w0; cb < w1; cb += CH_BLK) {
             const u32 ce = min(cb + CH_BLK, w1);
             __syncthreads();
             for (u32 x = threadIdx.x; x < (ce - cb) * ENG_JOB_WORDS; x += ENG_THREADS)
                 lj[x] = jobs[(u64)(cb - w0) * ENG_JOB_WORDS + x];
             __syncthreads();
-            for (u32 o = cb; o < ce; o += 4) {
-                const u32 *ja = lj + (o - cb) * ENG_JOB_WORDS, *jb = ja + ENG_JOB_WORDS, *jc = jb + ENG_JOB_WORDS,
-                          *jd = jc + ENG_JOB_WORDS;
-                const bool inb = o + 1 < ce, inc = o + 2 < ce, ind = o + 3 < ce;
-                const ChainJob a0 = chain_job(ja, 0, true), a1 = chain_job(ja, 1, true), a2 = chain_job(ja, 2, true);
-                const ChainJob b0 = chain_job(jb, 0, inb), b1 = chain_job(jb, 1, inb), b2 = chain_job(jb, 2, inb);
-                const ChainJob c0 = chain_job(jc, 0, inc), c1 = chain_job(jc, 1, inc), c2 = chain_job(jc, 2, inc);
-                const ChainJob d0 = chain_job(jd, 0, ind), d1 = chain_job(jd, 1, ind), d2 = chain_job(jd, 2, ind);
-                if (mine) {
-                    const uint4 pa0 = chain_part(a0, pool4, D4, ii), pa1 = chain_part(a1, pool4, D4, ii),
-                                pa2 = chain_part(a2, pool4, D4, ii);
-                    const uint4 pb0 = chain_part(b0, pool4, D4, ii), pb1 = chain_part(b1, pool4, D4, ii),
-                                pb2 = chain_part(b2, pool4, D4, ii);
-                    const uint4 pc0 = chain_part(c0, pool4, D4, ii), pc1 = chain_part(c1, pool4, D4, ii),
-                                pc2 = chain_part(c2, pool4, D4, ii);
-                    const uint4 pd0 = chain_part(d0, pool4, D4, ii), pd1 = chain_part(d1, pool4, D4, ii),
-                                pd2 = chain_part(d2, pool4, D4, ii);
-                    chain_run(C, a0, pa0, list, pool4, D4, ii);
-                    chain_run(C, a1, pa1, list, pool4, D4, ii);
-                    chain_run(C, a2, pa2, list, pool4, D4, ii);
-                    chain_run(C, b0, pb0, list, pool4, D4, ii);
-                    chain_run(C, b1, pb1, list, pool4, D4, ii);
-                    chain_run(C, b2, pb2, list, pool4, D4, ii);
-                    chain_run(C, c0, pc0, list, pool4, D4, ii);
-                    chain_run(C, c1, pc1, list, pool4, D4, ii);
-                    chain_run(C, c2, pc2, list, pool4, D4, ii);
-                    chain_run(C, d0, pd0, list, pool4, D4, ii);
-                    chain_run(C, d1, pd1, list, pool4, D4, ii);
-                    chain_run(C, d2, pd2, list, pool4, D4, ii);
-                }
-                if (reporter) atomicAdd(&b.prm->gprog, 1u);
+            // jobs with inputs from the window, in (operation, slot) order
+            const u32 x = threadIdx.x;  // job x = operation cb + x / 3, slot x % 3
+            bool act = false;
+            uint4 q = make_uint4(0, 0, 0, 0);
+            uint2 l = make_uint2(0, 0);
+            if (x < (ce - cb) * 3) {
+                const u32 *jo = lj + (x / 3) * ENG_JOB_WORDS;
+                q = ((const uint4 *)jo)[x % 3];
+                if (x % 3 == 0) l = make_uint2(jo[12], jo[13]);
+                act = q.x && (q.y | q.z | q.w | l.y);
             }
+            const u64 m = ballot(act);
+            if (lane == 0) A.wave_n[wave] = (u32)__builtin_popcountll(m);
+            __syncthreads();
+            u32 off = 0;
+            for (u32 w = 0; w < wave; w++) off += A.wave_n[w];
+            if (act) {
+                const u32 r = off + (u32)__builtin_popcountll(m & lanemask_lt());
+                A.q[r] = q;
+                A.l[r] = l;
+            }
+            if (threadIdx.x == ENG_THREADS - 1) A.n = off + (u32)__builtin_popcountll(m);
+            __syncthreads();
+            const u32 n = A.n;
+            // the partial results of the slice, every lane loading
+            for (u32 e = threadIdx.x; e < n * 64; e += ENG_THREADS) {
+                const u32 c = sl * 64 + (e & 63u);
+                part[e] = c < D ? pool[(u64)A.q[e >> 6].x * D + c] : 0u;
+            }
+            __syncthreads();
+            if (wave == 0)
+                for (u32 k = 0; k < n; k++) chain_run(C, A.q[k], A.l[k], part[k * 64 + lane], list, pool, D, cc, mine);
+            if (reporter) atomicAdd(&b.prm->gprog, 1u);
         }
     }
 }
@@ -910,6 +899,24 @@ __device__ inline void grid_barrier(DevParams *P, u32 round) {
     __syncthreads();
 }
 
+// The end of the run of small groups that starts at group g: the first later group with at least
+// ENG_WIDE operations, or ng.  The workgroup looks at ENG_THREADS groups at a time (a lock handed
+// through thousands of critical sections is one run of thousands of groups).
+__device__ inline u32 small_run_end(const Bufs &b, u32 g, u32 ng, u32 *lds) {
+    for (u32 base = g + 1; base < ng; base += ENG_THREADS) {
+        const u32 x = base + threadIdx.x;
+        const bool wide = x < ng && b.grp[x + 1] - b.grp[x] >= ENG_WIDE;
+        if (threadIdx.x == 0) *lds = NONE;
+        __syncthreads();
+        if (wide) atomicMin(lds, x);
+        __syncthreads();
+        const u32 f = *lds;
+        __syncthreads();
+        if (f != NONE) return f;
+    }
+    return ng;
+}
+
 // Cooperative: every workgroup runs the same group loop.  A wide group spreads its operations over
 // the workgroups; a run of small groups is evaluated in windows of two phases (above).
 __global__ __launch_bounds__(ENG_THREADS) void k_eng_eval(Bufs b, const u32 *rt_scan) {
@@ -918,6 +925,8 @@ __global__ __launch_bounds__(ENG_THREADS) void k_eng_eval(Bufs b, const u32 *rt_
     __shared__ u32 lds_list[3 * 1024];  // a barrier's inputs: up to three per participant
     __shared__ u32 lds_n;
     __shared__ u32 lds_jobs[CH_BLK * ENG_JOB_WORDS];
+    __shared__ ChainLds lds_chain;
+    __shared__ u32 lds_part[CH_BLK_JOBS * 64];
     const u32 D = P->D, ng = P->n_groups;
     u32 round = 0;
     if (blockIdx.x == 0) {
@@ -937,8 +946,7 @@ __global__ __launch_bounds__(ENG_THREADS) void k_eng_eval(Bufs b, const u32 *rt_
             grid_barrier(P, ++round);
             continue;
         }
-        u32 g2 = g + 1;
-        while (g2 < ng && b.grp[g2 + 1] - b.grp[g2] < ENG_WIDE) g2++;
+        const u32 g2 = small_run_end(b, g, ng, &lds_n);
         const u32 end = b.grp[g2];
         for (u32 w0 = g0; w0 < end; w0 += ENG_WIN) {
             const u32 w1 = min(w0 + ENG_WIN, end);
@@ -954,7 +962,7 @@ __global__ __launch_bounds__(ENG_THREADS) void k_eng_eval(Bufs b, const u32 *rt_
                 eval_op(b, rt_scan, o, D, lds_list, &lds_n, hint, js);
             }
             grid_barrier(P, ++round);
-            chain_window(b, w0, w1, D / 4, lds_jobs);
+            chain_window(b, w0, w1, D, lds_jobs, lds_chain, lds_part);
             if (blockIdx.x == 0 && threadIdx.x == 0) P->wlist = 0;  // the next window's list starts empty
             grid_barrier(P, ++round);
         }

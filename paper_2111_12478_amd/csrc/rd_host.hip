@@ -398,10 +398,12 @@ hipError_t enqueue_check(const Bufs &b, u64 *masks, u32 *rt_scan, hipStream_t s)
     prep_elements(b, acc_mask, s);
     prep_thread_sync(b, rt_scan, s);
     sort_elements(b, s);
-    const hipError_t e = engine_run(b, rt_scan, s);
-    if (e != hipSuccess) return e;
-    interp_run(b, rt_scan, s);
-    prep_validate_wbar(b, s);
+    if (!(b.spec & SPEC_NO_SYNC)) {
+        const hipError_t e = engine_run(b, rt_scan, s);
+        if (e != hipSuccess) return e;
+        interp_run(b, rt_scan, s);
+    }
+    if (!(b.spec & (SPEC_NO_SYNC | SPEC_NO_WBAR))) prep_validate_wbar(b, s);
     segcheck_run(b, rt_scan, s);
     return hipGetLastError();
 }
@@ -500,6 +502,8 @@ struct rd_trace_s {
     // the plain check captured into a graph (replayed by later checks of the same trace)
     std::vector<GraphSeg> segs;
     u32 graph_variant = 0;
+    u32 graph_spec = 0;      // stages the captured pass is built without
+    u32 last_mode = ~0u;     // the trace kinds (MODE_*) its last check found; all until one is read
     std::string graph_filter;
     bool graph_off = false;  // capture failed once: checks are enqueued kernel by kernel
     uint64_t n_checks = 0;
@@ -709,7 +713,7 @@ static void graph_drop(rd_trace t) {
 }
 
 // Captures the trace's plain check into graph pieces (cut around the profiled kernels).
-static bool graph_capture(rd_ctx ctx, rd_trace t) {
+static bool graph_capture(rd_ctx ctx, rd_trace t, u32 spec) {
     if (!ctx->cap_stream && hipStreamCreateWithFlags(&ctx->cap_stream, hipStreamNonBlocking) != hipSuccess) {
         ctx->cap_stream = nullptr;
         return false;
@@ -725,7 +729,9 @@ static bool graph_capture(rd_ctx ctx, rd_trace t) {
     hipError_t e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
     hipError_t e2 = hipSuccess;
     if (e == hipSuccess) {
-        e2 = enqueue_plain(t->bufs, t->masks, t->rt_scan, cs);
+        Bufs gb = t->bufs;
+        gb.spec = spec;
+        e2 = enqueue_plain(gb, t->masks, t->rt_scan, cs);
         GraphSeg last;
         e = hipStreamEndCapture(cs, &last.graph);
         last.name = p.group_name;
@@ -759,6 +765,7 @@ static bool graph_capture(rd_ctx ctx, rd_trace t) {
     }
     t->graph_variant = ctx->sort_variant;
     t->graph_filter = p.filter;
+    t->graph_spec = spec;
     return true;
 }
 
@@ -793,9 +800,15 @@ rd_status rd_check(rd_ctx ctx, rd_trace trace, hipStream_t stream) {
     // from the second check of a trace on, the pass is one graph launch (captured again when the
     // sort variant or the profiled kernels change)
     if (trace->n_checks++ > 0 && !trace->graph_off) {
-        if (trace->segs.empty() || trace->graph_variant != ctx->sort_variant || trace->graph_filter != ctx->prof.filter) {
+        // the pass is built without the stages the trace's last check did not need (checked on the
+        // device: a trace that needs one after all is checked again whole by rd_races)
+        u32 spec = 0;
+        if (!(trace->last_mode & MODE_SYNC)) spec |= SPEC_NO_SYNC;
+        if (!(trace->last_mode & MODE_WBAR)) spec |= SPEC_NO_WBAR;
+        if (trace->segs.empty() || trace->graph_variant != ctx->sort_variant || trace->graph_filter != ctx->prof.filter ||
+            trace->graph_spec != spec) {
             graph_drop(trace);
-            if (!graph_capture(ctx, trace)) trace->graph_off = true;
+            if (!graph_capture(ctx, trace, spec)) trace->graph_off = true;
         }
         if (!trace->segs.empty()) {
             const hipError_t e = graph_launch(ctx, trace, stream);
@@ -868,9 +881,25 @@ static bool batch_races(rd_ctx ctx, rd_trace trace, rd_pair *out, uint64_t capac
     return true;
 }
 
+// The check's own errors (the trace, its capacities, a wait that gave up), the pair buffer aside.
+static rd_status state_error(rd_ctx ctx, const DevParams &prm) {
+    if (prm.first_bad_record != NONE) return set_err(ctx, RD_ETRACE, prm.first_bad_record, "malformed record");
+    if (prm.err & ERR_PHASE) return set_err(ctx, RD_EINVAL, UINT64_MAX, "a thread passed more than 2^30 barriers");
+    if (prm.first_bad_sync != NONE)
+        return set_err(ctx, RD_ETRACE, prm.first_bad_sync, "event runs ahead of an unfinished barrier");
+    if (prm.err & ERR_SORT) return set_err(ctx, RD_EHIP, UINT64_MAX, "location sort look-back did not finish");
+    if (prm.err & ERR_ENGINE) return set_err(ctx, RD_EHIP, UINT64_MAX, "knowledge engine barrier did not finish");
+    if (prm.err & ERR_KEYSPAN)
+        return set_err(ctx, RD_EINVAL, UINT64_MAX, "address span too large for a 32-bit location key");
+    if (prm.err & ERR_POOL) return set_err(ctx, RD_ENOMEM, UINT64_MAX, "knowledge-vector pool exhausted (rd_limits.clock_bytes)");
+    if (prm.err & ERR_TABLE) return set_err(ctx, RD_ENOMEM, UINT64_MAX, "sync-variable or warp-barrier table full");
+    return RD_OK;
+}
+
 // The report of a check enqueued on `s` over buffers `b` (waits for it).
 static rd_status plain_races(rd_ctx ctx, const Bufs &b, hipStream_t s, rd_pair *out, uint64_t capacity,
-                             uint64_t *n_races, u64 *hint, HostStage *stage = nullptr) {
+                             uint64_t *n_races, u64 *hint, HostStage *stage = nullptr, u32 *mode = nullptr,
+                             bool *respec = nullptr) {
     // the check left the sorted report as rd_pair records (pack_pairs); as many as the previous
     // report of these buffers held are copied together with the state, so a report no longer than
     // the last one takes a single wait.  With a stage, both go by DMA to page-locked memory and only
@@ -888,16 +917,16 @@ static rd_status plain_races(rd_ctx ctx, const Bufs &b, hipStream_t s, rd_pair *
         hipStreamSynchronize(s) != hipSuccess)
         return set_err(ctx, RD_EHIP, UINT64_MAX, "reading the check state failed");
     if (staged) memcpy(&prm, stage->p, sizeof(prm));
-    if (prm.first_bad_record != NONE) return set_err(ctx, RD_ETRACE, prm.first_bad_record, "malformed record");
-    if (prm.err & ERR_PHASE) return set_err(ctx, RD_EINVAL, UINT64_MAX, "a thread passed more than 2^30 barriers");
-    if (prm.first_bad_sync != NONE)
-        return set_err(ctx, RD_ETRACE, prm.first_bad_sync, "event runs ahead of an unfinished barrier");
-    if (prm.err & ERR_SORT) return set_err(ctx, RD_EHIP, UINT64_MAX, "location sort look-back did not finish");
-    if (prm.err & ERR_ENGINE) return set_err(ctx, RD_EHIP, UINT64_MAX, "knowledge engine barrier did not finish");
-    if (prm.err & ERR_KEYSPAN)
-        return set_err(ctx, RD_EINVAL, UINT64_MAX, "address span too large for a 32-bit location key");
-    if (prm.err & ERR_POOL) return set_err(ctx, RD_ENOMEM, UINT64_MAX, "knowledge-vector pool exhausted (rd_limits.clock_bytes)");
-    if (prm.err & ERR_TABLE) return set_err(ctx, RD_ENOMEM, UINT64_MAX, "sync-variable or warp-barrier table full");
+    if (mode) *mode = prm.mode;
+    if (prm.err & ERR_RESPEC) {
+        if (respec) {
+            *respec = true;
+            return RD_OK;
+        }
+        return set_err(ctx, RD_ESTATE, UINT64_MAX, "the pass was built without a stage the trace needs");
+    }
+    const rd_status se = state_error(ctx, prm);
+    if (se != RD_OK) return se;
     if (prm.err & ERR_PAIRS) {
         *n_races = prm.n_pairs;
         return set_err(ctx, RD_ENOMEM, UINT64_MAX, "race pairs exceed rd_limits.max_pairs");
@@ -960,6 +989,22 @@ static rd_status member_alone(rd_ctx ctx, rd_trace trace, rd_pair *out, uint64_t
     return RD_OK;
 }
 
+// The trace's last check was a pass built without a stage that the trace turned out to need (its
+// events were rewritten in place): the check again, whole and kernel by kernel, and no graph until
+// the next rd_check captures one for the kinds now seen.
+static rd_status recheck_whole(rd_ctx ctx, rd_trace t) {
+    graph_drop(t);
+    t->last_mode = ~0u;
+    Bufs b = t->bufs;
+    b.spec = 0;
+    Profiler *saved = g_prof;
+    g_prof = ctx->prof.filter.empty() ? nullptr : &ctx->prof;
+    const hipError_t e = enqueue_plain(b, t->masks, t->rt_scan, t->stream);
+    g_prof = saved;
+    if (e != hipSuccess) return set_err(ctx, RD_EHIP, UINT64_MAX, hipGetErrorString(e));
+    return RD_OK;
+}
+
 rd_status rd_races(rd_ctx ctx, rd_trace trace, rd_pair *out, uint64_t capacity, uint64_t *n_races) {
     if (!ctx || !trace || !n_races) return RD_EINVAL;
     *n_races = 0;
@@ -972,7 +1017,16 @@ rd_status rd_races(rd_ctx ctx, rd_trace trace, rd_pair *out, uint64_t capacity, 
         const rd_status c = rd_check(ctx, trace, trace->batch->stream);  // on its own; drops the batch
         if (c != RD_OK) return c;
     }
-    return plain_races(ctx, trace->bufs, trace->stream, out, capacity, n_races, &trace->last_pairs, &trace->stage);
+    bool respec = false;
+    rd_status st = plain_races(ctx, trace->bufs, trace->stream, out, capacity, n_races, &trace->last_pairs,
+                               &trace->stage, &trace->last_mode, &respec);
+    if (respec) {
+        st = recheck_whole(ctx, trace);
+        if (st != RD_OK) return st;
+        st = plain_races(ctx, trace->bufs, trace->stream, out, capacity, n_races, &trace->last_pairs, &trace->stage,
+                         &trace->last_mode, nullptr);
+    }
+    return st;
 }
 
 rd_status rd_check_static(rd_ctx ctx, const rd_grid *grid, const rd_event *events, uint64_t n_events,
@@ -1004,6 +1058,48 @@ rd_status rd_check_static(rd_ctx ctx, const rd_grid *grid, const rd_event *event
     return plain_races(ctx, b, stream, out, capacity, n_races, nullptr, nullptr);
 }
 
+rd_status rd_lockset(rd_ctx ctx, rd_trace trace, rd_pair *out, uint64_t capacity, uint64_t *n_pairs) {
+    if (!ctx || !trace || !n_pairs || (capacity && !out)) return RD_EINVAL;
+    *n_pairs = 0;
+    if (!trace->ws) return set_err(ctx, RD_ESTATE, UINT64_MAX, "the lockset pass needs the trace's own workspace");
+    if (hipSetDevice(ctx->device) != hipSuccess) return set_err(ctx, RD_EHIP, UINT64_MAX, "hipSetDevice failed");
+    LocksetBufs L;
+    if (!lockset_layout(trace->bufs, trace->bufs.max_pairs, L))
+        return set_err(ctx, RD_ENOMEM, UINT64_MAX, "the knowledge-vector pool cannot hold the lockset pass's pairs");
+    // a check of its own (the pass reads its sync lists and sorted accesses), then the pass, on the
+    // trace's stream; the trace's report afterwards is that check's
+    trace->batch.reset();
+    trace->cached = 0;
+    trace->bufs.sort_variant = ctx->sort_variant;
+    trace->bufs.radix_bits = kSortVariants[ctx->sort_variant].rb;
+    Profiler *saved = g_prof;
+    g_prof = ctx->prof.filter.empty() ? nullptr : &ctx->prof;
+    hipError_t e = enqueue_plain(trace->bufs, trace->masks, trace->rt_scan, trace->stream);
+    if (e == hipSuccess) {
+        lockset_run(trace->bufs, L, trace->stream);
+        e = hipGetLastError();
+    }
+    g_prof = saved;
+    if (e != hipSuccess) return set_err(ctx, RD_EHIP, UINT64_MAX, hipGetErrorString(e));
+    trace->checked = 1;
+    DevParams prm;
+    if (hipMemcpyAsync(&prm, trace->bufs.prm, sizeof(prm), hipMemcpyDeviceToHost, trace->stream) != hipSuccess ||
+        hipStreamSynchronize(trace->stream) != hipSuccess)
+        return set_err(ctx, RD_EHIP, UINT64_MAX, "reading the check state failed");
+    const rd_status se = state_error(ctx, prm);
+    if (se != RD_OK) return se;
+    if (prm.err & ERR_LOCKSET)
+        return set_err(ctx, RD_ENOMEM, UINT64_MAX, "a thread holds more than 64 locks at once, or the lockset rows exceed the pool");
+    *n_pairs = prm.ls_pairs;
+    if (prm.err & ERR_LSPAIRS) return set_err(ctx, RD_ENOMEM, UINT64_MAX, "lockset pairs exceed rd_limits.max_pairs");
+    const u64 m = prm.ls_kept, k = capacity < m ? capacity : m;
+    if (k && (hipMemcpyAsync(out, L.report, 8 * k, hipMemcpyDeviceToHost, trace->stream) != hipSuccess ||
+              hipStreamSynchronize(trace->stream) != hipSuccess))
+        return set_err(ctx, RD_EHIP, UINT64_MAX, "copying the lockset pairs failed");
+    if (capacity < m) return set_err(ctx, RD_ETRUNC, UINT64_MAX, "more lockset pairs than capacity");
+    return RD_OK;
+}
+
 rd_status rd_race_kinds(rd_ctx ctx, rd_trace trace, rd_race_kind *out, uint64_t capacity, uint64_t *n_kinds) {
     if (!ctx || !trace || !n_kinds || (capacity && !out)) return RD_EINVAL;
     *n_kinds = 0;
@@ -1016,7 +1112,14 @@ rd_status rd_race_kinds(rd_ctx ctx, rd_trace trace, rd_race_kind *out, uint64_t 
         if (c != RD_OK) return c;
     }
     uint64_t m = 0;
-    const rd_status st = plain_races(ctx, trace->bufs, trace->stream, nullptr, 0, &m, nullptr);
+    bool respec = false;
+    rd_status st = plain_races(ctx, trace->bufs, trace->stream, nullptr, 0, &m, nullptr, nullptr, &trace->last_mode,
+                               &respec);
+    if (respec) {
+        st = recheck_whole(ctx, trace);
+        if (st != RD_OK) return st;
+        st = plain_races(ctx, trace->bufs, trace->stream, nullptr, 0, &m, nullptr, nullptr, &trace->last_mode);
+    }
     if (st != RD_OK && st != RD_ETRUNC) return st;
     if (!m) return RD_OK;
     // scratch in the trace's workspace (sized for max_pairs): 5m + 1 words, scan partials, 3m
@@ -1369,9 +1472,14 @@ rd_status rd_trace_stats(rd_ctx ctx, rd_trace trace, rd_stats *out) {
         if (c != RD_OK) return c;
     }
     DevParams prm;
-    if (hipMemcpyAsync(&prm, trace->bufs.prm, sizeof(prm), hipMemcpyDeviceToHost, trace->stream) != hipSuccess ||
-        hipStreamSynchronize(trace->stream) != hipSuccess)
-        return set_err(ctx, RD_EHIP, UINT64_MAX, "reading the check state failed");
+    for (int round = 0; round < 2; round++) {
+        if (hipMemcpyAsync(&prm, trace->bufs.prm, sizeof(prm), hipMemcpyDeviceToHost, trace->stream) != hipSuccess ||
+            hipStreamSynchronize(trace->stream) != hipSuccess)
+            return set_err(ctx, RD_EHIP, UINT64_MAX, "reading the check state failed");
+        if (!(prm.err & ERR_RESPEC)) break;
+        const rd_status st = recheck_whole(ctx, trace);
+        if (st != RD_OK) return st;
+    }
     memset(out, 0, sizeof(*out));
     out->n_events = trace->n;
     out->n_accesses = prm.n_acc;

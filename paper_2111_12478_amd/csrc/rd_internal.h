@@ -69,6 +69,16 @@ enum : u32 {
     ERR_PHASE = 16,     // a thread passed more than 2^30 barriers
     ERR_SORT = 32,      // a radix-sort look-back wait hit its spin limit
     ERR_ENGINE = 64,    // a grid barrier of the knowledge engine hit its spin limit
+    ERR_LOCKSET = 128,  // lockset pass: a thread held more than LS_MAX locks, or the row table is full
+    ERR_LSPAIRS = 256,  // lockset pass: more pairs than its buffer holds
+    ERR_RESPEC = 512,   // the trace needs a stage the launched pass was built without (SPEC_*)
+};
+
+// Stages a pass can be built without (Bufs::spec), for the kinds of trace its last check saw; the
+// plan flags ERR_RESPEC when the trace needs one of them, and the check is then run again whole.
+enum : u32 {
+    SPEC_NO_SYNC = 1,  // no releases, acquires or warp barriers: no knowledge vectors
+    SPEC_NO_WBAR = 2,  // no warp barriers
 };
 
 // Radix sort: the pair and key-value sorts use 8-bit digits (at most 8 passes: two 32-bit halves);
@@ -124,12 +134,14 @@ struct DevParams {
     u32 gprog;             // progress of the engine's sequential phases (bounds barrier waits)
     u32 wlist;             // entries of the engine's window input list
     u32 max_phase;         // the largest barrier phase of any thread
+    u32 ls_pairs;          // lockset pass: pairs found (may exceed its buffer)
+    u32 ls_kept;           // ... min(ls_pairs, its buffer)
     unsigned long long n_chunks;  // queued slow-path chunks of the segment check (8-byte aligned)
 };
 
 // Errors after which later stages must not read what the failed stage should have written (sorted
 // elements, operation tables, knowledge handles): the check's answer is the error, so they skip.
-constexpr u32 ERR_ABANDON = ERR_POOL | ERR_TABLE | ERR_SORT | ERR_ENGINE;
+constexpr u32 ERR_ABANDON = ERR_POOL | ERR_TABLE | ERR_SORT | ERR_ENGINE | ERR_RESPEC;
 __host__ __device__ inline bool check_abandoned(const DevParams *P) { return (P->err & ERR_ABANDON) != 0; }
 
 // The engine evaluates runs of small dependent groups in windows of ENG_WIN operations; each
@@ -239,6 +251,7 @@ struct Bufs {
     u32 sort_variant;       // index into kSortVariants
     u32 sorted_buf;         // which element buffer holds the sorted elements (set by the host plan)
     u32 pair_buf;
+    u32 spec;               // SPEC_* stages this pass is built without
 };
 
 // One member of a batched check (device table): where its events are, its grid and its place in
@@ -310,6 +323,34 @@ __device__ inline u32 list_search(const Bufs &b, u32 t, u32 idx) {
         else hi = mid;
     }
     return lo == first ? NONE : lo - 1;
+}
+
+// The sorted elements after the location sort (and the sort's free buffers, the segment check's
+// queue of slow-path chunks).
+struct SegCtx {
+    const u32 *k, *i, *t, *f;
+    u32 *cpos, *clo, *chi;  // the queue of slow-path chunks (in the sort's free buffers)
+    u32 n;
+    bool packed;            // category and phase in the key word, above key_bits
+    u32 key_bits, kmask;
+};
+
+__device__ inline SegCtx seg_ctx(const Bufs &b) {
+    // the sort leaves the elements in buffer (passes % 2); passes = ceil(key_bits / radix_bits)
+    const u32 bits = b.prm->key_bits, passes = (bits + b.radix_bits - 1) / b.radix_bits;
+    const u32 c = passes & 1;
+    SegCtx s; s.k = b.ekey[c]; s.i = b.eidx[c]; s.t = b.etid[c]; s.f = b.einfo[c]; s.n = b.prm->n_acc;
+    s.cpos = b.ekey[c ^ 1]; s.clo = b.etid[c ^ 1]; s.chi = b.einfo[c ^ 1];
+    s.packed = packed_elements(bits, b.prm->max_phase);
+    s.key_bits = bits;
+    s.kmask = s.packed ? key_mask(bits) : ~0u;
+    return s;
+}
+
+// the location key and the info (category | phase) of sorted element p
+__device__ inline u32 seg_key(const SegCtx &s, u64 p) { return s.k[p] & s.kmask; }
+__device__ inline u32 seg_info(const SegCtx &s, u64 p) {
+    return s.packed ? packed_info(s.k[p], s.key_bits) : s.f[p];
 }
 
 // The knowledge handle of thread t at its access with trace index idx and barrier phase ph (block

@@ -58,6 +58,22 @@ hipError_t engine_run(const Bufs &b, const u32 *rt_scan, hipStream_t s);
 
 void segcheck_run(const Bufs &b, const u32 *rt_scan, hipStream_t s);
 
+// The pair sort and the packing into (first, second) records over any buffers (count *m_dev, at
+// most max_m); the sorted pairs end in f[0], s2[0].
+void sort_pairs_to(const Bufs &b, u32 *const f[2], u32 *const s2[2], const u32 *m_dev, u64 max_m, hipStream_t s);
+void pack_pairs_to(const u32 *first, const u32 *second, const u32 *m_dev, u64 max_m, u64 *out, hipStream_t s);
+
+// lockset pass (rd_lockset.hip), after a check, in the knowledge-vector pool
+struct LocksetBufs {
+    u32 *pf[2], *ps[2];  // pair ping-pong buffers, `cap` each
+    u64 *report;         // sorted pairs as (first, second) records, `cap`
+    u32 *rows;           // lockset rows
+    u32 row_cap;
+    u64 cap;
+};
+bool lockset_layout(const Bufs &b, u64 cap, LocksetBufs &L);
+void lockset_run(const Bufs &b, const LocksetBufs &L, hipStream_t s);
+
 // batched form: merged trace from the members' events; each member's run of the merged report
 void batch_merge(BatchTrace *tr, const u32 *off, u32 n_traces, u32 N, u32 tpb_merged, uint4 *out, u32 *bad,
                  hipStream_t s);

@@ -391,6 +391,8 @@ __global__ __launch_bounds__(PLAN_THREADS) void k_plan(Bufs b) {
     if (p->kind_count[3] || p->kind_count[5] || p->kind_count[6] || p->kind_count[7]) mode |= MODE_SYNC;
     if (p->kind_count[5]) mode |= MODE_WBAR;
     p->mode = mode;
+    if (((mode & MODE_SYNC) && (b.spec & SPEC_NO_SYNC)) || ((mode & MODE_WBAR) && (b.spec & SPEC_NO_WBAR)))
+        p->err |= ERR_RESPEC;
     p->n_sync = n_other + ((mode & MODE_SYNC) ? n_atom : 0u);
 }
 
@@ -432,92 +434,61 @@ __global__ __launch_bounds__(WG_THREADS) void k_sync_compact(Bufs b, const u64 *
         if ((m[k] >> lane) & 1) b.s_tidx[pre[k]] = (u32)(base + (u64)k * 64 + lane);
 }
 
-// Scatter the sync events into per-thread lists (unordered inside a list; sorted next).
-__global__ void k_sync_scatter(Bufs b) {
+// The sync events in trace order keyed by their thread, for the stable sort into per-thread lists
+// (key[q] = tid, val[q] = q, kindq[q] = kind).
+__global__ void k_sync_keys(Bufs b, u32 *key, u32 *val, u32 *kindq) {
     const u32 n = b.prm->n_sync;
     for (u32 q = blockIdx.x * blockDim.x + threadIdx.x; q < n; q += gridDim.x * blockDim.x) {
-        const u32 idx = b.s_tidx[q];
-        const uint4 e = b.ev[idx];
-        const u32 p = b.s_cnt[e.y] + atomicAdd(&b.s_fill[e.y], 1u);
-        b.s_pidx[p] = idx;
-        b.s_pq[p] = q;
-        b.s_kind[p] = (uint8_t)(e.z & 15u);
+        const uint4 e = b.ev[b.s_tidx[q]];
+        key[q] = e.y;
+        val[q] = q;
+        kindq[q] = e.z & 15u;
     }
 }
 
-// One lane per program thread: sort its list by trace index, number its barriers.
-__device__ inline void list_swap(Bufs &b, u32 x, u32 y) {
-    u32 t0 = b.s_pidx[x]; b.s_pidx[x] = b.s_pidx[y]; b.s_pidx[y] = t0;
-    u32 t1 = b.s_pq[x]; b.s_pq[x] = b.s_pq[y]; b.s_pq[y] = t1;
-    uint8_t t2 = b.s_kind[x]; b.s_kind[x] = b.s_kind[y]; b.s_kind[y] = t2;
-}
-__device__ inline void sift_down(Bufs &b, u32 lo, u32 root, u32 n) {
-    for (;;) {
-        u32 c = 2 * root + 1;
-        if (c >= n) return;
-        if (c + 1 < n && b.s_pidx[lo + c + 1] > b.s_pidx[lo + c]) c++;
-        if (b.s_pidx[lo + root] >= b.s_pidx[lo + c]) return;
-        list_swap(b, lo + root, lo + c);
-        root = c;
+// After the sort by thread: list position p holds the thread's entries in trace order.  Each entry
+// gets its event, kind and trace-order position, its per-entry fields cleared, and a barrier flag
+// for the phase scan.  The sort's totals and tickets are cleared for the location sort.
+__global__ void k_sync_place(Bufs b, const u32 *val, const u32 *kindq, u32 *barflag) {
+    const u32 n = b.prm->n_sync;
+    if (blockIdx.x == 0)
+        for (u32 i = threadIdx.x; i < MAX_SORT_PASSES * (SORT_NDS + 1); i += blockDim.x) b.sort_tot[i] = 0;
+    for (u32 p = blockIdx.x * blockDim.x + threadIdx.x; p <= n; p += gridDim.x * blockDim.x) {
+        if (p == n) {
+            barflag[p] = 0;
+            continue;
+        }
+        const u32 q = val[p], kind = kindq[q];
+        b.s_pidx[p] = b.s_tidx[q];
+        b.s_pq[p] = q;
+        b.s_inv[q] = p;
+        b.s_kind[p] = (uint8_t)kind;
+        b.s_imin[p] = NONE;
+        b.s_flags[p] = 0;
+        b.s_scope[p] = 0;
+        barflag[p] = kind == 4u ? 1u : 0u;
     }
 }
-// One wavefront per workgroup; every lane runs the same iterations (lanes past the threads idle),
-// so the per-block barrier counts can be combined across lanes before the atomics.
-__global__ __launch_bounds__(64) void k_thread_lists(Bufs b) {
-    u32 top = 0;  // this lane's largest phase
+
+// Phase of each entry: the barriers of its thread's list up to and including it (barscan: exclusive
+// prefix of the barrier flags over all lists).
+__global__ void k_sync_phase(Bufs b, const u32 *key, const u32 *barscan) {
+    const u32 n = b.prm->n_sync;
+    for (u32 p = blockIdx.x * blockDim.x + threadIdx.x; p < n; p += gridDim.x * blockDim.x)
+        b.s_phase[p] = barscan[p + 1] - barscan[b.s_cnt[key[p]]];
+}
+
+// One lane per program thread: its barrier count (phase bound), the block's largest (one atomic per
+// block present in the wavefront) and the trace's largest.
+__global__ __launch_bounds__(64) void k_thread_maxbar(Bufs b, const u32 *barscan) {
+    u32 top = 0;
     const u32 lane = lane_id();
     for (u32 base = blockIdx.x * 64; base < b.T; base += gridDim.x * 64) {
         const u32 t = base + lane;
         const bool valid = t < b.T;
-        const u32 lo = valid ? b.s_cnt[t] : 0u, hi = valid ? b.s_cnt[t + 1] : 0u, n = hi - lo;
-        if (n > 1) {
-            if (n <= 8) {
-                // in registers: one read and one write per entry, a fixed sorting network between
-                u32 x[8], y[8], z[8];
-#pragma unroll
-                for (u32 i = 0; i < 8; i++) {
-                    const bool in = i < n;
-                    x[i] = in ? b.s_pidx[lo + i] : NONE;
-                    y[i] = in ? b.s_pq[lo + i] : 0u;
-                    z[i] = in ? b.s_kind[lo + i] : 0u;
-                }
-                auto ce = [&](int i, int j) {
-                    if (x[j] < x[i]) {
-                        u32 t0 = x[i]; x[i] = x[j]; x[j] = t0;
-                        u32 t1 = y[i]; y[i] = y[j]; y[j] = t1;
-                        u32 t2 = z[i]; z[i] = z[j]; z[j] = t2;
-                    }
-                };
-                // Batcher's odd-even merge network for 8 keys (19 comparators)
-                ce(0, 1); ce(2, 3); ce(4, 5); ce(6, 7);
-                ce(0, 2); ce(1, 3); ce(4, 6); ce(5, 7);
-                ce(1, 2); ce(5, 6);
-                ce(0, 4); ce(1, 5); ce(2, 6); ce(3, 7);
-                ce(2, 4); ce(3, 5);
-                ce(1, 2); ce(3, 4); ce(5, 6);
-#pragma unroll
-                for (u32 i = 0; i < 8; i++)
-                    if (i < n) { b.s_pidx[lo + i] = x[i]; b.s_pq[lo + i] = y[i]; b.s_kind[lo + i] = (uint8_t)z[i]; }
-            } else if (n <= 32) {
-                for (u32 i = lo + 1; i < hi; i++)
-                    for (u32 j = i; j > lo && b.s_pidx[j - 1] > b.s_pidx[j]; j--) list_swap(b, j - 1, j);
-            } else {
-                for (u32 r = n / 2; r-- > 0;) sift_down(b, lo, r, n);
-                for (u32 e = n - 1; e > 0; e--) { list_swap(b, lo, lo + e); sift_down(b, lo, 0, e); }
-            }
-        }
-        u32 ph = 0;
-        for (u32 p = lo; p < hi; p++) {
-            if (b.s_kind[p] == 4) ph++;
-            b.s_phase[p] = ph;
-            b.s_inv[b.s_pq[p]] = p;
-            b.s_imin[p] = NONE;
-            b.s_flags[p] = 0;
-            b.s_scope[p] = 0;
-        }
+        const u32 ph = valid ? barscan[b.s_cnt[t + 1]] - barscan[b.s_cnt[t]] : 0u;
         if (ph >= (1u << 30)) atomicOr(&b.prm->err, ERR_PHASE);
         top = max(top, ph);
-        // the block's largest phase: one atomic per block present in the wavefront
         const u32 blk = valid ? t / b.tpb : NONE;
         u64 pending = ballot(ph != 0);
         while (pending) {
@@ -535,6 +506,7 @@ __global__ __launch_bounds__(64) void k_thread_lists(Bufs b) {
     for (int d = 32; d >= 1; d >>= 1) top = max(top, (u32)__shfl_xor((int)top, d, 64));
     if (lane == 0 && top) atomicMax(&b.prm->max_phase, top);
 }
+
 
 // Barrier arrivals per (block, instance) and active threads per block.  Lanes of a wavefront are
 // consecutive threads, mostly of one block, so arrivals are aggregated per (instance) across the
@@ -832,8 +804,22 @@ void prep_sync_lists(const Bufs &b, const u64 *sync_mask, const u64 *atom_mask, 
     RD_LAUNCH("k_merge_counts", k_merge_counts, dim3(grid_for(b.T)), dim3(256), 0, s, b);
     if (b.N) RD_LAUNCH("k_sync_compact", k_sync_compact, dim3(b.n_tiles), dim3(WG_THREADS), 0, s, b, sync_mask, atom_mask);
     scan_exclusive(b.s_cnt, (u64)b.T + 1, b.part, s);
-    RD_LAUNCH("k_sync_scatter", k_sync_scatter, dim3(grid_for(b.N)), dim3(256), 0, s, b);
-    RD_LAUNCH("k_thread_lists", k_thread_lists, dim3(grid_for(b.T, 64)), dim3(64), 0, s, b);
+    // per-thread lists in trace order: a stable sort of the trace-ordered sync events by thread
+    // (the element buffers are free until the elements are written), then the entries placed and
+    // numbered with coalesced passes over the list positions
+    u32 tbits = 0;
+    while (tbits < 32 && ((u64)1 << tbits) < (u64)b.T) tbits++;
+    const u32 tpasses = (tbits + SORT_RB - 1) / SORT_RB;
+    u32 *const k2[2] = {b.ekey[0], b.ekey[1]}, *const v2[2] = {b.eidx[0], b.eidx[1]};
+    RD_LAUNCH("k_sync_keys", k_sync_keys, dim3(grid_for(b.N)), dim3(256), 0, s, b, k2[0], v2[0], b.e_scan1);
+    sort_kv(b, k2, v2, &b.prm->n_sync, b.N, tpasses, nullptr, "k_sync_sort", s);
+    const u32 c = tpasses & 1u;
+    RD_LAUNCH("k_sync_place", k_sync_place, dim3(grid_for(b.N + 1)), dim3(256), 0, s, b, (const u32 *)v2[c],
+              (const u32 *)b.e_scan1, b.e_scan0);
+    scan_exclusive(b.e_scan0, (u64)b.N + 1, b.part, s, nullptr, &b.prm->n_sync);
+    RD_LAUNCH("k_sync_phase", k_sync_phase, dim3(grid_for(b.N)), dim3(256), 0, s, b, (const u32 *)k2[c],
+              (const u32 *)b.e_scan0);
+    RD_LAUNCH("k_thread_maxbar", k_thread_maxbar, dim3(grid_for(b.T, 64)), dim3(64), 0, s, b, (const u32 *)b.e_scan0);
     scan_exclusive(b.blk_maxbar, (u64)b.B + 1, b.part, s);  // -> instance offsets (inst_off)
     FillJobs f = {};
     f.P = b.prm;

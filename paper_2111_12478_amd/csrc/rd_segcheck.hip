@@ -123,32 +123,6 @@ __device__ inline void agg_combine(const Agg &l, Agg &r) {
 
 // ---------------------------------------------------------------- shared pieces
 
-struct SegCtx {
-    const u32 *k, *i, *t, *f;
-    u32 *cpos, *clo, *chi;  // the queue of slow-path chunks (in the sort's free buffers)
-    u32 n;
-    bool packed;            // category and phase in the key word, above key_bits
-    u32 key_bits, kmask;
-};
-
-__device__ inline SegCtx seg_ctx(const Bufs &b) {
-    // the sort leaves the elements in buffer (passes % 2); passes = ceil(key_bits / radix_bits)
-    const u32 bits = b.prm->key_bits, passes = (bits + b.radix_bits - 1) / b.radix_bits;
-    const u32 c = passes & 1;
-    SegCtx s; s.k = b.ekey[c]; s.i = b.eidx[c]; s.t = b.etid[c]; s.f = b.einfo[c]; s.n = b.prm->n_acc;
-    s.cpos = b.ekey[c ^ 1]; s.clo = b.etid[c ^ 1]; s.chi = b.einfo[c ^ 1];
-    s.packed = packed_elements(bits, b.prm->max_phase);
-    s.key_bits = bits;
-    s.kmask = s.packed ? key_mask(bits) : ~0u;
-    return s;
-}
-
-// the location key and the info (category | phase) of sorted element p
-__device__ inline u32 seg_key(const SegCtx &s, u64 p) { return s.k[p] & s.kmask; }
-__device__ inline u32 seg_info(const SegCtx &s, u64 p) {
-    return s.packed ? packed_info(s.k[p], s.key_bits) : s.f[p];
-}
-
 // Thread x of a tile owns the ITEMS consecutive elements [tile*TILE + x*ITEMS, +ITEMS).
 struct Items {
     u32 key[ITEMS], tid[ITEMS], info[ITEMS];

@@ -442,6 +442,14 @@ void sort_pairs(const Bufs &b, const u32 *m_dev, u32 m_host, u64 max_m, hipStrea
     sort_pairs_in(b, f, s2, m_dev, m_host, max_m, half, names, s);
 }
 
+void sort_pairs_to(const Bufs &b, u32 *const f[2], u32 *const s2[2], const u32 *m_dev, u64 max_m, hipStream_t s) {
+    u32 bits = 0;
+    while (bits < 32 && ((u64)1 << bits) < (u64)b.N) bits++;
+    const u32 half = (bits + SORT_RB - 1) / SORT_RB;
+    static const char *const names[3] = {"k_ls_pair_count", "k_ls_pair_reduce", "k_ls_pair_sweep"};
+    sort_pairs_in(b, f, s2, m_dev, 0, max_m, half, names, s);
+}
+
 // Interleaves the sorted pairs into (first, second) records, the report's host layout.
 __global__ __launch_bounds__(WG_THREADS) void k_pair_pack(const u32 *first, const u32 *second, const u32 *m_dev,
                                                           u64 max_m, u64 *out) {
@@ -456,6 +464,13 @@ void pack_pairs(const Bufs &b, hipStream_t s) {
     const u32 grid = tiles < 1024 ? (u32)tiles : 1024u;
     RD_LAUNCH("k_pair_pack", k_pair_pack, dim3(grid), dim3(WG_THREADS), 0, s, b.pfirst[0], b.psecond[0],
               &b.prm->n_pairs_kept, b.max_pairs, b.preport);
+}
+
+void pack_pairs_to(const u32 *first, const u32 *second, const u32 *m_dev, u64 max_m, u64 *out, hipStream_t s) {
+    if (!max_m) return;
+    const u64 tiles = (max_m + WG_THREADS - 1) / WG_THREADS;
+    const u32 grid = tiles < 1024 ? (u32)tiles : 1024u;
+    RD_LAUNCH("k_ls_pair_pack", k_pair_pack, dim3(grid), dim3(WG_THREADS), 0, s, first, second, m_dev, max_m, out);
 }
 
 // Stable sort of (key, value) pairs in k[0], v[0] by key: n = *n_dev items (launches sized for max_n),

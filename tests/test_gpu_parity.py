@@ -127,6 +127,38 @@ def test_graph_replays_follow_the_events(rc):
         rd_trace_free(rc.ctx, tr)
 
 
+def test_graph_built_without_knowledge_stages_checks_again_when_needed(rc):
+    # a trace without releases, acquires or warp barriers is replayed from a graph built without the
+    # knowledge stages; rewritten in place into one that has fence-adjacent atomics (releases and
+    # acquires), the replay finds that and the report comes from a whole check again, then back
+    import torch
+    from paper_2111_12478_amd import rd_trace_free
+    from tracegen.format import KIND, make_meta
+    grid, ev_a, _, _ = tracegen.generate(tracegen.tiny(seed=31))
+    kinds = ev_a[:, 2] & 15
+    assert not np.isin(kinds, (KIND["F"], KIND["WBAR"], KIND["ACQ"], KIND["REL"])).any()
+    # the same records with some reads turned into device fences (a fence right before or after an
+    # atomic of its thread makes it a release or an acquire); still a valid trace
+    ev_b = ev_a.copy()
+    reads = np.nonzero(kinds == KIND["R"])[0]
+    for i in reads[::7]:
+        ev_b[i] = (0, ev_b[i, 1], make_meta(KIND["F"], 1, 0), 0)
+    want = {"a": oracle.check(grid, ev_a), "b": oracle.check(grid, ev_b)}
+    assert want["a"].status == want["b"].status == 0
+    assert not np.array_equal(want["a"].pairs, want["b"].pairs)
+    dev = torch.from_numpy(ev_a.view(np.int32).copy()).cuda()
+    tr, ws, keep = rc.prepare(grid, dev)
+    try:
+        for step, name in enumerate(["a", "a", "a", "b", "b", "b", "a", "a", "b"]):
+            dev.copy_(torch.from_numpy((ev_a if name == "a" else ev_b).view(np.int32)))
+            got = rc.run(tr)
+            torch.cuda.synchronize()
+            assert got.status == 0, (step, got)
+            np.testing.assert_array_equal(got.pairs, want[name].pairs, err_msg=f"step {step}")
+    finally:
+        rd_trace_free(rc.ctx, tr)
+
+
 def test_report_length_changes_between_checks(rc):
     # the report copy is sized by the trace's previous report: reports that grow, shrink, are cut
     # by a small capacity or only counted all come out whole and in order
