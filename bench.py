@@ -105,7 +105,7 @@ def method_bytes(n_events: int, locations: int, pairs: int) -> int:
 
 def sort_own_bytes(n_acc: int, packed: bool) -> int:
     """One pass of the location sort over its own arrays: each element read and written once
-    (12 B per element when category and phase ride in the key word, else 16 B)."""
+    (12 B per element when category and phase ride in the key or the thread word, else 16 B)."""
     return 2 * (12 if packed else 16) * n_acc
 
 
@@ -308,7 +308,7 @@ def plain_workload(args, rc, label: str, title: str, grid, ev: np.ndarray, limit
         "end_to_end": {"ms": float(np.median(e2e)) * 1e3, "events_per_s": n / float(np.median(e2e)),
                        "what": "events copied from page-locked host memory, check, report (median of 3)"},
         "config": {"workload": title, "events": n, "accesses": n_acc, "race_pairs": int(len(pairs)),
-                   "key_bits": stats["key_bits"], "sort_passes": passes, "packed_elements": bool(stats["packed"]),
+                   "key_bits": stats["key_bits"], "sort_passes": passes, "packed_elements": ["no", "key word", "thread word"][int(stats["packed"])],
                    "sort_variant": {"index": variant, "digit_bits": rb, "waves": waves, "items": items,
                                     "autotune_ms": tune_ms}},
         "roofline": roof,
@@ -469,6 +469,69 @@ def race_kinds_figures(rc, grid, ev, want):
         import paper_2111_12478_amd as rd
         rd.rd_trace_free(rc.ctx, tr)
         rc._report_len.pop(tr, None)
+
+
+def run_analyses(args, rc, with_oracle: bool) -> dict:
+    """The two other analyses over one lock-heavy trace (8 blocks of 256 threads, 32 lock words,
+    65,536 data words, nested and fence-inferred critical sections, flag publications, barriers):
+    the lockset pass (rd_lockset) and the GWCP
+    pass (rd_gwcp), each call a check of its own, the pass and the report copy, timed beside the
+    happens-before check of the same trace; parity of both reports with the oracle's."""
+    import torch
+    import paper_2111_12478_amd as rd
+    from tracegen.locktrace import lock_trace
+    n_target = max(2_000, 200_000 // args.scale)
+    seed = 77
+    grid, ev = lock_trace(seed, max_events=n_target, flags=True, barriers=True, grid=(8, 256), locks=32,
+                          data_words=max(64, 65536 // args.scale))
+    n = int(len(ev))
+    title = (f"lock trace: {grid[0]} blocks x {grid[1]} threads, {n:,} events, 32 lock words, "
+             f"{max(64, 65536 // args.scale):,} data words, nested and fence-inferred critical sections, "
+             f"flag publications, barriers, seed {seed}")
+    say(f"analyses: {title}")
+    dev_ev = torch.from_numpy(ev.view(np.int32)).cuda()
+    # 2,048 threads release: knowledge vectors of 2,056 words, and the GWCP pass keeps a copy of P
+    # (2,048 words) per event that changes it
+    tr, ws, keep = rc.prepare(grid, dev_ev, {"max_pairs": max(1 << 20, n // 4), "clock_bytes": 8 << 30})
+    out = {"workload": title, "events": n, "threads": int(grid[0] * grid[1])}
+    try:
+        def timed(fn, reps):
+            fn()
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(reps):
+                r = fn()
+            torch.cuda.synchronize()
+            return r, (time.perf_counter() - t0) * 1e3 / reps
+
+        reps = max(1, min(args.steps, 5))
+        hb, hb_ms = timed(lambda: rc.run(tr), reps)
+        ls, ls_ms = timed(lambda: rc.lockset(tr), reps)
+        gw, gw_ms = timed(lambda: rc.gwcp(tr, capacity=1 << 22), min(reps, 2))
+        out["happens_before"] = {"ms_per_call": hb_ms, "events_per_s": n / (hb_ms / 1e3), "pairs": int(len(hb.pairs)),
+                                 "status": int(hb.status)}
+        out["lockset"] = {"ms_per_call": ls_ms, "events_per_s": n / (ls_ms / 1e3), "pairs": int(len(ls.pairs)),
+                          "status": int(ls.status), "what": "rd_lockset: a check, the lockset pass, the report copy"}
+        out["gwcp"] = {"ms_per_call": gw_ms, "events_per_s": n / (gw_ms / 1e3), "pairs": int(len(gw.pairs)),
+                       "status": int(gw.status), "what": "rd_gwcp: a check, the GWCP pass, the report copy"}
+        if with_oracle:
+            import oracle
+            for name, fn, got in (("lockset", oracle.lockset, ls), ("gwcp", oracle.gwcp, gw)):
+                c0 = time.perf_counter()
+                want = fn(grid, ev)
+                secs = time.perf_counter() - c0
+                same = want.status == got.status and np.array_equal(want.pairs, got.pairs)
+                out[name]["parity"] = "bit-exact" if same else f"MISMATCH gpu={len(got.pairs)} oracle={len(want.pairs)}"
+                out[name]["cpu_baseline"] = {"value": n / secs, "unit": "events/s", "cores": 1, "kind": "oracle",
+                                             "sample": f"the whole {n:,}-event trace, one core"}
+        for name, r in (("happens-before", hb), ("lockset", ls), ("GWCP", gw)):
+            if r.status != 0:
+                raise RuntimeError(f"analyses: {name} failed: {r}")
+        say(f"analyses: happens-before {hb_ms:.2f} ms, lockset {ls_ms:.2f} ms, GWCP {gw_ms:.2f} ms per call")
+    finally:
+        rd.rd_trace_free(rc.ctx, tr)
+        rc._report_len.pop(tr, None)
+    return out
 
 
 def _gen_member(cfg):
@@ -861,7 +924,7 @@ def parse():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--scale", type=int, default=1, help="shrink the workloads (tests only)")
-    ap.add_argument("--workload", choices=("all", "stencil", "large", "batched", "served"), default="all",
+    ap.add_argument("--workload", choices=("all", "stencil", "large", "batched", "served", "analyses"), default="all",
                     help="all (default): every workload, the stencil trace as the headline; or one of them alone")
     ap.add_argument("--no-cpu-baseline", action="store_true", help="skip the oracle (parity and CPU baseline)")
     ap.add_argument("--no-tune", action="store_true", help="keep the default location-sort variant")
@@ -932,6 +995,10 @@ def main():
             out = run_served(args, rc, oracle_on)
             print(json.dumps({**head, **out, "steps": 1, "warmup": 0}), flush=True)
             return
+        if args.workload == "analyses":
+            out = run_analyses(args, rc, oracle_on)
+            print(json.dumps({**head, **out, "steps": args.steps, "warmup": 1}), flush=True)
+            return
         # headline: the stencil trace (its oracle runs meanwhile; the comparison is made last)
         st, st_pairs = run_stencil(args, rc, st_inputs, cpu_sample)
         configs = {}
@@ -942,6 +1009,7 @@ def main():
             del grid, ev, want
             configs["batched"] = run_batched(args, rc, oracle_on)
             configs["served"] = run_served(args, rc, oracle_on)
+            configs["analyses"] = run_analyses(args, rc, oracle_on)
         if oracle_wait is not None:
             say("stencil: waiting for the oracle over the whole trace")
             st["parity"] = parity_of(st_pairs, oracle_wait())

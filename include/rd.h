@@ -196,6 +196,28 @@ rd_status rd_race_kinds(rd_ctx ctx, rd_trace trace, rd_race_kind *out, uint64_t 
  * rd_races returns that check's report. */
 rd_status rd_lockset(rd_ctx ctx, rd_trace trace, rd_pair *out, uint64_t capacity, uint64_t *n_pairs);
 
+/* The predictive relation GWCP (Section 4, Algorithms 1 and 2), a third workload over the same
+ * trace: the races a reordering of the trace's critical sections could expose, a superset of the
+ * happens-before report.  Each thread t keeps a local time N_t and clocks P_t (GWCP) and H_t (scoped
+ * happens-before) with one word per program thread; lock operations (explicit, or atomics inferred
+ * from fences; the critical sections as rd_lockset defines them) update them by Algorithm 1 with
+ * scoped lock clocks, rule (ii)'s release-time joins and the read / write clocks L^r, L^w; reads and
+ * writes inside critical sections by Algorithm 2; barrier and warp-barrier completions give every
+ * participant the join of their clocks.  A pair (a, b) of conflicting accesses of different threads,
+ * a before b in the trace (conflict and atomic scopes as for rd_races), is reported when a's local
+ * time is above P_t at b for b's thread t.
+ * Runs a check of the trace and the pass on the trace's stream and waits: min(capacity, total)
+ * pairs, sorted, into `out` (host memory; NULL with capacity 0 for the count), *n_pairs = total.
+ * The pass keeps its clocks in the trace's knowledge-vector pool: 8 T^2 bytes for the dense clocks
+ * of T threads, 24 bytes per rd_limits.max_pairs pair, 4 T bytes per clock it keeps (lock clocks,
+ * L^r / L^w per lock and location, the acquire and release times of each critical section, a copy
+ * of P per event that changes it) and tables of about 100 bytes per lock operation and 20 bytes per
+ * (access, held lock) pair.  Errors: those of the check (RD_ETRACE ...), RD_EINVAL for more than 4096
+ * threads, RD_ENOMEM when a thread holds more than 64 locks at once, the pool is too small, or the
+ * pairs exceed max_pairs, RD_ETRUNC when capacity < total, RD_ESTATE for a trace bound without a
+ * workspace.  Afterwards rd_races returns that check's report. */
+rd_status rd_gwcp(rd_ctx ctx, rd_trace trace, rd_pair *out, uint64_t capacity, uint64_t *n_pairs);
+
 /* Batched form (the same check, many traces per pass).  The members are independent traces, each
  * bound by rd_trace_upload to its own workspace as for rd_check.  rd_check_many enqueues one pass
  * of the pipeline over their concatenation: every trace keeps its own blocks, threads and words
@@ -250,7 +272,8 @@ typedef struct {
     uint32_t key_bits;          /* significant bits of the location key (sort passes follow from it) */
     uint32_t max_phase;         /* the most block barriers any thread passed */
     uint32_t engine;            /* 0: no knowledge vectors needed; 1: parallel engine; 2: interpreter */
-    uint32_t packed;            /* 1 when category and phase rode in the location key word */
+    uint32_t packed;            /* where category and phase rode: 1 the location key word, 2 the
+                                   thread word, 0 a word of their own */
     uint64_t clock_vectors;     /* knowledge vectors written (the empty one included) */
     uint64_t clock_words;       /* words per vector: blocks + threads with a column */
     uint64_t clock_bytes;       /* clock_vectors * clock_words * 4: pool bytes the check used */

@@ -108,6 +108,7 @@ def load_library():
             "rd_check_static": ([vp, P(rd_grid), vp, u64, P(rd_limits), vp, u64, P(u64), vp], i32),
             "rd_race_kinds": ([vp, vp, vp, u64, P(u64)], i32),
             "rd_lockset": ([vp, vp, vp, u64, P(u64)], i32),
+            "rd_gwcp": ([vp, vp, vp, u64, P(u64)], i32),
             "rd_trace_free": ([vp, vp], i32),
             "rd_trace_stats": ([vp, vp, P(rd_stats)], i32),
             "rd_batch_workspace_bytes": ([vp, P(vp), u32, P(rd_limits), P(u64)], i32),
@@ -200,6 +201,14 @@ def rd_lockset(ctx, trace, out_ptr, capacity) -> tuple[int, int]:
     Returns (status, total pairs)."""
     n = ctypes.c_uint64()
     st = load_library().rd_lockset(ctx, trace, out_ptr, capacity, ctypes.byref(n))
+    return st, n.value
+
+
+def rd_gwcp(ctx, trace, out_ptr, capacity) -> tuple[int, int]:
+    """The GWCP pass (Section 4) over a bound trace: pairs into (capacity, 2) uint32 host memory at
+    out_ptr.  Returns (status, total pairs)."""
+    n = ctypes.c_uint64()
+    st = load_library().rd_gwcp(ctx, trace, out_ptr, capacity, ctypes.byref(n))
     return st, n.value
 
 
@@ -507,6 +516,19 @@ class RaceChecker:
             return CheckResult(st, np.zeros((0, 2), np.uint32), idx, msg)
         out = np.zeros((max(n, 1), 2), dtype=np.uint32)
         st, n = rd_lockset(self.ctx, trace, out.ctypes.data, n)
+        if st != RD_OK:
+            idx, msg = rd_last_error(self.ctx)
+            return CheckResult(st, np.zeros((0, 2), np.uint32), idx, msg)
+        return CheckResult(st, out[:n].copy())
+
+    def gwcp(self, trace, capacity=1 << 16):
+        """The GWCP pass over a bound trace: CheckResult with the sorted pairs (the pass runs again
+        with room for every pair when `capacity` is too small)."""
+        out = np.zeros((max(capacity, 1), 2), dtype=np.uint32)
+        st, n = rd_gwcp(self.ctx, trace, out.ctypes.data, capacity)
+        if st == RD_ETRUNC:
+            out = np.zeros((max(n, 1), 2), dtype=np.uint32)
+            st, n = rd_gwcp(self.ctx, trace, out.ctypes.data, n)
         if st != RD_OK:
             idx, msg = rd_last_error(self.ctx)
             return CheckResult(st, np.zeros((0, 2), np.uint32), idx, msg)

@@ -13,7 +13,7 @@ LIB = os.path.join(HERE, "librd.so")
 DEMO_LIB = os.path.join(HERE, "librd_demo.so")
 DEMO_SOURCE = "rd_demo.hip"
 SOURCES = ["rd_prep.hip", "rd_sort.hip", "rd_interp.hip", "rd_engine.hip", "rd_segcheck.hip", "rd_batch.hip", "rd_host.hip",
-           "rd_server.hip", "rd_kinds.hip", "rd_lockset.hip"]
+           "rd_server.hip", "rd_kinds.hip", "rd_lockset.hip", "rd_gwcp.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [
     "--offload-arch=gfx950", "-O3", "-fPIC", "-std=c++17",

@@ -1,0 +1,733 @@
+// rd_gwcp.hip -- the predictive relation GWCP (Section 4) over a checked trace, on gfx950.
+//
+// A pair (a, b) of conflicting accesses of different threads, a before b in the trace, is a GWCP race
+// when a's local time is above b's thread's clock at b, C_t[u] = P_t[u] for u != t, where P is the
+// clock Algorithms 1 and 2 keep.  P changes only at lock operations (releases and acquires, explicit
+// or inferred from fences), at barrier completions and at reads or writes inside critical sections;
+// every other access sees the P its thread had after the last such event.  The pass:
+//   k_gw_thread   one lane per program thread walks its sync list: the thread's local time after
+//                 each entry (releases and barrier arrivals increment it) and the critical sections
+//                 open after it (reading G1: an acquire of a word the thread does not hold opens one,
+//                 its next release of that word closes it);
+//   k_gw_mark     one lane per event flags the events at which P can change (a lock operation, the
+//                 last arrival of a barrier instance, a read or write inside a critical section) and
+//                 counts what the tables need; a scan numbers them in trace order, k_gw_list lists
+//                 them;
+//   k_gw_clear    the clocks' initial values (N_t = 1, H_t = the unit vector of t, P_t = 0);
+//   k_gw_interp   one workgroup walks that list in trace order over dense per-thread clocks P_t, H_t
+//                 (one word per thread, as the algorithms keep them): ACQUIRE joins the lock clocks
+//                 of overlapping scope; RELEASE joins, by rule (ii), the release time of other
+//                 threads' released critical sections of the word whose acquire time is below C_t,
+//                 until nothing joins, then publishes L^r / L^w for the section's reads and writes and
+//                 the lock clocks (joined) and increments; SYNC gives every participant the join of
+//                 their clocks; a read or write joins L^w (a write also L^r) of every held lock.  Lane
+//                 0 takes the decisions and keeps the tables, all lanes join the clocks.  After each
+//                 event whose thread's P changed, a copy of P is kept (barrier participants share
+//                 one);
+//   k_gw_post     one lane per thread carries those copies along its sync list;
+//   k_gw_check    one lane per sorted access b: every earlier access of its location that conflicts
+//                 with b, of another thread, with a local time above the copy's word for its thread,
+//                 makes a pair;
+// then the pair sort of the report.  Dense clocks limit the pass to GW_MAX_T threads.  Its clocks
+// and tables live in the knowledge-vector pool, which the check no longer reads once it has ended;
+// its per-entry arrays in the knowledge engine's per-entry scratch.
+#include "rd_internal.h"
+#include "rd_kernels.h"
+
+namespace rd {
+
+constexpr u32 GW_HELD = 64;          // critical sections a thread may hold at once
+constexpr u32 GW_THREADS = 1024;     // the interpreter's workgroup
+constexpr u32 GW_DEV = 0xffffffffu;  // scope key of a device / system scoped lock
+constexpr u32 GW_CSW = 9;            // words of a critical-section row (see k_gw_interp)
+
+// counters at the head of the pass's pool area
+enum : u32 { GH_LOCKOPS = 0, GH_CSREC = 1, GH_WORDS = 16 };
+
+__device__ inline bool gw_lockop(const Bufs &b, u32 p) { return (b.s_flags[p] & (SF_REL | SF_ACQ)) != 0; }
+__device__ inline bool gw_overlap(u32 a, u32 c) { return a == GW_DEV || c == GW_DEV || a == c; }
+
+// The location key of event e, as the elements carry it.
+__device__ inline u32 gw_loc(const Bufs &b, const DevParams *P, uint4 e) {
+    return ((e.z >> 6) & 1u) ? P->g_span + block_of(b, e.y) * P->s_span + (e.x - P->sbase) : e.x - P->gbase;
+}
+
+__device__ inline bool gw_active(const DevParams *P) {
+    return P->first_bad_record == NONE && P->first_bad_sync == NONE && !check_abandoned(P) && !(P->err & ERR_GWCP);
+}
+
+// The sync entry of event i of thread t (lock operations and barrier arrivals are entries), or NONE.
+__device__ inline u32 gw_entry(const Bufs &b, u32 t, u32 i) {
+    const u32 q = list_search(b, t, i + 1);
+    return q != NONE && b.s_pidx[q] == i ? q : NONE;
+}
+
+// ---------------------------------------------------------------- the pass's heap
+
+// Carved from the pool after the counters, the same way by every kernel: the dense clocks, the
+// per-thread state, the tables (sized by the counts k_gw_thread and k_gw_mark leave), then clock
+// vectors of T words to the end.
+struct GwHeap {
+    u32 *P, *H;        // [T][T]
+    u32 *N;            // [T] local times
+    u32 *held_n;       // [T] critical sections held
+    u32 *held;         // [T][GW_HELD] their rows
+    u32 *lastsnap;     // [T] the copy of P_t in force (NONE: P_t = 0)
+    u32 *JH;           // [T] scratch of a barrier join
+    u32 *wsnap;        // [wo_cap] the copy a warp-barrier instance leaves
+    u64 *wkey; u32 *wval; u32 cw;   // lock word -> word row
+    u64 *lkey; u32 *lval; u32 cl;   // (lock clock, location, read / write) -> vector
+    u32 *words;        // [n_lock][4] word, queue head, queue tail, first lock clock
+    u32 *nodes;        // [n_lock][4] scope key, H vector, P vector, next lock clock of the word
+    u32 *cs;           // [n_lock][GW_CSW] critical sections
+    u32 *rec;          // [n_rec][3] location, write, next record of the section
+    u32 n_lock, n_rec;
+    u32 *vec;          // clock vectors
+    u32 cap_vec;
+    bool ok;
+};
+
+__device__ inline u32 gw_pow2(u64 n) {
+    u64 c = 16;
+    while (c < n && c < (1ull << 31)) c <<= 1;
+    return (u32)c;
+}
+
+__device__ inline GwHeap gw_carve(const GwcpBufs &G, u32 T, u32 wo_cap) {
+    GwHeap m;
+    const u64 nl = G.hdr[GH_LOCKOPS], nr = G.hdr[GH_CSREC];
+    u64 o = 0;
+    // every array starts on an even word (8-byte aligned for the u64 keys)
+    auto take = [&](u64 words) -> u32 * {
+        u32 *p = G.heap + o;
+        o += (words + 1) & ~1ull;
+        return p;
+    };
+    const u64 TT = (u64)T * T;
+    m.P = take(TT);
+    m.H = take(TT);
+    m.N = take(T);
+    m.held_n = take(T);
+    m.held = take((u64)T * GW_HELD);
+    m.lastsnap = take(T);
+    m.JH = take(T);
+    m.wsnap = take(wo_cap);
+    m.cw = gw_pow2(2 * nl + 1);
+    m.wkey = (u64 *)take(2ull * m.cw);
+    m.wval = take(m.cw);
+    m.cl = gw_pow2(2 * nr + 1);
+    m.lkey = (u64 *)take(2ull * m.cl);
+    m.lval = take(m.cl);
+    m.n_lock = (u32)nl;
+    m.n_rec = (u32)nr;
+    m.words = take(4 * nl);
+    m.nodes = take(4 * nl);
+    m.cs = take(GW_CSW * nl);
+    m.rec = take(3 * nr);
+    m.ok = o <= G.heap_words && nl < (1u << 30) && nr < (1u << 30);
+    const u64 rest = m.ok ? (G.heap_words - o) / (T ? T : 1) : 0;
+    m.vec = G.heap + o;
+    m.cap_vec = (u32)(rest > 0x7fffffffull ? 0x7fffffffull : rest);
+    return m;
+}
+
+__device__ inline u32 gw_hash(u64 key, u32 cap) { return (u32)((key * 0x9E3779B97F4A7C15ull) >> 32) & (cap - 1); }
+
+// Lookup (any lane; the tables change only between barriers): the value of key, NONE when absent.
+__device__ inline u32 gw_find(const u64 *keys, const u32 *vals, u32 cap, u64 key) {
+    u32 s = gw_hash(key, cap);
+    for (u32 probe = 0; probe < cap; probe++, s = (s + 1) & (cap - 1)) {
+        const u64 k = keys[s];
+        if (k == key) return vals[s];
+        if (k == ~0ull) return NONE;
+    }
+    return NONE;
+}
+
+// Lane 0: the value slot of key, inserted with value NONE when absent (the tables are sized at
+// twice the keys they can receive, so a free slot is always found).
+__device__ inline u32 *gw_insert(u64 *keys, u32 *vals, u32 cap, u64 key) {
+    u32 s = gw_hash(key, cap);
+    for (u32 probe = 0; probe < cap; probe++, s = (s + 1) & (cap - 1)) {
+        const u64 k = keys[s];
+        if (k == key) return &vals[s];
+        if (k == ~0ull) {
+            keys[s] = key;
+            vals[s] = NONE;
+            return &vals[s];
+        }
+    }
+    return nullptr;
+}
+
+__device__ inline u64 gw_lkey(u32 node, u32 x, u32 rw) { return ((u64)node << 33) | ((u64)x << 1) | rw; }
+
+// ---------------------------------------------------------------- per-thread walk
+
+__global__ void k_gw_init(DevParams *P, u32 *hdr) {
+    if (threadIdx.x < GH_WORDS) hdr[threadIdx.x] = 0;
+    if (threadIdx.x == 0) P->gw_pairs = 0;
+}
+
+__global__ void k_gw_thread(Bufs b, GwcpBufs G) {
+    DevParams *P = b.prm;
+    if (!gw_active(P)) return;
+    for (u32 t = blockIdx.x * blockDim.x + threadIdx.x; t < b.T; t += gridDim.x * blockDim.x) {
+        const u32 lo = b.s_cnt[t], hi = b.s_cnt[t + 1];
+        u32 n = 1, depth = 0, lockops = 0;
+        u32 held[GW_HELD];
+        for (u32 p = lo; p < hi; p++) {
+            if ((P->mode & MODE_SYNC) && gw_lockop(b, p)) {
+                const uint8_t f = b.s_flags[p];
+                const u32 x = gw_loc(b, P, b.ev[b.s_pidx[p]]);
+                lockops++;
+                if (f & SF_REL) {
+                    for (u32 q = 0; q < depth; q++)
+                        if (held[q] == x) {
+                            for (u32 r = q + 1; r < depth; r++) held[r - 1] = held[r];
+                            depth--;
+                            break;
+                        }
+                    n++;
+                }
+                if (f & SF_ACQ) {
+                    bool h = false;
+                    for (u32 q = 0; q < depth; q++) h |= held[q] == x;
+                    if (!h) {
+                        if (depth == GW_HELD) {
+                            atomicOr(&P->err, ERR_GWCP);
+                            return;
+                        }
+                        held[depth++] = x;
+                    }
+                }
+            }
+            // a barrier arrival: the local time after the instance completes (a valid trace has no
+            // event of the thread before that)
+            const u32 kind = b.s_kind[p];
+            if (kind == 4u || kind == 5u) n++;
+            G.n_after[p] = n;
+            G.depth[p] = depth;
+        }
+        if (lockops) atomicAdd(&G.hdr[GH_LOCKOPS], lockops);
+    }
+}
+
+// ---------------------------------------------------------------- relevant events
+
+__device__ inline bool gw_bar_complete(const Bufs &b, u32 p, u32 i, u32 blk, u32 *slot) {
+    *slot = b.inst_off[blk] + b.s_phase[p] - 1;
+    return b.inst_last[*slot] == i && b.inst_cnt[*slot] == b.n_active[blk];
+}
+__device__ inline bool gw_wbar_complete(const Bufs &b, u32 p, u32 i) {
+    const u32 inst = b.s_winst[p];
+    return inst != NONE && b.winst_last[inst] == i && b.winst_arrived[inst] == b.winst_mask[inst];
+}
+
+// flag[i]: P can change at event i; flag[N] = 0.
+__global__ void k_gw_mark(Bufs b, GwcpBufs G, u32 *flag) {
+    DevParams *P = b.prm;
+    const bool on = gw_active(P);
+    for (u32 i = blockIdx.x * blockDim.x + threadIdx.x; i <= b.N; i += gridDim.x * blockDim.x) {
+        u32 f = 0;
+        if (on && i < b.N) {
+            const uint4 e = b.ev[i];
+            const u32 kind = e.z & 15u, t = e.y;
+            if (kind == 4u) {
+                const u32 p = gw_entry(b, t, i);
+                u32 slot;
+                f = p != NONE && gw_bar_complete(b, p, i, block_of(b, t), &slot);
+            } else if (kind == 5u) {
+                const u32 p = gw_entry(b, t, i);
+                f = p != NONE && (P->mode & MODE_WBAR) && gw_wbar_complete(b, p, i);
+            } else if (kind != 3u) {
+                const u32 p = kind == 2u || kind >= 6u ? gw_entry(b, t, i) : NONE;
+                if (p != NONE && (P->mode & MODE_SYNC) && gw_lockop(b, p)) {
+                    f = 1;
+                } else {
+                    // a read or write (an atomic that is no lock operation is a write) inside the
+                    // critical sections open after the thread's previous entry
+                    const u32 j = list_search(b, t, i);
+                    const u32 d = j == NONE ? 0u : G.depth[j];
+                    if (d) {
+                        f = 1;
+                        atomicAdd(&G.hdr[GH_CSREC], d);
+                    }
+                }
+            }
+        }
+        flag[i] = f;
+    }
+}
+
+__global__ void k_gw_list(Bufs b, const u32 *scan, u32 *list) {
+    if (!gw_active(b.prm)) return;
+    for (u32 i = blockIdx.x * blockDim.x + threadIdx.x; i < b.N; i += gridDim.x * blockDim.x)
+        if (scan[i + 1] != scan[i]) list[scan[i]] = i;
+}
+
+__global__ void k_gw_clear(Bufs b, GwcpBufs G) {
+    DevParams *P = b.prm;
+    if (!gw_active(P)) return;
+    const u32 T = b.T;
+    const GwHeap m = gw_carve(G, T, b.wo_cap);
+    if (!m.ok) {
+        if (blockIdx.x == 0 && threadIdx.x == 0) atomicOr(&P->err, ERR_GWCP);
+        return;
+    }
+    const u64 g = (u64)blockIdx.x * blockDim.x + threadIdx.x, stride = (u64)gridDim.x * blockDim.x;
+    const u64 TT = (u64)T * T;
+    for (u64 k = g; k < TT; k += stride) {
+        m.P[k] = 0;
+        m.H[k] = k % ((u64)T + 1) == 0 ? 1u : 0u;  // the diagonal
+    }
+    for (u64 t = g; t < T; t += stride) {
+        m.N[t] = 1;
+        m.held_n[t] = 0;
+        m.lastsnap[t] = NONE;
+    }
+    for (u64 s = g; s < m.cw; s += stride) m.wkey[s] = ~0ull;
+    for (u64 s = g; s < m.cl; s += stride) m.lkey[s] = ~0ull;
+}
+
+// ---------------------------------------------------------------- the interpreter
+
+// All lanes: dst = max(dst, src) over T words; true (in every lane) when a word grew.
+__device__ inline bool gw_join(u32 *dst, const u32 *src, u32 T) {
+    bool ch = false;
+    for (u32 w = threadIdx.x; w < T; w += GW_THREADS) {
+        const u32 v = src[w];
+        if (v > dst[w]) {
+            dst[w] = v;
+            ch = true;
+        }
+    }
+    return __syncthreads_or(ch);
+}
+
+// Lane 0's value to every lane.
+__device__ inline u32 gw_bcast(u32 v, u32 *slot) {
+    if (threadIdx.x == 0) *slot = v;
+    __syncthreads();
+    const u32 r = *slot;
+    __syncthreads();
+    return r;
+}
+
+// Critical-section row: [0] thread, [1] word row, [2] acquire key, [3] release key, [4] release
+// event (NONE while open), [5] vector of C_t at the acquire, [6] vector of H_t at the release,
+// [7] next section of the word in acquire order, [8] first read / write record.
+__global__ __launch_bounds__(GW_THREADS) void k_gw_interp(Bufs b, GwcpBufs G, const u32 *scan, const u32 *list) {
+    DevParams *P = b.prm;
+    if (!gw_active(P)) return;
+    const u32 T = b.T, n_rel = scan[b.N];
+    const GwHeap m = gw_carve(G, T, b.wo_cap);
+    __shared__ u32 s_b;                                    // broadcast slot
+    __shared__ u32 s_vec, s_cs, s_words, s_nodes, s_rec;  // lane 0's allocation counters
+    __shared__ u32 s_full;
+    if (threadIdx.x == 0) {
+        s_vec = s_cs = s_words = s_nodes = s_rec = 0;
+        s_full = 0;
+    }
+    __syncthreads();
+    // lane 0: a fresh clock vector, NONE when the pool is spent
+    auto new_vec = [&]() -> u32 {
+        if (s_vec >= m.cap_vec) {
+            s_full = 1;
+            return NONE;
+        }
+        return s_vec++;
+    };
+    auto vec = [&](u32 h) -> u32 * { return m.vec + (u64)h * T; };
+    for (u32 r = 0; r < n_rel; r++) {
+        const u32 i = list[r];
+        const uint4 e = b.ev[i];
+        const u32 t = e.y, kind = e.z & 15u, blk = block_of(b, t);
+        u32 *Pt = m.P + (u64)t * T, *Ht = m.H + (u64)t * T;
+        const u32 pre = m.lastsnap[t];
+        bool pch = false;
+
+        if (kind == 4u || kind == 5u) {
+            // SYNC at the last arrival: every participant takes the join J of their C (P with its
+            // own local time) and of their H, then increments; J is their shared copy of P
+            const u32 p = gw_entry(b, t, i);
+            u32 ulo, uhi, wbase = 0, mask = 0, slot = NONE, inst = NONE;
+            if (kind == 4u) {
+                gw_bar_complete(b, p, i, blk, &slot);
+                ulo = blk * b.tpb;
+                uhi = ulo + b.tpb;
+            } else {
+                inst = b.s_winst[p];
+                mask = b.winst_mask[inst];
+                wbase = t - t % b.tpb % b.ws;
+                ulo = wbase;
+                uhi = wbase + 32;
+            }
+            const u32 hj = gw_bcast(threadIdx.x == 0 ? new_vec() : 0u, &s_b);
+            if (hj == NONE) break;
+            u32 *J = vec(hj);
+            for (u32 w = threadIdx.x; w < T; w += GW_THREADS) {
+                u32 mj = 0, mh = 0;
+                for (u32 u = ulo; u < uhi; u++) {
+                    const bool part = kind == 4u ? b.act[u] != 0 : ((mask >> (u - wbase)) & 1u) != 0;
+                    if (!part) continue;
+                    mj = max(mj, w == u ? m.N[u] : m.P[(u64)u * T + w]);
+                    mh = max(mh, m.H[(u64)u * T + w]);
+                }
+                J[w] = mj;
+                m.JH[w] = mh;
+            }
+            __syncthreads();
+            for (u32 u = ulo; u < uhi; u++) {
+                const bool part = kind == 4u ? b.act[u] != 0 : ((mask >> (u - wbase)) & 1u) != 0;
+                if (!part) continue;
+                u32 *Pu = m.P + (u64)u * T, *Hu = m.H + (u64)u * T;
+                for (u32 w = threadIdx.x; w < T; w += GW_THREADS) {
+                    Pu[w] = J[w];
+                    Hu[w] = m.JH[w] + (w == u ? 1u : 0u);
+                }
+            }
+            for (u32 u = ulo + threadIdx.x; u < uhi; u += GW_THREADS) {
+                const bool part = kind == 4u ? b.act[u] != 0 : ((mask >> (u - wbase)) & 1u) != 0;
+                if (!part) continue;
+                m.N[u] += 1;
+                m.lastsnap[u] = hj;
+            }
+            if (threadIdx.x == 0) {
+                if (kind == 4u) G.barsnap[slot] = hj;
+                else m.wsnap[inst] = hj;
+            }
+            __syncthreads();
+            continue;
+        }
+
+        const u32 p = kind == 2u || kind >= 6u ? gw_entry(b, t, i) : NONE;
+        const bool lockop = p != NONE && (P->mode & MODE_SYNC) && gw_lockop(b, p);
+        const u32 x = gw_loc(b, P, e);
+        if (!lockop) {
+            // Algorithm 2 (a read, or a write: a plain write or an atomic): join L^w, for a write also
+            // L^r, of x under every lock clock of a held section's word whose scope overlaps the
+            // section's; then x joins the section's reads or writes
+            const bool write = kind != 0u;
+            const u32 nh = m.held_n[t];
+            for (u32 q = 0; q < nh; q++) {
+                const u32 *C = m.cs + (u64)m.held[(u64)t * GW_HELD + q] * GW_CSW;
+                for (u32 nd = m.words[(u64)C[1] * 4 + 3]; nd != NONE; nd = m.nodes[(u64)nd * 4 + 3]) {
+                    if (!gw_overlap(m.nodes[(u64)nd * 4], C[2])) continue;
+                    for (u32 rw = write ? 0u : 1u; rw < 2u; rw++) {
+                        const u32 h = gw_find(m.lkey, m.lval, m.cl, gw_lkey(nd, x, rw));
+                        if (h != NONE) pch |= gw_join(Pt, vec(h), T);
+                    }
+                }
+            }
+            if (threadIdx.x == 0)
+                for (u32 q = 0; q < nh; q++) {
+                    u32 *C = m.cs + (u64)m.held[(u64)t * GW_HELD + q] * GW_CSW;
+                    const u32 rc = s_rec++;  // counted by k_gw_mark: always below n_rec
+                    m.rec[(u64)rc * 3] = x;
+                    m.rec[(u64)rc * 3 + 1] = write ? 1u : 0u;
+                    m.rec[(u64)rc * 3 + 2] = C[8];
+                    C[8] = rc;
+                }
+            __syncthreads();
+        } else {
+            const uint8_t fl = b.s_flags[p], sc = b.s_scope[p];
+            // the word's row, created on first use
+            u32 wrow = 0;
+            if (threadIdx.x == 0) {
+                u32 *v = gw_insert(m.wkey, m.wval, m.cw, x);
+                if (*v == NONE) {
+                    const u32 w = s_words++;  // at most one per lock operation
+                    m.words[(u64)w * 4] = x;
+                    m.words[(u64)w * 4 + 1] = NONE;
+                    m.words[(u64)w * 4 + 2] = NONE;
+                    m.words[(u64)w * 4 + 3] = NONE;
+                    *v = w;
+                }
+                wrow = *v;
+            }
+            wrow = gw_bcast(wrow, &s_b);
+            u32 *W = m.words + (u64)wrow * 4;
+            if (fl & SF_REL) {
+                // RELEASE (Algorithm 1)
+                const u32 key = (sc & 3u) == 0 ? blk : GW_DEV;
+                u32 ci = NONE;
+                if (threadIdx.x == 0) {
+                    // the section it closes: the thread's open one on the word, if any
+                    const u32 nh = m.held_n[t];
+                    u32 *hl = m.held + (u64)t * GW_HELD;
+                    for (u32 q = 0; q < nh; q++)
+                        if (m.cs[(u64)hl[q] * GW_CSW + 1] == wrow) {
+                            ci = hl[q];
+                            for (u32 q2 = q + 1; q2 < nh; q2++) hl[q2 - 1] = hl[q2];
+                            m.held_n[t] = nh - 1;
+                            break;
+                        }
+                }
+                ci = gw_bcast(ci, &s_b);
+                if (ci != NONE) {
+                    // rule (ii): another thread's released section of the word, released with an
+                    // overlapping scope, whose acquire time is below C_t: its release time joins
+                    // P_t; again until a pass over the queue joins nothing new
+                    for (bool more = true; more;) {
+                        more = false;
+                        for (u32 f = W[1]; f != NONE; f = m.cs[(u64)f * GW_CSW + 7]) {
+                            const u32 *F = m.cs + (u64)f * GW_CSW;
+                            if (F[0] == t || F[4] == NONE || !gw_overlap(F[3], key)) continue;
+                            const u32 *A = vec(F[5]);
+                            // most sections fail on their own thread's word (every lane reads it)
+                            if (A[F[0]] > Pt[F[0]]) continue;
+                            bool above = false;
+                            for (u32 w = threadIdx.x; w < T; w += GW_THREADS)
+                                above |= A[w] > (w == t ? m.N[t] : Pt[w]);
+                            if (__syncthreads_or(above)) continue;
+                            if (gw_join(Pt, vec(F[6]), T)) {
+                                more = true;
+                                pch = true;
+                            }
+                        }
+                    }
+                }
+                // the lock clock of (word, key), created on first use
+                u32 nd = NONE, fresh = 0;
+                if (threadIdx.x == 0) {
+                    nd = W[3];
+                    while (nd != NONE && m.nodes[(u64)nd * 4] != key) nd = m.nodes[(u64)nd * 4 + 3];
+                    if (nd == NONE) {
+                        const u32 hv = new_vec(), pv = new_vec();
+                        if (hv != NONE && pv != NONE) {
+                            nd = s_nodes++;  // at most one per release
+                            m.nodes[(u64)nd * 4] = key;
+                            m.nodes[(u64)nd * 4 + 1] = hv;
+                            m.nodes[(u64)nd * 4 + 2] = pv;
+                            m.nodes[(u64)nd * 4 + 3] = W[3];
+                            W[3] = nd;
+                            fresh = 1;
+                        }
+                    }
+                }
+                nd = gw_bcast(nd, &s_b);
+                if (nd == NONE) break;
+                fresh = gw_bcast(fresh, &s_b);
+                u32 *HL = vec(m.nodes[(u64)nd * 4 + 1]), *PL = vec(m.nodes[(u64)nd * 4 + 2]);
+                if (fresh) {
+                    for (u32 w = threadIdx.x; w < T; w += GW_THREADS) HL[w] = PL[w] = 0;
+                    __syncthreads();
+                }
+                if (ci != NONE) {
+                    // L^r / L^w of (lock clock, x) join H_t for the section's reads / writes x
+                    const u32 head = m.cs[(u64)ci * GW_CSW + 8];
+                    for (u32 rc = head; rc != NONE; rc = m.rec[(u64)rc * 3 + 2]) {
+                        u32 h = NONE, nw = 0;
+                        if (threadIdx.x == 0) {
+                            u32 *v = gw_insert(m.lkey, m.lval, m.cl, gw_lkey(nd, m.rec[(u64)rc * 3], m.rec[(u64)rc * 3 + 1]));
+                            if (*v == NONE) {
+                                *v = new_vec();
+                                nw = 1;
+                            }
+                            h = *v;
+                        }
+                        h = gw_bcast(h, &s_b);
+                        nw = gw_bcast(nw, &s_b);
+                        if (h == NONE) break;
+                        u32 *L = vec(h);
+                        for (u32 w = threadIdx.x; w < T; w += GW_THREADS) L[w] = nw ? Ht[w] : max(L[w], Ht[w]);
+                        __syncthreads();
+                    }
+                    // the section's release time (Rel_l for the other threads)
+                    u32 h = NONE;
+                    if (threadIdx.x == 0) {
+                        h = new_vec();
+                        u32 *C = m.cs + (u64)ci * GW_CSW;
+                        C[3] = key;
+                        C[4] = i;
+                        C[6] = h;
+                    }
+                    h = gw_bcast(h, &s_b);
+                    if (h == NONE) break;
+                    u32 *RH = vec(h);
+                    for (u32 w = threadIdx.x; w < T; w += GW_THREADS) RH[w] = Ht[w];
+                    __syncthreads();
+                }
+                // H_<l,s> and P_<l,s> publish the thread's clocks (joined), then its local time moves
+                gw_join(HL, Ht, T);
+                gw_join(PL, Pt, T);
+                if (threadIdx.x == 0) {
+                    m.N[t] += 1;
+                    Ht[t] += 1;
+                }
+                __syncthreads();
+            }
+            if (fl & SF_ACQ) {
+                // ACQUIRE (Algorithm 1): P and H of every lock clock of the word whose scope overlaps
+                const u32 key = ((sc >> 2) & 3u) == 0 ? blk : GW_DEV;
+                for (u32 nd = W[3]; nd != NONE; nd = m.nodes[(u64)nd * 4 + 3]) {
+                    if (!gw_overlap(m.nodes[(u64)nd * 4], key)) continue;
+                    pch |= gw_join(Pt, vec(m.nodes[(u64)nd * 4 + 2]), T);
+                    gw_join(Ht, vec(m.nodes[(u64)nd * 4 + 1]), T);
+                }
+                // a section opens unless the thread holds the word (Acq_l for the other threads)
+                u32 h = NONE;
+                if (threadIdx.x == 0) {
+                    const u32 nh = m.held_n[t];
+                    bool holding = false;
+                    for (u32 q = 0; q < nh; q++) holding |= m.cs[(u64)m.held[(u64)t * GW_HELD + q] * GW_CSW + 1] == wrow;
+                    if (!holding) {
+                        h = new_vec();
+                        if (h != NONE) {
+                            const u32 ci = s_cs++;  // at most one per acquire
+                            u32 *C = m.cs + (u64)ci * GW_CSW;
+                            C[0] = t; C[1] = wrow; C[2] = key; C[3] = key; C[4] = NONE; C[5] = h; C[6] = NONE;
+                            C[7] = NONE; C[8] = NONE;
+                            if (W[2] == NONE) W[1] = ci;
+                            else m.cs[(u64)W[2] * GW_CSW + 7] = ci;
+                            W[2] = ci;
+                            m.held[(u64)t * GW_HELD + nh] = ci;  // below GW_HELD: k_gw_thread checked
+                            m.held_n[t] = nh + 1;
+                        }
+                    }
+                }
+                h = gw_bcast(h, &s_b);
+                if (h != NONE) {
+                    u32 *A = vec(h);
+                    for (u32 w = threadIdx.x; w < T; w += GW_THREADS) A[w] = w == t ? m.N[t] : Pt[w];
+                    __syncthreads();
+                }
+            }
+        }
+        if (s_full) break;
+        // the copy of P_t after the event: a new one when it changed
+        u32 post = pre;
+        if (pch) {
+            post = gw_bcast(threadIdx.x == 0 ? new_vec() : 0u, &s_b);
+            if (post == NONE) break;
+            u32 *S = vec(post);
+            for (u32 w = threadIdx.x; w < T; w += GW_THREADS) S[w] = Pt[w];
+        }
+        if (threadIdx.x == 0) {
+            m.lastsnap[t] = post;
+            G.evsnap[r] = post;
+            // the race check of an access sees P_t after Algorithm 2's joins, of a lock operation
+            // before its own effect
+            G.evchk[r] = lockop ? pre : post;
+        }
+        __syncthreads();
+    }
+    __syncthreads();
+    if (threadIdx.x == 0 && s_full) atomicOr(&P->err, ERR_GWCP);
+}
+
+// The copy of P in force after each sync entry, carried along every thread's list.
+__global__ void k_gw_post(Bufs b, GwcpBufs G, const u32 *scan) {
+    if (!gw_active(b.prm)) return;
+    const GwHeap m = gw_carve(G, b.T, b.wo_cap);
+    for (u32 t = blockIdx.x * blockDim.x + threadIdx.x; t < b.T; t += gridDim.x * blockDim.x) {
+        const u32 lo = b.s_cnt[t], hi = b.s_cnt[t + 1], blk = block_of(b, t);
+        u32 cur = NONE;
+        for (u32 p = lo; p < hi; p++) {
+            const u32 kind = b.s_kind[p];
+            if (kind == 4u) {
+                const u32 slot = b.inst_off[blk] + b.s_phase[p] - 1;
+                if (b.inst_cnt[slot] == b.n_active[blk]) cur = G.barsnap[slot];
+            } else if (kind == 5u) {
+                const u32 inst = (b.prm->mode & MODE_WBAR) ? b.s_winst[p] : NONE;
+                if (inst != NONE && b.winst_arrived[inst] == b.winst_mask[inst]) cur = m.wsnap[inst];
+            } else {
+                const u32 i = b.s_pidx[p];
+                if (scan[i + 1] != scan[i]) cur = G.evsnap[scan[i]];
+            }
+            G.snap[p] = cur;
+        }
+    }
+}
+
+// The local time of thread t at its event with trace index i.
+__device__ inline u32 gw_epoch(const Bufs &b, const GwcpBufs &G, u32 t, u32 i) {
+    const u32 j = list_search(b, t, i);
+    return j == NONE ? 1u : G.n_after[j];
+}
+
+__global__ __launch_bounds__(256) void k_gw_check(Bufs b, GwcpBufs G, const u32 *scan) {
+    DevParams *P = b.prm;
+    if (!gw_active(P)) return;
+    const GwHeap m = gw_carve(G, b.T, b.wo_cap);
+    const SegCtx s = seg_ctx(b);
+    for (u64 pos = (u64)blockIdx.x * blockDim.x + threadIdx.x; pos < s.n; pos += (u64)gridDim.x * blockDim.x) {
+        const u32 kb = seg_key(s, pos), ib = s.i[pos], tb = seg_tid(s, pos), cb = info_cat(seg_info(s, pos));
+        const u32 bb = block_of(b, tb);
+        // b's clock: its own when P can change at b, else the one after its thread's previous entry
+        u32 h;
+        if (scan[ib + 1] != scan[ib]) {
+            h = G.evchk[scan[ib]];
+        } else {
+            const u32 j = list_search(b, tb, ib);
+            h = j == NONE ? NONE : G.snap[j];
+        }
+        const u32 *V = h == NONE ? nullptr : m.vec + (u64)h * b.T;
+        for (u64 q = pos; q > 0;) {
+            q--;
+            if (seg_key(s, q) != kb) break;
+            const u32 ta = seg_tid(s, q);
+            if (ta == tb) continue;
+            const u32 ca = info_cat(seg_info(s, q));
+            if (ca == CAT_R && cb == CAT_R) continue;
+            if (ca >= CAT_AD && cb >= CAT_AD && (ca == CAT_AD || cb == CAT_AD || block_of(b, ta) == bb)) continue;
+            const u32 ia = s.i[q];
+            if (gw_epoch(b, G, ta, ia) <= (V ? V[ta] : 0u)) continue;
+            const u32 slot = atomicAdd(&P->gw_pairs, 1u);
+            if (slot < G.cap) {
+                G.pf[0][slot] = ia;
+                G.ps[0][slot] = ib;
+            } else {
+                atomicOr(&P->err, ERR_GWPAIRS);
+            }
+        }
+    }
+}
+
+__global__ void k_gw_kept(DevParams *P, u64 cap) {
+    if (threadIdx.x == 0) P->gw_kept = P->gw_pairs < cap ? P->gw_pairs : (u32)cap;
+}
+
+// Pool layout: four pair arrays and the report (6 words per pair of `cap`), the counters, then the
+// heap.  False when the pool cannot hold the pairs, the counters and the dense clocks.
+bool gwcp_layout(const Bufs &b, u64 cap, GwcpBufs &G) {
+    const u64 fixed = 6 * cap + GH_WORDS;
+    const u64 clocks = 2ull * b.T * b.T + (u64)b.T * (GW_HELD + 8) + b.wo_cap;
+    if (b.T > GW_MAX_T || b.pool_words < fixed + clocks) return false;
+    u32 *p = b.pool;
+    G.pf[0] = p; G.ps[0] = p + cap; G.pf[1] = p + 2 * cap; G.ps[1] = p + 3 * cap;
+    G.report = (u64 *)(p + 4 * cap);  // 8-byte aligned: the pool starts 256-byte aligned
+    G.cap = cap;
+    G.hdr = p + 6 * cap;
+    G.heap = G.hdr + GH_WORDS;
+    G.heap_words = b.pool_words - fixed;
+    G.n_after = b.e_prev0;
+    G.depth = b.e_prev1;
+    G.snap = b.e_src0;
+    G.evsnap = b.e_src1;
+    G.evchk = b.e_cur;
+    G.barsnap = b.inst_opo;
+    return true;
+}
+
+void gwcp_run(const Bufs &b, const GwcpBufs &G, hipStream_t s) {
+    const unsigned gn = (unsigned)((b.N + 256) / 256 > 8192 ? 8192 : (b.N + 256) / 256);
+    const unsigned gt = (unsigned)((b.T + 255) / 256 > 2048 ? 2048 : ((b.T + 255) / 256 ? (b.T + 255) / 256 : 1));
+    RD_LAUNCH("k_gw_init", k_gw_init, dim3(1), dim3(64), 0, s, b.prm, G.hdr);
+    RD_LAUNCH("k_gw_thread", k_gw_thread, dim3(gt), dim3(256), 0, s, b, G);
+    RD_LAUNCH("k_gw_mark", k_gw_mark, dim3(gn), dim3(256), 0, s, b, G, b.e_scan0);
+    scan_exclusive(b.e_scan0, (u64)b.N + 1, b.part, s);
+    RD_LAUNCH("k_gw_list", k_gw_list, dim3(gn), dim3(256), 0, s, b, (const u32 *)b.e_scan0, b.e_scan1);
+    RD_LAUNCH("k_gw_clear", k_gw_clear, dim3(1024), dim3(256), 0, s, b, G);
+    RD_LAUNCH("k_gw_interp", k_gw_interp, dim3(1), dim3(GW_THREADS), 0, s, b, G, (const u32 *)b.e_scan0,
+              (const u32 *)b.e_scan1);
+    RD_LAUNCH("k_gw_post", k_gw_post, dim3(gt), dim3(256), 0, s, b, G, (const u32 *)b.e_scan0);
+    RD_LAUNCH("k_gw_check", k_gw_check, dim3(gn), dim3(256), 0, s, b, G, (const u32 *)b.e_scan0);
+    RD_LAUNCH("k_gw_kept", k_gw_kept, dim3(1), dim3(64), 0, s, b.prm, G.cap);
+    u32 *const f[2] = {G.pf[0], G.pf[1]}, *const s2[2] = {G.ps[0], G.ps[1]};
+    sort_pairs_to(b, f, s2, &b.prm->gw_kept, G.cap, s);
+    pack_pairs_to(G.pf[0], G.ps[0], &b.prm->gw_kept, G.cap, G.report, s);
+}
+
+}  // namespace rd

@@ -1100,6 +1100,51 @@ rd_status rd_lockset(rd_ctx ctx, rd_trace trace, rd_pair *out, uint64_t capacity
     return RD_OK;
 }
 
+rd_status rd_gwcp(rd_ctx ctx, rd_trace trace, rd_pair *out, uint64_t capacity, uint64_t *n_pairs) {
+    if (!ctx || !trace || !n_pairs || (capacity && !out)) return RD_EINVAL;
+    *n_pairs = 0;
+    if (!trace->ws) return set_err(ctx, RD_ESTATE, UINT64_MAX, "the GWCP pass needs the trace's own workspace");
+    if (trace->bufs.T > GW_MAX_T)
+        return set_err(ctx, RD_EINVAL, UINT64_MAX, "the GWCP pass keeps dense clocks: at most 4096 threads");
+    if (hipSetDevice(ctx->device) != hipSuccess) return set_err(ctx, RD_EHIP, UINT64_MAX, "hipSetDevice failed");
+    GwcpBufs G;
+    if (!gwcp_layout(trace->bufs, trace->bufs.max_pairs, G))
+        return set_err(ctx, RD_ENOMEM, UINT64_MAX, "the knowledge-vector pool cannot hold the GWCP pass's pairs and clocks");
+    // a check of its own (the pass reads its sync lists, barrier instances and sorted accesses), then
+    // the pass, on the trace's stream; the trace's report afterwards is that check's
+    trace->batch.reset();
+    trace->cached = 0;
+    trace->bufs.sort_variant = ctx->sort_variant;
+    trace->bufs.radix_bits = kSortVariants[ctx->sort_variant].rb;
+    Profiler *saved = g_prof;
+    g_prof = ctx->prof.filter.empty() ? nullptr : &ctx->prof;
+    hipError_t e = enqueue_plain(trace->bufs, trace->masks, trace->rt_scan, trace->stream);
+    if (e == hipSuccess) {
+        gwcp_run(trace->bufs, G, trace->stream);
+        e = hipGetLastError();
+    }
+    g_prof = saved;
+    if (e != hipSuccess) return set_err(ctx, RD_EHIP, UINT64_MAX, hipGetErrorString(e));
+    trace->checked = 1;
+    DevParams prm;
+    if (hipMemcpyAsync(&prm, trace->bufs.prm, sizeof(prm), hipMemcpyDeviceToHost, trace->stream) != hipSuccess ||
+        hipStreamSynchronize(trace->stream) != hipSuccess)
+        return set_err(ctx, RD_EHIP, UINT64_MAX, "reading the check state failed");
+    const rd_status se = state_error(ctx, prm);
+    if (se != RD_OK) return se;
+    if (prm.err & ERR_GWCP)
+        return set_err(ctx, RD_ENOMEM, UINT64_MAX,
+                       "a thread holds more than 64 locks at once, or the GWCP clocks exceed the knowledge-vector pool");
+    *n_pairs = prm.gw_pairs;
+    if (prm.err & ERR_GWPAIRS) return set_err(ctx, RD_ENOMEM, UINT64_MAX, "GWCP pairs exceed rd_limits.max_pairs");
+    const u64 m = prm.gw_kept, k = capacity < m ? capacity : m;
+    if (k && (hipMemcpyAsync(out, G.report, 8 * k, hipMemcpyDeviceToHost, trace->stream) != hipSuccess ||
+              hipStreamSynchronize(trace->stream) != hipSuccess))
+        return set_err(ctx, RD_EHIP, UINT64_MAX, "copying the GWCP pairs failed");
+    if (capacity < m) return set_err(ctx, RD_ETRUNC, UINT64_MAX, "more GWCP pairs than capacity");
+    return RD_OK;
+}
+
 rd_status rd_race_kinds(rd_ctx ctx, rd_trace trace, rd_race_kind *out, uint64_t capacity, uint64_t *n_kinds) {
     if (!ctx || !trace || !n_kinds || (capacity && !out)) return RD_EINVAL;
     *n_kinds = 0;
@@ -1486,7 +1531,7 @@ rd_status rd_trace_stats(rd_ctx ctx, rd_trace trace, rd_stats *out) {
     for (int k = 0; k < 8; k++) out->kind_count[k] = prm.kind_count[k];
     out->key_bits = prm.key_bits;
     out->max_phase = prm.max_phase;
-    out->packed = packed_elements(prm.key_bits, prm.max_phase) ? 1u : 0u;
+    out->packed = packed_elements(prm.key_bits, prm.max_phase) ? 1u : tinfo_elements(prm.key_bits, prm.max_phase, trace->bufs.T) ? 2u : 0u;
     const bool sync = (prm.mode & MODE_SYNC) != 0;
     const bool par = sync && (prm.eng & ENG_PARALLEL) && !(prm.eng & ENG_FALLBACK);
     out->engine = !sync ? 0u : (par ? 1u : 2u);

@@ -49,6 +49,16 @@ __host__ __device__ inline u32 pack_element(u32 key, u32 key_bits, u32 cat, u32 
 __host__ __device__ inline u32 packed_info(u32 word, u32 key_bits) {
     return info_make((word >> key_bits) & 3u, key_bits + 2 >= 32 ? 0u : word >> (key_bits + 2));
 }
+// Otherwise, when the thread id, the category and the largest phase fit in 32 bits together, the
+// thread word holds tid | category << tid_bits | phase << (tid_bits + 2) and the info array is not
+// written either (three arrays move in the sort).
+__host__ __device__ inline u32 tid_bits(u32 T) { return T > 1 ? bits_of(T - 1) : 1u; }
+__host__ __device__ inline bool tinfo_elements(u32 key_bits, u32 max_phase, u32 T) {
+    return !packed_elements(key_bits, max_phase) && tid_bits(T) + 2 + bits_of(max_phase) <= 32;
+}
+__host__ __device__ inline u32 tinfo_word(u32 tid, u32 tb, u32 cat, u32 phase) {
+    return tid | (cat << tb) | (tb + 2 >= 32 ? 0u : phase << (tb + 2));
+}
 
 // sync-entry flags (per entry of the per-thread sync lists)
 enum : uint8_t {
@@ -72,6 +82,8 @@ enum : u32 {
     ERR_LOCKSET = 128,  // lockset pass: a thread held more than LS_MAX locks, or the row table is full
     ERR_LSPAIRS = 256,  // lockset pass: more pairs than its buffer holds
     ERR_RESPEC = 512,   // the trace needs a stage the launched pass was built without (SPEC_*)
+    ERR_GWCP = 1024,    // GWCP pass: a thread held more than 64 locks, or its clocks exceed the pool
+    ERR_GWPAIRS = 2048, // GWCP pass: more pairs than its buffer holds
 };
 
 // Stages a pass can be built without (Bufs::spec), for the kinds of trace its last check saw; the
@@ -136,6 +148,8 @@ struct DevParams {
     u32 max_phase;         // the largest barrier phase of any thread
     u32 ls_pairs;          // lockset pass: pairs found (may exceed its buffer)
     u32 ls_kept;           // ... min(ls_pairs, its buffer)
+    u32 gw_pairs;          // GWCP pass: pairs found (may exceed its buffer)
+    u32 gw_kept;           // ... min(gw_pairs, its buffer)
     unsigned long long n_chunks;  // queued slow-path chunks of the segment check (8-byte aligned)
 };
 
@@ -332,7 +346,9 @@ struct SegCtx {
     u32 *cpos, *clo, *chi;  // the queue of slow-path chunks (in the sort's free buffers)
     u32 n;
     bool packed;            // category and phase in the key word, above key_bits
+    bool tinfo;             // category and phase in the thread word, above tbits
     u32 key_bits, kmask;
+    u32 tbits, tmask;
 };
 
 __device__ inline SegCtx seg_ctx(const Bufs &b) {
@@ -342,16 +358,21 @@ __device__ inline SegCtx seg_ctx(const Bufs &b) {
     SegCtx s; s.k = b.ekey[c]; s.i = b.eidx[c]; s.t = b.etid[c]; s.f = b.einfo[c]; s.n = b.prm->n_acc;
     s.cpos = b.ekey[c ^ 1]; s.clo = b.etid[c ^ 1]; s.chi = b.einfo[c ^ 1];
     s.packed = packed_elements(bits, b.prm->max_phase);
+    s.tinfo = tinfo_elements(bits, b.prm->max_phase, b.T);
     s.key_bits = bits;
     s.kmask = s.packed ? key_mask(bits) : ~0u;
+    s.tbits = tid_bits(b.T);
+    s.tmask = s.tinfo ? key_mask(s.tbits) : ~0u;
     return s;
 }
 
 // the location key and the info (category | phase) of sorted element p
 __device__ inline u32 seg_key(const SegCtx &s, u64 p) { return s.k[p] & s.kmask; }
 __device__ inline u32 seg_info(const SegCtx &s, u64 p) {
-    return s.packed ? packed_info(s.k[p], s.key_bits) : s.f[p];
+    return s.packed ? packed_info(s.k[p], s.key_bits) : s.tinfo ? packed_info(s.t[p], s.tbits) : s.f[p];
 }
+// the thread of sorted element p
+__device__ inline u32 seg_tid(const SegCtx &s, u64 p) { return s.t[p] & s.tmask; }
 
 // The knowledge handle of thread t at its access with trace index idx and barrier phase ph (block
 // blk), 0 for none.  A thread without acquires of its own knows, after its k-th barrier, what its

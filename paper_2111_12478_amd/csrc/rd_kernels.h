@@ -74,6 +74,23 @@ struct LocksetBufs {
 bool lockset_layout(const Bufs &b, u64 cap, LocksetBufs &L);
 void lockset_run(const Bufs &b, const LocksetBufs &L, hipStream_t s);
 
+// GWCP pass (rd_gwcp.hip), after a check, in the knowledge-vector pool and the engine's per-entry
+// scratch; dense clocks: at most GW_MAX_T threads
+constexpr u32 GW_MAX_T = 4096;
+struct GwcpBufs {
+    u32 *pf[2], *ps[2];  // pair ping-pong buffers, `cap` each
+    u64 *report;         // sorted pairs as (first, second) records, `cap`
+    u64 cap;
+    u32 *hdr;            // counters
+    u32 *heap;           // clocks and tables (carved on the device)
+    u64 heap_words;
+    u32 *n_after, *depth, *snap;  // [sync entries] local time, sections open, copy of P after it
+    u32 *evsnap, *evchk;          // [events at which P can change] copy of P after it, seen by its check
+    u32 *barsnap;                 // [barrier instances] copy of P the instance leaves
+};
+bool gwcp_layout(const Bufs &b, u64 cap, GwcpBufs &G);
+void gwcp_run(const Bufs &b, const GwcpBufs &G, hipStream_t s);
+
 // batched form: merged trace from the members' events; each member's run of the merged report
 void batch_merge(BatchTrace *tr, const u32 *off, u32 n_traces, u32 N, u32 tpb_merged, uint4 *out, u32 *bad,
                  hipStream_t s);

@@ -133,7 +133,7 @@ __global__ __launch_bounds__(256) void k_ls_check(Bufs b, const u32 *row_of, con
     const SegCtx s = seg_ctx(b);
     for (u64 pos = (u64)blockIdx.x * blockDim.x + threadIdx.x; pos < s.n; pos += (u64)gridDim.x * blockDim.x) {
         if (pos == 0) continue;
-        const u32 kb = seg_key(s, pos), ib = s.i[pos], tb = s.t[pos], cb = info_cat(seg_info(s, pos));
+        const u32 kb = seg_key(s, pos), ib = s.i[pos], tb = seg_tid(s, pos), cb = info_cat(seg_info(s, pos));
         if (ls_access_is_lockop(b, tb, ib, cb)) continue;
         // the previous access of the location that is not a lock operation
         u64 q = pos;
@@ -143,7 +143,7 @@ __global__ __launch_bounds__(256) void k_ls_check(Bufs b, const u32 *row_of, con
             q--;
             if (seg_key(s, q) != kb) break;
             ia = s.i[q];
-            ta = s.t[q];
+            ta = seg_tid(s, q);
             ca = info_cat(seg_info(s, q));
             if (!ls_access_is_lockop(b, ta, ia, ca)) { found = true; break; }
         }

@@ -583,6 +583,8 @@ __global__ __launch_bounds__(WG_THREADS) void k_elements(Bufs b, const u64 *acc_
     const u32 mode = p->mode;
     const u32 np = (p->key_bits + rb - 1) / rb;
     const bool packed = packed_elements(p->key_bits, p->max_phase);
+    const bool tinfo = tinfo_elements(p->key_bits, p->max_phase, b.T);
+    const u32 tb = tid_bits(b.T);
     const bool lists = (mode & (MODE_SYNC | MODE_BAR)) != 0;
     u32 *ekey = b.ekey[0], *eidx = b.eidx[0], *etid = b.etid[0], *einfo = b.einfo[0];
     const u64 base = (u64)blockIdx.x * TILE + (u64)w * ITEMS * 64;
@@ -675,12 +677,16 @@ __global__ __launch_bounds__(WG_THREADS) void k_elements(Bufs b, const u64 *acc_
                 const u32 o = slot[k0 + i];
                 if (packed) {
                     ekey[o] = pack_element(key, p->key_bits, cat, ph[i]);
+                    etid[o] = t[i];
+                } else if (tinfo) {
+                    ekey[o] = key;
+                    etid[o] = tinfo_word(t[i], tb, cat, ph[i]);
                 } else {
                     ekey[o] = key;
                     einfo[o] = info_make(cat, ph[i]);
+                    etid[o] = t[i];
                 }
                 eidx[o] = idx[i];
-                etid[o] = t[i];
             }
             // digit counts: where every active lane has the wavefront's first digit (high digits of
             // clustered addresses), one lane adds them all instead of 64 atomics on one LDS word

@@ -42,6 +42,8 @@ struct Agg {
     u32 first_key, last_key;
     u32 run_blk, run_ph;
     u32 blk, blk2;       // up to two blocks of the last segment (blk2: a second one, or NONE)
+    u32 pw1, pa1;        // blk's latest phase + 1 of a write-ish access, of any access (0: none)
+    u32 pw2, pa2;        // ... of blk2
     u32 twa, tna, tall;  // a thread of the trailing run: write-ish, plain, any (NONE if none)
     u32 fl;
     u32 first_pos;       // sorted position of the first element of the range
@@ -56,11 +58,14 @@ __device__ inline void set1_merge(u32 &v, u32 &fl, u32 multi_bit, u32 ov, u32 of
     if ((ofl & multi_bit) || (ov != NONE && v != NONE && ov != v)) fl |= multi_bit;
     if (v == NONE) v = ov;
 }
-// a set of up to two members and a "more than two" flag
-__device__ inline void set2_add(u32 &a, u32 &c, u32 &fl, u32 x) {
-    if (x == NONE || x == a || x == c) return;
-    if (a == NONE) a = x;
-    else if (c == NONE) c = x;
+// up to two blocks with their latest phases (+1) of write-ish and of any accesses, and a "more
+// than two" flag: block x with phases (w, a) joins the set
+__device__ inline void blk_add(u32 &b1, u32 &b2, u32 &w1, u32 &a1, u32 &w2, u32 &a2, u32 &fl, u32 x, u32 w, u32 a) {
+    if (x == NONE) return;
+    if (x == b1) { w1 = max(w1, w); a1 = max(a1, a); }
+    else if (x == b2) { w2 = max(w2, w); a2 = max(a2, a); }
+    else if (b1 == NONE) { b1 = x; w1 = w; a1 = a; }
+    else if (b2 == NONE) { b2 = x; w2 = w; a2 = a; }
     else fl |= F_BLK3;
 }
 __device__ inline bool set1_has_other(u32 v, u32 fl, u32 multi_bit, u32 x) {
@@ -71,6 +76,7 @@ __device__ inline void agg_empty(Agg &a) {
     a.first_key = a.last_key = 0;
     a.run_blk = a.run_ph = 0;
     a.blk = a.blk2 = a.twa = a.tna = a.tall = NONE;
+    a.pw1 = a.pa1 = a.pw2 = a.pa2 = 0;
     a.fl = F_RUNWHOLE;
     a.first_pos = a.seg_pos = a.run_pos = 0;
 }
@@ -78,6 +84,9 @@ __device__ inline void agg_one(Agg &a, u32 key, u32 blk, u32 ph, u32 tid, u32 ca
     a.first_pos = a.seg_pos = a.run_pos = pos;
     a.first_key = a.last_key = key;
     a.run_blk = blk; a.run_ph = ph; a.blk = blk; a.blk2 = NONE;
+    a.pw1 = cat != CAT_R ? ph + 1 : 0u;
+    a.pa1 = ph + 1;
+    a.pw2 = a.pa2 = 0;
     a.tall = tid;
     a.twa = cat != CAT_R ? tid : NONE;
     a.tna = cat <= CAT_W ? tid : NONE;
@@ -92,14 +101,17 @@ __device__ inline void agg_combine(const Agg &l, Agg &r) {
     const bool extend = !boundary && (r.fl & F_RUNWHOLE) && r.run_blk == l.run_blk && r.run_ph == l.run_ph;
     u32 fl = F_NONEMPTY | ((l.fl | r.fl) & F_HEAD) | (keychange ? F_HEAD : 0u);
     if (!boundary) {
+        // the blocks of the segment (up to two tracked) with their latest phases: phases of one
+        // block at one location never decrease in trace order, so the latest is the largest
         u32 bfl = (l.fl | r.fl) & (F_BLKMULTI | F_BLK3);
-        u32 bv = l.blk, bv2 = l.blk2;
-        set2_add(bv, bv2, bfl, r.blk);
-        set2_add(bv, bv2, bfl, r.blk2);
+        u32 bv = l.blk, bv2 = l.blk2, w1 = l.pw1, a1 = l.pa1, w2 = l.pw2, a2 = l.pa2;
+        blk_add(bv, bv2, w1, a1, w2, a2, bfl, r.blk, r.pw1, r.pa1);
+        blk_add(bv, bv2, w1, a1, w2, a2, bfl, r.blk2, r.pw2, r.pa2);
         if (bv2 != NONE) bfl |= F_BLKMULTI;
         fl |= bfl | ((l.fl | r.fl) & F_CATS);
         r.blk = bv;
         r.blk2 = bv2;
+        r.pw1 = w1; r.pa1 = a1; r.pw2 = w2; r.pa2 = a2;
     } else {
         fl |= r.fl & (F_BLKMULTI | F_BLK3 | F_CATS);
     }
@@ -136,7 +148,7 @@ __device__ inline void load_items(const SegCtx &s, u64 base, Items &it) {
             const uint4 t4 = *(const uint4 *)(s.t + base + q);
             it.key[q] = k4.x; it.key[q + 1] = k4.y; it.key[q + 2] = k4.z; it.key[q + 3] = k4.w;
             it.tid[q] = t4.x; it.tid[q + 1] = t4.y; it.tid[q + 2] = t4.z; it.tid[q + 3] = t4.w;
-            if (!s.packed) {
+            if (!s.packed && !s.tinfo) {
                 const uint4 f4 = *(const uint4 *)(s.f + base + q);
                 it.info[q] = f4.x; it.info[q + 1] = f4.y; it.info[q + 2] = f4.z; it.info[q + 3] = f4.w;
             }
@@ -148,7 +160,7 @@ __device__ inline void load_items(const SegCtx &s, u64 base, Items &it) {
             const bool in = pos < s.n;
             it.key[q] = in ? s.k[pos] : 0;
             it.tid[q] = in ? s.t[pos] : 0;
-            it.info[q] = in && !s.packed ? s.f[pos] : 0;
+            it.info[q] = in && !s.packed && !s.tinfo ? s.f[pos] : 0;
         }
     }
     if (s.packed) {
@@ -156,6 +168,12 @@ __device__ inline void load_items(const SegCtx &s, u64 base, Items &it) {
         for (int q = 0; q < ITEMS; q++) {
             it.info[q] = packed_info(it.key[q], s.key_bits);
             it.key[q] &= s.kmask;
+        }
+    } else if (s.tinfo) {
+#pragma unroll
+        for (int q = 0; q < ITEMS; q++) {
+            it.info[q] = packed_info(it.tid[q], s.tbits);
+            it.tid[q] &= s.tmask;
         }
     }
 }
@@ -182,6 +200,10 @@ __device__ inline Agg shfl_up_agg(const Agg &a, u32 d) {
     r.run_ph = __shfl_up(a.run_ph, d, 64);
     r.blk = __shfl_up(a.blk, d, 64);
     r.blk2 = __shfl_up(a.blk2, d, 64);
+    r.pw1 = __shfl_up(a.pw1, d, 64);
+    r.pa1 = __shfl_up(a.pa1, d, 64);
+    r.pw2 = __shfl_up(a.pw2, d, 64);
+    r.pa2 = __shfl_up(a.pa2, d, 64);
     r.twa = __shfl_up(a.twa, d, 64);
     r.tna = __shfl_up(a.tna, d, 64);
     r.tall = __shfl_up(a.tall, d, 64);
@@ -261,27 +283,28 @@ __global__ __launch_bounds__(WG_THREADS) void k_seg_reduce(Bufs b) {
 // range of tiles, read four at a time so that their loads overlap)
 constexpr u32 SCAN_THREADS = 1024;
 
-// Four consecutive summaries (a range starting at a multiple of four tiles) are 13 aligned 16-byte
-// vectors: loaded and stored as such.
-static_assert(sizeof(Agg) == 52, "four summaries are thirteen 16-byte vectors");
+// Four consecutive summaries (a range starting at a multiple of four tiles) are AGG_WORDS aligned
+// 16-byte vectors: loaded and stored as such.
+constexpr int AGG_WORDS = (int)(sizeof(Agg) / 4);
+static_assert(sizeof(Agg) % 4 == 0, "a summary is whole words");
 __device__ inline void agg_load4(const Agg *src, Agg v[4]) {
-    u32 w[52];
+    u32 w[4 * AGG_WORDS];
     const uint4 *p = (const uint4 *)src;
 #pragma unroll
-    for (int k = 0; k < 13; k++) {
+    for (int k = 0; k < AGG_WORDS; k++) {
         const uint4 x = p[k];
         w[4 * k] = x.x; w[4 * k + 1] = x.y; w[4 * k + 2] = x.z; w[4 * k + 3] = x.w;
     }
 #pragma unroll
-    for (int j = 0; j < 4; j++) __builtin_memcpy(&v[j], &w[13 * j], sizeof(Agg));
+    for (int j = 0; j < 4; j++) __builtin_memcpy(&v[j], &w[AGG_WORDS * j], sizeof(Agg));
 }
 __device__ inline void agg_store4(Agg *dst, const Agg v[4]) {
-    u32 w[52];
+    u32 w[4 * AGG_WORDS];
 #pragma unroll
-    for (int j = 0; j < 4; j++) __builtin_memcpy(&w[13 * j], &v[j], sizeof(Agg));
+    for (int j = 0; j < 4; j++) __builtin_memcpy(&w[AGG_WORDS * j], &v[j], sizeof(Agg));
     uint4 *p = (uint4 *)dst;
 #pragma unroll
-    for (int k = 0; k < 13; k++) p[k] = make_uint4(w[4 * k], w[4 * k + 1], w[4 * k + 2], w[4 * k + 3]);
+    for (int k = 0; k < AGG_WORDS; k++) p[k] = make_uint4(w[4 * k], w[4 * k + 1], w[4 * k + 2], w[4 * k + 3]);
 }
 
 __global__ __launch_bounds__(SCAN_THREADS) void k_seg_scan(Bufs b) {
@@ -406,7 +429,7 @@ __device__ inline void wave_slow_check(const Bufs &b, const SegCtx &s, const u32
         if (valid) {
             stop = seg_key(s, q) != key;
             if (!stop) {
-                ta = s.t[q];
+                ta = seg_tid(s, q);
                 info = seg_info(s, q);
                 ba = block_of(b, ta);
                 pha = info_phase(info);
@@ -432,6 +455,9 @@ enum : u32 {
     SLOW_RUN = 1,   // only b's run (same block and phase) can: chunks over the run
     SLOW_SEG = 2,   // three or more blocks before b: chunks over the whole segment prefix
     SLOW_WALK = 3,  // one or two blocks before b: a backward walk that stops early
+    SLOW_KNOW = 4,  // one or two other blocks have conflicting accesses, b's own block none in b's
+                    // phase: none races if b's thread knows each such block's latest conflicting
+                    // phase (bits 8 and 9: which of the summary's two blocks), else SLOW_WALK
 };
 
 // Does b's thread have knowledge at b (at sorted position pos)?  Without it no other block can be
@@ -453,7 +479,40 @@ __device__ inline u32 decide(const Agg &P, u32 key, u32 tid, u32 blk, u32 ph, u3
         return slow ? SLOW_RUN : SLOW_NONE;
     }
     if (!(P.fl & conflict_cats(cat))) return SLOW_NONE;
-    return (P.fl & F_BLK3) ? SLOW_SEG : SLOW_WALK;
+    if (P.fl & F_BLK3) return SLOW_SEG;
+    // one or two blocks: the latest phase (+1) of each one's accesses that can conflict with b
+    // (write-ish ones for a read, any for the others: a superset for atomics)
+    const u32 l1 = cat == CAT_R ? P.pw1 : P.pa1, l2 = cat == CAT_R ? P.pw2 : P.pa2;
+    u32 need = 0;
+    if (l1) {
+        if (P.blk != blk) need |= 1u << 8;
+        else if (l1 - 1 >= ph) return SLOW_WALK;  // b's block in b's phase: threads decide
+    }
+    if (l2 && P.blk2 != NONE) {
+        if (P.blk2 != blk) need |= 1u << 9;
+        else if (l2 - 1 >= ph) return SLOW_WALK;
+    }
+    return need ? (SLOW_KNOW | need) : SLOW_NONE;
+}
+
+// SLOW_KNOW: each other block with conflicting accesses is ordered before b when b's thread knows a
+// later phase of it than its latest conflicting access (the accesses of one block to one location
+// have non-decreasing phase); otherwise the walk decides.
+__device__ inline u32 settle_known(const Bufs &b, const SegCtx &s, const Agg &P, u32 mode, u32 tid, u32 blk, u32 ph,
+                                   u32 cat, u32 pos) {
+    if (!(b.prm->mode & MODE_SYNC)) return SLOW_WALK;
+    const u32 h = knowledge_at(b, tid, s.i[pos], blk, ph);
+    if (!h) return SLOW_WALK;
+    const u32 *V = b.pool + (u64)h * b.prm->D;
+    if (mode & (1u << 8)) {
+        const u32 l = cat == CAT_R ? P.pw1 : P.pa1;
+        if (V[P.blk] < l) return SLOW_WALK;  // V[X] > latest phase, i.e. V[X] >= l
+    }
+    if (mode & (1u << 9)) {
+        const u32 l = cat == CAT_R ? P.pw2 : P.pa2;
+        if (V[P.blk2] < l) return SLOW_WALK;
+    }
+    return SLOW_NONE;
 }
 
 // Queue entries, one wavefront each: chunk (pos, lo, hi) = check b at pos against positions [lo, hi).
@@ -509,7 +568,7 @@ __device__ inline Walker walker_at(const Bufs &b, const SegCtx &s, u32 pos) {
     Walker w;
     w.pos = pos;
     w.key = seg_key(s, pos);
-    w.btid = s.t[pos];
+    w.btid = seg_tid(s, pos);
     w.bidx = s.i[pos];
     const u32 info = seg_info(s, pos);
     w.bblk = block_of(b, w.btid);
@@ -611,7 +670,7 @@ __device__ void lane_walks(const Bufs &b, const SegCtx &s, const u32 *rt_scan, u
             const bool ok = act && top > j;
             const u32 q = ok ? top - 1 - j : 0u;
             kq[j] = ok ? seg_key(s, q) : w.key ^ 1u;
-            tq[j] = ok ? s.t[q] : 0u;
+            tq[j] = ok ? seg_tid(s, q) : 0u;
             fq[j] = ok ? seg_info(s, q) : 0u;
         }
 #pragma unroll
@@ -676,8 +735,9 @@ __global__ __launch_bounds__(WG_THREADS) void k_seg_check(Bufs b, const u32 *rt_
             if ((u32)q >= cnt) continue;
             const u32 key = it.key[q], tid = it.tid[q], info = it.info[q];
             const u32 cat = info_cat(info), ph = info_phase(info), blk = block_of(b, tid);
-            const u32 mode = decide(P, key, tid, blk, ph, cat);
             const u32 pos = (u32)(base + q);
+            u32 mode = decide(P, key, tid, blk, ph, cat);
+            if ((mode & 0xffu) == SLOW_KNOW) mode = settle_known(b, s, P, mode, tid, blk, ph, cat, pos);
             if (mode == SLOW_WALK && knows_at(b, s, tid, pos)) {
                 walk_bits |= 1u << q;
                 if (P.fl & F_BLKMULTI) two_bits |= 1u << q;
@@ -745,7 +805,7 @@ __global__ __launch_bounds__(WG_THREADS) void k_seg_check(Bufs b, const u32 *rt_
             const u32 l = (u32)__builtin_ctzll(m);
             m &= m - 1;
             const u32 pos = (u32)(tile0 + (u64)(wv * 64 + l) * ITEMS + q);
-            const u32 tid = s.t[pos], info = seg_info(s, pos);
+            const u32 tid = seg_tid(s, pos), info = seg_info(s, pos);
             wave_slow_check(b, s, rt_scan, pos, seg_key(s, pos), tid, block_of(b, tid), info_phase(info),
                             info_cat(info), (mr >> l) & 1u);
         }
@@ -778,9 +838,9 @@ __global__ __launch_bounds__(WG_THREADS) void k_seg_slow(Bufs b, const u32 *rt_s
             const u32 pos = s.cpos[c], lo = s.clo[c], hi = s.chi[c];
             const u32 q = lo + lane;
             if (q < hi) {
-                const u32 btid = s.t[pos], binfo = seg_info(s, pos);
+                const u32 btid = seg_tid(s, pos), binfo = seg_info(s, pos);
                 const u32 bblk = block_of(b, btid), bph = info_phase(binfo), bcat = info_cat(binfo);
-                const u32 ta = s.t[q], info = seg_info(s, q);
+                const u32 ta = seg_tid(s, q), info = seg_info(s, q);
                 const u32 ba = block_of(b, ta), pha = info_phase(info);
                 if (ta != btid && conflicts(info_cat(info), ba, bcat, bblk)) {
                     u32 h = NONE;

@@ -119,6 +119,7 @@ struct SweepArgs {
     const u32 *tot;       // digit totals of the pass ([pass][SORT_NDS])
     u32 *ctr, *err;
     const DevParams *prm;  // the element sort: packed elements move their first two payloads only
+    u32 T;                 // ... (threads of the trace: whether the thread word is packed)
 };
 
 constexpr int LOOKBACK = 4;  // predecessor words read at once per digit
@@ -133,7 +134,11 @@ __global__ __launch_bounds__(NW * 64) void k_sort_sweep(SweepArgs a) {
     if (a.bits_dev && a.shift >= *a.bits_dev) return;  // past the key width: the pass is not needed
     // digits come from the key bits only (packed elements carry more above them)
     const u32 kmask = a.bits_dev ? key_mask(*a.bits_dev) : ~0u;
-    const u32 np_run = NP == 3 && a.prm && packed_elements(a.prm->key_bits, a.prm->max_phase) ? 2u : (u32)NP;
+    const u32 np_run = NP == 3 && a.prm &&
+                               (packed_elements(a.prm->key_bits, a.prm->max_phase) ||
+                                tinfo_elements(a.prm->key_bits, a.prm->max_phase, a.T))
+                           ? 2u
+                           : (u32)NP;
     const u32 n = a.n_dev ? *a.n_dev : a.n_host;
     const u32 n_tiles = (u32)(((u64)n + TS - 1) / TS);
     const u32 w = threadIdx.x >> 6, lane = lane_id(), dme = threadIdx.x;  // digit dme when dme < ND
@@ -361,6 +366,7 @@ static void elem_passes(const Bufs &b, const u32 *n_dev, const u32 *bits, hipStr
         a.pout[1] = b.etid[o];
         a.pout[2] = b.einfo[o];
         a.prm = b.prm;
+        a.T = b.T;
         RD_LAUNCH(kSweepName[pass], (k_sort_sweep<3, RB, NW, NI>), dim3(tiles), dim3(NW * 64), 0, s, a);
     }
 }

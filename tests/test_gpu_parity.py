@@ -188,19 +188,45 @@ def test_report_length_changes_between_checks(rc):
         rd_trace_free(rc.ctx, tr)
 
 
+def _check_with_stats(rc, grid, ev):
+    from paper_2111_12478_amd import rd_trace_free, rd_trace_stats
+    tr, ws, keep = rc.prepare(grid, ev)
+    try:
+        res = rc.run(tr)
+        return res, (rd_trace_stats(rc.ctx, tr) if res.status == 0 else None)
+    finally:
+        rd_trace_free(rc.ctx, tr)
+
+
 @pytest.mark.parametrize("seed", list(range(7000, 7030)))
 def test_random_traces_wide_addresses(rc, seed):
     # global words spread over about 2^31 addresses: 32-bit location keys leave no room for the
-    # category and phase, so the elements are not packed (four arrays through the sort)
+    # category and phase, which ride in the thread word instead (three arrays through the sort)
     grid, ev = tracegen.random_trace(seed, max_blocks=4, max_tpb=16, max_events=3000)
     ev = ev.copy()
     glob = ((ev[:, 2] >> 6) & 1) == 0
     ev[glob, 0] = ev[glob, 0] * np.uint32(1 << 29)
     want = oracle.check(grid, ev)
-    got = rc.check(grid, ev)
+    got, stats = _check_with_stats(rc, grid, ev)
     assert got.status == want.status, (seed, got, want)
     if want.status == 0:
         np.testing.assert_array_equal(got.pairs, want.pairs, err_msg=f"seed {seed}")
+        if stats["key_bits"] + 2 + int(stats["max_phase"]).bit_length() > 32:
+            assert stats["packed"] == 2, stats
+
+
+def test_elements_in_four_arrays(rc):
+    # 32-bit location keys, 65,536 threads and 16,384 barriers: neither the key word nor the thread
+    # word has room for the category and the phase, so the info array moves through the sort too
+    m = make_meta
+    ev = [(0, 0, m(KIND["W"]), 0)] + [(0, 0, m(KIND["BAR"]), 0)] * 16384
+    ev += [((1 << 31) + 5, 0, m(KIND["W"]), 0), (0, 0, m(KIND["R"]), 0)]
+    ev += [(0, 1, m(KIND["W"]), 0), ((1 << 31) + 5, 1, m(KIND["R"]), 0)]
+    ev = np.array(ev, dtype=np.uint32)
+    want = oracle.check((65536, 1), ev)
+    got, stats = _check_with_stats(rc, (65536, 1), ev)
+    assert got.status == 0 and stats["packed"] == 0, (got, stats)
+    np.testing.assert_array_equal(got.pairs, want.pairs)
 
 
 def test_device_resident_events(rc):

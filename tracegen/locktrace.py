@@ -22,14 +22,24 @@ BLK, DEV = 0, 1
 
 
 def lock_trace(seed: int, max_blocks: int = 3, max_tpb: int = 4, max_events: int = 300, barriers: bool = False,
-               flags: bool = False, inferred: bool = True):
-    """Returns (grid, events (N, 4) uint32)."""
+               flags: bool = False, inferred: bool = True, grid=None, locks: int | None = None,
+               data_words: int | None = None):
+    """Returns (grid, events (N, 4) uint32).  grid, locks (<= 64) and data_words fix what is
+    otherwise drawn: the grid, the number of lock words and of global data words (more than 100
+    data words start at word 4096)."""
     rng = np.random.default_rng(seed)
     nb = int(rng.integers(1, max_blocks + 1))
     tpb = int(rng.integers(1, max_tpb + 1))
+    if grid is not None:
+        nb, tpb = int(grid[0]), int(grid[1])
     T = nb * tpb
     n_locks = int(rng.integers(1, 4))
     n_data = int(rng.integers(1, 5))
+    if locks is not None:
+        n_locks = min(int(locks), 64)
+    if data_words is not None:
+        n_data = int(data_words)
+    data_base = 100 if n_data <= 100 else 4096
     n_shared = int(rng.integers(0, 2))
     n_phases = int(rng.integers(1, 3)) if barriers else 1
     budget = max(4, max_events // max(1, T))
@@ -38,7 +48,7 @@ def lock_trace(seed: int, max_blocks: int = 3, max_tpb: int = 4, max_events: int
         if n_shared and rng.random() < 0.25:
             space, addr = 1, int(rng.integers(0, n_shared))
         else:
-            space, addr = 0, 100 + int(rng.integers(0, n_data))
+            space, addr = 0, data_base + int(rng.integers(0, n_data))
         r = rng.random()
         kind = R if r < 0.45 else (W if r < 0.9 or not atomics else A)
         scope = int(rng.choice([0, 1])) if kind == A else 0
