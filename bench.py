@@ -687,7 +687,8 @@ def _served_cfg(i, n):
 def run_served(args, rc, with_oracle: bool) -> dict:
     """Poisson arrivals (rate, window) of check requests with sizes log-uniform on [102,400,
     8,388,608] events (256 threads per block, one block per 16,384 events, the mix of the large
-    trace, seed 5), answered by the request loop under a 64 GiB arena: open loop for latency, then
+    trace, seed 5; events in page-locked host memory), answered by the request loop under a 64 GiB
+    arena: open loop for latency, then
     the same requests submitted at once (saturated) for capacity; both again with one request per
     pass and one pass in flight (plain).  Requests draw their traces from a pool of distinct
     generated traces."""
@@ -705,6 +706,10 @@ def run_served(args, rc, with_oracle: bool) -> dict:
     workers = min(16, host_cores())
     with cf.ProcessPoolExecutor(max_workers=workers) as ex:
         pool = list(ex.map(_gen_member, cfgs, chunksize=1))
+    # the requests' events in page-locked host memory (as a serving front end would receive them),
+    # so the copies into the arena run at the link's rate
+    pinned = [torch.from_numpy(ev.view(np.int32)).pin_memory() for _, ev in pool]
+    pool = [(g, t.numpy().view(np.uint32)) for (g, _), t in zip(pool, pinned)]
     say(f"served: {n_req} requests over {args.served_seconds:.0f} s from {len(pool)} distinct traces")
     alone = [rc.check(g, ev) for g, ev in pool]  # each distinct trace checked alone (plain)
     budget = 64 << 30

@@ -625,18 +625,24 @@ __device__ void eval_bar(const Bufs &b, u32 p, u32 D, u32 *lds_list, u32 *lds_n,
             const u32 i = base + e * ENG_THREADS + threadIdx.x;
             v[e] = lprev && i < D4 ? prev[i] : make_uint4(0, 0, 0, 0);
         }
-        for (u32 c = 0; c < nc; c++) {
-            const u32 h = lds_list[c];
-            if (h >= hint) continue;
-            const uint4 *src = (const uint4 *)vecp(b, D, h);
-            uint4 w[EV];
+        // the inputs four at a time, all their loads issued before the joins
+        for (u32 c0 = 0; c0 < nc; c0 += 4) {
+            uint4 w[4][EV];
 #pragma unroll
-            for (u32 e = 0; e < EV; e++) {
-                const u32 i = base + e * ENG_THREADS + threadIdx.x;
-                w[e] = i < D4 ? src[i] : make_uint4(0, 0, 0, 0);
+            for (u32 j = 0; j < 4; j++) {
+                const u32 h = c0 + j < nc ? lds_list[c0 + j] : 0u;
+                const bool use = h != 0 && h < hint;  // (the empty vector, handle 0, is not read)
+                const uint4 *src = (const uint4 *)vecp(b, D, use ? h : 0u);
+#pragma unroll
+                for (u32 e = 0; e < EV; e++) {
+                    const u32 i = base + e * ENG_THREADS + threadIdx.x;
+                    w[j][e] = use && i < D4 ? src[i] : make_uint4(0, 0, 0, 0);
+                }
             }
 #pragma unroll
-            for (u32 e = 0; e < EV; e++) v[e] = max4(v[e], w[e]);
+            for (u32 j = 0; j < 4; j++)
+#pragma unroll
+                for (u32 e = 0; e < EV; e++) v[e] = max4(v[e], w[j][e]);
         }
 #pragma unroll
         for (u32 e = 0; e < EV; e++) {
@@ -927,6 +933,8 @@ __global__ __launch_bounds__(ENG_THREADS) void k_eng_eval(Bufs b, const u32 *rt_
     __shared__ u32 lds_jobs[CH_BLK * ENG_JOB_WORDS];
     __shared__ ChainLds lds_chain;
     __shared__ u32 lds_part[CH_BLK_JOBS * 64];
+    __shared__ u32 lds_ops[ENG_THREADS];
+    __shared__ u32 lds_nops;
     const u32 D = P->D, ng = P->n_groups;
     u32 round = 0;
     if (blockIdx.x == 0) {
@@ -940,8 +948,28 @@ __global__ __launch_bounds__(ENG_THREADS) void k_eng_eval(Bufs b, const u32 *rt_
     while (g < ng) {
         const u32 g0 = b.grp[g], g1 = b.grp[g + 1];
         if (g1 - g0 >= ENG_WIDE) {
-            for (u32 o = g0 + blockIdx.x; o < g1; o += gridDim.x)
-                eval_op(b, rt_scan, o, D, lds_list, &lds_n, NONE, none);
+            // the workgroup's operations g0 + blockIdx.x + k * gridDim.x, ENG_THREADS at a time: an
+            // acquire that only its thread's next barrier reads writes no vector and is marked by
+            // one lane (no loads beyond its entry); the others are evaluated one by one
+            for (u64 first = (u64)g0 + blockIdx.x; first < g1; first += (u64)ENG_THREADS * gridDim.x) {
+                const u64 o = first + (u64)threadIdx.x * gridDim.x;
+                bool keep = false;
+                if (o < g1) {
+                    const u32 p = b.op_p[o];
+                    const uint8_t f = b.s_flags[p];
+                    if (b.s_kind[p] != 4u && (f & SF_ACQ) && (f & SF_NOMAT) && !(f & SF_REL))
+                        b.op_dep[o] = OP_SKIPPED;
+                    else
+                        keep = true;
+                }
+                if (threadIdx.x == 0) lds_nops = 0;
+                __syncthreads();
+                if (keep) lds_ops[atomicAdd(&lds_nops, 1u)] = (u32)o;
+                __syncthreads();
+                const u32 nk = lds_nops;
+                for (u32 k = 0; k < nk; k++) eval_op(b, rt_scan, lds_ops[k], D, lds_list, &lds_n, NONE, none);
+                __syncthreads();
+            }
             g++;
             grid_barrier(P, ++round);
             continue;

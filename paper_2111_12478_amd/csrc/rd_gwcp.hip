@@ -39,10 +39,11 @@ namespace rd {
 constexpr u32 GW_HELD = 64;          // critical sections a thread may hold at once
 constexpr u32 GW_THREADS = 1024;     // the interpreter's workgroup
 constexpr u32 GW_DEV = 0xffffffffu;  // scope key of a device / system scoped lock
-constexpr u32 GW_CSW = 9;            // words of a critical-section row (see k_gw_interp)
+constexpr u32 GW_CSW = 8;            // words of a critical-section row (see k_gw_interp)
+constexpr u32 GW_NW = 5;             // words of a lock-clock row (see GwHeap::nodes)
 
 // counters at the head of the pass's pool area
-enum : u32 { GH_LOCKOPS = 0, GH_CSREC = 1, GH_WORDS = 16 };
+enum : u32 { GH_LOCKOPS = 0, GH_CSREC = 1, GH_NWORDS = 2, GH_WORDS = 16 };
 
 __device__ inline bool gw_lockop(const Bufs &b, u32 p) { return (b.s_flags[p] & (SF_REL | SF_ACQ)) != 0; }
 __device__ inline bool gw_overlap(u32 a, u32 c) { return a == GW_DEV || c == GW_DEV || a == c; }
@@ -69,6 +70,9 @@ __device__ inline u32 gw_entry(const Bufs &b, u32 t, u32 i) {
 // vectors of T words to the end.
 struct GwHeap {
     u32 *P, *H;        // [T][T]
+    u32 *J;            // [T][T] J[t][u]: u's latest local time at the release of a section whose
+                       // release time t has joined (rule (ii)): u's sections released no later
+                       // are covered, H_u being monotone
     u32 *N;            // [T] local times
     u32 *held_n;       // [T] critical sections held
     u32 *held;         // [T][GW_HELD] their rows
@@ -77,10 +81,16 @@ struct GwHeap {
     u32 *wsnap;        // [wo_cap] the copy a warp-barrier instance leaves
     u64 *wkey; u32 *wval; u32 cw;   // lock word -> word row
     u64 *lkey; u32 *lval; u32 cl;   // (lock clock, location, read / write) -> vector
-    u32 *words;        // [n_lock][4] word, queue head, queue tail, first lock clock
-    u32 *nodes;        // [n_lock][4] scope key, H vector, P vector, next lock clock of the word
+    u32 *words;        // [n_lock][4] word, its queue's offset in warr, sections queued, first lock clock
+    u32 *wcnt;         // [n_lock] sections each word will queue (counted before the walk)
+    u32 *warr;         // [n_lock] the words' queues: their sections in acquire order
+    u32 *nodes;        // [n_lock][GW_NW] scope key, H vector, P vector, next lock clock of the word,
+                       // L^r / L^w vectors made under it (0: none, no lookup needed)
     u32 *cs;           // [n_lock][GW_CSW] critical sections
     u32 *rec;          // [n_rec][3] location, write, next record of the section
+    u32 *wit;          // [n_lock] a thread whose word of section c's acquire time was above the
+                       // clock of the last thread that compared them (NONE: none yet): checked
+                       // first, it rejects most sections without a full comparison
     u32 n_lock, n_rec;
     u32 *vec;          // clock vectors
     u32 cap_vec;
@@ -106,6 +116,7 @@ __device__ inline GwHeap gw_carve(const GwcpBufs &G, u32 T, u32 wo_cap) {
     const u64 TT = (u64)T * T;
     m.P = take(TT);
     m.H = take(TT);
+    m.J = take(TT);
     m.N = take(T);
     m.held_n = take(T);
     m.held = take((u64)T * GW_HELD);
@@ -121,9 +132,12 @@ __device__ inline GwHeap gw_carve(const GwcpBufs &G, u32 T, u32 wo_cap) {
     m.n_lock = (u32)nl;
     m.n_rec = (u32)nr;
     m.words = take(4 * nl);
-    m.nodes = take(4 * nl);
+    m.wcnt = take(nl);
+    m.warr = take(nl);
+    m.nodes = take(GW_NW * nl);
     m.cs = take(GW_CSW * nl);
     m.rec = take(3 * nr);
+    m.wit = take(nl);
     m.ok = o <= G.heap_words && nl < (1u << 30) && nr < (1u << 30);
     const u64 rest = m.ok ? (G.heap_words - o) / (T ? T : 1) : 0;
     m.vec = G.heap + o;
@@ -177,6 +191,7 @@ __global__ void k_gw_thread(Bufs b, GwcpBufs G) {
         u32 n = 1, depth = 0, lockops = 0;
         u32 held[GW_HELD];
         for (u32 p = lo; p < hi; p++) {
+            u32 opens = 0;
             if ((P->mode & MODE_SYNC) && gw_lockop(b, p)) {
                 const uint8_t f = b.s_flags[p];
                 const u32 x = gw_loc(b, P, b.ev[b.s_pidx[p]]);
@@ -199,6 +214,7 @@ __global__ void k_gw_thread(Bufs b, GwcpBufs G) {
                             return;
                         }
                         held[depth++] = x;
+                        opens = 1;
                     }
                 }
             }
@@ -208,6 +224,7 @@ __global__ void k_gw_thread(Bufs b, GwcpBufs G) {
             if (kind == 4u || kind == 5u) n++;
             G.n_after[p] = n;
             G.depth[p] = depth;
+            G.snap[p] = opens;  // (snap is written again by k_gw_post, after the walk)
         }
         if (lockops) atomicAdd(&G.hdr[GH_LOCKOPS], lockops);
     }
@@ -279,6 +296,7 @@ __global__ void k_gw_clear(Bufs b, GwcpBufs G) {
     const u64 TT = (u64)T * T;
     for (u64 k = g; k < TT; k += stride) {
         m.P[k] = 0;
+        m.J[k] = 0;
         m.H[k] = k % ((u64)T + 1) == 0 ? 1u : 0u;  // the diagonal
     }
     for (u64 t = g; t < T; t += stride) {
@@ -287,7 +305,88 @@ __global__ void k_gw_clear(Bufs b, GwcpBufs G) {
         m.lastsnap[t] = NONE;
     }
     for (u64 s = g; s < m.cw; s += stride) m.wkey[s] = ~0ull;
+    for (u64 c = g; c < m.n_lock; c += stride) m.wit[c] = NONE;
     for (u64 s = g; s < m.cl; s += stride) m.lkey[s] = ~0ull;
+}
+
+// ---------------------------------------------------------------- lock words and their queues
+
+// Every lock operation's word joins the word table (lock-free inserts).
+__global__ void k_gw_words_insert(Bufs b, GwcpBufs G) {
+    const DevParams *P = b.prm;
+    if (!gw_active(P) || !(P->mode & MODE_SYNC)) return;
+    const GwHeap m = gw_carve(G, b.T, b.wo_cap);
+    if (!m.ok) return;
+    for (u32 p = blockIdx.x * blockDim.x + threadIdx.x; p < P->n_sync; p += gridDim.x * blockDim.x) {
+        if (!gw_lockop(b, p)) continue;
+        const u64 key = gw_loc(b, P, b.ev[b.s_pidx[p]]);
+        u32 sl = gw_hash(key, m.cw);
+        for (u32 probe = 0; probe < m.cw; probe++, sl = (sl + 1) & (m.cw - 1)) {
+            const u64 prev = atomicCAS((unsigned long long *)&m.wkey[sl], ~0ull, (unsigned long long)key);
+            if (prev == ~0ull || prev == key) break;
+        }
+    }
+}
+
+// A row per word of the table, its queue empty.
+__global__ void k_gw_words_rows(Bufs b, GwcpBufs G) {
+    DevParams *P = b.prm;
+    if (!gw_active(P) || !(P->mode & MODE_SYNC)) return;
+    const GwHeap m = gw_carve(G, b.T, b.wo_cap);
+    if (!m.ok) return;
+    for (u32 sl = blockIdx.x * blockDim.x + threadIdx.x; sl < m.cw; sl += gridDim.x * blockDim.x) {
+        const u64 key = m.wkey[sl];
+        if (key == ~0ull) continue;
+        const u32 w = atomicAdd(&G.hdr[GH_NWORDS], 1u);
+        m.wval[sl] = w;
+        m.words[(u64)w * 4] = (u32)key;
+        m.words[(u64)w * 4 + 1] = 0;
+        m.words[(u64)w * 4 + 2] = 0;
+        m.words[(u64)w * 4 + 3] = NONE;
+        m.wcnt[w] = 0;
+    }
+}
+
+// Sections each word will queue: one per acquire that opens one (k_gw_thread flagged them).
+__global__ void k_gw_words_count(Bufs b, GwcpBufs G) {
+    const DevParams *P = b.prm;
+    if (!gw_active(P) || !(P->mode & MODE_SYNC)) return;
+    const GwHeap m = gw_carve(G, b.T, b.wo_cap);
+    if (!m.ok) return;
+    for (u32 p = blockIdx.x * blockDim.x + threadIdx.x; p < P->n_sync; p += gridDim.x * blockDim.x) {
+        if (!G.snap[p]) continue;
+        const u32 w = gw_find(m.wkey, m.wval, m.cw, gw_loc(b, P, b.ev[b.s_pidx[p]]));
+        atomicAdd(&m.wcnt[w], 1u);
+    }
+}
+
+// The queues' offsets: an exclusive scan of the counts (one workgroup).
+__global__ __launch_bounds__(1024) void k_gw_words_off(Bufs b, GwcpBufs G) {
+    __shared__ u32 tot[1024];
+    const DevParams *P = b.prm;
+    if (!gw_active(P) || !(P->mode & MODE_SYNC)) return;
+    const GwHeap m = gw_carve(G, b.T, b.wo_cap);
+    if (!m.ok) return;
+    const u32 nw = G.hdr[GH_NWORDS], per = (nw + 1023) / 1024;
+    const u32 lo = min(threadIdx.x * per, nw), hi = min(lo + per, nw);
+    u32 sum = 0;
+    for (u32 w = lo; w < hi; w++) sum += m.wcnt[w];
+    tot[threadIdx.x] = sum;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        u32 run = 0;
+        for (u32 k = 0; k < 1024; k++) {
+            const u32 v = tot[k];
+            tot[k] = run;
+            run += v;
+        }
+    }
+    __syncthreads();
+    u32 off = tot[threadIdx.x];
+    for (u32 w = lo; w < hi; w++) {
+        m.words[(u64)w * 4 + 1] = off;
+        off += m.wcnt[w];
+    }
 }
 
 // ---------------------------------------------------------------- the interpreter
@@ -316,17 +415,19 @@ __device__ inline u32 gw_bcast(u32 v, u32 *slot) {
 
 // Critical-section row: [0] thread, [1] word row, [2] acquire key, [3] release key, [4] release
 // event (NONE while open), [5] vector of C_t at the acquire, [6] vector of H_t at the release,
-// [7] next section of the word in acquire order, [8] first read / write record.
+// [7] first read / write record.
 __global__ __launch_bounds__(GW_THREADS) void k_gw_interp(Bufs b, GwcpBufs G, const u32 *scan, const u32 *list) {
     DevParams *P = b.prm;
     if (!gw_active(P)) return;
     const u32 T = b.T, n_rel = scan[b.N];
     const GwHeap m = gw_carve(G, T, b.wo_cap);
     __shared__ u32 s_b;                                    // broadcast slot
-    __shared__ u32 s_vec, s_cs, s_words, s_nodes, s_rec;  // lane 0's allocation counters
+    __shared__ u32 s_vec, s_cs, s_nodes, s_rec;  // lane 0's allocation counters
     __shared__ u32 s_full;
+    __shared__ u32 s_cand[GW_THREADS], s_ncand, s_more;   // rule (ii)'s candidates
+    __shared__ u32 s_pt[GW_MAX_T];                         // ... and P_t meanwhile
     if (threadIdx.x == 0) {
-        s_vec = s_cs = s_words = s_nodes = s_rec = 0;
+        s_vec = s_cs = s_nodes = s_rec = 0;
         s_full = 0;
     }
     __syncthreads();
@@ -368,6 +469,7 @@ __global__ __launch_bounds__(GW_THREADS) void k_gw_interp(Bufs b, GwcpBufs G, co
             u32 *J = vec(hj);
             for (u32 w = threadIdx.x; w < T; w += GW_THREADS) {
                 u32 mj = 0, mh = 0;
+#pragma unroll 8
                 for (u32 u = ulo; u < uhi; u++) {
                     const bool part = kind == 4u ? b.act[u] != 0 : ((mask >> (u - wbase)) & 1u) != 0;
                     if (!part) continue;
@@ -412,8 +514,8 @@ __global__ __launch_bounds__(GW_THREADS) void k_gw_interp(Bufs b, GwcpBufs G, co
             const u32 nh = m.held_n[t];
             for (u32 q = 0; q < nh; q++) {
                 const u32 *C = m.cs + (u64)m.held[(u64)t * GW_HELD + q] * GW_CSW;
-                for (u32 nd = m.words[(u64)C[1] * 4 + 3]; nd != NONE; nd = m.nodes[(u64)nd * 4 + 3]) {
-                    if (!gw_overlap(m.nodes[(u64)nd * 4], C[2])) continue;
+                for (u32 nd = m.words[(u64)C[1] * 4 + 3]; nd != NONE; nd = m.nodes[(u64)nd * GW_NW + 3]) {
+                    if (!gw_overlap(m.nodes[(u64)nd * GW_NW], C[2]) || !m.nodes[(u64)nd * GW_NW + 4]) continue;
                     for (u32 rw = write ? 0u : 1u; rw < 2u; rw++) {
                         const u32 h = gw_find(m.lkey, m.lval, m.cl, gw_lkey(nd, x, rw));
                         if (h != NONE) pch |= gw_join(Pt, vec(h), T);
@@ -426,27 +528,14 @@ __global__ __launch_bounds__(GW_THREADS) void k_gw_interp(Bufs b, GwcpBufs G, co
                     const u32 rc = s_rec++;  // counted by k_gw_mark: always below n_rec
                     m.rec[(u64)rc * 3] = x;
                     m.rec[(u64)rc * 3 + 1] = write ? 1u : 0u;
-                    m.rec[(u64)rc * 3 + 2] = C[8];
-                    C[8] = rc;
+                    m.rec[(u64)rc * 3 + 2] = C[7];
+                    C[7] = rc;
                 }
             __syncthreads();
         } else {
             const uint8_t fl = b.s_flags[p], sc = b.s_scope[p];
-            // the word's row, created on first use
-            u32 wrow = 0;
-            if (threadIdx.x == 0) {
-                u32 *v = gw_insert(m.wkey, m.wval, m.cw, x);
-                if (*v == NONE) {
-                    const u32 w = s_words++;  // at most one per lock operation
-                    m.words[(u64)w * 4] = x;
-                    m.words[(u64)w * 4 + 1] = NONE;
-                    m.words[(u64)w * 4 + 2] = NONE;
-                    m.words[(u64)w * 4 + 3] = NONE;
-                    *v = w;
-                }
-                wrow = *v;
-            }
-            wrow = gw_bcast(wrow, &s_b);
+            // the word's row (every lock word has one: k_gw_words_rows)
+            const u32 wrow = gw_find(m.wkey, m.wval, m.cw, x);
             u32 *W = m.words + (u64)wrow * 4;
             if (fl & SF_REL) {
                 // RELEASE (Algorithm 1)
@@ -468,39 +557,98 @@ __global__ __launch_bounds__(GW_THREADS) void k_gw_interp(Bufs b, GwcpBufs G, co
                 if (ci != NONE) {
                     // rule (ii): another thread's released section of the word, released with an
                     // overlapping scope, whose acquire time is below C_t: its release time joins
-                    // P_t; again until a pass over the queue joins nothing new
+                    // P_t; again until a pass joins nothing new.  P_t lives in LDS meanwhile.  Every
+                    // lane screens one section of the word's queue at a time (most fail on their own
+                    // thread's word of the acquire time, or on a witness word); every wavefront then
+                    // compares one survivor at a time in full and joins it with LDS atomics.  Joins
+                    // only raise P_t, so a comparison that reads words another wavefront is raising
+                    // still decides against a clock P_t reaches, and the passes end at the same
+                    // least fixpoint as joins taken one by one
+                    for (u32 w = threadIdx.x; w < T; w += GW_THREADS) s_pt[w] = Pt[w];
+                    __syncthreads();
+                    const u32 qoff = W[1], qn = W[2], Nt = m.N[t];
+                    const u32 lane = threadIdx.x & 63u, wave = threadIdx.x >> 6;
+                    bool grew = false;
                     for (bool more = true; more;) {
-                        more = false;
-                        for (u32 f = W[1]; f != NONE; f = m.cs[(u64)f * GW_CSW + 7]) {
-                            const u32 *F = m.cs + (u64)f * GW_CSW;
-                            if (F[0] == t || F[4] == NONE || !gw_overlap(F[3], key)) continue;
-                            const u32 *A = vec(F[5]);
-                            // most sections fail on their own thread's word (every lane reads it)
-                            if (A[F[0]] > Pt[F[0]]) continue;
-                            bool above = false;
-                            for (u32 w = threadIdx.x; w < T; w += GW_THREADS)
-                                above |= A[w] > (w == t ? m.N[t] : Pt[w]);
-                            if (__syncthreads_or(above)) continue;
-                            if (gw_join(Pt, vec(F[6]), T)) {
-                                more = true;
-                                pch = true;
+                        if (threadIdx.x == 0) s_more = 0;
+                        __syncthreads();
+                        for (u32 c0 = 0; c0 < qn; c0 += GW_THREADS) {
+                            bool cand = false;
+                            u32 c = 0;
+                            if (c0 + threadIdx.x < qn) {
+                                c = m.warr[qoff + c0 + threadIdx.x];
+                                const u32 *F = m.cs + (u64)c * GW_CSW;
+                                if (F[0] != t && F[4] != NONE && gw_overlap(F[3], key)) {
+                                    // (covered when t has joined a later section's release time of
+                                    // the same thread)
+                                    const bool done = vec(F[6])[F[0]] <= m.J[(u64)t * T + F[0]];
+                                    const u32 *A = vec(F[5]);
+                                    const u32 wv = m.wit[c];
+                                    cand = !done && A[F[0]] <= s_pt[F[0]] &&
+                                           (wv == NONE || A[wv] <= (wv == t ? Nt : s_pt[wv]));
+                                }
                             }
+                            if (threadIdx.x == 0) s_ncand = 0;
+                            __syncthreads();
+                            if (cand) s_cand[atomicAdd(&s_ncand, 1u)] = c;
+                            __syncthreads();
+                            const u32 nc = s_ncand;
+                            for (u32 k = wave; k < nc; k += GW_THREADS / 64) {
+                                const u32 cc = s_cand[k];
+                                const u32 *F = m.cs + (u64)cc * GW_CSW;
+                                const u32 *A = vec(F[5]);
+                                u32 wfail = NONE;
+#pragma unroll 8
+                                for (u32 w = lane; w < T; w += 64)
+                                    if (A[w] > (w == t ? Nt : s_pt[w])) wfail = w;
+                                const u64 am = ballot(wfail != NONE);
+                                if (am) {
+                                    // a witness for the next comparisons
+                                    const u32 src = (u32)__builtin_ctzll(am);
+                                    const u32 wf = __shfl(wfail, (int)src, 64);
+                                    if (lane == 0) m.wit[cc] = wf;
+                                    continue;
+                                }
+                                const u32 *RH = vec(F[6]);
+                                if (lane == 0) atomicMax(&m.J[(u64)t * T + F[0]], RH[F[0]]);
+                                bool ch = false;
+#pragma unroll 8
+                                for (u32 w = lane; w < T; w += 64) {
+                                    const u32 v = RH[w];
+                                    if (v > s_pt[w]) {
+                                        atomicMax(&s_pt[w], v);
+                                        ch = true;
+                                    }
+                                }
+                                if (ballot(ch) && lane == 0) s_more = 1;
+                            }
+                            __syncthreads();  // s_cand and s_ncand are reused; the joins are done
                         }
+                        __syncthreads();
+                        more = s_more != 0;
+                        grew |= more;
+                        __syncthreads();  // s_more is reset next
+                    }
+                    if (grew) {
+                        for (u32 w = threadIdx.x; w < T; w += GW_THREADS) Pt[w] = s_pt[w];
+                        __syncthreads();
+                        pch = true;
                     }
                 }
                 // the lock clock of (word, key), created on first use
                 u32 nd = NONE, fresh = 0;
                 if (threadIdx.x == 0) {
                     nd = W[3];
-                    while (nd != NONE && m.nodes[(u64)nd * 4] != key) nd = m.nodes[(u64)nd * 4 + 3];
+                    while (nd != NONE && m.nodes[(u64)nd * GW_NW] != key) nd = m.nodes[(u64)nd * GW_NW + 3];
                     if (nd == NONE) {
                         const u32 hv = new_vec(), pv = new_vec();
                         if (hv != NONE && pv != NONE) {
                             nd = s_nodes++;  // at most one per release
-                            m.nodes[(u64)nd * 4] = key;
-                            m.nodes[(u64)nd * 4 + 1] = hv;
-                            m.nodes[(u64)nd * 4 + 2] = pv;
-                            m.nodes[(u64)nd * 4 + 3] = W[3];
+                            m.nodes[(u64)nd * GW_NW] = key;
+                            m.nodes[(u64)nd * GW_NW + 1] = hv;
+                            m.nodes[(u64)nd * GW_NW + 2] = pv;
+                            m.nodes[(u64)nd * GW_NW + 3] = W[3];
+                            m.nodes[(u64)nd * GW_NW + 4] = 0;
                             W[3] = nd;
                             fresh = 1;
                         }
@@ -509,14 +657,14 @@ __global__ __launch_bounds__(GW_THREADS) void k_gw_interp(Bufs b, GwcpBufs G, co
                 nd = gw_bcast(nd, &s_b);
                 if (nd == NONE) break;
                 fresh = gw_bcast(fresh, &s_b);
-                u32 *HL = vec(m.nodes[(u64)nd * 4 + 1]), *PL = vec(m.nodes[(u64)nd * 4 + 2]);
+                u32 *HL = vec(m.nodes[(u64)nd * GW_NW + 1]), *PL = vec(m.nodes[(u64)nd * GW_NW + 2]);
                 if (fresh) {
                     for (u32 w = threadIdx.x; w < T; w += GW_THREADS) HL[w] = PL[w] = 0;
                     __syncthreads();
                 }
                 if (ci != NONE) {
                     // L^r / L^w of (lock clock, x) join H_t for the section's reads / writes x
-                    const u32 head = m.cs[(u64)ci * GW_CSW + 8];
+                    const u32 head = m.cs[(u64)ci * GW_CSW + 7];
                     for (u32 rc = head; rc != NONE; rc = m.rec[(u64)rc * 3 + 2]) {
                         u32 h = NONE, nw = 0;
                         if (threadIdx.x == 0) {
@@ -524,6 +672,7 @@ __global__ __launch_bounds__(GW_THREADS) void k_gw_interp(Bufs b, GwcpBufs G, co
                             if (*v == NONE) {
                                 *v = new_vec();
                                 nw = 1;
+                                m.nodes[(u64)nd * GW_NW + 4] += 1;
                             }
                             h = *v;
                         }
@@ -561,10 +710,10 @@ __global__ __launch_bounds__(GW_THREADS) void k_gw_interp(Bufs b, GwcpBufs G, co
             if (fl & SF_ACQ) {
                 // ACQUIRE (Algorithm 1): P and H of every lock clock of the word whose scope overlaps
                 const u32 key = ((sc >> 2) & 3u) == 0 ? blk : GW_DEV;
-                for (u32 nd = W[3]; nd != NONE; nd = m.nodes[(u64)nd * 4 + 3]) {
-                    if (!gw_overlap(m.nodes[(u64)nd * 4], key)) continue;
-                    pch |= gw_join(Pt, vec(m.nodes[(u64)nd * 4 + 2]), T);
-                    gw_join(Ht, vec(m.nodes[(u64)nd * 4 + 1]), T);
+                for (u32 nd = W[3]; nd != NONE; nd = m.nodes[(u64)nd * GW_NW + 3]) {
+                    if (!gw_overlap(m.nodes[(u64)nd * GW_NW], key)) continue;
+                    pch |= gw_join(Pt, vec(m.nodes[(u64)nd * GW_NW + 2]), T);
+                    gw_join(Ht, vec(m.nodes[(u64)nd * GW_NW + 1]), T);
                 }
                 // a section opens unless the thread holds the word (Acq_l for the other threads)
                 u32 h = NONE;
@@ -578,10 +727,9 @@ __global__ __launch_bounds__(GW_THREADS) void k_gw_interp(Bufs b, GwcpBufs G, co
                             const u32 ci = s_cs++;  // at most one per acquire
                             u32 *C = m.cs + (u64)ci * GW_CSW;
                             C[0] = t; C[1] = wrow; C[2] = key; C[3] = key; C[4] = NONE; C[5] = h; C[6] = NONE;
-                            C[7] = NONE; C[8] = NONE;
-                            if (W[2] == NONE) W[1] = ci;
-                            else m.cs[(u64)W[2] * GW_CSW + 7] = ci;
-                            W[2] = ci;
+                            C[7] = NONE;
+                            m.warr[W[1] + W[2]] = ci;  // the word's queue (counted: k_gw_words_count)
+                            W[2] += 1;
                             m.held[(u64)t * GW_HELD + nh] = ci;  // below GW_HELD: k_gw_thread checked
                             m.held_n[t] = nh + 1;
                         }
@@ -693,7 +841,7 @@ __global__ void k_gw_kept(DevParams *P, u64 cap) {
 // heap.  False when the pool cannot hold the pairs, the counters and the dense clocks.
 bool gwcp_layout(const Bufs &b, u64 cap, GwcpBufs &G) {
     const u64 fixed = 6 * cap + GH_WORDS;
-    const u64 clocks = 2ull * b.T * b.T + (u64)b.T * (GW_HELD + 8) + b.wo_cap;
+    const u64 clocks = 3ull * b.T * b.T + (u64)b.T * (GW_HELD + 8) + b.wo_cap;
     if (b.T > GW_MAX_T || b.pool_words < fixed + clocks) return false;
     u32 *p = b.pool;
     G.pf[0] = p; G.ps[0] = p + cap; G.pf[1] = p + 2 * cap; G.ps[1] = p + 3 * cap;
@@ -720,6 +868,10 @@ void gwcp_run(const Bufs &b, const GwcpBufs &G, hipStream_t s) {
     scan_exclusive(b.e_scan0, (u64)b.N + 1, b.part, s);
     RD_LAUNCH("k_gw_list", k_gw_list, dim3(gn), dim3(256), 0, s, b, (const u32 *)b.e_scan0, b.e_scan1);
     RD_LAUNCH("k_gw_clear", k_gw_clear, dim3(1024), dim3(256), 0, s, b, G);
+    RD_LAUNCH("k_gw_words_insert", k_gw_words_insert, dim3(gn), dim3(256), 0, s, b, G);
+    RD_LAUNCH("k_gw_words_rows", k_gw_words_rows, dim3(1024), dim3(256), 0, s, b, G);
+    RD_LAUNCH("k_gw_words_count", k_gw_words_count, dim3(gn), dim3(256), 0, s, b, G);
+    RD_LAUNCH("k_gw_words_off", k_gw_words_off, dim3(1), dim3(1024), 0, s, b, G);
     RD_LAUNCH("k_gw_interp", k_gw_interp, dim3(1), dim3(GW_THREADS), 0, s, b, G, (const u32 *)b.e_scan0,
               (const u32 *)b.e_scan1);
     RD_LAUNCH("k_gw_post", k_gw_post, dim3(gt), dim3(256), 0, s, b, G, (const u32 *)b.e_scan0);

@@ -158,7 +158,8 @@ static Plan make_plan(u64 n, u32 nb, u32 tpb, const rd_limits *lim, bool copy_ev
     L.off_sort_partial = take(4ull * P.partial_words);
     L.off_sort_tot = take(4ull * (MAX_SORT_PASSES * SORT_NDS + MAX_SORT_PASSES));
     L.off_part = take(4ull * P.part_words);
-    L.off_tile_agg = take(agg_bytes() * ((u64)n_tiles + 1));
+    // the tile summaries, then the chunk totals of their scan (4,096 tiles a chunk)
+    L.off_tile_agg = take(agg_bytes() * ((u64)n_tiles + 1 + ((u64)n_tiles + 4095) / 4096 + 1));
     L.off_pfirst[0] = take(4 * max_pairs);
     L.off_psecond[0] = take(4 * max_pairs);
     // the second pair buffer is one block: after the sort it holds the report as rd_pair records

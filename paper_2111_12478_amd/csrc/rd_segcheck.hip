@@ -279,8 +279,7 @@ __global__ __launch_bounds__(WG_THREADS) void k_seg_reduce(Bufs b) {
     }
 }
 
-// exclusive scan over the tile totals (one workgroup of SCAN_THREADS; each thread a contiguous
-// range of tiles, read four at a time so that their loads overlap)
+// exclusive scan over the tile totals (workgroups of SCAN_THREADS)
 constexpr u32 SCAN_THREADS = 1024;
 
 // Four consecutive summaries (a range starting at a multiple of four tiles) are AGG_WORDS aligned
@@ -307,57 +306,102 @@ __device__ inline void agg_store4(Agg *dst, const Agg v[4]) {
     for (int k = 0; k < AGG_WORDS; k++) p[k] = make_uint4(w[4 * k], w[4 * k + 1], w[4 * k + 2], w[4 * k + 3]);
 }
 
-__global__ __launch_bounds__(SCAN_THREADS) void k_seg_scan(Bufs b) {
+// The tiles' exclusive prefixes in three launches: every workgroup scans a chunk of SCAN_CHUNK
+// tiles (four per thread) for its total, one workgroup scans the chunk totals, and every workgroup
+// scans its chunk again from its chunk's prefix and stores the tiles' prefixes.  The chunk totals
+// live after the tile summaries.
+constexpr u32 SCAN_PER = 4;
+constexpr u32 SCAN_CHUNK = SCAN_THREADS * SCAN_PER;
+
+__device__ inline u32 scan_tiles(const SegCtx &s) { return (u32)((s.n + TILE - 1) / TILE); }
+
+// This thread's (up to) four tiles of chunk blockIdx.x, loaded; the number in range.
+__device__ inline u32 chunk_load(const Agg *tile_agg, u32 nt, Agg v[4]) {
+    const u32 q = blockIdx.x * SCAN_CHUNK + threadIdx.x * SCAN_PER;
+    if (q >= nt) return 0;
+    if (q + 4 <= nt) {
+        agg_load4(tile_agg + q, v);
+        return 4;
+    }
+#pragma unroll
+    for (u32 j = 0; j < 4; j++)
+        if (q + j < nt) v[j] = tile_agg[q + j];
+    return nt - q;
+}
+
+__global__ __launch_bounds__(SCAN_THREADS) void k_seg_scan_up(Bufs b) {
     __shared__ Agg buf[SCAN_THREADS / 64];
     const SegCtx s = seg_ctx(b);
     if (check_abandoned(b.prm)) return;  // the answer is that error: nothing here is read
-    Agg *tile_agg = (Agg *)b.tile_agg;
-    const u32 nt = (u32)((s.n + TILE - 1) / TILE);
-    // each thread a range of a multiple of four tiles (16-byte aligned: the array is 256-aligned)
-    const u32 per = ((nt + SCAN_THREADS - 1) / SCAN_THREADS + 3) & ~3u;
-    const u32 lo = min(threadIdx.x * per, nt), hi = min(lo + per, nt);
+    const u32 nt = scan_tiles(s);
+    if (blockIdx.x * SCAN_CHUNK >= nt) return;
+    Agg *tile_agg = (Agg *)b.tile_agg, *chunk_tot = tile_agg + b.n_tiles + 1;
+    Agg v[4], acc;
+    agg_empty(acc);
+    const u32 m = chunk_load(tile_agg, nt, v);
+#pragma unroll
+    for (u32 j = 0; j < 4; j++)
+        if (j < m) { agg_combine(acc, v[j]); acc = v[j]; }
+    Agg total;
+    block_exscan_agg<SCAN_THREADS>(acc, buf, &total);
+    if (threadIdx.x == 0) chunk_tot[blockIdx.x] = total;
+}
+
+__global__ __launch_bounds__(SCAN_THREADS) void k_seg_scan_top(Bufs b) {
+    __shared__ Agg buf[SCAN_THREADS / 64];
+    const SegCtx s = seg_ctx(b);
+    if (check_abandoned(b.prm)) return;
+    const u32 nc = (scan_tiles(s) + SCAN_CHUNK - 1) / SCAN_CHUNK;
+    Agg *chunk_tot = (Agg *)b.tile_agg + b.n_tiles + 1;
+    // each thread a contiguous range of chunks
+    const u32 per = (nc + SCAN_THREADS - 1) / SCAN_THREADS;
+    const u32 lo = min(threadIdx.x * per, nc), hi = min(lo + per, nc);
     Agg acc;
     agg_empty(acc);
-    for (u32 q = lo; q < hi; q += 4) {
-        Agg v[4];
-        if (q + 4 <= hi) {
-            agg_load4(tile_agg + q, v);
-        } else {
-#pragma unroll
-            for (u32 j = 0; j < 4; j++)
-                if (q + j < hi) v[j] = tile_agg[q + j];
-        }
-#pragma unroll
-        for (u32 j = 0; j < 4; j++)
-            if (q + j < hi) { agg_combine(acc, v[j]); acc = v[j]; }
+    for (u32 c = lo; c < hi; c++) {
+        Agg v = chunk_tot[c];
+        agg_combine(acc, v);
+        acc = v;
     }
     block_exscan_agg<SCAN_THREADS>(acc, buf, nullptr);
-    for (u32 q = lo; q < hi; q += 4) {
-        Agg v[4];  // the totals in, the exclusive prefixes out
-        const bool whole = q + 4 <= hi;
-        if (whole) {
-            agg_load4(tile_agg + q, v);
-        } else {
+    for (u32 c = lo; c < hi; c++) {
+        Agg t = chunk_tot[c];
+        chunk_tot[c] = acc;
+        agg_combine(acc, t);
+        acc = t;
+    }
+}
+
+__global__ __launch_bounds__(SCAN_THREADS) void k_seg_scan_down(Bufs b) {
+    __shared__ Agg buf[SCAN_THREADS / 64];
+    const SegCtx s = seg_ctx(b);
+    if (check_abandoned(b.prm)) return;
+    const u32 nt = scan_tiles(s);
+    if (blockIdx.x * SCAN_CHUNK >= nt) return;
+    Agg *tile_agg = (Agg *)b.tile_agg;
+    const Agg *chunk_tot = tile_agg + b.n_tiles + 1;
+    Agg acc;
+    agg_empty(acc);
+    u32 m;
+    {
+        Agg v[4];
+        m = chunk_load(tile_agg, nt, v);
 #pragma unroll
-            for (u32 j = 0; j < 4; j++)
-                if (q + j < hi) v[j] = tile_agg[q + j];
-        }
-#pragma unroll
-        for (u32 j = 0; j < 4; j++) {
-            if (q + j < hi) {
-                Agg t = v[j];
-                v[j] = acc;
-                agg_combine(acc, t);
-                acc = t;
-            }
-        }
-        if (whole) {
-            agg_store4(tile_agg + q, v);
-        } else {
-#pragma unroll
-            for (u32 j = 0; j < 4; j++)
-                if (q + j < hi) tile_agg[q + j] = v[j];
-        }
+        for (u32 j = 0; j < 4; j++)
+            if (j < m) { agg_combine(acc, v[j]); acc = v[j]; }
+    }
+    block_exscan_agg<SCAN_THREADS>(acc, buf, nullptr);  // everything of the chunk before this thread
+    {
+        Agg pc = chunk_tot[blockIdx.x];                 // everything before the chunk
+        agg_combine(pc, acc);
+    }
+    // the totals in (read again, one at a time), the exclusive prefixes out
+    const u32 q = blockIdx.x * SCAN_CHUNK + threadIdx.x * SCAN_PER;
+    for (u32 j = 0; j < m; j++) {
+        Agg t = tile_agg[q + j];
+        tile_agg[q + j] = acc;
+        agg_combine(acc, t);
+        acc = t;
     }
 }
 
@@ -884,7 +928,10 @@ __global__ void k_pairs_kept(Bufs b) {
 void segcheck_run(const Bufs &b, const u32 *rt_scan, hipStream_t s) {
     if (!b.N) { RD_LAUNCH("k_pairs_kept", k_pairs_kept, dim3(1), dim3(64), 0, s, b); return; }
     RD_LAUNCH("k_seg_reduce", k_seg_reduce, dim3(b.n_tiles), dim3(WG_THREADS), 0, s, b);
-    RD_LAUNCH("k_seg_scan", k_seg_scan, dim3(1), dim3(SCAN_THREADS), 0, s, b);
+    const unsigned nch = (unsigned)((b.n_tiles + SCAN_CHUNK - 1) / SCAN_CHUNK);
+    RD_LAUNCH("k_seg_scan_up", k_seg_scan_up, dim3(nch ? nch : 1), dim3(SCAN_THREADS), 0, s, b);
+    RD_LAUNCH("k_seg_scan_top", k_seg_scan_top, dim3(1), dim3(SCAN_THREADS), 0, s, b);
+    RD_LAUNCH("k_seg_scan_down", k_seg_scan_down, dim3(nch ? nch : 1), dim3(SCAN_THREADS), 0, s, b);
     RD_LAUNCH("k_seg_check", k_seg_check, dim3(b.n_tiles), dim3(WG_THREADS), 0, s, b, rt_scan);
     RD_LAUNCH("k_seg_slow", k_seg_slow, dim3(b.n_tiles < 1024 ? b.n_tiles : 1024), dim3(WG_THREADS), 0, s, b, rt_scan);
     RD_LAUNCH("k_pairs_kept", k_pairs_kept, dim3(1), dim3(64), 0, s, b);
