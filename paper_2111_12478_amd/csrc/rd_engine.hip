@@ -791,14 +791,23 @@ struct ChainCache {
     u32 v0, v1, v2, v3;
 };
 
-__device__ __attribute__((always_inline)) inline u32 chain_get(const ChainCache &C, const u32 *pool, u32 D, u32 col,
-                                                               u32 h) {
-    // h is the same in every lane: the branches are uniform
-    if (h == C.h0) return C.v0;
-    if (h == C.h1) return C.v1;
-    if (h == C.h2) return C.v2;
-    if (h == C.h3) return C.v3;
-    return pool[(u64)h * D + col];
+// A load that waits for itself inside the same statement: the replay's join point then carries no
+// vector-memory wait, which on this target would also wait for the previous operations' stores.
+__device__ __attribute__((always_inline)) inline u32 load_now(const u32 *p) {
+    u32 x;
+    asm volatile("global_load_dword %0, %1, off\n\ts_waitcnt vmcnt(0)" : "=v"(x) : "v"(p) : "memory");
+    return x;
+}
+
+// v joined with output h (the same in every lane).  The tags are read as scalars so the branches
+// are uniform; only a miss reads memory.
+__device__ __attribute__((always_inline)) inline u32 chain_join(const ChainCache &C, const u32 *pool, u32 D, u32 col,
+                                                                u32 h, u32 v) {
+    if (h == uni(C.h0)) return max(v, C.v0);
+    if (h == uni(C.h1)) return max(v, C.v1);
+    if (h == uni(C.h2)) return max(v, C.v2);
+    if (h == uni(C.h3)) return max(v, C.v3);
+    return max(v, load_now(pool + (u64)h * D + col));
 }
 
 __device__ __attribute__((always_inline)) inline void chain_put(ChainCache &C, u32 h, u32 v) {
@@ -815,17 +824,20 @@ struct ChainLds {
     uint2 l[CH_BLK_JOBS];
     u32 wave_n[ENG_THREADS / 64];
     u32 n;
+    u32 ch[3];                         // the replay's three latest outputs before the block
+    u32 code[CH_BLK_JOBS];             // per job: which of the three latest outputs it joins (bits
+                                       // 0-2), or NONE when it needs the general step
 };
 
 __device__ __attribute__((always_inline)) inline void chain_run(ChainCache &C, uint4 q, uint2 l, u32 v,
                                                                 const u32 *list, u32 *pool, u32 D, u32 col,
                                                                 bool mine) {
     q = make_uint4(uni(q.x), uni(q.y), uni(q.z), uni(q.w));
-    if (q.y) v = max(v, chain_get(C, pool, D, col, q.y));
-    if (q.z) v = max(v, chain_get(C, pool, D, col, q.z));
-    if (q.w) v = max(v, chain_get(C, pool, D, col, q.w));
+    if (q.y) v = chain_join(C, pool, D, col, q.y, v);
+    if (q.z) v = chain_join(C, pool, D, col, q.z, v);
+    if (q.w) v = chain_join(C, pool, D, col, q.w, v);
     const u32 lo = uni(l.x), ln = uni(l.y);
-    for (u32 k = 0; k < ln; k++) v = max(v, chain_get(C, pool, D, col, uni(list[lo + k])));
+    for (u32 k = 0; k < ln; k++) v = chain_join(C, pool, D, col, uni(list[lo + k]), v);
     if (mine) pool[(u64)q.x * D + col] = v;
     chain_put(C, q.x, v);
 }
@@ -846,6 +858,11 @@ __device__ void chain_window(const Bufs &b, u32 w0, u32 w1, u32 D, u32 *lj /* CH
             __syncthreads();
             for (u32 x = threadIdx.x; x < (ce - cb) * ENG_JOB_WORDS; x += ENG_THREADS)
                 lj[x] = jobs[(u64)(cb - w0) * ENG_JOB_WORDS + x];
+            if (threadIdx.x == 0) {
+                A.ch[0] = uni(C.h0);
+                A.ch[1] = uni(C.h1);
+                A.ch[2] = uni(C.h2);
+            }
             __syncthreads();
             // jobs with inputs from the window, in (operation, slot) order
             const u32 x = threadIdx.x;  // job x = operation cb + x / 3, slot x % 3
@@ -871,14 +888,57 @@ __device__ void chain_window(const Bufs &b, u32 w0, u32 w1, u32 D, u32 *lj /* CH
             if (threadIdx.x == ENG_THREADS - 1) A.n = off + (u32)__builtin_popcountll(m);
             __syncthreads();
             const u32 n = A.n;
+            // Most jobs join only the outputs of the last three jobs before them (a lock handed on):
+            // each job's inputs are matched against those once, in parallel, so the replay of such
+            // a job is a few maximums over registers; the others take the general step.
+            if (threadIdx.x < n) {
+                const u32 k = threadIdx.x;
+                const uint4 jq = A.q[k];
+                const u32 o1 = k >= 1 ? A.q[k - 1].x : A.ch[0];
+                const u32 o2 = k >= 2 ? A.q[k - 2].x : A.ch[1 - k];
+                const u32 o3 = k >= 3 ? A.q[k - 3].x : A.ch[2 - k];
+                u32 code = 0;
+                bool lean = A.l[k].y == 0;
+                const u32 in[3] = {jq.y, jq.z, jq.w};
+#pragma unroll
+                for (u32 j = 0; j < 3; j++) {
+                    const u32 h = in[j];
+                    if (!h) continue;
+                    if (h == o1) code |= 1u;
+                    else if (h == o2) code |= 2u;
+                    else if (h == o3) code |= 4u;
+                    else lean = false;
+                }
+                A.code[k] = lean ? code : NONE;
+            }
             // the partial results of the slice, every lane loading
             for (u32 e = threadIdx.x; e < n * 64; e += ENG_THREADS) {
                 const u32 c = sl * 64 + (e & 63u);
                 part[e] = c < D ? pool[(u64)A.q[e >> 6].x * D + c] : 0u;
             }
             __syncthreads();
-            if (wave == 0)
-                for (u32 k = 0; k < n; k++) chain_run(C, A.q[k], A.l[k], part[k * 64 + lane], list, pool, D, cc, mine);
+            if (wave == 0 && n) {
+                // the next job's words are read from LDS while the current one runs
+                u32 code_n = A.code[0], h_n = A.q[0].x, p_n = part[lane];
+                for (u32 k = 0; k < n; k++) {
+                    const u32 code = uni(code_n), h = uni(h_n);
+                    u32 v = p_n;
+                    if (k + 1 < n) {
+                        code_n = A.code[k + 1];
+                        h_n = A.q[k + 1].x;
+                        p_n = part[(k + 1) * 64 + lane];
+                    }
+                    if (code != NONE) {
+                        v = max(v, (code & 1u) ? C.v0 : 0u);
+                        v = max(v, (code & 2u) ? C.v1 : 0u);
+                        v = max(v, (code & 4u) ? C.v2 : 0u);
+                        if (mine) pool[(u64)h * D + cc] = v;
+                        chain_put(C, h, v);
+                    } else {
+                        chain_run(C, A.q[k], A.l[k], v, list, pool, D, cc, mine);
+                    }
+                }
+            }
             if (reporter) atomicAdd(&b.prm->gprog, 1u);
         }
     }
