@@ -150,6 +150,7 @@ struct DevParams {
     u32 ls_kept;           // ... min(ls_pairs, its buffer)
     u32 gw_pairs;          // GWCP pass: pairs found (may exceed its buffer)
     u32 gw_kept;           // ... min(gw_pairs, its buffer)
+    u32 n_long;            // slow-path accesses of the segment check queued whole (chunk queue full)
     unsigned long long n_chunks;  // queued slow-path chunks of the segment check (8-byte aligned)
 };
 
@@ -344,6 +345,8 @@ __device__ inline u32 list_search(const Bufs &b, u32 t, u32 idx) {
 struct SegCtx {
     const u32 *k, *i, *t, *f;
     u32 *cpos, *clo, *chi;  // the queue of slow-path chunks (in the sort's free buffers)
+    u32 *lpos;              // accesses queued whole when the chunk queue is full: sorted position,
+                            // bit 31 set when only the access's block-and-phase run can race
     u32 n;
     bool packed;            // category and phase in the key word, above key_bits
     bool tinfo;             // category and phase in the thread word, above tbits
@@ -356,7 +359,7 @@ __device__ inline SegCtx seg_ctx(const Bufs &b) {
     const u32 bits = b.prm->key_bits, passes = (bits + b.radix_bits - 1) / b.radix_bits;
     const u32 c = passes & 1;
     SegCtx s; s.k = b.ekey[c]; s.i = b.eidx[c]; s.t = b.etid[c]; s.f = b.einfo[c]; s.n = b.prm->n_acc;
-    s.cpos = b.ekey[c ^ 1]; s.clo = b.etid[c ^ 1]; s.chi = b.einfo[c ^ 1];
+    s.cpos = b.ekey[c ^ 1]; s.clo = b.etid[c ^ 1]; s.chi = b.einfo[c ^ 1]; s.lpos = b.eidx[c ^ 1];
     s.packed = packed_elements(bits, b.prm->max_phase);
     s.tinfo = tinfo_elements(bits, b.prm->max_phase, b.T);
     s.key_bits = bits;

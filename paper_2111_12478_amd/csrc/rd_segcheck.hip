@@ -743,6 +743,8 @@ __device__ void lane_walks(const Bufs &b, const SegCtx &s, const u32 *rt_scan, u
     }
 }
 
+constexpr u64 LOW48 = (1ull << 48) - 1;
+
 union CheckLds {
     Agg buf[WAVES];
     struct { u32 pf[WAVES][WAVE_PAIRS], ps[WAVES][WAVE_PAIRS]; } pairs;
@@ -752,6 +754,7 @@ __global__ __launch_bounds__(WG_THREADS) void k_seg_check(Bufs b, const u32 *rt_
     __shared__ CheckLds L;
     __shared__ u64 wsum[WAVES];
     __shared__ u64 qbase;
+    __shared__ u32 lbase;
     const SegCtx s = seg_ctx(b);
     if (check_abandoned(b.prm)) return;  // the answer is that error: nothing here is read
     const Agg *tile_agg = (const Agg *)b.tile_agg;
@@ -796,24 +799,40 @@ __global__ __launch_bounds__(WG_THREADS) void k_seg_check(Bufs b, const u32 *rt_
             P = one;
         }
     }
+    // chunks (low 48 bits: at most 4,096 items of fewer than 2^26 chunks each) and chunk items
     u64 total;
-    const u64 off = block_exscan_u64(need, wsum, total);
+    const u64 packed_off = block_exscan_u64(need | ((u64)__builtin_popcount(chunk_bits) << 48), wsum, total);
+    const u64 off = packed_off & LOW48, item_off = packed_off >> 48;
+    const u64 total_items = total >> 48;
+    total &= LOW48;
     const bool any_walk = __syncthreads_or(walk_bits != 0);  // (also ends the use of L.buf)
     if (!total && !any_walk) return;
     if (threadIdx.x == 0) {
         qbase = ~0ull;
+        lbase = NONE;
         if (total) {
             const u64 c0 = atomicAdd(&b.prm->n_chunks, (unsigned long long)total);
             if (c0 + total <= s.n) qbase = c0;
             else {
                 // no room: neutralise the reserved slots below the capacity (the chunk kernel reads
-                // min(counter, capacity) slots) and check this tile's chunk items here
+                // min(counter, capacity) slots) and queue the tile's chunk items whole; an access is
+                // queued whole at most once, so that queue (as long as the elements) has room
                 for (u64 c = c0; c < c0 + total && c < s.n; c++) { s.cpos[c] = 0; s.clo[c] = 0; s.chi[c] = 0; }
+                if (s.n <= 0x80000000u) {
+                    const u32 l0 = atomicAdd(&b.prm->n_long, (u32)total_items);
+                    if ((u64)l0 + total_items <= s.n) lbase = l0;
+                }
             }
         }
     }
     __syncthreads();
-    if (qbase != ~0ull) {
+    if (lbase != NONE) {
+        u32 e = lbase + (u32)item_off;
+#pragma unroll
+        for (int q = 0; q < ITEMS; q++)
+            if (chunk_bits & (1u << q)) s.lpos[e++] = (u32)(base + q) | ((run_bits >> q) & 1u) << 31;
+        chunk_bits = 0;
+    } else if (qbase != ~0ull) {
         // pass 2: the same decisions, chunks written to the queue at this thread's offset
         u64 e = qbase + off;
         Agg P = P0;
@@ -840,8 +859,8 @@ __global__ __launch_bounds__(WG_THREADS) void k_seg_check(Bufs b, const u32 *rt_
     wp.pf = L.pairs.pf[wv];
     wp.ps = L.pairs.ps[wv];
     wp.fill = 0;
-    // queue full: each wavefront checks its lanes' chunk items by exact scans, of the run or of the
-    // whole segment prefix
+    // both queues full: each wavefront checks its lanes' chunk items by exact scans, of the run or
+    // of the whole segment prefix
     for (u32 q = 0; q < (u32)ITEMS; q++) {
         u64 m = ballot((chunk_bits >> q) & 1u);
         const u64 mr = ballot((run_bits >> q) & 1u);
@@ -859,63 +878,49 @@ __global__ __launch_bounds__(WG_THREADS) void k_seg_check(Bufs b, const u32 *rt_
     wp_flush(b, wp);
 }
 
-// One wavefront per queued chunk (lane l checks position lo + l against b), the four wavefronts of
-// a workgroup in step.  Pairs are gathered in LDS and appended with one device atomic per flush of
-// the workgroup.
-constexpr u32 PAIR_LDS = 2048;
+// One wavefront per queued chunk (lane l checks position lo + l against b), then one per access
+// queued whole (an exact backward scan of its segment, or of its run).  Each wavefront gathers its
+// pairs in LDS and appends them with one device atomic per flush.
+constexpr u32 SLOW_GRID = 2048;
 
 __global__ __launch_bounds__(WG_THREADS) void k_seg_slow(Bufs b, const u32 *rt_scan) {
-    __shared__ u32 pf[PAIR_LDS], ps[PAIR_LDS];
-    __shared__ u32 fill, gbase;
+    __shared__ u32 pf[WAVES][WAVE_PAIRS], ps[WAVES][WAVE_PAIRS];
     const SegCtx s = seg_ctx(b);
     if (check_abandoned(b.prm)) return;  // the answer is that error: nothing here is read
     const u32 n_chunks = (u32)min(b.prm->n_chunks, (unsigned long long)s.n);
+    const u32 n_long = min(b.prm->n_long, s.n);
     const u32 lane = lane_id(), w = threadIdx.x >> 6;
-    if (threadIdx.x == 0) fill = 0;
-    __syncthreads();
+    WavePairs wp;
+    wp.pf = pf[w];
+    wp.ps = ps[w];
+    wp.fill = 0;
     const u32 stride = gridDim.x * WAVES;
-    for (u32 c0 = blockIdx.x * WAVES; c0 < n_chunks; c0 += stride) {
-        const u32 c = c0 + w;
+    for (u32 c = blockIdx.x * WAVES + w; c < n_chunks; c += stride) {
+        const u32 pos = s.cpos[c], lo = s.clo[c], hi = s.chi[c];
+        const u32 q = lo + lane;
         bool want = false;
         u32 ia = 0, bidx = 0;
-        if (c < n_chunks) {
-            const u32 pos = s.cpos[c], lo = s.clo[c], hi = s.chi[c];
-            const u32 q = lo + lane;
-            if (q < hi) {
-                const u32 btid = seg_tid(s, pos), binfo = seg_info(s, pos);
-                const u32 bblk = block_of(b, btid), bph = info_phase(binfo), bcat = info_cat(binfo);
-                const u32 ta = seg_tid(s, q), info = seg_info(s, q);
-                const u32 ba = block_of(b, ta), pha = info_phase(info);
-                if (ta != btid && conflicts(info_cat(info), ba, bcat, bblk)) {
-                    u32 h = NONE;
-                    ia = s.i[q];
-                    bidx = s.i[pos];
-                    want = !happens_before(b, rt_scan, bidx, btid, bblk, bph, h, ta, ba, pha, ia);
-                }
+        if (q < hi) {
+            const u32 btid = seg_tid(s, pos), binfo = seg_info(s, pos);
+            const u32 bblk = block_of(b, btid), bph = info_phase(binfo), bcat = info_cat(binfo);
+            const u32 ta = seg_tid(s, q), info = seg_info(s, q);
+            const u32 ba = block_of(b, ta), pha = info_phase(info);
+            if (ta != btid && conflicts(info_cat(info), ba, bcat, bblk)) {
+                u32 h = NONE;
+                ia = s.i[q];
+                bidx = s.i[pos];
+                want = !happens_before(b, rt_scan, bidx, btid, bblk, bph, h, ta, ba, pha, ia);
             }
         }
-        const u64 m = ballot(want);
-        if (m) {
-            u32 off = 0;
-            const u32 leader = (u32)__builtin_ctzll(m);
-            if (lane == leader) off = atomicAdd(&fill, popc64(m));
-            off = __shfl(off, leader, 64) + popc64(m & lanemask_lt());
-            if (want) { pf[off] = ia; ps[off] = bidx; }
-        }
-        __syncthreads();
-        if (fill > PAIR_LDS - WG_THREADS || c0 + stride >= n_chunks) {
-            if (threadIdx.x == 0) gbase = fill ? atomicAdd(&b.prm->n_pairs, fill) : 0;
-            __syncthreads();
-            for (u32 k = threadIdx.x; k < fill; k += WG_THREADS) {
-                const u32 slot = gbase + k;
-                if (slot < b.max_pairs) { b.pfirst[0][slot] = pf[k]; b.psecond[0][slot] = ps[k]; }
-                else atomicOr(&b.prm->err, ERR_PAIRS);
-            }
-            __syncthreads();
-            if (threadIdx.x == 0) fill = 0;
-            __syncthreads();
-        }
+        wp_add(b, wp, want, ia, bidx);
     }
+    for (u32 c = blockIdx.x * WAVES + w; c < n_long; c += stride) {
+        const u32 e = s.lpos[c], pos = e & 0x7fffffffu;
+        const u32 tid = seg_tid(s, pos), info = seg_info(s, pos);
+        wave_slow_check(b, s, rt_scan, pos, seg_key(s, pos), tid, block_of(b, tid), info_phase(info),
+                        info_cat(info), (e >> 31) != 0u);
+    }
+    wp_flush(b, wp);
 }
 
 __global__ void k_pairs_kept(Bufs b) {
@@ -933,7 +938,7 @@ void segcheck_run(const Bufs &b, const u32 *rt_scan, hipStream_t s) {
     RD_LAUNCH("k_seg_scan_top", k_seg_scan_top, dim3(1), dim3(SCAN_THREADS), 0, s, b);
     RD_LAUNCH("k_seg_scan_down", k_seg_scan_down, dim3(nch ? nch : 1), dim3(SCAN_THREADS), 0, s, b);
     RD_LAUNCH("k_seg_check", k_seg_check, dim3(b.n_tiles), dim3(WG_THREADS), 0, s, b, rt_scan);
-    RD_LAUNCH("k_seg_slow", k_seg_slow, dim3(b.n_tiles < 1024 ? b.n_tiles : 1024), dim3(WG_THREADS), 0, s, b, rt_scan);
+    RD_LAUNCH("k_seg_slow", k_seg_slow, dim3(SLOW_GRID), dim3(WG_THREADS), 0, s, b, rt_scan);
     RD_LAUNCH("k_pairs_kept", k_pairs_kept, dim3(1), dim3(64), 0, s, b);
 }
 

@@ -273,6 +273,37 @@ def test_one_hot_location_many_blocks(rc):
         np.testing.assert_array_equal(got.pairs, want.pairs)
 
 
+def test_one_hot_location_one_block(rc):
+    # one block in one phase: only the access's own run can race, and the chunks over the run
+    # overflow the queue, so the accesses are queued whole (with the run flag) instead
+    for n in (4097, 9001):
+        rng = np.random.default_rng(n + 2)
+        ev = np.zeros((n, 4), np.uint32)
+        ev[:, 0] = 5
+        ev[:, 1] = rng.integers(0, 64, n)
+        ev[:, 2] = np.where(rng.random(n) < 0.01, make_meta(KIND["W"]), make_meta(KIND["R"]))
+        want = oracle.check((1, 64), ev)
+        got = rc.check((1, 64), ev, limits={"max_pairs": 1 << 25})
+        assert got.status == 0, got
+        np.testing.assert_array_equal(got.pairs, want.pairs)
+
+
+def test_hot_location_among_others(rc):
+    # a hot word shared by eight blocks inside an ordinary trace: the queue overflows part way, so
+    # some tiles queue chunks and later ones whole accesses
+    rng = np.random.default_rng(31)
+    n = 40000
+    ev = np.zeros((n, 4), np.uint32)
+    hot = rng.random(n) < 0.15
+    ev[:, 0] = np.where(hot, 7, 100 + rng.integers(0, 5000, n))
+    ev[:, 1] = rng.integers(0, 8 * 32, n)
+    ev[:, 2] = np.where(rng.random(n) < 0.05, make_meta(KIND["W"]), make_meta(KIND["R"]))
+    want = oracle.check((8, 32), ev)
+    got = rc.check((8, 32), ev, limits={"max_pairs": 1 << 25})
+    assert got.status == 0, got
+    np.testing.assert_array_equal(got.pairs, want.pairs)
+
+
 def test_pair_buffer_overflow_is_reported(rc):
     # 64 threads of one block each write one word: C(64, 2) = 2016 pairs, buffer of 1000
     ev = np.array([(3, t, make_meta(KIND["W"]), 0) for t in range(64)], np.uint32)
