@@ -778,18 +778,16 @@ __device__ inline u32 first_handle(const Bufs &b, u32 o) {
 
 // Second phase of a window.  Every output column of every operation depends only on the same
 // column of its inputs, so a workgroup owns a slice of 64 columns and its first wavefront replays
-// the window's jobs in order over them, one column per lane: no barrier between operations, the
-// latest outputs stay in registers.  For each block of CH_BLK operations the workgroup stages their
-// jobs in LDS (one coalesced read), compacts the ones with inputs from the window, in order, and
-// loads all of their partial results for the slice into LDS with every lane before the replay.
+// the window's jobs in order over them, one column per lane: no barrier between operations.  For
+// each block of CH_BLK operations the workgroup stages their jobs in LDS (one coalesced read),
+// compacts the ones with inputs from the window, in order, and builds a table of values for the
+// slice in LDS with every lane: each job's partial result (replaced by its output as the replay
+// goes), the outputs of earlier blocks that the block's jobs read, and a row of zeros.  Each input
+// of a job is then one of the replay's last three outputs (held in registers), or a row of the
+// table: the replay itself reads no global memory.  Jobs with list inputs (barriers), or whose rows
+// do not fit, take a general step that reads other outputs from the pool.
 
 __device__ inline u32 uni(u32 x) { return __builtin_amdgcn_readfirstlane(x); }
-
-// The latest four outputs of the replay (newest first); handle 0 is the empty vector.
-struct ChainCache {
-    u32 h0, h1, h2, h3;
-    u32 v0, v1, v2, v3;
-};
 
 // A load that waits for itself inside the same statement: the replay's join point then carries no
 // vector-memory wait, which on this target would also wait for the previous operations' stores.
@@ -799,23 +797,11 @@ __device__ __attribute__((always_inline)) inline u32 load_now(const u32 *p) {
     return x;
 }
 
-// v joined with output h (the same in every lane).  The tags are read as scalars so the branches
-// are uniform; only a miss reads memory.
-__device__ __attribute__((always_inline)) inline u32 chain_join(const ChainCache &C, const u32 *pool, u32 D, u32 col,
-                                                                u32 h, u32 v) {
-    if (h == uni(C.h0)) return max(v, C.v0);
-    if (h == uni(C.h1)) return max(v, C.v1);
-    if (h == uni(C.h2)) return max(v, C.v2);
-    if (h == uni(C.h3)) return max(v, C.v3);
-    return max(v, load_now(pool + (u64)h * D + col));
-}
-
-__device__ __attribute__((always_inline)) inline void chain_put(ChainCache &C, u32 h, u32 v) {
-    C.h3 = C.h2; C.v3 = C.v2;
-    C.h2 = C.h1; C.v2 = C.v1;
-    C.h1 = C.h0; C.v1 = C.v0;
-    C.h0 = h; C.v0 = v;
-}
+constexpr u32 CH_HASH = 1024;                 // open-addressed map of a block's output handles
+constexpr u32 CH_ZROW = CH_BLK_JOBS;          // the table's row of zeros
+constexpr u32 CH_ROWS_NONE = CH_ZROW | CH_ZROW << 10 | CH_ZROW << 20;
+constexpr u32 CH_TABLE_WORDS = (CH_BLK_JOBS + 1) * 64;
+static_assert(CH_ZROW < 1024, "rows are 10-bit fields");
 
 // One job with inputs from the window: output handle, up to three input handles, and for a
 // barrier a range of the window input list.
@@ -823,46 +809,48 @@ struct ChainLds {
     uint4 q[CH_BLK_JOBS];
     uint2 l[CH_BLK_JOBS];
     u32 wave_n[ENG_THREADS / 64];
-    u32 n;
-    u32 ch[3];                         // the replay's three latest outputs before the block
+    u32 n, nf;
+    u32 ch[3];                         // handles of the replay's three latest outputs before the block
     u32 code[CH_BLK_JOBS];             // per job: which of the three latest outputs it joins (bits
-                                       // 0-2), or NONE when it needs the general step
+                                       // 0-2), or NONE when it takes the general step
+    u32 rows[CH_BLK_JOBS];             // per job: three rows of the table it joins (10 bits each)
+    u32 farh[CH_BLK_JOBS];             // handle of each prefetched row
+    u32 hkey[CH_HASH], hval[CH_HASH];  // output handle -> job index within the block
 };
 
-__device__ __attribute__((always_inline)) inline void chain_run(ChainCache &C, uint4 q, uint2 l, u32 v,
-                                                                const u32 *list, u32 *pool, u32 D, u32 col,
-                                                                bool mine) {
-    q = make_uint4(uni(q.x), uni(q.y), uni(q.z), uni(q.w));
-    if (q.y) v = chain_join(C, pool, D, col, q.y, v);
-    if (q.z) v = chain_join(C, pool, D, col, q.z, v);
-    if (q.w) v = chain_join(C, pool, D, col, q.w, v);
-    const u32 lo = uni(l.x), ln = uni(l.y);
-    for (u32 k = 0; k < ln; k++) v = chain_join(C, pool, D, col, uni(list[lo + k]), v);
-    if (mine) pool[(u64)q.x * D + col] = v;
-    chain_put(C, q.x, v);
+__device__ inline u32 ch_slot(u32 h) { return (h * 0x9E3779B1u) >> 22; }
+
+// The general step's view of one input: a register when it is one of the three latest outputs,
+// else the pool (every output is stored there as soon as it is computed).
+__device__ __attribute__((always_inline)) inline u32 gen_join(u32 h, u32 h1, u32 h2, u32 h3, u32 a, u32 b2,
+                                                              u32 c, const u32 *pool, u32 D, u32 col, u32 v) {
+    if (h == h1) return max(v, a);
+    if (h == h2) return max(v, b2);
+    if (h == h3) return max(v, c);
+    return max(v, load_now(pool + (u64)h * D + col));
 }
 
 __device__ void chain_window(const Bufs &b, u32 w0, u32 w1, u32 D, u32 *lj /* CH_BLK * ENG_JOB_WORDS */,
-                             ChainLds &A, u32 *part /* CH_BLK_JOBS * 64 */) {
+                             ChainLds &A, u32 *val /* CH_TABLE_WORDS */) {
     const u32 *jobs = b.eng_jobs, *list = b.eng_jobs + ENG_WIN * ENG_JOB_WORDS;
     u32 *pool = b.pool;
     const bool reporter = blockIdx.x == 0 && threadIdx.x == 0;
     const u32 lane = lane_id(), wave = threadIdx.x >> 6, nsl = (D + 63) / 64;
+    if (threadIdx.x < 64) val[CH_ZROW * 64 + threadIdx.x] = 0;
     for (u32 sl = blockIdx.x; sl < nsl; sl += gridDim.x) {
         const u32 col = sl * 64 + lane;
         const bool mine = col < D;
         const u32 cc = mine ? col : 0u;
-        ChainCache C = {0, 0, 0, 0, 0, 0, 0, 0};
+        // the ring of the latest outputs: r2 the newest, r1 and r0 before it (r3 is written next)
+        u32 r0 = 0, r1 = 0, r2 = 0, r3 = 0;
+        if (threadIdx.x < 3) A.ch[threadIdx.x] = 0;
         for (u32 cb = w0; cb < w1; cb += CH_BLK) {
             const u32 ce = min(cb + CH_BLK, w1);
             __syncthreads();
             for (u32 x = threadIdx.x; x < (ce - cb) * ENG_JOB_WORDS; x += ENG_THREADS)
                 lj[x] = jobs[(u64)(cb - w0) * ENG_JOB_WORDS + x];
-            if (threadIdx.x == 0) {
-                A.ch[0] = uni(C.h0);
-                A.ch[1] = uni(C.h1);
-                A.ch[2] = uni(C.h2);
-            }
+            for (u32 x = threadIdx.x; x < CH_HASH; x += ENG_THREADS) A.hkey[x] = 0;
+            if (threadIdx.x == 0) A.nf = 0;
             __syncthreads();
             // jobs with inputs from the window, in (operation, slot) order
             const u32 x = threadIdx.x;  // job x = operation cb + x / 3, slot x % 3
@@ -884,59 +872,180 @@ __device__ void chain_window(const Bufs &b, u32 w0, u32 w1, u32 D, u32 *lj /* CH
                 const u32 r = off + (u32)__builtin_popcountll(m & lanemask_lt());
                 A.q[r] = q;
                 A.l[r] = l;
+                // output handles are written once each (handle 0, the empty vector, is never one)
+                for (u32 s = ch_slot(q.x);; s = (s + 1) & (CH_HASH - 1))
+                    if (atomicCAS(&A.hkey[s], 0u, q.x) == 0u) {
+                        A.hval[s] = r;
+                        break;
+                    }
             }
             if (threadIdx.x == ENG_THREADS - 1) A.n = off + (u32)__builtin_popcountll(m);
             __syncthreads();
             const u32 n = A.n;
-            // Most jobs join only the outputs of the last three jobs before them (a lock handed on):
-            // each job's inputs are matched against those once, in parallel, so the replay of such
-            // a job is a few maximums over registers; the others take the general step.
+            // each job's inputs: registers (code), rows of this block (an earlier job's output) and
+            // outputs of earlier blocks (prefetched rows, counted here and placed below)
+            u32 code = NONE, rows = CH_ROWS_NONE, nfar = 0, far = 0;
+            bool lean = false;
             if (threadIdx.x < n) {
                 const u32 k = threadIdx.x;
                 const uint4 jq = A.q[k];
                 const u32 o1 = k >= 1 ? A.q[k - 1].x : A.ch[0];
                 const u32 o2 = k >= 2 ? A.q[k - 2].x : A.ch[1 - k];
                 const u32 o3 = k >= 3 ? A.q[k - 3].x : A.ch[2 - k];
-                u32 code = 0;
-                bool lean = A.l[k].y == 0;
                 const u32 in[3] = {jq.y, jq.z, jq.w};
+                lean = A.l[k].y == 0;
+                code = 0;
 #pragma unroll
                 for (u32 j = 0; j < 3; j++) {
                     const u32 h = in[j];
                     if (!h) continue;
-                    if (h == o1) code |= 1u;
-                    else if (h == o2) code |= 2u;
-                    else if (h == o3) code |= 4u;
-                    else lean = false;
+                    if (h == o1) { code |= 1u; continue; }
+                    if (h == o2) { code |= 2u; continue; }
+                    if (h == o3) { code |= 4u; continue; }
+                    u32 r = NONE;
+                    for (u32 s = ch_slot(h);; s = (s + 1) & (CH_HASH - 1)) {
+                        const u32 key = A.hkey[s];
+                        if (key == h) { r = A.hval[s]; break; }
+                        if (key == 0u) break;
+                    }
+                    if (r == NONE) {
+                        far |= 1u << j;
+                        nfar++;
+                    } else if (r < k) {
+                        rows = (rows & ~(0x3FFu << (10 * j))) | (r << (10 * j));
+                    } else {
+                        lean = false;
+                    }
+                }
+                if (!lean) nfar = 0;
+            }
+            // prefetched rows: an exclusive prefix of nfar over the block's jobs
+            u32 incl = nfar;
+#pragma unroll
+            for (u32 d = 1; d < 64; d <<= 1) {
+                const u32 y = __shfl_up(incl, d, 64);
+                if (lane >= d) incl += y;
+            }
+            if (lane == 63) A.wave_n[wave] = incl;
+            __syncthreads();
+            u32 foff = incl - nfar;
+            for (u32 w = 0; w < wave; w++) foff += A.wave_n[w];
+            if (threadIdx.x < n) {
+                const u32 k = threadIdx.x;
+                if (nfar && n + foff + nfar <= CH_BLK_JOBS) {
+                    const uint4 jq = A.q[k];
+                    const u32 in[3] = {jq.y, jq.z, jq.w};
+                    u32 f = foff;
+#pragma unroll
+                    for (u32 j = 0; j < 3; j++)
+                        if (far & (1u << j)) {
+                            A.farh[f] = in[j];
+                            rows = (rows & ~(0x3FFu << (10 * j))) | ((n + f) << (10 * j));
+                            f++;
+                        }
+                    // the rows in use end with the last job that fits (offsets grow with the job)
+                    atomicMax(&A.nf, f);
+                } else if (nfar) {
+                    lean = false;
                 }
                 A.code[k] = lean ? code : NONE;
+                A.rows[k] = lean ? rows : CH_ROWS_NONE;
             }
-            // the partial results of the slice, every lane loading
-            for (u32 e = threadIdx.x; e < n * 64; e += ENG_THREADS) {
-                const u32 c = sl * 64 + (e & 63u);
-                part[e] = c < D ? pool[(u64)A.q[e >> 6].x * D + c] : 0u;
+            __syncthreads();
+            // the table: the jobs' partial results, then the outputs of earlier blocks (stored by
+            // this workgroup's first wavefront before the barriers above)
+            // (each wavefront loads every eighth row, eight rows in flight)
+            const u32 nr = n + A.nf;
+            constexpr u32 NW = ENG_THREADS / 64, RF = 8;
+            for (u32 r0 = wave; r0 < nr; r0 += NW * RF) {
+                u32 x[RF];
+#pragma unroll
+                for (u32 j = 0; j < RF; j++) {
+                    const u32 r = r0 + j * NW;
+                    x[j] = 0;
+                    if (r < nr && mine) x[j] = pool[(u64)(r < n ? A.q[r].x : A.farh[r - n]) * D + col];
+                }
+#pragma unroll
+                for (u32 j = 0; j < RF; j++)
+                    if (r0 + j * NW < nr) val[(r0 + j * NW) * 64 + lane] = x[j];
             }
             __syncthreads();
             if (wave == 0 && n) {
-                // the next job's words are read from LDS while the current one runs
-                u32 code_n = A.code[0], h_n = A.q[0].x, p_n = part[lane];
-                for (u32 k = 0; k < n; k++) {
-                    const u32 code = uni(code_n), h = uni(h_n);
-                    u32 v = p_n;
+                // The replay.  A job's rows were written at least four jobs before it (nearer
+                // outputs are registers), so its words and rows are read a job ahead.
+                // (the next job's four values are joined only when it runs, so the reads have the
+                // current job's time to arrive)
+                u32 code_n = A.code[0], h_n = A.q[0].x, rows_nn = A.rows[n > 1 ? 1 : 0];
+                u32 x0, x1, x2, x3;
+                {
+                    const u32 rr = uni(A.rows[0]);
+                    x0 = val[lane];
+                    x1 = val[(rr & 0x3FFu) * 64 + lane];
+                    x2 = val[((rr >> 10) & 0x3FFu) * 64 + lane];
+                    x3 = val[(rr >> 20) * 64 + lane];
+                }
+                auto step = [&](u32 k, u32 a, u32 b2, u32 c, u32 &dst) {
+                    const u32 cd = uni(code_n), h = uni(h_n);
+                    u32 v = max(max(x0, x1), max(x2, x3));
                     if (k + 1 < n) {
+                        const u32 rr = uni(rows_nn);
                         code_n = A.code[k + 1];
                         h_n = A.q[k + 1].x;
-                        p_n = part[(k + 1) * 64 + lane];
+                        rows_nn = A.rows[k + 2 < n ? k + 2 : k + 1];
+                        x0 = val[(k + 1) * 64 + lane];
+                        x1 = val[(rr & 0x3FFu) * 64 + lane];
+                        x2 = val[((rr >> 10) & 0x3FFu) * 64 + lane];
+                        x3 = val[(rr >> 20) * 64 + lane];
                     }
-                    if (code != NONE) {
-                        v = max(v, (code & 1u) ? C.v0 : 0u);
-                        v = max(v, (code & 2u) ? C.v1 : 0u);
-                        v = max(v, (code & 4u) ? C.v2 : 0u);
-                        if (mine) pool[(u64)h * D + cc] = v;
-                        chain_put(C, h, v);
+                    if (cd != NONE) {
+                        v = max(v, (cd & 1u) ? a : 0u);
+                        v = max(v, (cd & 2u) ? b2 : 0u);
+                        v = max(v, (cd & 4u) ? c : 0u);
                     } else {
-                        chain_run(C, A.q[k], A.l[k], v, list, pool, D, cc, mine);
+                        const uint4 jq = make_uint4(0, uni(A.q[k].y), uni(A.q[k].z), uni(A.q[k].w));
+                        const u32 h1 = uni(k >= 1 ? A.q[k - 1].x : A.ch[0]);
+                        const u32 h2 = uni(k >= 2 ? A.q[k - 2].x : A.ch[k < 2 ? 1 - k : 0]);
+                        const u32 h3 = uni(k >= 3 ? A.q[k - 3].x : A.ch[k < 3 ? 2 - k : 0]);
+                        if (jq.y) v = gen_join(jq.y, h1, h2, h3, a, b2, c, pool, D, cc, v);
+                        if (jq.z) v = gen_join(jq.z, h1, h2, h3, a, b2, c, pool, D, cc, v);
+                        if (jq.w) v = gen_join(jq.w, h1, h2, h3, a, b2, c, pool, D, cc, v);
+                        const u32 lo = uni(A.l[k].x), ln = uni(A.l[k].y);
+                        for (u32 i = 0; i < ln; i++)
+                            v = gen_join(uni(list[lo + i]), h1, h2, h3, a, b2, c, pool, D, cc, v);
                     }
+                    if (mine) pool[(u64)h * D + cc] = v;
+                    val[k * 64 + lane] = v;
+                    dst = v;
+                };
+                u32 k = 0;
+                for (; k + 4 <= n; k += 4) {
+                    step(k, r2, r1, r0, r3);
+                    step(k + 1, r3, r2, r1, r0);
+                    step(k + 2, r0, r3, r2, r1);
+                    step(k + 3, r1, r0, r3, r2);
+                }
+                const u32 rem = n - k;
+                if (rem == 1) {
+                    step(k, r2, r1, r0, r3);
+                    r0 = r1; r1 = r2; r2 = r3;
+                } else if (rem == 2) {
+                    step(k, r2, r1, r0, r3);
+                    step(k + 1, r3, r2, r1, r0);
+                    const u32 t0 = r0;
+                    r0 = r2; r1 = r3; r2 = t0;
+                } else if (rem == 3) {
+                    step(k, r2, r1, r0, r3);
+                    step(k + 1, r3, r2, r1, r0);
+                    step(k + 2, r0, r3, r2, r1);
+                    const u32 t0 = r0, t1 = r1;
+                    r0 = r3; r1 = t0; r2 = t1;
+                }
+                // the three latest handles for the next block
+                if (lane == 0) {
+                    const u32 c0 = A.ch[0], c1 = A.ch[1];
+                    A.ch[0] = A.q[n - 1].x;
+                    A.ch[1] = n >= 2 ? A.q[n - 2].x : c0;
+                    A.ch[2] = n >= 3 ? A.q[n - 3].x : (n == 2 ? c0 : c1);
                 }
             }
             if (reporter) atomicAdd(&b.prm->gprog, 1u);
@@ -992,7 +1101,7 @@ __global__ __launch_bounds__(ENG_THREADS) void k_eng_eval(Bufs b, const u32 *rt_
     __shared__ u32 lds_n;
     __shared__ u32 lds_jobs[CH_BLK * ENG_JOB_WORDS];
     __shared__ ChainLds lds_chain;
-    __shared__ u32 lds_part[CH_BLK_JOBS * 64];
+    __shared__ u32 lds_part[CH_TABLE_WORDS];
     __shared__ u32 lds_ops[ENG_THREADS];
     __shared__ u32 lds_nops;
     const u32 D = P->D, ng = P->n_groups;
