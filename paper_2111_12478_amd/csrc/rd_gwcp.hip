@@ -38,6 +38,7 @@ namespace rd {
 
 constexpr u32 GW_HELD = 64;          // critical sections a thread may hold at once
 constexpr u32 GW_THREADS = 1024;     // the interpreter's workgroup
+constexpr u32 GW_BATCH = 32;         // words per lane read at once by a full comparison
 constexpr u32 GW_DEV = 0xffffffffu;  // scope key of a device / system scoped lock
 constexpr u32 GW_CSW = 8;            // words of a critical-section row (see k_gw_interp)
 constexpr u32 GW_NW = 5;             // words of a lock-clock row (see GwHeap::nodes)
@@ -597,10 +598,22 @@ __global__ __launch_bounds__(GW_THREADS) void k_gw_interp(Bufs b, GwcpBufs G, co
                                 const u32 cc = s_cand[k];
                                 const u32 *F = m.cs + (u64)cc * GW_CSW;
                                 const u32 *A = vec(F[5]);
+                                // (32 words per lane in flight: the comparison waits for memory
+                                // once per 2,048 words)
                                 u32 wfail = NONE;
-#pragma unroll 8
-                                for (u32 w = lane; w < T; w += 64)
-                                    if (A[w] > (w == t ? Nt : s_pt[w])) wfail = w;
+                                for (u32 w0 = lane; w0 < T; w0 += 64 * GW_BATCH) {
+                                    u32 x[GW_BATCH];
+#pragma unroll
+                                    for (u32 j = 0; j < GW_BATCH; j++) {
+                                        const u32 w = w0 + j * 64;
+                                        x[j] = w < T ? A[w] : 0u;
+                                    }
+#pragma unroll
+                                    for (u32 j = 0; j < GW_BATCH; j++) {
+                                        const u32 w = w0 + j * 64;
+                                        if (w < T && x[j] > (w == t ? Nt : s_pt[w])) wfail = w;
+                                    }
+                                }
                                 const u64 am = ballot(wfail != NONE);
                                 if (am) {
                                     // a witness for the next comparisons
@@ -612,12 +625,20 @@ __global__ __launch_bounds__(GW_THREADS) void k_gw_interp(Bufs b, GwcpBufs G, co
                                 const u32 *RH = vec(F[6]);
                                 if (lane == 0) atomicMax(&m.J[(u64)t * T + F[0]], RH[F[0]]);
                                 bool ch = false;
-#pragma unroll 8
-                                for (u32 w = lane; w < T; w += 64) {
-                                    const u32 v = RH[w];
-                                    if (v > s_pt[w]) {
-                                        atomicMax(&s_pt[w], v);
-                                        ch = true;
+                                for (u32 w0 = lane; w0 < T; w0 += 64 * GW_BATCH) {
+                                    u32 x[GW_BATCH];
+#pragma unroll
+                                    for (u32 j = 0; j < GW_BATCH; j++) {
+                                        const u32 w = w0 + j * 64;
+                                        x[j] = w < T ? RH[w] : 0u;
+                                    }
+#pragma unroll
+                                    for (u32 j = 0; j < GW_BATCH; j++) {
+                                        const u32 w = w0 + j * 64;
+                                        if (w < T && x[j] > s_pt[w]) {
+                                            atomicMax(&s_pt[w], x[j]);
+                                            ch = true;
+                                        }
                                     }
                                 }
                                 if (ballot(ch) && lane == 0) s_more = 1;
