@@ -878,49 +878,72 @@ __global__ __launch_bounds__(WG_THREADS) void k_seg_check(Bufs b, const u32 *rt_
     wp_flush(b, wp);
 }
 
-// One wavefront per queued chunk (lane l checks position lo + l against b), then one per access
-// queued whole (an exact backward scan of its segment, or of its run).  Each wavefront gathers its
-// pairs in LDS and appends them with one device atomic per flush.
-constexpr u32 SLOW_GRID = 2048;
+// One wavefront per queued chunk (lane l checks position lo + l against b), the four wavefronts of
+// a workgroup in step; pairs are gathered in LDS and appended with one device atomic per flush of
+// the workgroup.  Then one wavefront per access queued whole: an exact backward scan of its segment
+// (or of its run), each wavefront on its own.
+constexpr u32 PAIR_LDS = 2048;
+constexpr u32 SLOW_GRID = 1024;
 
 __global__ __launch_bounds__(WG_THREADS) void k_seg_slow(Bufs b, const u32 *rt_scan) {
-    __shared__ u32 pf[WAVES][WAVE_PAIRS], ps[WAVES][WAVE_PAIRS];
+    __shared__ u32 pf[PAIR_LDS], ps[PAIR_LDS];
+    __shared__ u32 fill, gbase;
     const SegCtx s = seg_ctx(b);
     if (check_abandoned(b.prm)) return;  // the answer is that error: nothing here is read
     const u32 n_chunks = (u32)min(b.prm->n_chunks, (unsigned long long)s.n);
-    const u32 n_long = min(b.prm->n_long, s.n);
     const u32 lane = lane_id(), w = threadIdx.x >> 6;
-    WavePairs wp;
-    wp.pf = pf[w];
-    wp.ps = ps[w];
-    wp.fill = 0;
+    if (threadIdx.x == 0) fill = 0;
+    __syncthreads();
     const u32 stride = gridDim.x * WAVES;
-    for (u32 c = blockIdx.x * WAVES + w; c < n_chunks; c += stride) {
-        const u32 pos = s.cpos[c], lo = s.clo[c], hi = s.chi[c];
-        const u32 q = lo + lane;
+    for (u32 c0 = blockIdx.x * WAVES; c0 < n_chunks; c0 += stride) {
+        const u32 c = c0 + w;
         bool want = false;
         u32 ia = 0, bidx = 0;
-        if (q < hi) {
-            const u32 btid = seg_tid(s, pos), binfo = seg_info(s, pos);
-            const u32 bblk = block_of(b, btid), bph = info_phase(binfo), bcat = info_cat(binfo);
-            const u32 ta = seg_tid(s, q), info = seg_info(s, q);
-            const u32 ba = block_of(b, ta), pha = info_phase(info);
-            if (ta != btid && conflicts(info_cat(info), ba, bcat, bblk)) {
-                u32 h = NONE;
-                ia = s.i[q];
-                bidx = s.i[pos];
-                want = !happens_before(b, rt_scan, bidx, btid, bblk, bph, h, ta, ba, pha, ia);
+        if (c < n_chunks) {
+            const u32 pos = s.cpos[c], lo = s.clo[c], hi = s.chi[c];
+            const u32 q = lo + lane;
+            if (q < hi) {
+                const u32 btid = seg_tid(s, pos), binfo = seg_info(s, pos);
+                const u32 bblk = block_of(b, btid), bph = info_phase(binfo), bcat = info_cat(binfo);
+                const u32 ta = seg_tid(s, q), info = seg_info(s, q);
+                const u32 ba = block_of(b, ta), pha = info_phase(info);
+                if (ta != btid && conflicts(info_cat(info), ba, bcat, bblk)) {
+                    u32 h = NONE;
+                    ia = s.i[q];
+                    bidx = s.i[pos];
+                    want = !happens_before(b, rt_scan, bidx, btid, bblk, bph, h, ta, ba, pha, ia);
+                }
             }
         }
-        wp_add(b, wp, want, ia, bidx);
+        const u64 m = ballot(want);
+        if (m) {
+            u32 off = 0;
+            const u32 leader = (u32)__builtin_ctzll(m);
+            if (lane == leader) off = atomicAdd(&fill, popc64(m));
+            off = __shfl(off, leader, 64) + popc64(m & lanemask_lt());
+            if (want) { pf[off] = ia; ps[off] = bidx; }
+        }
+        __syncthreads();
+        if (fill > PAIR_LDS - WG_THREADS || c0 + stride >= n_chunks) {
+            if (threadIdx.x == 0) gbase = fill ? atomicAdd(&b.prm->n_pairs, fill) : 0;
+            __syncthreads();
+            for (u32 k = threadIdx.x; k < fill; k += WG_THREADS) {
+                const u32 slot = gbase + k;
+                if (slot < b.max_pairs) { b.pfirst[0][slot] = pf[k]; b.psecond[0][slot] = ps[k]; }
+                else atomicOr(&b.prm->err, ERR_PAIRS);
+            }
+            __syncthreads();
+            if (threadIdx.x == 0) fill = 0;
+            __syncthreads();
+        }
     }
+    const u32 n_long = min(b.prm->n_long, s.n);
     for (u32 c = blockIdx.x * WAVES + w; c < n_long; c += stride) {
         const u32 e = s.lpos[c], pos = e & 0x7fffffffu;
         const u32 tid = seg_tid(s, pos), info = seg_info(s, pos);
         wave_slow_check(b, s, rt_scan, pos, seg_key(s, pos), tid, block_of(b, tid), info_phase(info),
                         info_cat(info), (e >> 31) != 0u);
     }
-    wp_flush(b, wp);
 }
 
 __global__ void k_pairs_kept(Bufs b) {
