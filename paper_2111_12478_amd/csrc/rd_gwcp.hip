@@ -71,9 +71,11 @@ __device__ inline u32 gw_entry(const Bufs &b, u32 t, u32 i) {
 // vectors of T words to the end.
 struct GwHeap {
     u32 *P, *H;        // [T][T]
-    u32 *J;            // [T][T] J[t][u]: u's latest local time at the release of a section whose
-                       // release time t has joined (rule (ii)): u's sections released no later
-                       // are covered, H_u being monotone
+    u32 *J;            // [T][T] row t: the join of the sections' release times that rule (ii) has
+                       // found below P_t (joined, or already covered).  A release time is H_u when
+                       // u published it, and H clocks are happens-before clocks: J[t][u] >= a
+                       // release time's own word of u means row t, hence P_t, is above that whole
+                       // release time, so the section adds nothing and is passed over
     u32 *N;            // [T] local times
     u32 *held_n;       // [T] critical sections held
     u32 *held;         // [T][GW_HELD] their rows
@@ -427,6 +429,7 @@ __global__ __launch_bounds__(GW_THREADS) void k_gw_interp(Bufs b, GwcpBufs G, co
     __shared__ u32 s_full;
     __shared__ u32 s_cand[GW_THREADS], s_ncand, s_more;   // rule (ii)'s candidates
     __shared__ u32 s_pt[GW_MAX_T];                         // ... and P_t meanwhile
+    __shared__ u32 s_g[GW_MAX_T];                          // ... and the releaser's row of J
     if (threadIdx.x == 0) {
         s_vec = s_cs = s_nodes = s_rec = 0;
         s_full = 0;
@@ -564,8 +567,13 @@ __global__ __launch_bounds__(GW_THREADS) void k_gw_interp(Bufs b, GwcpBufs G, co
                     // compares one survivor at a time in full and joins it with LDS atomics.  Joins
                     // only raise P_t, so a comparison that reads words another wavefront is raising
                     // still decides against a clock P_t reaches, and the passes end at the same
-                    // least fixpoint as joins taken one by one
-                    for (u32 w = threadIdx.x; w < T; w += GW_THREADS) s_pt[w] = Pt[w];
+                    // least fixpoint as joins taken one by one.  A survivor whose release time is
+                    // already below P_t is passed over without the comparison, and that release time
+                    // joins the releaser's row of J, which screens later sections
+                    for (u32 w = threadIdx.x; w < T; w += GW_THREADS) {
+                        s_pt[w] = Pt[w];
+                        s_g[w] = m.J[(u64)t * T + w];
+                    }
                     __syncthreads();
                     const u32 qoff = W[1], qn = W[2], Nt = m.N[t];
                     const u32 lane = threadIdx.x & 63u, wave = threadIdx.x >> 6;
@@ -580,9 +588,9 @@ __global__ __launch_bounds__(GW_THREADS) void k_gw_interp(Bufs b, GwcpBufs G, co
                                 c = m.warr[qoff + c0 + threadIdx.x];
                                 const u32 *F = m.cs + (u64)c * GW_CSW;
                                 if (F[0] != t && F[4] != NONE && gw_overlap(F[3], key)) {
-                                    // (covered when t has joined a later section's release time of
-                                    // the same thread)
-                                    const bool done = vec(F[6])[F[0]] <= m.J[(u64)t * T + F[0]];
+                                    // (covered when the row of release times found below P_t
+                                    // holds its own word of this one)
+                                    const bool done = vec(F[6])[F[0]] <= s_g[F[0]];
                                     const u32 *A = vec(F[5]);
                                     const u32 wv = m.wit[c];
                                     cand = !done && A[F[0]] <= s_pt[F[0]] &&
@@ -597,9 +605,44 @@ __global__ __launch_bounds__(GW_THREADS) void k_gw_interp(Bufs b, GwcpBufs G, co
                             for (u32 k = wave; k < nc; k += GW_THREADS / 64) {
                                 const u32 cc = s_cand[k];
                                 const u32 *F = m.cs + (u64)cc * GW_CSW;
-                                const u32 *A = vec(F[5]);
-                                // (32 words per lane in flight: the comparison waits for memory
-                                // once per 2,048 words)
+                                const u32 *A = vec(F[5]), *RH = vec(F[6]);
+                                // (32 words per lane in flight: a comparison waits for memory once
+                                // per 2,048 words)
+                                // A release time already below P_t adds nothing, whatever the
+                                // acquire time: the section is passed over without comparing that,
+                                // and t covers its thread's sections up to it from now on (P_t only
+                                // grows, and H_u is monotone)
+                                bool adds = false;
+                                for (u32 w0 = lane; w0 < T; w0 += 64 * GW_BATCH) {
+                                    u32 x[GW_BATCH];
+#pragma unroll
+                                    for (u32 j = 0; j < GW_BATCH; j++) {
+                                        const u32 w = w0 + j * 64;
+                                        x[j] = w < T ? RH[w] : 0u;
+                                    }
+#pragma unroll
+                                    for (u32 j = 0; j < GW_BATCH; j++) {
+                                        const u32 w = w0 + j * 64;
+                                        if (w < T && x[j] > s_pt[w]) adds = true;
+                                    }
+                                }
+                                if (!ballot(adds)) {
+                                    // (read again: the words are in the cache)
+                                    for (u32 w0 = lane; w0 < T; w0 += 64 * GW_BATCH) {
+                                        u32 x[GW_BATCH];
+#pragma unroll
+                                        for (u32 j = 0; j < GW_BATCH; j++) {
+                                            const u32 w = w0 + j * 64;
+                                            x[j] = w < T ? RH[w] : 0u;
+                                        }
+#pragma unroll
+                                        for (u32 j = 0; j < GW_BATCH; j++) {
+                                            const u32 w = w0 + j * 64;
+                                            if (w < T && x[j] > s_g[w]) atomicMax(&s_g[w], x[j]);
+                                        }
+                                    }
+                                    continue;
+                                }
                                 u32 wfail = NONE;
                                 for (u32 w0 = lane; w0 < T; w0 += 64 * GW_BATCH) {
                                     u32 x[GW_BATCH];
@@ -622,8 +665,6 @@ __global__ __launch_bounds__(GW_THREADS) void k_gw_interp(Bufs b, GwcpBufs G, co
                                     if (lane == 0) m.wit[cc] = wf;
                                     continue;
                                 }
-                                const u32 *RH = vec(F[6]);
-                                if (lane == 0) atomicMax(&m.J[(u64)t * T + F[0]], RH[F[0]]);
                                 bool ch = false;
                                 for (u32 w0 = lane; w0 < T; w0 += 64 * GW_BATCH) {
                                     u32 x[GW_BATCH];
@@ -639,6 +680,7 @@ __global__ __launch_bounds__(GW_THREADS) void k_gw_interp(Bufs b, GwcpBufs G, co
                                             atomicMax(&s_pt[w], x[j]);
                                             ch = true;
                                         }
+                                        if (w < T && x[j] > s_g[w]) atomicMax(&s_g[w], x[j]);
                                     }
                                 }
                                 if (ballot(ch) && lane == 0) s_more = 1;
@@ -650,11 +692,12 @@ __global__ __launch_bounds__(GW_THREADS) void k_gw_interp(Bufs b, GwcpBufs G, co
                         grew |= more;
                         __syncthreads();  // s_more is reset next
                     }
-                    if (grew) {
-                        for (u32 w = threadIdx.x; w < T; w += GW_THREADS) Pt[w] = s_pt[w];
-                        __syncthreads();
-                        pch = true;
+                    for (u32 w = threadIdx.x; w < T; w += GW_THREADS) {
+                        if (grew) Pt[w] = s_pt[w];
+                        m.J[(u64)t * T + w] = s_g[w];
                     }
+                    __syncthreads();
+                    if (grew) pch = true;
                 }
                 // the lock clock of (word, key), created on first use
                 u32 nd = NONE, fresh = 0;
