@@ -39,6 +39,8 @@ namespace rd {
 constexpr u32 GW_HELD = 64;          // critical sections a thread may hold at once
 constexpr u32 GW_THREADS = 1024;     // the interpreter's workgroup
 constexpr u32 GW_BATCH = 32;         // words per lane read at once by a full comparison
+constexpr u32 GW_WPT = 4;            // clock words per lane of the workgroup (GW_MAX_T / GW_THREADS)
+static_assert(GW_WPT * GW_THREADS >= GW_MAX_T, "every clock word has a lane");
 constexpr u32 GW_DEV = 0xffffffffu;  // scope key of a device / system scoped lock
 constexpr u32 GW_CSW = 8;            // words of a critical-section row (see k_gw_interp)
 constexpr u32 GW_NW = 5;             // words of a lock-clock row (see GwHeap::nodes)
@@ -514,17 +516,41 @@ __global__ __launch_bounds__(GW_THREADS) void k_gw_interp(Bufs b, GwcpBufs G, co
             // Algorithm 2 (a read, or a write: a plain write or an atomic): join L^w, for a write also
             // L^r, of x under every lock clock of a held section's word whose scope overlaps the
             // section's; then x joins the section's reads or writes
+            // (every vector found is joined into registers, P_t written once)
             const bool write = kind != 0u;
             const u32 nh = m.held_n[t];
+            u32 acc[GW_WPT];
+#pragma unroll
+            for (u32 k = 0; k < GW_WPT; k++) acc[k] = 0;
+            bool any = false;
             for (u32 q = 0; q < nh; q++) {
                 const u32 *C = m.cs + (u64)m.held[(u64)t * GW_HELD + q] * GW_CSW;
                 for (u32 nd = m.words[(u64)C[1] * 4 + 3]; nd != NONE; nd = m.nodes[(u64)nd * GW_NW + 3]) {
                     if (!gw_overlap(m.nodes[(u64)nd * GW_NW], C[2]) || !m.nodes[(u64)nd * GW_NW + 4]) continue;
                     for (u32 rw = write ? 0u : 1u; rw < 2u; rw++) {
                         const u32 h = gw_find(m.lkey, m.lval, m.cl, gw_lkey(nd, x, rw));
-                        if (h != NONE) pch |= gw_join(Pt, vec(h), T);
+                        if (h == NONE) continue;
+                        any = true;
+                        const u32 *V = vec(h);
+#pragma unroll
+                        for (u32 k = 0; k < GW_WPT; k++) {
+                            const u32 w = threadIdx.x + k * GW_THREADS;
+                            if (w < T) acc[k] = max(acc[k], V[w]);
+                        }
                     }
                 }
+            }
+            if (any) {
+                bool ch = false;
+#pragma unroll
+                for (u32 k = 0; k < GW_WPT; k++) {
+                    const u32 w = threadIdx.x + k * GW_THREADS;
+                    if (w < T && acc[k] > Pt[w]) {
+                        Pt[w] = acc[k];
+                        ch = true;
+                    }
+                }
+                pch |= __syncthreads_or(ch);
             }
             if (threadIdx.x == 0)
                 for (u32 q = 0; q < nh; q++) {
@@ -774,10 +800,36 @@ __global__ __launch_bounds__(GW_THREADS) void k_gw_interp(Bufs b, GwcpBufs G, co
             if (fl & SF_ACQ) {
                 // ACQUIRE (Algorithm 1): P and H of every lock clock of the word whose scope overlaps
                 const u32 key = ((sc >> 2) & 3u) == 0 ? blk : GW_DEV;
-                for (u32 nd = W[3]; nd != NONE; nd = m.nodes[(u64)nd * GW_NW + 3]) {
-                    if (!gw_overlap(m.nodes[(u64)nd * GW_NW], key)) continue;
-                    pch |= gw_join(Pt, vec(m.nodes[(u64)nd * GW_NW + 2]), T);
-                    gw_join(Ht, vec(m.nodes[(u64)nd * GW_NW + 1]), T);
+                // (all of them joined into registers, P_t and H_t written once)
+                {
+                    u32 ap[GW_WPT], ah[GW_WPT];
+#pragma unroll
+                    for (u32 k = 0; k < GW_WPT; k++) ap[k] = ah[k] = 0;
+                    for (u32 nd = W[3]; nd != NONE; nd = m.nodes[(u64)nd * GW_NW + 3]) {
+                        if (!gw_overlap(m.nodes[(u64)nd * GW_NW], key)) continue;
+                        const u32 *PL = vec(m.nodes[(u64)nd * GW_NW + 2]), *HL = vec(m.nodes[(u64)nd * GW_NW + 1]);
+#pragma unroll
+                        for (u32 k = 0; k < GW_WPT; k++) {
+                            const u32 w = threadIdx.x + k * GW_THREADS;
+                            if (w < T) {
+                                ap[k] = max(ap[k], PL[w]);
+                                ah[k] = max(ah[k], HL[w]);
+                            }
+                        }
+                    }
+                    bool ch = false;
+#pragma unroll
+                    for (u32 k = 0; k < GW_WPT; k++) {
+                        const u32 w = threadIdx.x + k * GW_THREADS;
+                        if (w < T) {
+                            if (ap[k] > Pt[w]) {
+                                Pt[w] = ap[k];
+                                ch = true;
+                            }
+                            if (ah[k] > Ht[w]) Ht[w] = ah[k];
+                        }
+                    }
+                    pch |= __syncthreads_or(ch);
                 }
                 // a section opens unless the thread holds the word (Acq_l for the other threads)
                 u32 h = NONE;
