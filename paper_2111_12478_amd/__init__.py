@@ -508,14 +508,14 @@ class RaceChecker:
         st, n = rd_race_kinds(self.ctx, trace, out.ctypes.data if capacity else None, capacity)
         return st, out[: min(capacity, n)].copy()
 
-    def lockset(self, trace):
-        """The lockset pass over a bound trace: CheckResult with the sorted pairs."""
-        st, n = rd_lockset(self.ctx, trace, None, 0)
-        if st not in (RD_OK, RD_ETRUNC):
-            idx, msg = rd_last_error(self.ctx)
-            return CheckResult(st, np.zeros((0, 2), np.uint32), idx, msg)
-        out = np.zeros((max(n, 1), 2), dtype=np.uint32)
-        st, n = rd_lockset(self.ctx, trace, out.ctypes.data, n)
+    def lockset(self, trace, capacity=1 << 16):
+        """The lockset pass over a bound trace: CheckResult with the sorted pairs (the pass runs again
+        with room for every pair when `capacity` is too small)."""
+        out = np.zeros((max(capacity, 1), 2), dtype=np.uint32)
+        st, n = rd_lockset(self.ctx, trace, out.ctypes.data, capacity)
+        if st == RD_ETRUNC:
+            out = np.zeros((max(n, 1), 2), dtype=np.uint32)
+            st, n = rd_lockset(self.ctx, trace, out.ctypes.data, n)
         if st != RD_OK:
             idx, msg = rd_last_error(self.ctx)
             return CheckResult(st, np.zeros((0, 2), np.uint32), idx, msg)

@@ -114,3 +114,27 @@ def test_pool_too_small(rc):
     grid, ev = lock_trace(5, max_events=200)
     got, _ = _lockset(rc, grid, ev, limits={"clock_bytes": 1 << 20})
     assert got.status == -2, got
+
+
+def test_small_capacity_runs_again(rc):
+    # the binding's buffer holds fewer pairs than the pass finds: RD_ETRUNC, then one more pass with
+    # room for all of them; and the C call itself with a short buffer writes the first pairs
+    from paper_2111_12478_amd import rd_lockset, rd_trace_free, RD_ETRUNC
+    for seed in range(40):
+        grid, ev = lock_trace(seed, max_blocks=4, max_tpb=6, max_events=400, flags=True)
+        want = oracle.lockset(grid, ev)
+        if want.status == 0 and len(want.pairs) >= 3:
+            break
+    else:
+        pytest.skip("no seed with three lockset pairs")
+    tr, ws, keep = rc.prepare(grid, ev)
+    try:
+        got = rc.lockset(tr, capacity=1)
+        assert got.status == 0, got
+        np.testing.assert_array_equal(got.pairs, want.pairs)
+        out = np.zeros((2, 2), np.uint32)
+        st, n = rd_lockset(rc.ctx, tr, out.ctypes.data, 2)
+        assert st == RD_ETRUNC and n == len(want.pairs)
+        np.testing.assert_array_equal(out, want.pairs[:2])
+    finally:
+        rd_trace_free(rc.ctx, tr)
