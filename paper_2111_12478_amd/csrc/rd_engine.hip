@@ -806,14 +806,14 @@ static_assert(CH_ZROW < 1024, "rows are 10-bit fields");
 // One job with inputs from the window: output handle, up to three input handles, and for a
 // barrier a range of the window input list.
 struct ChainLds {
-    uint4 q[CH_BLK_JOBS];
+    uint4 q[CH_BLK_JOBS + 2];          // (two more entries: the replay reads a job ahead)
     uint2 l[CH_BLK_JOBS];
     u32 wave_n[ENG_THREADS / 64];
     u32 n, nf;
     u32 ch[3];                         // handles of the replay's three latest outputs before the block
-    u32 code[CH_BLK_JOBS];             // per job: which of the three latest outputs it joins (bits
+    u32 code[CH_BLK_JOBS + 2];         // per job: which of the three latest outputs it joins (bits
                                        // 0-2), or NONE when it takes the general step
-    u32 rows[CH_BLK_JOBS];             // per job: three rows of the table it joins (10 bits each)
+    u32 rows[CH_BLK_JOBS + 2];         // per job: three rows of the table it joins (10 bits each)
     u32 farh[CH_BLK_JOBS];             // handle of each prefetched row
     u32 hkey[CH_HASH], hval[CH_HASH];  // output handle -> job index within the block
 };
@@ -950,6 +950,9 @@ __device__ void chain_window(const Bufs &b, u32 w0, u32 w1, u32 D, u32 *lj /* CH
                 }
                 A.code[k] = lean ? code : NONE;
                 A.rows[k] = lean ? rows : CH_ROWS_NONE;
+            } else if (threadIdx.x < n + 2) {
+                A.code[threadIdx.x] = NONE;
+                A.rows[threadIdx.x] = CH_ROWS_NONE;
             }
             __syncthreads();
             // the table: the jobs' partial results, then the outputs of earlier blocks (stored by
@@ -975,7 +978,7 @@ __device__ void chain_window(const Bufs &b, u32 w0, u32 w1, u32 D, u32 *lj /* CH
                 // outputs are registers), so its words and rows are read a job ahead.
                 // (the next job's four values are joined only when it runs, so the reads have the
                 // current job's time to arrive)
-                u32 code_n = A.code[0], h_n = A.q[0].x, rows_nn = A.rows[n > 1 ? 1 : 0];
+                u32 code_n = A.code[0], h_n = A.q[0].x, rows_nn = A.rows[1];
                 u32 x0, x1, x2, x3;
                 {
                     const u32 rr = uni(A.rows[0]);
@@ -985,22 +988,20 @@ __device__ void chain_window(const Bufs &b, u32 w0, u32 w1, u32 D, u32 *lj /* CH
                     x3 = val[(rr >> 20) * 64 + lane];
                 }
                 auto step = [&](u32 k, u32 a, u32 b2, u32 c, u32 &dst) {
-                    const u32 cd = uni(code_n), h = uni(h_n);
+                    const u32 cd = uni(code_n), h = uni(h_n), rr = uni(rows_nn);
                     u32 v = max(max(x0, x1), max(x2, x3));
-                    if (k + 1 < n) {
-                        const u32 rr = uni(rows_nn);
-                        code_n = A.code[k + 1];
-                        h_n = A.q[k + 1].x;
-                        rows_nn = A.rows[k + 2 < n ? k + 2 : k + 1];
-                        x0 = val[(k + 1) * 64 + lane];
-                        x1 = val[(rr & 0x3FFu) * 64 + lane];
-                        x2 = val[((rr >> 10) & 0x3FFu) * 64 + lane];
-                        x3 = val[(rr >> 20) * 64 + lane];
-                    }
+                    // the next job's words and values (after the last job: the padding, unused)
+                    code_n = A.code[k + 1];
+                    h_n = A.q[k + 1].x;
+                    rows_nn = A.rows[k + 2];
+                    x0 = val[(k + 1) * 64 + lane];
+                    x1 = val[(rr & 0x3FFu) * 64 + lane];
+                    x2 = val[((rr >> 10) & 0x3FFu) * 64 + lane];
+                    x3 = val[(rr >> 20) * 64 + lane];
                     if (cd != NONE) {
-                        v = max(v, (cd & 1u) ? a : 0u);
-                        v = max(v, (cd & 2u) ? b2 : 0u);
-                        v = max(v, (cd & 4u) ? c : 0u);
+                        // (the selected registers, by masks: no branch)
+                        const u32 m0 = 0u - (cd & 1u), m1 = 0u - ((cd >> 1) & 1u), m2 = 0u - ((cd >> 2) & 1u);
+                        v = max(max(v, a & m0), max(b2 & m1, c & m2));
                     } else {
                         const uint4 jq = make_uint4(0, uni(A.q[k].y), uni(A.q[k].z), uni(A.q[k].w));
                         const u32 h1 = uni(k >= 1 ? A.q[k - 1].x : A.ch[0]);
