@@ -798,6 +798,8 @@ __device__ __attribute__((always_inline)) inline u32 load_now(const u32 *p) {
 }
 
 constexpr u32 CH_HASH = 1024;                 // open-addressed map of a block's output handles
+constexpr u32 CH_JOB_PER_THREAD = CH_BLK * ENG_JOB_WORDS / ENG_THREADS;
+static_assert(CH_JOB_PER_THREAD * ENG_THREADS == CH_BLK * ENG_JOB_WORDS, "a block's job words split evenly");
 constexpr u32 CH_ZROW = CH_BLK_JOBS;          // the table's row of zeros
 constexpr u32 CH_ROWS_NONE = CH_ZROW | CH_ZROW << 10 | CH_ZROW << 20;
 constexpr u32 CH_TABLE_WORDS = (CH_BLK_JOBS + 1) * 64;
@@ -844,11 +846,30 @@ __device__ void chain_window(const Bufs &b, u32 w0, u32 w1, u32 D, u32 *lj /* CH
         // the ring of the latest outputs: r2 the newest, r1 and r0 before it (r3 is written next)
         u32 r0 = 0, r1 = 0, r2 = 0, r3 = 0;
         if (threadIdx.x < 3) A.ch[threadIdx.x] = 0;
+        // each thread's words of the next block's jobs, loaded one block ahead (the window's jobs
+        // are all written before the grid barrier that starts this phase)
+        u32 nxt[CH_JOB_PER_THREAD];
+#pragma unroll
+        for (u32 i = 0; i < CH_JOB_PER_THREAD; i++) {
+            const u32 x = threadIdx.x + i * ENG_THREADS;
+            nxt[i] = x < (min(w0 + CH_BLK, w1) - w0) * ENG_JOB_WORDS ? jobs[x] : 0u;
+        }
         for (u32 cb = w0; cb < w1; cb += CH_BLK) {
             const u32 ce = min(cb + CH_BLK, w1);
             __syncthreads();
-            for (u32 x = threadIdx.x; x < (ce - cb) * ENG_JOB_WORDS; x += ENG_THREADS)
-                lj[x] = jobs[(u64)(cb - w0) * ENG_JOB_WORDS + x];
+#pragma unroll
+            for (u32 i = 0; i < CH_JOB_PER_THREAD; i++) {
+                const u32 x = threadIdx.x + i * ENG_THREADS;
+                if (x < (ce - cb) * ENG_JOB_WORDS) lj[x] = nxt[i];
+            }
+            if (ce < w1) {
+                const u32 ne = min(ce + CH_BLK, w1);
+#pragma unroll
+                for (u32 i = 0; i < CH_JOB_PER_THREAD; i++) {
+                    const u32 x = threadIdx.x + i * ENG_THREADS;
+                    nxt[i] = x < (ne - ce) * ENG_JOB_WORDS ? jobs[(u64)(ce - w0) * ENG_JOB_WORDS + x] : 0u;
+                }
+            }
             for (u32 x = threadIdx.x; x < CH_HASH; x += ENG_THREADS) A.hkey[x] = 0;
             if (threadIdx.x == 0) A.nf = 0;
             __syncthreads();
