@@ -968,7 +968,7 @@ def main():
         return
     oracle_on = not args.no_cpu_baseline
     head = {"metric": METRIC, "n_gpus": 1, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
-            "dtype": "u32", "data": "synthetic (seeded generators of the workloads' shapes; see DESIGN.md)"}
+            "dtype": "u32", "data": "synthetic (seeded generators of the workloads' shapes)"}
 
     # the stencil trace and its whole-trace oracle first: the oracle runs in a forked process (before
     # this one touches the GPU) while the GPU workloads run
